@@ -1,0 +1,289 @@
+"""Seeded synthetic inputs shared by the oracle and the HIP race checker.
+
+This module holds no part of the race-check arithmetic.  It only draws
+random numbers and lays out workload inputs as plain arrays: the data of the
+three workloads (tree reduction, Jacobi stencil, label propagation), the
+seeded race-injection tables, R-MAT graphs in CSR form, and tiny barrier
+programs for the access-program interpreter.  Both sides read these arrays
+and interpret them independently.
+
+Master seed of workload configuration c is ``0x24010470 + c``.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import List
+
+import numpy as np
+
+MASTER_SEED_BASE = 0x24010470
+
+
+def master_seed(config: int) -> int:
+    return MASTER_SEED_BASE + int(config)
+
+
+# --------------------------------------------------------------------------
+# Workload 0: one-block LDS tree reduction of 512 int32 over 9 barrier steps.
+# --------------------------------------------------------------------------
+REDUCE_N = 512
+REDUCE_THREADS = 256
+REDUCE_STEPS = 9
+
+
+def reduce_input(seed: int) -> np.ndarray:
+    """int32[512] drawn uniformly from [0, 2^20)."""
+    rng = np.random.default_rng(seed)
+    return rng.integers(0, 1 << 20, size=REDUCE_N, dtype=np.int64).astype(np.int32)
+
+
+# --------------------------------------------------------------------------
+# Workload 1: 5-point Jacobi stencil on an ny x nx fp32 grid, 16x16 blocks.
+# --------------------------------------------------------------------------
+JACOBI_BS = 16
+SIDE_N, SIDE_S, SIDE_W, SIDE_E = 0, 1, 2, 3
+
+
+def jacobi_grid(ny: int, nx: int, seed: int) -> np.ndarray:
+    """fp32 (ny, nx) grid drawn uniformly from [0, 1)."""
+    rng = np.random.default_rng(seed)
+    return rng.random((ny, nx), dtype=np.float32)
+
+
+def jacobi_blocks(ny: int, nx: int):
+    bs = JACOBI_BS
+    return (ny + bs - 1) // bs, (nx + bs - 1) // bs
+
+
+def _seed_options(ny: int, nx: int, bx: int, by: int):
+    """(side, offset) pairs whose writer thread and target cell lie in the grid."""
+    bs = JACOBI_BS
+    y0, x0 = by * bs, bx * bs
+    out = []
+    for o in range(bs):
+        # north: writer (ty=0, tx=o) at (y0, x0+o); target (y0-1, x0+o)
+        if y0 - 1 >= 0 and y0 < ny and x0 + o < nx:
+            out.append((SIDE_N, o))
+        # south: writer (ty=15, tx=o) at (y0+15, x0+o); target (y0+16, x0+o)
+        if y0 + bs < ny and x0 + o < nx:
+            out.append((SIDE_S, o))
+        # west: writer (ty=o, tx=0) at (y0+o, x0); target (y0+o, x0-1)
+        if x0 - 1 >= 0 and x0 < nx and y0 + o < ny:
+            out.append((SIDE_W, o))
+        # east: writer (ty=o, tx=15) at (y0+o, x0+15); target (y0+o, x0+16)
+        if x0 + bs < nx and y0 + o < ny:
+            out.append((SIDE_E, o))
+    return out
+
+
+def jacobi_seeds(ny: int, nx: int, seed: int, frac: float = 0.001,
+                 count: int | None = None) -> np.ndarray:
+    """Seeded race injection for the stencil.
+
+    Returns int32 (k, 3) rows ``(block_linear, side, offset)``: block
+    ``block_linear = by * nbx + bx`` also writes the neighbour-owned halo cell
+    on ``side`` at position ``offset`` along that side, every launch.
+    ``k = round(frac * nblocks)`` unless ``count`` is given.
+    """
+    nby, nbx = jacobi_blocks(ny, nx)
+    nb = nby * nbx
+    k = int(round(frac * nb)) if count is None else int(count)
+    rng = np.random.default_rng(seed ^ 0x5EED)
+    rows = []
+    if k <= 0:
+        return np.zeros((0, 3), dtype=np.int32)
+    order = rng.permutation(nb)
+    for b in order:
+        by, bx = divmod(int(b), nbx)
+        opts = _seed_options(ny, nx, bx, by)
+        if not opts:
+            continue
+        side, off = opts[int(rng.integers(0, len(opts)))]
+        rows.append((int(b), side, off))
+        if len(rows) == k:
+            break
+    rows.sort()
+    return np.asarray(rows, dtype=np.int32).reshape(-1, 3)
+
+
+def jacobi_seed_table(ny: int, nx: int, seeds: np.ndarray) -> np.ndarray:
+    """Per-block int32 table: -1, or ``side << 8 | offset`` for seeded blocks."""
+    nby, nbx = jacobi_blocks(ny, nx)
+    tab = np.full(nby * nbx, -1, dtype=np.int32)
+    for b, side, off in np.asarray(seeds).reshape(-1, 3):
+        tab[int(b)] = (int(side) << 8) | int(off)
+    return tab
+
+
+# --------------------------------------------------------------------------
+# Workload 2: label propagation over an R-MAT graph in CSR form.
+# --------------------------------------------------------------------------
+RMAT_ABCD = (0.57, 0.19, 0.19, 0.05)
+
+
+def rmat_edges(scale: int, n_edges: int, seed: int,
+               abc=(0.57, 0.19, 0.19)):
+    """Directed R-MAT edges (no noise, no permutation; self loops and
+    duplicates kept).  Returns (src, dst) uint32 arrays."""
+    a, b, c = abc
+    rng = np.random.default_rng(seed)
+    src = np.zeros(n_edges, dtype=np.uint32)
+    dst = np.zeros(n_edges, dtype=np.uint32)
+    t_ab = np.float32(a + b)
+    t_a = np.float32(a)
+    t_abc = np.float32(a + b + c)
+    for level in range(scale):
+        u = rng.random(n_edges, dtype=np.float32)
+        sbit = (u >= t_ab).astype(np.uint32)                 # quadrants c, d
+        dbit = (((u >= t_a) & (u < t_ab)) | (u >= t_abc)).astype(np.uint32)  # b, d
+        shift = np.uint32(scale - 1 - level)
+        src |= sbit << shift
+        dst |= dbit << shift
+    return src, dst
+
+
+def csr_by_source(src: np.ndarray, dst: np.ndarray, n_vertices: int):
+    """Stable CSR by source vertex: (row_ptr int32[n+1], col int32[m])."""
+    order = np.argsort(src, kind="stable")
+    col = dst[order].astype(np.int32)
+    counts = np.bincount(src, minlength=n_vertices).astype(np.int64)
+    row_ptr = np.zeros(n_vertices + 1, dtype=np.int64)
+    np.cumsum(counts, out=row_ptr[1:])
+    assert row_ptr[-1] < 2**31
+    return row_ptr.astype(np.int32), col
+
+
+def seeded_edge_mask(n_edges: int, p: float, seed: int) -> np.ndarray:
+    """uint8 Bernoulli(p) mask over CSR edge positions."""
+    rng = np.random.default_rng(seed ^ 0xED6E)
+    return (rng.random(n_edges, dtype=np.float64) < p).astype(np.uint8)
+
+
+def labelprop_graph(scale: int, n_edges: int, seed: int, p_seed: float):
+    """R-MAT graph in CSR plus its seeded-edge mask."""
+    src, dst = rmat_edges(scale, n_edges, seed)
+    row_ptr, col = csr_by_source(src, dst, 1 << scale)
+    mask = seeded_edge_mask(n_edges, p_seed, seed)
+    return row_ptr, col, mask
+
+
+# --------------------------------------------------------------------------
+# Barrier programs for the access-program interpreter.
+#
+# A program is a list of launches.  A launch has ``blocks`` blocks of
+# ``threads`` threads and a list of phases.  In each phase every thread runs
+# its own list of memory operations, then the phase ends with
+#   scope 0: nothing,
+#   scope 1: a wave-scope barrier in the waves whose bit is set in wave_mask,
+#   scope 2: a block-scope barrier in every thread of the block.
+# Operation word (uint32):
+#   bits  0..23  element index
+#   bits 24..26  region (global regions 0..7; LDS uses region 0)
+#   bits 27..28  kind: 0 plain read, 1 plain write, 2 atomic
+#   bit  29      space: 0 global, 1 LDS
+# op_off has phases*blocks*threads+1 entries; the operations of
+# (phase p, block b, thread t) are ops[op_off[i]:op_off[i+1]] with
+# i = (p * blocks + b) * threads + t.
+# --------------------------------------------------------------------------
+KIND_R, KIND_W, KIND_A = 0, 1, 2
+SPACE_GLOBAL, SPACE_LDS = 0, 1
+SCOPE_NONE, SCOPE_WAVE, SCOPE_BLOCK = 0, 1, 2
+
+
+def op_word(space: int, region: int, kind: int, index: int) -> int:
+    assert 0 <= index < (1 << 24) and 0 <= region < 8 and kind in (0, 1, 2)
+    return (index | (region << 24) | (kind << 27) | (space << 29)) & 0xFFFFFFFF
+
+
+def op_fields(word: int):
+    """(space, region, kind, index) of an operation word."""
+    w = int(word)
+    return (w >> 29) & 1, (w >> 24) & 7, (w >> 27) & 3, w & 0xFFFFFF
+
+
+@dataclasses.dataclass
+class Launch:
+    blocks: int
+    threads: int
+    scope: np.ndarray       # uint8[phases]
+    wave_mask: np.ndarray   # uint64[phases]
+    op_off: np.ndarray      # int32[phases*blocks*threads + 1]
+    ops: np.ndarray         # uint32[...]
+
+    @property
+    def phases(self) -> int:
+        return int(self.scope.shape[0])
+
+    def thread_ops(self, phase: int, block: int, thread: int) -> np.ndarray:
+        i = (phase * self.blocks + block) * self.threads + thread
+        return self.ops[self.op_off[i]:self.op_off[i + 1]]
+
+
+@dataclasses.dataclass
+class Program:
+    launches: List[Launch]
+    global_words: List[int]   # element count of each global region
+    lds_words: int            # element count of the LDS array
+
+
+def build_launch(blocks, threads, scopes, wave_masks, per_thread_ops) -> Launch:
+    """per_thread_ops[p][b][t] is a list of operation words."""
+    offs = [0]
+    flat = []
+    for p in range(len(scopes)):
+        for b in range(blocks):
+            for t in range(threads):
+                lst = per_thread_ops[p][b][t]
+                flat.extend(lst)
+                offs.append(len(flat))
+    return Launch(blocks=blocks, threads=threads,
+                  scope=np.asarray(scopes, dtype=np.uint8),
+                  wave_mask=np.asarray(wave_masks, dtype=np.uint64),
+                  op_off=np.asarray(offs, dtype=np.int32),
+                  ops=np.asarray(flat, dtype=np.uint32))
+
+
+def random_program(seed: int, launches: int = 2, blocks: int = 2,
+                   threads: int = 128, phases: int = 3, max_ops: int = 2,
+                   global_regions: int = 2, global_words: int = 64,
+                   lds_words: int = 64, p_lds: float = 0.3,
+                   kind_p=(0.5, 0.25, 0.25), scope_p=(0.3, 0.3, 0.4),
+                   p_active: float = 1.0, wave_width: int = 64) -> Program:
+    """Random barrier program.  Addresses are drawn from small ranges so that
+    conflicting accesses from different threads are common.  Every thread of
+    a block sees the same phase structure, so barriers are uniform.
+    wave_width only shapes the wave masks of wave-barrier phases."""
+    rng = np.random.default_rng(seed)
+    waves = min(64, (threads + wave_width - 1) // wave_width)
+    out = []
+    kind_p = np.asarray(kind_p, dtype=np.float64)
+    for _ in range(launches):
+        scopes = rng.choice(3, size=phases, p=scope_p).astype(np.uint8)
+        masks = np.zeros(phases, dtype=np.uint64)
+        for p in range(phases):
+            if scopes[p] == SCOPE_WAVE:
+                bits = rng.random(waves) < 0.7
+                m = 0
+                for w in np.nonzero(bits)[0]:
+                    m |= 1 << int(w)
+                masks[p] = m
+        n_slots = phases * blocks * threads
+        counts = rng.integers(0, max_ops + 1, size=n_slots)
+        counts[rng.random(n_slots) >= p_active] = 0
+        total = int(counts.sum())
+        kinds = rng.choice(3, size=total, p=kind_p).astype(np.uint32)
+        lds = rng.random(total) < p_lds
+        regions = rng.integers(0, global_regions, size=total).astype(np.uint32)
+        gidx = rng.integers(0, global_words, size=total).astype(np.uint32)
+        lidx = rng.integers(0, lds_words, size=total).astype(np.uint32)
+        index = np.where(lds, lidx, gidx)
+        regions = np.where(lds, 0, regions).astype(np.uint32)
+        ops = (index | (regions << 24) | (kinds << 27)
+               | (lds.astype(np.uint32) << 29)).astype(np.uint32)
+        op_off = np.zeros(n_slots + 1, dtype=np.int64)
+        np.cumsum(counts, out=op_off[1:])
+        out.append(Launch(blocks=blocks, threads=threads, scope=scopes,
+                          wave_mask=masks, op_off=op_off.astype(np.int32),
+                          ops=ops))
+    return Program(launches=out, global_words=[global_words] * global_regions,
+                   lds_words=lds_words)
