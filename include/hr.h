@@ -1,0 +1,206 @@
+/*
+ * hr.h -- C ABI of the MI355X (gfx950) race checker.
+ *
+ * The checker follows HiRace (Jacobson, Burtscher, Gopalakrishnan): every
+ * monitored 4-byte element of global memory or LDS has a constant-size
+ * shadow word holding a per-location state machine; each instrumented access
+ * advances it with a compare-and-swap (paper Sec. IV-B, Algorithm 1), and a
+ * transition into the race state is appended once to a report ring
+ * (Sec. V-C reports races on unique addresses).  Races are the paper's
+ * (Sec. II-A): same location, different threads, at least one write (or a
+ * plain access meeting an atomic, Sec. III-B), not ordered by a launch
+ * boundary, a block barrier or a wave barrier (Sec. II-B).
+ *
+ * Conventions for every call:
+ *  - Pointers named *_dev are device pointers (HIP device memory); all other
+ *    pointers are host pointers.  The caller owns its data buffers and
+ *    streams; a context owns its shadow memory, report ring and counters.
+ *  - `stream` is a hipStream_t passed as void*; NULL means the stream given
+ *    to hr_ctx_create.  Calls are stream-ordered and asynchronous unless
+ *    stated otherwise.
+ *  - Negative status: error, nothing was changed.  Positive status: a bit set
+ *    of warnings; results gathered so far remain valid.
+ *  - The caller serialises calls on one context (no internal locking).
+ */
+#ifndef HR_H
+#define HR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hr_ctx_s* hr_ctx;
+
+typedef enum {
+    HR_OK = 0,
+    /* Warnings (bit set).  Clock overflow: a block or wave clock passed its
+     * configured width; checking stopped in the affected threads after the
+     * races found so far were recorded (paper Sec. III-A, footnote on clock
+     * sizes). */
+    HR_W_CLOCK_OVERFLOW = 1,
+    /* More races than ring slots; hr_report then completes the global-memory
+     * part of the set from the sticky race states in shadow memory, while LDS
+     * races beyond the ring are lost. */
+    HR_W_RING_OVERFLOW = 2,
+    /* An instrumented access named an element outside its region; it was
+     * neither checked nor performed by the library's own kernels. */
+    HR_W_OUT_OF_RANGE = 4,
+    HR_E_INVAL = -1,   /* bad argument */
+    HR_E_NOMEM = -2,   /* allocation failed or shadow budget exceeded */
+    HR_E_HIP = -3,     /* a HIP runtime call failed */
+    HR_E_STATE = -4    /* call not valid in the context's current state */
+} hr_status;
+
+typedef enum { HR_GLOBAL = 0, HR_LDS = 1 } hr_space;
+/* An atomic load counts as HR_ATOMIC: atomics are the third access class of
+ * the paper's state machine (Sec. III-B). */
+typedef enum { HR_READ = 0, HR_WRITE = 1, HR_ATOMIC = 2 } hr_kind;
+
+typedef struct {
+    uint32_t ring_capacity;  /* race records kept on the device; 0: 65536 */
+    uint32_t bc_bits;        /* block-clock width 1..8; 0: 8 */
+    uint32_t wc_bits;        /* wave-clock width 1..6; 0: 6 */
+    uint32_t flags;          /* HR_CFG_* bits */
+    uint64_t shadow_budget;  /* cap on shadow bytes of this context; 0: none */
+} hr_config;
+
+/* Count every checked access in a device counter (read by hr_check_count). */
+#define HR_CFG_COUNT_CHECKS 1u
+
+/* One flagged location, 32 bytes.  The key is (space, region, block if LDS,
+ * index); the remaining fields describe the access that completed the race. */
+typedef struct {
+    uint8_t space;          /* hr_space */
+    uint8_t pad[3];
+    uint32_t region;        /* region id (global) or LDS array id */
+    uint32_t block;         /* owning block (LDS) / accessing block (global) */
+    uint32_t launch;        /* launch sequence number within the job */
+    uint64_t index;         /* element index within the region */
+    uint32_t tid;           /* thread index within its block */
+    uint32_t state_before;  /* low 32 bits of the shadow word before the race */
+} hr_race;
+
+/* Create a context whose default stream is `stream`.  Allocates the report
+ * ring and counters on the current HIP device.  cfg may be NULL (defaults).
+ * Errors: HR_E_INVAL (cfg out of range), HR_E_NOMEM, HR_E_HIP. */
+hr_status hr_ctx_create(hr_ctx* out, const hr_config* cfg, void* stream);
+
+/* Free every device allocation of the context.  Blocks until its default
+ * stream is idle. */
+hr_status hr_ctx_destroy(hr_ctx c);
+
+/* Monitor `bytes` of device memory at data_dev as 4-byte elements (the
+ * shadow-per-element layout of paper Sec. III-A, Fig. 2): allocates an
+ * 8-byte shadow word per element, owned by the context and cleared to the
+ * initial state.  Returns the region id (0..15) in *region_out.
+ * Errors: HR_E_INVAL (elem_bytes != 4, bytes not a multiple of 4, 16 regions
+ * in use), HR_E_NOMEM (allocation failed or shadow budget exceeded). */
+hr_status hr_shadow_alloc(hr_ctx c, const void* data_dev, size_t bytes, uint32_t elem_bytes,
+                          uint32_t* region_out);
+
+/* Copy the plain-old-data block that instrumented kernels receive (shadow
+ * pointers, region sizes, report ring, current launch epoch) into out
+ * (host memory, cap bytes).  *size_out receives its size.  The block is
+ * valid until the next hr_kernel_end.  Errors: HR_E_INVAL (cap too small). */
+hr_status hr_dev_args(hr_ctx c, void* out, size_t cap, size_t* size_out);
+
+/* Mark a kernel-launch boundary: every access of the launches before it
+ * happens before every access after it.  Advances the launch epoch; every
+ * 512 launches it clears the shadow on `stream` (races already found stay in
+ * the ring).  Asynchronous. */
+hr_status hr_kernel_end(hr_ctx c, void* stream);
+
+/* Start a new job on the same regions: clear shadow memory, report ring,
+ * counters and warnings, and restart the launch count.  Asynchronous. */
+hr_status hr_reset(hr_ctx c, void* stream);
+
+/* Synchronise `stream`, then copy out the flagged set: one record per racy
+ * key, sorted by (space, region, block if LDS, index), unique.  Writes up to
+ * cap records to out (host) and the full count to *n_out.  Returns the
+ * warning bits, HR_E_INVAL if cap is too small (*n_out then holds the count),
+ * or HR_E_HIP. */
+hr_status hr_report(hr_ctx c, hr_race* out, size_t cap, size_t* n_out, void* stream);
+
+/* Synchronise `stream` and read the checked-access counter (only counts when
+ * the context was created with HR_CFG_COUNT_CHECKS). */
+hr_status hr_check_count(hr_ctx c, uint64_t* out, void* stream);
+
+/* Host evaluation of the device transition function, for verification of
+ * the state machine; not used by the checking path.  space: hr_space; old:
+ * shadow word (low 32 bits for LDS); kind: hr_kind; the identity is the
+ * access's launch, block, thread-in-block and block/wave clocks.  Writes the
+ * new shadow word. */
+hr_status hr_fsm_step(uint32_t space, uint64_t old, uint32_t kind, uint32_t launch,
+                      uint32_t block, uint32_t thread, uint32_t bc, uint32_t wc,
+                      uint64_t* new_out);
+
+/* ----------------------------------------------------------------------
+ * Instrumented workloads.  Each *_check entry launches one instrumented
+ * kernel on `stream` (the caller calls hr_kernel_end after it); each *_plain
+ * entry launches the same kernel without hooks.  Data pointers are device
+ * pointers; region ids come from hr_shadow_alloc on those buffers.
+ * Errors: HR_E_INVAL (bad sizes, regions too small), HR_E_HIP.
+ * ---------------------------------------------------------------------- */
+
+/* One-block LDS tree reduction of in_dev[512] (int32) by 256 threads over 9
+ * halving steps with a block barrier after each; every thread then writes
+ * the sum to out_dev[256].  drop in 0..8 removes that step's barrier (a
+ * seeded race); other values keep all barriers.  LDS array id 0. */
+hr_status hr_reduce_check(hr_ctx c, uint32_t r_in, uint32_t r_out, const int32_t* in_dev,
+                          int32_t* out_dev, int32_t drop, void* stream);
+hr_status hr_reduce_plain(const int32_t* in_dev, int32_t* out_dev, int32_t drop, void* stream);
+
+/* One 5-point Jacobi sweep u_new = 0.2 (c + n + s + w + e) over an ny x nx
+ * fp32 grid (row-major), 16x16-thread blocks staging an 18x18 LDS tile (LDS
+ * array id 0; corners unused); neighbours outside the grid read the centre
+ * value.  seed_dev: NULL or int32 per block (row-major block order): -1, or
+ * side << 8 | offset, in which case that block's edge thread next to halo
+ * cell `offset` on `side` (0 N, 1 S, 2 W, 3 E) also writes that
+ * neighbour-owned cell of u_new (a seeded cross-block race). */
+hr_status hr_jacobi_check(hr_ctx c, uint32_t r_old, uint32_t r_new, const float* u_old_dev,
+                          float* u_new_dev, uint32_t ny, uint32_t nx, const int32_t* seed_dev,
+                          void* stream);
+hr_status hr_jacobi_plain(const float* u_old_dev, float* u_new_dev, uint32_t ny, uint32_t nx,
+                          const int32_t* seed_dev, void* stream);
+
+/* One label-propagation sweep over a CSR graph (row_ptr_dev[n+1],
+ * col_dev[m], int32), one thread per vertex v in blocks of tpb threads:
+ * l = atomic load of label[v]; for every edge (v, u): atomic min of l into
+ * label[u], or, where mask_dev[e] != 0, a plain read and plain write of
+ * label[u] (a seeded race).  r_row_ptr / r_col: region ids to also monitor
+ * the CSR reads, or UINT32_MAX. */
+hr_status hr_labelprop_check(hr_ctx c, uint32_t r_label, uint32_t r_row_ptr, uint32_t r_col,
+                             int32_t* label_dev, const int32_t* row_ptr_dev,
+                             const int32_t* col_dev, const uint8_t* mask_dev, uint32_t n,
+                             uint32_t tpb, void* stream);
+hr_status hr_labelprop_plain(int32_t* label_dev, const int32_t* row_ptr_dev,
+                             const int32_t* col_dev, const uint8_t* mask_dev, uint32_t n,
+                             uint32_t tpb, void* stream);
+
+/* One launch of an access program: `blocks` blocks of `threads` threads run
+ * `phases` phases; in phase p thread t of logical block b performs the
+ * operations ops_dev[op_off_dev[i] .. op_off_dev[i+1]) with
+ * i = (p * blocks + b) * threads + t, then the phase ends with nothing
+ * (scope 0), a wave barrier in waves whose bit is set in wave_mask_dev[p]
+ * (scope 1) or a block barrier (scope 2).  Operation word: bits 0..23 index,
+ * 24..26 program region (global: regions_host[region] is the context region;
+ * LDS: array 0 of lds_words int32), 27..28 hr_kind, 29 space.  Reads load,
+ * writes store, atomics add 1.  block_map_dev: NULL or a permutation giving
+ * the logical block of each hardware block.  n_ops / n_op_off bound the
+ * arrays; out-of-range operations are skipped and reported as
+ * HR_W_OUT_OF_RANGE.  Limits: threads <= 1024, lds_words <= 8192. */
+hr_status hr_program_check(hr_ctx c, const uint32_t* regions_host, uint32_t n_regions,
+                           uint32_t blocks, uint32_t threads, uint32_t phases,
+                           const uint8_t* scope_dev, const uint64_t* wave_mask_dev,
+                           const int32_t* op_off_dev, size_t n_op_off, const uint32_t* ops_dev,
+                           size_t n_ops, const uint32_t* block_map_dev, uint32_t lds_words,
+                           void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HR_H */

@@ -1,0 +1,233 @@
+// Device side of the race checker: what instrumented HIP kernels call.
+//
+//   hr_thread t = hr_thread_make(args, logical_block, thread_in_block);
+//   ... data access ...;  hr_access<HR_READ>(args, t, region, index);
+//   hr_barrier_block(args, t);   // replaces __syncthreads()
+//   hr_barrier_wave(args, t);    // wave-scope barrier
+//
+// Each hook is the lock-free shadow update of the paper's Algorithm 1
+// (Sec. IV-B): read the shadow word, derive the thread relation and sync
+// status, step the state machine, and publish the new word with a
+// compare-and-swap, retrying on contention.  The hook need not be atomic
+// with the access it checks (Sec. III-A, Scenario 1); it only has to finish
+// before the thread passes its next barrier or its launch ends, which the
+// blocking compare-and-swap guarantees, so shadow updates are applied in an
+// order consistent with happens-before.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hr_fsm.h"
+
+#define HR_MAX_REGIONS 16
+
+// Device-flag bits (hr_kargs::ctr[HR_CTR_FLAGS]).
+#define HR_DEVF_CLOCK 1u
+#define HR_DEVF_RANGE 4u
+
+// Counter words.
+#define HR_CTR_HEAD 0     // ring append index
+#define HR_CTR_FLAGS 1    // warning bits
+#define HR_CTR_COUNT 2    // checked accesses, 64-bit (words 2, 3)
+#define HR_CTR_WORDS 4
+
+// Record appended on a transition into the race state (matches hr_race).
+struct hr_race_rec {
+    uint8_t space;
+    uint8_t pad[3];
+    uint32_t region;
+    uint32_t block;
+    uint32_t launch;
+    uint64_t index;
+    uint32_t tid;
+    uint32_t state_before;
+};
+static_assert(sizeof(hr_race_rec) == 32, "race record is 32 bytes");
+
+// Plain-old-data block handed to instrumented kernels by value.
+struct hr_kargs {
+    uint64_t* shadow[HR_MAX_REGIONS];   // 8-byte shadow word per element
+    uint64_t n_elems[HR_MAX_REGIONS];   // elements per region (0: unused)
+    void* data[HR_MAX_REGIONS];         // monitored buffer of each region
+    hr_race_rec* ring;
+    uint32_t* ctr;                      // HR_CTR_* words
+    uint32_t ring_cap;
+    uint32_t launch;                    // launch epoch (9 bits)
+    uint32_t launch_seq;                // launch sequence number (reports)
+    uint32_t bc_max;                    // last valid block-clock value
+    uint32_t wc_max;                    // last valid wave-clock value
+    uint32_t count;                     // nonzero: count checked accesses
+};
+
+// Per-thread checker state, kept in registers.
+struct hr_thread {
+    uint64_t gid;        // identity fields in global-word layout
+    uint32_t lid;        // identity fields in LDS-word layout
+    uint32_t block;      // logical block id
+    uint32_t thread;     // thread index within the block
+    uint32_t bc, wc;     // block and wave clocks
+    uint32_t enabled;    // cleared after a clock overflow
+};
+
+__device__ __forceinline__ hr_thread hr_thread_make(const hr_kargs& a, uint32_t block,
+                                                    uint32_t thread)
+{
+    hr_thread t;
+    t.block = block;
+    t.thread = thread;
+    t.bc = 0;
+    t.wc = 0;
+    t.enabled = 1;
+    t.gid = hr::g::pack_id(a.launch, block, thread, 0, 0);
+    t.lid = hr::l::pack_id(thread, 0, 0);
+    return t;
+}
+
+__device__ __forceinline__ void hr_set_flag(const hr_kargs& a, uint32_t bit)
+{
+    __hip_atomic_fetch_or(a.ctr + HR_CTR_FLAGS, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void hr_count(const hr_kargs& a)
+{
+    if (a.count) {
+        const uint64_t m = __ballot(1);
+        if (__lane_id() == (uint32_t)__builtin_ctzll(m))
+            __hip_atomic_fetch_add((unsigned long long*)(a.ctr + HR_CTR_COUNT),
+                                   (unsigned long long)__popcll(m), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+__device__ __forceinline__ void hr_ring_push(const hr_kargs& a, uint32_t space, uint32_t region,
+                                             uint32_t block, uint64_t index, uint32_t tid,
+                                             uint32_t before)
+{
+    const uint32_t slot = __hip_atomic_fetch_add(a.ctr + HR_CTR_HEAD, 1u, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+    if (slot < a.ring_cap) {
+        hr_race_rec r;
+        r.space = (uint8_t)space;
+        r.pad[0] = r.pad[1] = r.pad[2] = 0;
+        r.region = region;
+        r.block = block;
+        r.launch = a.launch_seq;
+        r.index = index;
+        r.tid = tid;
+        r.state_before = before;
+        a.ring[slot] = r;
+    }
+}
+
+// Check one access of kind KIND (0 read, 1 write, 2 atomic) to element
+// `index` of global region `region`.
+template <int KIND>
+__device__ __forceinline__ void hr_access(const hr_kargs& a, const hr_thread& t,
+                                          uint32_t region, uint64_t index)
+{
+    if (!t.enabled) return;
+    hr_count(a);
+    if (region >= HR_MAX_REGIONS || index >= a.n_elems[region]) {
+        hr_set_flag(a, HR_DEVF_RANGE);
+        return;
+    }
+    constexpr uint32_t k = KIND == 0 ? hr::CL_R : (KIND == 2 ? hr::CL_A : hr::CL_X);
+    uint64_t* sp = a.shadow[region] + index;
+    uint64_t old = __hip_atomic_load(sp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (;;) {
+        const uint64_t nw = hr::g::step(old, t.gid, k);
+        if (nw == old) return;
+        uint64_t seen = old;
+        if (__hip_atomic_compare_exchange_strong(sp, &seen, nw, __ATOMIC_RELAXED,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+            if (nw == hr::T_RACE)
+                hr_ring_push(a, 0, region, t.block, index, t.thread, (uint32_t)old);
+            return;
+        }
+        old = seen;
+    }
+}
+
+// Check one access to word `index` of a block's LDS array `array_id`, whose
+// 4-byte shadow words live in LDS at `sh` (n_words of them, cleared to 0 at
+// block start).
+template <int KIND>
+__device__ __forceinline__ void hr_access_lds(const hr_kargs& a, const hr_thread& t,
+                                              uint32_t* sh, uint32_t n_words, uint32_t array_id,
+                                              uint32_t index)
+{
+    if (!t.enabled) return;
+    hr_count(a);
+    if (index >= n_words) {
+        hr_set_flag(a, HR_DEVF_RANGE);
+        return;
+    }
+    constexpr uint32_t k = KIND == 0 ? hr::CL_R : (KIND == 2 ? hr::CL_A : hr::CL_X);
+    uint32_t* sp = sh + index;
+    uint32_t old = __hip_atomic_load(sp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    for (;;) {
+        const uint32_t nw = hr::l::step(old, t.lid, k);
+        if (nw == old) return;
+        uint32_t seen = old;
+        if (__hip_atomic_compare_exchange_strong(sp, &seen, nw, __ATOMIC_RELAXED,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) {
+            if (nw == hr::T_RACE) hr_ring_push(a, 1, array_id, t.block, index, t.thread, old);
+            return;
+        }
+        old = seen;
+    }
+}
+
+// Runtime-kind forms (used where the kind is data, as in the interpreter).
+__device__ __forceinline__ void hr_access_k(const hr_kargs& a, const hr_thread& t, uint32_t kind,
+                                            uint32_t region, uint64_t index)
+{
+    if (kind == 0) hr_access<0>(a, t, region, index);
+    else if (kind == 1) hr_access<1>(a, t, region, index);
+    else hr_access<2>(a, t, region, index);
+}
+
+__device__ __forceinline__ void hr_access_lds_k(const hr_kargs& a, const hr_thread& t,
+                                                uint32_t kind, uint32_t* sh, uint32_t n_words,
+                                                uint32_t array_id, uint32_t index)
+{
+    if (kind == 0) hr_access_lds<0>(a, t, sh, n_words, array_id, index);
+    else if (kind == 1) hr_access_lds<1>(a, t, sh, n_words, array_id, index);
+    else hr_access_lds<2>(a, t, sh, n_words, array_id, index);
+}
+
+__device__ __forceinline__ void hr_retag(const hr_kargs& a, hr_thread& t)
+{
+    t.gid = hr::g::pack_id(a.launch, t.block, t.thread, t.bc, t.wc);
+    t.lid = hr::l::pack_id(t.thread, t.bc, t.wc);
+}
+
+// Block barrier: every thread of the block must call it (as __syncthreads).
+// Advances the block clock and restarts the wave clock (paper Sec. III-A,
+// Scenario 2: the block-scalar clock BC advances at each block barrier).
+__device__ __forceinline__ void hr_barrier_block(const hr_kargs& a, hr_thread& t)
+{
+    __syncthreads();
+    t.bc += 1;
+    t.wc = 0;
+    if (t.bc > a.bc_max && t.enabled) {
+        t.enabled = 0;
+        hr_set_flag(a, HR_DEVF_CLOCK);
+    }
+    hr_retag(a, t);
+}
+
+// Wave barrier: every lane of the wave must call it.  Lanes of a wave are
+// not otherwise ordered by the checker, whatever the hardware does.
+__device__ __forceinline__ void hr_barrier_wave(const hr_kargs& a, hr_thread& t)
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    t.wc += 1;
+    if (t.wc > a.wc_max && t.enabled) {
+        t.enabled = 0;
+        hr_set_flag(a, HR_DEVF_CLOCK);
+    }
+    hr_retag(a, t);
+}

@@ -1,0 +1,169 @@
+// Per-location race-check state machine and its shadow-word encodings.
+//
+// The paper (Sec. III, "Design of HiRace") summarises the whole access
+// history of one memory location by the hierarchical scope shared by its
+// accessors plus the last accessor's identity and barrier clocks, packed in a
+// constant-size shadow word and advanced by an atomic compare-and-swap
+// (Sec. IV-B, Algorithm 1: unpack, compare thread ids, check sync, look up
+// the transition, pack).  Its full 25-state machine is not published; the
+// machine below is this library's own, built on the same idea and exact for
+// launch, block-barrier and wave-barrier happens-before.
+//
+// Access classes: R = plain reads only, A = atomics only, X = a write, or
+// reads and atomics together.  Encoded as 2-bit masks R=1, A=2, X=3 so that
+// the join of two classes is their OR, and class c conflicts with access
+// class k exactly when (c | k) == 3 (two reads never conflict, two atomics
+// never conflict, everything else does; Sec. II-A and Sec. III-B).
+//
+// States (tag + classes), relative to the current launch:
+//   INIT               never accessed (all-zero word)
+//   RACE               a race has been seen (sticky)
+//   MB(k)              accesses from >= 2 blocks, all of class k in {R, A}
+//   MW(cL, k)          one block; in its latest block epoch >= 2 waves, all
+//                      of class k; cL = class of the block's whole launch
+//   MT(cL, cB, k)      one block, one wave in the latest block epoch (class
+//                      cB); >= 2 threads in that wave's latest wave epoch,
+//                      all of class k
+//   ST(cL, cB, cW)     as MT but one thread in the latest wave epoch, of
+//                      class cW
+// with cW <= cB <= cL in the class order.  Homogeneous multi-accessor summaries
+// are exact because any two of their accesses from different threads are
+// unordered, so they hold a concurrent access of class k from another
+// accessor for every later access in the same scope and epoch.
+//
+// A state keeps only the identity fields it needs (launch; + block, block
+// clock; + wave, wave clock; + thread), which makes the encoding canonical:
+// an access that changes nothing produces exactly the old word, and the hook
+// skips its compare-and-swap.
+#pragma once
+#include <stdint.h>
+
+#if defined(__HIPCC__)
+#define HR_HD __host__ __device__ __forceinline__
+#else
+#define HR_HD inline
+#endif
+
+namespace hr {
+
+enum : uint32_t { CL_R = 1u, CL_A = 2u, CL_X = 3u };
+enum : uint32_t { T_INIT = 0u, T_RACE = 1u, T_MB = 2u, T_MW = 3u, T_MT = 4u, T_ST = 5u };
+
+// Access kinds of the C ABI (plain read, plain write, atomic) -> class.
+HR_HD uint32_t kind_class(uint32_t kind) { return kind == 0u ? CL_R : (kind == 2u ? CL_A : CL_X); }
+HR_HD bool conflicts(uint32_t cls, uint32_t k) { return (cls | k) == CL_X; }
+
+// ---------------------------------------------------------------------------
+// Global-memory shadow word, 64 bits, least significant first:
+//   tag 3 | cW 2 | cB 2 | cL 2 | wc 6 | bc 8 | thread 10 | block 22 | launch 9
+// The wave of a thread is the top 4 bits of its 10-bit thread index.
+// ---------------------------------------------------------------------------
+namespace g {
+constexpr uint32_t TAG_SH = 0, CW_SH = 3, CB_SH = 5, CL_SH = 7, WC_SH = 9, BC_SH = 15,
+                   TH_SH = 23, BL_SH = 33, LA_SH = 55;
+constexpr uint64_t TAG_M = 7ull << TAG_SH;
+constexpr uint64_t CW_M = 3ull << CW_SH, CB_M = 3ull << CB_SH, CL_M = 3ull << CL_SH;
+constexpr uint64_t WC_M = 63ull << WC_SH;
+constexpr uint64_t BC_M = 255ull << BC_SH;
+constexpr uint64_t LANE_M = 63ull << TH_SH;           // thread within its wave
+constexpr uint64_t WAVE_M = 15ull << (TH_SH + 6);     // wave within the block
+constexpr uint64_t BL_M = ((1ull << 22) - 1) << BL_SH;
+constexpr uint64_t LA_M = 511ull << LA_SH;
+constexpr uint32_t BLOCK_LIMIT = 1u << 22;
+constexpr uint32_t LAUNCH_BITS = 9;
+
+// Identity fields of the accessing thread, packed in place.
+HR_HD uint64_t pack_id(uint32_t launch, uint32_t block, uint32_t thread, uint32_t bc, uint32_t wc)
+{
+    return ((uint64_t)(launch & 511u) << LA_SH) | ((uint64_t)(block & (BLOCK_LIMIT - 1)) << BL_SH) |
+           ((uint64_t)(thread & 1023u) << TH_SH) | ((uint64_t)(bc & 255u) << BC_SH) |
+           ((uint64_t)(wc & 63u) << WC_SH);
+}
+
+HR_HD uint64_t mk(uint32_t tag, uint32_t cl, uint32_t cb, uint32_t cw)
+{
+    return ((uint64_t)tag << TAG_SH) | ((uint64_t)cl << CL_SH) | ((uint64_t)cb << CB_SH) |
+           ((uint64_t)cw << CW_SH);
+}
+
+// One transition: old shadow word, identity of the access, class k of the access.
+HR_HD uint64_t step(uint64_t old, uint64_t id, uint32_t k)
+{
+    const uint32_t tag = (uint32_t)(old & TAG_M);
+    if (tag == T_RACE) return old;
+    const uint64_t d = old ^ id;
+    const uint32_t cl = (uint32_t)(old >> CL_SH) & 3u;
+    const uint32_t cb = (uint32_t)(old >> CB_SH) & 3u;
+    const uint32_t cw = (uint32_t)(old >> CW_SH) & 3u;
+    const uint64_t race = T_RACE;
+    const uint64_t keep_t = LA_M | BL_M | BC_M | WAVE_M | LANE_M | WC_M;   // ST
+    const uint64_t keep_w = LA_M | BL_M | BC_M | WAVE_M | WC_M;            // MT
+    const uint64_t keep_b = LA_M | BL_M | BC_M;                           // MW
+    // First access of this launch: everything earlier is ordered before it.
+    if (tag == T_INIT || (d & LA_M)) return mk(T_ST, k, k, k) | (id & keep_t);
+    // >= 2 blocks: every access meets a concurrent one of class cb.
+    if (tag == T_MB) return conflicts(cb, k) ? race : old;
+    // Another block: concurrent with everything the stored block did.
+    if (d & BL_M) return conflicts(cl, k) ? race : (mk(T_MB, 0, k, 0) | (id & LA_M));
+    // Same block, later block epoch: ordered after the stored history.
+    if (d & BC_M) return mk(T_ST, cl | k, k, k) | (id & keep_t);
+    // Same block epoch with >= 2 waves.
+    if (tag == T_MW) return conflicts(cb, k) ? race : old;
+    // Another wave in the same block epoch.
+    if (d & WAVE_M) return conflicts(cb, k) ? race : (mk(T_MW, cl, k, 0) | (id & keep_b));
+    // Same wave, later wave epoch.
+    if (d & WC_M) return mk(T_ST, cl | k, cb | k, k) | (id & keep_t);
+    // Same wave epoch with >= 2 threads.
+    if (tag == T_MT) return conflicts(cw, k) ? race : old;
+    // Another thread of the same wave epoch.
+    if (d & LANE_M) return conflicts(cw, k) ? race : (mk(T_MT, cl, cb, k) | (id & keep_w));
+    // Same thread.
+    return mk(T_ST, cl | k, cb | k, cw | k) | (id & keep_t);
+}
+}  // namespace g
+
+// ---------------------------------------------------------------------------
+// LDS shadow word, 32 bits: tag 3 | cW 2 | cB 2 | wc 6 | bc 8 | thread 10.
+// LDS is private to one block and one launch, so there is no launch, block,
+// multi-block state or launch-wide class.
+// ---------------------------------------------------------------------------
+namespace l {
+constexpr uint32_t TAG_SH = 0, CW_SH = 3, CB_SH = 5, WC_SH = 7, BC_SH = 13, TH_SH = 21;
+constexpr uint32_t TAG_M = 7u << TAG_SH;
+constexpr uint32_t WC_M = 63u << WC_SH;
+constexpr uint32_t BC_M = 255u << BC_SH;
+constexpr uint32_t LANE_M = 63u << TH_SH;
+constexpr uint32_t WAVE_M = 15u << (TH_SH + 6);
+
+HR_HD uint32_t pack_id(uint32_t thread, uint32_t bc, uint32_t wc)
+{
+    return ((thread & 1023u) << TH_SH) | ((bc & 255u) << BC_SH) | ((wc & 63u) << WC_SH);
+}
+
+HR_HD uint32_t mk(uint32_t tag, uint32_t cb, uint32_t cw)
+{
+    return (tag << TAG_SH) | (cb << CB_SH) | (cw << CW_SH);
+}
+
+HR_HD uint32_t step(uint32_t old, uint32_t id, uint32_t k)
+{
+    const uint32_t tag = old & TAG_M;
+    if (tag == T_RACE) return old;
+    const uint32_t d = old ^ id;
+    const uint32_t cb = (old >> CB_SH) & 3u;
+    const uint32_t cw = (old >> CW_SH) & 3u;
+    const uint32_t race = T_RACE;
+    const uint32_t keep_t = BC_M | WAVE_M | LANE_M | WC_M;
+    const uint32_t keep_w = BC_M | WAVE_M | WC_M;
+    const uint32_t keep_b = BC_M;
+    if (tag == T_INIT || (d & BC_M)) return mk(T_ST, k, k) | (id & keep_t);
+    if (tag == T_MW) return conflicts(cb, k) ? race : old;
+    if (d & WAVE_M) return conflicts(cb, k) ? race : (mk(T_MW, k, 0) | (id & keep_b));
+    if (d & WC_M) return mk(T_ST, cb | k, k) | (id & keep_t);
+    if (tag == T_MT) return conflicts(cw, k) ? race : old;
+    if (d & LANE_M) return conflicts(cw, k) ? race : (mk(T_MT, cb, k) | (id & keep_w));
+    return mk(T_ST, cb | k, cw | k) | (id & keep_t);
+}
+}  // namespace l
+
+}  // namespace hr

@@ -1,0 +1,269 @@
+// Host runtime of the race checker: contexts, shadow regions, launch epochs
+// and the race report.  See hr.h for the contract of each entry point.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "hr.h"
+#include "hr_device.h"
+#include "hr_internal.h"
+
+namespace {
+
+__global__ void k_fill64(uint64_t* __restrict__ p, size_t n, uint64_t v)
+{
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = v;
+}
+
+__global__ void k_fill32(uint32_t* __restrict__ p, size_t n, uint32_t v)
+{
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = v;
+}
+
+// Clears with a kernel rather than hipMemsetAsync so that the calls stay
+// safe inside a captured HIP graph.
+hipError_t fill64(uint64_t* p, size_t n, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    const size_t blocks = std::min<size_t>((n + 255) / 256, 8192);
+    (void)hipGetLastError();   // drop stale errors of unrelated earlier calls
+    hipLaunchKernelGGL(k_fill64, dim3((unsigned)blocks), dim3(256), 0, s, p, n, 0ull);
+    return hipGetLastError();
+}
+
+hipError_t fill32(uint32_t* p, size_t n, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    const size_t blocks = std::min<size_t>((n + 255) / 256, 1024);
+    (void)hipGetLastError();   // drop stale errors of unrelated earlier calls
+    hipLaunchKernelGGL(k_fill32, dim3((unsigned)blocks), dim3(256), 0, s, p, n, 0u);
+    return hipGetLastError();
+}
+
+hr_status clear_shadows(hr_ctx c, hipStream_t s)
+{
+    for (uint32_t r = 0; r < c->n_reg; ++r)
+        if (fill64(c->reg[r].shadow, c->reg[r].elems, s) != hipSuccess) return HR_E_HIP;
+    return HR_OK;
+}
+
+struct key_less {
+    static uint32_t kb(const hr_race& r) { return r.space == HR_LDS ? r.block : 0u; }
+    bool operator()(const hr_race& a, const hr_race& b) const
+    {
+        if (a.space != b.space) return a.space < b.space;
+        if (a.region != b.region) return a.region < b.region;
+        if (kb(a) != kb(b)) return kb(a) < kb(b);
+        if (a.index != b.index) return a.index < b.index;
+        return a.launch < b.launch;
+    }
+    static bool same(const hr_race& a, const hr_race& b)
+    {
+        return a.space == b.space && a.region == b.region && kb(a) == kb(b) && a.index == b.index;
+    }
+};
+
+}  // namespace
+
+hipStream_t hr_stream(hr_ctx c, void* stream)
+{
+    return stream ? (hipStream_t)stream : c->stream;
+}
+
+extern "C" hr_status hr_ctx_create(hr_ctx* out, const hr_config* cfg, void* stream)
+{
+    if (!out) return HR_E_INVAL;
+    *out = nullptr;
+    hr_config k = {};
+    if (cfg) k = *cfg;
+    if (k.ring_capacity == 0) k.ring_capacity = 65536;
+    if (k.bc_bits == 0) k.bc_bits = 8;
+    if (k.wc_bits == 0) k.wc_bits = 6;
+    if (k.bc_bits > 8 || k.wc_bits > 6 || k.ring_capacity > (1u << 26)) return HR_E_INVAL;
+    hr_ctx c = new (std::nothrow) hr_ctx_s();
+    if (!c) return HR_E_NOMEM;
+    c->cfg = k;
+    c->stream = (hipStream_t)stream;
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return HR_E_HIP;
+    }
+    if (hipMalloc(&c->ring, sizeof(hr_race_rec) * (size_t)k.ring_capacity) != hipSuccess) {
+        delete c;
+        return HR_E_NOMEM;
+    }
+    if (hipMalloc(&c->ctr, sizeof(uint32_t) * HR_CTR_WORDS) != hipSuccess) {
+        (void)hipFree(c->ring);
+        delete c;
+        return HR_E_NOMEM;
+    }
+    if (fill32(c->ctr, HR_CTR_WORDS, c->stream) != hipSuccess) {
+        hr_ctx_destroy(c);
+        return HR_E_HIP;
+    }
+    *out = c;
+    return HR_OK;
+}
+
+extern "C" hr_status hr_ctx_destroy(hr_ctx c)
+{
+    if (!c) return HR_E_INVAL;
+    hipError_t e = hipStreamSynchronize(c->stream);
+    for (uint32_t r = 0; r < c->n_reg; ++r) (void)hipFree(c->reg[r].shadow);
+    (void)hipFree(c->ring);
+    (void)hipFree(c->ctr);
+    delete c;
+    return e == hipSuccess ? HR_OK : HR_E_HIP;
+}
+
+extern "C" hr_status hr_shadow_alloc(hr_ctx c, const void* data_dev, size_t bytes,
+                                     uint32_t elem_bytes, uint32_t* region_out)
+{
+    if (!c || !region_out || elem_bytes != 4 || bytes == 0 || bytes % 4 != 0) return HR_E_INVAL;
+    if (c->n_reg >= HR_MAX_REGIONS) return HR_E_INVAL;
+    const size_t elems = bytes / 4;
+    const uint64_t sbytes = (uint64_t)elems * 8u;
+    if (c->cfg.shadow_budget && c->shadow_bytes + sbytes > c->cfg.shadow_budget) return HR_E_NOMEM;
+    uint64_t* sh = nullptr;
+    if (hipMalloc(&sh, sbytes) != hipSuccess) return HR_E_NOMEM;
+    if (fill64(sh, elems, c->stream) != hipSuccess) {
+        (void)hipFree(sh);
+        return HR_E_HIP;
+    }
+    hr_region& r = c->reg[c->n_reg];
+    r.data = data_dev;
+    r.elems = elems;
+    r.shadow = sh;
+    c->shadow_bytes += sbytes;
+    *region_out = c->n_reg++;
+    return HR_OK;
+}
+
+void hr_fill_args(hr_ctx c, hr_kargs* a)
+{
+    *a = hr_kargs{};
+    for (uint32_t r = 0; r < c->n_reg; ++r) {
+        a->shadow[r] = c->reg[r].shadow;
+        a->n_elems[r] = c->reg[r].elems;
+        a->data[r] = const_cast<void*>(c->reg[r].data);
+    }
+    a->ring = c->ring;
+    a->ctr = c->ctr;
+    a->ring_cap = c->cfg.ring_capacity;
+    a->launch = c->launch_seq & ((1u << hr::g::LAUNCH_BITS) - 1);
+    a->launch_seq = c->launch_seq;
+    a->bc_max = (1u << c->cfg.bc_bits) - 1;
+    a->wc_max = (1u << c->cfg.wc_bits) - 1;
+    a->count = (c->cfg.flags & HR_CFG_COUNT_CHECKS) ? 1u : 0u;
+}
+
+extern "C" hr_status hr_dev_args(hr_ctx c, void* out, size_t cap, size_t* size_out)
+{
+    if (!c) return HR_E_INVAL;
+    if (size_out) *size_out = sizeof(hr_kargs);
+    if (!out || cap < sizeof(hr_kargs)) return HR_E_INVAL;
+    hr_fill_args(c, (hr_kargs*)out);
+    return HR_OK;
+}
+
+extern "C" hr_status hr_kernel_end(hr_ctx c, void* stream)
+{
+    if (!c) return HR_E_INVAL;
+    c->launch_seq += 1;
+    // The launch epoch in a shadow word has 9 bits: before it wraps, return
+    // every word to the initial state.  Exact: all earlier accesses happen
+    // before all later ones, and the races found so far are in the ring.
+    if ((c->launch_seq & ((1u << hr::g::LAUNCH_BITS) - 1)) == 0)
+        return clear_shadows(c, hr_stream(c, stream));
+    return HR_OK;
+}
+
+extern "C" hr_status hr_reset(hr_ctx c, void* stream)
+{
+    if (!c) return HR_E_INVAL;
+    hipStream_t s = hr_stream(c, stream);
+    hr_status st = clear_shadows(c, s);
+    if (st != HR_OK) return st;
+    if (fill32(c->ctr, HR_CTR_WORDS, s) != hipSuccess) return HR_E_HIP;
+    c->launch_seq = 0;
+    return HR_OK;
+}
+
+extern "C" hr_status hr_report(hr_ctx c, hr_race* out, size_t cap, size_t* n_out, void* stream)
+{
+    if (!c || !n_out) return HR_E_INVAL;
+    hipStream_t s = hr_stream(c, stream);
+    if (hipStreamSynchronize(s) != hipSuccess) return HR_E_HIP;
+    uint32_t ctr[HR_CTR_WORDS];
+    if (hipMemcpy(ctr, c->ctr, sizeof(ctr), hipMemcpyDeviceToHost) != hipSuccess) return HR_E_HIP;
+    const uint32_t head = ctr[HR_CTR_HEAD];
+    const uint32_t n_ring = std::min(head, c->cfg.ring_capacity);
+    std::vector<hr_race> recs(n_ring);
+    if (n_ring &&
+        hipMemcpy(recs.data(), c->ring, sizeof(hr_race) * n_ring, hipMemcpyDeviceToHost) != hipSuccess)
+        return HR_E_HIP;
+    int warn = 0;
+    if (ctr[HR_CTR_FLAGS] & HR_DEVF_CLOCK) warn |= HR_W_CLOCK_OVERFLOW;
+    if (ctr[HR_CTR_FLAGS] & HR_DEVF_RANGE) warn |= HR_W_OUT_OF_RANGE;
+    if (head > c->cfg.ring_capacity) {
+        // Ring overflow: race states are sticky in global shadow memory, so
+        // the global part of the flagged set is recovered from it exactly.
+        warn |= HR_W_RING_OVERFLOW;
+        for (uint32_t r = 0; r < c->n_reg; ++r) {
+            std::vector<uint64_t> sh(c->reg[r].elems);
+            if (hipMemcpy(sh.data(), c->reg[r].shadow, sizeof(uint64_t) * sh.size(),
+                          hipMemcpyDeviceToHost) != hipSuccess)
+                return HR_E_HIP;
+            for (size_t i = 0; i < sh.size(); ++i) {
+                if ((sh[i] & hr::g::TAG_M) != hr::T_RACE) continue;
+                hr_race x = {};
+                x.space = HR_GLOBAL;
+                x.region = r;
+                x.block = 0xFFFFFFFFu;
+                x.launch = 0xFFFFFFFFu;
+                x.index = i;
+                x.tid = 0xFFFFFFFFu;
+                x.state_before = 0xFFFFFFFFu;
+                recs.push_back(x);
+            }
+        }
+    }
+    std::sort(recs.begin(), recs.end(), key_less());
+    size_t n = 0;
+    for (size_t i = 0; i < recs.size(); ++i)
+        if (n == 0 || !key_less::same(recs[n - 1], recs[i])) recs[n++] = recs[i];
+    *n_out = n;
+    if (n > cap || (n && !out)) return HR_E_INVAL;
+    std::copy(recs.begin(), recs.begin() + n, out);
+    return (hr_status)warn;
+}
+
+extern "C" hr_status hr_check_count(hr_ctx c, uint64_t* out, void* stream)
+{
+    if (!c || !out) return HR_E_INVAL;
+    if (hipStreamSynchronize(hr_stream(c, stream)) != hipSuccess) return HR_E_HIP;
+    if (hipMemcpy(out, c->ctr + HR_CTR_COUNT, sizeof(uint64_t), hipMemcpyDeviceToHost) != hipSuccess)
+        return HR_E_HIP;
+    return HR_OK;
+}
+
+extern "C" hr_status hr_fsm_step(uint32_t space, uint64_t old, uint32_t kind, uint32_t launch,
+                                 uint32_t block, uint32_t thread, uint32_t bc, uint32_t wc,
+                                 uint64_t* new_out)
+{
+    if (!new_out || kind > 2 || space > 1 || thread > 1023) return HR_E_INVAL;
+    const uint32_t k = hr::kind_class(kind);
+    if (space == HR_GLOBAL) {
+        if (block >= hr::g::BLOCK_LIMIT) return HR_E_INVAL;
+        *new_out = hr::g::step(old, hr::g::pack_id(launch, block, thread, bc, wc), k);
+    } else {
+        *new_out = hr::l::step((uint32_t)old, hr::l::pack_id(thread, bc, wc), k);
+    }
+    return HR_OK;
+}

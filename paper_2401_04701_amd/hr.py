@@ -1,0 +1,265 @@
+"""ctypes binding of libhr.so (the C ABI in include/hr.h).
+
+Argument marshalling only: every step of the checking path runs in the HIP
+kernels of the library.  PyTorch supplies device memory and streams.  There
+is no fallback: if libhr.so is missing, importing this module fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libhr.so")
+
+HR_OK = 0
+HR_W_CLOCK_OVERFLOW = 1
+HR_W_RING_OVERFLOW = 2
+HR_W_OUT_OF_RANGE = 4
+HR_E_INVAL, HR_E_NOMEM, HR_E_HIP, HR_E_STATE = -1, -2, -3, -4
+HR_GLOBAL, HR_LDS = 0, 1
+HR_READ, HR_WRITE, HR_ATOMIC = 0, 1, 2
+HR_CFG_COUNT_CHECKS = 1
+NO_REGION = 0xFFFFFFFF
+
+# Global shadow-word fields (see csrc/hr_fsm.h), for decoding in tests.
+T_INIT, T_RACE, T_MB, T_MW, T_MT, T_ST = 0, 1, 2, 3, 4, 5
+
+RACE_DTYPE = np.dtype([("space", np.uint8), ("pad", np.uint8, 3), ("region", np.uint32),
+                       ("block", np.uint32), ("launch", np.uint32), ("index", np.uint64),
+                       ("tid", np.uint32), ("state_before", np.uint32)])
+assert RACE_DTYPE.itemsize == 32
+
+
+class HRError(RuntimeError):
+    def __init__(self, fn: str, status: int):
+        super().__init__(f"{fn} failed with status {status}")
+        self.status = status
+
+
+class _Config(ctypes.Structure):
+    _fields_ = [("ring_capacity", ctypes.c_uint32), ("bc_bits", ctypes.c_uint32),
+                ("wc_bits", ctypes.c_uint32), ("flags", ctypes.c_uint32),
+                ("shadow_budget", ctypes.c_uint64)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+    # Load PyTorch's HIP runtime first: libhr.so then binds to that same
+    # libamdhip64.so.7 (matched by soname), so device pointers and streams
+    # handed over by PyTorch are valid in the library.
+    import torch  # noqa: F401
+    lib = ctypes.CDLL(LIB_PATH)
+    P, i32, u32, u64, sz = (ctypes.c_void_p, ctypes.c_int, ctypes.c_uint32, ctypes.c_uint64,
+                            ctypes.c_size_t)
+    sigs = {
+        "hr_ctx_create": [P, P, P],
+        "hr_ctx_destroy": [P],
+        "hr_shadow_alloc": [P, P, sz, u32, P],
+        "hr_dev_args": [P, P, sz, P],
+        "hr_kernel_end": [P, P],
+        "hr_reset": [P, P],
+        "hr_report": [P, P, sz, P, P],
+        "hr_check_count": [P, P, P],
+        "hr_fsm_step": [u32, u64, u32, u32, u32, u32, u32, u32, P],
+        "hr_reduce_check": [P, u32, u32, P, P, ctypes.c_int32, P],
+        "hr_reduce_plain": [P, P, ctypes.c_int32, P],
+        "hr_jacobi_check": [P, u32, u32, P, P, u32, u32, P, P],
+        "hr_jacobi_plain": [P, P, u32, u32, P, P],
+        "hr_labelprop_check": [P, u32, u32, u32, P, P, P, P, u32, u32, P],
+        "hr_labelprop_plain": [P, P, P, P, u32, u32, P],
+        "hr_program_check": [P, P, u32, u32, u32, u32, P, P, P, sz, P, sz, P, u32, P],
+    }
+    for name, args in sigs.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = i32
+    return lib
+
+
+_lib = _load()
+EXPORTED = ("hr_ctx_create", "hr_ctx_destroy", "hr_shadow_alloc", "hr_dev_args",
+            "hr_kernel_end", "hr_reset", "hr_report", "hr_check_count", "hr_fsm_step",
+            "hr_reduce_check", "hr_reduce_plain", "hr_jacobi_check", "hr_jacobi_plain",
+            "hr_labelprop_check", "hr_labelprop_plain", "hr_program_check")
+
+
+def lib():
+    return _lib
+
+
+def _check(fn: str, st: int) -> int:
+    if st < 0:
+        raise HRError(fn, st)
+    return st
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def fsm_step(space: int, old: int, kind: int, launch: int, block: int, thread: int,
+             bc: int, wc: int) -> int:
+    """Host evaluation of the device transition function (verification aid)."""
+    out = ctypes.c_uint64(0)
+    _check("hr_fsm_step", _lib.hr_fsm_step(space, old, kind, launch, block, thread, bc, wc,
+                                           ctypes.byref(out)))
+    return int(out.value)
+
+
+# ---------------------------------------------------------------- plain runs
+def reduce_plain(inp, out, drop=-1, stream=None):
+    _check("hr_reduce_plain", _lib.hr_reduce_plain(_dptr(inp), _dptr(out), int(drop),
+                                                   _stream_ptr(stream)))
+
+
+def jacobi_plain(u_old, u_new, seeds=None, stream=None):
+    ny, nx = u_old.shape
+    _check("hr_jacobi_plain", _lib.hr_jacobi_plain(_dptr(u_old), _dptr(u_new), ny, nx,
+                                                   _dptr(seeds), _stream_ptr(stream)))
+
+
+def labelprop_plain(label, row_ptr, col, mask, tpb=256, stream=None):
+    n = label.shape[0]
+    _check("hr_labelprop_plain", _lib.hr_labelprop_plain(_dptr(label), _dptr(row_ptr), _dptr(col),
+                                                         _dptr(mask), n, tpb, _stream_ptr(stream)))
+
+
+class DeviceProgram:
+    """One launch of an access program, uploaded to device memory."""
+
+    def __init__(self, launch, device="cuda"):
+        import torch
+        self.blocks, self.threads, self.phases = launch.blocks, launch.threads, launch.phases
+        self.scope = torch.from_numpy(np.ascontiguousarray(launch.scope, np.uint8)).to(device)
+        self.wmask = torch.from_numpy(
+            np.ascontiguousarray(launch.wave_mask, np.uint64).view(np.int64)).to(device)
+        self.op_off = torch.from_numpy(np.ascontiguousarray(launch.op_off, np.int32)).to(device)
+        ops = np.ascontiguousarray(launch.ops, np.uint32)
+        if ops.size == 0:
+            ops = np.zeros(1, np.uint32)
+            self.n_ops = 0
+        else:
+            self.n_ops = ops.size
+        self.ops = torch.from_numpy(ops.view(np.int32)).to(device)
+
+
+class Context:
+    """A checking job: shadow regions, report ring, launch epochs."""
+
+    def __init__(self, ring_capacity=0, bc_bits=0, wc_bits=0, count_checks=False,
+                 shadow_budget=0, stream=None):
+        cfg = _Config(ring_capacity, bc_bits, wc_bits,
+                      HR_CFG_COUNT_CHECKS if count_checks else 0, shadow_budget)
+        self._c = ctypes.c_void_p(0)
+        self._stream = _stream_ptr(stream)
+        _check("hr_ctx_create", _lib.hr_ctx_create(ctypes.byref(self._c), ctypes.byref(cfg),
+                                                   self._stream))
+        self.status = 0
+
+    def close(self):
+        if self._c:
+            _check("hr_ctx_destroy", _lib.hr_ctx_destroy(self._c))
+            self._c = ctypes.c_void_p(0)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._c
+
+    def shadow_alloc(self, tensor) -> int:
+        assert tensor.is_cuda and tensor.element_size() == 4 and tensor.is_contiguous()
+        r = ctypes.c_uint32(0)
+        _check("hr_shadow_alloc", _lib.hr_shadow_alloc(self._c, _dptr(tensor),
+                                                       tensor.numel() * 4, 4, ctypes.byref(r)))
+        return int(r.value)
+
+    def dev_args(self) -> bytes:
+        size = ctypes.c_size_t(0)
+        _lib.hr_dev_args(self._c, None, 0, ctypes.byref(size))
+        buf = ctypes.create_string_buffer(size.value)
+        _check("hr_dev_args", _lib.hr_dev_args(self._c, buf, size.value, ctypes.byref(size)))
+        return buf.raw
+
+    def kernel_end(self, stream=None):
+        _check("hr_kernel_end", _lib.hr_kernel_end(self._c, _stream_ptr(stream)))
+
+    def reset(self, stream=None):
+        _check("hr_reset", _lib.hr_reset(self._c, _stream_ptr(stream)))
+
+    def report(self, stream=None):
+        """Flagged records (RACE_DTYPE array) and the warning bits."""
+        n = ctypes.c_size_t(0)
+        cap = 4096
+        while True:
+            out = np.zeros(cap, dtype=RACE_DTYPE)
+            st = _lib.hr_report(self._c, out.ctypes.data_as(ctypes.c_void_p), cap,
+                                ctypes.byref(n), _stream_ptr(stream))
+            if st == HR_E_INVAL and n.value > cap:
+                cap = int(n.value)
+                continue
+            _check("hr_report", st)
+            self.status = st
+            return out[:n.value], st
+
+    def flagged(self, stream=None) -> set:
+        recs, _ = self.report(stream)
+        return {(int(r["space"]), int(r["region"]),
+                 int(r["block"]) if r["space"] == HR_LDS else 0, int(r["index"]))
+                for r in recs}
+
+    def check_count(self, stream=None) -> int:
+        out = ctypes.c_uint64(0)
+        _check("hr_check_count", _lib.hr_check_count(self._c, ctypes.byref(out),
+                                                     _stream_ptr(stream)))
+        return int(out.value)
+
+    # ------------------------------------------------------- workloads
+    def reduce_check(self, r_in, r_out, inp, out, drop=-1, stream=None):
+        _check("hr_reduce_check", _lib.hr_reduce_check(self._c, r_in, r_out, _dptr(inp),
+                                                       _dptr(out), int(drop),
+                                                       _stream_ptr(stream)))
+
+    def jacobi_check(self, r_old, r_new, u_old, u_new, seeds=None, stream=None):
+        ny, nx = u_old.shape
+        _check("hr_jacobi_check", _lib.hr_jacobi_check(self._c, r_old, r_new, _dptr(u_old),
+                                                       _dptr(u_new), ny, nx, _dptr(seeds),
+                                                       _stream_ptr(stream)))
+
+    def labelprop_check(self, r_label, label, row_ptr, col, mask, tpb=256,
+                        r_row_ptr=NO_REGION, r_col=NO_REGION, stream=None):
+        n = label.shape[0]
+        _check("hr_labelprop_check", _lib.hr_labelprop_check(
+            self._c, r_label, r_row_ptr, r_col, _dptr(label), _dptr(row_ptr), _dptr(col),
+            _dptr(mask), n, tpb, _stream_ptr(stream)))
+
+    def program_check(self, prog: DeviceProgram, regions, lds_words, block_map=None,
+                      stream=None):
+        regs = (ctypes.c_uint32 * max(1, len(regions)))(*regions)
+        _check("hr_program_check", _lib.hr_program_check(
+            self._c, regs, len(regions), prog.blocks, prog.threads, prog.phases,
+            _dptr(prog.scope), _dptr(prog.wmask), _dptr(prog.op_off), prog.op_off.numel(),
+            _dptr(prog.ops), prog.n_ops, _dptr(block_map), lds_words, _stream_ptr(stream)))

@@ -1,0 +1,140 @@
+"""The checker's transition function (the device code, evaluated on the host
+through hr_fsm_step) against the oracle: every happens-before-consistent
+processing order of a program's accesses must reach the race state at
+exactly the locations the pairwise definition flags.  Also pins the paper's
+worked scenarios."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth_inputs as si
+from fsm_replay import random_orders, replay
+from paper_2401_04701_amd import hr
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def widen(log, narrow):
+    """Relabel threads of a log built with `narrow`-lane waves onto 64-lane
+    waves: lane l of narrow wave w becomes thread 64*w + l."""
+    out = log.copy()
+    t = out["thread"].astype(np.int64)
+    out["thread"] = ((t // narrow) * 64 + t % narrow).astype(np.uint32)
+    return out
+
+
+SETTINGS = [
+    # blocks, threads, narrow wave width, phases, max_ops, gwords, lwords, launches
+    (1, 4, 2, 3, 2, 3, 2, 2),
+    (2, 2, 1, 3, 2, 3, 2, 2),
+    (2, 4, 2, 4, 2, 4, 3, 3),
+    (3, 3, 1, 4, 2, 2, 2, 2),
+    (2, 6, 3, 3, 3, 5, 3, 2),
+]
+
+
+@pytest.mark.parametrize("setting", SETTINGS)
+def test_fsm_flags_oracle_set_in_every_order(setting):
+    blocks, threads, ww, phases, max_ops, gw, lw, launches = setting
+    racy = clean = 0
+    for s in range(40):
+        prog = si.random_program(7919 * s + blocks * 31 + threads, launches=launches,
+                                 blocks=blocks, threads=threads, phases=phases,
+                                 max_ops=max_ops, global_regions=2, global_words=gw,
+                                 lds_words=lw, kind_p=(0.5, 0.25, 0.25),
+                                 scope_p=(0.25, 0.35, 0.4), wave_width=ww)
+        log = oracle.model_program(prog, ww)
+        want = oracle.flagged(log.copy(), ww)
+        wide = widen(log, ww)
+        for order in random_orders(wide, 12, seed=s):
+            assert replay(wide, order) == want, (setting, s)
+        touched = {(int(r["space"]), int(r["region"]), int(r["lds_block"]), int(r["index"]))
+                   for r in log}
+        racy += len(want)
+        clean += len(touched - want)
+    assert racy > 0 and clean > 0
+
+
+def test_fsm_on_litmus_programs_many_orders():
+    """Larger homogeneous groups: many readers then one writer, per scope."""
+    G, L = si.SPACE_GLOBAL, si.SPACE_LDS
+    for space in (G, L):
+        for writer_epoch in (0, 1):
+            per = [[[[] for _ in range(5)] for _ in range(2)] for _ in range(2)]
+            for b in range(2 if space == G else 1):
+                for t in range(5):
+                    per[0][b][t].append(si.op_word(space, 0, si.KIND_R, 0))
+            per[writer_epoch][0][4].append(si.op_word(space, 0, si.KIND_W, 0))
+            launch = si.build_launch(2, 5, [si.SCOPE_BLOCK, 0], [0, 0], per)
+            prog = si.Program([launch], [4], 4)
+            log = oracle.model_program(prog, 2)
+            want = oracle.flagged(log.copy(), 2)
+            wide = widen(log, 2)
+            for order in random_orders(wide, 60, seed=writer_epoch):
+                assert replay(wide, order) == want
+
+
+def _thread(label):
+    b, w, t = (int(ch) for ch in label[1:])
+    return b, 64 * w + t
+
+
+def _name(word):
+    tag = word & 7
+    cl = (word >> 7) & 3
+    cb = (word >> 5) & 3
+    if tag == hr.T_RACE:
+        return "RACE"
+    if tag == hr.T_MB:
+        return "GREAD" if cb == 1 else "MB"
+    if tag in (hr.T_MW, hr.T_MT):
+        return "BREAD" if cl == 1 and (tag == hr.T_MT or cb == 1) else "MULTI"
+    if tag == hr.T_ST:
+        return "WRITE" if cl == 3 else ("READ" if cl == 1 else "ST")
+    return "INIT"
+
+
+@pytest.mark.parametrize("sc", json.load(open(os.path.join(GOLDEN, "scenarios.json")))["scenarios"],
+                         ids=lambda s: s["name"])
+def test_paper_scenarios(sc):
+    word = 0
+    kinds = {"R": hr.HR_READ, "W": hr.HR_WRITE, "A": hr.HR_ATOMIC}
+    for kind, who, bc, want in sc["steps"]:
+        b, t = _thread(who)
+        word = hr.fsm_step(hr.HR_GLOBAL, word, kinds[kind], 0, b, t, bc, 0)
+        assert _name(word) == want, (sc["name"], kind, who, want, hex(word))
+
+
+def test_race_is_sticky_and_repeat_access_is_noop():
+    rng = np.random.default_rng(5)
+    for _ in range(2000):
+        sp = int(rng.integers(0, 2))
+        args = [int(rng.integers(0, 3)), int(rng.integers(0, 3)), int(rng.integers(0, 3)),
+                int(rng.integers(0, 200)), int(rng.integers(0, 3)), int(rng.integers(0, 2))]
+        kind, launch, block, thread, bc, wc = args
+        if sp == hr.HR_LDS:
+            launch = block = 0
+        w = hr.fsm_step(sp, hr.T_RACE, kind, launch, block, thread, bc, wc)
+        assert w == hr.T_RACE
+        w1 = hr.fsm_step(sp, 0, kind, launch, block, thread, bc, wc)
+        w2 = hr.fsm_step(sp, w1, kind, launch, block, thread, bc, wc)
+        assert w1 == w2 != 0
+
+
+def test_state_changes_per_epoch_are_bounded():
+    """Within one launch a location changes state only a bounded number of
+    times: the summary classes only grow until a new epoch starts, which
+    bounds the compare-and-swap retries of contending lanes."""
+    rng = np.random.default_rng(9)
+    for _ in range(300):
+        word, changes = 0, 0
+        for _ in range(40):
+            kind = int(rng.integers(0, 3))
+            b, t = int(rng.integers(0, 3)), int(rng.integers(0, 130))
+            new = hr.fsm_step(hr.HR_GLOBAL, word, kind, 1, b, t, 0, 0)
+            changes += new != word
+            word = new
+        assert changes <= 8

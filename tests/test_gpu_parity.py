@@ -1,0 +1,264 @@
+"""GPU parity: the HIP checker's flagged (space, region, block-if-LDS, index)
+set must equal the oracle's, bit for bit, on the same seeded inputs.  The
+work is integer and exact, so the tolerance is zero.  Calls go through the
+C ABI (ctypes binding of libhr.so)."""
+import numpy as np
+import pytest
+
+import oracle
+import synth_inputs as si
+from oracle import closed_forms as cf
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2401_04701_amd import hr
+    torch.cuda.set_device(0)
+    return torch, hr
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+# ------------------------------------------------------------ reduction
+@pytest.mark.parametrize("drop", [-1] + list(range(9)))
+def test_reduce_flagged_set(env, drop):
+    torch, hr = env
+    say("reduce drop", drop)
+    x = si.reduce_input(si.master_seed(0) + drop)
+    inp = torch.from_numpy(x).cuda()
+    out = torch.zeros(256, dtype=torch.int32, device="cuda")
+    with hr.Context(count_checks=True) as ctx:
+        r_in, r_out = ctx.shadow_alloc(inp), ctx.shadow_alloc(out)
+        ctx.reduce_check(r_in, r_out, inp, out, drop=drop)
+        ctx.kernel_end()
+        got = ctx.flagged()
+        assert ctx.status == 0
+        assert ctx.check_count() == 3069
+    log = oracle.model_reduce(drop)
+    assert got == oracle.flagged(log) == cf.reduce_flagged(drop)
+    if drop < 0:
+        assert (out.cpu().numpy() == x.astype(np.int64).sum()).all()
+        out2 = torch.zeros_like(out)
+        hr.reduce_plain(inp, out2, -1)
+        torch.cuda.synchronize()
+        assert torch.equal(out, out2)
+
+
+# ------------------------------------------------------- access programs
+PROGRAMS = [
+    # seed, launches, blocks, threads, phases, max_ops, gwords, lwords, p_lds
+    (1, 2, 4, 128, 4, 2, 64, 64, 0.3),
+    (2, 3, 16, 256, 5, 3, 512, 256, 0.4),
+    (3, 2, 64, 256, 6, 2, 4096, 1024, 0.3),
+    (4, 2, 8, 1000, 4, 2, 2048, 512, 0.3),
+    (5, 2, 33, 130, 5, 3, 300, 100, 0.5),
+    (6, 4, 3, 1024, 3, 1, 1024, 2048, 0.2),
+    (7, 1, 200, 64, 8, 2, 8192, 64, 0.3),
+]
+
+
+def run_program(torch, hr, prog, block_perm_seed=None, ctx_kwargs=None):
+    data = [torch.zeros(w, dtype=torch.int32, device="cuda") for w in prog.global_words]
+    with hr.Context(**(ctx_kwargs or {})) as ctx:
+        regs = [ctx.shadow_alloc(d) for d in data]
+        for launch in prog.launches:
+            dp = hr.DeviceProgram(launch)
+            bmap = None
+            if block_perm_seed is not None:
+                perm = np.random.default_rng(block_perm_seed).permutation(launch.blocks)
+                bmap = torch.from_numpy(perm.astype(np.int32)).cuda()
+            ctx.program_check(dp, regs, prog.lds_words, block_map=bmap)
+            ctx.kernel_end()
+        got = ctx.flagged()
+        return got, ctx.status
+
+
+@pytest.mark.parametrize("cfg", PROGRAMS, ids=lambda c: f"seed{c[0]}_b{c[2]}_t{c[3]}")
+def test_program_flagged_set(env, cfg):
+    torch, hr = env
+    seed, launches, blocks, threads, phases, max_ops, gw, lw, p_lds = cfg
+    prog = si.random_program(seed, launches=launches, blocks=blocks, threads=threads,
+                             phases=phases, max_ops=max_ops, global_regions=3,
+                             global_words=gw, lds_words=lw, p_lds=p_lds)
+    want = oracle.flagged_program(prog)
+    say("program", cfg, "oracle flags", len(want))
+    got, st = run_program(torch, hr, prog)
+    assert st == 0
+    assert got == want
+    # a different mapping of logical blocks to hardware blocks changes the
+    # schedule but not the verdict
+    got2, _ = run_program(torch, hr, prog, block_perm_seed=seed)
+    assert got2 == want
+
+
+def test_program_race_free_variants(env):
+    torch, hr = env
+    for kinds in [(1.0, 0.0, 0.0), (0.0, 0.0, 1.0)]:
+        prog = si.random_program(17, launches=2, blocks=32, threads=256, phases=4,
+                                 max_ops=3, global_regions=2, global_words=128,
+                                 lds_words=64, kind_p=kinds)
+        say("race-free program", kinds)
+        got, st = run_program(torch, hr, prog)
+        assert got == set() and st == 0
+
+
+def test_program_empty_and_idle(env):
+    torch, hr = env
+    say("empty program")
+    prog = si.random_program(3, launches=2, blocks=5, threads=70, phases=3, max_ops=0)
+    got, st = run_program(torch, hr, prog)
+    assert got == set() and st == 0
+
+
+# --------------------------------------------------------------- Jacobi
+JACOBI = [(64, 64, 3, 6), (50, 37, 2, 5), (33, 80, 4, 8), (96, 17, 3, 4), (16, 16, 2, 0),
+          (256, 192, 3, 20)]
+
+
+def run_jacobi(torch, hr, ny, nx, launches, tab, ctx_kwargs=None, grid_seed=1):
+    u = [torch.from_numpy(si.jacobi_grid(ny, nx, grid_seed)).cuda(),
+         torch.zeros((ny, nx), dtype=torch.float32, device="cuda")]
+    tab_d = None if tab is None else torch.from_numpy(tab).cuda()
+    with hr.Context(**(ctx_kwargs or {})) as ctx:
+        regs = [ctx.shadow_alloc(u[0]), ctx.shadow_alloc(u[1])]
+        for L in range(launches):
+            ctx.jacobi_check(regs[L % 2], regs[(L + 1) % 2], u[L % 2], u[(L + 1) % 2], tab_d)
+            ctx.kernel_end()
+        got = ctx.flagged()
+        st = ctx.status
+        count = ctx.check_count() if ctx_kwargs and ctx_kwargs.get("count_checks") else None
+    return got, st, u, count
+
+
+@pytest.mark.parametrize("ny,nx,launches,count", JACOBI)
+def test_jacobi_flagged_set(env, ny, nx, launches, count):
+    torch, hr = env
+    seeds = si.jacobi_seeds(ny, nx, si.master_seed(1) + nx, count=count)
+    tab = si.jacobi_seed_table(ny, nx, seeds)
+    say("jacobi", ny, nx, launches, count)
+    got, st, _, n = run_jacobi(torch, hr, ny, nx, launches, tab, {"count_checks": True})
+    log = oracle.model_jacobi(ny, nx, launches, tab)
+    assert st == 0
+    assert n == log.shape[0]
+    assert got == oracle.flagged(log) == cf.jacobi_flagged(ny, nx, launches, seeds)
+
+
+def test_jacobi_race_free_output_matches_plain(env):
+    torch, hr = env
+    ny, nx = 200, 130
+    say("jacobi race-free vs plain", ny, nx)
+    got, st, u, _ = run_jacobi(torch, hr, ny, nx, 3, None)
+    assert got == set() and st == 0
+    p = [torch.from_numpy(si.jacobi_grid(ny, nx, 1)).cuda(), torch.zeros_like(u[1])]
+    for L in range(3):
+        hr.jacobi_plain(p[L % 2], p[(L + 1) % 2], None)
+    torch.cuda.synchronize()
+    assert torch.equal(u[1], p[1]) and torch.equal(u[0], p[0])
+
+
+# ------------------------------------------------------- label propagation
+@pytest.mark.parametrize("scale,edges,p,tpb", [(10, 8 * 1024, 0.01, 256), (12, 8 * 4096, 0.02, 256),
+                                               (13, 8 * 8192, 0.01, 128), (9, 4096, 0.05, 1000)])
+def test_labelprop_flagged_set(env, scale, edges, p, tpb):
+    torch, hr = env
+    rp, col, mask = si.labelprop_graph(scale, edges, si.master_seed(2) + scale, p)
+    n = rp.shape[0] - 1
+    say("labelprop", scale, edges, p, tpb)
+    label = torch.arange(n, dtype=torch.int32, device="cuda")
+    rp_d, col_d = torch.from_numpy(rp).cuda(), torch.from_numpy(col).cuda()
+    mask_d = torch.from_numpy(mask).cuda()
+    with hr.Context(count_checks=True) as ctx:
+        r_lab = ctx.shadow_alloc(label)
+        r_rp, r_col = ctx.shadow_alloc(rp_d), ctx.shadow_alloc(col_d)
+        for L in range(3):
+            ctx.labelprop_check(r_lab, label, rp_d, col_d, mask_d, tpb=tpb,
+                                r_row_ptr=r_rp, r_col=r_col)
+            ctx.kernel_end()
+        got = ctx.flagged()
+        cnt = ctx.check_count()
+        assert ctx.status == 0
+    log = oracle.model_labelprop(rp, col, mask, 3, tpb, monitor_csr=True)
+    assert cnt == log.shape[0]
+    assert got == oracle.flagged(log) == cf.labelprop_flagged(rp, col, mask)
+
+
+# ----------------------------------------------------- failure handling
+def test_clock_overflow_stops_with_warning(env):
+    """bc_bits=2 allows 3 block barriers; a 6-barrier program overflows.  The
+    warning is set and races seen before the overflow are still reported."""
+    torch, hr = env
+    G = si.SPACE_GLOBAL
+    per = [[[[] for _ in range(64)] for _ in range(2)] for _ in range(6)]
+    per[0][0][0].append(si.op_word(G, 0, si.KIND_W, 3))
+    per[0][1][0].append(si.op_word(G, 0, si.KIND_W, 3))       # race, epoch 0
+    per[5][0][0].append(si.op_word(G, 0, si.KIND_W, 5))
+    per[5][1][0].append(si.op_word(G, 0, si.KIND_W, 5))       # race after overflow
+    launch = si.build_launch(2, 64, [2] * 6, [0] * 6, per)
+    prog = si.Program([launch], [16], 16)
+    say("clock overflow")
+    got, st = run_program(torch, hr, prog, ctx_kwargs={"bc_bits": 2})
+    assert st & hr.HR_W_CLOCK_OVERFLOW
+    assert got == {(0, 0, 0, 3)}
+    got, st = run_program(torch, hr, prog)
+    assert st == 0 and got == {(0, 0, 0, 3), (0, 0, 0, 5)}
+
+
+def test_ring_overflow_recovers_global_set(env):
+    torch, hr = env
+    prog = si.random_program(23, launches=2, blocks=16, threads=256, phases=3, max_ops=2,
+                             global_regions=2, global_words=256, lds_words=64, p_lds=0.3)
+    want = oracle.flagged_program(prog)
+    want_global = {k for k in want if k[0] == 0}
+    assert len(want) > 4
+    say("ring overflow")
+    got, st = run_program(torch, hr, prog, ctx_kwargs={"ring_capacity": 1})
+    assert st & hr.HR_W_RING_OVERFLOW
+    assert {k for k in got if k[0] == 0} == want_global
+    assert got <= want
+
+
+def test_out_of_range_operation_is_skipped(env):
+    torch, hr = env
+    G = si.SPACE_GLOBAL
+    per = [[[[si.op_word(G, 0, si.KIND_W, 100)], [si.op_word(1, 0, si.KIND_W, 50)]]]]
+    launch = si.build_launch(1, 2, [0], [0], per)
+    prog = si.Program([launch], [16], 16)
+    say("out of range")
+    got, st = run_program(torch, hr, prog)
+    assert st & hr.HR_W_OUT_OF_RANGE and got == set()
+
+
+def test_shadow_budget_and_bad_arguments(env):
+    torch, hr = env
+    say("budget")
+    x = torch.zeros(1024, dtype=torch.int32, device="cuda")
+    with hr.Context(shadow_budget=4096) as ctx:
+        with pytest.raises(hr.HRError) as e:
+            ctx.shadow_alloc(x)
+        assert e.value.status == hr.HR_E_NOMEM
+    with hr.Context() as ctx:
+        r = ctx.shadow_alloc(x)
+        y = torch.zeros(256, dtype=torch.int32, device="cuda")
+        with pytest.raises(hr.HRError):          # region too small for 512 inputs
+            ctx.reduce_check(r, r, y, y, -1)
+
+
+def test_launch_epoch_wrap(env):
+    """More than 512 launches: the shadow is cleared when the 9-bit launch
+    epoch wraps; the flagged set is unchanged."""
+    torch, hr = env
+    ny, nx = 48, 48
+    seeds = si.jacobi_seeds(ny, nx, 77, count=2)
+    tab = si.jacobi_seed_table(ny, nx, seeds)
+    say("epoch wrap")
+    got, st, _, _ = run_jacobi(torch, hr, ny, nx, 530, tab)
+    assert st == 0
+    assert got == cf.jacobi_flagged(ny, nx, 530, seeds)
+    got, st, _, _ = run_jacobi(torch, hr, ny, nx, 530, None)
+    assert got == set()
