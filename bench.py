@@ -1,0 +1,272 @@
+#!/usr/bin/env python3
+"""Race-check throughput on one MI355X.
+
+Workload: a 5-point Jacobi stencil over a 4096 x 4096 fp32 grid, 16 x 16
+thread blocks staging an 18 x 18 LDS tile, 20 launches ping-ponging two
+arrays (a launch boundary orders every launch after the previous one), with
+0.1 % of the blocks (66) seeded to also write one neighbour-owned halo cell
+(a cross-block race).  Every global and LDS access is checked by the HIP
+hook.  One step is one whole checking job on resident inputs: reset the
+shadow, 20 instrumented launches with their launch boundaries, and the
+report (device-to-host copy of the flagged set).
+
+Prints one JSON line: checks/s, slowdown against the same kernel without
+hooks, p50/p99 per-launch latency, the roofline of the instrumented kernel,
+measured device peaks, and the CPU oracle timed on a sample of the job.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+NY = NX = 4096
+LAUNCHES = 20
+HBM_PEAK_GBS = 8000.0          # MI355X published HBM3E bandwidth
+
+
+def jacobi_check_counts(ny: int, nx: int, seeded_writes: int):
+    """Instrumented accesses of one sweep: (global checks, LDS checks)."""
+    cells = ny * nx
+    halo = 2 * nx * (((ny + 15) // 16) - 1) + 2 * ny * (((nx + 15) // 16) - 1)
+    g_read, l_write = cells + halo, cells + halo
+    l_read = 5 * cells - 2 * nx - 2 * ny
+    g_write = cells + seeded_writes
+    return g_read + g_write, l_write + l_read
+
+
+def algorithmic_bytes_per_launch(ny: int, nx: int) -> int:
+    """HBM bytes one checked sweep must move: the stencil's own data (4-byte
+    read of u_old and 4-byte write of u_new per cell) plus, for each of the
+    two monitored arrays, one 8-byte shadow word read and written back per
+    cell (every word changes state at least once per launch)."""
+    cells = ny * nx
+    return cells * (4 + 4) + 2 * cells * (8 + 8)
+
+
+def pct(a, q):
+    return float(np.percentile(np.asarray(a, dtype=np.float64), q))
+
+
+def cpu_baseline():
+    """The oracle, single-threaded, on a 512 x 512 sample of the job."""
+    import oracle
+    import synth_inputs as si
+    n = 512
+    seeds = si.jacobi_seeds(n, n, si.master_seed(1))
+    tab = si.jacobi_seed_table(n, n, seeds)
+    t0 = time.perf_counter()
+    checks = 0
+    flagged = set()
+    for L in range(LAUNCHES):
+        log = oracle.model_jacobi(n, n, 1, tab, launch0=L)
+        checks += log.shape[0]
+        flagged |= oracle.flagged(log)
+    dt = time.perf_counter() - t0
+    return {"value": checks / dt, "unit": "checks/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n}x{n} grid (1/64 of the cells), {LAUNCHES} launches, "
+                      f"{len(seeds)} seeded block: access-log generation plus pairwise check, "
+                      f"{checks} checks in {dt:.1f} s, {len(flagged)} flagged",
+            "seconds": dt}
+
+
+def measure_peaks(torch, hr, stream):
+    """Measured agent-scope atomic and HBM peaks (best of a few rounds)."""
+    out = {}
+    n = 1 << 25                                     # 256 MiB of 8-byte words
+    words = torch.zeros(n, dtype=torch.int64, device="cuda")
+    fails = torch.zeros(1, dtype=torch.int32, device="cuda")
+    sink = torch.zeros(1, dtype=torch.int64, device="cuda")
+    rnd = 0
+    for scatter, key in ((0, "cas_coalesced"), (1, "cas_scattered")):
+        best = None
+        for _ in range(6):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            hr.peak_cas(words, rnd, scatter, fails)
+            e1.record(stream)
+            e1.synchronize()
+            rnd += 1
+            ms = e0.elapsed_time(e1)
+            best = ms if best is None else min(best, ms)
+        out[key + "_per_s"] = n / (best * 1e-3)
+    out["cas_failures"] = int(fails.item())
+    for scatter, key in ((0, "load_coalesced"), (1, "load_scattered")):
+        best = None
+        for _ in range(6):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            hr.peak_load(words, scatter, sink)
+            e1.record(stream)
+            e1.synchronize()
+            ms = e0.elapsed_time(e1)
+            best = ms if best is None else min(best, ms)
+        out[key + "_per_s"] = n / (best * 1e-3)
+    src = torch.empty(1 << 28, dtype=torch.uint8, device="cuda").random_(0, 255)
+    dst = torch.empty_like(src)
+    best = None
+    for _ in range(6):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        hr.peak_copy(src, dst)
+        e1.record(stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    out["copy_gbs"] = 2 * src.numel() / (best * 1e-3) / 1e9
+    del words, src, dst
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-peaks", action="store_true")
+    ap.add_argument("--plain-only", action="store_true",
+                    help="time only the uninstrumented kernel (profiling aid)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the checker runs each job on a single device "
+              "(jobs shard across GPUs with no exchange); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth_inputs as si
+    from paper_2401_04701_amd import hr
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+
+    seeds = si.jacobi_seeds(NY, NX, si.master_seed(1))
+    tab = torch.from_numpy(si.jacobi_seed_table(NY, NX, seeds)).cuda()
+    u0 = torch.from_numpy(si.jacobi_grid(NY, NX, si.master_seed(1))).cuda()
+    u = [u0.clone(), torch.zeros_like(u0)]
+    n_g, n_l = jacobi_check_counts(NY, NX, len(seeds))
+    checks_per_launch = n_g + n_l
+    checks_per_step = checks_per_launch * LAUNCHES
+
+    # exact access count from the device counter (untimed)
+    with hr.Context(count_checks=True) as cctx:
+        regs = [cctx.shadow_alloc(u[0]), cctx.shadow_alloc(u[1])]
+        for L in range(LAUNCHES):
+            cctx.jacobi_check(regs[L % 2], regs[(L + 1) % 2], u[L % 2], u[(L + 1) % 2], tab)
+            cctx.kernel_end()
+        counted = cctx.check_count()
+        flagged_count = len(cctx.flagged())
+    assert counted == checks_per_step, (counted, checks_per_step)
+
+    ctx = hr.Context()
+    regs = [ctx.shadow_alloc(u[0]), ctx.shadow_alloc(u[1])]
+
+    def checked_step(events):
+        ctx.reset()
+        for L in range(LAUNCHES):
+            if events is not None:
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+            ctx.jacobi_check(regs[L % 2], regs[(L + 1) % 2], u[L % 2], u[(L + 1) % 2], tab)
+            if events is not None:
+                e1.record(stream)
+                events.append((e0, e1))
+            ctx.kernel_end()
+        recs, st = ctx.report()
+        return recs, st
+
+    def plain_step(events):
+        for L in range(LAUNCHES):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            hr.jacobi_plain(u[L % 2], u[(L + 1) % 2], tab)
+            e1.record(stream)
+            events.append((e0, e1))
+
+    if args.plain_only:
+        for _ in range(args.warmup + args.steps):
+            plain_step([])
+        torch.cuda.synchronize()
+        return
+
+    for _ in range(args.warmup):
+        checked_step(None)
+    torch.cuda.synchronize()
+    ev = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        recs, st = checked_step(ev)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    launch_ms = [a.elapsed_time(b) for a, b in ev]
+    step_s = (t1 - t0) / args.steps
+    assert st == 0 and len(recs) == flagged_count
+
+    pev = []
+    for _ in range(max(1, args.warmup)):
+        plain_step([])
+    torch.cuda.synchronize()
+    tp0 = time.perf_counter()
+    for _ in range(args.steps):
+        plain_step(pev)
+    torch.cuda.synchronize()
+    tp1 = time.perf_counter()
+    plain_ms = [a.elapsed_time(b) for a, b in pev]
+    ctx.close()
+
+    avg_launch_s = float(np.mean(launch_ms)) * 1e-3
+    alg = algorithmic_bytes_per_launch(NY, NX)
+    achieved = alg / avg_launch_s / 1e9
+    result = {
+        "metric": "instrumented accesses checked/sec + slowdown vs uninstrumented; p50/p99 check latency",
+        "value": checks_per_step / step_s,
+        "unit": "checks/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": step_s * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": "jacobi5pt_fp32_4096x4096_b16x16_lds18x18_20launches_seeded66",
+                   "grid": [NY, NX], "launches": LAUNCHES, "seeded_blocks": int(len(seeds)),
+                   "checks_per_step": int(checks_per_step),
+                   "global_checks_per_launch": int(n_g), "lds_checks_per_launch": int(n_l),
+                   "parallelism": "single GPU"},
+        "slowdown": float(np.median(launch_ms) / np.median(plain_ms)),
+        "slowdown_step": step_s / ((tp1 - tp0) / args.steps),
+        "p50_launch_ms": pct(launch_ms, 50),
+        "p99_launch_ms": pct(launch_ms, 99),
+        "plain_p50_launch_ms": pct(plain_ms, 50),
+        "flagged": int(flagged_count),
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_jacobi<true>", "alg_bytes_per_launch": alg,
+                     "avg_launch_ms": avg_launch_s * 1e3},
+    }
+    if not args.no_peaks:
+        peaks = measure_peaks(torch, hr, stream)
+        g_rate = n_g / avg_launch_s
+        result["atomic"] = {"global_checks_per_s": g_rate,
+                            "peak_cas_per_s": peaks["cas_coalesced_per_s"],
+                            "frac": g_rate / peaks["cas_coalesced_per_s"], **peaks}
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

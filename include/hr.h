@@ -137,6 +137,11 @@ hr_status hr_fsm_step(uint32_t space, uint64_t old, uint32_t kind, uint32_t laun
                       uint32_t block, uint32_t thread, uint32_t bc, uint32_t wc,
                       uint64_t* new_out);
 
+/* Host evaluation of the device merge of two global shadow words (the summary
+ * of the union of their access sets; x of the current launch), used when an
+ * exchange overwrote a concurrent update; for verification only. */
+hr_status hr_fsm_merge(uint64_t x, uint64_t y, uint64_t* out);
+
 /* ----------------------------------------------------------------------
  * Instrumented workloads.  Each *_check entry launches one instrumented
  * kernel on `stream` (the caller calls hr_kernel_end after it); each *_plain
@@ -198,6 +203,29 @@ hr_status hr_program_check(hr_ctx c, const uint32_t* regions_host, uint32_t n_re
                            const int32_t* op_off_dev, size_t n_op_off, const uint32_t* ops_dev,
                            size_t n_ops, const uint32_t* block_map_dev, uint32_t lds_words,
                            void* stream);
+
+/* ----------------------------------------------------------------------
+ * Device microbenchmarks: the roofline denominators of the checking path
+ * (its cost is HBM traffic of shadow words and agent-scope atomics).
+ * ---------------------------------------------------------------------- */
+
+/* Copy `bytes` (a multiple of 16) from src_dev to dst_dev with 16-byte
+ * vector loads and stores: streaming HBM bandwidth, and the calibration
+ * kernel for the HBM byte counters. */
+hr_status hr_peak_copy(const void* src_dev, void* dst_dev, size_t bytes, void* stream);
+
+/* One agent-scope 64-bit compare-and-swap per word of words_dev[n]: word w
+ * must hold `round`; it becomes round+1.  scatter != 0 permutes words within
+ * 64 KiB windows (n should be a multiple of 8192) so the lanes of a wave hit
+ * different cache lines.  Failed exchanges are added to *fails_dev. */
+hr_status hr_peak_cas(uint64_t* words_dev, size_t n, uint32_t round, uint32_t scatter,
+                      uint32_t* fails_dev, void* stream);
+
+/* One agent-scope (coherent) 64-bit atomic load per word of words_dev[n],
+ * same index patterns as hr_peak_cas; sink_dev receives nothing unless an
+ * improbable value appears (it keeps the loads from being removed). */
+hr_status hr_peak_load(const uint64_t* words_dev, size_t n, uint32_t scatter, uint64_t* sink_dev,
+                       void* stream);
 
 #ifdef __cplusplus
 }

@@ -28,8 +28,8 @@
 // Counter words.
 #define HR_CTR_HEAD 0     // ring append index
 #define HR_CTR_FLAGS 1    // warning bits
-#define HR_CTR_COUNT 2    // checked accesses, 64-bit (words 2, 3)
-#define HR_CTR_WORDS 4
+#define HR_CTR_WORDS 2
+#define HR_COUNT_SLOTS 256   // checked-access counters, spread by block
 
 // Record appended on a transition into the race state (matches hr_race).
 struct hr_race_rec {
@@ -56,7 +56,7 @@ struct hr_kargs {
     uint32_t launch_seq;                // launch sequence number (reports)
     uint32_t bc_max;                    // last valid block-clock value
     uint32_t wc_max;                    // last valid wave-clock value
-    uint32_t count;                     // nonzero: count checked accesses
+    unsigned long long* count;          // HR_COUNT_SLOTS counters, or null
 };
 
 // Per-thread checker state, kept in registers.
@@ -88,12 +88,14 @@ __device__ __forceinline__ void hr_set_flag(const hr_kargs& a, uint32_t bit)
     __hip_atomic_fetch_or(a.ctr + HR_CTR_FLAGS, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ void hr_count(const hr_kargs& a)
+// Debug counting of checked accesses: one atomic per wave and hook, spread
+// over HR_COUNT_SLOTS words by block to avoid a single hot address.
+__device__ __forceinline__ void hr_count(const hr_kargs& a, const hr_thread& t)
 {
     if (a.count) {
         const uint64_t m = __ballot(1);
         if (__lane_id() == (uint32_t)__builtin_ctzll(m))
-            __hip_atomic_fetch_add((unsigned long long*)(a.ctr + HR_CTR_COUNT),
+            __hip_atomic_fetch_add(a.count + (t.block % HR_COUNT_SLOTS),
                                    (unsigned long long)__popcll(m), __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
     }
@@ -119,32 +121,62 @@ __device__ __forceinline__ void hr_ring_push(const hr_kargs& a, uint32_t space, 
     }
 }
 
+// Fold a summary `lost` that our exchange overwrote back into the word at
+// sp, which we set to `mine`.  Each successful compare-and-swap grows the
+// summary, so the loop ends after a bounded number of rounds.  Returns the
+// word replaced when this fold itself created the race state (the caller
+// reports it), else HR_NO_REPORT; a `lost` race state was already reported
+// by whoever created it.  Out of line and with scalar arguments only: it is
+// the rare path and must not make the caller spill its kernel arguments.
+#define HR_NO_REPORT (~0ull)
+__device__ __noinline__ uint64_t hr_fold(uint64_t* sp, uint64_t mine, uint64_t lost)
+{
+    uint64_t cur = mine;
+    for (;;) {
+        const uint64_t m = hr::g::merge(cur, lost);
+        if (m == cur) return HR_NO_REPORT;
+        uint64_t seen = cur;
+        if (__hip_atomic_compare_exchange_strong(sp, &seen, m, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT))
+            return (m == hr::T_RACE && lost != hr::T_RACE) ? cur : HR_NO_REPORT;
+        cur = seen;
+    }
+}
+
 // Check one access of kind KIND (0 read, 1 write, 2 atomic) to element
 // `index` of global region `region`.
+//
+// The copy-compute-publish loop of the paper's Algorithm 1, published with an
+// atomic exchange instead of a compare-and-swap (on gfx950 a 64-bit exchange
+// costs less than half a 64-bit compare-and-swap).  The coherent load decides
+// the transition; an unchanged word costs nothing more.  If the exchange
+// returns the loaded word, it acted exactly as a successful compare-and-swap.
+// Otherwise it overwrote updates made since the load, and hr_fold merges
+// them back.
 template <int KIND>
 __device__ __forceinline__ void hr_access(const hr_kargs& a, const hr_thread& t,
                                           uint32_t region, uint64_t index)
 {
     if (!t.enabled) return;
-    hr_count(a);
+    hr_count(a, t);
     if (region >= HR_MAX_REGIONS || index >= a.n_elems[region]) {
         hr_set_flag(a, HR_DEVF_RANGE);
         return;
     }
     constexpr uint32_t k = KIND == 0 ? hr::CL_R : (KIND == 2 ? hr::CL_A : hr::CL_X);
     uint64_t* sp = a.shadow[region] + index;
-    uint64_t old = __hip_atomic_load(sp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    for (;;) {
-        const uint64_t nw = hr::g::step(old, t.gid, k);
-        if (nw == old) return;
-        uint64_t seen = old;
-        if (__hip_atomic_compare_exchange_strong(sp, &seen, nw, __ATOMIC_RELAXED,
-                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-            if (nw == hr::T_RACE)
-                hr_ring_push(a, 0, region, t.block, index, t.thread, (uint32_t)old);
-            return;
-        }
-        old = seen;
+    const uint64_t old = __hip_atomic_load(sp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t nw = hr::g::step(old, t.gid, k);
+    if (nw == old) return;
+    const uint64_t r = __hip_atomic_exchange(sp, nw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (nw == hr::T_RACE) {
+        if (r != hr::T_RACE) hr_ring_push(a, 0, region, t.block, index, t.thread, (uint32_t)old);
+        return;
+    }
+    if (r != old) {
+        const uint64_t before = hr_fold(sp, nw, r);
+        if (before != HR_NO_REPORT)
+            hr_ring_push(a, 0, region, t.block, index, t.thread, (uint32_t)before);
     }
 }
 
@@ -157,7 +189,7 @@ __device__ __forceinline__ void hr_access_lds(const hr_kargs& a, const hr_thread
                                               uint32_t index)
 {
     if (!t.enabled) return;
-    hr_count(a);
+    hr_count(a, t);
     if (index >= n_words) {
         hr_set_flag(a, HR_DEVF_RANGE);
         return;

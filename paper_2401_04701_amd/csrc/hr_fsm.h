@@ -120,6 +120,64 @@ HR_HD uint64_t step(uint64_t old, uint64_t id, uint32_t k)
     // Same thread.
     return mk(T_ST, cl | k, cb | k, cw | k) | (id & keep_t);
 }
+
+// Summary of the union of the access sets summarised by x and y, where x
+// belongs to the current launch (an initial y, or one of another launch,
+// adds nothing).  Used to fold
+// back an update that a concurrent exchange overwrote.  Exact under the
+// condition the hook guarantees: every access in one summary but not the
+// other either comes from another block (then the union spans >= 2 blocks)
+// or lies in the latest block epoch, and within one wave in the latest wave
+// epoch, of both summaries, because a thread still inside its hook holds
+// back its own block and wave barriers.  With accesses from >= 2 blocks
+// (or waves, or threads) in the same scope and epoch, the union is free of
+// races exactly when all of it has one class, R or A.
+HR_HD uint64_t merge(uint64_t x, uint64_t y)
+{
+    const uint32_t tx = (uint32_t)(x & TAG_M), ty = (uint32_t)(y & TAG_M);
+    const uint64_t race = T_RACE;
+    if (tx == T_RACE || ty == T_RACE) return race;
+    if (ty == T_INIT || ((x ^ y) & LA_M)) return x;
+    if (tx == T_INIT) return y;
+    const uint32_t clx = (uint32_t)(x >> CL_SH) & 3u, cly = (uint32_t)(y >> CL_SH) & 3u;
+    const uint32_t cbx = (uint32_t)(x >> CB_SH) & 3u, cby = (uint32_t)(y >> CB_SH) & 3u;
+    const uint32_t cwx = (uint32_t)(x >> CW_SH) & 3u, cwy = (uint32_t)(y >> CW_SH) & 3u;
+    const uint64_t d = x ^ y;
+    const uint64_t la = x & LA_M;
+    // >= 2 blocks: one class for everything, or a race.
+    if (tx == T_MB || ty == T_MB || (d & BL_M)) {
+        const uint32_t c = (tx == T_MB ? cbx : clx) | (ty == T_MB ? cby : cly);
+        return c == CL_X ? race : (mk(T_MB, 0, c, 0) | la);
+    }
+    const uint32_t cl = clx | cly;
+    // One block.  Different latest block epochs: the older summary's epoch
+    // is ordered before the newer one's, which keeps its detail.  Clocks
+    // never wrap (an overflow stops checking), so the larger one is newer.
+    if (d & BC_M) {
+        const uint64_t newer = (x & BC_M) > (y & BC_M) ? x : y;
+        return (newer & ~CL_M) | ((uint64_t)cl << CL_SH);
+    }
+    const uint64_t keep_b = LA_M | BL_M | BC_M;
+    const uint64_t keep_w = keep_b | WAVE_M | WC_M;
+    // Same block epoch with >= 2 waves.
+    if (tx == T_MW || ty == T_MW || (d & WAVE_M)) {
+        const uint32_t c = cbx | cby;
+        return c == CL_X ? race : (mk(T_MW, cl, c, 0) | (x & keep_b));
+    }
+    const uint32_t cb = cbx | cby;
+    // One wave.  Different latest wave epochs: keep the newer detail.
+    if (d & WC_M) {
+        const uint64_t newer = (x & WC_M) > (y & WC_M) ? x : y;
+        return (newer & ~(CL_M | CB_M)) | ((uint64_t)cl << CL_SH) | ((uint64_t)cb << CB_SH);
+    }
+    // Same wave epoch with >= 2 threads.
+    if (tx == T_MT || ty == T_MT || (d & LANE_M)) {
+        const uint32_t c = cwx | cwy;
+        return c == CL_X ? race : (mk(T_MT, cl, cb, c) | (x & keep_w));
+    }
+    // Same thread.
+    return mk(T_ST, cl, cb, cwx | cwy) | (x & ~(TAG_M | CL_M | CB_M | CW_M));
+}
 }  // namespace g
 
 // ---------------------------------------------------------------------------

@@ -21,6 +21,7 @@ struct hr_ctx_s {
     uint32_t n_reg;
     hr_race_rec* ring;
     uint32_t* ctr;
+    unsigned long long* count;   // HR_COUNT_SLOTS debug counters
     uint32_t launch_seq;     // launches since the job started
     uint64_t shadow_bytes;
 };

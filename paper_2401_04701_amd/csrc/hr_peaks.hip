@@ -1,0 +1,95 @@
+// Device microbenchmarks that give the roofline denominators of the checker:
+// streaming copy (HBM bandwidth, also the calibration kernel for the HBM
+// byte counters), agent-scope 64-bit compare-and-swap on distinct words
+// (coalesced or scattered), and agent-scope 64-bit atomic loads.
+#include <hip/hip_runtime.h>
+
+#include "hr.h"
+#include "hr_internal.h"
+
+namespace {
+
+__global__ __launch_bounds__(256) void k_copy(const uint4* __restrict__ src,
+                                              uint4* __restrict__ dst, size_t n)
+{
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) dst[i] = src[i];
+}
+
+// Word w holds `round` before round `round`; every compare-and-swap succeeds.
+// scatter != 0 permutes word indices inside each 64 KiB window so that the
+// lanes of a wave touch different cache lines.
+__device__ __forceinline__ size_t peak_index(size_t i, size_t n, uint32_t scatter)
+{
+    if (!scatter) return i;
+    const size_t win = 8192;                        // 64 KiB of 8-byte words
+    const size_t base = i & ~(win - 1);
+    const size_t j = ((i & (win - 1)) * 4099u) & (win - 1);   // odd multiplier: a bijection
+    const size_t k = base + j;
+    return k < n ? k : i;
+}
+
+__global__ __launch_bounds__(256) void k_cas(uint64_t* __restrict__ w, size_t n, uint32_t round,
+                                             uint32_t scatter, uint32_t* __restrict__ fails)
+{
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    uint32_t bad = 0;
+    for (; i < n; i += stride) {
+        uint64_t* p = w + peak_index(i, n, scatter);
+        uint64_t expect = round;
+        if (!__hip_atomic_compare_exchange_strong(p, &expect, (uint64_t)round + 1, __ATOMIC_RELAXED,
+                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            ++bad;
+    }
+    if (bad) atomicAdd(fails, bad);
+}
+
+__global__ __launch_bounds__(256) void k_load(const uint64_t* __restrict__ w, size_t n,
+                                              uint32_t scatter, uint64_t* __restrict__ sink)
+{
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    uint64_t acc = 0;
+    for (; i < n; i += stride)
+        acc ^= __hip_atomic_load(w + peak_index(i, n, scatter), __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
+    if (acc == 0x9E3779B97F4A7C15ull) *sink = acc;    // keeps the loads alive
+}
+
+unsigned grid_for(size_t n)
+{
+    const size_t blocks = (n + 255) / 256;
+    return (unsigned)(blocks < 65536 ? blocks : 65536);
+}
+
+}  // namespace
+
+extern "C" hr_status hr_peak_copy(const void* src_dev, void* dst_dev, size_t bytes, void* stream)
+{
+    if (!src_dev || !dst_dev || bytes % 16) return HR_E_INVAL;
+    const size_t n = bytes / 16;
+    if (n == 0) return HR_OK;
+    HR_LAUNCH(k_copy, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream, (const uint4*)src_dev,
+              (uint4*)dst_dev, n);
+    return HR_OK;
+}
+
+extern "C" hr_status hr_peak_cas(uint64_t* words_dev, size_t n, uint32_t round, uint32_t scatter,
+                                 uint32_t* fails_dev, void* stream)
+{
+    if (!words_dev || !fails_dev || n == 0) return HR_E_INVAL;
+    HR_LAUNCH(k_cas, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream, words_dev, n, round,
+              scatter, fails_dev);
+    return HR_OK;
+}
+
+extern "C" hr_status hr_peak_load(const uint64_t* words_dev, size_t n, uint32_t scatter,
+                                  uint64_t* sink_dev, void* stream)
+{
+    if (!words_dev || !sink_dev || n == 0) return HR_E_INVAL;
+    HR_LAUNCH(k_load, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream, words_dev, n, scatter,
+              sink_dev);
+    return HR_OK;
+}

@@ -103,7 +103,14 @@ extern "C" hr_status hr_ctx_create(hr_ctx* out, const hr_config* cfg, void* stre
         delete c;
         return HR_E_NOMEM;
     }
-    if (fill32(c->ctr, HR_CTR_WORDS, c->stream) != hipSuccess) {
+    if (hipMalloc(&c->count, sizeof(unsigned long long) * HR_COUNT_SLOTS) != hipSuccess) {
+        (void)hipFree(c->ring);
+        (void)hipFree(c->ctr);
+        delete c;
+        return HR_E_NOMEM;
+    }
+    if (fill32(c->ctr, HR_CTR_WORDS, c->stream) != hipSuccess ||
+        fill64((uint64_t*)c->count, HR_COUNT_SLOTS, c->stream) != hipSuccess) {
         hr_ctx_destroy(c);
         return HR_E_HIP;
     }
@@ -118,6 +125,7 @@ extern "C" hr_status hr_ctx_destroy(hr_ctx c)
     for (uint32_t r = 0; r < c->n_reg; ++r) (void)hipFree(c->reg[r].shadow);
     (void)hipFree(c->ring);
     (void)hipFree(c->ctr);
+    (void)hipFree(c->count);
     delete c;
     return e == hipSuccess ? HR_OK : HR_E_HIP;
 }
@@ -160,7 +168,7 @@ void hr_fill_args(hr_ctx c, hr_kargs* a)
     a->launch_seq = c->launch_seq;
     a->bc_max = (1u << c->cfg.bc_bits) - 1;
     a->wc_max = (1u << c->cfg.wc_bits) - 1;
-    a->count = (c->cfg.flags & HR_CFG_COUNT_CHECKS) ? 1u : 0u;
+    a->count = (c->cfg.flags & HR_CFG_COUNT_CHECKS) ? c->count : nullptr;
 }
 
 extern "C" hr_status hr_dev_args(hr_ctx c, void* out, size_t cap, size_t* size_out)
@@ -191,6 +199,7 @@ extern "C" hr_status hr_reset(hr_ctx c, void* stream)
     hr_status st = clear_shadows(c, s);
     if (st != HR_OK) return st;
     if (fill32(c->ctr, HR_CTR_WORDS, s) != hipSuccess) return HR_E_HIP;
+    if (fill64((uint64_t*)c->count, HR_COUNT_SLOTS, s) != hipSuccess) return HR_E_HIP;
     c->launch_seq = 0;
     return HR_OK;
 }
@@ -248,8 +257,12 @@ extern "C" hr_status hr_check_count(hr_ctx c, uint64_t* out, void* stream)
 {
     if (!c || !out) return HR_E_INVAL;
     if (hipStreamSynchronize(hr_stream(c, stream)) != hipSuccess) return HR_E_HIP;
-    if (hipMemcpy(out, c->ctr + HR_CTR_COUNT, sizeof(uint64_t), hipMemcpyDeviceToHost) != hipSuccess)
+    unsigned long long slots[HR_COUNT_SLOTS];
+    if (hipMemcpy(slots, c->count, sizeof(slots), hipMemcpyDeviceToHost) != hipSuccess)
         return HR_E_HIP;
+    uint64_t sum = 0;
+    for (int i = 0; i < HR_COUNT_SLOTS; ++i) sum += slots[i];
+    *out = sum;
     return HR_OK;
 }
 
@@ -265,5 +278,12 @@ extern "C" hr_status hr_fsm_step(uint32_t space, uint64_t old, uint32_t kind, ui
     } else {
         *new_out = hr::l::step((uint32_t)old, hr::l::pack_id(thread, bc, wc), k);
     }
+    return HR_OK;
+}
+
+extern "C" hr_status hr_fsm_merge(uint64_t x, uint64_t y, uint64_t* out)
+{
+    if (!out) return HR_E_INVAL;
+    *out = hr::g::merge(x, y);
     return HR_OK;
 }

@@ -65,6 +65,7 @@ def _load():
         "hr_report": [P, P, sz, P, P],
         "hr_check_count": [P, P, P],
         "hr_fsm_step": [u32, u64, u32, u32, u32, u32, u32, u32, P],
+        "hr_fsm_merge": [u64, u64, P],
         "hr_reduce_check": [P, u32, u32, P, P, ctypes.c_int32, P],
         "hr_reduce_plain": [P, P, ctypes.c_int32, P],
         "hr_jacobi_check": [P, u32, u32, P, P, u32, u32, P, P],
@@ -72,6 +73,9 @@ def _load():
         "hr_labelprop_check": [P, u32, u32, u32, P, P, P, P, u32, u32, P],
         "hr_labelprop_plain": [P, P, P, P, u32, u32, P],
         "hr_program_check": [P, P, u32, u32, u32, u32, P, P, P, sz, P, sz, P, u32, P],
+        "hr_peak_copy": [P, P, sz, P],
+        "hr_peak_cas": [P, sz, u32, u32, P, P],
+        "hr_peak_load": [P, sz, u32, P, P],
     }
     for name, args in sigs.items():
         fn = getattr(lib, name)
@@ -82,9 +86,10 @@ def _load():
 
 _lib = _load()
 EXPORTED = ("hr_ctx_create", "hr_ctx_destroy", "hr_shadow_alloc", "hr_dev_args",
-            "hr_kernel_end", "hr_reset", "hr_report", "hr_check_count", "hr_fsm_step",
+            "hr_kernel_end", "hr_reset", "hr_report", "hr_check_count", "hr_fsm_step", "hr_fsm_merge",
             "hr_reduce_check", "hr_reduce_plain", "hr_jacobi_check", "hr_jacobi_plain",
-            "hr_labelprop_check", "hr_labelprop_plain", "hr_program_check")
+            "hr_labelprop_check", "hr_labelprop_plain", "hr_program_check",
+            "hr_peak_copy", "hr_peak_cas", "hr_peak_load")
 
 
 def lib():
@@ -119,6 +124,13 @@ def fsm_step(space: int, old: int, kind: int, launch: int, block: int, thread: i
     return int(out.value)
 
 
+def fsm_merge(x: int, y: int) -> int:
+    """Host evaluation of the device summary merge (verification aid)."""
+    out = ctypes.c_uint64(0)
+    _check("hr_fsm_merge", _lib.hr_fsm_merge(x, y, ctypes.byref(out)))
+    return int(out.value)
+
+
 # ---------------------------------------------------------------- plain runs
 def reduce_plain(inp, out, drop=-1, stream=None):
     _check("hr_reduce_plain", _lib.hr_reduce_plain(_dptr(inp), _dptr(out), int(drop),
@@ -135,6 +147,21 @@ def labelprop_plain(label, row_ptr, col, mask, tpb=256, stream=None):
     n = label.shape[0]
     _check("hr_labelprop_plain", _lib.hr_labelprop_plain(_dptr(label), _dptr(row_ptr), _dptr(col),
                                                          _dptr(mask), n, tpb, _stream_ptr(stream)))
+
+
+def peak_copy(src, dst, stream=None):
+    _check("hr_peak_copy", _lib.hr_peak_copy(_dptr(src), _dptr(dst), src.numel() * src.element_size(),
+                                             _stream_ptr(stream)))
+
+
+def peak_cas(words, rnd, scatter, fails, stream=None):
+    _check("hr_peak_cas", _lib.hr_peak_cas(_dptr(words), words.numel(), rnd, scatter, _dptr(fails),
+                                           _stream_ptr(stream)))
+
+
+def peak_load(words, scatter, sink, stream=None):
+    _check("hr_peak_load", _lib.hr_peak_load(_dptr(words), words.numel(), scatter, _dptr(sink),
+                                             _stream_ptr(stream)))
 
 
 class DeviceProgram:
