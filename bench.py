@@ -52,6 +52,27 @@ def algorithmic_bytes_per_launch(ny: int, nx: int) -> int:
     return cells * (4 + 4) + 2 * cells * (8 + 8)
 
 
+def counter_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or
+    None when the kernel sources changed since the counters were taken."""
+    import hashlib
+    import re as _re
+    path = os.path.join(ROOT, "profiles", "k_jacobi_check_4096x4096_hbm_counters.md")
+    if not os.path.exists(path):
+        return None
+    m = _re.search(r"```json\n(.*?)\n```", open(path).read(), flags=_re.S)
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    h = hashlib.sha256()
+    for src in rec["sources"]:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    if rec["kernel"] != kernel or h.hexdigest() != rec["source_sha256"]:
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
 def pct(a, q):
     return float(np.percentile(np.asarray(a, dtype=np.float64), q))
 
@@ -78,52 +99,161 @@ def cpu_baseline():
             "seconds": dt}
 
 
+def _best_ms(torch, stream, fn, reps=6):
+    best = None
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    return best
+
+
 def measure_peaks(torch, hr, stream):
-    """Measured agent-scope atomic and HBM peaks (best of a few rounds)."""
+    """Measured agent-scope atomic, coherent-load and copy peaks (best of 6)."""
     out = {}
     n = 1 << 25                                     # 256 MiB of 8-byte words
     words = torch.zeros(n, dtype=torch.int64, device="cuda")
     fails = torch.zeros(1, dtype=torch.int32, device="cuda")
     sink = torch.zeros(1, dtype=torch.int64, device="cuda")
-    rnd = 0
-    for scatter, key in ((0, "cas_coalesced"), (1, "cas_scattered")):
-        best = None
-        for _ in range(6):
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            hr.peak_cas(words, rnd, scatter, fails)
-            e1.record(stream)
-            e1.synchronize()
-            rnd += 1
-            ms = e0.elapsed_time(e1)
-            best = ms if best is None else min(best, ms)
-        out[key + "_per_s"] = n / (best * 1e-3)
-    out["cas_failures"] = int(fails.item())
-    for scatter, key in ((0, "load_coalesced"), (1, "load_scattered")):
-        best = None
-        for _ in range(6):
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            hr.peak_load(words, scatter, sink)
-            e1.record(stream)
-            e1.synchronize()
-            ms = e0.elapsed_time(e1)
-            best = ms if best is None else min(best, ms)
-        out[key + "_per_s"] = n / (best * 1e-3)
+    rnd = [0]
+    for op, opname in ((0, "cas"), (1, "xchg")):
+        for scatter, pat in ((0, "coalesced"), (1, "scattered")):
+            def run(op=op, scatter=scatter):
+                hr.peak_atomic(words, op, rnd[0], scatter, fails)
+                rnd[0] += 1
+            out[f"{opname}_{pat}_per_s"] = n / (_best_ms(torch, stream, run) * 1e-3)
+    out["atomic_failures"] = int(fails.item())
+    for scatter, pat in ((0, "coalesced"), (1, "scattered")):
+        ms = _best_ms(torch, stream, lambda scatter=scatter: hr.peak_load(words, scatter, sink))
+        out[f"load_{pat}_per_s"] = n / (ms * 1e-3)
     src = torch.empty(1 << 28, dtype=torch.uint8, device="cuda").random_(0, 255)
     dst = torch.empty_like(src)
-    best = None
-    for _ in range(6):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        hr.peak_copy(src, dst)
-        e1.record(stream)
-        e1.synchronize()
-        ms = e0.elapsed_time(e1)
-        best = ms if best is None else min(best, ms)
-    out["copy_gbs"] = 2 * src.numel() / (best * 1e-3) / 1e9
+    ms = _best_ms(torch, stream, lambda: hr.peak_copy(src, dst))
+    out["copy_gbs"] = 2 * src.numel() / (ms * 1e-3) / 1e9
     del words, src, dst
     return out
+
+
+def _timed_job(args, torch, stream, job, launches):
+    """Warm up, then time `steps` whole jobs; per-launch HIP events."""
+    for _ in range(args.warmup):
+        job(None)
+    torch.cuda.synchronize()
+    ev = []
+    t0 = time.perf_counter()
+    out = None
+    for _ in range(args.steps):
+        out = job(ev)
+    torch.cuda.synchronize()
+    step_s = (time.perf_counter() - t0) / args.steps
+    return step_s, [a.elapsed_time(b) for a, b in ev], out
+
+
+def _launch_events(torch, stream, events, fn):
+    if events is None:
+        fn()
+        return
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    fn()
+    e1.record(stream)
+    events.append((e0, e1))
+
+
+def _common(args, metric_value, step_s, launch_ms, plain_ms, plain_step_s, workload, extra):
+    return {
+        "metric": "instrumented accesses checked/sec + slowdown vs uninstrumented; p50/p99 check latency",
+        "value": metric_value, "unit": "checks/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": step_s * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": workload, **extra, "parallelism": "single GPU"},
+        "slowdown": float(np.median(launch_ms) / np.median(plain_ms)),
+        "slowdown_step": step_s / plain_step_s,
+        "p50_launch_ms": pct(launch_ms, 50), "p99_launch_ms": pct(launch_ms, 99),
+        "plain_p50_launch_ms": pct(plain_ms, 50)}
+
+
+def bench_labelprop(args, torch, si, hr, stream):
+    """R-MAT scale 22, 2^25 edges, 1 % seeded edges, 10 launches per job."""
+    scale, edges, launches, tpb = 22, 1 << 25, 10, 256
+    rp, col, mask = si.labelprop_graph(scale, edges, si.master_seed(2), 0.01)
+    n = 1 << scale
+    checks_per_launch = n + edges + int(mask.sum())
+    label = torch.arange(n, dtype=torch.int32, device="cuda")
+    init = label.clone()
+    rp_d, col_d = torch.from_numpy(rp).cuda(), torch.from_numpy(col).cuda()
+    mask_d = torch.from_numpy(mask).cuda()
+    ctx = hr.Context(ring_capacity=1 << 21)
+    r_lab = ctx.shadow_alloc(label)
+
+    def job(ev):
+        ctx.reset()
+        label.copy_(init)
+        for _ in range(launches):
+            _launch_events(torch, stream, ev, lambda: ctx.labelprop_check(
+                r_lab, label, rp_d, col_d, mask_d, tpb=tpb))
+            ctx.kernel_end()
+        return ctx.report()
+
+    def plain(ev):
+        label.copy_(init)
+        for _ in range(launches):
+            _launch_events(torch, stream, ev, lambda: hr.labelprop_plain(label, rp_d, col_d, mask_d, tpb))
+
+    step_s, launch_ms, (recs, st) = _timed_job(args, torch, stream, job, launches)
+    pstep_s, plain_ms, _ = _timed_job(args, torch, stream, plain, launches)
+    ctx.close()
+    assert st == 0
+    res = _common(args, checks_per_launch * launches / step_s, step_s, launch_ms, plain_ms,
+                  pstep_s, "labelprop_rmat22_2p25edges_seeded1pct_10launches",
+                  {"vertices": n, "edges": edges, "launches": launches,
+                   "checks_per_step": checks_per_launch * launches})
+    # algorithmic bytes: the sweep's own data (row_ptr and the label load per
+    # vertex, col + mask + label min per edge) plus one 8-byte shadow load per
+    # check; the shadow words themselves change only a few times per launch
+    alg = n * (8 + 4) + edges * (4 + 1 + 4) + checks_per_launch * 8 + n * 16
+    avg = float(np.mean(launch_ms)) * 1e-3
+    res["flagged"] = int(len(recs))
+    res["roofline"] = {"bound": "hbm", "achieved": alg / avg / 1e9, "peak": HBM_PEAK_GBS,
+                       "unit": "GB/s", "frac": alg / avg / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                       "kernel": "k_labelprop<true>", "alg_bytes_per_launch": alg,
+                       "avg_launch_ms": avg * 1e3}
+    print(json.dumps(res), flush=True)
+
+
+def bench_reduce(args, torch, si, hr, stream):
+    """One block, 256 threads, LDS int32[512] tree reduction (latency)."""
+    x = torch.from_numpy(si.reduce_input(si.master_seed(0))).cuda()
+    out = torch.zeros(256, dtype=torch.int32, device="cuda")
+    ctx = hr.Context()
+    r_in, r_out = ctx.shadow_alloc(x), ctx.shadow_alloc(out)
+    reps = 50
+
+    def job(ev):
+        ctx.reset()
+        for _ in range(reps):
+            _launch_events(torch, stream, ev, lambda: ctx.reduce_check(r_in, r_out, x, out, 3))
+            ctx.kernel_end()
+        return ctx.report()
+
+    def plain(ev):
+        for _ in range(reps):
+            _launch_events(torch, stream, ev, lambda: hr.reduce_plain(x, out, 3))
+
+    step_s, launch_ms, (recs, st) = _timed_job(args, torch, stream, job, reps)
+    pstep_s, plain_ms, _ = _timed_job(args, torch, stream, plain, reps)
+    ctx.close()
+    res = _common(args, 3069 * reps / step_s, step_s, launch_ms, plain_ms, pstep_s,
+                  "reduce_lds_int32x512_1block256_drop3", {"launches_per_step": reps,
+                                                          "checks_per_launch": 3069})
+    res["flagged"] = int(len(recs))
+    res["p50_launch_us"] = pct(launch_ms, 50) * 1e3
+    res["p99_launch_us"] = pct(launch_ms, 99) * 1e3
+    print(json.dumps(res), flush=True)
 
 
 def main():
@@ -133,8 +263,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-peaks", action="store_true")
-    ap.add_argument("--plain-only", action="store_true",
-                    help="time only the uninstrumented kernel (profiling aid)")
+    ap.add_argument("--verify-count", action="store_true",
+                    help="first run one job with the device access counter (untimed)")
+    ap.add_argument("--workload", default="jacobi", choices=["jacobi", "labelprop", "reduce"],
+                    help="jacobi: the headline 4096^2 stencil job; labelprop: R-MAT scale-22 "
+                         "label propagation job; reduce: one-block LDS reduction latency")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the checker runs each job on a single device "
@@ -148,6 +281,10 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    if args.workload == "labelprop":
+        return bench_labelprop(args, torch, si, hr, stream)
+    if args.workload == "reduce":
+        return bench_reduce(args, torch, si, hr, stream)
 
     seeds = si.jacobi_seeds(NY, NX, si.master_seed(1))
     tab = torch.from_numpy(si.jacobi_seed_table(NY, NX, seeds)).cuda()
@@ -157,15 +294,15 @@ def main():
     checks_per_launch = n_g + n_l
     checks_per_step = checks_per_launch * LAUNCHES
 
-    # exact access count from the device counter (untimed)
-    with hr.Context(count_checks=True) as cctx:
-        regs = [cctx.shadow_alloc(u[0]), cctx.shadow_alloc(u[1])]
-        for L in range(LAUNCHES):
-            cctx.jacobi_check(regs[L % 2], regs[(L + 1) % 2], u[L % 2], u[(L + 1) % 2], tab)
-            cctx.kernel_end()
-        counted = cctx.check_count()
-        flagged_count = len(cctx.flagged())
-    assert counted == checks_per_step, (counted, checks_per_step)
+    if args.verify_count:
+        # the access count from the device counter (untimed, slower kernel)
+        with hr.Context(count_checks=True) as cctx:
+            regs = [cctx.shadow_alloc(u[0]), cctx.shadow_alloc(u[1])]
+            for L in range(LAUNCHES):
+                cctx.jacobi_check(regs[L % 2], regs[(L + 1) % 2], u[L % 2], u[(L + 1) % 2], tab)
+                cctx.kernel_end()
+            counted = cctx.check_count()
+        assert counted == checks_per_step, (counted, checks_per_step)
 
     ctx = hr.Context()
     regs = [ctx.shadow_alloc(u[0]), ctx.shadow_alloc(u[1])]
@@ -194,12 +331,6 @@ def main():
             e1.record(stream)
             events.append((e0, e1))
 
-    if args.plain_only:
-        for _ in range(args.warmup + args.steps):
-            plain_step([])
-        torch.cuda.synchronize()
-        return
-
     for _ in range(args.warmup):
         checked_step(None)
     torch.cuda.synchronize()
@@ -211,7 +342,8 @@ def main():
     t1 = time.perf_counter()
     launch_ms = [a.elapsed_time(b) for a, b in ev]
     step_s = (t1 - t0) / args.steps
-    assert st == 0 and len(recs) == flagged_count
+    flagged_count = len(recs)
+    assert st == 0 and flagged_count > 0
 
     pev = []
     for _ in range(max(1, args.warmup)):
@@ -253,7 +385,7 @@ def main():
         "plain_p50_launch_ms": pct(plain_ms, 50),
         "flagged": int(flagged_count),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic("k_jacobi<true>"),
                      "kernel": "k_jacobi<true>", "alg_bytes_per_launch": alg,
                      "avg_launch_ms": avg_launch_s * 1e3},
     }
@@ -261,8 +393,8 @@ def main():
         peaks = measure_peaks(torch, hr, stream)
         g_rate = n_g / avg_launch_s
         result["atomic"] = {"global_checks_per_s": g_rate,
-                            "peak_cas_per_s": peaks["cas_coalesced_per_s"],
-                            "frac": g_rate / peaks["cas_coalesced_per_s"], **peaks}
+                            "peak_xchg_per_s": peaks["xchg_coalesced_per_s"],
+                            "frac": g_rate / peaks["xchg_coalesced_per_s"], **peaks}
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline()
     print(json.dumps(result), flush=True)

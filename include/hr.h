@@ -214,15 +214,17 @@ hr_status hr_program_check(hr_ctx c, const uint32_t* regions_host, uint32_t n_re
  * kernel for the HBM byte counters. */
 hr_status hr_peak_copy(const void* src_dev, void* dst_dev, size_t bytes, void* stream);
 
-/* One agent-scope 64-bit compare-and-swap per word of words_dev[n]: word w
- * must hold `round`; it becomes round+1.  scatter != 0 permutes words within
- * 64 KiB windows (n should be a multiple of 8192) so the lanes of a wave hit
- * different cache lines.  Failed exchanges are added to *fails_dev. */
-hr_status hr_peak_cas(uint64_t* words_dev, size_t n, uint32_t round, uint32_t scatter,
-                      uint32_t* fails_dev, void* stream);
+/* One agent-scope 64-bit atomic per word of words_dev[n]: op 0 is a
+ * compare-and-swap from `round` to round+1, op 1 an exchange writing round+1
+ * (the two forms the checking path uses).  Every word must hold `round`;
+ * scatter != 0 permutes words within 64 KiB windows (n should be a multiple
+ * of 8192) so the lanes of a wave hit different cache lines.  Operations that
+ * found another value are added to *fails_dev. */
+hr_status hr_peak_atomic(uint64_t* words_dev, size_t n, uint32_t op, uint32_t round,
+                         uint32_t scatter, uint32_t* fails_dev, void* stream);
 
 /* One agent-scope (coherent) 64-bit atomic load per word of words_dev[n],
- * same index patterns as hr_peak_cas; sink_dev receives nothing unless an
+ * same index patterns as hr_peak_atomic; sink_dev receives nothing unless an
  * improbable value appears (it keeps the loads from being removed). */
 hr_status hr_peak_load(const uint64_t* words_dev, size_t n, uint32_t scatter, uint64_t* sink_dev,
                        void* stream);

@@ -1,7 +1,8 @@
 // Device microbenchmarks that give the roofline denominators of the checker:
 // streaming copy (HBM bandwidth, also the calibration kernel for the HBM
-// byte counters), agent-scope 64-bit compare-and-swap on distinct words
-// (coalesced or scattered), and agent-scope 64-bit atomic loads.
+// byte counters), agent-scope 64-bit compare-and-swap and exchange on
+// distinct words (coalesced or scattered), and agent-scope 64-bit atomic
+// loads.
 #include <hip/hip_runtime.h>
 
 #include "hr.h"
@@ -30,18 +31,29 @@ __device__ __forceinline__ size_t peak_index(size_t i, size_t n, uint32_t scatte
     return k < n ? k : i;
 }
 
-__global__ __launch_bounds__(256) void k_cas(uint64_t* __restrict__ w, size_t n, uint32_t round,
-                                             uint32_t scatter, uint32_t* __restrict__ fails)
+// op 0: compare-and-swap round -> round+1; op 1: exchange in round+1 and
+// check the returned value.  Either way a failure means the word did not
+// hold `round`.
+template <int OP>
+__global__ __launch_bounds__(256) void k_atomic(uint64_t* __restrict__ w, size_t n, uint32_t round,
+                                                uint32_t scatter, uint32_t* __restrict__ fails)
 {
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     uint32_t bad = 0;
     for (; i < n; i += stride) {
         uint64_t* p = w + peak_index(i, n, scatter);
-        uint64_t expect = round;
-        if (!__hip_atomic_compare_exchange_strong(p, &expect, (uint64_t)round + 1, __ATOMIC_RELAXED,
-                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-            ++bad;
+        if (OP == 0) {
+            uint64_t expect = round;
+            if (!__hip_atomic_compare_exchange_strong(p, &expect, (uint64_t)round + 1,
+                                                      __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT))
+                ++bad;
+        } else {
+            if (__hip_atomic_exchange(p, (uint64_t)round + 1, __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT) != round)
+                ++bad;
+        }
     }
     if (bad) atomicAdd(fails, bad);
 }
@@ -76,12 +88,16 @@ extern "C" hr_status hr_peak_copy(const void* src_dev, void* dst_dev, size_t byt
     return HR_OK;
 }
 
-extern "C" hr_status hr_peak_cas(uint64_t* words_dev, size_t n, uint32_t round, uint32_t scatter,
-                                 uint32_t* fails_dev, void* stream)
+extern "C" hr_status hr_peak_atomic(uint64_t* words_dev, size_t n, uint32_t op, uint32_t round,
+                                    uint32_t scatter, uint32_t* fails_dev, void* stream)
 {
-    if (!words_dev || !fails_dev || n == 0) return HR_E_INVAL;
-    HR_LAUNCH(k_cas, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream, words_dev, n, round,
-              scatter, fails_dev);
+    if (!words_dev || !fails_dev || n == 0 || op > 1) return HR_E_INVAL;
+    if (op == 0)
+        HR_LAUNCH(k_atomic<0>, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream, words_dev, n,
+                  round, scatter, fails_dev);
+    else
+        HR_LAUNCH(k_atomic<1>, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream, words_dev, n,
+                  round, scatter, fails_dev);
     return HR_OK;
 }
 

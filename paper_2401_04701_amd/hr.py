@@ -74,7 +74,7 @@ def _load():
         "hr_labelprop_plain": [P, P, P, P, u32, u32, P],
         "hr_program_check": [P, P, u32, u32, u32, u32, P, P, P, sz, P, sz, P, u32, P],
         "hr_peak_copy": [P, P, sz, P],
-        "hr_peak_cas": [P, sz, u32, u32, P, P],
+        "hr_peak_atomic": [P, sz, u32, u32, u32, P, P],
         "hr_peak_load": [P, sz, u32, P, P],
     }
     for name, args in sigs.items():
@@ -89,7 +89,7 @@ EXPORTED = ("hr_ctx_create", "hr_ctx_destroy", "hr_shadow_alloc", "hr_dev_args",
             "hr_kernel_end", "hr_reset", "hr_report", "hr_check_count", "hr_fsm_step", "hr_fsm_merge",
             "hr_reduce_check", "hr_reduce_plain", "hr_jacobi_check", "hr_jacobi_plain",
             "hr_labelprop_check", "hr_labelprop_plain", "hr_program_check",
-            "hr_peak_copy", "hr_peak_cas", "hr_peak_load")
+            "hr_peak_copy", "hr_peak_atomic", "hr_peak_load")
 
 
 def lib():
@@ -154,9 +154,9 @@ def peak_copy(src, dst, stream=None):
                                              _stream_ptr(stream)))
 
 
-def peak_cas(words, rnd, scatter, fails, stream=None):
-    _check("hr_peak_cas", _lib.hr_peak_cas(_dptr(words), words.numel(), rnd, scatter, _dptr(fails),
-                                           _stream_ptr(stream)))
+def peak_atomic(words, op, rnd, scatter, fails, stream=None):
+    _check("hr_peak_atomic", _lib.hr_peak_atomic(_dptr(words), words.numel(), op, rnd, scatter,
+                                                 _dptr(fails), _stream_ptr(stream)))
 
 
 def peak_load(words, scatter, sink, stream=None):
