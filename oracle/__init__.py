@@ -58,6 +58,8 @@ def _lib():
         lib.orc_race_pair.restype = i32
         lib.orc_model_reduce.argtypes = [i32, u32, P, sz]
         lib.orc_model_reduce.restype = sz
+        lib.orc_model_reduce_n.argtypes = [u32, u32, u32, i32, u32, P, sz]
+        lib.orc_model_reduce_n.restype = sz
         lib.orc_model_jacobi.argtypes = [u32, u32, u32, u32, P, u32, u32, u32, u32, P, sz]
         lib.orc_model_jacobi.restype = sz
         lib.orc_model_labelprop.argtypes = [u32, P, P, P, u32, u32, u32, i32, P, P, sz]
@@ -118,6 +120,12 @@ def _run_model(fn, *args):
 def model_reduce(drop: int = -1, launch: int = 0) -> np.ndarray:
     """Access log of the one-block LDS tree reduction (drop: barrier removed)."""
     return _run_model(_lib().orc_model_reduce, int(drop), int(launch))
+
+
+def model_reduce_n(n: int, threads: int, blocks: int, drop: int = -1,
+                   launch: int = 0) -> np.ndarray:
+    """Access log of the scaled LDS tree reduction (n words per block)."""
+    return _run_model(_lib().orc_model_reduce_n, n, threads, blocks, int(drop), int(launch))
 
 
 def model_jacobi(ny: int, nx: int, launches: int, seed_tab=None, window=None,

@@ -26,6 +26,26 @@ def reduce_flagged(drop: int) -> set:
     return {(1, 0, 0, i) for i in range(128 >> drop, 256 >> drop)}
 
 
+def reduce_n_flagged(n: int, threads: int, blocks: int, drop: int) -> set:
+    """Scaled reduction (n words per block, n a power of two <= 2 * threads).
+
+    Step s halves h = n >> (s+1).  Without the barrier after step k (not the
+    last), step k+1 reads a[t + h'] (h' = n >> (k+2)) in the block epoch in
+    which thread t + h' wrote it: words [n >> (k+2), n >> (k+1)) race in every
+    block.  Without the last step's barrier, the final reads of a[0] meet
+    thread 0's last write.  The load barrier (n != 2 * threads) is never
+    dropped, so the loads race with nothing.
+    """
+    steps = n.bit_length() - 1
+    if drop is None or drop < 0 or drop >= steps:
+        return set()
+    if drop == steps - 1:
+        words = [0]
+    else:
+        words = range(n >> (drop + 2), n >> (drop + 1))
+    return {(1, 0, b, i) for b in range(blocks) for i in words}
+
+
 def jacobi_flagged(ny: int, nx: int, launches: int, seeds, launch0: int = 0) -> set:
     """Jacobi sweeps with seeded neighbour-cell writes.
 

@@ -200,33 +200,49 @@ static void emit(sink* s, uint32_t space, uint32_t region, uint64_t index,
 }
 
 /*
- * One-block LDS tree reduction (512 int32, 256 threads, 9 halving steps with
- * a block barrier after each, then every thread copies a[0] out).
- * Global region 0 = in[512], global region 1 = out[256], LDS region 0 = a[512].
- * drop in 0..8 removes that step's barrier; any other value removes none.
+ * LDS tree reduction: each of `blocks` blocks of T threads sums n int32
+ * words (n a power of two, n <= 2T).  Thread t loads words t, t+T, ... of
+ * its block's slice; when n != 2T a block barrier follows the loads (a
+ * thread's first operand then comes from another thread).  Step s
+ * (h = n >> (s+1)): threads t < h read a[t] and a[t+h] and write a[t]; a
+ * block barrier follows unless s == drop.  Every thread then reads a[0] and
+ * writes out[b*T + t].  Global region 0 = in, 1 = out; LDS array 0 = a.
+ * The paper-sized case is n = 512, T = 256, one block.
  */
-size_t orc_model_reduce(int drop, uint32_t launch, orc_rec* out, size_t cap)
+size_t orc_model_reduce_n(uint32_t n, uint32_t T, uint32_t blocks, int drop, uint32_t launch,
+                          orc_rec* out, size_t cap)
 {
     sink s = {out, cap, 0};
-    for (uint32_t t = 0; t < 256; ++t) {
-        uint32_t bc = 0;
-        emit(&s, SP_GLOBAL, 0, t, K_READ, launch, 0, t, bc, 0);
-        emit(&s, SP_LDS, 0, t, K_WRITE, launch, 0, t, bc, 0);
-        emit(&s, SP_GLOBAL, 0, t + 256, K_READ, launch, 0, t, bc, 0);
-        emit(&s, SP_LDS, 0, t + 256, K_WRITE, launch, 0, t, bc, 0);
-        for (int step = 0; step < 9; ++step) {
-            uint32_t h = 256u >> step;
-            if (t < h) {
-                emit(&s, SP_LDS, 0, t, K_READ, launch, 0, t, bc, 0);
-                emit(&s, SP_LDS, 0, t + h, K_READ, launch, 0, t, bc, 0);
-                emit(&s, SP_LDS, 0, t, K_WRITE, launch, 0, t, bc, 0);
+    uint32_t steps = 0;
+    while ((1u << steps) < n) ++steps;
+    for (uint32_t b = 0; b < blocks; ++b) {
+        for (uint32_t t = 0; t < T; ++t) {
+            uint32_t bc = 0;
+            for (uint32_t j = t; j < n; j += T) {
+                emit(&s, SP_GLOBAL, 0, (uint64_t)b * n + j, K_READ, launch, b, t, bc, 0);
+                emit(&s, SP_LDS, 0, j, K_WRITE, launch, b, t, bc, 0);
             }
-            if (step != drop) ++bc;
+            if (n != 2 * T) ++bc;
+            for (uint32_t step = 0; step < steps; ++step) {
+                const uint32_t h = n >> (step + 1);
+                if (t < h) {
+                    emit(&s, SP_LDS, 0, t, K_READ, launch, b, t, bc, 0);
+                    emit(&s, SP_LDS, 0, t + h, K_READ, launch, b, t, bc, 0);
+                    emit(&s, SP_LDS, 0, t, K_WRITE, launch, b, t, bc, 0);
+                }
+                if ((int)step != drop) ++bc;
+            }
+            emit(&s, SP_LDS, 0, 0, K_READ, launch, b, t, bc, 0);
+            emit(&s, SP_GLOBAL, 1, (uint64_t)b * T + t, K_WRITE, launch, b, t, bc, 0);
         }
-        emit(&s, SP_LDS, 0, 0, K_READ, launch, 0, t, bc, 0);
-        emit(&s, SP_GLOBAL, 1, t, K_WRITE, launch, 0, t, bc, 0);
     }
     return s.n;
+}
+
+/* The paper-sized reduction: 512 words, 256 threads, one block. */
+size_t orc_model_reduce(int drop, uint32_t launch, orc_rec* out, size_t cap)
+{
+    return orc_model_reduce_n(512, 256, 1, drop, launch, out, cap);
 }
 
 /*

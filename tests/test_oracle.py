@@ -102,6 +102,20 @@ def test_reduce_closed_form(drop):
     assert oracle.flagged(log) == cf.reduce_flagged(drop)
 
 
+@pytest.mark.parametrize("n,threads,blocks", [(512, 256, 1), (256, 256, 3), (64, 128, 2),
+                                             (2, 64, 1), (128, 64, 4), (2048, 1024, 2)])
+def test_scaled_reduce_closed_form(n, threads, blocks):
+    """The scaled reduction used by batched jobs; with n = 2 * threads there
+    is no barrier after the loads, as in the paper-sized case."""
+    steps = n.bit_length() - 1
+    for drop in [-1] + list(range(steps)):
+        log = oracle.model_reduce_n(n, threads, blocks, drop)
+        assert log.shape[0] == blocks * (2 * n + 3 * (n - 1) + 2 * threads)
+        assert oracle.flagged(log) == cf.reduce_n_flagged(n, threads, blocks, drop)
+    if (n, threads, blocks) == (512, 256, 1):
+        assert np.array_equal(oracle.model_reduce_n(512, 256, 1, 3), oracle.model_reduce(3))
+
+
 @pytest.mark.parametrize("ny,nx,launches,count", [
     (64, 64, 3, 6), (50, 37, 2, 5), (33, 80, 4, 8), (16, 16, 2, 0), (96, 17, 3, 4)])
 def test_jacobi_closed_form(ny, nx, launches, count):
@@ -220,7 +234,8 @@ MUTANTS = {
     "wave_barrier_orders_across_waves": (
         r"p->thread / wave_width == c->thread / wave_width && p->wc != c->wc", "p->wc != c->wc"),
     "reduce_model_drops_epilogue_read": (
-        r"emit\(&s, SP_LDS, 0, 0, K_READ, launch, 0, t, bc, 0\);", ""),
+        r"emit\(&s, SP_LDS, 0, 0, K_READ, launch, b, t, bc, 0\);", ""),
+    "reduce_model_no_load_barrier": (r"if \(n != 2 \* T\) \+\+bc;", ""),
 }
 
 
@@ -233,6 +248,9 @@ def _pins_hold():
                 return False
         for drop in [-1, 3, 8]:
             if oracle.flagged(oracle.model_reduce(drop)) != cf.reduce_flagged(drop):
+                return False
+        for n, t, b, drop in [(64, 64, 2, 1), (128, 128, 1, -1), (32, 64, 2, 4)]:
+            if oracle.flagged(oracle.model_reduce_n(n, t, b, drop)) != cf.reduce_n_flagged(n, t, b, drop):
                 return False
         seeds = si.jacobi_seeds(64, 64, 5, count=6)
         tab = si.jacobi_seed_table(64, 64, seeds)
