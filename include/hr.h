@@ -48,6 +48,9 @@ typedef enum {
     /* An instrumented access named an element outside its region; it was
      * neither checked nor performed by the library's own kernels. */
     HR_W_OUT_OF_RANGE = 4,
+    /* A batched work item waited too long for the previous phase of its job
+     * and was skipped; that job's results are incomplete. */
+    HR_W_STALLED = 8,
     HR_E_INVAL = -1,   /* bad argument */
     HR_E_NOMEM = -2,   /* allocation failed or shadow budget exceeded */
     HR_E_HIP = -3,     /* a HIP runtime call failed */
@@ -101,6 +104,12 @@ hr_status hr_ctx_destroy(hr_ctx c);
 hr_status hr_shadow_alloc(hr_ctx c, const void* data_dev, size_t bytes, uint32_t elem_bytes,
                           uint32_t* region_out);
 
+/* Release the shadow memory of a region made by hr_shadow_alloc (for
+ * long-lived contexts whose jobs end at different times).  Synchronises the
+ * context's stream.  Errors: HR_E_INVAL (unknown or freed region),
+ * HR_E_STATE (the region is a view into a batch's shared allocation). */
+hr_status hr_shadow_free(hr_ctx c, uint32_t region);
+
 /* Copy the plain-old-data block that instrumented kernels receive (shadow
  * pointers, region sizes, report ring, current launch epoch) into out
  * (host memory, cap bytes).  *size_out receives its size.  The block is
@@ -150,13 +159,19 @@ hr_status hr_fsm_merge(uint64_t x, uint64_t y, uint64_t* out);
  * Errors: HR_E_INVAL (bad sizes, regions too small), HR_E_HIP.
  * ---------------------------------------------------------------------- */
 
-/* One-block LDS tree reduction of in_dev[512] (int32) by 256 threads over 9
- * halving steps with a block barrier after each; every thread then writes
- * the sum to out_dev[256].  drop in 0..8 removes that step's barrier (a
- * seeded race); other values keep all barriers.  LDS array id 0. */
+/* LDS tree reduction: each of `blocks` blocks of `threads` threads (a
+ * multiple of 64, <= 1024) sums in_dev[b*n .. b*n+n) (int32; n a power of
+ * two, 2 <= n <= 2*threads) in LDS over log2(n) halving steps with a block
+ * barrier after each (and one after the loads when n != 2*threads); every
+ * thread then writes its block's sum to out_dev[b*threads + t].  drop
+ * names a step whose barrier is removed (a seeded race); a value outside
+ * 0..log2(n)-1 keeps all barriers.  LDS array id 0.  The paper-sized case
+ * is n = 512, threads = 256, blocks = 1. */
 hr_status hr_reduce_check(hr_ctx c, uint32_t r_in, uint32_t r_out, const int32_t* in_dev,
-                          int32_t* out_dev, int32_t drop, void* stream);
-hr_status hr_reduce_plain(const int32_t* in_dev, int32_t* out_dev, int32_t drop, void* stream);
+                          int32_t* out_dev, uint32_t n, uint32_t threads, uint32_t blocks,
+                          int32_t drop, void* stream);
+hr_status hr_reduce_plain(const int32_t* in_dev, int32_t* out_dev, uint32_t n, uint32_t threads,
+                          uint32_t blocks, int32_t drop, void* stream);
 
 /* One 5-point Jacobi sweep u_new = 0.2 (c + n + s + w + e) over an ny x nx
  * fp32 grid (row-major), 16x16-thread blocks staging an 18x18 LDS tile (LDS
@@ -203,6 +218,76 @@ hr_status hr_program_check(hr_ctx c, const uint32_t* regions_host, uint32_t n_re
                            const int32_t* op_off_dev, size_t n_op_off, const uint32_t* ops_dev,
                            size_t n_ops, const uint32_t* block_map_dev, uint32_t lds_words,
                            void* stream);
+
+/* ----------------------------------------------------------------------
+ * Batched checking: many independent checked jobs in one persistent launch.
+ * ---------------------------------------------------------------------- */
+
+#define HR_PAT_REDUCE 0u      /* hr_reduce_check's kernel, phases = 1 */
+#define HR_PAT_JACOBI 1u      /* hr_jacobi_check's kernel, ping-pong over phases */
+#define HR_PAT_LABELPROP 2u   /* hr_labelprop_check's kernel (CSR not monitored) */
+
+/* One checked job.  A phase is one launch of the job's kernel.
+ *  reduce:    n = words per block, threads, blocks, drop; data[0] = in,
+ *             data[1] = out.
+ *  jacobi:    n = columns (nx), ny = rows; data[0] = u0, data[1] = u1
+ *             (phase p reads u[p%2] and writes u[(p+1)%2]), data[2] = NULL
+ *             or the per-block seed table; blocks and threads are derived.
+ *  labelprop: n = vertices, threads = block size; data[0] = label,
+ *             data[1] = row_ptr, data[2] = col, data[3] = seeded-edge mask;
+ *             blocks is derived.
+ * region[] is written by hr_batch_create: the context regions holding the
+ * job's shadow (reduce in/out, jacobi u0/u1, labelprop label / UINT32_MAX).
+ * LDS race records of a batched job carry region[0] as their array id. */
+typedef struct {
+    uint32_t pattern;
+    uint32_t blocks, threads, phases;
+    uint32_t n, ny;
+    int32_t drop;
+    uint32_t region[2];
+    uint32_t pad;
+    const void* data[4];
+} hr_instance;
+
+typedef struct hr_batch_s* hr_batch;
+
+typedef struct {
+    uint32_t workers;     /* resident worker blocks; 0 or too many: all that fit */
+    uint32_t order;       /* 0: phase-major queue; 1: phase-major, largest jobs first */
+    uint32_t spin_limit;  /* wait rounds before an item is skipped; 0: 2^24 */
+    uint32_t variant;     /* 0: one worker per compute unit, 128 registers per lane;
+                             1: two workers per compute unit, 64 registers */
+} hr_batch_tuning;
+
+/* Prepare a batch: allocate one shadow arena for every job (counted against
+ * the context's shadow budget), register its regions in the context, build
+ * the work queues (instance, phase, block) and upload the job table.  inst
+ * stays owned by the caller; region[] is filled in.  Errors: HR_E_INVAL (a
+ * job's shape), HR_E_NOMEM, HR_E_HIP. */
+hr_status hr_batch_create(hr_ctx c, hr_instance* inst, uint32_t n_inst, hr_batch* out);
+
+/* Run every job of the batch to completion in one persistent launch of
+ * 1024-thread worker blocks on `stream`: worker blocks claim items in queue
+ * order; an item of phase p waits until every block of phase p-1 of its job
+ * has finished, and the job's shadow words carry p as their launch epoch.
+ * Clears the batch's shadow and phase counters first.  Races go to the
+ * context's ring (read them with hr_report).  Asynchronous. */
+hr_status hr_batch_run(hr_batch b, const hr_batch_tuning* tune, void* stream);
+
+/* Number of worker blocks of kernel `variant` that fit on the device, and of
+ * work items. */
+hr_status hr_batch_info(hr_batch b, uint32_t variant, uint32_t* max_workers, uint64_t* items);
+
+/* Free the batch's queues and shadow arena (its regions become invalid).
+ * Synchronises the context's stream. */
+hr_status hr_batch_destroy(hr_batch b);
+
+/* The serial path for one job: create a context with cfg, allocate its
+ * shadow, launch each phase with the job's *_check kernel and a launch
+ * boundary, report into out (as hr_report; region ids 0 and 1), and free
+ * everything.  Synchronous. */
+hr_status hr_job_run(const hr_instance* inst, const hr_config* cfg, hr_race* out, size_t cap,
+                     size_t* n_out, void* stream);
 
 /* ----------------------------------------------------------------------
  * Device microbenchmarks: the roofline denominators of the checking path

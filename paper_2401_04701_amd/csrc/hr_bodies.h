@@ -1,0 +1,220 @@
+// Bodies of the instrumented workloads, as device functions of one logical
+// block.  The standalone kernels run one logical block per hardware block;
+// the batch executor runs them inside persistent worker blocks that may have
+// more threads than the logical block (threads beyond `T` only take part in
+// the block barriers).  CHECK=false compiles the hooks out (plain kernels).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hr_device.h"
+
+// A global region as the hooks see it: its shadow, length and report id.
+struct hr_gref {
+    uint64_t* shadow;
+    uint64_t n;
+    uint32_t id;
+};
+
+template <int KIND, bool CHECK>
+__device__ __forceinline__ void hr_g(const hr_env& e, const hr_thread& t, const hr_gref& g,
+                                     uint64_t index)
+{
+    if constexpr (CHECK) hr_check<KIND>(e, t, g.shadow, g.n, g.id, index);
+}
+
+template <int KIND, bool CHECK>
+__device__ __forceinline__ void hr_l(const hr_env& e, const hr_thread& t, uint32_t* sh,
+                                     uint32_t n, uint32_t id, uint32_t index)
+{
+    if constexpr (CHECK) hr_access_lds<KIND>(e, t, sh, n, id, index);
+}
+
+template <bool CHECK>
+__device__ __forceinline__ void hr_bar(const hr_env& e, hr_thread& t)
+{
+    if constexpr (CHECK) hr_barrier_block(e, t);
+    else __syncthreads();
+}
+
+// Tree reduction of in[lb*n .. lb*n+n) (n a power of two, n <= 2T) by T
+// threads in LDS: load, then log2(n) halving steps, step s adding
+// a[t + (n >> (s+1))] into a[t] for t < n >> (s+1), with a block barrier
+// after each step unless s == drop; every thread then writes a[0] to
+// out[lb*T + t].  When n < 2T a thread's step-0 operand was loaded by
+// another thread, so a barrier also follows the loads.
+template <bool CHECK>
+__device__ void reduce_body(const hr_env& e, const hr_gref& gin, const hr_gref& gout,
+                            const int32_t* __restrict__ in, int32_t* __restrict__ out, uint32_t n,
+                            uint32_t T, uint32_t lb, int32_t drop, int32_t* s, uint32_t* sh,
+                            uint32_t lds_id)
+{
+    const uint32_t t = threadIdx.x;
+    const bool act = t < T;
+    hr_thread th{};
+    if constexpr (CHECK) {
+        th = hr_thread_make(e, lb, t);
+        for (uint32_t i = t; i < n; i += blockDim.x) sh[i] = 0;
+        __syncthreads();
+    }
+    const size_t base = (size_t)lb * n;
+    if (act) {
+        for (uint32_t j = t; j < n; j += T) {
+            s[j] = in[base + j];
+            hr_g<0, CHECK>(e, th, gin, base + j);
+            hr_l<1, CHECK>(e, th, sh, n, lds_id, j);
+        }
+    }
+    if (n != 2 * T) hr_bar<CHECK>(e, th);
+    const int32_t steps = 31 - __builtin_clz(n);
+    for (int32_t step = 0; step < steps; ++step) {
+        const uint32_t h = n >> (step + 1);
+        if (act && t < h) {
+            const int32_t x = s[t];
+            hr_l<0, CHECK>(e, th, sh, n, lds_id, t);
+            const int32_t y = s[t + h];
+            hr_l<0, CHECK>(e, th, sh, n, lds_id, t + h);
+            s[t] = x + y;
+            hr_l<1, CHECK>(e, th, sh, n, lds_id, t);
+        }
+        if (step != drop) hr_bar<CHECK>(e, th);
+    }
+    if (act) {
+        const int32_t r = s[0];
+        hr_l<0, CHECK>(e, th, sh, n, lds_id, 0);
+        out[(size_t)lb * T + t] = r;
+        hr_g<1, CHECK>(e, th, gout, (size_t)lb * T + t);
+    }
+}
+
+constexpr uint32_t JACOBI_TILE = 18;
+constexpr uint32_t JACOBI_TILE_WORDS = JACOBI_TILE * JACOBI_TILE;
+
+// One 16x16 tile (logical block lb of a grid nbx tiles wide) of the 5-point
+// sweep u_new = 0.2 (c + n + s + w + e), staged through an 18x18 LDS tile.
+// seeds: NULL or per-block (side << 8 | offset) entries (-1: none); a seeded
+// block's edge thread also writes the neighbour-owned halo cell.
+template <bool CHECK>
+__device__ void jacobi_body(const hr_env& e, const hr_gref& gold, const hr_gref& gnew,
+                            const float* __restrict__ uo, float* __restrict__ un, uint32_t ny,
+                            uint32_t nx, uint32_t nbx, const int32_t* __restrict__ seeds,
+                            uint32_t lb, float* tile, uint32_t* tsh, uint32_t lds_id)
+{
+    constexpr uint32_t TW = JACOBI_TILE_WORDS, TL = JACOBI_TILE;
+    const uint32_t t = threadIdx.x, tx = t & 15u, ty = (t >> 4) & 15u;
+    const uint32_t bx = lb % nbx, by = lb / nbx;
+    const uint32_t gx = bx * 16u + tx, gy = by * 16u + ty;
+    const bool inside = t < 256 && gx < nx && gy < ny;
+    hr_thread th{};
+    if constexpr (CHECK) {
+        th = hr_thread_make(e, lb, t);
+        for (uint32_t i = t; i < TW; i += blockDim.x) tsh[i] = 0;
+        __syncthreads();
+    }
+    const size_t g = (size_t)gy * nx + gx;
+    const uint32_t cl = (ty + 1) * TL + tx + 1;
+    if (inside) {
+        tile[cl] = uo[g];
+        hr_g<0, CHECK>(e, th, gold, g);
+        hr_l<1, CHECK>(e, th, tsh, TW, lds_id, cl);
+        if (ty == 0 && gy > 0) {
+            tile[tx + 1] = uo[g - nx];
+            hr_g<0, CHECK>(e, th, gold, g - nx);
+            hr_l<1, CHECK>(e, th, tsh, TW, lds_id, tx + 1);
+        }
+        if (ty == 15 && gy + 1 < ny) {
+            tile[17 * TL + tx + 1] = uo[g + nx];
+            hr_g<0, CHECK>(e, th, gold, g + nx);
+            hr_l<1, CHECK>(e, th, tsh, TW, lds_id, 17 * TL + tx + 1);
+        }
+        if (tx == 0 && gx > 0) {
+            tile[(ty + 1) * TL] = uo[g - 1];
+            hr_g<0, CHECK>(e, th, gold, g - 1);
+            hr_l<1, CHECK>(e, th, tsh, TW, lds_id, (ty + 1) * TL);
+        }
+        if (tx == 15 && gx + 1 < nx) {
+            tile[(ty + 1) * TL + 17] = uo[g + 1];
+            hr_g<0, CHECK>(e, th, gold, g + 1);
+            hr_l<1, CHECK>(e, th, tsh, TW, lds_id, (ty + 1) * TL + 17);
+        }
+    }
+    hr_bar<CHECK>(e, th);
+    if (inside) {
+        const float c = tile[cl];
+        hr_l<0, CHECK>(e, th, tsh, TW, lds_id, cl);
+        float vn = c, vs = c, vw = c, ve = c;
+        if (gy > 0) {
+            vn = tile[cl - TL];
+            hr_l<0, CHECK>(e, th, tsh, TW, lds_id, cl - TL);
+        }
+        if (gy + 1 < ny) {
+            vs = tile[cl + TL];
+            hr_l<0, CHECK>(e, th, tsh, TW, lds_id, cl + TL);
+        }
+        if (gx > 0) {
+            vw = tile[cl - 1];
+            hr_l<0, CHECK>(e, th, tsh, TW, lds_id, cl - 1);
+        }
+        if (gx + 1 < nx) {
+            ve = tile[cl + 1];
+            hr_l<0, CHECK>(e, th, tsh, TW, lds_id, cl + 1);
+        }
+        const float r = 0.2f * (c + vn + vs + vw + ve);
+        un[g] = r;
+        hr_g<1, CHECK>(e, th, gnew, g);
+        if (seeds) {
+            const int32_t sd = seeds[lb];
+            if (sd >= 0) {
+                const uint32_t side = (uint32_t)sd >> 8, off = (uint32_t)sd & 255u;
+                int64_t tgt = -1;
+                if (side == 0 && ty == 0 && tx == off && gy > 0) tgt = (int64_t)g - nx;
+                else if (side == 1 && ty == 15 && tx == off && gy + 1 < ny) tgt = (int64_t)g + nx;
+                else if (side == 2 && tx == 0 && ty == off && gx > 0) tgt = (int64_t)g - 1;
+                else if (side == 3 && tx == 15 && ty == off && gx + 1 < nx) tgt = (int64_t)g + 1;
+                if (tgt >= 0) {
+                    un[tgt] = r;
+                    hr_g<1, CHECK>(e, th, gnew, (uint64_t)tgt);
+                }
+            }
+        }
+    }
+}
+
+// One logical block (T threads, vertices lb*T .. lb*T+T) of label
+// propagation: l = atomic load of label[v]; for every edge (v, u) an atomic
+// min of l into label[u], or for a seeded edge a plain read and plain write
+// of label[u].  grp / gcol: optional monitoring of the CSR reads (shadow
+// null when off).
+template <bool CHECK>
+__device__ void labelprop_body(const hr_env& e, const hr_gref& glab, const hr_gref& grp,
+                               const hr_gref& gcol, int32_t* __restrict__ label,
+                               const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                               const uint8_t* __restrict__ mask, uint32_t n, uint32_t T, uint32_t lb)
+{
+    const uint32_t t = threadIdx.x;
+    const uint32_t v = lb * T + t;
+    if (t >= T || v >= n) return;
+    hr_thread th{};
+    if constexpr (CHECK) th = hr_thread_make(e, lb, t);
+    const int32_t l = __hip_atomic_load(label + v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    hr_g<2, CHECK>(e, th, glab, v);
+    const int32_t e0 = rp[v], e1 = rp[v + 1];
+    if (CHECK && grp.shadow) {
+        hr_g<0, CHECK>(e, th, grp, v);
+        hr_g<0, CHECK>(e, th, grp, v + 1);
+    }
+    for (int32_t k = e0; k < e1; ++k) {
+        const uint32_t u = (uint32_t)col[k];
+        if (CHECK && gcol.shadow) hr_g<0, CHECK>(e, th, gcol, (uint64_t)k);
+        if (u >= n) continue;
+        if (mask[k]) {
+            const int32_t r = label[u];
+            hr_g<0, CHECK>(e, th, glab, u);
+            label[u] = r < l ? r : l;
+            hr_g<1, CHECK>(e, th, glab, u);
+        } else {
+            atomicMin(label + u, l);
+            hr_g<2, CHECK>(e, th, glab, u);
+        }
+    }
+}

@@ -1,29 +1,29 @@
 // Device side of the race checker: what instrumented HIP kernels call.
 //
-//   hr_thread t = hr_thread_make(args, logical_block, thread_in_block);
+//   hr_thread t = hr_thread_make(args.env, logical_block, thread_in_block);
 //   ... data access ...;  hr_access<HR_READ>(args, t, region, index);
-//   hr_barrier_block(args, t);   // replaces __syncthreads()
-//   hr_barrier_wave(args, t);    // wave-scope barrier
+//   hr_barrier_block(args.env, t);   // replaces __syncthreads()
+//   hr_barrier_wave(args.env, t);    // wave-scope barrier
 //
 // Each hook is the lock-free shadow update of the paper's Algorithm 1
 // (Sec. IV-B): read the shadow word, derive the thread relation and sync
-// status, step the state machine, and publish the new word with a
-// compare-and-swap, retrying on contention.  The hook need not be atomic
-// with the access it checks (Sec. III-A, Scenario 1); it only has to finish
-// before the thread passes its next barrier or its launch ends, which the
-// blocking compare-and-swap guarantees, so shadow updates are applied in an
-// order consistent with happens-before.
+// status, step the state machine, and publish the new word atomically.  The
+// hook need not be atomic with the access it checks (Sec. III-A, Scenario 1);
+// it only has to finish before the thread passes its next barrier or its
+// launch ends.  Every hook waits for the result of its own atomics, so shadow
+// updates are applied in an order consistent with happens-before.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 #include "hr_fsm.h"
 
-#define HR_MAX_REGIONS 16
+#define HR_MAX_REGIONS 16   // regions addressable by kernel arguments
 
-// Device-flag bits (hr_kargs::ctr[HR_CTR_FLAGS]).
+// Device-flag bits (ctr[HR_CTR_FLAGS]).
 #define HR_DEVF_CLOCK 1u
 #define HR_DEVF_RANGE 4u
+#define HR_DEVF_STALL 8u    // a batched item gave up waiting for its phase
 
 // Counter words.
 #define HR_CTR_HEAD 0     // ring append index
@@ -44,19 +44,25 @@ struct hr_race_rec {
 };
 static_assert(sizeof(hr_race_rec) == 32, "race record is 32 bytes");
 
-// Plain-old-data block handed to instrumented kernels by value.
-struct hr_kargs {
-    uint64_t* shadow[HR_MAX_REGIONS];   // 8-byte shadow word per element
-    uint64_t n_elems[HR_MAX_REGIONS];   // elements per region (0: unused)
-    void* data[HR_MAX_REGIONS];         // monitored buffer of each region
+// What hooks and barriers need besides the shadow of the accessed region:
+// the report ring, counters, the launch epoch and the clock limits.
+struct hr_env {
     hr_race_rec* ring;
     uint32_t* ctr;                      // HR_CTR_* words
+    unsigned long long* count;          // HR_COUNT_SLOTS counters, or null
     uint32_t ring_cap;
     uint32_t launch;                    // launch epoch (9 bits)
     uint32_t launch_seq;                // launch sequence number (reports)
     uint32_t bc_max;                    // last valid block-clock value
     uint32_t wc_max;                    // last valid wave-clock value
-    unsigned long long* count;          // HR_COUNT_SLOTS counters, or null
+};
+
+// Plain-old-data block handed to instrumented kernels by value.
+struct hr_kargs {
+    hr_env env;
+    uint64_t* shadow[HR_MAX_REGIONS];   // 8-byte shadow word per element
+    uint64_t n_elems[HR_MAX_REGIONS];   // elements per region (0: unused)
+    void* data[HR_MAX_REGIONS];         // monitored buffer of each region
 };
 
 // Per-thread checker state, kept in registers.
@@ -69,7 +75,7 @@ struct hr_thread {
     uint32_t enabled;    // cleared after a clock overflow
 };
 
-__device__ __forceinline__ hr_thread hr_thread_make(const hr_kargs& a, uint32_t block,
+__device__ __forceinline__ hr_thread hr_thread_make(const hr_env& e, uint32_t block,
                                                     uint32_t thread)
 {
     hr_thread t;
@@ -78,46 +84,46 @@ __device__ __forceinline__ hr_thread hr_thread_make(const hr_kargs& a, uint32_t 
     t.bc = 0;
     t.wc = 0;
     t.enabled = 1;
-    t.gid = hr::g::pack_id(a.launch, block, thread, 0, 0);
+    t.gid = hr::g::pack_id(e.launch, block, thread, 0, 0);
     t.lid = hr::l::pack_id(thread, 0, 0);
     return t;
 }
 
-__device__ __forceinline__ void hr_set_flag(const hr_kargs& a, uint32_t bit)
+__device__ __forceinline__ void hr_set_flag(const hr_env& e, uint32_t bit)
 {
-    __hip_atomic_fetch_or(a.ctr + HR_CTR_FLAGS, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_or(e.ctr + HR_CTR_FLAGS, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Debug counting of checked accesses: one atomic per wave and hook, spread
 // over HR_COUNT_SLOTS words by block to avoid a single hot address.
-__device__ __forceinline__ void hr_count(const hr_kargs& a, const hr_thread& t)
+__device__ __forceinline__ void hr_count(const hr_env& e, const hr_thread& t)
 {
-    if (a.count) {
+    if (e.count) {
         const uint64_t m = __ballot(1);
         if (__lane_id() == (uint32_t)__builtin_ctzll(m))
-            __hip_atomic_fetch_add(a.count + (t.block % HR_COUNT_SLOTS),
+            __hip_atomic_fetch_add(e.count + (t.block % HR_COUNT_SLOTS),
                                    (unsigned long long)__popcll(m), __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
-__device__ __forceinline__ void hr_ring_push(const hr_kargs& a, uint32_t space, uint32_t region,
+__device__ __forceinline__ void hr_ring_push(const hr_env& e, uint32_t space, uint32_t region,
                                              uint32_t block, uint64_t index, uint32_t tid,
                                              uint32_t before)
 {
-    const uint32_t slot = __hip_atomic_fetch_add(a.ctr + HR_CTR_HEAD, 1u, __ATOMIC_RELAXED,
+    const uint32_t slot = __hip_atomic_fetch_add(e.ctr + HR_CTR_HEAD, 1u, __ATOMIC_RELAXED,
                                                  __HIP_MEMORY_SCOPE_AGENT);
-    if (slot < a.ring_cap) {
+    if (slot < e.ring_cap) {
         hr_race_rec r;
         r.space = (uint8_t)space;
         r.pad[0] = r.pad[1] = r.pad[2] = 0;
         r.region = region;
         r.block = block;
-        r.launch = a.launch_seq;
+        r.launch = e.launch_seq;
         r.index = index;
         r.tid = tid;
         r.state_before = before;
-        a.ring[slot] = r;
+        e.ring[slot] = r;
     }
 }
 
@@ -144,7 +150,8 @@ __device__ __noinline__ uint64_t hr_fold(uint64_t* sp, uint64_t mine, uint64_t l
 }
 
 // Check one access of kind KIND (0 read, 1 write, 2 atomic) to element
-// `index` of global region `region`.
+// `index` of a global region whose shadow is shadow[0..n); `region` is the
+// id written into a race record.
 //
 // The copy-compute-publish loop of the paper's Algorithm 1, published with an
 // atomic exchange instead of a compare-and-swap (on gfx950 a 64-bit exchange
@@ -154,44 +161,56 @@ __device__ __noinline__ uint64_t hr_fold(uint64_t* sp, uint64_t mine, uint64_t l
 // Otherwise it overwrote updates made since the load, and hr_fold merges
 // them back.
 template <int KIND>
-__device__ __forceinline__ void hr_access(const hr_kargs& a, const hr_thread& t,
-                                          uint32_t region, uint64_t index)
+__device__ __forceinline__ void hr_check(const hr_env& e, const hr_thread& t, uint64_t* shadow,
+                                         uint64_t n, uint32_t region, uint64_t index)
 {
     if (!t.enabled) return;
-    hr_count(a, t);
-    if (region >= HR_MAX_REGIONS || index >= a.n_elems[region]) {
-        hr_set_flag(a, HR_DEVF_RANGE);
+    hr_count(e, t);
+    if (index >= n) {
+        hr_set_flag(e, HR_DEVF_RANGE);
         return;
     }
     constexpr uint32_t k = KIND == 0 ? hr::CL_R : (KIND == 2 ? hr::CL_A : hr::CL_X);
-    uint64_t* sp = a.shadow[region] + index;
+    uint64_t* sp = shadow + index;
     const uint64_t old = __hip_atomic_load(sp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const uint64_t nw = hr::g::step(old, t.gid, k);
     if (nw == old) return;
     const uint64_t r = __hip_atomic_exchange(sp, nw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (nw == hr::T_RACE) {
-        if (r != hr::T_RACE) hr_ring_push(a, 0, region, t.block, index, t.thread, (uint32_t)old);
+        if (r != hr::T_RACE) hr_ring_push(e, 0, region, t.block, index, t.thread, (uint32_t)old);
         return;
     }
     if (r != old) {
         const uint64_t before = hr_fold(sp, nw, r);
         if (before != HR_NO_REPORT)
-            hr_ring_push(a, 0, region, t.block, index, t.thread, (uint32_t)before);
+            hr_ring_push(e, 0, region, t.block, index, t.thread, (uint32_t)before);
     }
+}
+
+// The same check for a region named by its kernel-argument slot.
+template <int KIND>
+__device__ __forceinline__ void hr_access(const hr_kargs& a, const hr_thread& t, uint32_t region,
+                                          uint64_t index)
+{
+    if (region >= HR_MAX_REGIONS) {
+        if (t.enabled) hr_set_flag(a.env, HR_DEVF_RANGE);
+        return;
+    }
+    hr_check<KIND>(a.env, t, a.shadow[region], a.n_elems[region], region, index);
 }
 
 // Check one access to word `index` of a block's LDS array `array_id`, whose
 // 4-byte shadow words live in LDS at `sh` (n_words of them, cleared to 0 at
-// block start).
+// block start).  LDS atomics are cheap, so this path keeps the
+// compare-and-swap loop.
 template <int KIND>
-__device__ __forceinline__ void hr_access_lds(const hr_kargs& a, const hr_thread& t,
-                                              uint32_t* sh, uint32_t n_words, uint32_t array_id,
-                                              uint32_t index)
+__device__ __forceinline__ void hr_access_lds(const hr_env& e, const hr_thread& t, uint32_t* sh,
+                                              uint32_t n_words, uint32_t array_id, uint32_t index)
 {
     if (!t.enabled) return;
-    hr_count(a, t);
+    hr_count(e, t);
     if (index >= n_words) {
-        hr_set_flag(a, HR_DEVF_RANGE);
+        hr_set_flag(e, HR_DEVF_RANGE);
         return;
     }
     constexpr uint32_t k = KIND == 0 ? hr::CL_R : (KIND == 2 ? hr::CL_A : hr::CL_X);
@@ -203,7 +222,7 @@ __device__ __forceinline__ void hr_access_lds(const hr_kargs& a, const hr_thread
         uint32_t seen = old;
         if (__hip_atomic_compare_exchange_strong(sp, &seen, nw, __ATOMIC_RELAXED,
                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) {
-            if (nw == hr::T_RACE) hr_ring_push(a, 1, array_id, t.block, index, t.thread, old);
+            if (nw == hr::T_RACE) hr_ring_push(e, 1, array_id, t.block, index, t.thread, old);
             return;
         }
         old = seen;
@@ -211,55 +230,56 @@ __device__ __forceinline__ void hr_access_lds(const hr_kargs& a, const hr_thread
 }
 
 // Runtime-kind forms (used where the kind is data, as in the interpreter).
-__device__ __forceinline__ void hr_access_k(const hr_kargs& a, const hr_thread& t, uint32_t kind,
-                                            uint32_t region, uint64_t index)
+__device__ __forceinline__ void hr_check_k(const hr_env& e, const hr_thread& t, uint32_t kind,
+                                           uint64_t* shadow, uint64_t n, uint32_t region,
+                                           uint64_t index)
 {
-    if (kind == 0) hr_access<0>(a, t, region, index);
-    else if (kind == 1) hr_access<1>(a, t, region, index);
-    else hr_access<2>(a, t, region, index);
+    if (kind == 0) hr_check<0>(e, t, shadow, n, region, index);
+    else if (kind == 1) hr_check<1>(e, t, shadow, n, region, index);
+    else hr_check<2>(e, t, shadow, n, region, index);
 }
 
-__device__ __forceinline__ void hr_access_lds_k(const hr_kargs& a, const hr_thread& t,
+__device__ __forceinline__ void hr_access_lds_k(const hr_env& e, const hr_thread& t,
                                                 uint32_t kind, uint32_t* sh, uint32_t n_words,
                                                 uint32_t array_id, uint32_t index)
 {
-    if (kind == 0) hr_access_lds<0>(a, t, sh, n_words, array_id, index);
-    else if (kind == 1) hr_access_lds<1>(a, t, sh, n_words, array_id, index);
-    else hr_access_lds<2>(a, t, sh, n_words, array_id, index);
+    if (kind == 0) hr_access_lds<0>(e, t, sh, n_words, array_id, index);
+    else if (kind == 1) hr_access_lds<1>(e, t, sh, n_words, array_id, index);
+    else hr_access_lds<2>(e, t, sh, n_words, array_id, index);
 }
 
-__device__ __forceinline__ void hr_retag(const hr_kargs& a, hr_thread& t)
+__device__ __forceinline__ void hr_retag(const hr_env& e, hr_thread& t)
 {
-    t.gid = hr::g::pack_id(a.launch, t.block, t.thread, t.bc, t.wc);
+    t.gid = hr::g::pack_id(e.launch, t.block, t.thread, t.bc, t.wc);
     t.lid = hr::l::pack_id(t.thread, t.bc, t.wc);
 }
 
 // Block barrier: every thread of the block must call it (as __syncthreads).
 // Advances the block clock and restarts the wave clock (paper Sec. III-A,
 // Scenario 2: the block-scalar clock BC advances at each block barrier).
-__device__ __forceinline__ void hr_barrier_block(const hr_kargs& a, hr_thread& t)
+__device__ __forceinline__ void hr_barrier_block(const hr_env& e, hr_thread& t)
 {
     __syncthreads();
     t.bc += 1;
     t.wc = 0;
-    if (t.bc > a.bc_max && t.enabled) {
+    if (t.bc > e.bc_max && t.enabled) {
         t.enabled = 0;
-        hr_set_flag(a, HR_DEVF_CLOCK);
+        hr_set_flag(e, HR_DEVF_CLOCK);
     }
-    hr_retag(a, t);
+    hr_retag(e, t);
 }
 
 // Wave barrier: every lane of the wave must call it.  Lanes of a wave are
 // not otherwise ordered by the checker, whatever the hardware does.
-__device__ __forceinline__ void hr_barrier_wave(const hr_kargs& a, hr_thread& t)
+__device__ __forceinline__ void hr_barrier_wave(const hr_env& e, hr_thread& t)
 {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     t.wc += 1;
-    if (t.wc > a.wc_max && t.enabled) {
+    if (t.wc > e.wc_max && t.enabled) {
         t.enabled = 0;
-        hr_set_flag(a, HR_DEVF_CLOCK);
+        hr_set_flag(e, HR_DEVF_CLOCK);
     }
-    hr_retag(a, t);
+    hr_retag(e, t);
 }

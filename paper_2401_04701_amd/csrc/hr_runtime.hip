@@ -26,30 +26,10 @@ __global__ void k_fill32(uint32_t* __restrict__ p, size_t n, uint32_t v)
     for (; i < n; i += stride) p[i] = v;
 }
 
-// Clears with a kernel rather than hipMemsetAsync so that the calls stay
-// safe inside a captured HIP graph.
-hipError_t fill64(uint64_t* p, size_t n, hipStream_t s)
-{
-    if (n == 0) return hipSuccess;
-    const size_t blocks = std::min<size_t>((n + 255) / 256, 8192);
-    (void)hipGetLastError();   // drop stale errors of unrelated earlier calls
-    hipLaunchKernelGGL(k_fill64, dim3((unsigned)blocks), dim3(256), 0, s, p, n, 0ull);
-    return hipGetLastError();
-}
-
-hipError_t fill32(uint32_t* p, size_t n, hipStream_t s)
-{
-    if (n == 0) return hipSuccess;
-    const size_t blocks = std::min<size_t>((n + 255) / 256, 1024);
-    (void)hipGetLastError();   // drop stale errors of unrelated earlier calls
-    hipLaunchKernelGGL(k_fill32, dim3((unsigned)blocks), dim3(256), 0, s, p, n, 0u);
-    return hipGetLastError();
-}
-
 hr_status clear_shadows(hr_ctx c, hipStream_t s)
 {
-    for (uint32_t r = 0; r < c->n_reg; ++r)
-        if (fill64(c->reg[r].shadow, c->reg[r].elems, s) != hipSuccess) return HR_E_HIP;
+    for (const hr_alloc& al : c->allocs)
+        if (al.live && hr_fill64(al.mem, al.words, s) != hipSuccess) return HR_E_HIP;
     return HR_OK;
 }
 
@@ -71,9 +51,95 @@ struct key_less {
 
 }  // namespace
 
+// Clears run as kernels rather than hipMemsetAsync so the calls stay safe
+// inside a captured HIP graph.
+hipError_t hr_fill64(uint64_t* p, size_t n, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    const size_t blocks = std::min<size_t>((n + 255) / 256, 8192);
+    (void)hipGetLastError();   // drop stale errors of unrelated earlier calls
+    hipLaunchKernelGGL(k_fill64, dim3((unsigned)blocks), dim3(256), 0, s, p, n, 0ull);
+    return hipGetLastError();
+}
+
+hipError_t hr_fill32(uint32_t* p, size_t n, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    const size_t blocks = std::min<size_t>((n + 255) / 256, 1024);
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(k_fill32, dim3((unsigned)blocks), dim3(256), 0, s, p, n, 0u);
+    return hipGetLastError();
+}
+
 hipStream_t hr_stream(hr_ctx c, void* stream)
 {
     return stream ? (hipStream_t)stream : c->stream;
+}
+
+hr_env hr_make_env(hr_ctx c)
+{
+    hr_env e{};
+    e.ring = c->ring;
+    e.ctr = c->ctr;
+    e.count = (c->cfg.flags & HR_CFG_COUNT_CHECKS) ? c->count : nullptr;
+    e.ring_cap = c->cfg.ring_capacity;
+    e.launch = c->launch_seq & ((1u << hr::g::LAUNCH_BITS) - 1);
+    e.launch_seq = c->launch_seq;
+    e.bc_max = (1u << c->cfg.bc_bits) - 1;
+    e.wc_max = (1u << c->cfg.wc_bits) - 1;
+    return e;
+}
+
+void hr_fill_args(hr_ctx c, hr_kargs* a)
+{
+    *a = hr_kargs{};
+    a->env = hr_make_env(c);
+    const uint32_t n = (uint32_t)std::min<size_t>(c->reg.size(), HR_MAX_REGIONS);
+    for (uint32_t r = 0; r < n; ++r) {
+        if (!c->reg[r].live) continue;
+        a->shadow[r] = c->reg[r].shadow;
+        a->n_elems[r] = c->reg[r].elems;
+        a->data[r] = const_cast<void*>(c->reg[r].data);
+    }
+}
+
+bool hr_region_ok(hr_ctx c, uint32_t r, const void* data, size_t min_elems)
+{
+    return r < HR_MAX_REGIONS && r < c->reg.size() && c->reg[r].live && c->reg[r].data == data &&
+           c->reg[r].elems >= min_elems;
+}
+
+hr_status hr_new_alloc(hr_ctx c, size_t words, uint32_t* alloc_out)
+{
+    const uint64_t bytes = (uint64_t)words * 8u;
+    if (c->cfg.shadow_budget && c->shadow_bytes + bytes > c->cfg.shadow_budget) return HR_E_NOMEM;
+    uint64_t* mem = nullptr;
+    if (hipMalloc(&mem, bytes) != hipSuccess) return HR_E_NOMEM;
+    if (hr_fill64(mem, words, c->stream) != hipSuccess) {
+        (void)hipFree(mem);
+        return HR_E_HIP;
+    }
+    c->allocs.push_back(hr_alloc{mem, words, true});
+    c->shadow_bytes += bytes;
+    *alloc_out = (uint32_t)(c->allocs.size() - 1);
+    return HR_OK;
+}
+
+uint32_t hr_new_region(hr_ctx c, const void* data, size_t elems, uint64_t* shadow, uint32_t alloc)
+{
+    c->reg.push_back(hr_region{data, elems, shadow, alloc, true});
+    return (uint32_t)(c->reg.size() - 1);
+}
+
+void hr_free_alloc(hr_ctx c, uint32_t alloc)
+{
+    hr_alloc& al = c->allocs[alloc];
+    if (!al.live) return;
+    (void)hipFree(al.mem);
+    al.live = false;
+    c->shadow_bytes -= (uint64_t)al.words * 8u;
+    for (hr_region& r : c->reg)
+        if (r.alloc == alloc) r.live = false;
 }
 
 extern "C" hr_status hr_ctx_create(hr_ctx* out, const hr_config* cfg, void* stream)
@@ -94,23 +160,14 @@ extern "C" hr_status hr_ctx_create(hr_ctx* out, const hr_config* cfg, void* stre
         delete c;
         return HR_E_HIP;
     }
-    if (hipMalloc(&c->ring, sizeof(hr_race_rec) * (size_t)k.ring_capacity) != hipSuccess) {
-        delete c;
+    if (hipMalloc(&c->ring, sizeof(hr_race_rec) * (size_t)k.ring_capacity) != hipSuccess ||
+        hipMalloc(&c->ctr, sizeof(uint32_t) * HR_CTR_WORDS) != hipSuccess ||
+        hipMalloc(&c->count, sizeof(unsigned long long) * HR_COUNT_SLOTS) != hipSuccess) {
+        hr_ctx_destroy(c);
         return HR_E_NOMEM;
     }
-    if (hipMalloc(&c->ctr, sizeof(uint32_t) * HR_CTR_WORDS) != hipSuccess) {
-        (void)hipFree(c->ring);
-        delete c;
-        return HR_E_NOMEM;
-    }
-    if (hipMalloc(&c->count, sizeof(unsigned long long) * HR_COUNT_SLOTS) != hipSuccess) {
-        (void)hipFree(c->ring);
-        (void)hipFree(c->ctr);
-        delete c;
-        return HR_E_NOMEM;
-    }
-    if (fill32(c->ctr, HR_CTR_WORDS, c->stream) != hipSuccess ||
-        fill64((uint64_t*)c->count, HR_COUNT_SLOTS, c->stream) != hipSuccess) {
+    if (hr_fill32(c->ctr, HR_CTR_WORDS, c->stream) != hipSuccess ||
+        hr_fill64((uint64_t*)c->count, HR_COUNT_SLOTS, c->stream) != hipSuccess) {
         hr_ctx_destroy(c);
         return HR_E_HIP;
     }
@@ -122,10 +179,11 @@ extern "C" hr_status hr_ctx_destroy(hr_ctx c)
 {
     if (!c) return HR_E_INVAL;
     hipError_t e = hipStreamSynchronize(c->stream);
-    for (uint32_t r = 0; r < c->n_reg; ++r) (void)hipFree(c->reg[r].shadow);
-    (void)hipFree(c->ring);
-    (void)hipFree(c->ctr);
-    (void)hipFree(c->count);
+    for (hr_alloc& al : c->allocs)
+        if (al.live) (void)hipFree(al.mem);
+    if (c->ring) (void)hipFree(c->ring);
+    if (c->ctr) (void)hipFree(c->ctr);
+    if (c->count) (void)hipFree(c->count);
     delete c;
     return e == hipSuccess ? HR_OK : HR_E_HIP;
 }
@@ -134,41 +192,24 @@ extern "C" hr_status hr_shadow_alloc(hr_ctx c, const void* data_dev, size_t byte
                                      uint32_t elem_bytes, uint32_t* region_out)
 {
     if (!c || !region_out || elem_bytes != 4 || bytes == 0 || bytes % 4 != 0) return HR_E_INVAL;
-    if (c->n_reg >= HR_MAX_REGIONS) return HR_E_INVAL;
+    if (c->reg.size() >= (1u << 24)) return HR_E_INVAL;
     const size_t elems = bytes / 4;
-    const uint64_t sbytes = (uint64_t)elems * 8u;
-    if (c->cfg.shadow_budget && c->shadow_bytes + sbytes > c->cfg.shadow_budget) return HR_E_NOMEM;
-    uint64_t* sh = nullptr;
-    if (hipMalloc(&sh, sbytes) != hipSuccess) return HR_E_NOMEM;
-    if (fill64(sh, elems, c->stream) != hipSuccess) {
-        (void)hipFree(sh);
-        return HR_E_HIP;
-    }
-    hr_region& r = c->reg[c->n_reg];
-    r.data = data_dev;
-    r.elems = elems;
-    r.shadow = sh;
-    c->shadow_bytes += sbytes;
-    *region_out = c->n_reg++;
+    uint32_t alloc = 0;
+    const hr_status st = hr_new_alloc(c, elems, &alloc);
+    if (st != HR_OK) return st;
+    *region_out = hr_new_region(c, data_dev, elems, c->allocs[alloc].mem, alloc);
     return HR_OK;
 }
 
-void hr_fill_args(hr_ctx c, hr_kargs* a)
+extern "C" hr_status hr_shadow_free(hr_ctx c, uint32_t region)
 {
-    *a = hr_kargs{};
-    for (uint32_t r = 0; r < c->n_reg; ++r) {
-        a->shadow[r] = c->reg[r].shadow;
-        a->n_elems[r] = c->reg[r].elems;
-        a->data[r] = const_cast<void*>(c->reg[r].data);
-    }
-    a->ring = c->ring;
-    a->ctr = c->ctr;
-    a->ring_cap = c->cfg.ring_capacity;
-    a->launch = c->launch_seq & ((1u << hr::g::LAUNCH_BITS) - 1);
-    a->launch_seq = c->launch_seq;
-    a->bc_max = (1u << c->cfg.bc_bits) - 1;
-    a->wc_max = (1u << c->cfg.wc_bits) - 1;
-    a->count = (c->cfg.flags & HR_CFG_COUNT_CHECKS) ? c->count : nullptr;
+    if (!c || region >= c->reg.size() || !c->reg[region].live) return HR_E_INVAL;
+    const uint32_t alloc = c->reg[region].alloc;
+    for (const hr_region& r : c->reg)
+        if (r.live && r.alloc == alloc && &r != &c->reg[region]) return HR_E_STATE;   // shared arena
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return HR_E_HIP;
+    hr_free_alloc(c, alloc);
+    return HR_OK;
 }
 
 extern "C" hr_status hr_dev_args(hr_ctx c, void* out, size_t cap, size_t* size_out)
@@ -198,8 +239,8 @@ extern "C" hr_status hr_reset(hr_ctx c, void* stream)
     hipStream_t s = hr_stream(c, stream);
     hr_status st = clear_shadows(c, s);
     if (st != HR_OK) return st;
-    if (fill32(c->ctr, HR_CTR_WORDS, s) != hipSuccess) return HR_E_HIP;
-    if (fill64((uint64_t*)c->count, HR_COUNT_SLOTS, s) != hipSuccess) return HR_E_HIP;
+    if (hr_fill32(c->ctr, HR_CTR_WORDS, s) != hipSuccess) return HR_E_HIP;
+    if (hr_fill64((uint64_t*)c->count, HR_COUNT_SLOTS, s) != hipSuccess) return HR_E_HIP;
     c->launch_seq = 0;
     return HR_OK;
 }
@@ -220,11 +261,13 @@ extern "C" hr_status hr_report(hr_ctx c, hr_race* out, size_t cap, size_t* n_out
     int warn = 0;
     if (ctr[HR_CTR_FLAGS] & HR_DEVF_CLOCK) warn |= HR_W_CLOCK_OVERFLOW;
     if (ctr[HR_CTR_FLAGS] & HR_DEVF_RANGE) warn |= HR_W_OUT_OF_RANGE;
+    if (ctr[HR_CTR_FLAGS] & HR_DEVF_STALL) warn |= HR_W_STALLED;
     if (head > c->cfg.ring_capacity) {
         // Ring overflow: race states are sticky in global shadow memory, so
         // the global part of the flagged set is recovered from it exactly.
         warn |= HR_W_RING_OVERFLOW;
-        for (uint32_t r = 0; r < c->n_reg; ++r) {
+        for (uint32_t r = 0; r < c->reg.size(); ++r) {
+            if (!c->reg[r].live) continue;
             std::vector<uint64_t> sh(c->reg[r].elems);
             if (hipMemcpy(sh.data(), c->reg[r].shadow, sizeof(uint64_t) * sh.size(),
                           hipMemcpyDeviceToHost) != hipSuccess)

@@ -18,11 +18,13 @@ HR_OK = 0
 HR_W_CLOCK_OVERFLOW = 1
 HR_W_RING_OVERFLOW = 2
 HR_W_OUT_OF_RANGE = 4
+HR_W_STALLED = 8
 HR_E_INVAL, HR_E_NOMEM, HR_E_HIP, HR_E_STATE = -1, -2, -3, -4
 HR_GLOBAL, HR_LDS = 0, 1
 HR_READ, HR_WRITE, HR_ATOMIC = 0, 1, 2
 HR_CFG_COUNT_CHECKS = 1
 NO_REGION = 0xFFFFFFFF
+HR_PAT_REDUCE, HR_PAT_JACOBI, HR_PAT_LABELPROP = 0, 1, 2
 
 # Global shadow-word fields (see csrc/hr_fsm.h), for decoding in tests.
 T_INIT, T_RACE, T_MB, T_MW, T_MT, T_ST = 0, 1, 2, 3, 4, 5
@@ -45,6 +47,23 @@ class _Config(ctypes.Structure):
                 ("shadow_budget", ctypes.c_uint64)]
 
 
+class Instance(ctypes.Structure):
+    """hr_instance: one checked job of a batch (see include/hr.h)."""
+    _fields_ = [("pattern", ctypes.c_uint32), ("blocks", ctypes.c_uint32),
+                ("threads", ctypes.c_uint32), ("phases", ctypes.c_uint32),
+                ("n", ctypes.c_uint32), ("ny", ctypes.c_uint32), ("drop", ctypes.c_int32),
+                ("region", ctypes.c_uint32 * 2), ("pad", ctypes.c_uint32),
+                ("data", ctypes.c_void_p * 4)]
+
+
+class _Tuning(ctypes.Structure):
+    _fields_ = [("workers", ctypes.c_uint32), ("order", ctypes.c_uint32),
+                ("spin_limit", ctypes.c_uint32), ("variant", ctypes.c_uint32)]
+
+
+assert ctypes.sizeof(Instance) == 72
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
@@ -59,6 +78,7 @@ def _load():
         "hr_ctx_create": [P, P, P],
         "hr_ctx_destroy": [P],
         "hr_shadow_alloc": [P, P, sz, u32, P],
+        "hr_shadow_free": [P, u32],
         "hr_dev_args": [P, P, sz, P],
         "hr_kernel_end": [P, P],
         "hr_reset": [P, P],
@@ -66,13 +86,18 @@ def _load():
         "hr_check_count": [P, P, P],
         "hr_fsm_step": [u32, u64, u32, u32, u32, u32, u32, u32, P],
         "hr_fsm_merge": [u64, u64, P],
-        "hr_reduce_check": [P, u32, u32, P, P, ctypes.c_int32, P],
-        "hr_reduce_plain": [P, P, ctypes.c_int32, P],
+        "hr_reduce_check": [P, u32, u32, P, P, u32, u32, u32, ctypes.c_int32, P],
+        "hr_reduce_plain": [P, P, u32, u32, u32, ctypes.c_int32, P],
         "hr_jacobi_check": [P, u32, u32, P, P, u32, u32, P, P],
         "hr_jacobi_plain": [P, P, u32, u32, P, P],
         "hr_labelprop_check": [P, u32, u32, u32, P, P, P, P, u32, u32, P],
         "hr_labelprop_plain": [P, P, P, P, u32, u32, P],
         "hr_program_check": [P, P, u32, u32, u32, u32, P, P, P, sz, P, sz, P, u32, P],
+        "hr_batch_create": [P, P, u32, P],
+        "hr_batch_run": [P, P, P],
+        "hr_batch_info": [P, u32, P, P],
+        "hr_batch_destroy": [P],
+        "hr_job_run": [P, P, P, sz, P, P],
         "hr_peak_copy": [P, P, sz, P],
         "hr_peak_atomic": [P, sz, u32, u32, u32, P, P],
         "hr_peak_load": [P, sz, u32, P, P],
@@ -85,7 +110,9 @@ def _load():
 
 
 _lib = _load()
-EXPORTED = ("hr_ctx_create", "hr_ctx_destroy", "hr_shadow_alloc", "hr_dev_args",
+EXPORTED = ("hr_ctx_create", "hr_ctx_destroy", "hr_shadow_alloc", "hr_shadow_free",
+            "hr_dev_args", "hr_batch_create", "hr_batch_run", "hr_batch_info",
+            "hr_batch_destroy", "hr_job_run",
             "hr_kernel_end", "hr_reset", "hr_report", "hr_check_count", "hr_fsm_step", "hr_fsm_merge",
             "hr_reduce_check", "hr_reduce_plain", "hr_jacobi_check", "hr_jacobi_plain",
             "hr_labelprop_check", "hr_labelprop_plain", "hr_program_check",
@@ -132,9 +159,9 @@ def fsm_merge(x: int, y: int) -> int:
 
 
 # ---------------------------------------------------------------- plain runs
-def reduce_plain(inp, out, drop=-1, stream=None):
-    _check("hr_reduce_plain", _lib.hr_reduce_plain(_dptr(inp), _dptr(out), int(drop),
-                                                   _stream_ptr(stream)))
+def reduce_plain(inp, out, drop=-1, n=512, threads=256, blocks=1, stream=None):
+    _check("hr_reduce_plain", _lib.hr_reduce_plain(_dptr(inp), _dptr(out), n, threads, blocks,
+                                                   int(drop), _stream_ptr(stream)))
 
 
 def jacobi_plain(u_old, u_new, seeds=None, stream=None):
@@ -265,9 +292,13 @@ class Context:
         return int(out.value)
 
     # ------------------------------------------------------- workloads
-    def reduce_check(self, r_in, r_out, inp, out, drop=-1, stream=None):
+    def shadow_free(self, region: int):
+        _check("hr_shadow_free", _lib.hr_shadow_free(self._c, region))
+
+    def reduce_check(self, r_in, r_out, inp, out, drop=-1, n=512, threads=256, blocks=1,
+                     stream=None):
         _check("hr_reduce_check", _lib.hr_reduce_check(self._c, r_in, r_out, _dptr(inp),
-                                                       _dptr(out), int(drop),
+                                                       _dptr(out), n, threads, blocks, int(drop),
                                                        _stream_ptr(stream)))
 
     def jacobi_check(self, r_old, r_new, u_old, u_new, seeds=None, stream=None):
@@ -290,3 +321,82 @@ class Context:
             self._c, regs, len(regions), prog.blocks, prog.threads, prog.phases,
             _dptr(prog.scope), _dptr(prog.wmask), _dptr(prog.op_off), prog.op_off.numel(),
             _dptr(prog.ops), prog.n_ops, _dptr(block_map), lds_words, _stream_ptr(stream)))
+
+
+def _races_to_keys(recs):
+    return {(int(r["space"]), int(r["region"]),
+             int(r["block"]) if r["space"] == HR_LDS else 0, int(r["index"])) for r in recs}
+
+
+def job_run(inst: Instance, ring_capacity=0, stream=None):
+    """The serial path for one job (own context and shadow, synchronous).
+    Returns (flagged keys with region ids 0/1, warning bits)."""
+    cfg = _Config(ring_capacity, 0, 0, 0, 0)
+    n = ctypes.c_size_t(0)
+    cap = 4096
+    while True:
+        out = np.zeros(cap, dtype=RACE_DTYPE)
+        st = _lib.hr_job_run(ctypes.byref(inst), ctypes.byref(cfg),
+                             out.ctypes.data_as(ctypes.c_void_p), cap, ctypes.byref(n),
+                             _stream_ptr(stream))
+        if st == HR_E_INVAL and n.value > cap:
+            cap = int(n.value)
+            continue
+        _check("hr_job_run", st)
+        return _races_to_keys(out[:n.value]), st
+
+
+class Batch:
+    """Many checked jobs run to completion in one persistent launch."""
+
+    def __init__(self, ctx: Context, instances):
+        self.ctx = ctx
+        self.n = len(instances)
+        self.inst = (Instance * self.n)(*instances)
+        self._b = ctypes.c_void_p(0)
+        _check("hr_batch_create", _lib.hr_batch_create(ctx.handle, self.inst, self.n,
+                                                       ctypes.byref(self._b)))
+
+    def regions(self, i):
+        return tuple(self.inst[i].region)
+
+    def info(self, variant=0):
+        w, it = ctypes.c_uint32(0), ctypes.c_uint64(0)
+        _check("hr_batch_info", _lib.hr_batch_info(self._b, variant, ctypes.byref(w),
+                                                   ctypes.byref(it)))
+        return int(w.value), int(it.value)
+
+    def run(self, workers=0, order=0, variant=0, spin_limit=0, stream=None):
+        t = _Tuning(workers, order, spin_limit, variant)
+        _check("hr_batch_run", _lib.hr_batch_run(self._b, ctypes.byref(t), _stream_ptr(stream)))
+
+    def split(self, keys):
+        """Per-job flagged keys, with job-local region ids (0 and 1, as the
+        serial path reports them)."""
+        owner = {}
+        for i in range(self.n):
+            for k, r in enumerate(self.inst[i].region):
+                if r != NO_REGION:
+                    owner[r] = (i, k)
+        per = [set() for _ in range(self.n)]
+        for sp, rg, blk, ix in keys:
+            i, k = owner[rg]
+            per[i].add((sp, k if sp == HR_GLOBAL else 0, blk, ix))
+        return per
+
+    def close(self):
+        if self._b:
+            _check("hr_batch_destroy", _lib.hr_batch_destroy(self._b))
+            self._b = ctypes.c_void_p(0)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

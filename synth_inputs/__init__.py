@@ -287,3 +287,87 @@ def random_program(seed: int, launches: int = 2, blocks: int = 2,
                           ops=ops))
     return Program(launches=out, global_words=[global_words] * global_regions,
                    lds_words=lds_words)
+
+
+# --------------------------------------------------------------------------
+# Batched jobs: a manifest of independent checked jobs of mixed patterns.
+# --------------------------------------------------------------------------
+PAT_REDUCE, PAT_JACOBI, PAT_LABELPROP = 0, 1, 2
+
+
+def _log_uniform(rng, lo: float, hi: float) -> float:
+    return float(np.exp(rng.uniform(np.log(lo), np.log(hi))))
+
+
+def batched_manifest(seed: int, n_instances: int = 1000, max_blocks: int = 512,
+                     min_threads: int = 64, max_threads: int = 1024, max_lds_kib: float = 64.0,
+                     seeded_frac: float = 0.1, jacobi_phases: int = 20,
+                     labelprop_phases: int = 10):
+    """Job specs: pattern uniform over (reduce, jacobi, labelprop); blocks
+    log-uniform in [1, max_blocks]; threads log-uniform in [min_threads,
+    max_threads] rounded to a multiple of 64; LDS log-uniform in [1,
+    max_lds_kib] KiB; a seeded_frac share of jobs carries its pattern's
+    seeded race.  Scaled sizes:
+      reduce:    n = largest power of two <= min(LDS words, 2 * threads);
+                 the seeded variant drops one step's barrier;
+      jacobi:    a square grid of side 16 * ceil(sqrt(blocks)), 256-thread
+                 blocks, `jacobi_phases` launches, one seeded block;
+      labelprop: V = blocks * threads vertices, 8 V edges, `labelprop_phases`
+                 launches, 1 % of the edges seeded.
+    """
+    rng = np.random.default_rng(seed)
+    specs = []
+    for i in range(n_instances):
+        pattern = int(rng.integers(0, 3))
+        blocks = max(1, int(round(_log_uniform(rng, 1, max_blocks))))
+        threads = 64 * max(1, int(round(_log_uniform(rng, min_threads, max_threads) / 64)))
+        lds_kib = _log_uniform(rng, 1.0, max_lds_kib)
+        seeded = bool(rng.random() < seeded_frac)
+        iseed = int(rng.integers(0, 2 ** 31 - 1))
+        spec = {"index": i, "pattern": pattern, "blocks": blocks, "threads": threads,
+                "lds_kib": lds_kib, "seeded": seeded, "seed": iseed}
+        if pattern == PAT_REDUCE:
+            words = int(lds_kib * 1024) // 4
+            n = 1 << int(np.floor(np.log2(max(2, min(words, 2 * threads)))))
+            steps = n.bit_length() - 1
+            drop = int(np.random.default_rng(iseed).integers(0, steps)) if seeded else -1
+            spec.update(n=n, drop=drop, phases=1)
+        elif pattern == PAT_JACOBI:
+            g = int(np.ceil(np.sqrt(blocks)))
+            spec.update(ny=16 * g, nx=16 * g, phases=jacobi_phases, threads=256, blocks=g * g)
+        else:
+            v = blocks * threads
+            spec.update(vertices=v, edges=8 * v, phases=labelprop_phases,
+                        p_seed=0.01 if seeded else 0.0)
+        specs.append(spec)
+    return specs
+
+
+def rmat_folded(n_vertices: int, n_edges: int, seed: int):
+    """R-MAT edges at scale ceil(log2 n_vertices), vertex ids folded into
+    [0, n_vertices) modulo n_vertices."""
+    scale = max(1, int(np.ceil(np.log2(n_vertices))))
+    src, dst = rmat_edges(scale, n_edges, seed)
+    return (src % np.uint32(n_vertices)).astype(np.uint32), \
+           (dst % np.uint32(n_vertices)).astype(np.uint32)
+
+
+def instance_inputs(spec):
+    """Host arrays of one job of a batched manifest."""
+    seed = spec["seed"]
+    if spec["pattern"] == PAT_REDUCE:
+        rng = np.random.default_rng(seed)
+        n, b, t = spec["n"], spec["blocks"], spec["threads"]
+        return {"in": rng.integers(0, 1 << 20, size=n * b, dtype=np.int64).astype(np.int32),
+                "out": np.zeros(b * t, dtype=np.int32)}
+    if spec["pattern"] == PAT_JACOBI:
+        ny, nx = spec["ny"], spec["nx"]
+        seeds = jacobi_seeds(ny, nx, seed, count=1) if spec["seeded"] else np.zeros((0, 3), np.int32)
+        return {"u0": jacobi_grid(ny, nx, seed), "u1": np.zeros((ny, nx), np.float32),
+                "seeds": seeds,
+                "seed_tab": jacobi_seed_table(ny, nx, seeds) if len(seeds) else None}
+    v, e = spec["vertices"], spec["edges"]
+    src, dst = rmat_folded(v, e, seed)
+    row_ptr, col = csr_by_source(src, dst, v)
+    mask = seeded_edge_mask(e, spec["p_seed"], seed) if spec["seeded"] else np.zeros(e, np.uint8)
+    return {"label": np.arange(v, dtype=np.int32), "row_ptr": row_ptr, "col": col, "mask": mask}
