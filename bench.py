@@ -256,6 +256,80 @@ def bench_reduce(args, torch, si, hr, stream):
     print(json.dumps(res), flush=True)
 
 
+def bench_batched(args, torch, si, hr, stream):
+    """1000 checked jobs (reduce / jacobi / labelprop, blocks 1-512, threads
+    64-1024, LDS 1-64 KiB, 10 % seeded) in one persistent launch, against the
+    serial path running the same jobs one at a time (context, shadow, one
+    launch per phase, report, free)."""
+    from paper_2401_04701_amd import jobs, tune
+
+    def note(*a):
+        print("[batched]", *a, file=sys.stderr, flush=True)
+    note("building 1000 job inputs")
+    specs = si.batched_manifest(si.master_seed(3))
+    arrays = [si.instance_inputs(s) for s in specs]
+    js = [jobs.Job(s, a) for s, a in zip(specs, arrays)]
+    checks = sum(jobs.check_count_arrays(s, a) for s, a in zip(specs, arrays))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx = hr.Context(ring_capacity=1 << 20)
+    batch = hr.Batch(ctx, [j.inst for j in js])
+    torch.cuda.synchronize()
+    create_ms = (time.perf_counter() - t0) * 1e3
+    note("autotuning")
+    best, trials = tune.autotune(ctx, batch)
+    note("timed batched runs with", best)
+
+    def job(ev):
+        ctx.reset()
+        _launch_events(torch, stream, ev, lambda: batch.run(**best))
+        return ctx.report()
+
+    step_s, launch_ms, (recs, st) = _timed_job(args, torch, stream, job, 1)
+    assert st == 0
+    per_batch = batch.split({(int(r["space"]), int(r["region"]),
+                              int(r["block"]) if r["space"] == hr.HR_LDS else 0, int(r["index"]))
+                             for r in recs})
+    # the serial path over the same jobs (timed once, whole)
+    note("serial path")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    per_serial = [j.serial(ring_capacity=1 << 20) for j in js]
+    serial_s = time.perf_counter() - t0
+    equal = all(st2 == 0 and a == b for (a, st2), b in zip(per_serial, per_batch))
+    batch.close()
+    ctx.close()
+    res = {
+        "metric": "instrumented accesses checked/sec + slowdown vs uninstrumented; p50/p99 check latency",
+        "value": checks / step_s, "unit": "checks/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": step_s * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "batched_1000_mixed_jobs_one_persistent_launch", "jobs": len(js),
+                   "checks_per_step": int(checks), "work_items": batch_items(specs),
+                   "parallelism": "single GPU"},
+        "jobs_per_s": len(js) / step_s,
+        "serial_jobs_per_s": len(js) / serial_s,
+        "serial_checks_per_s": checks / serial_s,
+        "batched_vs_serial": serial_s / step_s,
+        "equal_results": bool(equal),
+        "flagged": int(len(recs)),
+        "tuning": best, "tuning_trials_ms": trials, "batch_create_ms": create_ms,
+        "p50_launch_ms": pct(launch_ms, 50), "p99_launch_ms": pct(launch_ms, 99)}
+    print(json.dumps(res), flush=True)
+
+
+def batch_items(specs):
+    n = 0
+    for s in specs:
+        if s["pattern"] == 1:
+            n += (s["ny"] // 16) * (s["nx"] // 16) * s["phases"]
+        elif s["pattern"] == 2:
+            n += -(-s["vertices"] // s["threads"]) * s["phases"]
+        else:
+            n += s["blocks"]
+    return n
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -265,9 +339,11 @@ def main():
     ap.add_argument("--no-peaks", action="store_true")
     ap.add_argument("--verify-count", action="store_true",
                     help="first run one job with the device access counter (untimed)")
-    ap.add_argument("--workload", default="jacobi", choices=["jacobi", "labelprop", "reduce"],
+    ap.add_argument("--workload", default="jacobi",
+                    choices=["jacobi", "labelprop", "reduce", "batched"],
                     help="jacobi: the headline 4096^2 stencil job; labelprop: R-MAT scale-22 "
-                         "label propagation job; reduce: one-block LDS reduction latency")
+                         "label propagation job; reduce: one-block LDS reduction latency; "
+                         "batched: 1000 mixed jobs in one persistent launch vs one at a time")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the checker runs each job on a single device "
@@ -285,6 +361,8 @@ def main():
         return bench_labelprop(args, torch, si, hr, stream)
     if args.workload == "reduce":
         return bench_reduce(args, torch, si, hr, stream)
+    if args.workload == "batched":
+        return bench_batched(args, torch, si, hr, stream)
 
     seeds = si.jacobi_seeds(NY, NX, si.master_seed(1))
     tab = torch.from_numpy(si.jacobi_seed_table(NY, NX, seeds)).cuda()
