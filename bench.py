@@ -318,6 +318,77 @@ def bench_batched(args, torch, si, hr, stream):
     print(json.dumps(res), flush=True)
 
 
+def bench_serving(args, torch, si, hr, stream):
+    """Poisson streams of check jobs (95 % the batched mix, 5 % full 4096^2
+    stencil jobs, 20 launches, 0.1 % of blocks seeded) at each arrival rate,
+    served with continuous batching against a 64 GiB shadow budget, and the
+    serial plain path (context, shadow, launches, report, free; one job at a
+    time) replaying the same arrival trace.  Latency = finish - arrival."""
+    from paper_2401_04701_amd import jobs
+
+    def note(*a):
+        print("[serving]", *a, file=sys.stderr, flush=True)
+    rates = [float(r) for r in args.rates.split(",")]
+    specs = si.serving_stream(si.master_seed(4), n_jobs=args.serve_jobs)
+    note("building", len(specs), "job inputs")
+    js, checks = [], 0
+    for i, spec in enumerate(specs):
+        a = si.instance_inputs(spec)
+        checks += jobs.check_count_arrays(spec, a)
+        js.append(jobs.Job(spec, a))
+        del a
+        if (i + 1) % 250 == 0:
+            note("  built", i + 1)
+    torch.cuda.synchronize()
+    insts = [j.inst for j in js]
+    ctx = hr.Context(ring_capacity=1 << 20)
+    note("warm-up")
+    hr.serve(ctx, insts[:64], np.zeros(64), stream=stream)
+    hr.serve(ctx, insts[:16], np.zeros(16), serial=True, stream=stream)
+    out, equal = [], True
+    for rate in rates:
+        arr = si.poisson_arrivals(si.master_seed(4) + int(rate), len(js), rate)
+        row, sets = {"rate_per_s": rate}, {}
+        for mode in ("served", "serial"):
+            note("rate", rate, mode)
+            sets[mode], times = hr.serve(ctx, insts, arr, serial=(mode == "serial"),
+                                         stream=stream)
+            fin = np.array([t.finish_s for t in times])
+            lat = fin - arr
+            span = float(fin.max())
+            row[mode] = {"jobs_per_s": len(js) / span, "checks_per_s": checks / span,
+                         "makespan_s": span, "p50_ms": pct(lat, 50) * 1e3,
+                         "p99_ms": pct(lat, 99) * 1e3,
+                         "clean_status": all(t.status == 0 for t in times),
+                         "flagged": int(sum(t.flagged for t in times))}
+            note("  %.0f jobs/s, p50 %.2f ms, p99 %.2f ms"
+                 % (row[mode]["jobs_per_s"], row[mode]["p50_ms"], row[mode]["p99_ms"]))
+        # every job's flagged set served in the mix equals its set run alone
+        row["equal_results"] = (sets["served"] == sets["serial"]
+                                and row["served"]["clean_status"]
+                                and row["serial"]["clean_status"])
+        equal &= row["equal_results"]
+        row["served_vs_serial_jobs_per_s"] = (row["served"]["jobs_per_s"]
+                                              / row["serial"]["jobs_per_s"])
+        out.append(row)
+    ctx.close()
+    top = out[-1]
+    res = {
+        "metric": "instrumented accesses checked/sec + slowdown vs uninstrumented; p50/p99 check latency",
+        "value": top["served"]["jobs_per_s"], "unit": "jobs/s", "n_gpus": 1,
+        "steps": len(rates), "warmup": 1, "ms_per_step": top["served"]["makespan_s"] * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": "serving_poisson_stream_%d_jobs_5pct_4096sq_stencil" % len(js),
+                   "jobs": len(js), "full_size_jobs": sum(bool(s.get("big")) for s in specs),
+                   "checks_per_stream": int(checks), "shadow_budget_bytes": 64 << 30,
+                   "parallelism": "single GPU"},
+        "p50_ms": top["served"]["p50_ms"], "p99_ms": top["served"]["p99_ms"],
+        "served_vs_serial": top["served_vs_serial_jobs_per_s"],
+        "equal_results": bool(equal), "rates": out}
+    print(json.dumps(res), flush=True)
+
+
 def batch_items(specs):
     n = 0
     for s in specs:
@@ -340,10 +411,14 @@ def main():
     ap.add_argument("--verify-count", action="store_true",
                     help="first run one job with the device access counter (untimed)")
     ap.add_argument("--workload", default="jacobi",
-                    choices=["jacobi", "labelprop", "reduce", "batched"],
+                    choices=["jacobi", "labelprop", "reduce", "batched", "serving"],
                     help="jacobi: the headline 4096^2 stencil job; labelprop: R-MAT scale-22 "
                          "label propagation job; reduce: one-block LDS reduction latency; "
-                         "batched: 1000 mixed jobs in one persistent launch vs one at a time")
+                         "batched: 1000 mixed jobs in one persistent launch vs one at a time; "
+                         "serving: Poisson job streams, continuous batching vs one at a time")
+    ap.add_argument("--rates", default="100,250,500,1000,2500,5000",
+                    help="serving: arrival rates in jobs/s")
+    ap.add_argument("--serve-jobs", type=int, default=2000, help="serving: jobs per stream")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the checker runs each job on a single device "
@@ -363,6 +438,8 @@ def main():
         return bench_reduce(args, torch, si, hr, stream)
     if args.workload == "batched":
         return bench_batched(args, torch, si, hr, stream)
+    if args.workload == "serving":
+        return bench_serving(args, torch, si, hr, stream)
 
     seeds = si.jacobi_seeds(NY, NX, si.master_seed(1))
     tab = torch.from_numpy(si.jacobi_seed_table(NY, NX, seeds)).cuda()

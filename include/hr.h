@@ -241,7 +241,7 @@ hr_status hr_program_check(hr_ctx c, const uint32_t* regions_host, uint32_t n_re
  * LDS race records of a batched job carry region[0] as their array id. */
 typedef struct {
     uint32_t pattern;
-    uint32_t blocks, threads, phases;
+    uint32_t blocks, threads, phases;   /* phases: 1..512 */
     uint32_t n, ny;
     int32_t drop;
     uint32_t region[2];
@@ -288,6 +288,51 @@ hr_status hr_batch_destroy(hr_batch b);
  * everything.  Synchronous. */
 hr_status hr_job_run(const hr_instance* inst, const hr_config* cfg, hr_race* out, size_t cap,
                      size_t* n_out, void* stream);
+
+/* ----------------------------------------------------------------------
+ * Serving: a stream of jobs checked with continuous batching.
+ *
+ * A job's launches run one after another (Sec. II-B: a kernel boundary
+ * orders everything before it), so a device iteration may run the next
+ * phase of every resident job side by side.  Jobs are admitted in arrival
+ * order between iterations, while a job slot and shadow memory under the
+ * budget are free; a job's shadow words stay resident until its last phase
+ * has been reported.
+ * ---------------------------------------------------------------------- */
+
+typedef struct {
+    double arrival_s;   /* in: arrival time, seconds after the call starts;
+                           non-decreasing over the job list */
+    double admit_s;     /* out: when the job was admitted (its shadow placed) */
+    double finish_s;    /* out: when its last phase was reported */
+    uint32_t flagged;   /* out: distinct flagged locations of the job */
+    int32_t status;     /* out: HR_W_* bits of the iterations the job ran in
+                           (serial path: the job's hr_job_run status) */
+} hr_serve_job;
+
+typedef struct {
+    uint64_t shadow_budget;  /* bytes of shadow resident at once; 0: 64 GiB */
+    uint32_t max_slots;      /* jobs resident at once, < 2^20; 0: 1024 */
+    uint32_t workers;        /* worker blocks per iteration; 0: all that fit */
+    uint32_t serial;         /* nonzero: replay the arrivals one job at a time
+                                through hr_job_run (the plain path) */
+    uint32_t pad;
+} hr_serve_config;
+
+/* Check n_jobs jobs (hr_instance as for hr_batch_create; region[] unused)
+ * arriving at times[j].arrival_s, on the context's device and `stream`, and
+ * wait for all of them.  The call paces itself by the arrival times (it
+ * sleeps while nothing is resident).  Race records of job j carry region id
+ * 2j (its first buffer, and its LDS arrays) or 2j+1 (its second buffer); out
+ * receives every job's deduplicated records, sorted by (region, space,
+ * block if LDS, index); *n_out is their number.  The context's ring and
+ * counters are reused by every iteration; its regions are not touched.
+ * Errors: HR_E_INVAL (a job's shape, unsorted arrivals, cap too small: then
+ * *n_out holds the number needed), HR_E_NOMEM (a job larger than the
+ * budget, or the device allocation failed), HR_E_HIP. */
+hr_status hr_serve(hr_ctx c, const hr_instance* jobs, hr_serve_job* times, uint32_t n_jobs,
+                   const hr_serve_config* cfg, hr_race* out, size_t cap, size_t* n_out,
+                   void* stream);
 
 /* ----------------------------------------------------------------------
  * Device microbenchmarks: the roofline denominators of the checking path

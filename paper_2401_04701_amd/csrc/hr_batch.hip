@@ -21,75 +21,11 @@
 #include "hr.h"
 #include "hr_bodies.h"
 #include "hr_device.h"
+#include "hr_exec.h"
 #include "hr_internal.h"
 
 namespace {
 
-struct hr_inst_dev {
-    uint32_t pattern, blocks, threads, phases;
-    uint32_t n, ny, nbx;
-    int32_t drop;
-    uint32_t done_off, lds_id;
-    hr_gref g0, g1;
-    const void* p0;
-    void* p1;
-    const void* p2;
-    const void* p3;
-};
-
-constexpr uint32_t ITEM_BLOCK_BITS = 22;
-constexpr uint32_t ITEM_PHASE_BITS = 10;
-
-// Values the whole worker block agrees on, moved into scalar registers.  The
-// bodies' block barriers sit under branches on these values (pattern, sizes,
-// dropped step); the compiler must see those branches as uniform, or its
-// control-flow structurizer may place a barrier under a divergent mask.
-__device__ __forceinline__ uint32_t uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
-__device__ __forceinline__ uint64_t uni64(uint64_t x)
-{
-    return ((uint64_t)uni((uint32_t)(x >> 32)) << 32) | uni((uint32_t)x);
-}
-template <class T>
-__device__ __forceinline__ T* unip(T* p)
-{
-    return (T*)uni64((uint64_t)p);
-}
-
-__device__ __forceinline__ hr_gref uni_gref(const hr_gref& g)
-{
-    return hr_gref{unip(g.shadow), uni64(g.n), uni(g.id)};
-}
-
-__device__ __forceinline__ void run_item(const hr_env& e, const hr_inst_dev& I, uint32_t phase,
-                                         uint32_t lb, uint32_t* smem)
-{
-    switch (I.pattern) {
-    case HR_PAT_REDUCE:
-        reduce_body<true>(e, I.g0, I.g1, (const int32_t*)I.p0, (int32_t*)I.p1, I.n, I.threads, lb,
-                          I.drop, (int32_t*)smem, smem + I.n, I.lds_id);
-        break;
-    case HR_PAT_JACOBI: {
-        const bool odd = phase & 1u;
-        const float* uo = (const float*)(odd ? I.p1 : I.p0);
-        float* un = (float*)(odd ? I.p0 : I.p1);
-        jacobi_body<true>(e, odd ? I.g1 : I.g0, odd ? I.g0 : I.g1, uo, un, I.ny, I.n, I.nbx,
-                          (const int32_t*)I.p2, lb, (float*)smem, smem + JACOBI_TILE_WORDS,
-                          I.lds_id);
-        break;
-    }
-    default: {
-        const hr_gref none{nullptr, 0, 0};
-        labelprop_body<true>(e, I.g0, none, none, (int32_t*)I.p0, (const int32_t*)I.p1,
-                             (const int32_t*)I.p2, (const uint8_t*)I.p3, I.n, I.threads, lb);
-        break;
-    }
-    }
-}
-
-// Worker loop.  MIN_WAVES is the occupancy target per SIMD: 4 gives one
-// 1024-thread worker per compute unit with up to 128 registers per lane, 8
-// gives two workers per compute unit within 64 registers (some values then
-// live in scratch).  The autotuner picks between them by measurement.
 __device__ __forceinline__ uint64_t claim(uint32_t* cursor, const uint64_t* items, uint32_t n_items)
 {
     const uint32_t i = __hip_atomic_fetch_add(cursor, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -121,24 +57,7 @@ __device__ __forceinline__ void batch_loop(const hr_env& base, const hr_inst_dev
         const uint32_t ii = (uint32_t)(it >> 32);
         const uint32_t phase = (uint32_t)(it >> ITEM_BLOCK_BITS) & ((1u << ITEM_PHASE_BITS) - 1);
         const uint32_t lb = (uint32_t)it & ((1u << ITEM_BLOCK_BITS) - 1);
-        const hr_inst_dev& G = insts[ii];
-        hr_inst_dev I;
-        I.pattern = uni(G.pattern);
-        I.blocks = uni(G.blocks);
-        I.threads = uni(G.threads);
-        I.phases = uni(G.phases);
-        I.n = uni(G.n);
-        I.ny = uni(G.ny);
-        I.nbx = uni(G.nbx);
-        I.drop = (int32_t)uni((uint32_t)G.drop);
-        I.done_off = uni(G.done_off);
-        I.lds_id = uni(G.lds_id);
-        I.g0 = uni_gref(G.g0);
-        I.g1 = uni_gref(G.g1);
-        I.p0 = unip(G.p0);
-        I.p1 = unip(G.p1);
-        I.p2 = unip(G.p2);
-        I.p3 = unip(G.p3);
+        const hr_inst_dev I = load_uniform(insts[ii]);
         if (threadIdx.x == 0) {
             uint32_t go = 1;
             if (phase > 0) {
@@ -190,10 +109,12 @@ __global__ __launch_bounds__(1024, 8) void k_batch_dense(hr_env base, const hr_i
     batch_loop<8>(base, insts, items, n_items, cursor, done, spin_limit);
 }
 
-// Shape checks and derived sizes of one instance; fills blocks and elems.
-bool instance_shape(hr_instance& in, size_t elems[2], size_t* lds_bytes)
+}  // namespace
+
+bool hr_instance_shape(hr_instance& in, size_t elems[2], size_t* lds_bytes)
 {
-    if (in.phases == 0 || in.phases >= (1u << ITEM_PHASE_BITS)) return false;
+    // a job's phases are its launch epochs, which must stay distinct
+    if (in.phases == 0 || in.phases > (1u << hr::g::LAUNCH_BITS)) return false;
     switch (in.pattern) {
     case HR_PAT_REDUCE: {
         const uint32_t n = in.n, T = in.threads;
@@ -231,7 +152,29 @@ bool instance_shape(hr_instance& in, size_t elems[2], size_t* lds_bytes)
     return in.blocks > 0 && in.blocks < (1u << ITEM_BLOCK_BITS);
 }
 
-}  // namespace
+
+hr_inst_dev hr_make_inst_dev(const hr_instance& in, const size_t elems[2], uint64_t* sh0,
+                             uint64_t* sh1, uint32_t r0, uint32_t r1, uint32_t done_off)
+{
+    hr_inst_dev d{};
+    d.pattern = in.pattern;
+    d.blocks = in.blocks;
+    d.threads = in.threads;
+    d.phases = in.phases;
+    d.n = in.n;
+    d.ny = in.ny;
+    d.nbx = (in.n + 15) / 16;
+    d.drop = in.drop;
+    d.done_off = done_off;
+    d.lds_id = r0;
+    d.g0 = hr_gref{sh0, sh0 ? elems[0] : 0, r0};
+    d.g1 = hr_gref{sh1, sh1 ? elems[1] : 0, r1};
+    d.p0 = in.data[0];
+    d.p1 = const_cast<void*>(in.data[1]);
+    d.p2 = in.data[2];
+    d.p3 = in.data[3];
+    return d;
+}
 
 struct hr_batch_s {
     hr_ctx ctx;
@@ -269,7 +212,7 @@ extern "C" hr_status hr_batch_create(hr_ctx c, hr_instance* inst, uint32_t n_ins
     size_t total = 0, lds = 0;
     for (uint32_t i = 0; i < n_inst; ++i) {
         size_t lb = 0;
-        if (!instance_shape(inst[i], &el[2 * i], &lb)) return HR_E_INVAL;
+        if (!hr_instance_shape(inst[i], &el[2 * i], &lb)) return HR_E_INVAL;
         total += el[2 * i] + el[2 * i + 1];
         lds = std::max(lds, lb);
     }
@@ -292,33 +235,16 @@ extern "C" hr_status hr_batch_create(hr_ctx c, hr_instance* inst, uint32_t n_ins
     uint32_t done_off = 0;
     for (uint32_t i = 0; i < n_inst; ++i) {
         hr_instance& in = inst[i];
-        hr_inst_dev& d = hd[i];
         in.region[0] = in.region[1] = UINT32_MAX;
+        uint64_t* sh[2] = {nullptr, nullptr};
         for (int k = 0; k < 2; ++k) {
             if (!el[2 * i + k]) continue;
-            in.region[k] = hr_new_region(c, in.data[k], el[2 * i + k], base + off, arena);
+            sh[k] = base + off;
+            in.region[k] = hr_new_region(c, in.data[k], el[2 * i + k], sh[k], arena);
             off += el[2 * i + k];
         }
-        d.pattern = in.pattern;
-        d.blocks = in.blocks;
-        d.threads = in.threads;
-        d.phases = in.phases;
-        d.n = in.n;
-        d.ny = in.ny;
-        d.nbx = (in.n + 15) / 16;
-        d.drop = in.drop;
-        d.done_off = done_off;
-        d.lds_id = in.region[0];
-        for (int k = 0; k < 2; ++k) {
-            hr_gref& g = k ? d.g1 : d.g0;
-            g.id = in.region[k];
-            g.shadow = in.region[k] != UINT32_MAX ? c->reg[in.region[k]].shadow : nullptr;
-            g.n = in.region[k] != UINT32_MAX ? c->reg[in.region[k]].elems : 0;
-        }
-        d.p0 = in.data[0];
-        d.p1 = const_cast<void*>(in.data[1]);
-        d.p2 = in.data[2];
-        d.p3 = in.data[3];
+        hd[i] = hr_make_inst_dev(in, &el[2 * i], sh[0], sh[1], in.region[0], in.region[1],
+                                 done_off);
         done_off += in.phases;
     }
     b->n_done = done_off;
@@ -422,7 +348,7 @@ extern "C" hr_status hr_job_run(const hr_instance* inst, const hr_config* cfg, h
     if (!inst || !n_out) return HR_E_INVAL;
     hr_instance in = *inst;
     size_t el[2] = {0, 0}, lds = 0;
-    if (!instance_shape(in, el, &lds)) return HR_E_INVAL;
+    if (!hr_instance_shape(in, el, &lds)) return HR_E_INVAL;
     hr_ctx c = nullptr;
     hr_status st = hr_ctx_create(&c, cfg, stream);
     if (st != HR_OK) return st;

@@ -1,0 +1,107 @@
+// Pieces shared by the batched executor and the serving executor: the
+// device job descriptor, block-uniform loads, and the dispatch of one work
+// item (one logical block of one phase of one job) to its workload body.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hr.h"
+#include "hr_bodies.h"
+#include "hr_device.h"
+
+struct hr_inst_dev {
+    uint32_t pattern, blocks, threads, phases;
+    uint32_t n, ny, nbx;
+    int32_t drop;
+    uint32_t done_off, lds_id;
+    hr_gref g0, g1;
+    const void* p0;
+    void* p1;
+    const void* p2;
+    const void* p3;
+};
+
+constexpr uint32_t ITEM_BLOCK_BITS = 22;
+constexpr uint32_t ITEM_PHASE_BITS = 10;
+
+// Values the whole worker block agrees on, moved into scalar registers.  The
+// bodies' block barriers sit under branches on these values (pattern, sizes,
+// dropped step); the compiler must see those branches as uniform, or its
+// control-flow structurizer may place a barrier under a divergent mask.
+__device__ __forceinline__ uint32_t uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ uint64_t uni64(uint64_t x)
+{
+    return ((uint64_t)uni((uint32_t)(x >> 32)) << 32) | uni((uint32_t)x);
+}
+template <class T>
+__device__ __forceinline__ T* unip(T* p)
+{
+    return (T*)uni64((uint64_t)p);
+}
+
+__device__ __forceinline__ hr_gref uni_gref(const hr_gref& g)
+{
+    return hr_gref{unip(g.shadow), uni64(g.n), uni(g.id)};
+}
+
+__device__ __forceinline__ void run_item(const hr_env& e, const hr_inst_dev& I, uint32_t phase,
+                                         uint32_t lb, uint32_t* smem)
+{
+    switch (I.pattern) {
+    case HR_PAT_REDUCE:
+        reduce_body<true>(e, I.g0, I.g1, (const int32_t*)I.p0, (int32_t*)I.p1, I.n, I.threads, lb,
+                          I.drop, (int32_t*)smem, smem + I.n, I.lds_id);
+        break;
+    case HR_PAT_JACOBI: {
+        const bool odd = phase & 1u;
+        const float* uo = (const float*)(odd ? I.p1 : I.p0);
+        float* un = (float*)(odd ? I.p0 : I.p1);
+        jacobi_body<true>(e, odd ? I.g1 : I.g0, odd ? I.g0 : I.g1, uo, un, I.ny, I.n, I.nbx,
+                          (const int32_t*)I.p2, lb, (float*)smem, smem + JACOBI_TILE_WORDS,
+                          I.lds_id);
+        break;
+    }
+    default: {
+        const hr_gref none{nullptr, 0, 0};
+        labelprop_body<true>(e, I.g0, none, none, (int32_t*)I.p0, (const int32_t*)I.p1,
+                             (const int32_t*)I.p2, (const uint8_t*)I.p3, I.n, I.threads, lb);
+        break;
+    }
+    }
+}
+
+// Worker loop.  MIN_WAVES is the occupancy target per SIMD: 4 gives one
+// 1024-thread worker per compute unit with up to 128 registers per lane, 8
+// gives two workers per compute unit within 64 registers (some values then
+// live in scratch).  The autotuner picks between them by measurement.
+// The descriptor as every thread of the worker block sees it, in scalar
+// registers.
+__device__ __forceinline__ hr_inst_dev load_uniform(const hr_inst_dev& G)
+{
+    hr_inst_dev I;
+    I.pattern = uni(G.pattern);
+    I.blocks = uni(G.blocks);
+    I.threads = uni(G.threads);
+    I.phases = uni(G.phases);
+    I.n = uni(G.n);
+    I.ny = uni(G.ny);
+    I.nbx = uni(G.nbx);
+    I.drop = (int32_t)uni((uint32_t)G.drop);
+    I.done_off = uni(G.done_off);
+    I.lds_id = uni(G.lds_id);
+    I.g0 = uni_gref(G.g0);
+    I.g1 = uni_gref(G.g1);
+    I.p0 = unip(G.p0);
+    I.p1 = unip(G.p1);
+    I.p2 = unip(G.p2);
+    I.p3 = unip(G.p3);
+    return I;
+}
+
+// Shape checks and derived sizes of one job; fills blocks (and threads for
+// jacobi), the element counts of its two monitored buffers and its LDS need.
+bool hr_instance_shape(hr_instance& in, size_t elems[2], size_t* lds_bytes);
+
+// Descriptor of a job whose shadow words are at sh0 / sh1; report ids r0/r1.
+hr_inst_dev hr_make_inst_dev(const hr_instance& in, const size_t elems[2], uint64_t* sh0,
+                             uint64_t* sh1, uint32_t r0, uint32_t r1, uint32_t done_off);

@@ -1,0 +1,375 @@
+// Serving: a stream of check jobs with continuous batching at the
+// granularity of one phase (one launch of a job's kernel).
+//
+// The host loop admits jobs that have arrived, in arrival order, while a
+// job slot and shadow memory under the budget are free; every iteration is
+// one launch that advances each resident job by one phase, so jobs that
+// arrive while others run join at the next iteration and their work shares
+// the device with everyone else's.  The launch boundary of every iteration
+// is the launch boundary of each job's phase; a job's shadow stays resident
+// across its phases (its launch epoch is its phase) and is released when its
+// last phase is reported.  No kernel waits for another block: items of one
+// iteration are independent.
+//
+// The serial path replays the same arrivals one job at a time through
+// hr_job_run (own context, shadow allocation, one launch per phase, report,
+// free).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <map>
+#include <thread>
+#include <vector>
+
+#include "hr.h"
+#include "hr_exec.h"
+#include "hr_internal.h"
+
+namespace {
+
+__global__ __launch_bounds__(1024) void k_iter(hr_env base, const hr_inst_dev* __restrict__ slots,
+                                               const uint32_t* __restrict__ act,
+                                               const uint64_t* __restrict__ prefix, uint32_t n_act,
+                                               uint32_t total, uint32_t* cursor)
+{
+    extern __shared__ uint32_t smem[];
+    __shared__ uint32_t s_i;
+    if (threadIdx.x == 0)
+        s_i = __hip_atomic_fetch_add(cursor, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    for (;;) {
+        const uint32_t i = uni(s_i);
+        if (i >= total) break;                         // iteration drained: every wave leaves
+        // the job owning item i: the largest k with prefix[k] <= i
+        uint32_t lo = 0, hi = n_act;
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (uni64(prefix[mid]) <= i) lo = mid;
+            else hi = mid;
+        }
+        const uint32_t a = uni(act[lo]);
+        const uint32_t slot = a & 0xFFFFFu, phase = a >> 20;
+        const uint32_t lb = i - (uint32_t)uni64(prefix[lo]);
+        const hr_inst_dev I = load_uniform(slots[slot]);
+        hr_env e = base;
+        e.launch = phase & ((1u << hr::g::LAUNCH_BITS) - 1);
+        e.launch_seq = phase;
+        run_item(e, I, phase, lb, smem);
+        __syncthreads();                               // every hook of the item is done
+        if (threadIdx.x == 0)
+            s_i = __hip_atomic_fetch_add(cursor, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+    }
+}
+
+// First-fit allocator of 256-byte granules inside one device arena.
+struct arena_alloc {
+    std::map<uint64_t, uint64_t> free_;   // offset -> length, in granules
+    explicit arena_alloc(uint64_t granules) { free_[0] = granules; }
+    bool alloc(uint64_t n, uint64_t* off)
+    {
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < n) continue;
+            *off = it->first;
+            const uint64_t rest = it->second - n;
+            const uint64_t at = it->first + n;
+            free_.erase(it);
+            if (rest) free_[at] = rest;
+            return true;
+        }
+        return false;
+    }
+    void release(uint64_t off, uint64_t n)
+    {
+        auto it = free_.emplace(off, n).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+};
+
+constexpr uint64_t GRANULE_WORDS = 32;   // 256 bytes of 8-byte shadow words
+
+struct job_state {
+    hr_instance in;
+    size_t elems[2] = {0, 0};
+    uint64_t off = 0, granules = 0;   // arena placement
+    uint32_t slot = 0, phase = 0;
+    int32_t status = 0;
+};
+
+using clock_t_ = std::chrono::steady_clock;
+
+double seconds_since(clock_t_::time_point t0)
+{
+    return std::chrono::duration<double>(clock_t_::now() - t0).count();
+}
+
+void wait_until(clock_t_::time_point t0, double at)
+{
+    for (;;) {
+        const double left = at - seconds_since(t0);
+        if (left <= 0) return;
+        if (left > 2e-3) std::this_thread::sleep_for(std::chrono::microseconds((int64_t)(left * 5e5)));
+        else std::this_thread::yield();
+    }
+}
+
+hr_race tag_region(hr_race r, uint32_t job)
+{
+    r.region = 2u * job + (r.space == HR_LDS ? 0u : std::min(r.region, 1u));
+    return r;
+}
+
+hr_status serve_serial(hr_ctx c, const hr_instance* jobs, hr_serve_job* times, uint32_t n,
+                       std::vector<hr_race>& all, void* stream)
+{
+    const auto t0 = clock_t_::now();
+    std::vector<hr_race> buf(4096);
+    for (uint32_t j = 0; j < n; ++j) {
+        wait_until(t0, times[j].arrival_s);
+        times[j].admit_s = seconds_since(t0);
+        size_t got = 0;
+        hr_status st;
+        for (;;) {
+            st = hr_job_run(&jobs[j], &c->cfg, buf.data(), buf.size(), &got, stream);
+            if (st == HR_E_INVAL && got > buf.size()) {
+                buf.resize(got);
+                continue;
+            }
+            break;
+        }
+        times[j].finish_s = seconds_since(t0);
+        times[j].status = st;
+        if (st < 0) return st;
+        for (size_t i = 0; i < got; ++i) all.push_back(tag_region(buf[i], j));
+    }
+    return HR_OK;
+}
+
+struct serve_buffers {
+    uint64_t* arena = nullptr;
+    hr_inst_dev* slots = nullptr;
+    uint32_t* act = nullptr;
+    uint64_t* prefix = nullptr;
+    uint32_t* cursor = nullptr;
+    uint32_t* h_act = nullptr;      // pinned staging
+    uint64_t* h_prefix = nullptr;
+    hr_inst_dev* h_desc = nullptr;
+    ~serve_buffers()
+    {
+        if (arena) (void)hipFree(arena);
+        if (slots) (void)hipFree(slots);
+        if (act) (void)hipFree(act);
+        if (prefix) (void)hipFree(prefix);
+        if (cursor) (void)hipFree(cursor);
+        if (h_act) (void)hipHostFree(h_act);
+        if (h_prefix) (void)hipHostFree(h_prefix);
+        if (h_desc) (void)hipHostFree(h_desc);
+    }
+};
+
+hr_status serve_continuous(hr_ctx c, const hr_instance* jobs, hr_serve_job* times, uint32_t n,
+                           const hr_serve_config& cfg, std::vector<hr_race>& all, void* stream)
+{
+    hipStream_t s = hr_stream(c, stream);
+    std::vector<job_state> js(n);
+    size_t lds = 0;
+    const uint64_t budget_granules = cfg.shadow_budget / (GRANULE_WORDS * 8);
+    uint64_t need = 0;
+    for (uint32_t j = 0; j < n; ++j) {
+        js[j].in = jobs[j];
+        size_t l = 0;
+        if (!hr_instance_shape(js[j].in, js[j].elems, &l)) return HR_E_INVAL;
+        lds = std::max(lds, l);
+        const uint64_t words = js[j].elems[0] + js[j].elems[1];
+        js[j].granules = (words + GRANULE_WORDS - 1) / GRANULE_WORDS + 1;
+        if (js[j].granules > budget_granules) return HR_E_NOMEM;   // could never be admitted
+        need += js[j].granules;
+    }
+    // the arena never needs more than every job at once
+    const uint64_t arena_granules = std::min(budget_granules, need);
+    const uint32_t max_slots = cfg.max_slots;
+    serve_buffers b;
+    if (hipMalloc(&b.arena, arena_granules * GRANULE_WORDS * 8) != hipSuccess ||
+        hipMalloc(&b.slots, sizeof(hr_inst_dev) * max_slots) != hipSuccess ||
+        hipMalloc(&b.act, sizeof(uint32_t) * max_slots) != hipSuccess ||
+        hipMalloc(&b.prefix, sizeof(uint64_t) * (max_slots + 1)) != hipSuccess ||
+        hipMalloc(&b.cursor, sizeof(uint32_t)) != hipSuccess ||
+        hipHostMalloc(&b.h_act, sizeof(uint32_t) * max_slots, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(&b.h_prefix, sizeof(uint64_t) * (max_slots + 1), hipHostMallocDefault) !=
+            hipSuccess ||
+        hipHostMalloc(&b.h_desc, sizeof(hr_inst_dev) * max_slots, hipHostMallocDefault) !=
+            hipSuccess)
+        return HR_E_NOMEM;
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_iter, 1024, lds) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) !=
+            hipSuccess ||
+        per_cu <= 0 || cus <= 0)
+        return HR_E_HIP;
+    const uint32_t max_workers = (uint32_t)(per_cu * cus);
+    const uint32_t workers = cfg.workers ? std::min(cfg.workers, max_workers) : max_workers;
+    arena_alloc arena(arena_granules);
+    std::vector<uint32_t> free_slots;
+    for (uint32_t k = max_slots; k-- > 0;) free_slots.push_back(k);
+    std::vector<uint32_t> active;
+    std::vector<hr_race> ring(c->cfg.ring_capacity);
+    const hr_env env_base = hr_make_env(c);
+    uint32_t next = 0;
+    const auto t0 = clock_t_::now();
+    for (;;) {
+        // admit arrived jobs in order while a slot and shadow memory are free
+        const double now = seconds_since(t0);
+        while (next < n && times[next].arrival_s <= now && !free_slots.empty()) {
+            job_state& st = js[next];
+            uint64_t off = 0;
+            if (!arena.alloc(st.granules, &off)) break;
+            st.off = off;
+            st.slot = free_slots.back();
+            free_slots.pop_back();
+            uint64_t* sh0 = b.arena + off * GRANULE_WORDS;
+            uint64_t* sh1 = st.elems[1] ? sh0 + st.elems[0] : nullptr;
+            if (hr_fill64(sh0, st.elems[0] + st.elems[1], s) != hipSuccess) return HR_E_HIP;
+            b.h_desc[st.slot] = hr_make_inst_dev(st.in, st.elems, sh0, sh1, 2 * next, 2 * next + 1, 0);
+            if (hipMemcpyAsync(b.slots + st.slot, b.h_desc + st.slot, sizeof(hr_inst_dev),
+                               hipMemcpyHostToDevice, s) != hipSuccess)
+                return HR_E_HIP;
+            times[next].admit_s = now;
+            active.push_back(next);
+            ++next;
+        }
+        if (active.empty()) {
+            if (next >= n) break;
+            wait_until(t0, times[next].arrival_s);
+            continue;
+        }
+        // one iteration: the next phase of every resident job
+        uint64_t total = 0;
+        for (size_t k = 0; k < active.size(); ++k) {
+            const job_state& st = js[active[k]];
+            b.h_prefix[k] = total;
+            b.h_act[k] = st.slot | (st.phase << 20);
+            total += st.in.blocks;
+        }
+        b.h_prefix[active.size()] = total;
+        if (total >= (1ull << 32)) return HR_E_INVAL;
+        if (hipMemcpyAsync(b.act, b.h_act, sizeof(uint32_t) * active.size(),
+                           hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipMemcpyAsync(b.prefix, b.h_prefix, sizeof(uint64_t) * (active.size() + 1),
+                           hipMemcpyHostToDevice, s) != hipSuccess ||
+            hr_fill32(b.cursor, 1, s) != hipSuccess || hr_fill32(c->ctr, HR_CTR_WORDS, s) != hipSuccess)
+            return HR_E_HIP;
+        HR_LAUNCH(k_iter, dim3(workers), dim3(1024), lds, s, env_base, b.slots, b.act, b.prefix,
+                  (uint32_t)active.size(), (uint32_t)total, b.cursor);
+        uint32_t ctr[HR_CTR_WORDS];
+        if (hipMemcpyAsync(ctr, c->ctr, sizeof(ctr), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return HR_E_HIP;
+        const uint32_t got = std::min(ctr[HR_CTR_HEAD], c->cfg.ring_capacity);
+        if (got && hipMemcpy(ring.data(), c->ring, sizeof(hr_race_rec) * got,
+                             hipMemcpyDeviceToHost) != hipSuccess)
+            return HR_E_HIP;
+        // the descriptors carry 2*job (+1) as report ids
+        all.insert(all.end(), ring.begin(), ring.begin() + got);
+        int warn = 0;
+        if (ctr[HR_CTR_FLAGS] & HR_DEVF_CLOCK) warn |= HR_W_CLOCK_OVERFLOW;
+        if (ctr[HR_CTR_FLAGS] & HR_DEVF_RANGE) warn |= HR_W_OUT_OF_RANGE;
+        if (ctr[HR_CTR_HEAD] > c->cfg.ring_capacity) {
+            // recover the global part of every resident job from its sticky
+            // race words
+            warn |= HR_W_RING_OVERFLOW;
+            for (uint32_t j : active) {
+                const job_state& st = js[j];
+                std::vector<uint64_t> sh(st.elems[0] + st.elems[1]);
+                if (hipMemcpy(sh.data(), b.arena + st.off * GRANULE_WORDS, 8 * sh.size(),
+                              hipMemcpyDeviceToHost) != hipSuccess)
+                    return HR_E_HIP;
+                for (size_t i = 0; i < sh.size(); ++i) {
+                    if ((sh[i] & hr::g::TAG_M) != hr::T_RACE) continue;
+                    hr_race r = {};
+                    r.space = HR_GLOBAL;
+                    r.region = 2 * j + (i >= st.elems[0] ? 1 : 0);
+                    r.index = i >= st.elems[0] ? i - st.elems[0] : i;
+                    r.block = r.launch = r.tid = r.state_before = 0xFFFFFFFFu;
+                    all.push_back(r);
+                }
+            }
+        }
+        // advance, and retire the jobs whose last phase just ran
+        const double end = seconds_since(t0);
+        std::vector<uint32_t> still;
+        for (uint32_t j : active) {
+            job_state& st = js[j];
+            st.status |= warn;
+            if (++st.phase < st.in.phases) {
+                still.push_back(j);
+                continue;
+            }
+            times[j].finish_s = end;
+            times[j].status = st.status;
+            arena.release(st.off, st.granules);
+            free_slots.push_back(st.slot);
+        }
+        active.swap(still);
+    }
+    return HR_OK;
+}
+
+bool race_key_less(const hr_race& a, const hr_race& b)
+{
+    const uint32_t ka = a.space == HR_LDS ? a.block : 0u, kb = b.space == HR_LDS ? b.block : 0u;
+    if (a.region != b.region) return a.region < b.region;
+    if (a.space != b.space) return a.space < b.space;
+    if (ka != kb) return ka < kb;
+    return a.index < b.index;
+}
+
+bool race_key_same(const hr_race& a, const hr_race& b)
+{
+    return a.region == b.region && a.space == b.space && a.index == b.index &&
+           (a.space != HR_LDS || a.block == b.block);
+}
+
+}  // namespace
+
+extern "C" hr_status hr_serve(hr_ctx c, const hr_instance* jobs, hr_serve_job* times,
+                              uint32_t n_jobs, const hr_serve_config* cfg_in, hr_race* out,
+                              size_t cap, size_t* n_out, void* stream)
+{
+    if (!c || !jobs || !times || !n_out || n_jobs == 0 || n_jobs >= (1u << 30)) return HR_E_INVAL;
+    hr_serve_config cfg = {};
+    if (cfg_in) cfg = *cfg_in;
+    if (cfg.max_slots == 0) cfg.max_slots = 1024;
+    if (cfg.shadow_budget == 0) cfg.shadow_budget = 64ull << 30;
+    if (cfg.max_slots >= (1u << 20)) return HR_E_INVAL;
+    for (uint32_t j = 0; j < n_jobs; ++j) {
+        times[j].admit_s = times[j].finish_s = -1.0;
+        times[j].flagged = 0;
+        times[j].status = 0;
+        if (j && times[j].arrival_s < times[j - 1].arrival_s) return HR_E_INVAL;
+    }
+    std::vector<hr_race> all;
+    const hr_status st = cfg.serial ? serve_serial(c, jobs, times, n_jobs, all, stream)
+                                    : serve_continuous(c, jobs, times, n_jobs, cfg, all, stream);
+    if (st < 0) return st;
+    std::sort(all.begin(), all.end(), race_key_less);
+    size_t n = 0;
+    for (size_t i = 0; i < all.size(); ++i)
+        if (n == 0 || !race_key_same(all[n - 1], all[i])) all[n++] = all[i];
+    for (size_t i = 0; i < n; ++i) times[all[i].region / 2].flagged += 1;
+    *n_out = n;
+    if (n > cap || (n && !out)) return HR_E_INVAL;
+    std::copy(all.begin(), all.begin() + n, out);
+    return HR_OK;
+}

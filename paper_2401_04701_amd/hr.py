@@ -61,7 +61,21 @@ class _Tuning(ctypes.Structure):
                 ("spin_limit", ctypes.c_uint32), ("variant", ctypes.c_uint32)]
 
 
+class ServeJob(ctypes.Structure):
+    """hr_serve_job: arrival time in, admission/finish times and counts out."""
+    _fields_ = [("arrival_s", ctypes.c_double), ("admit_s", ctypes.c_double),
+                ("finish_s", ctypes.c_double), ("flagged", ctypes.c_uint32),
+                ("status", ctypes.c_int32)]
+
+
+class _ServeConfig(ctypes.Structure):
+    _fields_ = [("shadow_budget", ctypes.c_uint64), ("max_slots", ctypes.c_uint32),
+                ("workers", ctypes.c_uint32), ("serial", ctypes.c_uint32),
+                ("pad", ctypes.c_uint32)]
+
+
 assert ctypes.sizeof(Instance) == 72
+assert ctypes.sizeof(ServeJob) == 32
 
 
 def _load():
@@ -98,6 +112,7 @@ def _load():
         "hr_batch_info": [P, u32, P, P],
         "hr_batch_destroy": [P],
         "hr_job_run": [P, P, P, sz, P, P],
+        "hr_serve": [P, P, P, u32, P, P, sz, P, P],
         "hr_peak_copy": [P, P, sz, P],
         "hr_peak_atomic": [P, sz, u32, u32, u32, P, P],
         "hr_peak_load": [P, sz, u32, P, P],
@@ -112,7 +127,7 @@ def _load():
 _lib = _load()
 EXPORTED = ("hr_ctx_create", "hr_ctx_destroy", "hr_shadow_alloc", "hr_shadow_free",
             "hr_dev_args", "hr_batch_create", "hr_batch_run", "hr_batch_info",
-            "hr_batch_destroy", "hr_job_run",
+            "hr_batch_destroy", "hr_job_run", "hr_serve",
             "hr_kernel_end", "hr_reset", "hr_report", "hr_check_count", "hr_fsm_step", "hr_fsm_merge",
             "hr_reduce_check", "hr_reduce_plain", "hr_jacobi_check", "hr_jacobi_plain",
             "hr_labelprop_check", "hr_labelprop_plain", "hr_program_check",
@@ -344,6 +359,39 @@ def job_run(inst: Instance, ring_capacity=0, stream=None):
             continue
         _check("hr_job_run", st)
         return _races_to_keys(out[:n.value]), st
+
+
+def serve(ctx: Context, instances, arrivals, shadow_budget=0, max_slots=0, workers=0,
+          serial=False, stream=None):
+    """Check a stream of jobs arriving at `arrivals` (seconds from the call,
+    non-decreasing) with continuous batching, or one at a time (serial).
+    Returns (per-job flagged keys with job-local region ids 0/1, ServeJob
+    array with admission/finish times, flagged counts and warning bits)."""
+    n = len(instances)
+    inst = (Instance * n)(*instances)
+    times = (ServeJob * n)()
+    for j, a in enumerate(arrivals):
+        times[j].arrival_s = float(a)
+    cfg = _ServeConfig(int(shadow_budget), int(max_slots), int(workers), int(bool(serial)), 0)
+    cnt = ctypes.c_size_t(0)
+    cap = 1 << 20          # a larger count re-runs the whole stream
+    while True:
+        out = np.zeros(cap, dtype=RACE_DTYPE)
+        st = _lib.hr_serve(ctx.handle, inst, times, n, ctypes.byref(cfg),
+                           out.ctypes.data_as(ctypes.c_void_p), cap, ctypes.byref(cnt),
+                           _stream_ptr(stream))
+        if st == HR_E_INVAL and cnt.value > cap:
+            cap = int(cnt.value)
+            continue
+        _check("hr_serve", st)
+        break
+    per = [set() for _ in range(n)]
+    for r in out[:cnt.value]:
+        j, k = divmod(int(r["region"]), 2)
+        lds = r["space"] == HR_LDS
+        per[j].add((int(r["space"]), 0 if lds else k, int(r["block"]) if lds else 0,
+                    int(r["index"])))
+    return per, times
 
 
 class Batch:

@@ -362,7 +362,12 @@ def instance_inputs(spec):
                 "out": np.zeros(b * t, dtype=np.int32)}
     if spec["pattern"] == PAT_JACOBI:
         ny, nx = spec["ny"], spec["nx"]
-        seeds = jacobi_seeds(ny, nx, seed, count=1) if spec["seeded"] else np.zeros((0, 3), np.int32)
+        if not spec["seeded"]:
+            seeds = np.zeros((0, 3), np.int32)
+        elif "seed_frac" in spec:
+            seeds = jacobi_seeds(ny, nx, seed, frac=spec["seed_frac"])
+        else:
+            seeds = jacobi_seeds(ny, nx, seed, count=1)
         return {"u0": jacobi_grid(ny, nx, seed), "u1": np.zeros((ny, nx), np.float32),
                 "seeds": seeds,
                 "seed_tab": jacobi_seed_table(ny, nx, seeds) if len(seeds) else None}
@@ -371,3 +376,40 @@ def instance_inputs(spec):
     row_ptr, col = csr_by_source(src, dst, v)
     mask = seeded_edge_mask(e, spec["p_seed"], seed) if spec["seeded"] else np.zeros(e, np.uint8)
     return {"label": np.arange(v, dtype=np.int32), "row_ptr": row_ptr, "col": col, "mask": mask}
+
+
+# --------------------------------------------------------------------------
+# Serving stream: the batched mix plus a share of full-size stencil jobs,
+# arriving as a Poisson process.
+# --------------------------------------------------------------------------
+def serving_stream(seed: int, n_jobs: int = 2000, big_frac: float = 0.05, big_side: int = 4096,
+                   big_phases: int = 20, big_seed_frac: float = 0.001, **manifest_kw):
+    """Job specs in arrival order: round(big_frac * n_jobs) full-size Jacobi
+    jobs (big_side^2 grid, big_phases launches, big_seed_frac of the blocks
+    seeded) at seeded random positions; every other job is drawn as in
+    batched_manifest (keyword arguments are passed on to it)."""
+    rng = np.random.default_rng(seed)
+    n_big = int(round(big_frac * n_jobs))
+    big_at = set(int(i) for i in rng.choice(n_jobs, n_big, replace=False)) if n_big else set()
+    small = iter(batched_manifest(seed ^ 0x5E2F, n_instances=n_jobs - n_big, **manifest_kw))
+    g = (big_side + JACOBI_BS - 1) // JACOBI_BS
+    specs = []
+    for i in range(n_jobs):
+        if i in big_at:
+            spec = {"pattern": PAT_JACOBI, "ny": big_side, "nx": big_side, "phases": big_phases,
+                    "threads": 256, "blocks": g * g, "lds_kib": 0.0, "seeded": True,
+                    "seed": int(rng.integers(0, 2 ** 31 - 1)), "seed_frac": big_seed_frac,
+                    "big": True}
+        else:
+            spec = dict(next(small))
+        spec["index"] = i
+        specs.append(spec)
+    return specs
+
+
+def poisson_arrivals(seed: int, n: int, rate: float) -> np.ndarray:
+    """Arrival times (seconds, from 0) of n jobs of a Poisson process."""
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate, size=n)
+    gaps[0] = 0.0
+    return np.cumsum(gaps)
