@@ -297,6 +297,7 @@ def bench_batched(args, torch, si, hr, stream):
     per_serial = [j.serial(ring_capacity=1 << 20) for j in js]
     serial_s = time.perf_counter() - t0
     equal = all(st2 == 0 and a == b for (a, st2), b in zip(per_serial, per_batch))
+    items = batch.info(0)[1]
     batch.close()
     ctx.close()
     res = {
@@ -305,7 +306,7 @@ def bench_batched(args, torch, si, hr, stream):
         "warmup": args.warmup, "ms_per_step": step_s * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
         "config": {"workload": "batched_1000_mixed_jobs_one_persistent_launch", "jobs": len(js),
-                   "checks_per_step": int(checks), "work_items": batch_items(specs),
+                   "checks_per_step": int(checks), "work_items": items,
                    "parallelism": "single GPU"},
         "jobs_per_s": len(js) / step_s,
         "serial_jobs_per_s": len(js) / serial_s,
@@ -387,18 +388,6 @@ def bench_serving(args, torch, si, hr, stream):
         "served_vs_serial": top["served_vs_serial_jobs_per_s"],
         "equal_results": bool(equal), "rates": out}
     print(json.dumps(res), flush=True)
-
-
-def batch_items(specs):
-    n = 0
-    for s in specs:
-        if s["pattern"] == 1:
-            n += (s["ny"] // 16) * (s["nx"] // 16) * s["phases"]
-        elif s["pattern"] == 2:
-            n += -(-s["vertices"] // s["threads"]) * s["phases"]
-        else:
-            n += s["blocks"]
-    return n
 
 
 def main():

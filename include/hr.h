@@ -313,10 +313,8 @@ typedef struct {
 typedef struct {
     uint64_t shadow_budget;  /* bytes of shadow resident at once; 0: 64 GiB */
     uint32_t max_slots;      /* jobs resident at once, < 2^20; 0: 1024 */
-    uint32_t workers;        /* worker blocks per iteration; 0: all that fit */
     uint32_t serial;         /* nonzero: replay the arrivals one job at a time
                                 through hr_job_run (the plain path) */
-    uint32_t pad;
 } hr_serve_config;
 
 /* Check n_jobs jobs (hr_instance as for hr_batch_create; region[] unused)

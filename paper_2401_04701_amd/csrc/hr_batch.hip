@@ -3,10 +3,10 @@
 // at a time (allocate shadow, launch each phase, report, free).
 //
 // The persistent launch keeps every worker block resident.  Workers claim
-// work items (instance, phase, logical block) in queue order from a global
-// cursor.  A phase of an instance stands in for one kernel launch of that job:
-// an item of phase p waits until every block of phase p-1 of its instance has
-// finished, which gives the launch boundary's happens-before edge, and the
+// work items (instance, phase, pack of logical blocks) in queue order from a
+// global cursor.  A phase of an instance stands in for one kernel launch of
+// that job: an item of phase p waits until every item of phase p-1 of its
+// instance has finished, which gives the launch boundary's happens-before edge, and the
 // shadow words of the instance carry p as their launch epoch.  Every item
 // that phase p waits for sits earlier in the queue and was claimed by a
 // resident worker, so the earliest unfinished item always makes progress; a
@@ -37,7 +37,7 @@ __device__ __forceinline__ uint64_t claim(uint32_t* cursor, const uint64_t* item
 // gives two workers per compute unit within 64 registers (some values then
 // live in scratch).  The autotuner picks between them by measurement.
 //
-// Thread 0 alone claims items, waits for phases and counts finished blocks.
+// Thread 0 alone claims items, waits for phases and counts finished items.
 // Each of those thread-0 regions sits strictly between two block barriers,
 // and every iteration ends with a barrier, so no divergent region spans the
 // loop's back edge and every barrier runs with the whole block active.
@@ -56,14 +56,14 @@ __device__ __forceinline__ void batch_loop(const hr_env& base, const hr_inst_dev
         if (it == ~0ull) break;                         // queue drained: every wave leaves
         const uint32_t ii = (uint32_t)(it >> 32);
         const uint32_t phase = (uint32_t)(it >> ITEM_BLOCK_BITS) & ((1u << ITEM_PHASE_BITS) - 1);
-        const uint32_t lb = (uint32_t)it & ((1u << ITEM_BLOCK_BITS) - 1);
+        const uint32_t item = (uint32_t)it & ((1u << ITEM_BLOCK_BITS) - 1);
         const hr_inst_dev I = load_uniform(insts[ii]);
         if (threadIdx.x == 0) {
             uint32_t go = 1;
             if (phase > 0) {
                 const uint32_t* d = done + I.done_off + phase - 1;
                 uint32_t spins = 0;
-                while (__hip_atomic_load(d, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < I.blocks) {
+                while (__hip_atomic_load(d, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < I.items) {
                     __builtin_amdgcn_s_sleep(8);
                     if (++spins >= spin_limit) {
                         go = 0;
@@ -80,7 +80,7 @@ __device__ __forceinline__ void batch_loop(const hr_env& base, const hr_inst_dev
             hr_env e = base;
             e.launch = phase & ((1u << hr::g::LAUNCH_BITS) - 1);
             e.launch_seq = phase;
-            run_item(e, I, phase, lb, smem);
+            run_item(e, I, phase, item, smem);
         }
         __syncthreads();                                // every hook of the item is done
         if (threadIdx.x == 0) {
@@ -124,7 +124,7 @@ bool hr_instance_shape(hr_instance& in, size_t elems[2], size_t* lds_bytes)
         if (!in.data[0] || !in.data[1]) return false;
         elems[0] = (size_t)in.blocks * n;
         elems[1] = (size_t)in.blocks * T;
-        *lds_bytes = (size_t)n * 8;
+        *lds_bytes = (size_t)(HR_WORKER_THREADS / T) * n * 8;
         break;
     }
     case HR_PAT_JACOBI: {
@@ -133,7 +133,7 @@ bool hr_instance_shape(hr_instance& in, size_t elems[2], size_t* lds_bytes)
         in.blocks = (uint32_t)(nbx * nby);
         in.threads = 256;
         elems[0] = elems[1] = (size_t)in.n * in.ny;
-        *lds_bytes = JACOBI_TILE_WORDS * 8;
+        *lds_bytes = (size_t)(HR_WORKER_THREADS / 256) * JACOBI_TILE_WORDS * 8;
         break;
     }
     case HR_PAT_LABELPROP: {
@@ -167,6 +167,11 @@ hr_inst_dev hr_make_inst_dev(const hr_instance& in, const size_t elems[2], uint6
     d.drop = in.drop;
     d.done_off = done_off;
     d.lds_id = r0;
+    d.pack = HR_WORKER_THREADS / in.threads;
+    d.items = (in.blocks + d.pack - 1) / d.pack;
+    d.lds_words = in.pattern == HR_PAT_REDUCE   ? 2 * in.n
+                  : in.pattern == HR_PAT_JACOBI ? 2 * JACOBI_TILE_WORDS
+                                                : 0;
     d.g0 = hr_gref{sh0, sh0 ? elems[0] : 0, r0};
     d.g1 = hr_gref{sh1, sh1 ? elems[1] : 0, r1};
     d.p0 = in.data[0];
@@ -262,8 +267,8 @@ extern "C" hr_status hr_batch_create(hr_ctx c, hr_instance* inst, uint32_t n_ins
             for (uint32_t k = 0; k < n_inst; ++k) {
                 const uint32_t i = o ? by_size[k] : k;
                 if (p >= inst[i].phases) continue;
-                for (uint32_t lb = 0; lb < inst[i].blocks; ++lb)
-                    q[o].push_back(((uint64_t)i << 32) | ((uint64_t)p << ITEM_BLOCK_BITS) | lb);
+                for (uint32_t it = 0; it < hd[i].items; ++it)
+                    q[o].push_back(((uint64_t)i << 32) | ((uint64_t)p << ITEM_BLOCK_BITS) | it);
             }
     }
     b->n_items = (uint32_t)q[0].size();

@@ -1,8 +1,11 @@
 // Bodies of the instrumented workloads, as device functions of one logical
 // block.  The standalone kernels run one logical block per hardware block;
-// the batch executor runs them inside persistent worker blocks that may have
-// more threads than the logical block (threads beyond `T` only take part in
-// the block barriers).  CHECK=false compiles the hooks out (plain kernels).
+// the job executors run several logical blocks of one job side by side in a
+// larger hardware block (each a group of `T` consecutive threads, a multiple
+// of the wave size).  `t` is the thread's index in its logical block; a
+// thread with t >= T has no logical block and only takes part in the block
+// barriers, which every logical block of a hardware block reaches in the
+// same order.  CHECK=false compiles the hooks out (plain kernels).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -46,15 +49,15 @@ __device__ __forceinline__ void hr_bar(const hr_env& e, hr_thread& t)
 template <bool CHECK>
 __device__ void reduce_body(const hr_env& e, const hr_gref& gin, const hr_gref& gout,
                             const int32_t* __restrict__ in, int32_t* __restrict__ out, uint32_t n,
-                            uint32_t T, uint32_t lb, int32_t drop, int32_t* s, uint32_t* sh,
-                            uint32_t lds_id)
+                            uint32_t T, uint32_t lb, uint32_t t, int32_t drop, int32_t* s,
+                            uint32_t* sh, uint32_t lds_id)
 {
-    const uint32_t t = threadIdx.x;
     const bool act = t < T;
     hr_thread th{};
     if constexpr (CHECK) {
         th = hr_thread_make(e, lb, t);
-        for (uint32_t i = t; i < n; i += blockDim.x) sh[i] = 0;
+        if (act)
+            for (uint32_t i = t; i < n; i += T) sh[i] = 0;
         __syncthreads();
     }
     const size_t base = (size_t)lb * n;
@@ -98,17 +101,18 @@ template <bool CHECK>
 __device__ void jacobi_body(const hr_env& e, const hr_gref& gold, const hr_gref& gnew,
                             const float* __restrict__ uo, float* __restrict__ un, uint32_t ny,
                             uint32_t nx, uint32_t nbx, const int32_t* __restrict__ seeds,
-                            uint32_t lb, float* tile, uint32_t* tsh, uint32_t lds_id)
+                            uint32_t lb, uint32_t t, float* tile, uint32_t* tsh, uint32_t lds_id)
 {
     constexpr uint32_t TW = JACOBI_TILE_WORDS, TL = JACOBI_TILE;
-    const uint32_t t = threadIdx.x, tx = t & 15u, ty = (t >> 4) & 15u;
+    const uint32_t tx = t & 15u, ty = (t >> 4) & 15u;
     const uint32_t bx = lb % nbx, by = lb / nbx;
     const uint32_t gx = bx * 16u + tx, gy = by * 16u + ty;
     const bool inside = t < 256 && gx < nx && gy < ny;
     hr_thread th{};
     if constexpr (CHECK) {
         th = hr_thread_make(e, lb, t);
-        for (uint32_t i = t; i < TW; i += blockDim.x) tsh[i] = 0;
+        if (t < 256)
+            for (uint32_t i = t; i < TW; i += 256) tsh[i] = 0;
         __syncthreads();
     }
     const size_t g = (size_t)gy * nx + gx;
@@ -189,9 +193,9 @@ template <bool CHECK>
 __device__ void labelprop_body(const hr_env& e, const hr_gref& glab, const hr_gref& grp,
                                const hr_gref& gcol, int32_t* __restrict__ label,
                                const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
-                               const uint8_t* __restrict__ mask, uint32_t n, uint32_t T, uint32_t lb)
+                               const uint8_t* __restrict__ mask, uint32_t n, uint32_t T, uint32_t lb,
+                               uint32_t t)
 {
-    const uint32_t t = threadIdx.x;
     const uint32_t v = lb * T + t;
     if (t >= T || v >= n) return;
     hr_thread th{};

@@ -1,6 +1,9 @@
 // Pieces shared by the batched executor and the serving executor: the
 // device job descriptor, block-uniform loads, and the dispatch of one work
-// item (one logical block of one phase of one job) to its workload body.
+// item to its workload body.  A work item is `pack` consecutive logical
+// blocks of one phase of one job, run side by side by one 1024-thread
+// hardware block (pack = 1024 / the job's block size), so that jobs with
+// small blocks still fill the hardware block's waves.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -9,11 +12,15 @@
 #include "hr_bodies.h"
 #include "hr_device.h"
 
+constexpr uint32_t HR_WORKER_THREADS = 1024;
+
 struct hr_inst_dev {
     uint32_t pattern, blocks, threads, phases;
     uint32_t n, ny, nbx;
     int32_t drop;
     uint32_t done_off, lds_id;
+    uint32_t pack, items;     // logical blocks per work item; work items per phase
+    uint32_t lds_words;       // LDS words of one logical block
     hr_gref g0, g1;
     const void* p0;
     void* p1;
@@ -44,36 +51,45 @@ __device__ __forceinline__ hr_gref uni_gref(const hr_gref& g)
     return hr_gref{unip(g.shadow), uni64(g.n), uni(g.id)};
 }
 
+// Work item `item` of `phase`: thread group g (threads g*T .. g*T+T-1, T the
+// job's block size) runs logical block item*pack + g with its own slice of
+// the LDS; threads past the last group, and groups past the job's last
+// block, only take part in the barriers.
 __device__ __forceinline__ void run_item(const hr_env& e, const hr_inst_dev& I, uint32_t phase,
-                                         uint32_t lb, uint32_t* smem)
+                                         uint32_t item, uint32_t* smem)
 {
+    const uint32_t T = I.threads;
+    const uint32_t g = threadIdx.x / T;
+    uint32_t lb = item * I.pack + g, t = threadIdx.x - g * T;
+    uint32_t* lds = smem + g * I.lds_words;
+    if (g >= I.pack || lb >= I.blocks) {
+        t = UINT32_MAX;
+        lb = item * I.pack;
+        lds = smem;
+    }
     switch (I.pattern) {
     case HR_PAT_REDUCE:
-        reduce_body<true>(e, I.g0, I.g1, (const int32_t*)I.p0, (int32_t*)I.p1, I.n, I.threads, lb,
-                          I.drop, (int32_t*)smem, smem + I.n, I.lds_id);
+        reduce_body<true>(e, I.g0, I.g1, (const int32_t*)I.p0, (int32_t*)I.p1, I.n, T, lb, t,
+                          I.drop, (int32_t*)lds, lds + I.n, I.lds_id);
         break;
     case HR_PAT_JACOBI: {
         const bool odd = phase & 1u;
         const float* uo = (const float*)(odd ? I.p1 : I.p0);
         float* un = (float*)(odd ? I.p0 : I.p1);
         jacobi_body<true>(e, odd ? I.g1 : I.g0, odd ? I.g0 : I.g1, uo, un, I.ny, I.n, I.nbx,
-                          (const int32_t*)I.p2, lb, (float*)smem, smem + JACOBI_TILE_WORDS,
+                          (const int32_t*)I.p2, lb, t, (float*)lds, lds + JACOBI_TILE_WORDS,
                           I.lds_id);
         break;
     }
     default: {
         const hr_gref none{nullptr, 0, 0};
         labelprop_body<true>(e, I.g0, none, none, (int32_t*)I.p0, (const int32_t*)I.p1,
-                             (const int32_t*)I.p2, (const uint8_t*)I.p3, I.n, I.threads, lb);
+                             (const int32_t*)I.p2, (const uint8_t*)I.p3, I.n, T, lb, t);
         break;
     }
     }
 }
 
-// Worker loop.  MIN_WAVES is the occupancy target per SIMD: 4 gives one
-// 1024-thread worker per compute unit with up to 128 registers per lane, 8
-// gives two workers per compute unit within 64 registers (some values then
-// live in scratch).  The autotuner picks between them by measurement.
 // The descriptor as every thread of the worker block sees it, in scalar
 // registers.
 __device__ __forceinline__ hr_inst_dev load_uniform(const hr_inst_dev& G)
@@ -89,6 +105,9 @@ __device__ __forceinline__ hr_inst_dev load_uniform(const hr_inst_dev& G)
     I.drop = (int32_t)uni((uint32_t)G.drop);
     I.done_off = uni(G.done_off);
     I.lds_id = uni(G.lds_id);
+    I.pack = uni(G.pack);
+    I.items = uni(G.items);
+    I.lds_words = uni(G.lds_words);
     I.g0 = uni_gref(G.g0);
     I.g1 = uni_gref(G.g1);
     I.p0 = unip(G.p0);
@@ -99,7 +118,8 @@ __device__ __forceinline__ hr_inst_dev load_uniform(const hr_inst_dev& G)
 }
 
 // Shape checks and derived sizes of one job; fills blocks (and threads for
-// jacobi), the element counts of its two monitored buffers and its LDS need.
+// jacobi), the element counts of its two monitored buffers and the LDS bytes
+// of one work item.
 bool hr_instance_shape(hr_instance& in, size_t elems[2], size_t* lds_bytes);
 
 // Descriptor of a job whose shadow words are at sh0 / sh1; report ids r0/r1.

@@ -3,9 +3,9 @@
 //
 // The host loop admits jobs that have arrived, in arrival order, while a
 // job slot and shadow memory under the budget are free; every iteration is
-// one launch that advances each resident job by one phase, so jobs that
-// arrive while others run join at the next iteration and their work shares
-// the device with everyone else's.  The launch boundary of every iteration
+// one launch with one 1024-thread block per work item of every resident
+// job's next phase, so jobs that arrive while others run join at the next
+// iteration and their work shares the device with everyone else's.  The launch boundary of every iteration
 // is the launch boundary of each job's phase; a job's shadow stays resident
 // across its phases (its launch epoch is its phase) and is released when its
 // last phase is reported.  No kernel waits for another block: items of one
@@ -28,39 +28,30 @@
 
 namespace {
 
-__global__ __launch_bounds__(1024) void k_iter(hr_env base, const hr_inst_dev* __restrict__ slots,
+// One iteration: work item blockIdx.x of the flat list of the resident
+// jobs' items, each job contributing the items of its next phase (prefix[k]
+// = items of the jobs before job k in the list).
+__global__ __launch_bounds__(1024, 8) void k_iter(hr_env base, const hr_inst_dev* __restrict__ slots,
                                                const uint32_t* __restrict__ act,
-                                               const uint64_t* __restrict__ prefix, uint32_t n_act,
-                                               uint32_t total, uint32_t* cursor)
+                                               const uint64_t* __restrict__ prefix, uint32_t n_act)
 {
     extern __shared__ uint32_t smem[];
-    __shared__ uint32_t s_i;
-    if (threadIdx.x == 0)
-        s_i = __hip_atomic_fetch_add(cursor, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __syncthreads();
-    for (;;) {
-        const uint32_t i = uni(s_i);
-        if (i >= total) break;                         // iteration drained: every wave leaves
-        // the job owning item i: the largest k with prefix[k] <= i
-        uint32_t lo = 0, hi = n_act;
-        while (hi - lo > 1) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (uni64(prefix[mid]) <= i) lo = mid;
-            else hi = mid;
-        }
-        const uint32_t a = uni(act[lo]);
-        const uint32_t slot = a & 0xFFFFFu, phase = a >> 20;
-        const uint32_t lb = i - (uint32_t)uni64(prefix[lo]);
-        const hr_inst_dev I = load_uniform(slots[slot]);
-        hr_env e = base;
-        e.launch = phase & ((1u << hr::g::LAUNCH_BITS) - 1);
-        e.launch_seq = phase;
-        run_item(e, I, phase, lb, smem);
-        __syncthreads();                               // every hook of the item is done
-        if (threadIdx.x == 0)
-            s_i = __hip_atomic_fetch_add(cursor, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __syncthreads();
+    const uint32_t i = blockIdx.x;
+    // the job owning item i: the largest k with prefix[k] <= i
+    uint32_t lo = 0, hi = n_act;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (uni64(prefix[mid]) <= i) lo = mid;
+        else hi = mid;
     }
+    const uint32_t a = uni(act[lo]);
+    const uint32_t slot = a & 0xFFFFFu, phase = a >> 20;
+    const uint32_t item = i - (uint32_t)uni64(prefix[lo]);
+    const hr_inst_dev I = load_uniform(slots[slot]);
+    hr_env e = base;
+    e.launch = phase & ((1u << hr::g::LAUNCH_BITS) - 1);
+    e.launch_seq = phase;
+    run_item(e, I, phase, item, smem);
 }
 
 // First-fit allocator of 256-byte granules inside one device arena.
@@ -162,7 +153,6 @@ struct serve_buffers {
     hr_inst_dev* slots = nullptr;
     uint32_t* act = nullptr;
     uint64_t* prefix = nullptr;
-    uint32_t* cursor = nullptr;
     uint32_t* h_act = nullptr;      // pinned staging
     uint64_t* h_prefix = nullptr;
     hr_inst_dev* h_desc = nullptr;
@@ -172,7 +162,6 @@ struct serve_buffers {
         if (slots) (void)hipFree(slots);
         if (act) (void)hipFree(act);
         if (prefix) (void)hipFree(prefix);
-        if (cursor) (void)hipFree(cursor);
         if (h_act) (void)hipHostFree(h_act);
         if (h_prefix) (void)hipHostFree(h_prefix);
         if (h_desc) (void)hipHostFree(h_desc);
@@ -205,21 +194,17 @@ hr_status serve_continuous(hr_ctx c, const hr_instance* jobs, hr_serve_job* time
         hipMalloc(&b.slots, sizeof(hr_inst_dev) * max_slots) != hipSuccess ||
         hipMalloc(&b.act, sizeof(uint32_t) * max_slots) != hipSuccess ||
         hipMalloc(&b.prefix, sizeof(uint64_t) * (max_slots + 1)) != hipSuccess ||
-        hipMalloc(&b.cursor, sizeof(uint32_t)) != hipSuccess ||
         hipHostMalloc(&b.h_act, sizeof(uint32_t) * max_slots, hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc(&b.h_prefix, sizeof(uint64_t) * (max_slots + 1), hipHostMallocDefault) !=
             hipSuccess ||
         hipHostMalloc(&b.h_desc, sizeof(hr_inst_dev) * max_slots, hipHostMallocDefault) !=
             hipSuccess)
         return HR_E_NOMEM;
-    int per_cu = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_iter, 1024, lds) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) !=
+    int per_cu = 0;   // the iteration kernel must fit with the largest item's LDS
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_iter, HR_WORKER_THREADS, lds) !=
             hipSuccess ||
-        per_cu <= 0 || cus <= 0)
+        per_cu <= 0)
         return HR_E_HIP;
-    const uint32_t max_workers = (uint32_t)(per_cu * cus);
-    const uint32_t workers = cfg.workers ? std::min(cfg.workers, max_workers) : max_workers;
     arena_alloc arena(arena_granules);
     std::vector<uint32_t> free_slots;
     for (uint32_t k = max_slots; k-- > 0;) free_slots.push_back(k);
@@ -260,7 +245,7 @@ hr_status serve_continuous(hr_ctx c, const hr_instance* jobs, hr_serve_job* time
             const job_state& st = js[active[k]];
             b.h_prefix[k] = total;
             b.h_act[k] = st.slot | (st.phase << 20);
-            total += st.in.blocks;
+            total += b.h_desc[st.slot].items;
         }
         b.h_prefix[active.size()] = total;
         if (total >= (1ull << 32)) return HR_E_INVAL;
@@ -268,10 +253,10 @@ hr_status serve_continuous(hr_ctx c, const hr_instance* jobs, hr_serve_job* time
                            hipMemcpyHostToDevice, s) != hipSuccess ||
             hipMemcpyAsync(b.prefix, b.h_prefix, sizeof(uint64_t) * (active.size() + 1),
                            hipMemcpyHostToDevice, s) != hipSuccess ||
-            hr_fill32(b.cursor, 1, s) != hipSuccess || hr_fill32(c->ctr, HR_CTR_WORDS, s) != hipSuccess)
+            hr_fill32(c->ctr, HR_CTR_WORDS, s) != hipSuccess)
             return HR_E_HIP;
-        HR_LAUNCH(k_iter, dim3(workers), dim3(1024), lds, s, env_base, b.slots, b.act, b.prefix,
-                  (uint32_t)active.size(), (uint32_t)total, b.cursor);
+        HR_LAUNCH(k_iter, dim3((uint32_t)total), dim3(HR_WORKER_THREADS), lds, s, env_base, b.slots,
+                  b.act, b.prefix, (uint32_t)active.size());
         uint32_t ctr[HR_CTR_WORDS];
         if (hipMemcpyAsync(ctr, c->ctr, sizeof(ctr), hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess)

@@ -28,8 +28,8 @@ __global__ __launch_bounds__(1024) void k_reduce(hr_kargs a, hr_gref gin, hr_gre
                                                  int32_t drop)
 {
     extern __shared__ uint32_t smem[];
-    reduce_body<CHECK>(a.env, gin, gout, in, out, n, blockDim.x, blockIdx.x, drop, (int32_t*)smem,
-                       smem + n, 0);
+    reduce_body<CHECK>(a.env, gin, gout, in, out, n, blockDim.x, blockIdx.x, threadIdx.x, drop,
+                       (int32_t*)smem, smem + n, 0);
 }
 
 template <bool CHECK>
@@ -41,7 +41,7 @@ __global__ __launch_bounds__(256) void k_jacobi(hr_kargs a, hr_gref gold, hr_gre
     __shared__ float tile[JACOBI_TILE_WORDS];
     __shared__ uint32_t tsh[CHECK ? JACOBI_TILE_WORDS : 1];
     jacobi_body<CHECK>(a.env, gold, gnew, uo, un, ny, nx, gridDim.x, seeds,
-                       blockIdx.y * gridDim.x + blockIdx.x, tile, tsh, 0);
+                       blockIdx.y * gridDim.x + blockIdx.x, threadIdx.x, tile, tsh, 0);
 }
 
 template <bool CHECK>
@@ -51,7 +51,8 @@ __global__ __launch_bounds__(1024) void k_labelprop(hr_kargs a, hr_gref glab, hr
                                                     const int32_t* __restrict__ col,
                                                     const uint8_t* __restrict__ mask, uint32_t n)
 {
-    labelprop_body<CHECK>(a.env, glab, grp, gcol, label, rp, col, mask, n, blockDim.x, blockIdx.x);
+    labelprop_body<CHECK>(a.env, glab, grp, gcol, label, rp, col, mask, n, blockDim.x, blockIdx.x,
+                          threadIdx.x);
 }
 
 // ----------------------------------------------------------- interpreter

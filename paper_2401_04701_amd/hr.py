@@ -70,8 +70,7 @@ class ServeJob(ctypes.Structure):
 
 class _ServeConfig(ctypes.Structure):
     _fields_ = [("shadow_budget", ctypes.c_uint64), ("max_slots", ctypes.c_uint32),
-                ("workers", ctypes.c_uint32), ("serial", ctypes.c_uint32),
-                ("pad", ctypes.c_uint32)]
+                ("serial", ctypes.c_uint32)]
 
 
 assert ctypes.sizeof(Instance) == 72
@@ -361,8 +360,8 @@ def job_run(inst: Instance, ring_capacity=0, stream=None):
         return _races_to_keys(out[:n.value]), st
 
 
-def serve(ctx: Context, instances, arrivals, shadow_budget=0, max_slots=0, workers=0,
-          serial=False, stream=None):
+def serve(ctx: Context, instances, arrivals, shadow_budget=0, max_slots=0, serial=False,
+          stream=None):
     """Check a stream of jobs arriving at `arrivals` (seconds from the call,
     non-decreasing) with continuous batching, or one at a time (serial).
     Returns (per-job flagged keys with job-local region ids 0/1, ServeJob
@@ -372,7 +371,7 @@ def serve(ctx: Context, instances, arrivals, shadow_budget=0, max_slots=0, worke
     times = (ServeJob * n)()
     for j, a in enumerate(arrivals):
         times[j].arrival_s = float(a)
-    cfg = _ServeConfig(int(shadow_budget), int(max_slots), int(workers), int(bool(serial)), 0)
+    cfg = _ServeConfig(int(shadow_budget), int(max_slots), int(bool(serial)))
     cnt = ctypes.c_size_t(0)
     cap = 1 << 20          # a larger count re-runs the whole stream
     while True:
