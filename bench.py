@@ -126,7 +126,21 @@ def measure_peaks(torch, hr, stream):
                 hr.peak_atomic(words, op, rnd[0], scatter, fails)
                 rnd[0] += 1
             out[f"{opname}_{pat}_per_s"] = n / (_best_ms(torch, stream, run) * 1e-3)
+    # spread over a 32 MiB array (the label-propagation shadow size)
+    nr = 1 << 22
+    for op, opname in ((0, "cas"), (1, "xchg")):
+        def run(op=op):
+            hr.peak_atomic(words[:nr], op, rnd[0], 2, fails)
+            rnd[0] += 1
+        words[:nr].fill_(rnd[0])
+        torch.cuda.synchronize()
+        out[f"{opname}_random32MiB_per_s"] = nr / (_best_ms(torch, stream, run) * 1e-3)
     out["atomic_failures"] = int(fails.item())
+    blocks, iters = 4096, 256
+    for op, name in ((0, "lds_cas_per_s"), (1, "lds_load_cas_per_s")):
+        ms = _best_ms(torch, stream, lambda op=op: hr.peak_lds(blocks, iters, op, fails))
+        out[name] = blocks * 1024 * iters / (ms * 1e-3)
+    out["lds_failures"] = int(fails.item()) - out["atomic_failures"]
     for scatter, pat in ((0, "coalesced"), (1, "scattered")):
         ms = _best_ms(torch, stream, lambda scatter=scatter: hr.peak_load(words, scatter, sink))
         out[f"load_{pat}_per_s"] = n / (ms * 1e-3)

@@ -72,6 +72,11 @@ typedef struct {
 
 /* Count every checked access in a device counter (read by hr_check_count). */
 #define HR_CFG_COUNT_CHECKS 1u
+/* Wave grouping at hook sites with data-dependent addresses: lanes of one
+ * hook instruction that hit the same shadow word are folded into one update
+ * by an owner lane (the result is unchanged; only the number of atomics
+ * drops under same-word contention).  Off by default. */
+#define HR_CFG_WAVE_GROUPING 2u
 
 /* One flagged location, 32 bytes.  The key is (space, region, block if LDS,
  * index); the remaining fields describe the access that completed the race. */
@@ -345,11 +350,20 @@ hr_status hr_peak_copy(const void* src_dev, void* dst_dev, size_t bytes, void* s
 /* One agent-scope 64-bit atomic per word of words_dev[n]: op 0 is a
  * compare-and-swap from `round` to round+1, op 1 an exchange writing round+1
  * (the two forms the checking path uses).  Every word must hold `round`;
- * scatter != 0 permutes words within 64 KiB windows (n should be a multiple
- * of 8192) so the lanes of a wave hit different cache lines.  Operations that
+ * scatter 1 permutes words within 64 KiB windows (n should be a multiple of
+ * 8192) so the lanes of a wave hit different cache lines; scatter 2 (n a
+ * power of two) spreads consecutive operations over the whole array.  Operations that
  * found another value are added to *fails_dev. */
 hr_status hr_peak_atomic(uint64_t* words_dev, size_t n, uint32_t op, uint32_t round,
                          uint32_t scatter, uint32_t* fails_dev, void* stream);
+
+/* LDS 32-bit compare-and-swap throughput: `blocks` blocks of 1024 threads,
+ * each thread taking its own LDS word through `iters` successful
+ * compare-and-swaps (op 0), or each time a load then a compare-and-swap from
+ * the loaded value (op 1, the LDS hook's pattern): blocks * 1024 * iters
+ * operations.  A failed operation is added to *fails_dev. */
+hr_status hr_peak_lds(uint32_t blocks, uint32_t iters, uint32_t op, uint32_t* fails_dev,
+                      void* stream);
 
 /* One agent-scope (coherent) 64-bit atomic load per word of words_dev[n],
  * same index patterns as hr_peak_atomic; sink_dev receives nothing unless an

@@ -19,11 +19,12 @@ struct hr_gref {
     uint32_t id;
 };
 
-template <int KIND, bool CHECK>
+// Global hook at a lane-affine site (GROUP false) or a data-dependent one.
+template <int KIND, bool CHECK, bool GROUP = false>
 __device__ __forceinline__ void hr_g(const hr_env& e, const hr_thread& t, const hr_gref& g,
                                      uint64_t index)
 {
-    if constexpr (CHECK) hr_check<KIND>(e, t, g.shadow, g.n, g.id, index);
+    if constexpr (CHECK) hr_check<KIND, GROUP>(e, t, g.shadow, g.n, g.id, index);
 }
 
 template <int KIND, bool CHECK>
@@ -213,12 +214,12 @@ __device__ void labelprop_body(const hr_env& e, const hr_gref& glab, const hr_gr
         if (u >= n) continue;
         if (mask[k]) {
             const int32_t r = label[u];
-            hr_g<0, CHECK>(e, th, glab, u);
+            hr_g<0, CHECK, true>(e, th, glab, u);
             label[u] = r < l ? r : l;
-            hr_g<1, CHECK>(e, th, glab, u);
+            hr_g<1, CHECK, true>(e, th, glab, u);
         } else {
             atomicMin(label + u, l);
-            hr_g<2, CHECK>(e, th, glab, u);
+            hr_g<2, CHECK, true>(e, th, glab, u);
         }
     }
 }

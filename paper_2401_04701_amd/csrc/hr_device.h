@@ -55,6 +55,7 @@ struct hr_env {
     uint32_t launch_seq;                // launch sequence number (reports)
     uint32_t bc_max;                    // last valid block-clock value
     uint32_t wc_max;                    // last valid wave-clock value
+    uint32_t group;                     // wave grouping at data-dependent hook sites
 };
 
 // Plain-old-data block handed to instrumented kernels by value.
@@ -149,9 +150,75 @@ __device__ __noinline__ uint64_t hr_fold(uint64_t* sp, uint64_t mine, uint64_t l
     }
 }
 
+// Wave grouping of one hook instruction.  Lanes of a wave that run the
+// same hook on the same shadow word at once (a hub vertex, a broadcast
+// read) share the access kind, the block, the wave and both epochs, and
+// differ only in thread; after the first two distinct threads of such a
+// group a further member never changes the word.  So one owner lane applies
+// itself and one other member and the rest skip their update, which turns a
+// burst of same-word atomics (the contention the paper's lock-free update
+// is built against, Sec. IV-B) into one.
+//
+// Fast path: if the words' low 32 bits rise strictly over the active lanes
+// in lane order (every coalesced or strided pattern), all words differ.
+// Otherwise each lane claims a hash bucket of its word in a per-wave LDS
+// table; lanes whose word equals their bucket owner's word are members and
+// leave a note for the owner.  Lanes whose bucket went to another word just
+// update alone, so the grouping never changes the result, only the number
+// of atomics.
+#define HR_GROUP_SLOTS 1024   // one byte per thread of a block, per table
+#define HR_NO_LANE 64u
+
+__device__ __forceinline__ uint32_t hr_flat_thread()
+{
+    return threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
+}
+
+// Returns the lane of another member for an owner (HR_NO_LANE if alone) and
+// sets *member for lanes whose update the owner makes.
+__device__ __forceinline__ uint32_t hr_group(uint64_t word_addr, bool* member)
+{
+    const uint32_t lane = __lane_id();
+    const uint64_t act = __ballot(1);
+    *member = false;
+    if ((act & (act - 1)) == 0) return HR_NO_LANE;      // a single lane
+    const uint64_t below = act & ((1ull << lane) - 1ull);
+    const int prev = below ? 63 - __builtin_clzll(below) : (int)lane;
+    const uint32_t key = (uint32_t)word_addr;
+    const uint32_t pk = (uint32_t)__shfl((int)key, prev);
+    if (__ballot(below != 0 && key <= pk) == 0) return HR_NO_LANE;
+    __shared__ uint8_t owner_of[HR_GROUP_SLOTS];
+    __shared__ uint8_t partner[HR_GROUP_SLOTS];
+    const uint32_t base = hr_flat_thread() & ~63u;
+    const uint32_t h = (key ^ (key >> 6) ^ (key >> 12) ^ (uint32_t)(word_addr >> 32)) & 63u;
+    // Relaxed wave-scope atomics keep the compiler from forwarding a lane's
+    // own store; the hardware runs a wave's LDS operations in issue order.
+    __hip_atomic_store(&partner[base + lane], (uint8_t)HR_NO_LANE, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_WAVEFRONT);
+    __hip_atomic_store(&owner_of[base + h], (uint8_t)lane, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_WAVEFRONT);             // one writer per bucket wins
+    const uint32_t own =
+        __hip_atomic_load(&owner_of[base + h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    const uint32_t olo = (uint32_t)__shfl((int)(uint32_t)word_addr, (int)own);
+    const uint32_t ohi = (uint32_t)__shfl((int)(uint32_t)(word_addr >> 32), (int)own);
+    const bool mem = own != lane && (((uint64_t)ohi << 32) | olo) == word_addr;
+    if (mem)                                                       // one member's note wins
+        __hip_atomic_store(&partner[base + own], (uint8_t)lane, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_WAVEFRONT);
+    const uint32_t other =
+        own == lane ? (uint32_t)__hip_atomic_load(&partner[base + lane], __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_WAVEFRONT)
+                    : HR_NO_LANE;
+    *member = mem;
+    return other;
+}
+
 // Check one access of kind KIND (0 read, 1 write, 2 atomic) to element
 // `index` of a global region whose shadow is shadow[0..n); `region` is the
-// id written into a race record.
+// id written into a race record.  GROUP marks a call site whose addresses
+// depend on data (a gather or scatter); there the wave grouping runs when
+// the context enables it.  Call sites with lane-affine addresses (the lanes
+// of a wave touch distinct words by construction) never group.
 //
 // The copy-compute-publish loop of the paper's Algorithm 1, published with an
 // atomic exchange instead of a compare-and-swap (on gfx950 a 64-bit exchange
@@ -160,7 +227,7 @@ __device__ __noinline__ uint64_t hr_fold(uint64_t* sp, uint64_t mine, uint64_t l
 // returns the loaded word, it acted exactly as a successful compare-and-swap.
 // Otherwise it overwrote updates made since the load, and hr_fold merges
 // them back.
-template <int KIND>
+template <int KIND, bool GROUP = false>
 __device__ __forceinline__ void hr_check(const hr_env& e, const hr_thread& t, uint64_t* shadow,
                                          uint64_t n, uint32_t region, uint64_t index)
 {
@@ -172,8 +239,17 @@ __device__ __forceinline__ void hr_check(const hr_env& e, const hr_thread& t, ui
     }
     constexpr uint32_t k = KIND == 0 ? hr::CL_R : (KIND == 2 ? hr::CL_A : hr::CL_X);
     uint64_t* sp = shadow + index;
+    uint32_t other = HR_NO_LANE;
+    if (GROUP && e.group) {
+        bool member;
+        other = hr_group((uint64_t)sp >> 3, &member);
+        if (member) return;
+    }
     const uint64_t old = __hip_atomic_load(sp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const uint64_t nw = hr::g::step(old, t.gid, k);
+    uint64_t nw = hr::g::step(old, t.gid, k);
+    if (other != HR_NO_LANE)
+        nw = hr::g::step(nw, hr::g::pack_id(e.launch, t.block, t.thread - __lane_id() + other,
+                                            t.bc, t.wc), k);
     if (nw == old) return;
     const uint64_t r = __hip_atomic_exchange(sp, nw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (nw == hr::T_RACE) {
@@ -196,7 +272,7 @@ __device__ __forceinline__ void hr_access(const hr_kargs& a, const hr_thread& t,
         if (t.enabled) hr_set_flag(a.env, HR_DEVF_RANGE);
         return;
     }
-    hr_check<KIND>(a.env, t, a.shadow[region], a.n_elems[region], region, index);
+    hr_check<KIND, true>(a.env, t, a.shadow[region], a.n_elems[region], region, index);
 }
 
 // Check one access to word `index` of a block's LDS array `array_id`, whose
@@ -234,9 +310,9 @@ __device__ __forceinline__ void hr_check_k(const hr_env& e, const hr_thread& t, 
                                            uint64_t* shadow, uint64_t n, uint32_t region,
                                            uint64_t index)
 {
-    if (kind == 0) hr_check<0>(e, t, shadow, n, region, index);
-    else if (kind == 1) hr_check<1>(e, t, shadow, n, region, index);
-    else hr_check<2>(e, t, shadow, n, region, index);
+    if (kind == 0) hr_check<0, true>(e, t, shadow, n, region, index);
+    else if (kind == 1) hr_check<1, true>(e, t, shadow, n, region, index);
+    else hr_check<2, true>(e, t, shadow, n, region, index);
 }
 
 __device__ __forceinline__ void hr_access_lds_k(const hr_env& e, const hr_thread& t,

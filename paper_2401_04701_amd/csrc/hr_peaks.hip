@@ -1,8 +1,9 @@
 // Device microbenchmarks that give the roofline denominators of the checker:
 // streaming copy (HBM bandwidth, also the calibration kernel for the HBM
 // byte counters), agent-scope 64-bit compare-and-swap and exchange on
-// distinct words (coalesced or scattered), and agent-scope 64-bit atomic
-// loads.
+// distinct words (coalesced, scattered in 64 KiB windows, or spread over the
+// whole array), agent-scope 64-bit atomic loads, and 32-bit LDS
+// compare-and-swap (alone, and after a load as the LDS hook does it).
 #include <hip/hip_runtime.h>
 
 #include "hr.h"
@@ -19,11 +20,14 @@ __global__ __launch_bounds__(256) void k_copy(const uint4* __restrict__ src,
 }
 
 // Word w holds `round` before round `round`; every compare-and-swap succeeds.
-// scatter != 0 permutes word indices inside each 64 KiB window so that the
-// lanes of a wave touch different cache lines.
+// scatter 1 permutes word indices inside each 64 KiB window so that the
+// lanes of a wave touch different cache lines; scatter 2 (n a power of two)
+// spreads consecutive indices over the whole array.
 __device__ __forceinline__ size_t peak_index(size_t i, size_t n, uint32_t scatter)
 {
     if (!scatter) return i;
+    if (scatter == 2 && (n & (n - 1)) == 0)
+        return (i * 0x9E3779B1ull) & (n - 1);       // odd multiplier: a bijection mod n
     const size_t win = 8192;                        // 64 KiB of 8-byte words
     const size_t base = i & ~(win - 1);
     const size_t j = ((i & (win - 1)) * 4099u) & (win - 1);   // odd multiplier: a bijection
@@ -70,6 +74,29 @@ __global__ __launch_bounds__(256) void k_load(const uint64_t* __restrict__ w, si
     if (acc == 0x9E3779B97F4A7C15ull) *sink = acc;    // keeps the loads alive
 }
 
+// LDS 32-bit compare-and-swap: every thread owns word threadIdx.x of a
+// block-local array and takes it from r to r+1 for r = 0 .. iters-1
+// (op 0), or first loads it and swaps from the loaded value (op 1, the LDS
+// hook's load + compare-and-swap).  Lanes of a wave hit distinct banks.
+template <int OP>
+__global__ __launch_bounds__(1024) void k_lds_cas(uint32_t iters, uint32_t* __restrict__ fails)
+{
+    __shared__ uint32_t w[1024];
+    uint32_t* p = w + threadIdx.x;
+    *p = 0;
+    uint32_t bad = 0;
+    for (uint32_t r = 0; r < iters; ++r) {
+        uint32_t expect = OP == 0 ? r
+                                  : __hip_atomic_load(p, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (!__hip_atomic_compare_exchange_strong(p, &expect, expect + 1, __ATOMIC_RELAXED,
+                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))
+            ++bad;
+    }
+    if (*p != iters) ++bad;
+    if (bad) atomicAdd(fails, bad);
+}
+
 unsigned grid_for(size_t n)
 {
     const size_t blocks = (n + 255) / 256;
@@ -107,5 +134,16 @@ extern "C" hr_status hr_peak_load(const uint64_t* words_dev, size_t n, uint32_t 
     if (!words_dev || !sink_dev || n == 0) return HR_E_INVAL;
     HR_LAUNCH(k_load, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream, words_dev, n, scatter,
               sink_dev);
+    return HR_OK;
+}
+
+extern "C" hr_status hr_peak_lds(uint32_t blocks, uint32_t iters, uint32_t op, uint32_t* fails_dev,
+                                 void* stream)
+{
+    if (!fails_dev || blocks == 0 || iters == 0 || op > 1) return HR_E_INVAL;
+    if (op == 0)
+        HR_LAUNCH(k_lds_cas<0>, dim3(blocks), dim3(1024), 0, (hipStream_t)stream, iters, fails_dev);
+    else
+        HR_LAUNCH(k_lds_cas<1>, dim3(blocks), dim3(1024), 0, (hipStream_t)stream, iters, fails_dev);
     return HR_OK;
 }

@@ -87,6 +87,7 @@ hr_env hr_make_env(hr_ctx c)
     e.launch_seq = c->launch_seq;
     e.bc_max = (1u << c->cfg.bc_bits) - 1;
     e.wc_max = (1u << c->cfg.wc_bits) - 1;
+    e.group = (c->cfg.flags & HR_CFG_WAVE_GROUPING) ? 1u : 0u;
     return e;
 }
 
@@ -152,6 +153,7 @@ extern "C" hr_status hr_ctx_create(hr_ctx* out, const hr_config* cfg, void* stre
     if (k.bc_bits == 0) k.bc_bits = 8;
     if (k.wc_bits == 0) k.wc_bits = 6;
     if (k.bc_bits > 8 || k.wc_bits > 6 || k.ring_capacity > (1u << 26)) return HR_E_INVAL;
+    if (k.flags & ~(HR_CFG_COUNT_CHECKS | HR_CFG_WAVE_GROUPING)) return HR_E_INVAL;
     hr_ctx c = new (std::nothrow) hr_ctx_s();
     if (!c) return HR_E_NOMEM;
     c->cfg = k;

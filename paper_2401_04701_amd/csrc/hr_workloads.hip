@@ -33,7 +33,7 @@ __global__ __launch_bounds__(1024) void k_reduce(hr_kargs a, hr_gref gin, hr_gre
 }
 
 template <bool CHECK>
-__global__ __launch_bounds__(256) void k_jacobi(hr_kargs a, hr_gref gold, hr_gref gnew,
+__global__ __launch_bounds__(256, 8) void k_jacobi(hr_kargs a, hr_gref gold, hr_gref gnew,
                                                 const float* __restrict__ uo,
                                                 float* __restrict__ un, uint32_t ny, uint32_t nx,
                                                 const int32_t* __restrict__ seeds)

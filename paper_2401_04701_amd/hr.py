@@ -23,6 +23,7 @@ HR_E_INVAL, HR_E_NOMEM, HR_E_HIP, HR_E_STATE = -1, -2, -3, -4
 HR_GLOBAL, HR_LDS = 0, 1
 HR_READ, HR_WRITE, HR_ATOMIC = 0, 1, 2
 HR_CFG_COUNT_CHECKS = 1
+HR_CFG_WAVE_GROUPING = 2
 NO_REGION = 0xFFFFFFFF
 HR_PAT_REDUCE, HR_PAT_JACOBI, HR_PAT_LABELPROP = 0, 1, 2
 
@@ -115,6 +116,7 @@ def _load():
         "hr_peak_copy": [P, P, sz, P],
         "hr_peak_atomic": [P, sz, u32, u32, u32, P, P],
         "hr_peak_load": [P, sz, u32, P, P],
+        "hr_peak_lds": [u32, u32, u32, P, P],
     }
     for name, args in sigs.items():
         fn = getattr(lib, name)
@@ -130,7 +132,7 @@ EXPORTED = ("hr_ctx_create", "hr_ctx_destroy", "hr_shadow_alloc", "hr_shadow_fre
             "hr_kernel_end", "hr_reset", "hr_report", "hr_check_count", "hr_fsm_step", "hr_fsm_merge",
             "hr_reduce_check", "hr_reduce_plain", "hr_jacobi_check", "hr_jacobi_plain",
             "hr_labelprop_check", "hr_labelprop_plain", "hr_program_check",
-            "hr_peak_copy", "hr_peak_atomic", "hr_peak_load")
+            "hr_peak_copy", "hr_peak_atomic", "hr_peak_load", "hr_peak_lds")
 
 
 def lib():
@@ -200,6 +202,10 @@ def peak_atomic(words, op, rnd, scatter, fails, stream=None):
                                                  _dptr(fails), _stream_ptr(stream)))
 
 
+def peak_lds(blocks, iters, op, fails, stream=None):
+    _check("hr_peak_lds", _lib.hr_peak_lds(blocks, iters, op, _dptr(fails), _stream_ptr(stream)))
+
+
 def peak_load(words, scatter, sink, stream=None):
     _check("hr_peak_load", _lib.hr_peak_load(_dptr(words), words.numel(), scatter, _dptr(sink),
                                              _stream_ptr(stream)))
@@ -228,9 +234,10 @@ class Context:
     """A checking job: shadow regions, report ring, launch epochs."""
 
     def __init__(self, ring_capacity=0, bc_bits=0, wc_bits=0, count_checks=False,
-                 shadow_budget=0, stream=None):
-        cfg = _Config(ring_capacity, bc_bits, wc_bits,
-                      HR_CFG_COUNT_CHECKS if count_checks else 0, shadow_budget)
+                 shadow_budget=0, wave_grouping=False, stream=None):
+        flags = (HR_CFG_COUNT_CHECKS if count_checks else 0) | \
+                (HR_CFG_WAVE_GROUPING if wave_grouping else 0)
+        cfg = _Config(ring_capacity, bc_bits, wc_bits, flags, shadow_budget)
         self._c = ctypes.c_void_p(0)
         self._stream = _stream_ptr(stream)
         _check("hr_ctx_create", _lib.hr_ctx_create(ctypes.byref(self._c), ctypes.byref(cfg),

@@ -29,3 +29,15 @@ def test_binding_has_no_fallback_path():
     """The binding imports only libhr.so; it never imports the oracle."""
     src = open(os.path.join(ROOT, "paper_2401_04701_amd", "hr.py")).read()
     assert "oracle" not in src
+
+
+def test_unknown_config_flags_are_rejected():
+    """Argument checks that run before any device call."""
+    import ctypes
+    from paper_2401_04701_amd import hr
+    c = ctypes.c_void_p(0)
+    cfg = hr._Config(0, 0, 0, 1 << 7, 0)
+    assert hr.lib().hr_ctx_create(ctypes.byref(c), ctypes.byref(cfg), None) == hr.HR_E_INVAL
+    cfg = hr._Config(0, 9, 0, 0, 0)                  # block clock wider than 8 bits
+    assert hr.lib().hr_ctx_create(ctypes.byref(c), ctypes.byref(cfg), None) == hr.HR_E_INVAL
+    assert not c.value

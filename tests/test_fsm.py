@@ -138,3 +138,41 @@ def test_state_changes_per_epoch_are_bounded():
             changes += new != word
             word = new
         assert changes <= 8
+
+
+def test_wave_group_effect_is_its_first_two_lanes():
+    """Grouping lanes of one hook instruction that hit the same word: the
+    lanes share kind, block, wave and both epochs and differ in thread, and
+    after any reachable state every lane past the first two distinct ones
+    leaves the word unchanged.  So an owner lane applying itself and one
+    other member is the whole group's effect (in the order owner, other,
+    rest, an order the hook may see anyway)."""
+    rng = np.random.default_rng(13)
+    tried = 0
+    for sp in (hr.HR_GLOBAL, hr.HR_LDS):
+        for _ in range(1500):
+            # a reachable word: a happens-before-consistent walk of one launch
+            word, bcs, wcs = 0, [0, 0, 0], {}
+            for _ in range(int(rng.integers(0, 10))):
+                b = int(rng.integers(0, 3)) if sp == hr.HR_GLOBAL else 0
+                t = int(rng.integers(0, 192))
+                if rng.random() < 0.2:
+                    bcs[b] += 1
+                w = (b, t >> 6, bcs[b])
+                if rng.random() < 0.2:
+                    wcs[w] = wcs.get(w, 0) + 1
+                word = hr.fsm_step(sp, word, int(rng.integers(0, 3)), 1, b, t, bcs[b],
+                                   wcs.get(w, 0))
+            # one hook instruction of one wave at the current epochs
+            kind = int(rng.integers(0, 3))
+            b = int(rng.integers(0, 3)) if sp == hr.HR_GLOBAL else 0
+            wave = int(rng.integers(0, 3))
+            bc = bcs[b] + int(rng.integers(0, 2))
+            wc = wcs.get((b, wave, bcs[b]), 0) if bc == bcs[b] else 0
+            lanes = rng.choice(64, size=int(rng.integers(3, 7)), replace=False)
+            seq = [word]
+            for ln in lanes:
+                seq.append(hr.fsm_step(sp, seq[-1], kind, 1, b, 64 * wave + int(ln), bc, wc))
+            assert all(x == seq[2] for x in seq[3:]), (sp, hex(word), kind, lanes)
+            tried += 1
+    assert tried == 3000

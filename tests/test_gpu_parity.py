@@ -60,6 +60,7 @@ PROGRAMS = [
     (5, 2, 33, 130, 5, 3, 300, 100, 0.5),
     (6, 4, 3, 1024, 3, 1, 1024, 2048, 0.2),
     (7, 1, 200, 64, 8, 2, 8192, 64, 0.3),
+    (8, 2, 6, 256, 4, 3, 2, 4, 0.2),           # heavy same-word contention
 ]
 
 
@@ -95,6 +96,9 @@ def test_program_flagged_set(env, cfg):
     # schedule but not the verdict
     got2, _ = run_program(torch, hr, prog, block_perm_seed=seed)
     assert got2 == want
+    # wave grouping of same-word lanes changes the number of atomics only
+    got3, st3 = run_program(torch, hr, prog, ctx_kwargs={"wave_grouping": True})
+    assert st3 == 0 and got3 == want
 
 
 def test_program_race_free_variants(env):
@@ -163,17 +167,18 @@ def test_jacobi_race_free_output_matches_plain(env):
 
 
 # ------------------------------------------------------- label propagation
+@pytest.mark.parametrize("grouping", [False, True])
 @pytest.mark.parametrize("scale,edges,p,tpb", [(10, 8 * 1024, 0.01, 256), (12, 8 * 4096, 0.02, 256),
                                                (13, 8 * 8192, 0.01, 128), (9, 4096, 0.05, 1000)])
-def test_labelprop_flagged_set(env, scale, edges, p, tpb):
+def test_labelprop_flagged_set(env, scale, edges, p, tpb, grouping):
     torch, hr = env
     rp, col, mask = si.labelprop_graph(scale, edges, si.master_seed(2) + scale, p)
     n = rp.shape[0] - 1
-    say("labelprop", scale, edges, p, tpb)
+    say("labelprop", scale, edges, p, tpb, "grouping", grouping)
     label = torch.arange(n, dtype=torch.int32, device="cuda")
     rp_d, col_d = torch.from_numpy(rp).cuda(), torch.from_numpy(col).cuda()
     mask_d = torch.from_numpy(mask).cuda()
-    with hr.Context(count_checks=True) as ctx:
+    with hr.Context(count_checks=True, wave_grouping=grouping) as ctx:
         r_lab = ctx.shadow_alloc(label)
         r_rp, r_col = ctx.shadow_alloc(rp_d), ctx.shadow_alloc(col_d)
         for L in range(3):

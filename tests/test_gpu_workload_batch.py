@@ -87,6 +87,14 @@ def test_batch_small_matches_serial_and_oracle(env):
             n = ctx.check_count()
     expect = sum(jobs.check_count_arrays(s, a) for s, a in zip(specs, arrays))
     assert n == expect                            # the last run (reset clears the counter)
+    say("batch with wave grouping")
+    with hr.Context(wave_grouping=True) as ctx:
+        with hr.Batch(ctx, [j.inst for j in js]) as b:
+            b.run(spin_limit=1 << 16)
+            per = b.split(ctx.flagged())
+            assert ctx.status == 0
+    for i, (w, p) in enumerate(zip(want, per)):
+        assert p == w, (i, specs[i])
 
 
 def test_batch_full_manifest(env):
