@@ -51,6 +51,9 @@ typedef enum {
     /* A batched work item waited too long for the previous phase of its job
      * and was skipped; that job's results are incomplete. */
     HR_W_STALLED = 8,
+    /* Some call site reached hr_config.site_limit: its further race records
+     * were dropped, so the reported set may be incomplete. */
+    HR_W_REPORT_LIMITED = 16,
     HR_E_INVAL = -1,   /* bad argument */
     HR_E_NOMEM = -2,   /* allocation failed or shadow budget exceeded */
     HR_E_HIP = -3,     /* a HIP runtime call failed */
@@ -68,7 +71,16 @@ typedef struct {
     uint32_t wc_bits;        /* wave-clock width 1..6; 0: 6 */
     uint32_t flags;          /* HR_CFG_* bits */
     uint64_t shadow_budget;  /* cap on shadow bytes of this context; 0: none */
+    uint32_t site_limit;     /* race records kept per call site (site id mod
+                                HR_SITES) between two hr_reset calls; 0: no
+                                limit.  Past it, records of that site are
+                                dropped and hr_report warns
+                                HR_W_REPORT_LIMITED.  The batched and serving
+                                executors do not apply it. */
+    uint32_t pad;
 } hr_config;
+
+#define HR_SITES 256   /* call-site counters of the report limit */
 
 /* Count every checked access in a device counter (read by hr_check_count). */
 #define HR_CFG_COUNT_CHECKS 1u
@@ -78,18 +90,53 @@ typedef struct {
  * drops under same-word contention).  Off by default. */
 #define HR_CFG_WAVE_GROUPING 2u
 
-/* One flagged location, 32 bytes.  The key is (space, region, block if LDS,
- * index); the remaining fields describe the access that completed the race. */
+/* One flagged location, 48 bytes.  The key is (space, region, block if LDS,
+ * index).  The other fields describe how the race was found: `before` and
+ * `with` are two shadow summaries (global- or LDS-word layout, by space;
+ * decode them with hr_describe) whose accesses include a racing pair.
+ * `before` is the word the race state replaced.  `with` is the completing
+ * access alone (a single-thread summary holding its launch, block, thread,
+ * block clock, wave clock and class) or, for a record made while folding
+ * back an overwritten update (HR_RACE_FOLD), the summary folded back. */
 typedef struct {
     uint8_t space;          /* hr_space */
-    uint8_t pad[3];
+    uint8_t kind;           /* hr_kind of the access whose hook found the race */
+    uint16_t site;          /* its call-site id (0: none given) */
     uint32_t region;        /* region id (global) or LDS array id */
-    uint32_t block;         /* owning block (LDS) / accessing block (global) */
+    uint32_t block;         /* owning block (LDS) / block of that access (global) */
     uint32_t launch;        /* launch sequence number within the job */
     uint64_t index;         /* element index within the region */
-    uint32_t tid;           /* thread index within its block */
-    uint32_t state_before;  /* low 32 bits of the shadow word before the race */
+    uint64_t before;        /* summary replaced by the race state */
+    uint64_t with;          /* summary it met (see above) */
+    uint32_t tid;           /* thread of that access within its block */
+    uint32_t flags;         /* HR_RACE_* bits */
 } hr_race;
+
+#define HR_RACE_FOLD 1u      /* found while folding back an overwritten summary */
+#define HR_RACE_SCANNED 2u   /* recovered by the ring-overflow scan: only the key is valid */
+
+/* A shadow summary decoded (hr_describe).  Fields a state does not keep are
+ * UINT32_MAX; classes are 1 (reads), 2 (atomics), 3 (a write, or reads and
+ * atomics), 0 when not kept. */
+typedef enum {
+    HR_S_INIT = 0,          /* never accessed */
+    HR_S_RACE = 1,          /* race state */
+    HR_S_BLOCKS = 2,        /* accesses from >= 2 blocks, all of class_block */
+    HR_S_WAVES = 3,         /* one block; >= 2 waves in its latest block epoch */
+    HR_S_THREADS = 4,       /* one wave; >= 2 threads in its latest wave epoch */
+    HR_S_THREAD = 5         /* one thread in the latest wave epoch */
+} hr_summary_state;
+
+typedef struct {
+    uint32_t state;         /* hr_summary_state */
+    uint32_t class_launch;  /* class of the (single) block's accesses this launch */
+    uint32_t class_block;   /* class in the latest block epoch (HR_S_BLOCKS: of all) */
+    uint32_t class_wave;    /* class in the latest wave epoch */
+    uint32_t launch;        /* launch epoch (global words; 9 bits) */
+    uint32_t block, bc;     /* the block and its block clock */
+    uint32_t wave, wc;      /* the wave and its wave clock */
+    uint32_t thread;        /* the thread (HR_S_THREAD) */
+} hr_summary;
 
 /* Create a context whose default stream is `stream`.  Allocates the report
  * ring and counters on the current HIP device.  cfg may be NULL (defaults).
@@ -156,6 +203,11 @@ hr_status hr_fsm_step(uint32_t space, uint64_t old, uint32_t kind, uint32_t laun
  * exchange overwrote a concurrent update; for verification only. */
 hr_status hr_fsm_merge(uint64_t x, uint64_t y, uint64_t* out);
 
+/* Decode a shadow summary word of `space` (for instance the `before` and
+ * `with` fields of a race record).  Errors: HR_E_INVAL (null out, unknown
+ * space or state tag). */
+hr_status hr_describe(uint32_t space, uint64_t word, hr_summary* out);
+
 /* ----------------------------------------------------------------------
  * Instrumented workloads.  Each *_check entry launches one instrumented
  * kernel on `stream` (the caller calls hr_kernel_end after it); each *_plain
@@ -163,6 +215,32 @@ hr_status hr_fsm_merge(uint64_t x, uint64_t y, uint64_t* out);
  * pointers; region ids come from hr_shadow_alloc on those buffers.
  * Errors: HR_E_INVAL (bad sizes, regions too small), HR_E_HIP.
  * ---------------------------------------------------------------------- */
+
+/* Call-site ids carried by the workloads' race records. */
+enum {
+    /* reduction */
+    HR_SITE_REDUCE_LOAD = 1,        /* global read of the input */
+    HR_SITE_REDUCE_STAGE = 2,       /* LDS write of the loaded value */
+    HR_SITE_REDUCE_LEFT = 3,        /* LDS read of a[t] in a halving step */
+    HR_SITE_REDUCE_RIGHT = 4,       /* LDS read of a[t + h] */
+    HR_SITE_REDUCE_SUM = 5,         /* LDS write of a[t] */
+    HR_SITE_REDUCE_TOTAL = 6,       /* LDS read of a[0] after the steps */
+    HR_SITE_REDUCE_OUT = 7,         /* global write of the output */
+    /* stencil */
+    HR_SITE_JACOBI_CENTRE = 16,     /* global read of the thread's own cell */
+    HR_SITE_JACOBI_HALO = 17,       /* global read of a halo cell */
+    HR_SITE_JACOBI_STAGE = 18,      /* LDS write into the tile */
+    HR_SITE_JACOBI_TILE = 19,       /* LDS read of the centre or a neighbour */
+    HR_SITE_JACOBI_OUT = 20,        /* global write of the thread's own cell */
+    HR_SITE_JACOBI_SEED = 21,       /* seeded global write of a neighbour's cell */
+    /* label propagation */
+    HR_SITE_LP_OWN = 32,            /* atomic load of the vertex's own label */
+    HR_SITE_LP_CSR = 33,            /* read of row_ptr or col (when monitored) */
+    HR_SITE_LP_MIN = 34,            /* atomic min into a neighbour's label */
+    HR_SITE_LP_SEED_READ = 35,      /* seeded plain read of a neighbour's label */
+    HR_SITE_LP_SEED_WRITE = 36      /* seeded plain write of a neighbour's label */
+    /* access programs: site = phase + 1 */
+};
 
 /* LDS tree reduction: each of `blocks` blocks of `threads` threads (a
  * multiple of 64, <= 1024) sums in_dev[b*n .. b*n+n) (int32; n a power of

@@ -336,6 +336,7 @@ extern "C" hr_status hr_batch_run(hr_batch b, const hr_batch_tuning* tune, void*
         hr_fill32(b->d_cursor, 1, s) != hipSuccess)
         return HR_E_HIP;
     hr_env e = hr_make_env(c);
+    e.site_limit = 0;   // site ids are per job; the limit does not apply to a batch
     if (t.variant == 0)
         HR_LAUNCH(k_batch_wide, dim3(workers), dim3(1024), b->lds_bytes, s, e, b->d_inst,
                   b->d_items[t.order], b->n_items, b->d_cursor, b->d_done, spin);

@@ -22,16 +22,16 @@ struct hr_gref {
 // Global hook at a lane-affine site (GROUP false) or a data-dependent one.
 template <int KIND, bool CHECK, bool GROUP = false>
 __device__ __forceinline__ void hr_g(const hr_env& e, const hr_thread& t, const hr_gref& g,
-                                     uint64_t index)
+                                     uint64_t index, uint32_t site)
 {
-    if constexpr (CHECK) hr_check<KIND, GROUP>(e, t, g.shadow, g.n, g.id, index);
+    if constexpr (CHECK) hr_check<KIND, GROUP>(e, t, g.shadow, g.n, g.id, index, site);
 }
 
 template <int KIND, bool CHECK>
 __device__ __forceinline__ void hr_l(const hr_env& e, const hr_thread& t, uint32_t* sh,
-                                     uint32_t n, uint32_t id, uint32_t index)
+                                     uint32_t n, uint32_t id, uint32_t index, uint32_t site)
 {
-    if constexpr (CHECK) hr_access_lds<KIND>(e, t, sh, n, id, index);
+    if constexpr (CHECK) hr_access_lds<KIND>(e, t, sh, n, id, index, site);
 }
 
 template <bool CHECK>
@@ -65,8 +65,8 @@ __device__ void reduce_body(const hr_env& e, const hr_gref& gin, const hr_gref& 
     if (act) {
         for (uint32_t j = t; j < n; j += T) {
             s[j] = in[base + j];
-            hr_g<0, CHECK>(e, th, gin, base + j);
-            hr_l<1, CHECK>(e, th, sh, n, lds_id, j);
+            hr_g<0, CHECK>(e, th, gin, base + j, HR_SITE_REDUCE_LOAD);
+            hr_l<1, CHECK>(e, th, sh, n, lds_id, j, HR_SITE_REDUCE_STAGE);
         }
     }
     if (n != 2 * T) hr_bar<CHECK>(e, th);
@@ -75,19 +75,19 @@ __device__ void reduce_body(const hr_env& e, const hr_gref& gin, const hr_gref& 
         const uint32_t h = n >> (step + 1);
         if (act && t < h) {
             const int32_t x = s[t];
-            hr_l<0, CHECK>(e, th, sh, n, lds_id, t);
+            hr_l<0, CHECK>(e, th, sh, n, lds_id, t, HR_SITE_REDUCE_LEFT);
             const int32_t y = s[t + h];
-            hr_l<0, CHECK>(e, th, sh, n, lds_id, t + h);
+            hr_l<0, CHECK>(e, th, sh, n, lds_id, t + h, HR_SITE_REDUCE_RIGHT);
             s[t] = x + y;
-            hr_l<1, CHECK>(e, th, sh, n, lds_id, t);
+            hr_l<1, CHECK>(e, th, sh, n, lds_id, t, HR_SITE_REDUCE_SUM);
         }
         if (step != drop) hr_bar<CHECK>(e, th);
     }
     if (act) {
         const int32_t r = s[0];
-        hr_l<0, CHECK>(e, th, sh, n, lds_id, 0);
+        hr_l<0, CHECK>(e, th, sh, n, lds_id, 0, HR_SITE_REDUCE_TOTAL);
         out[(size_t)lb * T + t] = r;
-        hr_g<1, CHECK>(e, th, gout, (size_t)lb * T + t);
+        hr_g<1, CHECK>(e, th, gout, (size_t)lb * T + t, HR_SITE_REDUCE_OUT);
     }
 }
 
@@ -120,53 +120,53 @@ __device__ void jacobi_body(const hr_env& e, const hr_gref& gold, const hr_gref&
     const uint32_t cl = (ty + 1) * TL + tx + 1;
     if (inside) {
         tile[cl] = uo[g];
-        hr_g<0, CHECK>(e, th, gold, g);
-        hr_l<1, CHECK>(e, th, tsh, TW, lds_id, cl);
+        hr_g<0, CHECK>(e, th, gold, g, HR_SITE_JACOBI_CENTRE);
+        hr_l<1, CHECK>(e, th, tsh, TW, lds_id, cl, HR_SITE_JACOBI_STAGE);
         if (ty == 0 && gy > 0) {
             tile[tx + 1] = uo[g - nx];
-            hr_g<0, CHECK>(e, th, gold, g - nx);
-            hr_l<1, CHECK>(e, th, tsh, TW, lds_id, tx + 1);
+            hr_g<0, CHECK>(e, th, gold, g - nx, HR_SITE_JACOBI_HALO);
+            hr_l<1, CHECK>(e, th, tsh, TW, lds_id, tx + 1, HR_SITE_JACOBI_STAGE);
         }
         if (ty == 15 && gy + 1 < ny) {
             tile[17 * TL + tx + 1] = uo[g + nx];
-            hr_g<0, CHECK>(e, th, gold, g + nx);
-            hr_l<1, CHECK>(e, th, tsh, TW, lds_id, 17 * TL + tx + 1);
+            hr_g<0, CHECK>(e, th, gold, g + nx, HR_SITE_JACOBI_HALO);
+            hr_l<1, CHECK>(e, th, tsh, TW, lds_id, 17 * TL + tx + 1, HR_SITE_JACOBI_STAGE);
         }
         if (tx == 0 && gx > 0) {
             tile[(ty + 1) * TL] = uo[g - 1];
-            hr_g<0, CHECK>(e, th, gold, g - 1);
-            hr_l<1, CHECK>(e, th, tsh, TW, lds_id, (ty + 1) * TL);
+            hr_g<0, CHECK>(e, th, gold, g - 1, HR_SITE_JACOBI_HALO);
+            hr_l<1, CHECK>(e, th, tsh, TW, lds_id, (ty + 1) * TL, HR_SITE_JACOBI_STAGE);
         }
         if (tx == 15 && gx + 1 < nx) {
             tile[(ty + 1) * TL + 17] = uo[g + 1];
-            hr_g<0, CHECK>(e, th, gold, g + 1);
-            hr_l<1, CHECK>(e, th, tsh, TW, lds_id, (ty + 1) * TL + 17);
+            hr_g<0, CHECK>(e, th, gold, g + 1, HR_SITE_JACOBI_HALO);
+            hr_l<1, CHECK>(e, th, tsh, TW, lds_id, (ty + 1) * TL + 17, HR_SITE_JACOBI_STAGE);
         }
     }
     hr_bar<CHECK>(e, th);
     if (inside) {
         const float c = tile[cl];
-        hr_l<0, CHECK>(e, th, tsh, TW, lds_id, cl);
+        hr_l<0, CHECK>(e, th, tsh, TW, lds_id, cl, HR_SITE_JACOBI_TILE);
         float vn = c, vs = c, vw = c, ve = c;
         if (gy > 0) {
             vn = tile[cl - TL];
-            hr_l<0, CHECK>(e, th, tsh, TW, lds_id, cl - TL);
+            hr_l<0, CHECK>(e, th, tsh, TW, lds_id, cl - TL, HR_SITE_JACOBI_TILE);
         }
         if (gy + 1 < ny) {
             vs = tile[cl + TL];
-            hr_l<0, CHECK>(e, th, tsh, TW, lds_id, cl + TL);
+            hr_l<0, CHECK>(e, th, tsh, TW, lds_id, cl + TL, HR_SITE_JACOBI_TILE);
         }
         if (gx > 0) {
             vw = tile[cl - 1];
-            hr_l<0, CHECK>(e, th, tsh, TW, lds_id, cl - 1);
+            hr_l<0, CHECK>(e, th, tsh, TW, lds_id, cl - 1, HR_SITE_JACOBI_TILE);
         }
         if (gx + 1 < nx) {
             ve = tile[cl + 1];
-            hr_l<0, CHECK>(e, th, tsh, TW, lds_id, cl + 1);
+            hr_l<0, CHECK>(e, th, tsh, TW, lds_id, cl + 1, HR_SITE_JACOBI_TILE);
         }
         const float r = 0.2f * (c + vn + vs + vw + ve);
         un[g] = r;
-        hr_g<1, CHECK>(e, th, gnew, g);
+        hr_g<1, CHECK>(e, th, gnew, g, HR_SITE_JACOBI_OUT);
         if (seeds) {
             const int32_t sd = seeds[lb];
             if (sd >= 0) {
@@ -178,7 +178,7 @@ __device__ void jacobi_body(const hr_env& e, const hr_gref& gold, const hr_gref&
                 else if (side == 3 && tx == 15 && ty == off && gx + 1 < nx) tgt = (int64_t)g + 1;
                 if (tgt >= 0) {
                     un[tgt] = r;
-                    hr_g<1, CHECK>(e, th, gnew, (uint64_t)tgt);
+                    hr_g<1, CHECK>(e, th, gnew, (uint64_t)tgt, HR_SITE_JACOBI_SEED);
                 }
             }
         }
@@ -202,24 +202,24 @@ __device__ void labelprop_body(const hr_env& e, const hr_gref& glab, const hr_gr
     hr_thread th{};
     if constexpr (CHECK) th = hr_thread_make(e, lb, t);
     const int32_t l = __hip_atomic_load(label + v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    hr_g<2, CHECK>(e, th, glab, v);
+    hr_g<2, CHECK>(e, th, glab, v, HR_SITE_LP_OWN);
     const int32_t e0 = rp[v], e1 = rp[v + 1];
     if (CHECK && grp.shadow) {
-        hr_g<0, CHECK>(e, th, grp, v);
-        hr_g<0, CHECK>(e, th, grp, v + 1);
+        hr_g<0, CHECK>(e, th, grp, v, HR_SITE_LP_CSR);
+        hr_g<0, CHECK>(e, th, grp, v + 1, HR_SITE_LP_CSR);
     }
     for (int32_t k = e0; k < e1; ++k) {
         const uint32_t u = (uint32_t)col[k];
-        if (CHECK && gcol.shadow) hr_g<0, CHECK>(e, th, gcol, (uint64_t)k);
+        if (CHECK && gcol.shadow) hr_g<0, CHECK>(e, th, gcol, (uint64_t)k, HR_SITE_LP_CSR);
         if (u >= n) continue;
         if (mask[k]) {
             const int32_t r = label[u];
-            hr_g<0, CHECK, true>(e, th, glab, u);
+            hr_g<0, CHECK, true>(e, th, glab, u, HR_SITE_LP_SEED_READ);
             label[u] = r < l ? r : l;
-            hr_g<1, CHECK, true>(e, th, glab, u);
+            hr_g<1, CHECK, true>(e, th, glab, u, HR_SITE_LP_SEED_WRITE);
         } else {
             atomicMin(label + u, l);
-            hr_g<2, CHECK, true>(e, th, glab, u);
+            hr_g<2, CHECK, true>(e, th, glab, u, HR_SITE_LP_MIN);
         }
     }
 }

@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "hr.h"
 #include "hr_fsm.h"
 
 #define HR_MAX_REGIONS 16   // regions addressable by kernel arguments
@@ -24,25 +25,30 @@
 #define HR_DEVF_CLOCK 1u
 #define HR_DEVF_RANGE 4u
 #define HR_DEVF_STALL 8u    // a batched item gave up waiting for its phase
+#define HR_DEVF_LIMIT 16u   // a call site reached its record limit
 
 // Counter words.
 #define HR_CTR_HEAD 0     // ring append index
 #define HR_CTR_FLAGS 1    // warning bits
-#define HR_CTR_WORDS 2
+#define HR_CTR_SITES 2    // HR_SITES per-site record counters
+#define HR_CTR_WORDS (HR_CTR_SITES + HR_SITES)
 #define HR_COUNT_SLOTS 256   // checked-access counters, spread by block
 
 // Record appended on a transition into the race state (matches hr_race).
 struct hr_race_rec {
     uint8_t space;
-    uint8_t pad[3];
+    uint8_t kind;
+    uint16_t site;
     uint32_t region;
     uint32_t block;
     uint32_t launch;
     uint64_t index;
+    uint64_t before;
+    uint64_t with;
     uint32_t tid;
-    uint32_t state_before;
+    uint32_t flags;
 };
-static_assert(sizeof(hr_race_rec) == 32, "race record is 32 bytes");
+static_assert(sizeof(hr_race_rec) == 48, "race record is 48 bytes");
 
 // What hooks and barriers need besides the shadow of the accessed region:
 // the report ring, counters, the launch epoch and the clock limits.
@@ -56,6 +62,7 @@ struct hr_env {
     uint32_t bc_max;                    // last valid block-clock value
     uint32_t wc_max;                    // last valid wave-clock value
     uint32_t group;                     // wave grouping at data-dependent hook sites
+    uint32_t site_limit;                // race records per call site; 0: no limit
 };
 
 // Plain-old-data block handed to instrumented kernels by value.
@@ -108,22 +115,36 @@ __device__ __forceinline__ void hr_count(const hr_env& e, const hr_thread& t)
     }
 }
 
+// Append a race record: `before` and `with` are the two summaries whose
+// accesses race (see hr_race).
 __device__ __forceinline__ void hr_ring_push(const hr_env& e, uint32_t space, uint32_t region,
                                              uint32_t block, uint64_t index, uint32_t tid,
-                                             uint32_t before)
+                                             uint32_t kind, uint32_t site, uint64_t before,
+                                             uint64_t with, uint32_t flags)
 {
+    if (e.site_limit) {
+        const uint32_t n = __hip_atomic_fetch_add(e.ctr + HR_CTR_SITES + (site & (HR_SITES - 1)),
+                                                  1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (n >= e.site_limit) {
+            hr_set_flag(e, HR_DEVF_LIMIT);
+            return;
+        }
+    }
     const uint32_t slot = __hip_atomic_fetch_add(e.ctr + HR_CTR_HEAD, 1u, __ATOMIC_RELAXED,
                                                  __HIP_MEMORY_SCOPE_AGENT);
     if (slot < e.ring_cap) {
         hr_race_rec r;
         r.space = (uint8_t)space;
-        r.pad[0] = r.pad[1] = r.pad[2] = 0;
+        r.kind = (uint8_t)kind;
+        r.site = (uint16_t)site;
         r.region = region;
         r.block = block;
         r.launch = e.launch_seq;
         r.index = index;
+        r.before = before;
+        r.with = with;
         r.tid = tid;
-        r.state_before = before;
+        r.flags = flags;
         e.ring[slot] = r;
     }
 }
@@ -229,7 +250,8 @@ __device__ __forceinline__ uint32_t hr_group(uint64_t word_addr, bool* member)
 // them back.
 template <int KIND, bool GROUP = false>
 __device__ __forceinline__ void hr_check(const hr_env& e, const hr_thread& t, uint64_t* shadow,
-                                         uint64_t n, uint32_t region, uint64_t index)
+                                         uint64_t n, uint32_t region, uint64_t index,
+                                         uint32_t site = 0)
 {
     if (!t.enabled) return;
     hr_count(e, t);
@@ -247,32 +269,40 @@ __device__ __forceinline__ void hr_check(const hr_env& e, const hr_thread& t, ui
     }
     const uint64_t old = __hip_atomic_load(sp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     uint64_t nw = hr::g::step(old, t.gid, k);
-    if (other != HR_NO_LANE)
-        nw = hr::g::step(nw, hr::g::pack_id(e.launch, t.block, t.thread - __lane_id() + other,
-                                            t.bc, t.wc), k);
+    uint64_t other_id = 0;
+    if (other != HR_NO_LANE) {
+        other_id = hr::g::pack_id(e.launch, t.block, t.thread - __lane_id() + other, t.bc, t.wc);
+        nw = hr::g::step(nw, other_id, k);
+    }
     if (nw == old) return;
     const uint64_t r = __hip_atomic_exchange(sp, nw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (nw == hr::T_RACE) {
-        if (r != hr::T_RACE) hr_ring_push(e, 0, region, t.block, index, t.thread, (uint32_t)old);
+        if (r != hr::T_RACE) {
+            // the completing access alone (with its group partner, if any)
+            uint64_t with = hr::g::step(hr::T_INIT, t.gid, k);
+            if (other != HR_NO_LANE) with = hr::g::step(with, other_id, k);
+            hr_ring_push(e, 0, region, t.block, index, t.thread, KIND, site, old, with, 0);
+        }
         return;
     }
     if (r != old) {
         const uint64_t before = hr_fold(sp, nw, r);
         if (before != HR_NO_REPORT)
-            hr_ring_push(e, 0, region, t.block, index, t.thread, (uint32_t)before);
+            hr_ring_push(e, 0, region, t.block, index, t.thread, KIND, site, before, r,
+                         HR_RACE_FOLD);
     }
 }
 
 // The same check for a region named by its kernel-argument slot.
 template <int KIND>
 __device__ __forceinline__ void hr_access(const hr_kargs& a, const hr_thread& t, uint32_t region,
-                                          uint64_t index)
+                                          uint64_t index, uint32_t site = 0)
 {
     if (region >= HR_MAX_REGIONS) {
         if (t.enabled) hr_set_flag(a.env, HR_DEVF_RANGE);
         return;
     }
-    hr_check<KIND, true>(a.env, t, a.shadow[region], a.n_elems[region], region, index);
+    hr_check<KIND, true>(a.env, t, a.shadow[region], a.n_elems[region], region, index, site);
 }
 
 // Check one access to word `index` of a block's LDS array `array_id`, whose
@@ -281,7 +311,8 @@ __device__ __forceinline__ void hr_access(const hr_kargs& a, const hr_thread& t,
 // compare-and-swap loop.
 template <int KIND>
 __device__ __forceinline__ void hr_access_lds(const hr_env& e, const hr_thread& t, uint32_t* sh,
-                                              uint32_t n_words, uint32_t array_id, uint32_t index)
+                                              uint32_t n_words, uint32_t array_id, uint32_t index,
+                                              uint32_t site = 0)
 {
     if (!t.enabled) return;
     hr_count(e, t);
@@ -298,7 +329,9 @@ __device__ __forceinline__ void hr_access_lds(const hr_env& e, const hr_thread& 
         uint32_t seen = old;
         if (__hip_atomic_compare_exchange_strong(sp, &seen, nw, __ATOMIC_RELAXED,
                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) {
-            if (nw == hr::T_RACE) hr_ring_push(e, 1, array_id, t.block, index, t.thread, old);
+            if (nw == hr::T_RACE)
+                hr_ring_push(e, 1, array_id, t.block, index, t.thread, KIND, site, old,
+                             hr::l::step(hr::T_INIT, t.lid, k), 0);
             return;
         }
         old = seen;
@@ -308,20 +341,21 @@ __device__ __forceinline__ void hr_access_lds(const hr_env& e, const hr_thread& 
 // Runtime-kind forms (used where the kind is data, as in the interpreter).
 __device__ __forceinline__ void hr_check_k(const hr_env& e, const hr_thread& t, uint32_t kind,
                                            uint64_t* shadow, uint64_t n, uint32_t region,
-                                           uint64_t index)
+                                           uint64_t index, uint32_t site = 0)
 {
-    if (kind == 0) hr_check<0, true>(e, t, shadow, n, region, index);
-    else if (kind == 1) hr_check<1, true>(e, t, shadow, n, region, index);
-    else hr_check<2, true>(e, t, shadow, n, region, index);
+    if (kind == 0) hr_check<0, true>(e, t, shadow, n, region, index, site);
+    else if (kind == 1) hr_check<1, true>(e, t, shadow, n, region, index, site);
+    else hr_check<2, true>(e, t, shadow, n, region, index, site);
 }
 
 __device__ __forceinline__ void hr_access_lds_k(const hr_env& e, const hr_thread& t,
                                                 uint32_t kind, uint32_t* sh, uint32_t n_words,
-                                                uint32_t array_id, uint32_t index)
+                                                uint32_t array_id, uint32_t index,
+                                                uint32_t site = 0)
 {
-    if (kind == 0) hr_access_lds<0>(e, t, sh, n_words, array_id, index);
-    else if (kind == 1) hr_access_lds<1>(e, t, sh, n_words, array_id, index);
-    else hr_access_lds<2>(e, t, sh, n_words, array_id, index);
+    if (kind == 0) hr_access_lds<0>(e, t, sh, n_words, array_id, index, site);
+    else if (kind == 1) hr_access_lds<1>(e, t, sh, n_words, array_id, index, site);
+    else hr_access_lds<2>(e, t, sh, n_words, array_id, index, site);
 }
 
 __device__ __forceinline__ void hr_retag(const hr_env& e, hr_thread& t)

@@ -88,6 +88,7 @@ hr_env hr_make_env(hr_ctx c)
     e.bc_max = (1u << c->cfg.bc_bits) - 1;
     e.wc_max = (1u << c->cfg.wc_bits) - 1;
     e.group = (c->cfg.flags & HR_CFG_WAVE_GROUPING) ? 1u : 0u;
+    e.site_limit = c->cfg.site_limit;
     return e;
 }
 
@@ -252,7 +253,7 @@ extern "C" hr_status hr_report(hr_ctx c, hr_race* out, size_t cap, size_t* n_out
     if (!c || !n_out) return HR_E_INVAL;
     hipStream_t s = hr_stream(c, stream);
     if (hipStreamSynchronize(s) != hipSuccess) return HR_E_HIP;
-    uint32_t ctr[HR_CTR_WORDS];
+    uint32_t ctr[HR_CTR_SITES];
     if (hipMemcpy(ctr, c->ctr, sizeof(ctr), hipMemcpyDeviceToHost) != hipSuccess) return HR_E_HIP;
     const uint32_t head = ctr[HR_CTR_HEAD];
     const uint32_t n_ring = std::min(head, c->cfg.ring_capacity);
@@ -264,6 +265,7 @@ extern "C" hr_status hr_report(hr_ctx c, hr_race* out, size_t cap, size_t* n_out
     if (ctr[HR_CTR_FLAGS] & HR_DEVF_CLOCK) warn |= HR_W_CLOCK_OVERFLOW;
     if (ctr[HR_CTR_FLAGS] & HR_DEVF_RANGE) warn |= HR_W_OUT_OF_RANGE;
     if (ctr[HR_CTR_FLAGS] & HR_DEVF_STALL) warn |= HR_W_STALLED;
+    if (ctr[HR_CTR_FLAGS] & HR_DEVF_LIMIT) warn |= HR_W_REPORT_LIMITED;
     if (head > c->cfg.ring_capacity) {
         // Ring overflow: race states are sticky in global shadow memory, so
         // the global part of the flagged set is recovered from it exactly.
@@ -283,7 +285,7 @@ extern "C" hr_status hr_report(hr_ctx c, hr_race* out, size_t cap, size_t* n_out
                 x.launch = 0xFFFFFFFFu;
                 x.index = i;
                 x.tid = 0xFFFFFFFFu;
-                x.state_before = 0xFFFFFFFFu;
+                x.flags = HR_RACE_SCANNED;
                 recs.push_back(x);
             }
         }
@@ -323,6 +325,56 @@ extern "C" hr_status hr_fsm_step(uint32_t space, uint64_t old, uint32_t kind, ui
     } else {
         *new_out = hr::l::step((uint32_t)old, hr::l::pack_id(thread, bc, wc), k);
     }
+    return HR_OK;
+}
+
+extern "C" hr_status hr_describe(uint32_t space, uint64_t word, hr_summary* out)
+{
+    if (!out || space > HR_LDS) return HR_E_INVAL;
+    const uint32_t none = UINT32_MAX;
+    hr_summary d = {};
+    d.launch = d.block = d.bc = d.wave = d.wc = d.thread = none;
+    uint32_t tag, cl = 0, cb, cw, bc, wc, th;
+    if (space == HR_GLOBAL) {
+        namespace g = hr::g;
+        tag = (uint32_t)(word & g::TAG_M);
+        cl = (uint32_t)(word >> g::CL_SH) & 3u;
+        cb = (uint32_t)(word >> g::CB_SH) & 3u;
+        cw = (uint32_t)(word >> g::CW_SH) & 3u;
+        bc = (uint32_t)(word >> g::BC_SH) & 255u;
+        wc = (uint32_t)(word >> g::WC_SH) & 63u;
+        th = (uint32_t)(word >> g::TH_SH) & 1023u;
+        if (tag > hr::T_ST) return HR_E_INVAL;
+        if (tag >= hr::T_MB) d.launch = (uint32_t)(word >> g::LA_SH) & 511u;
+        if (tag >= hr::T_MW) d.block = (uint32_t)(word >> g::BL_SH) & (g::BLOCK_LIMIT - 1);
+    } else {
+        namespace l = hr::l;
+        const uint32_t w = (uint32_t)word;
+        tag = w & l::TAG_M;
+        cb = (w >> l::CB_SH) & 3u;
+        cw = (w >> l::CW_SH) & 3u;
+        bc = (w >> l::BC_SH) & 255u;
+        wc = (w >> l::WC_SH) & 63u;
+        th = (w >> l::TH_SH) & 1023u;
+        if (tag > hr::T_ST || tag == hr::T_MB) return HR_E_INVAL;
+    }
+    d.state = tag;
+    if (tag >= hr::T_MW) {
+        d.class_launch = cl;
+        d.bc = bc;
+    }
+    if (tag == hr::T_MB || tag == hr::T_MW) d.class_block = cb;
+    if (tag >= hr::T_MT) {
+        d.class_block = cb;
+        d.wave = th >> 6;
+        d.wc = wc;
+    }
+    if (tag == hr::T_MW || tag == hr::T_MT) d.class_wave = tag == hr::T_MT ? cw : 0;
+    if (tag == hr::T_ST) {
+        d.class_wave = cw;
+        d.thread = th;
+    }
+    *out = d;
     return HR_OK;
 }
 

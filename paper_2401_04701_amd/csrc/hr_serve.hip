@@ -210,7 +210,8 @@ hr_status serve_continuous(hr_ctx c, const hr_instance* jobs, hr_serve_job* time
     for (uint32_t k = max_slots; k-- > 0;) free_slots.push_back(k);
     std::vector<uint32_t> active;
     std::vector<hr_race> ring(c->cfg.ring_capacity);
-    const hr_env env_base = hr_make_env(c);
+    hr_env env_base = hr_make_env(c);
+    env_base.site_limit = 0;   // site ids are per job; the limit does not apply here
     uint32_t next = 0;
     const auto t0 = clock_t_::now();
     for (;;) {
@@ -257,7 +258,7 @@ hr_status serve_continuous(hr_ctx c, const hr_instance* jobs, hr_serve_job* time
             return HR_E_HIP;
         HR_LAUNCH(k_iter, dim3((uint32_t)total), dim3(HR_WORKER_THREADS), lds, s, env_base, b.slots,
                   b.act, b.prefix, (uint32_t)active.size());
-        uint32_t ctr[HR_CTR_WORDS];
+        uint32_t ctr[HR_CTR_SITES];
         if (hipMemcpyAsync(ctr, c->ctr, sizeof(ctr), hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess)
             return HR_E_HIP;
@@ -286,7 +287,8 @@ hr_status serve_continuous(hr_ctx c, const hr_instance* jobs, hr_serve_job* time
                     r.space = HR_GLOBAL;
                     r.region = 2 * j + (i >= st.elems[0] ? 1 : 0);
                     r.index = i >= st.elems[0] ? i - st.elems[0] : i;
-                    r.block = r.launch = r.tid = r.state_before = 0xFFFFFFFFu;
+                    r.block = r.launch = r.tid = 0xFFFFFFFFu;
+                    r.flags = HR_RACE_SCANNED;
                     all.push_back(r);
                 }
             }

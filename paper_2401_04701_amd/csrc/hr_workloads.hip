@@ -106,7 +106,7 @@ __global__ __launch_bounds__(1024) void k_program(hr_kargs a, prog_map pm, uint3
                 if (kind == 0) (void)*(volatile uint32_t*)(ldata + idx);
                 else if (kind == 1) ldata[idx] = t + 1;
                 else atomicAdd(ldata + idx, 1u);
-                hr_access_lds_k(a.env, th, kind, lsh, lds_words, 0, idx);
+                hr_access_lds_k(a.env, th, kind, lsh, lds_words, 0, idx, p + 1);
             } else {
                 const uint32_t r = pm.r[reg];
                 if (r >= HR_MAX_REGIONS || idx >= a.n_elems[r]) {
@@ -117,7 +117,7 @@ __global__ __launch_bounds__(1024) void k_program(hr_kargs a, prog_map pm, uint3
                 if (kind == 0) (void)*(volatile uint32_t*)(d + idx);
                 else if (kind == 1) d[idx] = t + 1;
                 else atomicAdd(d + idx, 1u);
-                hr_check_k(a.env, th, kind, a.shadow[r], a.n_elems[r], r, idx);
+                hr_check_k(a.env, th, kind, a.shadow[r], a.n_elems[r], r, idx, p + 1);
             }
         }
         const uint8_t sc = scope[p];

@@ -19,6 +19,9 @@ HR_W_CLOCK_OVERFLOW = 1
 HR_W_RING_OVERFLOW = 2
 HR_W_OUT_OF_RANGE = 4
 HR_W_STALLED = 8
+HR_W_REPORT_LIMITED = 16
+HR_RACE_FOLD, HR_RACE_SCANNED = 1, 2
+HR_S_INIT, HR_S_RACE, HR_S_BLOCKS, HR_S_WAVES, HR_S_THREADS, HR_S_THREAD = range(6)
 HR_E_INVAL, HR_E_NOMEM, HR_E_HIP, HR_E_STATE = -1, -2, -3, -4
 HR_GLOBAL, HR_LDS = 0, 1
 HR_READ, HR_WRITE, HR_ATOMIC = 0, 1, 2
@@ -26,14 +29,27 @@ HR_CFG_COUNT_CHECKS = 1
 HR_CFG_WAVE_GROUPING = 2
 NO_REGION = 0xFFFFFFFF
 HR_PAT_REDUCE, HR_PAT_JACOBI, HR_PAT_LABELPROP = 0, 1, 2
+HR_SITES = 256
+# call-site ids of the workloads' race records (the enum in hr.h)
+SITES = {
+    "HR_SITE_REDUCE_LOAD": 1, "HR_SITE_REDUCE_STAGE": 2, "HR_SITE_REDUCE_LEFT": 3,
+    "HR_SITE_REDUCE_RIGHT": 4, "HR_SITE_REDUCE_SUM": 5, "HR_SITE_REDUCE_TOTAL": 6,
+    "HR_SITE_REDUCE_OUT": 7,
+    "HR_SITE_JACOBI_CENTRE": 16, "HR_SITE_JACOBI_HALO": 17, "HR_SITE_JACOBI_STAGE": 18,
+    "HR_SITE_JACOBI_TILE": 19, "HR_SITE_JACOBI_OUT": 20, "HR_SITE_JACOBI_SEED": 21,
+    "HR_SITE_LP_OWN": 32, "HR_SITE_LP_CSR": 33, "HR_SITE_LP_MIN": 34,
+    "HR_SITE_LP_SEED_READ": 35, "HR_SITE_LP_SEED_WRITE": 36,
+}
+globals().update(SITES)
 
 # Global shadow-word fields (see csrc/hr_fsm.h), for decoding in tests.
 T_INIT, T_RACE, T_MB, T_MW, T_MT, T_ST = 0, 1, 2, 3, 4, 5
 
-RACE_DTYPE = np.dtype([("space", np.uint8), ("pad", np.uint8, 3), ("region", np.uint32),
-                       ("block", np.uint32), ("launch", np.uint32), ("index", np.uint64),
-                       ("tid", np.uint32), ("state_before", np.uint32)])
-assert RACE_DTYPE.itemsize == 32
+RACE_DTYPE = np.dtype([("space", np.uint8), ("kind", np.uint8), ("site", np.uint16),
+                       ("region", np.uint32), ("block", np.uint32), ("launch", np.uint32),
+                       ("index", np.uint64), ("before", np.uint64), ("with", np.uint64),
+                       ("tid", np.uint32), ("flags", np.uint32)])
+assert RACE_DTYPE.itemsize == 48
 
 
 class HRError(RuntimeError):
@@ -45,7 +61,18 @@ class HRError(RuntimeError):
 class _Config(ctypes.Structure):
     _fields_ = [("ring_capacity", ctypes.c_uint32), ("bc_bits", ctypes.c_uint32),
                 ("wc_bits", ctypes.c_uint32), ("flags", ctypes.c_uint32),
-                ("shadow_budget", ctypes.c_uint64)]
+                ("shadow_budget", ctypes.c_uint64), ("site_limit", ctypes.c_uint32),
+                ("pad", ctypes.c_uint32)]
+
+
+class Summary(ctypes.Structure):
+    """hr_summary: a decoded shadow summary (UINT32_MAX: field not kept)."""
+    _fields_ = [(f, ctypes.c_uint32) for f in
+                ("state", "class_launch", "class_block", "class_wave", "launch", "block", "bc",
+                 "wave", "wc", "thread")]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class Instance(ctypes.Structure):
@@ -100,6 +127,7 @@ def _load():
         "hr_check_count": [P, P, P],
         "hr_fsm_step": [u32, u64, u32, u32, u32, u32, u32, u32, P],
         "hr_fsm_merge": [u64, u64, P],
+        "hr_describe": [u32, u64, P],
         "hr_reduce_check": [P, u32, u32, P, P, u32, u32, u32, ctypes.c_int32, P],
         "hr_reduce_plain": [P, P, u32, u32, u32, ctypes.c_int32, P],
         "hr_jacobi_check": [P, u32, u32, P, P, u32, u32, P, P],
@@ -130,6 +158,7 @@ EXPORTED = ("hr_ctx_create", "hr_ctx_destroy", "hr_shadow_alloc", "hr_shadow_fre
             "hr_dev_args", "hr_batch_create", "hr_batch_run", "hr_batch_info",
             "hr_batch_destroy", "hr_job_run", "hr_serve",
             "hr_kernel_end", "hr_reset", "hr_report", "hr_check_count", "hr_fsm_step", "hr_fsm_merge",
+            "hr_describe",
             "hr_reduce_check", "hr_reduce_plain", "hr_jacobi_check", "hr_jacobi_plain",
             "hr_labelprop_check", "hr_labelprop_plain", "hr_program_check",
             "hr_peak_copy", "hr_peak_atomic", "hr_peak_load", "hr_peak_lds")
@@ -165,6 +194,13 @@ def fsm_step(space: int, old: int, kind: int, launch: int, block: int, thread: i
     _check("hr_fsm_step", _lib.hr_fsm_step(space, old, kind, launch, block, thread, bc, wc,
                                            ctypes.byref(out)))
     return int(out.value)
+
+
+def describe(space: int, word: int) -> dict:
+    """Decode a shadow summary word (a race record's `before` or `with`)."""
+    out = Summary()
+    _check("hr_describe", _lib.hr_describe(space, word, ctypes.byref(out)))
+    return out.as_dict()
 
 
 def fsm_merge(x: int, y: int) -> int:
@@ -234,10 +270,10 @@ class Context:
     """A checking job: shadow regions, report ring, launch epochs."""
 
     def __init__(self, ring_capacity=0, bc_bits=0, wc_bits=0, count_checks=False,
-                 shadow_budget=0, wave_grouping=False, stream=None):
+                 shadow_budget=0, wave_grouping=False, site_limit=0, stream=None):
         flags = (HR_CFG_COUNT_CHECKS if count_checks else 0) | \
                 (HR_CFG_WAVE_GROUPING if wave_grouping else 0)
-        cfg = _Config(ring_capacity, bc_bits, wc_bits, flags, shadow_budget)
+        cfg = _Config(ring_capacity, bc_bits, wc_bits, flags, shadow_budget, site_limit, 0)
         self._c = ctypes.c_void_p(0)
         self._stream = _stream_ptr(stream)
         _check("hr_ctx_create", _lib.hr_ctx_create(ctypes.byref(self._c), ctypes.byref(cfg),
@@ -352,7 +388,7 @@ def _races_to_keys(recs):
 def job_run(inst: Instance, ring_capacity=0, stream=None):
     """The serial path for one job (own context and shadow, synchronous).
     Returns (flagged keys with region ids 0/1, warning bits)."""
-    cfg = _Config(ring_capacity, 0, 0, 0, 0)
+    cfg = _Config(ring_capacity, 0, 0, 0, 0, 0, 0)
     n = ctypes.c_size_t(0)
     cap = 4096
     while True:

@@ -41,3 +41,13 @@ def test_unknown_config_flags_are_rejected():
     cfg = hr._Config(0, 9, 0, 0, 0)                  # block clock wider than 8 bits
     assert hr.lib().hr_ctx_create(ctypes.byref(c), ctypes.byref(cfg), None) == hr.HR_E_INVAL
     assert not c.value
+
+
+def test_binding_site_ids_match_header():
+    import re
+    from paper_2401_04701_amd import hr
+    text = open(os.path.join(ROOT, "include", "hr.h")).read()
+    declared = {m.group(1): int(m.group(2))
+                for m in re.finditer(r"\b(HR_SITE_[A-Z_]+) = (\d+)", text)}
+    assert declared == hr.SITES
+    assert "#define HR_SITES %d" % hr.HR_SITES in text

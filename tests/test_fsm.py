@@ -176,3 +176,91 @@ def test_wave_group_effect_is_its_first_two_lanes():
             assert all(x == seq[2] for x in seq[3:]), (sp, hex(word), kind, lanes)
             tried += 1
     assert tried == 3000
+
+
+def test_describe_decodes_each_summary_state():
+    """hr_describe against summaries built by the transition function."""
+    G, L = hr.HR_GLOBAL, hr.HR_LDS
+    R, W, A = hr.HR_READ, hr.HR_WRITE, hr.HR_ATOMIC
+    none = 0xFFFFFFFF
+    st = hr.fsm_step(G, 0, R, 3, 5, 70, 2, 1)             # one thread
+    d = hr.describe(G, st)
+    assert d == {"state": hr.HR_S_THREAD, "class_launch": 1, "class_block": 1, "class_wave": 1,
+                 "launch": 3, "block": 5, "bc": 2, "wave": 1, "wc": 1, "thread": 70}
+    mt = hr.fsm_step(G, st, R, 3, 5, 71, 2, 1)            # another thread of that wave
+    d = hr.describe(G, mt)
+    assert d["state"] == hr.HR_S_THREADS and d["thread"] == none and d["wave"] == 1
+    assert (d["class_wave"], d["block"], d["bc"], d["wc"]) == (1, 5, 2, 1)
+    mw = hr.fsm_step(G, mt, A, 3, 5, 200, 2, 0)           # another wave: read + atomic race
+    assert hr.describe(G, mw)["state"] == hr.HR_S_RACE
+    mw = hr.fsm_step(G, mt, R, 3, 5, 200, 2, 0)
+    d = hr.describe(G, mw)
+    assert d["state"] == hr.HR_S_WAVES and d["wave"] == none and d["wc"] == none
+    assert (d["class_block"], d["block"], d["bc"]) == (1, 5, 2)
+    mb = hr.fsm_step(G, mw, R, 3, 6, 0, 0, 0)             # another block
+    d = hr.describe(G, mb)
+    assert d["state"] == hr.HR_S_BLOCKS and d["block"] == none and d["bc"] == none
+    assert (d["launch"], d["class_block"]) == (3, 1)
+    w2 = hr.fsm_step(G, st, W, 3, 5, 70, 3, 0)            # same thread, later block epoch
+    d = hr.describe(G, w2)
+    assert (d["state"], d["class_launch"], d["class_block"], d["bc"]) == (hr.HR_S_THREAD, 3, 3, 3)
+    assert hr.describe(G, 0)["state"] == hr.HR_S_INIT
+    # LDS words carry no launch, block or launch class
+    ls = hr.fsm_step(L, 0, W, 0, 0, 130, 4, 2)
+    d = hr.describe(L, ls)
+    assert (d["state"], d["thread"], d["bc"], d["wc"], d["wave"]) == (hr.HR_S_THREAD, 130, 4, 2, 2)
+    assert d["launch"] == none and d["block"] == none and d["class_launch"] == 0
+    lw = hr.fsm_step(L, hr.fsm_step(L, 0, R, 0, 0, 1, 0, 0), R, 0, 0, 65, 0, 0)
+    d = hr.describe(L, lw)
+    assert (d["state"], d["class_block"], d["bc"]) == (hr.HR_S_WAVES, 1, 0)
+    with pytest.raises(hr.HRError):
+        hr.describe(L, hr.fsm_step(G, mw, R, 3, 6, 0, 0, 0) & 7)   # no multi-block LDS state
+
+
+def _host_records(log, order):
+    """Race records as the hook would make them, replaying `order` on the
+    host: the word replaced and the completing access alone."""
+    from race_records import CLASS  # noqa: F401
+    words, recs = {}, []
+    for i in order:
+        r = log[i]
+        sp, rg, ix = int(r["space"]), int(r["region"]), int(r["index"])
+        b, t, L = int(r["block"]), int(r["thread"]), int(r["launch"])
+        wkey = (1, rg, b, ix, L) if sp == hr.HR_LDS else (0, rg, 0, ix)
+        old = words.get(wkey, 0)
+        args = (int(r["kind"]), L & 511, b, t, int(r["bc"]), int(r["wc"]))
+        new = hr.fsm_step(sp, old, *args)
+        words[wkey] = new
+        if (new & 7) == hr.T_RACE and (old & 7) != hr.T_RACE:
+            rec = np.zeros(1, dtype=hr.RACE_DTYPE)[0]
+            rec["space"], rec["kind"], rec["region"] = sp, int(r["kind"]), rg
+            rec["block"], rec["launch"], rec["index"], rec["tid"] = b, L, ix, t
+            rec["before"] = old
+            rec["with"] = hr.fsm_step(sp, 0, *args)
+            recs.append(rec)
+    return recs
+
+
+def test_race_record_check_accepts_host_records_and_rejects_planted():
+    """The record validity check (used on the GPU's records) accepts the
+    records a host replay makes and rejects records with a planted mistake."""
+    from race_records import by_key, record_key, record_problem
+    checked = rejected = 0
+    for s in range(25):
+        prog = si.random_program(4099 * s + 11, launches=2, blocks=2, threads=4, phases=3,
+                                 max_ops=2, global_regions=2, global_words=3, lds_words=2,
+                                 kind_p=(0.5, 0.25, 0.25), scope_p=(0.25, 0.35, 0.4),
+                                 wave_width=2)
+        log = widen(oracle.model_program(prog, 2), 2)
+        keys = by_key(log)
+        for order in random_orders(log, 3, seed=s):
+            for rec in _host_records(log, order):
+                assert record_problem(rec, keys[record_key(rec)]) is None
+                checked += 1
+                bad = rec.copy()
+                bad["tid"] = int(rec["tid"]) ^ 1            # another thread
+                rejected += record_problem(bad, keys[record_key(rec)]) is not None
+                bad = rec.copy()
+                bad["before"] = 0                           # an empty history cannot race
+                rejected += record_problem(bad, keys[record_key(rec)]) is not None
+    assert checked > 50 and rejected == 2 * checked
