@@ -278,10 +278,15 @@ __device__ __forceinline__ void hr_check(const hr_env& e, const hr_thread& t, ui
     const uint64_t r = __hip_atomic_exchange(sp, nw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (nw == hr::T_RACE) {
         if (r != hr::T_RACE) {
-            // the completing access alone (with its group partner, if any)
-            uint64_t with = hr::g::step(hr::T_INIT, t.gid, k);
-            if (other != HR_NO_LANE) with = hr::g::step(with, other_id, k);
-            hr_ring_push(e, 0, region, t.block, index, t.thread, KIND, site, old, with, 0);
+            // the completing access alone; with a group partner, the pair
+            // of lanes (if they race with each other) or their summary
+            uint64_t before = old, with = hr::g::step(hr::T_INIT, t.gid, k);
+            if (other != HR_NO_LANE) {
+                const uint64_t pair = hr::g::step(with, other_id, k);
+                if (pair == hr::T_RACE) before = hr::g::step(hr::T_INIT, other_id, k);
+                else with = pair;
+            }
+            hr_ring_push(e, 0, region, t.block, index, t.thread, KIND, site, before, with, 0);
         }
         return;
     }
