@@ -77,7 +77,13 @@ typedef struct {
                                 dropped and hr_report warns
                                 HR_W_REPORT_LIMITED.  The batched and serving
                                 executors do not apply it. */
-    uint32_t pad;
+    uint32_t wave_bits;      /* lanes of the wave-scope synchronization group,
+                                log2: 6 (0 means 6) for whole waves, 1..5 for
+                                aligned tiles of 2^wave_bits lanes; then every
+                                wave-scope barrier of the job is a tile
+                                barrier (a tiled partition's sync) and orders
+                                only its tile's lanes.  Wave grouping of hook
+                                lanes only runs with whole waves. */
 } hr_config;
 
 #define HR_SITES 256   /* call-site counters of the report limit */
@@ -134,7 +140,7 @@ typedef struct {
     uint32_t class_wave;    /* class in the latest wave epoch */
     uint32_t launch;        /* launch epoch (global words; 9 bits) */
     uint32_t block, bc;     /* the block and its block clock */
-    uint32_t wave, wc;      /* the wave and its wave clock */
+    uint32_t wave, wc;      /* the wave (or tile) and its clock */
     uint32_t thread;        /* the thread (HR_S_THREAD) */
 } hr_summary;
 
@@ -192,21 +198,25 @@ hr_status hr_check_count(hr_ctx c, uint64_t* out, void* stream);
 /* Host evaluation of the device transition function, for verification of
  * the state machine; not used by the checking path.  space: hr_space; old:
  * shadow word (low 32 bits for LDS); kind: hr_kind; the identity is the
- * access's launch, block, thread-in-block and block/wave clocks.  Writes the
- * new shadow word. */
+ * access's launch, block, thread-in-block and block/wave clocks; wave_bits
+ * as in hr_config (6: waves, s < 6: tiles of 2^s lanes; wc counts the
+ * group's barriers).  Writes the new shadow word. */
 hr_status hr_fsm_step(uint32_t space, uint64_t old, uint32_t kind, uint32_t launch,
                       uint32_t block, uint32_t thread, uint32_t bc, uint32_t wc,
-                      uint64_t* new_out);
+                      uint32_t wave_bits, uint64_t* new_out);
 
 /* Host evaluation of the device merge of two global shadow words (the summary
  * of the union of their access sets; x of the current launch), used when an
- * exchange overwrote a concurrent update; for verification only. */
-hr_status hr_fsm_merge(uint64_t x, uint64_t y, uint64_t* out);
+ * exchange overwrote a concurrent update; for verification only.  wave_bits
+ * as in hr_fsm_step. */
+hr_status hr_fsm_merge(uint64_t x, uint64_t y, uint32_t wave_bits, uint64_t* out);
 
 /* Decode a shadow summary word of `space` (for instance the `before` and
- * `with` fields of a race record).  Errors: HR_E_INVAL (null out, unknown
- * space or state tag). */
-hr_status hr_describe(uint32_t space, uint64_t word, hr_summary* out);
+ * `with` fields of a race record) of a context with the given wave_bits: the
+ * `wave` and `wc` fields then name the synchronization group (wave or tile)
+ * and its clock.  Errors: HR_E_INVAL (null out, unknown space or state tag,
+ * wave_bits outside 1..6). */
+hr_status hr_describe(uint32_t space, uint64_t word, uint32_t wave_bits, hr_summary* out);
 
 /* ----------------------------------------------------------------------
  * Instrumented workloads.  Each *_check entry launches one instrumented
@@ -287,8 +297,9 @@ hr_status hr_labelprop_plain(int32_t* label_dev, const int32_t* row_ptr_dev,
  * `phases` phases; in phase p thread t of logical block b performs the
  * operations ops_dev[op_off_dev[i] .. op_off_dev[i+1]) with
  * i = (p * blocks + b) * threads + t, then the phase ends with nothing
- * (scope 0), a wave barrier in waves whose bit is set in wave_mask_dev[p]
- * (scope 1) or a block barrier (scope 2).  Operation word: bits 0..23 index,
+ * (scope 0), a wave barrier in waves (tiles, when the context's wave_bits
+ * is below 6) whose bit is set in wave_mask_dev[p] (scope 1; groups past the
+ * 64th never synchronize) or a block barrier (scope 2).  Operation word: bits 0..23 index,
  * 24..26 program region (global: regions_host[region] is the context region;
  * LDS: array 0 of lds_words int32), 27..28 hr_kind, 29 space.  Reads load,
  * writes store, atomics add 1.  block_map_dev: NULL or a permutation giving

@@ -98,3 +98,23 @@ def labelprop_flagged(row_ptr, col, mask) -> set:
     loop_targets[col[seeded_loop]] = True
     flagged |= loop_targets & has_foreign_in
     return {(0, 0, 0, int(u)) for u in np.nonzero(flagged)[0]}
+
+
+def tile_reduce_flagged(tile: int, blocks: int, threads: int, drop: int) -> set:
+    """Sub-wave tree reduction (tiles of `tile` lanes, each over its own LDS
+    segment of n = 2 * tile words, tile barriers after each step).
+
+    The segments are disjoint and each is touched only by its tile's lanes,
+    so each tile is the scaled block reduction with n = 2 * tile: without the
+    barrier after step k (not the last), step k+1 reads seg[l + h'] (h' =
+    n >> (k+2)) in the tile epoch in which lane l + h' wrote it: words
+    [n >> (k+2), n >> (k+1)) of every segment race.  Without the last step's
+    barrier, every lane's final read of seg[0] meets lane 0's last write.
+    """
+    n = 2 * tile
+    steps = n.bit_length() - 1
+    if drop is None or drop < 0 or drop >= steps:
+        return set()
+    words = [0] if drop == steps - 1 else range(n >> (drop + 2), n >> (drop + 1))
+    return {(1, 0, b, seg * n + w) for b in range(blocks) for seg in range(threads // tile)
+            for w in words}

@@ -27,6 +27,21 @@ __device__ __forceinline__ void hr_g(const hr_env& e, const hr_thread& t, const 
     if constexpr (CHECK) hr_check<KIND, GROUP>(e, t, g.shadow, g.n, g.id, index, site);
 }
 
+// Global hook on a word loaded earlier by hr_gload (data-dependent site).
+template <bool CHECK>
+__device__ __forceinline__ uint64_t hr_gload(const hr_thread& t, const hr_gref& g, uint64_t index)
+{
+    if constexpr (CHECK) return hr_check_load(t, g.shadow, g.n, index);
+    return 0;
+}
+
+template <int KIND, bool CHECK>
+__device__ __forceinline__ void hr_gpre(const hr_env& e, const hr_thread& t, const hr_gref& g,
+                                        uint64_t index, uint32_t site, uint64_t pre)
+{
+    if constexpr (CHECK) hr_check<KIND, true, true>(e, t, g.shadow, g.n, g.id, index, site, pre);
+}
+
 template <int KIND, bool CHECK>
 __device__ __forceinline__ void hr_l(const hr_env& e, const hr_thread& t, uint32_t* sh,
                                      uint32_t n, uint32_t id, uint32_t index, uint32_t site)
@@ -208,18 +223,31 @@ __device__ void labelprop_body(const hr_env& e, const hr_gref& glab, const hr_gr
         hr_g<0, CHECK>(e, th, grp, v, HR_SITE_LP_CSR);
         hr_g<0, CHECK>(e, th, grp, v + 1, HR_SITE_LP_CSR);
     }
+    // Software pipeline over the edge list, for the long lists of hub
+    // vertices whose threads bound the launch: while edge k is checked, the
+    // column index of edge k+2 and the shadow word of edge k+1's target are
+    // already in flight.
+    uint32_t u0 = e0 < e1 ? (uint32_t)col[e0] : 0u;
+    uint32_t u1 = e0 + 1 < e1 ? (uint32_t)col[e0 + 1] : 0u;
+    uint64_t s0 = e0 < e1 ? hr_gload<CHECK>(th, glab, u0) : 0;
     for (int32_t k = e0; k < e1; ++k) {
-        const uint32_t u = (uint32_t)col[k];
+        const uint32_t u2 = k + 2 < e1 ? (uint32_t)col[k + 2] : 0u;
+        const uint64_t s1 = k + 1 < e1 ? hr_gload<CHECK>(th, glab, u1) : 0;
+        const uint32_t u = u0;
+        const uint64_t su = s0;
+        u0 = u1;
+        u1 = u2;
+        s0 = s1;
         if (CHECK && gcol.shadow) hr_g<0, CHECK>(e, th, gcol, (uint64_t)k, HR_SITE_LP_CSR);
         if (u >= n) continue;
         if (mask[k]) {
             const int32_t r = label[u];
-            hr_g<0, CHECK, true>(e, th, glab, u, HR_SITE_LP_SEED_READ);
+            hr_gpre<0, CHECK>(e, th, glab, u, HR_SITE_LP_SEED_READ, su);
             label[u] = r < l ? r : l;
             hr_g<1, CHECK, true>(e, th, glab, u, HR_SITE_LP_SEED_WRITE);
         } else {
             atomicMin(label + u, l);
-            hr_g<2, CHECK, true>(e, th, glab, u, HR_SITE_LP_MIN);
+            hr_gpre<2, CHECK>(e, th, glab, u, HR_SITE_LP_MIN, su);
         }
     }
 }

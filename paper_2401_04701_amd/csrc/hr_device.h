@@ -63,6 +63,7 @@ struct hr_env {
     uint32_t wc_max;                    // last valid wave-clock value
     uint32_t group;                     // wave grouping at data-dependent hook sites
     uint32_t site_limit;                // race records per call site; 0: no limit
+    uint32_t wave_bits;                 // 6: waves synchronize; s < 6: tiles of 2^s lanes
 };
 
 // Plain-old-data block handed to instrumented kernels by value.
@@ -157,11 +158,12 @@ __device__ __forceinline__ void hr_ring_push(const hr_env& e, uint32_t space, ui
 // by whoever created it.  Out of line and with scalar arguments only: it is
 // the rare path and must not make the caller spill its kernel arguments.
 #define HR_NO_REPORT (~0ull)
-__device__ __noinline__ uint64_t hr_fold(uint64_t* sp, uint64_t mine, uint64_t lost)
+__device__ __noinline__ uint64_t hr_fold(uint64_t* sp, uint64_t mine, uint64_t lost,
+                                         uint64_t wm)
 {
     uint64_t cur = mine;
     for (;;) {
-        const uint64_t m = hr::g::merge(cur, lost);
+        const uint64_t m = hr::g::merge(cur, lost, wm);
         if (m == cur) return HR_NO_REPORT;
         uint64_t seen = cur;
         if (__hip_atomic_compare_exchange_strong(sp, &seen, m, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
@@ -248,10 +250,16 @@ __device__ __forceinline__ uint32_t hr_group(uint64_t word_addr, bool* member)
 // returns the loaded word, it acted exactly as a successful compare-and-swap.
 // Otherwise it overwrote updates made since the load, and hr_fold merges
 // them back.
-template <int KIND, bool GROUP = false>
+//
+// PRE: the caller loaded the word earlier (hr_check_load) and passes it as
+// `pre`, to overlap that load with its other work.  Between the load and
+// this call the thread passes no barrier; if another update (the thread's
+// own included) landed in between, the exchange returns it and the fold
+// merges it back, exactly as for an update that lands inside one hook.
+template <int KIND, bool GROUP = false, bool PRE = false>
 __device__ __forceinline__ void hr_check(const hr_env& e, const hr_thread& t, uint64_t* shadow,
                                          uint64_t n, uint32_t region, uint64_t index,
-                                         uint32_t site = 0)
+                                         uint32_t site = 0, uint64_t pre = 0)
 {
     if (!t.enabled) return;
     hr_count(e, t);
@@ -261,18 +269,20 @@ __device__ __forceinline__ void hr_check(const hr_env& e, const hr_thread& t, ui
     }
     constexpr uint32_t k = KIND == 0 ? hr::CL_R : (KIND == 2 ? hr::CL_A : hr::CL_X);
     uint64_t* sp = shadow + index;
+    const uint64_t wm = hr::g::group_mask(e.wave_bits);
     uint32_t other = HR_NO_LANE;
-    if (GROUP && e.group) {
+    if (GROUP && e.group && e.wave_bits == 6) {     // lanes of one tile only when tiles are waves
         bool member;
         other = hr_group((uint64_t)sp >> 3, &member);
         if (member) return;
     }
-    const uint64_t old = __hip_atomic_load(sp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    uint64_t nw = hr::g::step(old, t.gid, k);
+    const uint64_t old =
+        PRE ? pre : __hip_atomic_load(sp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint64_t nw = hr::g::step(old, t.gid, k, wm);
     uint64_t other_id = 0;
     if (other != HR_NO_LANE) {
         other_id = hr::g::pack_id(e.launch, t.block, t.thread - __lane_id() + other, t.bc, t.wc);
-        nw = hr::g::step(nw, other_id, k);
+        nw = hr::g::step(nw, other_id, k, wm);
     }
     if (nw == old) return;
     const uint64_t r = __hip_atomic_exchange(sp, nw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -280,10 +290,10 @@ __device__ __forceinline__ void hr_check(const hr_env& e, const hr_thread& t, ui
         if (r != hr::T_RACE) {
             // the completing access alone; with a group partner, the pair
             // of lanes (if they race with each other) or their summary
-            uint64_t before = old, with = hr::g::step(hr::T_INIT, t.gid, k);
+            uint64_t before = old, with = hr::g::step(hr::T_INIT, t.gid, k, wm);
             if (other != HR_NO_LANE) {
-                const uint64_t pair = hr::g::step(with, other_id, k);
-                if (pair == hr::T_RACE) before = hr::g::step(hr::T_INIT, other_id, k);
+                const uint64_t pair = hr::g::step(with, other_id, k, wm);
+                if (pair == hr::T_RACE) before = hr::g::step(hr::T_INIT, other_id, k, wm);
                 else with = pair;
             }
             hr_ring_push(e, 0, region, t.block, index, t.thread, KIND, site, before, with, 0);
@@ -291,11 +301,21 @@ __device__ __forceinline__ void hr_check(const hr_env& e, const hr_thread& t, ui
         return;
     }
     if (r != old) {
-        const uint64_t before = hr_fold(sp, nw, r);
+        const uint64_t before = hr_fold(sp, nw, r, wm);
         if (before != HR_NO_REPORT)
             hr_ring_push(e, 0, region, t.block, index, t.thread, KIND, site, before, r,
                          HR_RACE_FOLD);
     }
+}
+
+// The early load of hr_check<..., PRE = true>: the shadow word of element
+// `index`, or 0 when the check will not use it.
+__device__ __forceinline__ uint64_t hr_check_load(const hr_thread& t, uint64_t* shadow,
+                                                  uint64_t n, uint64_t index)
+{
+    return (t.enabled && index < n)
+               ? __hip_atomic_load(shadow + index, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+               : 0;
 }
 
 // The same check for a region named by its kernel-argument slot.
@@ -329,14 +349,14 @@ __device__ __forceinline__ void hr_access_lds(const hr_env& e, const hr_thread& 
     uint32_t* sp = sh + index;
     uint32_t old = __hip_atomic_load(sp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     for (;;) {
-        const uint32_t nw = hr::l::step(old, t.lid, k);
+        const uint32_t nw = hr::l::step(old, t.lid, k, hr::l::group_mask(e.wave_bits));
         if (nw == old) return;
         uint32_t seen = old;
         if (__hip_atomic_compare_exchange_strong(sp, &seen, nw, __ATOMIC_RELAXED,
                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) {
             if (nw == hr::T_RACE)
                 hr_ring_push(e, 1, array_id, t.block, index, t.thread, KIND, site, old,
-                             hr::l::step(hr::T_INIT, t.lid, k), 0);
+                             hr::l::step(hr::T_INIT, t.lid, k), 0);   // one access: split-free
             return;
         }
         old = seen;
@@ -384,8 +404,11 @@ __device__ __forceinline__ void hr_barrier_block(const hr_env& e, hr_thread& t)
     hr_retag(e, t);
 }
 
-// Wave barrier: every lane of the wave must call it.  Lanes of a wave are
-// not otherwise ordered by the checker, whatever the hardware does.
+// Wave barrier: every lane of the wave must call it; when the context
+// synchronizes tiles of 2^s lanes (hr_config.wave_bits = s < 6), every lane
+// of the calling lane's tile, and it orders that tile only (a tiled
+// partition's sync).  Lanes are not otherwise ordered by the checker,
+// whatever the hardware does.
 __device__ __forceinline__ void hr_barrier_wave(const hr_env& e, hr_thread& t)
 {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");

@@ -56,7 +56,11 @@ HR_HD bool conflicts(uint32_t cls, uint32_t k) { return (cls | k) == CL_X; }
 // ---------------------------------------------------------------------------
 // Global-memory shadow word, 64 bits, least significant first:
 //   tag 3 | cW 2 | cB 2 | cL 2 | wc 6 | bc 8 | thread 10 | block 22 | launch 9
-// The wave of a thread is the top 4 bits of its 10-bit thread index.
+// The wave of a thread is the top 4 bits of its 10-bit thread index.  A
+// context may instead synchronize tiles of 2^s lanes (s < 6): then the
+// "wave" level of the machine is the tile (the top 10 - s bits of the thread
+// index), wave barriers are tile barriers, and wc counts them.  The split is
+// passed to step and merge as the mask of the group bits (group_mask(s)).
 // ---------------------------------------------------------------------------
 namespace g {
 constexpr uint32_t TAG_SH = 0, CW_SH = 3, CB_SH = 5, CL_SH = 7, WC_SH = 9, BC_SH = 15,
@@ -65,8 +69,13 @@ constexpr uint64_t TAG_M = 7ull << TAG_SH;
 constexpr uint64_t CW_M = 3ull << CW_SH, CB_M = 3ull << CB_SH, CL_M = 3ull << CL_SH;
 constexpr uint64_t WC_M = 63ull << WC_SH;
 constexpr uint64_t BC_M = 255ull << BC_SH;
+constexpr uint64_t TH_M = 1023ull << TH_SH;          // thread within the block
 constexpr uint64_t LANE_M = 63ull << TH_SH;           // thread within its wave
 constexpr uint64_t WAVE_M = 15ull << (TH_SH + 6);     // wave within the block
+
+// Mask of the thread bits naming the synchronization group: the wave (s =
+// 6) or a tile of 2^s lanes.
+HR_HD uint64_t group_mask(uint32_t s) { return (uint64_t)((1023u >> s) << s) << TH_SH; }
 constexpr uint64_t BL_M = ((1ull << 22) - 1) << BL_SH;
 constexpr uint64_t LA_M = 511ull << LA_SH;
 constexpr uint32_t BLOCK_LIMIT = 1u << 22;
@@ -86,8 +95,9 @@ HR_HD uint64_t mk(uint32_t tag, uint32_t cl, uint32_t cb, uint32_t cw)
            ((uint64_t)cw << CW_SH);
 }
 
-// One transition: old shadow word, identity of the access, class k of the access.
-HR_HD uint64_t step(uint64_t old, uint64_t id, uint32_t k)
+// One transition: old shadow word, identity of the access, class k of the
+// access, mask of the group bits of the thread index.
+HR_HD uint64_t step(uint64_t old, uint64_t id, uint32_t k, uint64_t wm = WAVE_M)
 {
     const uint32_t tag = (uint32_t)(old & TAG_M);
     if (tag == T_RACE) return old;
@@ -96,8 +106,9 @@ HR_HD uint64_t step(uint64_t old, uint64_t id, uint32_t k)
     const uint32_t cb = (uint32_t)(old >> CB_SH) & 3u;
     const uint32_t cw = (uint32_t)(old >> CW_SH) & 3u;
     const uint64_t race = T_RACE;
-    const uint64_t keep_t = LA_M | BL_M | BC_M | WAVE_M | LANE_M | WC_M;   // ST
-    const uint64_t keep_w = LA_M | BL_M | BC_M | WAVE_M | WC_M;            // MT
+    const uint64_t lm = TH_M & ~wm;
+    const uint64_t keep_t = LA_M | BL_M | BC_M | TH_M | WC_M;   // ST
+    const uint64_t keep_w = LA_M | BL_M | BC_M | wm | WC_M;     // MT
     const uint64_t keep_b = LA_M | BL_M | BC_M;                           // MW
     // First access of this launch: everything earlier is ordered before it.
     if (tag == T_INIT || (d & LA_M)) return mk(T_ST, k, k, k) | (id & keep_t);
@@ -110,13 +121,13 @@ HR_HD uint64_t step(uint64_t old, uint64_t id, uint32_t k)
     // Same block epoch with >= 2 waves.
     if (tag == T_MW) return conflicts(cb, k) ? race : old;
     // Another wave in the same block epoch.
-    if (d & WAVE_M) return conflicts(cb, k) ? race : (mk(T_MW, cl, k, 0) | (id & keep_b));
+    if (d & wm) return conflicts(cb, k) ? race : (mk(T_MW, cl, k, 0) | (id & keep_b));
     // Same wave, later wave epoch.
     if (d & WC_M) return mk(T_ST, cl | k, cb | k, k) | (id & keep_t);
     // Same wave epoch with >= 2 threads.
     if (tag == T_MT) return conflicts(cw, k) ? race : old;
     // Another thread of the same wave epoch.
-    if (d & LANE_M) return conflicts(cw, k) ? race : (mk(T_MT, cl, cb, k) | (id & keep_w));
+    if (d & lm) return conflicts(cw, k) ? race : (mk(T_MT, cl, cb, k) | (id & keep_w));
     // Same thread.
     return mk(T_ST, cl | k, cb | k, cw | k) | (id & keep_t);
 }
@@ -132,7 +143,7 @@ HR_HD uint64_t step(uint64_t old, uint64_t id, uint32_t k)
 // back its own block and wave barriers.  With accesses from >= 2 blocks
 // (or waves, or threads) in the same scope and epoch, the union is free of
 // races exactly when all of it has one class, R or A.
-HR_HD uint64_t merge(uint64_t x, uint64_t y)
+HR_HD uint64_t merge(uint64_t x, uint64_t y, uint64_t wm = WAVE_M)
 {
     const uint32_t tx = (uint32_t)(x & TAG_M), ty = (uint32_t)(y & TAG_M);
     const uint64_t race = T_RACE;
@@ -158,9 +169,9 @@ HR_HD uint64_t merge(uint64_t x, uint64_t y)
         return (newer & ~CL_M) | ((uint64_t)cl << CL_SH);
     }
     const uint64_t keep_b = LA_M | BL_M | BC_M;
-    const uint64_t keep_w = keep_b | WAVE_M | WC_M;
+    const uint64_t keep_w = keep_b | wm | WC_M;
     // Same block epoch with >= 2 waves.
-    if (tx == T_MW || ty == T_MW || (d & WAVE_M)) {
+    if (tx == T_MW || ty == T_MW || (d & wm)) {
         const uint32_t c = cbx | cby;
         return c == CL_X ? race : (mk(T_MW, cl, c, 0) | (x & keep_b));
     }
@@ -171,7 +182,7 @@ HR_HD uint64_t merge(uint64_t x, uint64_t y)
         return (newer & ~(CL_M | CB_M)) | ((uint64_t)cl << CL_SH) | ((uint64_t)cb << CB_SH);
     }
     // Same wave epoch with >= 2 threads.
-    if (tx == T_MT || ty == T_MT || (d & LANE_M)) {
+    if (tx == T_MT || ty == T_MT || (d & (TH_M & ~wm))) {
         const uint32_t c = cwx | cwy;
         return c == CL_X ? race : (mk(T_MT, cl, cb, c) | (x & keep_w));
     }
@@ -190,8 +201,11 @@ constexpr uint32_t TAG_SH = 0, CW_SH = 3, CB_SH = 5, WC_SH = 7, BC_SH = 13, TH_S
 constexpr uint32_t TAG_M = 7u << TAG_SH;
 constexpr uint32_t WC_M = 63u << WC_SH;
 constexpr uint32_t BC_M = 255u << BC_SH;
+constexpr uint32_t TH_M = 1023u << TH_SH;
 constexpr uint32_t LANE_M = 63u << TH_SH;
 constexpr uint32_t WAVE_M = 15u << (TH_SH + 6);
+
+HR_HD uint32_t group_mask(uint32_t s) { return ((1023u >> s) << s) << TH_SH; }
 
 HR_HD uint32_t pack_id(uint32_t thread, uint32_t bc, uint32_t wc)
 {
@@ -203,7 +217,7 @@ HR_HD uint32_t mk(uint32_t tag, uint32_t cb, uint32_t cw)
     return (tag << TAG_SH) | (cb << CB_SH) | (cw << CW_SH);
 }
 
-HR_HD uint32_t step(uint32_t old, uint32_t id, uint32_t k)
+HR_HD uint32_t step(uint32_t old, uint32_t id, uint32_t k, uint32_t wm = WAVE_M)
 {
     const uint32_t tag = old & TAG_M;
     if (tag == T_RACE) return old;
@@ -211,15 +225,16 @@ HR_HD uint32_t step(uint32_t old, uint32_t id, uint32_t k)
     const uint32_t cb = (old >> CB_SH) & 3u;
     const uint32_t cw = (old >> CW_SH) & 3u;
     const uint32_t race = T_RACE;
-    const uint32_t keep_t = BC_M | WAVE_M | LANE_M | WC_M;
-    const uint32_t keep_w = BC_M | WAVE_M | WC_M;
+    const uint32_t lm = TH_M & ~wm;
+    const uint32_t keep_t = BC_M | TH_M | WC_M;
+    const uint32_t keep_w = BC_M | wm | WC_M;
     const uint32_t keep_b = BC_M;
     if (tag == T_INIT || (d & BC_M)) return mk(T_ST, k, k) | (id & keep_t);
     if (tag == T_MW) return conflicts(cb, k) ? race : old;
-    if (d & WAVE_M) return conflicts(cb, k) ? race : (mk(T_MW, k, 0) | (id & keep_b));
+    if (d & wm) return conflicts(cb, k) ? race : (mk(T_MW, k, 0) | (id & keep_b));
     if (d & WC_M) return mk(T_ST, cb | k, k) | (id & keep_t);
     if (tag == T_MT) return conflicts(cw, k) ? race : old;
-    if (d & LANE_M) return conflicts(cw, k) ? race : (mk(T_MT, cb, k) | (id & keep_w));
+    if (d & lm) return conflicts(cw, k) ? race : (mk(T_MT, cb, k) | (id & keep_w));
     return mk(T_ST, cb | k, cw | k) | (id & keep_t);
 }
 }  // namespace l

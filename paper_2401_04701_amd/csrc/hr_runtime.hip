@@ -89,6 +89,7 @@ hr_env hr_make_env(hr_ctx c)
     e.wc_max = (1u << c->cfg.wc_bits) - 1;
     e.group = (c->cfg.flags & HR_CFG_WAVE_GROUPING) ? 1u : 0u;
     e.site_limit = c->cfg.site_limit;
+    e.wave_bits = c->cfg.wave_bits;
     return e;
 }
 
@@ -155,6 +156,8 @@ extern "C" hr_status hr_ctx_create(hr_ctx* out, const hr_config* cfg, void* stre
     if (k.wc_bits == 0) k.wc_bits = 6;
     if (k.bc_bits > 8 || k.wc_bits > 6 || k.ring_capacity > (1u << 26)) return HR_E_INVAL;
     if (k.flags & ~(HR_CFG_COUNT_CHECKS | HR_CFG_WAVE_GROUPING)) return HR_E_INVAL;
+    if (k.wave_bits == 0) k.wave_bits = 6;
+    if (k.wave_bits > 6) return HR_E_INVAL;
     hr_ctx c = new (std::nothrow) hr_ctx_s();
     if (!c) return HR_E_NOMEM;
     c->cfg = k;
@@ -315,22 +318,26 @@ extern "C" hr_status hr_check_count(hr_ctx c, uint64_t* out, void* stream)
 
 extern "C" hr_status hr_fsm_step(uint32_t space, uint64_t old, uint32_t kind, uint32_t launch,
                                  uint32_t block, uint32_t thread, uint32_t bc, uint32_t wc,
-                                 uint64_t* new_out)
+                                 uint32_t wave_bits, uint64_t* new_out)
 {
     if (!new_out || kind > 2 || space > 1 || thread > 1023) return HR_E_INVAL;
+    if (wave_bits < 1 || wave_bits > 6) return HR_E_INVAL;
     const uint32_t k = hr::kind_class(kind);
     if (space == HR_GLOBAL) {
         if (block >= hr::g::BLOCK_LIMIT) return HR_E_INVAL;
-        *new_out = hr::g::step(old, hr::g::pack_id(launch, block, thread, bc, wc), k);
+        *new_out = hr::g::step(old, hr::g::pack_id(launch, block, thread, bc, wc), k,
+                               hr::g::group_mask(wave_bits));
     } else {
-        *new_out = hr::l::step((uint32_t)old, hr::l::pack_id(thread, bc, wc), k);
+        *new_out = hr::l::step((uint32_t)old, hr::l::pack_id(thread, bc, wc), k,
+                               hr::l::group_mask(wave_bits));
     }
     return HR_OK;
 }
 
-extern "C" hr_status hr_describe(uint32_t space, uint64_t word, hr_summary* out)
+extern "C" hr_status hr_describe(uint32_t space, uint64_t word, uint32_t wave_bits,
+                                 hr_summary* out)
 {
-    if (!out || space > HR_LDS) return HR_E_INVAL;
+    if (!out || space > HR_LDS || wave_bits < 1 || wave_bits > 6) return HR_E_INVAL;
     const uint32_t none = UINT32_MAX;
     hr_summary d = {};
     d.launch = d.block = d.bc = d.wave = d.wc = d.thread = none;
@@ -366,7 +373,7 @@ extern "C" hr_status hr_describe(uint32_t space, uint64_t word, hr_summary* out)
     if (tag == hr::T_MB || tag == hr::T_MW) d.class_block = cb;
     if (tag >= hr::T_MT) {
         d.class_block = cb;
-        d.wave = th >> 6;
+        d.wave = th >> wave_bits;
         d.wc = wc;
     }
     if (tag == hr::T_MW || tag == hr::T_MT) d.class_wave = tag == hr::T_MT ? cw : 0;
@@ -378,9 +385,9 @@ extern "C" hr_status hr_describe(uint32_t space, uint64_t word, hr_summary* out)
     return HR_OK;
 }
 
-extern "C" hr_status hr_fsm_merge(uint64_t x, uint64_t y, uint64_t* out)
+extern "C" hr_status hr_fsm_merge(uint64_t x, uint64_t y, uint32_t wave_bits, uint64_t* out)
 {
-    if (!out) return HR_E_INVAL;
-    *out = hr::g::merge(x, y);
+    if (!out || wave_bits < 1 || wave_bits > 6) return HR_E_INVAL;
+    *out = hr::g::merge(x, y, hr::g::group_mask(wave_bits));
     return HR_OK;
 }

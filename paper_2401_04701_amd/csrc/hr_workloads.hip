@@ -81,7 +81,7 @@ __global__ __launch_bounds__(1024) void k_program(hr_kargs a, prog_map pm, uint3
         lsh[i] = 0;
     }
     __syncthreads();
-    const uint32_t w = t >> 6;
+    const uint32_t w = t >> a.env.wave_bits;     // the thread's wave, or tile
     for (uint32_t p = 0; p < phases; ++p) {
         const size_t i = ((size_t)p * blocks + b) * threads + t;
         int64_t k0 = 0, k1 = 0;

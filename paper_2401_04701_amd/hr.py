@@ -62,7 +62,7 @@ class _Config(ctypes.Structure):
     _fields_ = [("ring_capacity", ctypes.c_uint32), ("bc_bits", ctypes.c_uint32),
                 ("wc_bits", ctypes.c_uint32), ("flags", ctypes.c_uint32),
                 ("shadow_budget", ctypes.c_uint64), ("site_limit", ctypes.c_uint32),
-                ("pad", ctypes.c_uint32)]
+                ("wave_bits", ctypes.c_uint32)]
 
 
 class Summary(ctypes.Structure):
@@ -125,9 +125,9 @@ def _load():
         "hr_reset": [P, P],
         "hr_report": [P, P, sz, P, P],
         "hr_check_count": [P, P, P],
-        "hr_fsm_step": [u32, u64, u32, u32, u32, u32, u32, u32, P],
-        "hr_fsm_merge": [u64, u64, P],
-        "hr_describe": [u32, u64, P],
+        "hr_fsm_step": [u32, u64, u32, u32, u32, u32, u32, u32, u32, P],
+        "hr_fsm_merge": [u64, u64, u32, P],
+        "hr_describe": [u32, u64, u32, P],
         "hr_reduce_check": [P, u32, u32, P, P, u32, u32, u32, ctypes.c_int32, P],
         "hr_reduce_plain": [P, P, u32, u32, u32, ctypes.c_int32, P],
         "hr_jacobi_check": [P, u32, u32, P, P, u32, u32, P, P],
@@ -188,25 +188,27 @@ def _dptr(t):
 
 
 def fsm_step(space: int, old: int, kind: int, launch: int, block: int, thread: int,
-             bc: int, wc: int) -> int:
-    """Host evaluation of the device transition function (verification aid)."""
+             bc: int, wc: int, wave_bits: int = 6) -> int:
+    """Host evaluation of the device transition function (verification aid);
+    wave_bits < 6 makes tiles of 2**wave_bits lanes the synchronization
+    groups (wc then counts tile barriers)."""
     out = ctypes.c_uint64(0)
     _check("hr_fsm_step", _lib.hr_fsm_step(space, old, kind, launch, block, thread, bc, wc,
-                                           ctypes.byref(out)))
+                                           wave_bits, ctypes.byref(out)))
     return int(out.value)
 
 
-def describe(space: int, word: int) -> dict:
+def describe(space: int, word: int, wave_bits: int = 6) -> dict:
     """Decode a shadow summary word (a race record's `before` or `with`)."""
     out = Summary()
-    _check("hr_describe", _lib.hr_describe(space, word, ctypes.byref(out)))
+    _check("hr_describe", _lib.hr_describe(space, word, wave_bits, ctypes.byref(out)))
     return out.as_dict()
 
 
-def fsm_merge(x: int, y: int) -> int:
+def fsm_merge(x: int, y: int, wave_bits: int = 6) -> int:
     """Host evaluation of the device summary merge (verification aid)."""
     out = ctypes.c_uint64(0)
-    _check("hr_fsm_merge", _lib.hr_fsm_merge(x, y, ctypes.byref(out)))
+    _check("hr_fsm_merge", _lib.hr_fsm_merge(x, y, wave_bits, ctypes.byref(out)))
     return int(out.value)
 
 
@@ -270,10 +272,12 @@ class Context:
     """A checking job: shadow regions, report ring, launch epochs."""
 
     def __init__(self, ring_capacity=0, bc_bits=0, wc_bits=0, count_checks=False,
-                 shadow_budget=0, wave_grouping=False, site_limit=0, stream=None):
+                 shadow_budget=0, wave_grouping=False, site_limit=0, wave_bits=0, stream=None):
         flags = (HR_CFG_COUNT_CHECKS if count_checks else 0) | \
                 (HR_CFG_WAVE_GROUPING if wave_grouping else 0)
-        cfg = _Config(ring_capacity, bc_bits, wc_bits, flags, shadow_budget, site_limit, 0)
+        cfg = _Config(ring_capacity, bc_bits, wc_bits, flags, shadow_budget, site_limit,
+                      wave_bits)
+        self.wave_bits = wave_bits or 6
         self._c = ctypes.c_void_p(0)
         self._stream = _stream_ptr(stream)
         _check("hr_ctx_create", _lib.hr_ctx_create(ctypes.byref(self._c), ctypes.byref(cfg),

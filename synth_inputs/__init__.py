@@ -289,6 +289,47 @@ def random_program(seed: int, launches: int = 2, blocks: int = 2,
                    lds_words=lds_words)
 
 
+def tile_reduce_program(tile: int, blocks: int, threads: int, drop: int = -1) -> Program:
+    """Wave-synchronous (sub-wave) tree reduction as an access program.
+
+    Every tile of `tile` lanes (a power of two) owns an LDS segment of
+    n = 2 * tile int32 words at tile_index * n.  Lane l of a tile reads the
+    global input words l and l + tile of its segment (region 0, laid out
+    like the LDS) and stores them to the segment, then runs log2(n) halving
+    steps: in step s lanes l < h = n >> (s+1) read seg[l] and seg[l+h] and
+    write seg[l], and each step ends with a tile barrier (a wave-scope barrier
+    in every tile, with tiles as the synchronization groups) unless s ==
+    drop.  Finally every lane reads seg[0] and writes global out[b*threads +
+    t] (region 1).  One launch."""
+    assert tile >= 2 and tile & (tile - 1) == 0 and threads % tile == 0
+    tiles = threads // tile
+    assert tiles <= 64, "the wave mask holds 64 groups"
+    n = 2 * tile
+    steps = n.bit_length() - 1
+    mask = (1 << tiles) - 1
+    per = [[[[] for _ in range(threads)] for _ in range(blocks)] for _ in range(steps + 1)]
+    for b in range(blocks):
+        for t in range(threads):
+            l, base = t % tile, (t // tile) * n
+            gbase = b * threads * 2 + base
+            ops0 = per[0][b][t]
+            for j in (l, l + tile):
+                ops0.append(op_word(SPACE_GLOBAL, 0, KIND_R, gbase + j))
+                ops0.append(op_word(SPACE_LDS, 0, KIND_W, base + j))
+            for st in range(steps):
+                h = n >> (st + 1)
+                if l < h:
+                    per[st][b][t] += [op_word(SPACE_LDS, 0, KIND_R, base + l),
+                                      op_word(SPACE_LDS, 0, KIND_R, base + l + h),
+                                      op_word(SPACE_LDS, 0, KIND_W, base + l)]
+            per[steps][b][t] += [op_word(SPACE_LDS, 0, KIND_R, base),
+                                 op_word(SPACE_GLOBAL, 1, KIND_W, b * threads + t)]
+    scopes = [SCOPE_NONE if st == drop else SCOPE_WAVE for st in range(steps)] + [SCOPE_NONE]
+    masks = [mask if sc == SCOPE_WAVE else 0 for sc in scopes]
+    launch = build_launch(blocks, threads, scopes, masks, per)
+    return Program([launch], [blocks * threads * 2, blocks * threads], 2 * threads)
+
+
 # --------------------------------------------------------------------------
 # Batched jobs: a manifest of independent checked jobs of mixed patterns.
 # --------------------------------------------------------------------------

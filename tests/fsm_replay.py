@@ -69,7 +69,7 @@ def _one_launch_order(log, idx, rng, wave_width):
     return out
 
 
-def replay(log: np.ndarray, order) -> set:
+def replay(log: np.ndarray, order, wave_bits: int = 6) -> set:
     """Apply the transition function in `order`; return the keys that reached
     the race state.  LDS shadow starts fresh for every block and launch."""
     words = {}
@@ -85,7 +85,8 @@ def replay(log: np.ndarray, order) -> set:
             wkey = (0, rg, 0, ix)
             key = wkey
         old = words.get(wkey, 0)
-        new = hr.fsm_step(sp, old, int(r["kind"]), L & 511, b, t, int(r["bc"]), int(r["wc"]))
+        new = hr.fsm_step(sp, old, int(r["kind"]), L & 511, b, t, int(r["bc"]), int(r["wc"]),
+                          wave_bits)
         words[wkey] = new
         if (new & 7) == hr.T_RACE:
             racy.add(key)

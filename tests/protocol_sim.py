@@ -31,9 +31,10 @@ class _Thread:
         self.pc, self.bc, self.wc, self.hook = 0, 0, 0, None
 
 
-def _expand(launch, narrow):
+def _expand(launch, narrow, tiles=False):
     """Per-thread op lists: ('A', space, region, index, kind) / ('B',) / ('W',).
-    Threads of `narrow`-lane waves are relabelled onto 64-lane waves."""
+    Threads of `narrow`-lane waves are relabelled onto 64-lane waves, or, with
+    `tiles`, keep their index and the groups are tiles of `narrow` lanes."""
     threads = []
     for b in range(launch.blocks):
         for t in range(launch.threads):
@@ -48,20 +49,23 @@ def _expand(launch, narrow):
                     ops.append(("B",))
                 elif sc == si.SCOPE_WAVE and (int(launch.wave_mask[p]) >> w) & 1:
                     ops.append(("W",))
-            threads.append(_Thread(b, w * 64 + t % narrow, w, ops))
+            threads.append(_Thread(b, t if tiles else w * 64 + t % narrow, w, ops))
     return threads
 
 
 STATS = {"folds": 0, "fold_rounds": 0}
 
 
-def simulate(program, narrow: int, seed: int):
+def simulate(program, narrow: int, seed: int, tiles: bool = False):
+    """tiles: the checker synchronizes tiles of `narrow` lanes (wave_bits =
+    log2 narrow) instead of relabelling them onto 64-lane waves."""
     rng = np.random.default_rng(seed)
+    wb = int(narrow).bit_length() - 1 if tiles else 6
     gwords = {}
     pushed = []
     for L, launch in enumerate(program.launches):
         lwords = {}
-        ths = _expand(launch, narrow)
+        ths = _expand(launch, narrow, tiles)
         by_block = {}
         by_wave = {}
         for th in ths:
@@ -90,11 +94,11 @@ def simulate(program, narrow: int, seed: int):
                 assert all(th.pc == len(th.ops) for th in ths), "barrier deadlock"
                 break
             th = runnable[int(rng.integers(0, len(runnable)))]
-            _micro_step(th, L, gwords, lwords, pushed)
+            _micro_step(th, L, gwords, lwords, pushed, wb)
     return pushed, gwords
 
 
-def _micro_step(th, L, gwords, lwords, pushed):
+def _micro_step(th, L, gwords, lwords, pushed, wb=6):
     if th.hook is None:
         _, space, region, index, kind = th.ops[th.pc]
         th.hook = {"space": space, "region": region, "index": index, "kind": kind,
@@ -105,7 +109,7 @@ def _micro_step(th, L, gwords, lwords, pushed):
         if h["stage"] == "load":
             old = gwords.get(key, 0)
             nw = hr.fsm_step(hr.HR_GLOBAL, old, h["kind"], L & 511, th.block, th.thread,
-                             th.bc, th.wc)
+                             th.bc, th.wc, wb)
             if nw == old:
                 return _done(th)
             h.update(stage="xchg", old=old, nw=nw)
@@ -124,7 +128,7 @@ def _micro_step(th, L, gwords, lwords, pushed):
             return
         if h["stage"] == "fold":
             STATS["fold_rounds"] += 1
-            m = hr.fsm_merge(h["cur"], h["lost"])
+            m = hr.fsm_merge(h["cur"], h["lost"], wb)
             if m == h["cur"]:
                 return _done(th)
             seen = gwords.get(key, 0)
@@ -141,7 +145,7 @@ def _micro_step(th, L, gwords, lwords, pushed):
         if h["stage"] == "load":
             h.update(stage="cas", old=lwords.get(wkey, 0))
             return
-        nw = hr.fsm_step(hr.HR_LDS, h["old"], h["kind"], 0, 0, th.thread, th.bc, th.wc)
+        nw = hr.fsm_step(hr.HR_LDS, h["old"], h["kind"], 0, 0, th.thread, th.bc, th.wc, wb)
         if nw == h["old"]:
             return _done(th)
         seen = lwords.get(wkey, 0)

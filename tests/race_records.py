@@ -23,8 +23,9 @@ def _within(c_acc: int, c_sum: int) -> bool:
     return c_sum != 0 and (c_acc | c_sum) == c_sum
 
 
-def stands_for(acc, s: dict, space: int, launch: int) -> bool:
-    """Whether summary `s` (decoded) may include access `acc`."""
+def stands_for(acc, s: dict, space: int, launch: int, wave_bits: int = 6) -> bool:
+    """Whether summary `s` (decoded) may include access `acc`; groups are
+    waves (wave_bits 6) or tiles of 2**wave_bits lanes."""
     if space == hr.HR_GLOBAL:
         if (int(acc["launch"]) & 511) != s["launch"]:
             return False
@@ -45,20 +46,20 @@ def stands_for(acc, s: dict, space: int, launch: int) -> bool:
         return True                      # the block's latest epoch
     if s["state"] == hr.HR_S_WAVES:
         return False
-    if (int(acc["thread"]) >> 6) != s["wave"] or int(acc["wc"]) != s["wc"]:
+    if (int(acc["thread"]) >> wave_bits) != s["wave"] or int(acc["wc"]) != s["wc"]:
         return False
     if s["state"] == hr.HR_S_THREAD and int(acc["thread"]) != s["thread"]:
         return False
     return _within(c, s["class_wave"])
 
 
-def record_problem(rec, log_at_key: np.ndarray, strict_with: bool = True):
+def record_problem(rec, log_at_key: np.ndarray, strict_with: bool = True, wave_bits: int = 6):
     """None if the record is valid for the accesses at its key, else a reason."""
     space = int(rec["space"])
     if int(rec["flags"]) & hr.HR_RACE_SCANNED:
         return None                      # only the key is reported
-    b = hr.describe(space, int(rec["before"]))
-    w = hr.describe(space, int(rec["with"]))
+    b = hr.describe(space, int(rec["before"]), wave_bits)
+    w = hr.describe(space, int(rec["with"]), wave_bits)
     launch = int(rec["launch"])
     fold = bool(int(rec["flags"]) & hr.HR_RACE_FOLD)
     if not fold and strict_with:
@@ -68,15 +69,15 @@ def record_problem(rec, log_at_key: np.ndarray, strict_with: bool = True):
             return "with has another class than the record's kind"
         if space == hr.HR_GLOBAL and w["block"] != int(rec["block"]):
             return "with names another block"
-    ps = [a for a in log_at_key if stands_for(a, b, space, launch)]
-    qs = [a for a in log_at_key if stands_for(a, w, space, launch)]
+    ps = [a for a in log_at_key if stands_for(a, b, space, launch, wave_bits)]
+    qs = [a for a in log_at_key if stands_for(a, w, space, launch, wave_bits)]
     if not ps:
         return "no access of the log matches before"
     if not qs:
         return "no access of the log matches with"
     for p in ps:
         for q in qs:
-            if oracle.race_pair(p, q):
+            if oracle.race_pair(p, q, 1 << wave_bits):
                 return None
     return "no racing pair between before and with"
 

@@ -264,3 +264,54 @@ def test_race_record_check_accepts_host_records_and_rejects_planted():
                 bad["before"] = 0                           # an empty history cannot race
                 rejected += record_problem(bad, keys[record_key(rec)]) is not None
     assert checked > 50 and rejected == 2 * checked
+
+
+TILE_SETTINGS = [
+    # blocks, threads, tile width, phases, max_ops, gwords, lwords, launches
+    (1, 8, 2, 4, 2, 3, 2, 2),
+    (2, 8, 4, 3, 2, 3, 3, 2),
+    (1, 48, 16, 4, 1, 40, 24, 2),
+    (2, 64, 32, 3, 1, 48, 24, 2),
+    (1, 12, 4, 5, 1, 12, 8, 1),
+]
+
+
+@pytest.mark.parametrize("setting", TILE_SETTINGS)
+def test_fsm_with_tiles_flags_oracle_set_in_every_order(setting):
+    """Sub-wave synchronization: with tiles of 2^s lanes as the groups
+    (wave_bits = s), barriers of a tile order only its lanes, and the machine
+    must reach the oracle's set (waves of the tile width) in every
+    happens-before-consistent order, with thread indices as they are."""
+    blocks, threads, tw, phases, max_ops, gw, lw, launches = setting
+    wb = tw.bit_length() - 1
+    racy = clean = 0
+    for s in range(30):
+        prog = si.random_program(6151 * s + tw * 7 + threads, launches=launches,
+                                 blocks=blocks, threads=threads, phases=phases,
+                                 max_ops=max_ops, global_regions=2, global_words=gw,
+                                 lds_words=lw, kind_p=(0.5, 0.25, 0.25),
+                                 scope_p=(0.2, 0.55, 0.25), wave_width=tw)
+        log = oracle.model_program(prog, tw)
+        want = oracle.flagged(log.copy(), tw)
+        for order in random_orders(log, 10, seed=s, wave_width=tw):
+            assert replay(log, order, wb) == want, (setting, s)
+        touched = {(int(r["space"]), int(r["region"]), int(r["lds_block"]), int(r["index"]))
+                   for r in log}
+        racy += len(want)
+        clean += len(touched - want)
+    assert racy > 0 and clean > 0
+
+
+def test_tile_barrier_orders_only_its_tile():
+    """Two lanes of one wave in different 4-lane tiles: a tile barrier
+    between a write and a read orders them only when both lanes are in the
+    tile that synchronized."""
+    G, W, R = hr.HR_GLOBAL, hr.HR_WRITE, hr.HR_READ
+    w = hr.fsm_step(G, 0, W, 1, 0, 1, 0, 0, 2)                  # lane 1, tile 0, epoch 0
+    same_tile = hr.fsm_step(G, w, R, 1, 0, 2, 0, 1, 2)          # lane 2 after tile 0's barrier
+    other_tile = hr.fsm_step(G, w, R, 1, 0, 5, 0, 0, 2)         # lane 5 (tile 1), no barrier
+    assert (same_tile & 7) != hr.T_RACE and (other_tile & 7) == hr.T_RACE
+    # with whole waves the same two lanes are one group: the read of lane 5
+    # after a wave barrier is ordered
+    assert (hr.fsm_step(G, hr.fsm_step(G, 0, W, 1, 0, 1, 0, 0), R, 1, 0, 5, 0, 1) & 7) \
+        != hr.T_RACE

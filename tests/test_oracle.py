@@ -293,3 +293,19 @@ def test_planted_mistake_is_caught(name, tmp_path):
     finally:
         oracle._SO, oracle._lib_handle = saved_so, saved_handle
     assert _pins_hold()
+
+
+@pytest.mark.parametrize("tile,threads,blocks", [(2, 4, 1), (4, 4, 1), (4, 8, 2), (8, 16, 1)])
+def test_tile_reduction_closed_form(tile, threads, blocks):
+    """Sub-wave reduction: the oracle (waves of the tile width), the
+    operational brute force (up to 4 threads) and the closed form agree for
+    every dropped tile barrier."""
+    from oracle import brute
+    steps = (2 * tile).bit_length() - 1
+    for drop in [-1] + list(range(steps)):
+        prog = si.tile_reduce_program(tile, blocks, threads, drop)
+        want = cf.tile_reduce_flagged(tile, blocks, threads, drop)
+        assert oracle.flagged_program(prog, tile) == want, (tile, drop)
+        if threads * blocks <= 4:
+            assert brute.flagged_program(prog, tile) == want, (tile, drop)
+    assert cf.tile_reduce_flagged(tile, blocks, threads, -1) == set()

@@ -63,3 +63,20 @@ def test_protocol_contended_single_location():
             pushed, _ = ps.simulate(prog, 2, seed=s * 100 + sched)
             assert set(pushed) == want, (s, sched)
     assert ps.STATS["folds"] - folds0 > 50
+
+
+@pytest.mark.parametrize("tw", [2, 4])
+def test_protocol_with_tiles_reports_oracle_set(tw):
+    """The exchange + fold protocol with tiles of `tw` lanes as the groups."""
+    folds0 = ps.STATS["folds"]
+    for s in range(30):
+        prog = si.random_program(7919 * s + tw, launches=2, blocks=2, threads=2 * tw,
+                                 phases=3, max_ops=2, global_regions=1, global_words=2,
+                                 lds_words=2, kind_p=(0.5, 0.2, 0.3), scope_p=(0.3, 0.45, 0.25),
+                                 wave_width=tw)
+        log = oracle.model_program(prog, tw)
+        want = oracle.flagged(log.copy(), tw)
+        for sched in range(20):
+            pushed, _ = ps.simulate(prog, tw, seed=100 * s + sched, tiles=True)
+            assert set(pushed) == want, (tw, s, sched)
+    assert ps.STATS["folds"] > folds0
