@@ -162,6 +162,15 @@ hr_status hr_ctx_destroy(hr_ctx c);
 hr_status hr_shadow_alloc(hr_ctx c, const void* data_dev, size_t bytes, uint32_t elem_bytes,
                           uint32_t* region_out);
 
+/* Switch the monitoring of a region off (on = 0) or back on, for the
+ * kernels launched afterwards (the paper lets a tool enable or disable the
+ * instrumentation of individual data at run time, Sec. IV-A).  Hooks on an
+ * unmonitored region do nothing; its shadow words keep their state, so
+ * switching it on again resumes checking with the history it had.  Device
+ * code switches individual threads with hr_thread_enable.  Errors:
+ * HR_E_INVAL (unknown or freed region). */
+hr_status hr_region_enable(hr_ctx c, uint32_t region, uint32_t on);
+
 /* Release the shadow memory of a region made by hr_shadow_alloc (for
  * long-lived contexts whose jobs end at different times).  Synchronises the
  * context's stream.  Errors: HR_E_INVAL (unknown or freed region),
@@ -301,7 +310,9 @@ hr_status hr_labelprop_plain(int32_t* label_dev, const int32_t* row_ptr_dev,
  * is below 6) whose bit is set in wave_mask_dev[p] (scope 1; groups past the
  * 64th never synchronize) or a block barrier (scope 2).  Operation word: bits 0..23 index,
  * 24..26 program region (global: regions_host[region] is the context region;
- * LDS: array 0 of lds_words int32), 27..28 hr_kind, 29 space.  Reads load,
+ * LDS: array 0 of lds_words int32), 27..28 hr_kind, or 3 for an operation
+ * that switches the thread's checking off (bit 0 clear) or on (bit 0 set)
+ * with hr_thread_enable, 29 space.  Reads load,
  * writes store, atomics add 1.  block_map_dev: NULL or a permutation giving
  * the logical block of each hardware block.  n_ops / n_op_off bound the
  * arrays; out-of-range operations are skipped and reported as

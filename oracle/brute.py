@@ -35,9 +35,15 @@ def thread_lists(launch, wave_width: int):
         for t in range(launch.threads):
             lst = []
             w = t // wave_width
+            on = True                      # kind 3 switches monitoring off / on
             for p in range(launch.phases):
                 for word in launch.thread_ops(p, b, t):
                     space, region, kind, index = si.op_fields(word)
+                    if kind == si.KIND_SWITCH:
+                        on = bool(index & 1)
+                        continue
+                    if not on:
+                        continue
                     key = (space, region, b if space == si.SPACE_LDS else 0, index)
                     lst.append(("A", key, kind))
                 sc = int(launch.scope[p])

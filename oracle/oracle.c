@@ -360,6 +360,10 @@ size_t orc_model_labelprop(uint32_t n, const int32_t* row_ptr, const int32_t* co
  * program generator): per phase, every thread's operations, then the phase's
  * barrier.  A block barrier advances the block epoch and restarts the wave
  * epoch; a wave barrier advances the wave epoch of the waves in wave_mask.
+ * An operation of kind 3 switches the thread's monitoring off (index bit 0
+ * clear) or on (set): the accesses a switched-off thread makes are not
+ * monitored, so they are not in the log (paper Sec. IV-A: the instrumentation
+ * of individual threads can be enabled or disabled at run time).
  */
 size_t orc_model_launch(uint32_t launch, uint32_t blocks, uint32_t threads,
                         uint32_t phases, const uint8_t* scope,
@@ -371,14 +375,19 @@ size_t orc_model_launch(uint32_t launch, uint32_t blocks, uint32_t threads,
     if (wave_width == 0) wave_width = 64;
     for (uint32_t b = 0; b < blocks; ++b) {
         for (uint32_t t = 0; t < threads; ++t) {
-            uint32_t bc = 0, wc = 0;
+            uint32_t bc = 0, wc = 0, on = 1;
             const uint32_t w = t / wave_width;
             for (uint32_t p = 0; p < phases; ++p) {
                 const size_t i = ((size_t)p * blocks + b) * threads + t;
                 for (int32_t k = op_off[i]; k < op_off[i + 1]; ++k) {
                     const uint32_t op = ops[k];
-                    emit(&s, (op >> 29) & 1, (op >> 24) & 7, op & 0xFFFFFF,
-                         (op >> 27) & 3, launch, b, t, bc, wc);
+                    if (((op >> 27) & 3) == 3) {
+                        on = op & 1;
+                        continue;
+                    }
+                    if (on)
+                        emit(&s, (op >> 29) & 1, (op >> 24) & 7, op & 0xFFFFFF,
+                             (op >> 27) & 3, launch, b, t, bc, wc);
                 }
                 if (scope[p] == 2) { ++bc; wc = 0; }
                 else if (scope[p] == 1 && w < 64 && ((wave_mask[p] >> w) & 1)) ++wc;

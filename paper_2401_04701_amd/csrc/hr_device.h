@@ -81,7 +81,8 @@ struct hr_thread {
     uint32_t block;      // logical block id
     uint32_t thread;     // thread index within the block
     uint32_t bc, wc;     // block and wave clocks
-    uint32_t enabled;    // cleared after a clock overflow
+    uint32_t enabled;    // 1: checking; bit 0 clears after a clock overflow,
+                         // bit 1 is set while the thread is switched off
 };
 
 __device__ __forceinline__ hr_thread hr_thread_make(const hr_env& e, uint32_t block,
@@ -261,7 +262,7 @@ __device__ __forceinline__ void hr_check(const hr_env& e, const hr_thread& t, ui
                                          uint64_t n, uint32_t region, uint64_t index,
                                          uint32_t site = 0, uint64_t pre = 0)
 {
-    if (!t.enabled) return;
+    if (t.enabled != 1 || !shadow) return;      // thread switched off / region not monitored
     hr_count(e, t);
     if (index >= n) {
         hr_set_flag(e, HR_DEVF_RANGE);
@@ -313,7 +314,7 @@ __device__ __forceinline__ void hr_check(const hr_env& e, const hr_thread& t, ui
 __device__ __forceinline__ uint64_t hr_check_load(const hr_thread& t, uint64_t* shadow,
                                                   uint64_t n, uint64_t index)
 {
-    return (t.enabled && index < n)
+    return (t.enabled == 1 && shadow && index < n)
                ? __hip_atomic_load(shadow + index, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
                : 0;
 }
@@ -324,7 +325,7 @@ __device__ __forceinline__ void hr_access(const hr_kargs& a, const hr_thread& t,
                                           uint64_t index, uint32_t site = 0)
 {
     if (region >= HR_MAX_REGIONS) {
-        if (t.enabled) hr_set_flag(a.env, HR_DEVF_RANGE);
+        if (t.enabled == 1) hr_set_flag(a.env, HR_DEVF_RANGE);
         return;
     }
     hr_check<KIND, true>(a.env, t, a.shadow[region], a.n_elems[region], region, index, site);
@@ -339,7 +340,7 @@ __device__ __forceinline__ void hr_access_lds(const hr_env& e, const hr_thread& 
                                               uint32_t n_words, uint32_t array_id, uint32_t index,
                                               uint32_t site = 0)
 {
-    if (!t.enabled) return;
+    if (t.enabled != 1) return;
     hr_count(e, t);
     if (index >= n_words) {
         hr_set_flag(e, HR_DEVF_RANGE);
@@ -389,6 +390,17 @@ __device__ __forceinline__ void hr_retag(const hr_env& e, hr_thread& t)
     t.lid = hr::l::pack_id(t.thread, t.bc, t.wc);
 }
 
+// Switch the checking of this thread's accesses off or on (the paper lets a
+// tool enable or disable individual threads at run time, for instance to
+// track only a representative thread of each group of symmetric threads,
+// Sec. IV-A).  A switched-off thread's accesses are invisible to the
+// checker; its barriers still advance its clocks, so it can be switched on
+// again at any point.
+__device__ __forceinline__ void hr_thread_enable(hr_thread& t, bool on)
+{
+    t.enabled = on ? (t.enabled & ~2u) : (t.enabled | 2u);
+}
+
 // Block barrier: every thread of the block must call it (as __syncthreads).
 // Advances the block clock and restarts the wave clock (paper Sec. III-A,
 // Scenario 2: the block-scalar clock BC advances at each block barrier).
@@ -397,8 +409,8 @@ __device__ __forceinline__ void hr_barrier_block(const hr_env& e, hr_thread& t)
     __syncthreads();
     t.bc += 1;
     t.wc = 0;
-    if (t.bc > e.bc_max && t.enabled) {
-        t.enabled = 0;
+    if (t.bc > e.bc_max && (t.enabled & 1u)) {
+        t.enabled &= ~1u;
         hr_set_flag(e, HR_DEVF_CLOCK);
     }
     hr_retag(e, t);
@@ -415,8 +427,8 @@ __device__ __forceinline__ void hr_barrier_wave(const hr_env& e, hr_thread& t)
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     t.wc += 1;
-    if (t.wc > e.wc_max && t.enabled) {
-        t.enabled = 0;
+    if (t.wc > e.wc_max && (t.enabled & 1u)) {
+        t.enabled &= ~1u;
         hr_set_flag(e, HR_DEVF_CLOCK);
     }
     hr_retag(e, t);

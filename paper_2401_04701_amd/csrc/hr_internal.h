@@ -23,6 +23,7 @@ struct hr_region {
     uint64_t* shadow;    // one 8-byte word per element, inside allocs[alloc]
     uint32_t alloc;
     bool live;
+    bool monitored;      // cleared by hr_region_enable(..., 0)
 };
 
 struct hr_ctx_s {

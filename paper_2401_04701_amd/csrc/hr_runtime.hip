@@ -100,7 +100,7 @@ void hr_fill_args(hr_ctx c, hr_kargs* a)
     const uint32_t n = (uint32_t)std::min<size_t>(c->reg.size(), HR_MAX_REGIONS);
     for (uint32_t r = 0; r < n; ++r) {
         if (!c->reg[r].live) continue;
-        a->shadow[r] = c->reg[r].shadow;
+        a->shadow[r] = c->reg[r].monitored ? c->reg[r].shadow : nullptr;
         a->n_elems[r] = c->reg[r].elems;
         a->data[r] = const_cast<void*>(c->reg[r].data);
     }
@@ -130,7 +130,7 @@ hr_status hr_new_alloc(hr_ctx c, size_t words, uint32_t* alloc_out)
 
 uint32_t hr_new_region(hr_ctx c, const void* data, size_t elems, uint64_t* shadow, uint32_t alloc)
 {
-    c->reg.push_back(hr_region{data, elems, shadow, alloc, true});
+    c->reg.push_back(hr_region{data, elems, shadow, alloc, true, true});
     return (uint32_t)(c->reg.size() - 1);
 }
 
@@ -248,6 +248,13 @@ extern "C" hr_status hr_reset(hr_ctx c, void* stream)
     if (hr_fill32(c->ctr, HR_CTR_WORDS, s) != hipSuccess) return HR_E_HIP;
     if (hr_fill64((uint64_t*)c->count, HR_COUNT_SLOTS, s) != hipSuccess) return HR_E_HIP;
     c->launch_seq = 0;
+    return HR_OK;
+}
+
+extern "C" hr_status hr_region_enable(hr_ctx c, uint32_t region, uint32_t on)
+{
+    if (!c || region >= c->reg.size() || !c->reg[region].live) return HR_E_INVAL;
+    c->reg[region].monitored = on != 0;
     return HR_OK;
 }
 

@@ -94,8 +94,8 @@ __global__ __launch_bounds__(1024) void k_program(hr_kargs a, prog_map pm, uint3
         for (int64_t k = k0; k < k1; ++k) {
             const uint32_t op = ops[k];
             const uint32_t idx = op & 0xFFFFFFu, reg = (op >> 24) & 7u, kind = (op >> 27) & 3u;
-            if (kind > 2) {
-                hr_set_flag(a.env, HR_DEVF_RANGE);
+            if (kind == 3) {                        // switch this thread's checking
+                hr_thread_enable(th, idx & 1u);
                 continue;
             }
             if ((op >> 29) & 1u) {

@@ -120,6 +120,7 @@ def _load():
         "hr_ctx_destroy": [P],
         "hr_shadow_alloc": [P, P, sz, u32, P],
         "hr_shadow_free": [P, u32],
+        "hr_region_enable": [P, u32, u32],
         "hr_dev_args": [P, P, sz, P],
         "hr_kernel_end": [P, P],
         "hr_reset": [P, P],
@@ -155,6 +156,7 @@ def _load():
 
 _lib = _load()
 EXPORTED = ("hr_ctx_create", "hr_ctx_destroy", "hr_shadow_alloc", "hr_shadow_free",
+            "hr_region_enable",
             "hr_dev_args", "hr_batch_create", "hr_batch_run", "hr_batch_info",
             "hr_batch_destroy", "hr_job_run", "hr_serve",
             "hr_kernel_end", "hr_reset", "hr_report", "hr_check_count", "hr_fsm_step", "hr_fsm_merge",
@@ -355,6 +357,10 @@ class Context:
     # ------------------------------------------------------- workloads
     def shadow_free(self, region: int):
         _check("hr_shadow_free", _lib.hr_shadow_free(self._c, region))
+
+    def region_enable(self, region: int, on: bool):
+        """Monitor a region (on) or not, for the kernels launched afterwards."""
+        _check("hr_region_enable", _lib.hr_region_enable(self._c, region, int(bool(on))))
 
     def reduce_check(self, r_in, r_out, inp, out, drop=-1, n=512, threads=256, blocks=1,
                      stream=None):

@@ -179,13 +179,15 @@ def labelprop_graph(scale: int, n_edges: int, seed: int, p_seed: float):
 # Operation word (uint32):
 #   bits  0..23  element index
 #   bits 24..26  region (global regions 0..7; LDS uses region 0)
-#   bits 27..28  kind: 0 plain read, 1 plain write, 2 atomic
+#   bits 27..28  kind: 0 plain read, 1 plain write, 2 atomic, 3 switch the
+#                thread's monitoring off (bit 0 clear) or on (bit 0 set)
 #   bit  29      space: 0 global, 1 LDS
 # op_off has phases*blocks*threads+1 entries; the operations of
 # (phase p, block b, thread t) are ops[op_off[i]:op_off[i+1]] with
 # i = (p * blocks + b) * threads + t.
 # --------------------------------------------------------------------------
 KIND_R, KIND_W, KIND_A = 0, 1, 2
+KIND_SWITCH = 3          # not an access: switches the thread's monitoring off / on
 SPACE_GLOBAL, SPACE_LDS = 0, 1
 SCOPE_NONE, SCOPE_WAVE, SCOPE_BLOCK = 0, 1, 2
 
@@ -193,6 +195,11 @@ SCOPE_NONE, SCOPE_WAVE, SCOPE_BLOCK = 0, 1, 2
 def op_word(space: int, region: int, kind: int, index: int) -> int:
     assert 0 <= index < (1 << 24) and 0 <= region < 8 and kind in (0, 1, 2)
     return (index | (region << 24) | (kind << 27) | (space << 29)) & 0xFFFFFFFF
+
+
+def switch_word(on: bool) -> int:
+    """Operation that switches the thread's monitoring off or on."""
+    return (int(bool(on)) | (KIND_SWITCH << 27)) & 0xFFFFFFFF
 
 
 def op_fields(word: int):
@@ -248,11 +255,13 @@ def random_program(seed: int, launches: int = 2, blocks: int = 2,
                    global_regions: int = 2, global_words: int = 64,
                    lds_words: int = 64, p_lds: float = 0.3,
                    kind_p=(0.5, 0.25, 0.25), scope_p=(0.3, 0.3, 0.4),
-                   p_active: float = 1.0, wave_width: int = 64) -> Program:
+                   p_active: float = 1.0, wave_width: int = 64,
+                   p_switch: float = 0.0) -> Program:
     """Random barrier program.  Addresses are drawn from small ranges so that
     conflicting accesses from different threads are common.  Every thread of
     a block sees the same phase structure, so barriers are uniform.
-    wave_width only shapes the wave masks of wave-barrier phases."""
+    wave_width only shapes the wave masks of wave-barrier phases.  A share
+    p_switch of the operations switch the thread's monitoring off or on."""
     rng = np.random.default_rng(seed)
     waves = min(64, (threads + wave_width - 1) // wave_width)
     out = []
@@ -280,6 +289,10 @@ def random_program(seed: int, launches: int = 2, blocks: int = 2,
         regions = np.where(lds, 0, regions).astype(np.uint32)
         ops = (index | (regions << 24) | (kinds << 27)
                | (lds.astype(np.uint32) << 29)).astype(np.uint32)
+        if p_switch > 0:
+            sw = rng.random(total) < p_switch
+            on = rng.integers(0, 2, size=total).astype(np.uint32)
+            ops = np.where(sw, on | np.uint32(KIND_SWITCH << 27), ops).astype(np.uint32)
         op_off = np.zeros(n_slots + 1, dtype=np.int64)
         np.cumsum(counts, out=op_off[1:])
         out.append(Launch(blocks=blocks, threads=threads, scope=scopes,

@@ -309,3 +309,26 @@ def test_tile_reduction_closed_form(tile, threads, blocks):
         if threads * blocks <= 4:
             assert brute.flagged_program(prog, tile) == want, (tile, drop)
     assert cf.tile_reduce_flagged(tile, blocks, threads, -1) == set()
+
+
+def test_switched_off_threads_are_not_monitored():
+    """Monitoring switched off in a thread (operation kind 3): its accesses
+    leave the log, so races that need them are not flagged.  Oracle against
+    the operational brute force on random programs with switch operations."""
+    G = si.SPACE_GLOBAL
+    w = si.op_word(G, 0, si.KIND_W, 0)
+    r = si.op_word(G, 0, si.KIND_R, 0)
+    for off in (False, True):
+        first = [si.switch_word(False), w] if off else [w]
+        per = [[[first, [r]]]]
+        prog = si.Program([si.build_launch(1, 2, [0], [0], per)], [1], 1)
+        want = set() if off else {(0, 0, 0, 0)}
+        assert oracle.flagged_program(prog) == want == brute.flagged_program(prog)
+    n = 0
+    for s in range(60):
+        prog = si.random_program(811 * s + 3, launches=2, blocks=2, threads=3, phases=3,
+                                 max_ops=2, global_regions=1, global_words=2, lds_words=2,
+                                 scope_p=(0.4, 0.2, 0.4), wave_width=2, p_switch=0.25)
+        assert oracle.flagged_program(prog, 2) == brute.flagged_program(prog, 2), s
+        n += len(oracle.flagged_program(prog, 2))
+    assert n > 0
