@@ -42,5 +42,37 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+EXAMPLES = ["reduce_block.hip", "stencil3.hip", "histogram.hip"]
+EXAMPLES_LIB = os.path.join(PKG, "libhr_examples.so")
+
+
+def build_examples(verbose: bool = False) -> str:
+    """Instrument the example kernels with the source instrumenter and
+    compile them, with their launchers, into libhr_examples.so (linked to
+    libhr.so).  The instrumented sources go to _gen/."""
+    from . import instrument
+    gen = os.path.join(PKG, "_gen")
+    os.makedirs(gen, exist_ok=True)
+    outs = []
+    for name in EXAMPLES:
+        text, _ = instrument.instrument(os.path.join(PKG, "examples", name))
+        out = os.path.join(gen, name.replace(".hip", ".inst.hip"))
+        with open(out, "w") as f:
+            f.write(text)
+        outs.append(out)
+    tmp = EXAMPLES_LIB + ".tmp"
+    cmd = [hipcc()] + HIPCC_FLAGS + ["-I", INCLUDE, "-I", CSRC] + outs + [
+        "-L", PKG, "-lhr", "-Wl,-rpath,$ORIGIN", "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        sys.stderr.write(res.stdout + res.stderr)
+        raise RuntimeError("hipcc failed building libhr_examples.so")
+    os.replace(tmp, EXAMPLES_LIB)
+    return EXAMPLES_LIB
+
+
 if __name__ == "__main__":
     print(build(verbose=True))
+    print(build_examples(verbose=True))

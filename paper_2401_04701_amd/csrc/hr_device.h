@@ -390,6 +390,48 @@ __device__ __forceinline__ void hr_retag(const hr_env& e, hr_thread& t)
     t.lid = hr::l::pack_id(t.thread, t.bc, t.wc);
 }
 
+// ---------------------------------------------------------------------------
+// Support for kernels rewritten by the source instrumenter
+// (paper_2401_04701_amd/instrument.py): every checked subscript becomes a
+// call that checks the access and returns the element's address.
+// ---------------------------------------------------------------------------
+struct hr_rmap {
+    uint32_t id[8];   // context region of each pointer parameter of the kernel
+};
+
+// Global element base[i] of the kernel's pointer parameter `slot`; K: 0 read,
+// 1 write, 2 atomic, 3 read and write (compound assignment, ++, --).
+template <int K, class T>
+__device__ __forceinline__ T* hr_gat(const hr_kargs& a, const hr_rmap& m, const hr_thread& t,
+                                     uint32_t slot, T* base, int64_t i, uint32_t site)
+{
+    const uint32_t r = m.id[slot];
+    if (r < HR_MAX_REGIONS) {
+        if (K == 3) {
+            hr_check<0, true>(a.env, t, a.shadow[r], a.n_elems[r], r, (uint64_t)i, site);
+            hr_check<1, true>(a.env, t, a.shadow[r], a.n_elems[r], r, (uint64_t)i, site);
+        } else {
+            hr_check<K, true>(a.env, t, a.shadow[r], a.n_elems[r], r, (uint64_t)i, site);
+        }
+    }
+    return base + i;
+}
+
+// LDS element base[i] of the kernel's shared array `id` (n words, shadow sh).
+template <int K, class T>
+__device__ __forceinline__ T* hr_lat(const hr_env& e, const hr_thread& t, uint32_t* sh, uint32_t n,
+                                     uint32_t id, T* base, int64_t i, uint32_t site)
+{
+    const uint32_t idx = (i < 0 || i > (int64_t)UINT32_MAX) ? UINT32_MAX : (uint32_t)i;
+    if (K == 3) {
+        hr_access_lds<0>(e, t, sh, n, id, idx, site);
+        hr_access_lds<1>(e, t, sh, n, id, idx, site);
+    } else {
+        hr_access_lds<K>(e, t, sh, n, id, idx, site);
+    }
+    return base + i;
+}
+
 // Switch the checking of this thread's accesses off or on (the paper lets a
 // tool enable or disable individual threads at run time, for instance to
 // track only a representative thread of each group of symmetric threads,

@@ -1,0 +1,90 @@
+"""Kernels instrumented by the source rewriter, on the GPU: the flagged sets
+of the rewritten example kernels must equal their closed forms (the
+reduction's is the oracle-pinned set of the hand-instrumented reduction),
+and the rewritten kernels must still compute their results."""
+import numpy as np
+import pytest
+
+import synth_inputs as si
+from oracle import closed_forms as cf
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2401_04701_amd import hr
+    from paper_2401_04701_amd import examples
+    torch.cuda.set_device(0)
+    return torch, hr, examples
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.mark.parametrize("drop", [-1, 0, 4, 7, 8])
+def test_instrumented_reduction(env, drop):
+    torch, hr, ex = env
+    x = si.reduce_input(si.master_seed(0) + drop)
+    inp = torch.from_numpy(x).cuda()
+    out = torch.zeros(256, dtype=torch.int32, device="cuda")
+    say("instrumented reduction drop", drop)
+    with hr.Context() as ctx:
+        r_in, r_out = ctx.shadow_alloc(inp), ctx.shadow_alloc(out)
+        ex.launch("reduce_block", ctx, [r_in, r_out], (1,), (256,), inp, out, drop)
+        ctx.kernel_end()
+        got = ctx.flagged()
+        assert ctx.status == 0
+    assert got == cf.reduce_flagged(drop)
+    if drop < 0:
+        assert (out.cpu().numpy() == x.astype(np.int64).sum()).all()
+
+
+@pytest.mark.parametrize("seeded", [-1, 3, 8])
+def test_instrumented_stencil(env, seeded):
+    torch, hr, ex = env
+    n = 256 * 8 + 100                     # nine blocks, the last one ragged
+    u = torch.from_numpy(si.jacobi_grid(1, n, 5)[0].copy()).cuda()
+    v = torch.zeros(n, dtype=torch.float32, device="cuda")
+    say("instrumented stencil seeded block", seeded)
+    with hr.Context() as ctx:
+        r_u, r_v = ctx.shadow_alloc(u), ctx.shadow_alloc(v)
+        ex.launch("stencil3", ctx, [r_u, r_v], (9,), (256,), u, v, n, seeded)
+        ctx.kernel_end()
+        got = ctx.flagged()
+        assert ctx.status == 0
+    # the seeded block writes the first cell of the next block, which its
+    # owner also writes; the last block has no next block
+    want = {(0, r_v, 0, (seeded + 1) * 256)} if 0 <= seeded < 8 else set()
+    assert got == want
+    if seeded < 0:
+        h = u.cpu().numpy().astype(np.float64)
+        left = np.concatenate([h[:1], h[:-1]])
+        right = np.concatenate([h[1:], h[-1:]])
+        assert np.allclose(v.cpu().numpy(), (left + h + right) / 3.0, rtol=1e-6, atol=1e-6)
+
+
+@pytest.mark.parametrize("plain", [0, 1])
+def test_instrumented_histogram(env, plain):
+    torch, hr, ex = env
+    n, bins_n = 5000, 64
+    keys_h = np.random.default_rng(si.master_seed(5)).integers(0, bins_n, n).astype(np.int32)
+    keys_h[:3] = 63                       # bin 63 hit by at least 3 threads
+    keys_h[keys_h == 17] = 18             # bin 17 never hit
+    keys = torch.from_numpy(keys_h).cuda()
+    bins = torch.zeros(bins_n, dtype=torch.int32, device="cuda")
+    say("instrumented histogram plain", plain)
+    with hr.Context() as ctx:
+        r_k, r_b = ctx.shadow_alloc(keys), ctx.shadow_alloc(bins)
+        ex.launch("histogram", ctx, [r_k, r_b], ((n + 255) // 256,), (256,), keys, bins, n, plain)
+        ctx.kernel_end()
+        got = ctx.flagged()
+        assert ctx.status == 0
+    counts = np.bincount(keys_h, minlength=bins_n)
+    want = {(0, r_b, 0, int(b)) for b in np.nonzero(counts >= 2)[0]} if plain else set()
+    assert got == want
+    if not plain:
+        assert (bins.cpu().numpy() == counts).all()

@@ -1,0 +1,59 @@
+"""The source instrumenter on the CPU: which subscripts it checks, with which
+access kind, how it nests rewrites, and what it leaves unchecked (GPU runs
+of the instrumented examples are in test_gpu_instrumented.py)."""
+import os
+import re
+
+from paper_2401_04701_amd import instrument
+
+EX = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                  "paper_2401_04701_amd", "examples")
+
+
+def kinds(text, fn):
+    return [(int(k), int(line)) for k, line in
+            re.findall(fn + r"<(\d)>\(.*?, (\d+)\)\)", text)]
+
+
+def test_reduction_example_sites_and_kinds():
+    text, (rep,) = instrument.instrument(os.path.join(EX, "reduce_block.hip"))
+    assert rep.pointer_params == ["in", "out"] and rep.shared_arrays == [("a", 512)]
+    assert (rep.global_sites, rep.lds_sites, rep.barriers, rep.skipped) == (3, 5, 1, [])
+    # a[t] = in[t]: LDS write, global read; a[t] += a[t + h]: read-write and read
+    assert sorted(kinds(text, "hr_lat")) == [(0, 14), (0, 17), (1, 10), (1, 11), (3, 14)]
+    assert sorted(kinds(text, "hr_gat")) == [(0, 10), (0, 11), (1, 17)]
+    assert "__syncthreads()" not in text.split("LDS shadow cleared")[1]
+    assert "hr_barrier_block(hr_a.env, hr_t)" in text
+    assert "hr_launch_reduce_block" in text
+
+
+def test_histogram_atomic_and_compound_kinds():
+    text, (rep,) = instrument.instrument(os.path.join(EX, "histogram.hip"))
+    assert sorted(kinds(text, "hr_gat")) == [(0, 10), (2, 12), (3, 11)]
+    assert "atomicAdd(&(*hr_gat<2>(" in text
+
+
+def test_nested_and_unsupported_subscripts(tmp_path):
+    src = tmp_path / "k.hip"
+    src.write_text("""#include <hip/hip_runtime.h>
+__global__ void gather(const int* idx, const float* in, float* out, double* wide, int n)
+{
+    __shared__ float m[4][4];
+    const int i = threadIdx.x;
+    if (i < n) out[idx[i]] = in[idx[i] + 1] + (i ? in[i] : 0.0f);
+    wide[i] = 1.0;
+    m[i % 4][0] = 1.0f;
+    float* p = &out[i];
+    *p = 2.0f;
+}
+""")
+    text, (rep,) = instrument.instrument(str(src))
+    # out[idx[i]]: the inner idx[i] is rewritten inside the outer index
+    assert "(*hr_gat<1>(hr_a, hr_m, hr_t, 2, out, ((*hr_gat<0>(hr_a, hr_m, hr_t, 0, idx, (i), 6))), 6))" in text
+    assert "in, ((*hr_gat<0>(hr_a, hr_m, hr_t, 0, idx, (i), 6)) + 1), 6)" in text
+    assert "(*hr_gat<0>(hr_a, hr_m, hr_t, 1, in, (i), 6))" in text        # through ?:
+    assert rep.global_sites == 5 and rep.lds_sites == 0
+    skipped = " ".join(rep.skipped)
+    assert "wide" in skipped and "double" in skipped                      # 8-byte elements
+    assert "shared m" in skipped                                          # 2-D array
+    assert "line 9: out" in skipped                                       # address taken
