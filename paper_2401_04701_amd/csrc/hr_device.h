@@ -118,37 +118,45 @@ __device__ __forceinline__ void hr_count(const hr_env& e, const hr_thread& t)
 }
 
 // Append a race record: `before` and `with` are the two summaries whose
-// accesses race (see hr_race).
+// accesses race (see hr_race).  The rare path: out of line, with scalar
+// arguments only, so that the hooks inlined into a kernel keep neither the
+// record nor the environment in registers or scratch.
+__device__ __noinline__ void hr_push_rec(hr_race_rec* ring, uint32_t* ctr, uint32_t ring_cap,
+                                         uint32_t site_limit, uint32_t launch_seq,
+                                         uint32_t head, uint32_t region, uint32_t block,
+                                         uint64_t index, uint32_t tid, uint64_t before,
+                                         uint64_t with, uint32_t flags)
+{
+    if (site_limit) {
+        const uint32_t site = head >> 16;
+        const uint32_t n = __hip_atomic_fetch_add(ctr + HR_CTR_SITES + (site & (HR_SITES - 1)),
+                                                  1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (n >= site_limit) {
+            __hip_atomic_fetch_or(ctr + HR_CTR_FLAGS, HR_DEVF_LIMIT, __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT);
+            return;
+        }
+    }
+    const uint32_t slot = __hip_atomic_fetch_add(ctr + HR_CTR_HEAD, 1u, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+    if (slot < ring_cap) {
+        // three 16-byte stores of the 48-byte record (layout of hr_race)
+        uint4* p = reinterpret_cast<uint4*>(ring + slot);
+        p[0] = make_uint4(head, region, block, launch_seq);
+        p[1] = make_uint4((uint32_t)index, (uint32_t)(index >> 32), (uint32_t)before,
+                          (uint32_t)(before >> 32));
+        p[2] = make_uint4((uint32_t)with, (uint32_t)(with >> 32), tid, flags);
+    }
+}
+
 __device__ __forceinline__ void hr_ring_push(const hr_env& e, uint32_t space, uint32_t region,
                                              uint32_t block, uint64_t index, uint32_t tid,
                                              uint32_t kind, uint32_t site, uint64_t before,
                                              uint64_t with, uint32_t flags)
 {
-    if (e.site_limit) {
-        const uint32_t n = __hip_atomic_fetch_add(e.ctr + HR_CTR_SITES + (site & (HR_SITES - 1)),
-                                                  1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (n >= e.site_limit) {
-            hr_set_flag(e, HR_DEVF_LIMIT);
-            return;
-        }
-    }
-    const uint32_t slot = __hip_atomic_fetch_add(e.ctr + HR_CTR_HEAD, 1u, __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_AGENT);
-    if (slot < e.ring_cap) {
-        hr_race_rec r;
-        r.space = (uint8_t)space;
-        r.kind = (uint8_t)kind;
-        r.site = (uint16_t)site;
-        r.region = region;
-        r.block = block;
-        r.launch = e.launch_seq;
-        r.index = index;
-        r.before = before;
-        r.with = with;
-        r.tid = tid;
-        r.flags = flags;
-        e.ring[slot] = r;
-    }
+    hr_push_rec(e.ring, e.ctr, e.ring_cap, e.site_limit, e.launch_seq,
+                (space & 0xFFu) | ((kind & 0xFFu) << 8) | ((site & 0xFFFFu) << 16), region, block,
+                index, tid, before, with, flags);
 }
 
 // Fold a summary `lost` that our exchange overwrote back into the word at
