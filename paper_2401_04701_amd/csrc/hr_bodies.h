@@ -223,6 +223,20 @@ __device__ void labelprop_body(const hr_env& e, const hr_gref& glab, const hr_gr
         hr_g<0, CHECK>(e, th, grp, v, HR_SITE_LP_CSR);
         hr_g<0, CHECK>(e, th, grp, v + 1, HR_SITE_LP_CSR);
     }
+    if constexpr (!CHECK) {
+        // the plain kernel: nothing to hide, the simple loop is its fastest form
+        for (int32_t k = e0; k < e1; ++k) {
+            const uint32_t u = (uint32_t)col[k];
+            if (u >= n) continue;
+            if (mask[k]) {
+                const int32_t r = label[u];
+                label[u] = r < l ? r : l;
+            } else {
+                atomicMin(label + u, l);
+            }
+        }
+        return;
+    }
     // Software pipeline over the edge list, for the long lists of hub
     // vertices whose threads bound the launch: while edge k is checked, the
     // column index of edge k+2 and the shadow word of edge k+1's target are
