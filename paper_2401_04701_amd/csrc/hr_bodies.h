@@ -137,25 +137,24 @@ __device__ void jacobi_body(const hr_env& e, const hr_gref& gold, const hr_gref&
         tile[cl] = uo[g];
         hr_g<0, CHECK>(e, th, gold, g, HR_SITE_JACOBI_CENTRE);
         hr_l<1, CHECK>(e, th, tsh, TW, lds_id, cl, HR_SITE_JACOBI_STAGE);
-        if (ty == 0 && gy > 0) {
-            tile[tx + 1] = uo[g - nx];
-            hr_g<0, CHECK>(e, th, gold, g - nx, HR_SITE_JACOBI_HALO);
-            hr_l<1, CHECK>(e, th, tsh, TW, lds_id, tx + 1, HR_SITE_JACOBI_STAGE);
+        // An edge thread stages at most one row halo cell (north or south)
+        // and one column halo cell (west or east); each pair shares one hook
+        // site, so a wave issues two halo hooks instead of four.
+        const bool hn = ty == 0 && gy > 0, hs = ty == 15 && gy + 1 < ny;
+        const bool hw = tx == 0 && gx > 0, he = tx == 15 && gx + 1 < nx;
+        if (hn || hs) {
+            const size_t gr = hn ? g - nx : g + nx;
+            const uint32_t lr = hn ? tx + 1 : 17 * TL + tx + 1;
+            tile[lr] = uo[gr];
+            hr_g<0, CHECK>(e, th, gold, gr, HR_SITE_JACOBI_HALO);
+            hr_l<1, CHECK>(e, th, tsh, TW, lds_id, lr, HR_SITE_JACOBI_STAGE);
         }
-        if (ty == 15 && gy + 1 < ny) {
-            tile[17 * TL + tx + 1] = uo[g + nx];
-            hr_g<0, CHECK>(e, th, gold, g + nx, HR_SITE_JACOBI_HALO);
-            hr_l<1, CHECK>(e, th, tsh, TW, lds_id, 17 * TL + tx + 1, HR_SITE_JACOBI_STAGE);
-        }
-        if (tx == 0 && gx > 0) {
-            tile[(ty + 1) * TL] = uo[g - 1];
-            hr_g<0, CHECK>(e, th, gold, g - 1, HR_SITE_JACOBI_HALO);
-            hr_l<1, CHECK>(e, th, tsh, TW, lds_id, (ty + 1) * TL, HR_SITE_JACOBI_STAGE);
-        }
-        if (tx == 15 && gx + 1 < nx) {
-            tile[(ty + 1) * TL + 17] = uo[g + 1];
-            hr_g<0, CHECK>(e, th, gold, g + 1, HR_SITE_JACOBI_HALO);
-            hr_l<1, CHECK>(e, th, tsh, TW, lds_id, (ty + 1) * TL + 17, HR_SITE_JACOBI_STAGE);
+        if (hw || he) {
+            const size_t gc = hw ? g - 1 : g + 1;
+            const uint32_t lc = hw ? (ty + 1) * TL : (ty + 1) * TL + 17;
+            tile[lc] = uo[gc];
+            hr_g<0, CHECK>(e, th, gold, gc, HR_SITE_JACOBI_HALO);
+            hr_l<1, CHECK>(e, th, tsh, TW, lds_id, lc, HR_SITE_JACOBI_STAGE);
         }
     }
     hr_bar<CHECK>(e, th);
