@@ -134,26 +134,30 @@ __device__ void jacobi_body(const hr_env& e, const hr_gref& gold, const hr_gref&
     const size_t g = (size_t)gy * nx + gx;
     const uint32_t cl = (ty + 1) * TL + tx + 1;
     if (inside) {
-        tile[cl] = uo[g];
-        hr_g<0, CHECK>(e, th, gold, g, HR_SITE_JACOBI_CENTRE);
-        hr_l<1, CHECK>(e, th, tsh, TW, lds_id, cl, HR_SITE_JACOBI_STAGE);
         // An edge thread stages at most one row halo cell (north or south)
         // and one column halo cell (west or east); each pair shares one hook
-        // site, so a wave issues two halo hooks instead of four.
+        // site, so a wave issues two halo hooks instead of four.  The data
+        // loads are issued first, so that they are in flight together with
+        // the first hook's shadow load.
         const bool hn = ty == 0 && gy > 0, hs = ty == 15 && gy + 1 < ny;
         const bool hw = tx == 0 && gx > 0, he = tx == 15 && gx + 1 < nx;
+        const size_t gr = hn ? g - nx : g + nx, gc = hw ? g - 1 : g + 1;
+        const float vc = uo[g];
+        const float vr = hn || hs ? uo[gr] : 0.0f;
+        const float vk = hw || he ? uo[gc] : 0.0f;
+        hr_g<0, CHECK>(e, th, gold, g, HR_SITE_JACOBI_CENTRE);
+        tile[cl] = vc;
+        hr_l<1, CHECK>(e, th, tsh, TW, lds_id, cl, HR_SITE_JACOBI_STAGE);
         if (hn || hs) {
-            const size_t gr = hn ? g - nx : g + nx;
             const uint32_t lr = hn ? tx + 1 : 17 * TL + tx + 1;
-            tile[lr] = uo[gr];
             hr_g<0, CHECK>(e, th, gold, gr, HR_SITE_JACOBI_HALO);
+            tile[lr] = vr;
             hr_l<1, CHECK>(e, th, tsh, TW, lds_id, lr, HR_SITE_JACOBI_STAGE);
         }
         if (hw || he) {
-            const size_t gc = hw ? g - 1 : g + 1;
             const uint32_t lc = hw ? (ty + 1) * TL : (ty + 1) * TL + 17;
-            tile[lc] = uo[gc];
             hr_g<0, CHECK>(e, th, gold, gc, HR_SITE_JACOBI_HALO);
+            tile[lc] = vk;
             hr_l<1, CHECK>(e, th, tsh, TW, lds_id, lc, HR_SITE_JACOBI_STAGE);
         }
     }
