@@ -27,7 +27,7 @@ __device__ __forceinline__ void hr_g(const hr_env& e, const hr_thread& t, const 
     if constexpr (CHECK) hr_check<KIND, GROUP>(e, t, g.shadow, g.n, g.id, index, site);
 }
 
-// Global hook on a word loaded earlier by hr_gload (data-dependent site).
+// Global hook on a word loaded earlier by hr_gload.
 template <bool CHECK>
 __device__ __forceinline__ uint64_t hr_gload(const hr_thread& t, const hr_gref& g, uint64_t index)
 {
@@ -35,11 +35,11 @@ __device__ __forceinline__ uint64_t hr_gload(const hr_thread& t, const hr_gref& 
     return 0;
 }
 
-template <int KIND, bool CHECK>
+template <int KIND, bool CHECK, bool GROUP = true>
 __device__ __forceinline__ void hr_gpre(const hr_env& e, const hr_thread& t, const hr_gref& g,
                                         uint64_t index, uint32_t site, uint64_t pre)
 {
-    if constexpr (CHECK) hr_check<KIND, true, true>(e, t, g.shadow, g.n, g.id, index, site, pre);
+    if constexpr (CHECK) hr_check<KIND, GROUP, true>(e, t, g.shadow, g.n, g.id, index, site, pre);
 }
 
 template <int KIND, bool CHECK>
@@ -163,6 +163,8 @@ __device__ void jacobi_body(const hr_env& e, const hr_gref& gold, const hr_gref&
     }
     hr_bar<CHECK>(e, th);
     if (inside) {
+        // the output word's shadow load is in flight during the LDS reads
+        const uint64_t pre_out = hr_gload<CHECK>(th, gnew, g);
         const float c = tile[cl];
         hr_l<0, CHECK>(e, th, tsh, TW, lds_id, cl, HR_SITE_JACOBI_TILE);
         float vn = c, vs = c, vw = c, ve = c;
@@ -184,7 +186,7 @@ __device__ void jacobi_body(const hr_env& e, const hr_gref& gold, const hr_gref&
         }
         const float r = 0.2f * (c + vn + vs + vw + ve);
         un[g] = r;
-        hr_g<1, CHECK>(e, th, gnew, g, HR_SITE_JACOBI_OUT);
+        hr_gpre<1, CHECK, false>(e, th, gnew, g, HR_SITE_JACOBI_OUT, pre_out);
         if (seeds) {
             const int32_t sd = seeds[lb];
             if (sd >= 0) {
