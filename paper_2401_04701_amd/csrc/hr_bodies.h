@@ -42,6 +42,23 @@ __device__ __forceinline__ void hr_gpre(const hr_env& e, const hr_thread& t, con
     if constexpr (CHECK) hr_check<KIND, GROUP, true>(e, t, g.shadow, g.n, g.id, index, site, pre);
 }
 
+// The two halves of a global hook at a lane-affine site (hr_check_issue /
+// hr_check_settle); `pre` as for hr_gpre when PRE.
+template <int KIND, bool CHECK, bool PRE = false>
+__device__ __forceinline__ hr_pend hr_gi(const hr_env& e, const hr_thread& t, const hr_gref& g,
+                                         uint64_t index, uint64_t pre = 0)
+{
+    if constexpr (CHECK) return hr_check_issue<KIND, PRE>(e, t, g.shadow, g.n, index, pre);
+    return hr_pend{nullptr, 0, 0, 0};
+}
+
+template <int KIND, bool CHECK>
+__device__ __forceinline__ void hr_gs(const hr_env& e, const hr_thread& t, const hr_gref& g,
+                                      const hr_pend& p, uint64_t index, uint32_t site)
+{
+    if constexpr (CHECK) hr_check_settle<KIND>(e, t, p, g.id, index, site);
+}
+
 template <int KIND, bool CHECK>
 __device__ __forceinline__ void hr_l(const hr_env& e, const hr_thread& t, uint32_t* sh,
                                      uint32_t n, uint32_t id, uint32_t index, uint32_t site)
@@ -145,20 +162,28 @@ __device__ void jacobi_body(const hr_env& e, const hr_gref& gold, const hr_gref&
         const float vc = uo[g];
         const float vr = hn || hs ? uo[gr] : 0.0f;
         const float vk = hw || he ? uo[gc] : 0.0f;
-        hr_g<0, CHECK>(e, th, gold, g, HR_SITE_JACOBI_CENTRE);
-        tile[cl] = vc;
+        // Each global hook is settled after the LDS hook of the staging
+        // store that follows it, so the LDS hook runs while the exchange is
+        // in flight.  (The staging hook comes before its store: the store
+        // needs the loaded value, and waiting for it waits for the exchange
+        // too.)
+        const hr_pend pc = hr_gi<0, CHECK>(e, th, gold, g);
         hr_l<1, CHECK>(e, th, tsh, TW, lds_id, cl, HR_SITE_JACOBI_STAGE);
+        tile[cl] = vc;
+        hr_gs<0, CHECK>(e, th, gold, pc, g, HR_SITE_JACOBI_CENTRE);
         if (hn || hs) {
             const uint32_t lr = hn ? tx + 1 : 17 * TL + tx + 1;
-            hr_g<0, CHECK>(e, th, gold, gr, HR_SITE_JACOBI_HALO);
-            tile[lr] = vr;
+            const hr_pend pr = hr_gi<0, CHECK>(e, th, gold, gr);
             hr_l<1, CHECK>(e, th, tsh, TW, lds_id, lr, HR_SITE_JACOBI_STAGE);
+            tile[lr] = vr;
+            hr_gs<0, CHECK>(e, th, gold, pr, gr, HR_SITE_JACOBI_HALO);
         }
         if (hw || he) {
             const uint32_t lc = hw ? (ty + 1) * TL : (ty + 1) * TL + 17;
-            hr_g<0, CHECK>(e, th, gold, gc, HR_SITE_JACOBI_HALO);
-            tile[lc] = vk;
+            const hr_pend pk = hr_gi<0, CHECK>(e, th, gold, gc);
             hr_l<1, CHECK>(e, th, tsh, TW, lds_id, lc, HR_SITE_JACOBI_STAGE);
+            tile[lc] = vk;
+            hr_gs<0, CHECK>(e, th, gold, pk, gc, HR_SITE_JACOBI_HALO);
         }
     }
     hr_bar<CHECK>(e, th);

@@ -265,6 +265,40 @@ __device__ __forceinline__ uint32_t hr_group(uint64_t word_addr, bool* member)
 // this call the thread passes no barrier; if another update (the thread's
 // own included) landed in between, the exchange returns it and the fold
 // merges it back, exactly as for an update that lands inside one hook.
+// What the exchange of a check returned decides its rare paths: a race
+// completed by this access is recorded; an exchange that overwrote updates
+// made since the load is folded back (and a race found by the fold is
+// recorded).  other / other_id: the wave-grouping partner lane, if any.
+template <int KIND>
+__device__ __forceinline__ void hr_settle(const hr_env& e, const hr_thread& t, uint64_t* sp,
+                                          uint32_t region, uint64_t index, uint32_t site,
+                                          uint64_t old, uint64_t nw, uint64_t r, uint32_t other,
+                                          uint64_t other_id)
+{
+    constexpr uint32_t k = KIND == 0 ? hr::CL_R : (KIND == 2 ? hr::CL_A : hr::CL_X);
+    const uint64_t wm = hr::g::group_mask(e.wave_bits);
+    if (nw == hr::T_RACE) {
+        if (r != hr::T_RACE) {
+            // the completing access alone; with a group partner, the pair
+            // of lanes (if they race with each other) or their summary
+            uint64_t before = old, with = hr::g::step(hr::T_INIT, t.gid, k, wm);
+            if (other != HR_NO_LANE) {
+                const uint64_t pair = hr::g::step(with, other_id, k, wm);
+                if (pair == hr::T_RACE) before = hr::g::step(hr::T_INIT, other_id, k, wm);
+                else with = pair;
+            }
+            hr_ring_push(e, 0, region, t.block, index, t.thread, KIND, site, before, with, 0);
+        }
+        return;
+    }
+    if (r != old) {
+        const uint64_t before = hr_fold(sp, nw, r, wm);
+        if (before != HR_NO_REPORT)
+            hr_ring_push(e, 0, region, t.block, index, t.thread, KIND, site, before, r,
+                         HR_RACE_FOLD);
+    }
+}
+
 template <int KIND, bool GROUP = false, bool PRE = false>
 __device__ __forceinline__ void hr_check(const hr_env& e, const hr_thread& t, uint64_t* shadow,
                                          uint64_t n, uint32_t region, uint64_t index,
@@ -295,26 +329,50 @@ __device__ __forceinline__ void hr_check(const hr_env& e, const hr_thread& t, ui
     }
     if (nw == old) return;
     const uint64_t r = __hip_atomic_exchange(sp, nw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (nw == hr::T_RACE) {
-        if (r != hr::T_RACE) {
-            // the completing access alone; with a group partner, the pair
-            // of lanes (if they race with each other) or their summary
-            uint64_t before = old, with = hr::g::step(hr::T_INIT, t.gid, k, wm);
-            if (other != HR_NO_LANE) {
-                const uint64_t pair = hr::g::step(with, other_id, k, wm);
-                if (pair == hr::T_RACE) before = hr::g::step(hr::T_INIT, other_id, k, wm);
-                else with = pair;
-            }
-            hr_ring_push(e, 0, region, t.block, index, t.thread, KIND, site, before, with, 0);
-        }
-        return;
+    hr_settle<KIND>(e, t, sp, region, index, site, old, nw, r, other, other_id);
+}
+
+// A check split in two at a lane-affine site: hr_check_issue publishes the
+// update and returns with the exchange still in flight; hr_check_settle
+// reads what it returned.  Between the two the thread may do other work
+// (LDS hooks, data loads) but passes no barrier, which keeps the fold exact
+// (a thread that has not settled holds back its own barriers).
+struct hr_pend {
+    uint64_t* sp;        // nullptr: nothing to settle
+    uint64_t old, nw, r;
+};
+
+template <int KIND, bool PRE = false>
+__device__ __forceinline__ hr_pend hr_check_issue(const hr_env& e, const hr_thread& t,
+                                                  uint64_t* shadow, uint64_t n, uint64_t index,
+                                                  uint64_t pre = 0)
+{
+    hr_pend p{nullptr, 0, 0, 0};
+    if (t.enabled != 1 || !shadow) return p;
+    hr_count(e, t);
+    if (index >= n) {
+        hr_set_flag(e, HR_DEVF_RANGE);
+        return p;
     }
-    if (r != old) {
-        const uint64_t before = hr_fold(sp, nw, r, wm);
-        if (before != HR_NO_REPORT)
-            hr_ring_push(e, 0, region, t.block, index, t.thread, KIND, site, before, r,
-                         HR_RACE_FOLD);
-    }
+    constexpr uint32_t k = KIND == 0 ? hr::CL_R : (KIND == 2 ? hr::CL_A : hr::CL_X);
+    uint64_t* sp = shadow + index;
+    const uint64_t old =
+        PRE ? pre : __hip_atomic_load(sp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t nw = hr::g::step(old, t.gid, k, hr::g::group_mask(e.wave_bits));
+    if (nw == old) return p;
+    p.sp = sp;
+    p.old = old;
+    p.nw = nw;
+    p.r = __hip_atomic_exchange(sp, nw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return p;
+}
+
+template <int KIND>
+__device__ __forceinline__ void hr_check_settle(const hr_env& e, const hr_thread& t,
+                                                const hr_pend& p, uint32_t region, uint64_t index,
+                                                uint32_t site)
+{
+    if (p.sp) hr_settle<KIND>(e, t, p.sp, region, index, site, p.old, p.nw, p.r, HR_NO_LANE, 0);
 }
 
 // The early load of hr_check<..., PRE = true>: the shadow word of element
