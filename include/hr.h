@@ -293,7 +293,11 @@ hr_status hr_jacobi_plain(const float* u_old_dev, float* u_new_dev, uint32_t ny,
  * l = atomic load of label[v]; for every edge (v, u): atomic min of l into
  * label[u], or, where mask_dev[e] != 0, a plain read and plain write of
  * label[u] (a seeded race).  r_row_ptr / r_col: region ids to also monitor
- * the CSR reads, or UINT32_MAX. */
+ * the CSR reads, or UINT32_MAX.  All pointers must be non-NULL (a graph
+ * without edges still passes some col and mask buffer), else HR_E_INVAL;
+ * row_ptr_dev[n] must not exceed the length of col_dev and mask_dev, which
+ * is not checked (it lies in device memory).  Limits: 1 <= tpb <= 1024,
+ * ceil(n / tpb) < 2^22 blocks. */
 hr_status hr_labelprop_check(hr_ctx c, uint32_t r_label, uint32_t r_row_ptr, uint32_t r_col,
                              int32_t* label_dev, const int32_t* row_ptr_dev,
                              const int32_t* col_dev, const uint8_t* mask_dev, uint32_t n,

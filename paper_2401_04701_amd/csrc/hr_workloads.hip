@@ -207,7 +207,8 @@ extern "C" hr_status hr_labelprop_check(hr_ctx c, uint32_t r_label, uint32_t r_r
                                         const uint8_t* mask_dev, uint32_t n, uint32_t tpb,
                                         void* stream)
 {
-    if (!c || !labelprop_shape_ok(n, tpb) || !hr_region_ok(c, r_label, label_dev, n))
+    if (!c || !row_ptr_dev || !col_dev || !mask_dev || !labelprop_shape_ok(n, tpb) ||
+        !hr_region_ok(c, r_label, label_dev, n))
         return HR_E_INVAL;
     if (r_row_ptr != UINT32_MAX && !hr_region_ok(c, r_row_ptr, row_ptr_dev, (size_t)n + 1))
         return HR_E_INVAL;

@@ -122,7 +122,10 @@ def test_program_empty_and_idle(env):
 
 # --------------------------------------------------------------- Jacobi
 JACOBI = [(64, 64, 3, 6), (50, 37, 2, 5), (33, 80, 4, 8), (96, 17, 3, 4), (16, 16, 2, 0),
-          (256, 192, 3, 20)]
+          (256, 192, 3, 20),
+          # degenerate shapes: one cell, one row, one column, one past a tile
+          (1, 1, 2, 0), (2, 2, 3, 0), (1, 40, 3, 2), (40, 1, 3, 2), (1, 17, 2, 1), (17, 17, 3, 2),
+          (15, 33, 2, 1)]
 
 
 def run_jacobi(torch, hr, ny, nx, launches, tab, ctx_kwargs=None, grid_seed=1):
@@ -193,6 +196,51 @@ def test_labelprop_flagged_set(env, scale, edges, p, tpb, grouping):
     assert got == oracle.flagged(log) == cf.labelprop_flagged(rp, col, mask)
 
 
+def _lp_case(name):
+    """Degenerate graphs: (row_ptr, col, mask) and the vertex count."""
+    n = 70
+    if name == "one_vertex":
+        return [0, 0], [], []
+    if name == "no_edges":
+        return [0] * (n + 1), [], []
+    if name == "self_loops_seeded":        # no other thread touches label[v]
+        return list(range(n + 1)), list(range(n)), [1] * n
+    if name == "star_out_seeded":          # vertex 0 writes every other label
+        return [0] + [n - 1] * n, list(range(1, n)), [1] * (n - 1)
+    if name == "star_in_seeded":           # every vertex writes label[0]
+        return [0] + list(range(n)), [0] * (n - 1), [1] * (n - 1)
+    if name == "star_in_atomic":           # the same with atomics only
+        return [0] + list(range(n)), [0] * (n - 1), [0] * (n - 1)
+    raise ValueError(name)
+
+
+@pytest.mark.parametrize("name", ["one_vertex", "no_edges", "self_loops_seeded", "star_out_seeded",
+                                  "star_in_seeded", "star_in_atomic"])
+@pytest.mark.parametrize("tpb", [1, 64, 1024])
+def test_labelprop_degenerate_graphs(env, name, tpb):
+    torch, hr = env
+    rp, col, mask = (np.asarray(x, dtype=t) for x, t in zip(_lp_case(name),
+                                                           (np.int32, np.int32, np.uint8)))
+    n = rp.shape[0] - 1
+    say("labelprop degenerate", name, "tpb", tpb)
+    label = torch.arange(n, dtype=torch.int32, device="cuda")
+    rp_d = torch.from_numpy(rp).cuda()
+    # an edge-free graph still hands the kernel some col / mask buffer
+    col_d = torch.from_numpy(col if col.size else np.zeros(1, np.int32)).cuda()
+    mask_d = torch.from_numpy(mask if mask.size else np.zeros(1, np.uint8)).cuda()
+    with hr.Context(count_checks=True) as ctx:
+        r_lab = ctx.shadow_alloc(label)
+        for L in range(2):
+            ctx.labelprop_check(r_lab, label, rp_d, col_d, mask_d, tpb=tpb)
+            ctx.kernel_end()
+        got = ctx.flagged()
+        cnt = ctx.check_count()
+        assert ctx.status == 0
+    log = oracle.model_labelprop(rp, col, mask, 2, tpb)
+    assert cnt == log.shape[0]
+    assert got == oracle.flagged(log) == cf.labelprop_flagged(rp, col, mask)
+
+
 # ----------------------------------------------------- failure handling
 def test_clock_overflow_stops_with_warning(env):
     """bc_bits=2 allows 3 block barriers; a 6-barrier program overflows.  The
@@ -252,6 +300,21 @@ def test_shadow_budget_and_bad_arguments(env):
         y = torch.zeros(256, dtype=torch.int32, device="cuda")
         with pytest.raises(hr.HRError):          # region too small for 512 inputs
             ctx.reduce_check(r, r, y, y, -1)
+    say("labelprop argument checks")
+    with hr.Context() as ctx:
+        lab = torch.zeros(64, dtype=torch.int32, device="cuda")
+        rp = torch.zeros(65, dtype=torch.int32, device="cuda")
+        r_lab = ctx.shadow_alloc(lab)
+
+        def raw(ptrs, tpb):          # the C entry point itself, without the binding's checks
+            return hr._lib.hr_labelprop_check(ctx._c, r_lab, hr.NO_REGION, hr.NO_REGION,
+                                              *ptrs, 64, tpb, None)
+        for bad in ((0, 1, 1, 1), (1, 0, 1, 1), (1, 1, 0, 1), (1, 1, 1, 0)):
+            ptrs = [t.data_ptr() if ok else None for t, ok in zip((lab, rp, rp, rp), bad)]
+            assert raw(ptrs, 64) == hr.HR_E_INVAL, bad
+        good = [lab.data_ptr(), rp.data_ptr(), rp.data_ptr(), rp.data_ptr()]
+        assert raw(good, 2048) == hr.HR_E_INVAL     # more than 1024 threads per block
+        assert raw(good, 0) == hr.HR_E_INVAL
 
 
 def test_launch_epoch_wrap(env):
