@@ -404,9 +404,9 @@ hr_status hr_job_run(const hr_instance* inst, const hr_config* cfg, hr_race* out
  * A job's launches run one after another (Sec. II-B: a kernel boundary
  * orders everything before it), so a device iteration may run the next
  * phase of every resident job side by side.  Jobs are admitted in arrival
- * order between iterations, while a job slot and shadow memory under the
- * budget are free; a job's shadow words stay resident until its last phase
- * has been reported.
+ * order between iterations, while a job slot, shadow memory under the
+ * budget and room under the iteration's item cap are free; a job's shadow
+ * words stay resident until its last phase has been reported.
  * ---------------------------------------------------------------------- */
 
 typedef struct {
@@ -424,7 +424,15 @@ typedef struct {
     uint32_t max_slots;      /* jobs resident at once, < 2^20; 0: 1024 */
     uint32_t serial;         /* nonzero: replay the arrivals one job at a time
                                 through hr_job_run (the plain path) */
+    uint32_t max_items;      /* work items (1024-thread blocks) of the resident
+                                jobs' phases in one iteration, at most
+                                HR_SERVE_MAX_ITEMS; 0: HR_SERVE_MAX_ITEMS */
+    uint32_t pad;
 } hr_serve_config;
+
+/* One iteration is one launch of 1024-thread blocks, whose grid may not
+ * exceed 2^32 - 1 threads. */
+#define HR_SERVE_MAX_ITEMS ((1u << 22) - 1u)
 
 /* Check n_jobs jobs (hr_instance as for hr_batch_create; region[] unused)
  * arriving at times[j].arrival_s, on the context's device and `stream`, and
@@ -434,9 +442,10 @@ typedef struct {
  * receives every job's deduplicated records, sorted by (region, space,
  * block if LDS, index); *n_out is their number.  The context's ring and
  * counters are reused by every iteration; its regions are not touched.
- * Errors: HR_E_INVAL (a job's shape, unsorted arrivals, cap too small: then
- * *n_out holds the number needed), HR_E_NOMEM (a job larger than the
- * budget, or the device allocation failed), HR_E_HIP. */
+ * Errors: HR_E_INVAL (a job's shape, unsorted arrivals, max_items above
+ * HR_SERVE_MAX_ITEMS, a job with more items per phase than max_items, cap
+ * too small: then *n_out holds the number needed), HR_E_NOMEM (a job larger
+ * than the budget, or the device allocation failed), HR_E_HIP. */
 hr_status hr_serve(hr_ctx c, const hr_instance* jobs, hr_serve_job* times, uint32_t n_jobs,
                    const hr_serve_config* cfg, hr_race* out, size_t cap, size_t* n_out,
                    void* stream);

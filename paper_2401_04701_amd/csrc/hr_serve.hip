@@ -95,6 +95,7 @@ struct job_state {
     hr_instance in;
     size_t elems[2] = {0, 0};
     uint64_t off = 0, granules = 0;   // arena placement
+    uint32_t items = 0;               // work items of one phase
     uint32_t slot = 0, phase = 0;
     int32_t status = 0;
 };
@@ -184,6 +185,8 @@ hr_status serve_continuous(hr_ctx c, const hr_instance* jobs, hr_serve_job* time
         const uint64_t words = js[j].elems[0] + js[j].elems[1];
         js[j].granules = (words + GRANULE_WORDS - 1) / GRANULE_WORDS + 1;
         if (js[j].granules > budget_granules) return HR_E_NOMEM;   // could never be admitted
+        js[j].items = hr_make_inst_dev(js[j].in, js[j].elems, nullptr, nullptr, 0, 0, 0).items;
+        if (js[j].items > cfg.max_items) return HR_E_INVAL;         // nor this one
         need += js[j].granules;
     }
     // the arena never needs more than every job at once
@@ -213,14 +216,18 @@ hr_status serve_continuous(hr_ctx c, const hr_instance* jobs, hr_serve_job* time
     hr_env env_base = hr_make_env(c);
     env_base.site_limit = 0;   // site ids are per job; the limit does not apply here
     uint32_t next = 0;
+    uint64_t resident_items = 0;   // items of one iteration over the resident jobs
     const auto t0 = clock_t_::now();
     for (;;) {
-        // admit arrived jobs in order while a slot and shadow memory are free
+        // admit arrived jobs in order while a slot, shadow memory and room
+        // under the item cap are free
         const double now = seconds_since(t0);
         while (next < n && times[next].arrival_s <= now && !free_slots.empty()) {
             job_state& st = js[next];
+            if (resident_items + st.items > cfg.max_items) break;
             uint64_t off = 0;
             if (!arena.alloc(st.granules, &off)) break;
+            resident_items += st.items;
             st.off = off;
             st.slot = free_slots.back();
             free_slots.pop_back();
@@ -249,7 +256,6 @@ hr_status serve_continuous(hr_ctx c, const hr_instance* jobs, hr_serve_job* time
             total += b.h_desc[st.slot].items;
         }
         b.h_prefix[active.size()] = total;
-        if (total >= (1ull << 32)) return HR_E_INVAL;
         if (hipMemcpyAsync(b.act, b.h_act, sizeof(uint32_t) * active.size(),
                            hipMemcpyHostToDevice, s) != hipSuccess ||
             hipMemcpyAsync(b.prefix, b.h_prefix, sizeof(uint64_t) * (active.size() + 1),
@@ -305,6 +311,7 @@ hr_status serve_continuous(hr_ctx c, const hr_instance* jobs, hr_serve_job* time
             }
             times[j].finish_s = end;
             times[j].status = st.status;
+            resident_items -= st.items;
             arena.release(st.off, st.granules);
             free_slots.push_back(st.slot);
         }
@@ -339,7 +346,8 @@ extern "C" hr_status hr_serve(hr_ctx c, const hr_instance* jobs, hr_serve_job* t
     if (cfg_in) cfg = *cfg_in;
     if (cfg.max_slots == 0) cfg.max_slots = 1024;
     if (cfg.shadow_budget == 0) cfg.shadow_budget = 64ull << 30;
-    if (cfg.max_slots >= (1u << 20)) return HR_E_INVAL;
+    if (cfg.max_items == 0) cfg.max_items = HR_SERVE_MAX_ITEMS;
+    if (cfg.max_slots >= (1u << 20) || cfg.max_items > HR_SERVE_MAX_ITEMS) return HR_E_INVAL;
     for (uint32_t j = 0; j < n_jobs; ++j) {
         times[j].admit_s = times[j].finish_s = -1.0;
         times[j].flagged = 0;

@@ -98,11 +98,15 @@ class ServeJob(ctypes.Structure):
 
 class _ServeConfig(ctypes.Structure):
     _fields_ = [("shadow_budget", ctypes.c_uint64), ("max_slots", ctypes.c_uint32),
-                ("serial", ctypes.c_uint32)]
+                ("serial", ctypes.c_uint32), ("max_items", ctypes.c_uint32),
+                ("pad", ctypes.c_uint32)]
 
+
+SERVE_MAX_ITEMS = (1 << 22) - 1    # work items of one serving iteration (one launch)
 
 assert ctypes.sizeof(Instance) == 72
 assert ctypes.sizeof(ServeJob) == 32
+assert ctypes.sizeof(_ServeConfig) == 24
 
 
 def _load():
@@ -414,17 +418,19 @@ def job_run(inst: Instance, ring_capacity=0, stream=None):
 
 
 def serve(ctx: Context, instances, arrivals, shadow_budget=0, max_slots=0, serial=False,
-          stream=None):
+          max_items=0, stream=None):
     """Check a stream of jobs arriving at `arrivals` (seconds from the call,
     non-decreasing) with continuous batching, or one at a time (serial).
-    Returns (per-job flagged keys with job-local region ids 0/1, ServeJob
-    array with admission/finish times, flagged counts and warning bits)."""
+    max_items caps the work items (1024-thread blocks) of one iteration
+    (0: SERVE_MAX_ITEMS).  Returns (per-job flagged keys with job-local
+    region ids 0/1, ServeJob array with admission/finish times, flagged
+    counts and warning bits)."""
     n = len(instances)
     inst = (Instance * n)(*instances)
     times = (ServeJob * n)()
     for j, a in enumerate(arrivals):
         times[j].arrival_s = float(a)
-    cfg = _ServeConfig(int(shadow_budget), int(max_slots), int(bool(serial)))
+    cfg = _ServeConfig(int(shadow_budget), int(max_slots), int(bool(serial)), int(max_items), 0)
     cnt = ctypes.c_size_t(0)
     cap = 1 << 20          # a larger count re-runs the whole stream
     while True:

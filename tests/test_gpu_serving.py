@@ -62,6 +62,21 @@ def shadow_bytes(spec):
     return ((words + 31) // 32 + 1) * 256
 
 
+def items_of(spec):
+    """Work items (1024-thread blocks) of one phase of a job: its blocks
+    packed 1024 / threads to an item."""
+    p = spec["pattern"]
+    if p == si.PAT_REDUCE:
+        blocks, threads = spec["blocks"], spec["threads"]
+    elif p == si.PAT_JACOBI:
+        blocks, threads = -(-spec["ny"] // 16) * -(-spec["nx"] // 16), 256
+    else:
+        threads = spec["threads"]
+        blocks = -(-spec["vertices"] // threads)
+    pack = 1024 // threads
+    return -(-blocks // pack)
+
+
 @pytest.fixture(scope="module")
 def stream(env):
     torch, hr, jobs = env
@@ -137,4 +152,43 @@ def test_serving_rejects_job_over_budget(env, stream):
         arrivals[3], arrivals[2] = 1.0, 2.0         # unsorted arrivals
         with pytest.raises(hr.HRError) as e:
             hr.serve(ctx, [j.inst for j in js], arrivals)
+        assert e.value.status == hr.HR_E_INVAL
+
+
+def test_serving_item_cap(env, stream):
+    """An iteration holds at most max_items work items: with the cap at the
+    largest job's items, jobs wait for room, the results stay those of each
+    job alone, and no two jobs whose items together exceed the cap are ever
+    resident together."""
+    torch, hr, jobs = env
+    specs, js, want = stream
+    items = [items_of(s) for s in specs]
+    cap = max(items)
+    arrivals = si.poisson_arrivals(9, len(js), 5000.0)
+    say("serve with item cap", cap, "items per job", sorted(items)[-5:])
+    with hr.Context(ring_capacity=1 << 16) as ctx:
+        per, times = hr.serve(ctx, [j.inst for j in js], arrivals, max_items=cap)
+    for i, (w, p) in enumerate(zip(want, per)):
+        assert p == w, (i, specs[i])
+        assert times[i].status == 0
+    # resident intervals [admit, finish): the items of the jobs resident at
+    # any admission never exceed the cap
+    iv = [(t.admit_s, t.finish_s) for t in times]
+    for i, (a, _) in enumerate(iv):
+        resident = sum(items[k] for k, (b, f) in enumerate(iv) if b <= a < f)
+        assert resident <= cap, (i, resident)
+    say("  item cap held")
+
+
+def test_serving_item_cap_arguments(env, stream):
+    torch, hr, jobs = env
+    specs, js, want = stream
+    items = [items_of(s) for s in specs]
+    arrivals = np.zeros(len(js))
+    with hr.Context() as ctx:
+        with pytest.raises(hr.HRError) as e:        # a job that can never fit
+            hr.serve(ctx, [j.inst for j in js], arrivals, max_items=max(items) - 1)
+        assert e.value.status == hr.HR_E_INVAL
+        with pytest.raises(hr.HRError) as e:        # above the launch limit
+            hr.serve(ctx, [j.inst for j in js], arrivals, max_items=hr.SERVE_MAX_ITEMS + 1)
         assert e.value.status == hr.HR_E_INVAL
