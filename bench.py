@@ -12,7 +12,8 @@ report (device-to-host copy of the flagged set).
 
 Prints one JSON line: checks/s, slowdown against the same kernel without
 hooks, p50/p99 per-launch latency, the roofline of the instrumented kernel,
-measured device peaks, and the CPU oracle timed on a sample of the job.
+measured device peaks, and the CPU oracle timed on a sample of the job, on
+one core and on the host threads available (at most 16).
 """
 from __future__ import annotations
 
@@ -97,6 +98,45 @@ def cpu_baseline():
             "sample": f"{n}x{n} grid ({n * n / (NY * NX):.4f} of the cells), {LAUNCHES} launches, "
                       f"{len(seeds)} seeded blocks: access-log generation plus pairwise check, "
                       f"{checks} checks in {dt:.1f} s, {len(flagged)} flagged",
+            "seconds": dt}
+
+
+def _oracle_ready(_):
+    import oracle
+    oracle._lib()
+    return os.getpid()
+
+
+def _oracle_launch(job):
+    """One launch of the sampled job through the oracle (a worker task)."""
+    import oracle
+    n, L, tab = job
+    log = oracle.model_jacobi(n, n, 1, tab, launch0=L)
+    return int(log.shape[0]), oracle.flagged(log)
+
+
+def cpu_baseline_parallel():
+    """The same oracle on the same sample with its launches spread over
+    worker processes, one launch per task (a launch boundary orders every
+    access of a launch before the next launch, so races never span two
+    launches).  Workers: the host threads this process may use, at most 16.
+    The pool is started and warm before the timed region."""
+    import multiprocessing as mp
+    import synth_inputs as si
+    n = 768
+    seeds = si.jacobi_seeds(n, n, si.master_seed(1))
+    tab = si.jacobi_seed_table(n, n, seeds)
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    with mp.get_context("spawn").Pool(workers) as pool:
+        pool.map(_oracle_ready, range(4 * workers), chunksize=1)
+        t0 = time.perf_counter()
+        res = pool.map(_oracle_launch, [(n, L, tab) for L in range(LAUNCHES)], chunksize=1)
+        dt = time.perf_counter() - t0
+    checks = sum(c for c, _ in res)
+    flagged = set().union(*(f for _, f in res))
+    return {"value": checks / dt, "unit": "checks/s", "cores": workers, "kind": "oracle",
+            "sample": f"{n}x{n} grid, {LAUNCHES} launches over {workers} worker processes, "
+                      f"{checks} checks in {dt:.2f} s, {len(flagged)} flagged",
             "seconds": dt}
 
 
@@ -556,6 +596,7 @@ def main():
                             "frac": g_rate / peaks["xchg_coalesced_per_s"], **peaks}
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline()
+        result["cpu_baseline_parallel"] = cpu_baseline_parallel()
     print(json.dumps(result), flush=True)
 
 
