@@ -149,44 +149,114 @@ hr_status serve_serial(hr_ctx c, const hr_instance* jobs, hr_serve_job* times, u
     return HR_OK;
 }
 
+// Jobs run in lanes by class: a lane has its own stream, ring and counters
+// and runs its iterations one after another, while the lanes' iterations
+// overlap on the device.  An iteration lasts as long as its slowest item,
+// so jobs whose phases are long (label propagation, bound by the edge list
+// of its largest hub; jobs of many items) would hold back the short jobs
+// sharing their iterations.
+constexpr uint32_t N_LANES = 3;
+constexpr uint32_t LANE_SHORT = 0, LANE_GRAPH = 1, LANE_LARGE = 2;
+constexpr uint32_t LARGE_ITEMS = 1024;   // items per phase above which a job is large
+
+uint32_t lane_of(const hr_instance& in, uint32_t items)
+{
+    if (in.pattern == HR_PAT_LABELPROP) return LANE_GRAPH;
+    return items > LARGE_ITEMS ? LANE_LARGE : LANE_SHORT;
+}
+
+struct lane_state {
+    hipStream_t s = nullptr;
+    bool own_stream = false;
+    hipEvent_t done = nullptr;
+    hr_race_rec* ring = nullptr;     // the context's ring and counters for the
+    uint32_t* ctr = nullptr;         // first lane, own ones for the others
+    bool own_ring = false;
+    uint32_t* act = nullptr;         // device copies of the iteration's job list
+    uint64_t* prefix = nullptr;
+    uint32_t* h_act = nullptr;       // pinned staging
+    uint64_t* h_prefix = nullptr;
+    uint32_t* h_ctr = nullptr;       // counters after the iteration
+    size_t lds = 0;                  // dynamic LDS of the lane's iterations
+    std::vector<uint32_t> jobs;      // resident jobs of the lane
+    std::vector<uint32_t> running;   // the jobs of the iteration in flight
+    bool in_flight = false;
+};
+
 struct serve_buffers {
     uint64_t* arena = nullptr;
     hr_inst_dev* slots = nullptr;
-    uint32_t* act = nullptr;
-    uint64_t* prefix = nullptr;
-    uint32_t* h_act = nullptr;      // pinned staging
-    uint64_t* h_prefix = nullptr;
-    hr_inst_dev* h_desc = nullptr;
+    hr_inst_dev* h_desc = nullptr;   // pinned staging
+    lane_state lane[N_LANES];
     ~serve_buffers()
     {
+        for (lane_state& L : lane)
+            if (L.s) (void)hipStreamSynchronize(L.s);   // nothing in flight uses what is freed
+        for (lane_state& L : lane) {
+            if (L.own_stream && L.s) (void)hipStreamDestroy(L.s);
+            if (L.done) (void)hipEventDestroy(L.done);
+            if (L.own_ring) {
+                if (L.ring) (void)hipFree(L.ring);
+                if (L.ctr) (void)hipFree(L.ctr);
+            }
+            if (L.act) (void)hipFree(L.act);
+            if (L.prefix) (void)hipFree(L.prefix);
+            if (L.h_act) (void)hipHostFree(L.h_act);
+            if (L.h_prefix) (void)hipHostFree(L.h_prefix);
+            if (L.h_ctr) (void)hipHostFree(L.h_ctr);
+        }
         if (arena) (void)hipFree(arena);
         if (slots) (void)hipFree(slots);
-        if (act) (void)hipFree(act);
-        if (prefix) (void)hipFree(prefix);
-        if (h_act) (void)hipHostFree(h_act);
-        if (h_prefix) (void)hipHostFree(h_prefix);
         if (h_desc) (void)hipHostFree(h_desc);
     }
 };
 
+hr_status lane_init(lane_state& L, hr_ctx c, hipStream_t caller, bool first, uint32_t max_slots)
+{
+    if (first) {
+        L.s = caller;
+        L.ring = c->ring;
+        L.ctr = c->ctr;
+    } else {
+        if (hipStreamCreateWithFlags(&L.s, hipStreamNonBlocking) != hipSuccess) return HR_E_HIP;
+        L.own_stream = true;
+        L.own_ring = true;
+        if (hipMalloc(&L.ring, sizeof(hr_race_rec) * std::max(1u, c->cfg.ring_capacity)) !=
+                hipSuccess ||
+            hipMalloc(&L.ctr, sizeof(uint32_t) * HR_CTR_WORDS) != hipSuccess)
+            return HR_E_NOMEM;
+    }
+    if (hipEventCreateWithFlags(&L.done, hipEventDisableTiming) != hipSuccess) return HR_E_HIP;
+    if (hipMalloc(&L.act, sizeof(uint32_t) * max_slots) != hipSuccess ||
+        hipMalloc(&L.prefix, sizeof(uint64_t) * (max_slots + 1)) != hipSuccess ||
+        hipHostMalloc(&L.h_act, sizeof(uint32_t) * max_slots, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(&L.h_prefix, sizeof(uint64_t) * (max_slots + 1), hipHostMallocDefault) !=
+            hipSuccess ||
+        hipHostMalloc(&L.h_ctr, sizeof(uint32_t) * HR_CTR_SITES, hipHostMallocDefault) !=
+            hipSuccess)
+        return HR_E_NOMEM;
+    return HR_OK;
+}
+
 hr_status serve_continuous(hr_ctx c, const hr_instance* jobs, hr_serve_job* times, uint32_t n,
                            const hr_serve_config& cfg, std::vector<hr_race>& all, void* stream)
 {
-    hipStream_t s = hr_stream(c, stream);
     std::vector<job_state> js(n);
-    size_t lds = 0;
+    std::vector<uint32_t> lane_of_job(n);
+    size_t lds[N_LANES] = {0, 0, 0};
     const uint64_t budget_granules = cfg.shadow_budget / (GRANULE_WORDS * 8);
     uint64_t need = 0;
     for (uint32_t j = 0; j < n; ++j) {
         js[j].in = jobs[j];
         size_t l = 0;
         if (!hr_instance_shape(js[j].in, js[j].elems, &l)) return HR_E_INVAL;
-        lds = std::max(lds, l);
         const uint64_t words = js[j].elems[0] + js[j].elems[1];
         js[j].granules = (words + GRANULE_WORDS - 1) / GRANULE_WORDS + 1;
         if (js[j].granules > budget_granules) return HR_E_NOMEM;   // could never be admitted
         js[j].items = hr_make_inst_dev(js[j].in, js[j].elems, nullptr, nullptr, 0, 0, 0).items;
         if (js[j].items > cfg.max_items) return HR_E_INVAL;         // nor this one
+        lane_of_job[j] = lane_of(js[j].in, js[j].items);
+        lds[lane_of_job[j]] = std::max(lds[lane_of_job[j]], l);
         need += js[j].granules;
     }
     // the arena never needs more than every job at once
@@ -195,32 +265,36 @@ hr_status serve_continuous(hr_ctx c, const hr_instance* jobs, hr_serve_job* time
     serve_buffers b;
     if (hipMalloc(&b.arena, arena_granules * GRANULE_WORDS * 8) != hipSuccess ||
         hipMalloc(&b.slots, sizeof(hr_inst_dev) * max_slots) != hipSuccess ||
-        hipMalloc(&b.act, sizeof(uint32_t) * max_slots) != hipSuccess ||
-        hipMalloc(&b.prefix, sizeof(uint64_t) * (max_slots + 1)) != hipSuccess ||
-        hipHostMalloc(&b.h_act, sizeof(uint32_t) * max_slots, hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc(&b.h_prefix, sizeof(uint64_t) * (max_slots + 1), hipHostMallocDefault) !=
-            hipSuccess ||
         hipHostMalloc(&b.h_desc, sizeof(hr_inst_dev) * max_slots, hipHostMallocDefault) !=
             hipSuccess)
         return HR_E_NOMEM;
-    int per_cu = 0;   // the iteration kernel must fit with the largest item's LDS
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_iter, HR_WORKER_THREADS, lds) !=
-            hipSuccess ||
-        per_cu <= 0)
-        return HR_E_HIP;
+    hr_env env[N_LANES];
+    const hr_env env_base = hr_make_env(c);
+    for (uint32_t k = 0; k < N_LANES; ++k) {
+        lane_state& L = b.lane[k];
+        const hr_status st = lane_init(L, c, hr_stream(c, stream), k == 0, max_slots);
+        if (st != HR_OK) return st;
+        L.lds = lds[k];
+        int per_cu = 0;   // the iteration kernel must fit with the lane's largest LDS
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_iter, HR_WORKER_THREADS,
+                                                         L.lds) != hipSuccess ||
+            per_cu <= 0)
+            return HR_E_HIP;
+        env[k] = env_base;
+        env[k].ring = L.ring;
+        env[k].ctr = L.ctr;
+        env[k].site_limit = 0;   // site ids are per job; the limit does not apply here
+    }
     arena_alloc arena(arena_granules);
     std::vector<uint32_t> free_slots;
     for (uint32_t k = max_slots; k-- > 0;) free_slots.push_back(k);
-    std::vector<uint32_t> active;
     std::vector<hr_race> ring(c->cfg.ring_capacity);
-    hr_env env_base = hr_make_env(c);
-    env_base.site_limit = 0;   // site ids are per job; the limit does not apply here
-    uint32_t next = 0;
-    uint64_t resident_items = 0;   // items of one iteration over the resident jobs
+    uint32_t next = 0, finished = 0;
+    uint64_t resident_items = 0;   // items of one phase of every resident job
     const auto t0 = clock_t_::now();
-    for (;;) {
+    while (finished < n) {
         // admit arrived jobs in order while a slot, shadow memory and room
-        // under the item cap are free
+        // under the item cap are free; a job joins its lane's next iteration
         const double now = seconds_since(t0);
         while (next < n && times[next].arrival_s <= now && !free_slots.empty()) {
             job_state& st = js[next];
@@ -231,91 +305,127 @@ hr_status serve_continuous(hr_ctx c, const hr_instance* jobs, hr_serve_job* time
             st.off = off;
             st.slot = free_slots.back();
             free_slots.pop_back();
+            lane_state& L = b.lane[lane_of_job[next]];
             uint64_t* sh0 = b.arena + off * GRANULE_WORDS;
             uint64_t* sh1 = st.elems[1] ? sh0 + st.elems[0] : nullptr;
-            if (hr_fill64(sh0, st.elems[0] + st.elems[1], s) != hipSuccess) return HR_E_HIP;
+            if (hr_fill64(sh0, st.elems[0] + st.elems[1], L.s) != hipSuccess) return HR_E_HIP;
             b.h_desc[st.slot] = hr_make_inst_dev(st.in, st.elems, sh0, sh1, 2 * next, 2 * next + 1, 0);
             if (hipMemcpyAsync(b.slots + st.slot, b.h_desc + st.slot, sizeof(hr_inst_dev),
-                               hipMemcpyHostToDevice, s) != hipSuccess)
+                               hipMemcpyHostToDevice, L.s) != hipSuccess)
                 return HR_E_HIP;
             times[next].admit_s = now;
-            active.push_back(next);
+            L.jobs.push_back(next);
             ++next;
         }
-        if (active.empty()) {
-            if (next >= n) break;
-            wait_until(t0, times[next].arrival_s);
-            continue;
+        // an idle lane with resident jobs starts its next iteration: the next
+        // phase of each of them
+        for (uint32_t k = 0; k < N_LANES; ++k) {
+            lane_state& L = b.lane[k];
+            if (L.in_flight || L.jobs.empty()) continue;
+            uint64_t total = 0;
+            for (size_t q = 0; q < L.jobs.size(); ++q) {
+                const job_state& st = js[L.jobs[q]];
+                L.h_prefix[q] = total;
+                L.h_act[q] = st.slot | (st.phase << 20);
+                total += st.items;
+            }
+            L.h_prefix[L.jobs.size()] = total;
+            if (hipMemcpyAsync(L.act, L.h_act, sizeof(uint32_t) * L.jobs.size(),
+                               hipMemcpyHostToDevice, L.s) != hipSuccess ||
+                hipMemcpyAsync(L.prefix, L.h_prefix, sizeof(uint64_t) * (L.jobs.size() + 1),
+                               hipMemcpyHostToDevice, L.s) != hipSuccess ||
+                hr_fill32(L.ctr, HR_CTR_WORDS, L.s) != hipSuccess)
+                return HR_E_HIP;
+            HR_LAUNCH(k_iter, dim3((uint32_t)total), dim3(HR_WORKER_THREADS), L.lds, L.s, env[k],
+                      b.slots, L.act, L.prefix, (uint32_t)L.jobs.size());
+            if (hipMemcpyAsync(L.h_ctr, L.ctr, sizeof(uint32_t) * HR_CTR_SITES,
+                               hipMemcpyDeviceToHost, L.s) != hipSuccess ||
+                hipEventRecord(L.done, L.s) != hipSuccess)
+                return HR_E_HIP;
+            L.running = L.jobs;
+            L.in_flight = true;
         }
-        // one iteration: the next phase of every resident job
-        uint64_t total = 0;
-        for (size_t k = 0; k < active.size(); ++k) {
-            const job_state& st = js[active[k]];
-            b.h_prefix[k] = total;
-            b.h_act[k] = st.slot | (st.phase << 20);
-            total += b.h_desc[st.slot].items;
-        }
-        b.h_prefix[active.size()] = total;
-        if (hipMemcpyAsync(b.act, b.h_act, sizeof(uint32_t) * active.size(),
-                           hipMemcpyHostToDevice, s) != hipSuccess ||
-            hipMemcpyAsync(b.prefix, b.h_prefix, sizeof(uint64_t) * (active.size() + 1),
-                           hipMemcpyHostToDevice, s) != hipSuccess ||
-            hr_fill32(c->ctr, HR_CTR_WORDS, s) != hipSuccess)
-            return HR_E_HIP;
-        HR_LAUNCH(k_iter, dim3((uint32_t)total), dim3(HR_WORKER_THREADS), lds, s, env_base, b.slots,
-                  b.act, b.prefix, (uint32_t)active.size());
-        uint32_t ctr[HR_CTR_SITES];
-        if (hipMemcpyAsync(ctr, c->ctr, sizeof(ctr), hipMemcpyDeviceToHost, s) != hipSuccess ||
-            hipStreamSynchronize(s) != hipSuccess)
-            return HR_E_HIP;
-        const uint32_t got = std::min(ctr[HR_CTR_HEAD], c->cfg.ring_capacity);
-        if (got && hipMemcpy(ring.data(), c->ring, sizeof(hr_race_rec) * got,
-                             hipMemcpyDeviceToHost) != hipSuccess)
-            return HR_E_HIP;
-        // the descriptors carry 2*job (+1) as report ids
-        all.insert(all.end(), ring.begin(), ring.begin() + got);
-        int warn = 0;
-        if (ctr[HR_CTR_FLAGS] & HR_DEVF_CLOCK) warn |= HR_W_CLOCK_OVERFLOW;
-        if (ctr[HR_CTR_FLAGS] & HR_DEVF_RANGE) warn |= HR_W_OUT_OF_RANGE;
-        if (ctr[HR_CTR_HEAD] > c->cfg.ring_capacity) {
-            // recover the global part of every resident job from its sticky
-            // race words
-            warn |= HR_W_RING_OVERFLOW;
-            for (uint32_t j : active) {
-                const job_state& st = js[j];
-                std::vector<uint64_t> sh(st.elems[0] + st.elems[1]);
-                if (hipMemcpy(sh.data(), b.arena + st.off * GRANULE_WORDS, 8 * sh.size(),
-                              hipMemcpyDeviceToHost) != hipSuccess)
-                    return HR_E_HIP;
-                for (size_t i = 0; i < sh.size(); ++i) {
-                    if ((sh[i] & hr::g::TAG_M) != hr::T_RACE) continue;
-                    hr_race r = {};
-                    r.space = HR_GLOBAL;
-                    r.region = 2 * j + (i >= st.elems[0] ? 1 : 0);
-                    r.index = i >= st.elems[0] ? i - st.elems[0] : i;
-                    r.block = r.launch = r.tid = 0xFFFFFFFFu;
-                    r.flags = HR_RACE_SCANNED;
-                    all.push_back(r);
+        // collect the lanes whose iteration has finished
+        bool progressed = false;
+        for (uint32_t k = 0; k < N_LANES; ++k) {
+            lane_state& L = b.lane[k];
+            if (!L.in_flight) continue;
+            const hipError_t q = hipEventQuery(L.done);
+            if (q == hipErrorNotReady) continue;
+            if (q != hipSuccess) return HR_E_HIP;
+            L.in_flight = false;
+            progressed = true;
+            const uint32_t head = L.h_ctr[HR_CTR_HEAD], flags = L.h_ctr[HR_CTR_FLAGS];
+            const uint32_t got = std::min(head, c->cfg.ring_capacity);
+            if (got && (hipMemcpyAsync(ring.data(), L.ring, sizeof(hr_race_rec) * got,
+                                       hipMemcpyDeviceToHost, L.s) != hipSuccess ||
+                        hipStreamSynchronize(L.s) != hipSuccess))
+                return HR_E_HIP;
+            // the descriptors carry 2*job (+1) as report ids
+            all.insert(all.end(), ring.begin(), ring.begin() + got);
+            int warn = 0;
+            if (flags & HR_DEVF_CLOCK) warn |= HR_W_CLOCK_OVERFLOW;
+            if (flags & HR_DEVF_RANGE) warn |= HR_W_OUT_OF_RANGE;
+            if (head > c->cfg.ring_capacity) {
+                // recover the global part of the iteration's jobs from their
+                // sticky race words
+                warn |= HR_W_RING_OVERFLOW;
+                for (uint32_t j : L.running) {
+                    const job_state& st = js[j];
+                    std::vector<uint64_t> sh(st.elems[0] + st.elems[1]);
+                    if (hipMemcpyAsync(sh.data(), b.arena + st.off * GRANULE_WORDS, 8 * sh.size(),
+                                       hipMemcpyDeviceToHost, L.s) != hipSuccess ||
+                        hipStreamSynchronize(L.s) != hipSuccess)
+                        return HR_E_HIP;
+                    for (size_t i = 0; i < sh.size(); ++i) {
+                        if ((sh[i] & hr::g::TAG_M) != hr::T_RACE) continue;
+                        hr_race r = {};
+                        r.space = HR_GLOBAL;
+                        r.region = 2 * j + (i >= st.elems[0] ? 1 : 0);
+                        r.index = i >= st.elems[0] ? i - st.elems[0] : i;
+                        r.block = r.launch = r.tid = 0xFFFFFFFFu;
+                        r.flags = HR_RACE_SCANNED;
+                        all.push_back(r);
+                    }
                 }
             }
-        }
-        // advance, and retire the jobs whose last phase just ran
-        const double end = seconds_since(t0);
-        std::vector<uint32_t> still;
-        for (uint32_t j : active) {
-            job_state& st = js[j];
-            st.status |= warn;
-            if (++st.phase < st.in.phases) {
-                still.push_back(j);
-                continue;
+            // advance, and retire the jobs whose last phase just ran; jobs
+            // admitted during the iteration keep their place
+            const double end = seconds_since(t0);
+            std::vector<uint32_t> still;
+            for (uint32_t j : L.jobs) {
+                job_state& st = js[j];
+                if (std::find(L.running.begin(), L.running.end(), j) == L.running.end()) {
+                    still.push_back(j);
+                    continue;
+                }
+                st.status |= warn;
+                if (++st.phase < st.in.phases) {
+                    still.push_back(j);
+                    continue;
+                }
+                times[j].finish_s = end;
+                times[j].status = st.status;
+                resident_items -= st.items;
+                arena.release(st.off, st.granules);
+                free_slots.push_back(st.slot);
+                ++finished;
             }
-            times[j].finish_s = end;
-            times[j].status = st.status;
-            resident_items -= st.items;
-            arena.release(st.off, st.granules);
-            free_slots.push_back(st.slot);
+            L.jobs.swap(still);
+            L.running.clear();
         }
-        active.swap(still);
+        if (progressed || finished == n) continue;
+        bool busy = false;
+        for (const lane_state& L : b.lane) busy |= L.in_flight;
+        if (!busy && next < n) {
+            wait_until(t0, times[next].arrival_s);   // nothing resident: wait for the next job
+        } else if (busy) {
+            // wait for an iteration or the next arrival, whichever comes first
+            const double until = next < n ? times[next].arrival_s : 1e300;
+            const double left = until - seconds_since(t0);
+            if (left > 0) std::this_thread::sleep_for(std::chrono::microseconds(
+                              std::max<int64_t>(1, std::min<int64_t>(20, (int64_t)(left * 1e6)))));
+        }
     }
     return HR_OK;
 }
