@@ -404,9 +404,11 @@ hr_status hr_job_run(const hr_instance* inst, const hr_config* cfg, hr_race* out
  * A job's launches run one after another (Sec. II-B: a kernel boundary
  * orders everything before it), so a device iteration may run the next
  * phase of every resident job side by side.  Jobs are admitted in arrival
- * order between iterations, while a job slot, shadow memory under the
- * budget and room under the iteration's item cap are free; a job's shadow
- * words stay resident until its last phase has been reported.
+ * order, while a job slot, shadow memory under the budget and room under
+ * the item cap are free; a job's shadow words stay resident until its last
+ * phase has been reported.  Jobs run in three lanes by class (short jobs,
+ * label propagation, jobs of more than 1024 items per phase); each lane runs
+ * its own iterations, and the lanes' iterations overlap on the device.
  * ---------------------------------------------------------------------- */
 
 typedef struct {
@@ -440,8 +442,11 @@ typedef struct {
  * sleeps while nothing is resident).  Race records of job j carry region id
  * 2j (its first buffer, and its LDS arrays) or 2j+1 (its second buffer); out
  * receives every job's deduplicated records, sorted by (region, space,
- * block if LDS, index); *n_out is their number.  The context's ring and
- * counters are reused by every iteration; its regions are not touched.
+ * block if LDS, index); *n_out is their number.  The first lane runs on
+ * `stream` with the context's ring and counters; the call creates two
+ * non-blocking streams (default priority) and their rings for the other
+ * lanes, and frees them before it returns.  The context's regions are not
+ * touched.
  * Errors: HR_E_INVAL (a job's shape, unsorted arrivals, max_items above
  * HR_SERVE_MAX_ITEMS, a job with more items per phase than max_items, cap
  * too small: then *n_out holds the number needed), HR_E_NOMEM (a job larger
