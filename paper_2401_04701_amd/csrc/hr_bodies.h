@@ -269,22 +269,26 @@ __device__ void labelprop_body(const hr_env& e, const hr_gref& glab, const hr_gr
     }
     // Software pipeline over the edge list, for the long lists of hub
     // vertices whose threads bound the launch: while edge k is checked, the
-    // column index of edge k+2 and the shadow word of edge k+1's target are
-    // already in flight.
+    // column index of edge k+2, and the seeded flag of edge k+1 and the
+    // shadow word of its target, are already in flight.
     uint32_t u0 = e0 < e1 ? (uint32_t)col[e0] : 0u;
     uint32_t u1 = e0 + 1 < e1 ? (uint32_t)col[e0 + 1] : 0u;
     uint64_t s0 = e0 < e1 ? hr_gload<CHECK>(th, glab, u0) : 0;
+    uint8_t m0 = e0 < e1 ? mask[e0] : 0;
     for (int32_t k = e0; k < e1; ++k) {
         const uint32_t u2 = k + 2 < e1 ? (uint32_t)col[k + 2] : 0u;
         const uint64_t s1 = k + 1 < e1 ? hr_gload<CHECK>(th, glab, u1) : 0;
+        const uint8_t m1 = k + 1 < e1 ? mask[k + 1] : 0;
         const uint32_t u = u0;
         const uint64_t su = s0;
+        const uint8_t seeded = m0;
         u0 = u1;
         u1 = u2;
         s0 = s1;
+        m0 = m1;
         if (CHECK && gcol.shadow) hr_g<0, CHECK>(e, th, gcol, (uint64_t)k, HR_SITE_LP_CSR);
         if (u >= n) continue;
-        if (mask[k]) {
+        if (seeded) {
             const int32_t r = label[u];
             hr_gpre<0, CHECK>(e, th, glab, u, HR_SITE_LP_SEED_READ, su);
             label[u] = r < l ? r : l;
