@@ -235,7 +235,7 @@ __device__ void jacobi_body(const hr_env& e, const hr_gref& gold, const hr_gref&
 // min of l into label[u], or for a seeded edge a plain read and plain write
 // of label[u].  grp / gcol: optional monitoring of the CSR reads (shadow
 // null when off).
-template <bool CHECK>
+template <bool CHECK, bool PAIRS = false>
 __device__ void labelprop_body(const hr_env& e, const hr_gref& glab, const hr_gref& grp,
                                const hr_gref& gcol, int32_t* __restrict__ label,
                                const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
@@ -267,8 +267,69 @@ __device__ void labelprop_body(const hr_env& e, const hr_gref& glab, const hr_gr
         }
         return;
     }
-    // Software pipeline over the edge list, for the long lists of hub
-    // vertices whose threads bound the launch: while edge k is checked, the
+    if (PAIRS && !e.group) {
+        // Edges in pairs, for the long lists of hub vertices whose threads
+        // bound the launch: the exchanges of both edges of a pair are in
+        // flight together and settled after both are issued, while the
+        // column indices of the pair after next and the seeded flags and
+        // shadow words of the next pair are loaded.  (It takes more
+        // registers than the batch and serving workers, which inline every
+        // workload body, can give; they run the one-edge loop below.)
+        const auto col_at = [&](int32_t q) { return q < e1 ? (uint32_t)col[q] : 0u; };
+        uint32_t a0 = col_at(e0), b0 = col_at(e0 + 1), a1 = col_at(e0 + 2), b1 = col_at(e0 + 3);
+        uint64_t sa = e0 < e1 ? hr_gload<CHECK>(th, glab, a0) : 0;
+        uint64_t sb = e0 + 1 < e1 ? hr_gload<CHECK>(th, glab, b0) : 0;
+        uint8_t ma = e0 < e1 ? mask[e0] : 0, mb = e0 + 1 < e1 ? mask[e0 + 1] : 0;
+        for (int32_t k = e0; k < e1; k += 2) {
+            const uint32_t a2 = col_at(k + 4), b2 = col_at(k + 5);
+            const uint64_t na = k + 2 < e1 ? hr_gload<CHECK>(th, glab, a1) : 0;
+            const uint64_t nb = k + 3 < e1 ? hr_gload<CHECK>(th, glab, b1) : 0;
+            const uint8_t nma = k + 2 < e1 ? mask[k + 2] : 0, nmb = k + 3 < e1 ? mask[k + 3] : 0;
+            const uint32_t ua = a0, ub = b0;
+            const uint64_t qa = sa, qb = sb;
+            const uint8_t fa = ma, fb = mb;
+            const bool two = k + 1 < e1;
+            a0 = a1;
+            b0 = b1;
+            a1 = a2;
+            b1 = b2;
+            sa = na;
+            sb = nb;
+            ma = nma;
+            mb = nmb;
+            if (gcol.shadow) {
+                hr_g<0, CHECK>(e, th, gcol, (uint64_t)k, HR_SITE_LP_CSR);
+                if (two) hr_g<0, CHECK>(e, th, gcol, (uint64_t)k + 1, HR_SITE_LP_CSR);
+            }
+            hr_pend pa{nullptr, 0, 0, 0}, pb{nullptr, 0, 0, 0};
+            if (ua < n) {
+                if (fa) {
+                    const int32_t r = label[ua];
+                    hr_gpre<0, CHECK>(e, th, glab, ua, HR_SITE_LP_SEED_READ, qa);
+                    label[ua] = r < l ? r : l;
+                    hr_g<1, CHECK, true>(e, th, glab, ua, HR_SITE_LP_SEED_WRITE);
+                } else {
+                    atomicMin(label + ua, l);
+                    pa = hr_gi<2, CHECK, true>(e, th, glab, ua, qa);
+                }
+            }
+            if (two && ub < n) {
+                if (fb) {
+                    const int32_t r = label[ub];
+                    hr_gpre<0, CHECK>(e, th, glab, ub, HR_SITE_LP_SEED_READ, qb);
+                    label[ub] = r < l ? r : l;
+                    hr_g<1, CHECK, true>(e, th, glab, ub, HR_SITE_LP_SEED_WRITE);
+                } else {
+                    atomicMin(label + ub, l);
+                    pb = hr_gi<2, CHECK, true>(e, th, glab, ub, qb);
+                }
+            }
+            hr_gs<2, CHECK>(e, th, glab, pa, ua, HR_SITE_LP_MIN);
+            hr_gs<2, CHECK>(e, th, glab, pb, ub, HR_SITE_LP_MIN);
+        }
+        return;
+    }
+    // One edge at a time.  While edge k is checked, the
     // column index of edge k+2, and the seeded flag of edge k+1 and the
     // shadow word of its target, are already in flight.
     uint32_t u0 = e0 < e1 ? (uint32_t)col[e0] : 0u;

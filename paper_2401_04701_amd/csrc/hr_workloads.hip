@@ -51,8 +51,8 @@ __global__ __launch_bounds__(1024) void k_labelprop(hr_kargs a, hr_gref glab, hr
                                                     const int32_t* __restrict__ col,
                                                     const uint8_t* __restrict__ mask, uint32_t n)
 {
-    labelprop_body<CHECK>(a.env, glab, grp, gcol, label, rp, col, mask, n, blockDim.x, blockIdx.x,
-                          threadIdx.x);
+    labelprop_body<CHECK, true>(a.env, glab, grp, gcol, label, rp, col, mask, n, blockDim.x,
+                                blockIdx.x, threadIdx.x);
 }
 
 // ----------------------------------------------------------- interpreter
