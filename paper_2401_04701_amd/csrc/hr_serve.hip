@@ -98,6 +98,7 @@ struct job_state {
     uint32_t items = 0;               // work items of one phase
     uint32_t slot = 0, phase = 0;
     int32_t status = 0;
+    bool running = false;             // in its lane's iteration in flight
 };
 
 using clock_t_ = std::chrono::steady_clock;
@@ -178,8 +179,7 @@ struct lane_state {
     uint64_t* h_prefix = nullptr;
     uint32_t* h_ctr = nullptr;       // counters after the iteration
     size_t lds = 0;                  // dynamic LDS of the lane's iterations
-    std::vector<uint32_t> jobs;      // resident jobs of the lane
-    std::vector<uint32_t> running;   // the jobs of the iteration in flight
+    std::vector<uint32_t> jobs;      // resident jobs of the lane, in admission order
     bool in_flight = false;
 };
 
@@ -342,7 +342,7 @@ hr_status serve_continuous(hr_ctx c, const hr_instance* jobs, hr_serve_job* time
                                hipMemcpyDeviceToHost, L.s) != hipSuccess ||
                 hipEventRecord(L.done, L.s) != hipSuccess)
                 return HR_E_HIP;
-            L.running = L.jobs;
+            for (uint32_t j : L.jobs) js[j].running = true;
             L.in_flight = true;
         }
         // collect the lanes whose iteration has finished
@@ -370,8 +370,9 @@ hr_status serve_continuous(hr_ctx c, const hr_instance* jobs, hr_serve_job* time
                 // recover the global part of the iteration's jobs from their
                 // sticky race words
                 warn |= HR_W_RING_OVERFLOW;
-                for (uint32_t j : L.running) {
+                for (uint32_t j : L.jobs) {
                     const job_state& st = js[j];
+                    if (!st.running) continue;
                     std::vector<uint64_t> sh(st.elems[0] + st.elems[1]);
                     if (hipMemcpyAsync(sh.data(), b.arena + st.off * GRANULE_WORDS, 8 * sh.size(),
                                        hipMemcpyDeviceToHost, L.s) != hipSuccess ||
@@ -395,10 +396,11 @@ hr_status serve_continuous(hr_ctx c, const hr_instance* jobs, hr_serve_job* time
             std::vector<uint32_t> still;
             for (uint32_t j : L.jobs) {
                 job_state& st = js[j];
-                if (std::find(L.running.begin(), L.running.end(), j) == L.running.end()) {
+                if (!st.running) {
                     still.push_back(j);
                     continue;
                 }
+                st.running = false;
                 st.status |= warn;
                 if (++st.phase < st.in.phases) {
                     still.push_back(j);
@@ -412,7 +414,6 @@ hr_status serve_continuous(hr_ctx c, const hr_instance* jobs, hr_serve_job* time
                 ++finished;
             }
             L.jobs.swap(still);
-            L.running.clear();
         }
         if (progressed || finished == n) continue;
         bool busy = false;
