@@ -185,8 +185,10 @@ hr_status hr_dev_args(hr_ctx c, void* out, size_t cap, size_t* size_out);
 
 /* Mark a kernel-launch boundary: every access of the launches before it
  * happens before every access after it.  Advances the launch epoch; every
- * 512 launches it clears the shadow on `stream` (races already found stay in
- * the ring).  Asynchronous. */
+ * 512 launches it clears the shadow on `stream`.  Races already found stay
+ * in the ring; if the ring has overflowed, the global races held in the
+ * shadow are first read back and kept for hr_report.  Asynchronous, except
+ * at those clears, where it synchronises `stream` to read the ring count. */
 hr_status hr_kernel_end(hr_ctx c, void* stream);
 
 /* Start a new job on the same regions: clear shadow memory, report ring,

@@ -37,6 +37,7 @@ struct hr_ctx_s {
     unsigned long long* count;       // HR_COUNT_SLOTS debug counters
     uint32_t launch_seq;             // launches since the job started
     uint64_t shadow_bytes;           // live shadow memory
+    std::vector<hr_race> carried;    // global races recovered before a shadow clear
 };
 
 hipStream_t hr_stream(hr_ctx c, void* stream);

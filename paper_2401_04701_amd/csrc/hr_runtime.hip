@@ -227,6 +227,31 @@ extern "C" hr_status hr_dev_args(hr_ctx c, void* out, size_t cap, size_t* size_o
     return HR_OK;
 }
 
+// The global races held in the sticky race words of every live region.
+static hr_status scan_races(hr_ctx c, std::vector<hr_race>& out)
+{
+    for (uint32_t r = 0; r < c->reg.size(); ++r) {
+        if (!c->reg[r].live) continue;
+        std::vector<uint64_t> sh(c->reg[r].elems);
+        if (hipMemcpy(sh.data(), c->reg[r].shadow, sizeof(uint64_t) * sh.size(),
+                      hipMemcpyDeviceToHost) != hipSuccess)
+            return HR_E_HIP;
+        for (size_t i = 0; i < sh.size(); ++i) {
+            if ((sh[i] & hr::g::TAG_M) != hr::T_RACE) continue;
+            hr_race x = {};
+            x.space = HR_GLOBAL;
+            x.region = r;
+            x.block = 0xFFFFFFFFu;
+            x.launch = 0xFFFFFFFFu;
+            x.index = i;
+            x.tid = 0xFFFFFFFFu;
+            x.flags = HR_RACE_SCANNED;
+            out.push_back(x);
+        }
+    }
+    return HR_OK;
+}
+
 extern "C" hr_status hr_kernel_end(hr_ctx c, void* stream)
 {
     if (!c) return HR_E_INVAL;
@@ -234,8 +259,21 @@ extern "C" hr_status hr_kernel_end(hr_ctx c, void* stream)
     // The launch epoch in a shadow word has 9 bits: before it wraps, return
     // every word to the initial state.  Exact: all earlier accesses happen
     // before all later ones, and the races found so far are in the ring.
-    if ((c->launch_seq & ((1u << hr::g::LAUNCH_BITS) - 1)) == 0)
-        return clear_shadows(c, hr_stream(c, stream));
+    // If the ring has overflowed, the races it lost live only in the race
+    // words, so they are recovered before the clear and carried to the report.
+    if ((c->launch_seq & ((1u << hr::g::LAUNCH_BITS) - 1)) == 0) {
+        hipStream_t s = hr_stream(c, stream);
+        uint32_t head = 0;
+        if (hipMemcpyAsync(&head, c->ctr + HR_CTR_HEAD, sizeof(head), hipMemcpyDeviceToHost, s) !=
+                hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return HR_E_HIP;
+        if (head > c->cfg.ring_capacity) {
+            const hr_status st = scan_races(c, c->carried);
+            if (st != HR_OK) return st;
+        }
+        return clear_shadows(c, s);
+    }
     return HR_OK;
 }
 
@@ -248,6 +286,7 @@ extern "C" hr_status hr_reset(hr_ctx c, void* stream)
     if (hr_fill32(c->ctr, HR_CTR_WORDS, s) != hipSuccess) return HR_E_HIP;
     if (hr_fill64((uint64_t*)c->count, HR_COUNT_SLOTS, s) != hipSuccess) return HR_E_HIP;
     c->launch_seq = 0;
+    c->carried.clear();
     return HR_OK;
 }
 
@@ -278,27 +317,12 @@ extern "C" hr_status hr_report(hr_ctx c, hr_race* out, size_t cap, size_t* n_out
     if (ctr[HR_CTR_FLAGS] & HR_DEVF_LIMIT) warn |= HR_W_REPORT_LIMITED;
     if (head > c->cfg.ring_capacity) {
         // Ring overflow: race states are sticky in global shadow memory, so
-        // the global part of the flagged set is recovered from it exactly.
+        // the global part of the flagged set is recovered from it exactly
+        // (and from the races carried over a shadow clear).
         warn |= HR_W_RING_OVERFLOW;
-        for (uint32_t r = 0; r < c->reg.size(); ++r) {
-            if (!c->reg[r].live) continue;
-            std::vector<uint64_t> sh(c->reg[r].elems);
-            if (hipMemcpy(sh.data(), c->reg[r].shadow, sizeof(uint64_t) * sh.size(),
-                          hipMemcpyDeviceToHost) != hipSuccess)
-                return HR_E_HIP;
-            for (size_t i = 0; i < sh.size(); ++i) {
-                if ((sh[i] & hr::g::TAG_M) != hr::T_RACE) continue;
-                hr_race x = {};
-                x.space = HR_GLOBAL;
-                x.region = r;
-                x.block = 0xFFFFFFFFu;
-                x.launch = 0xFFFFFFFFu;
-                x.index = i;
-                x.tid = 0xFFFFFFFFu;
-                x.flags = HR_RACE_SCANNED;
-                recs.push_back(x);
-            }
-        }
+        const hr_status st = scan_races(c, recs);
+        if (st != HR_OK) return st;
+        recs.insert(recs.end(), c->carried.begin(), c->carried.end());
     }
     std::sort(recs.begin(), recs.end(), key_less());
     size_t n = 0;

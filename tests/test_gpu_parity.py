@@ -332,6 +332,31 @@ def test_launch_epoch_wrap(env):
     assert got == set()
 
 
+def test_ring_overflow_across_epoch_wrap(env):
+    """Races seen only before the launch epoch wraps, with a ring that holds
+    one record: the clear at the wrap must not lose the global races that
+    only their race words still hold."""
+    torch, hr = env
+    ny, nx = 48, 48
+    seeds = si.jacobi_seeds(ny, nx, 78, count=3)
+    tab = si.jacobi_seed_table(ny, nx, seeds)
+    want = cf.jacobi_flagged(ny, nx, 4, seeds)
+    assert len(want) > 1 and all(k[0] == 0 for k in want)
+    say("ring overflow across epoch wrap")
+    u = [torch.from_numpy(si.jacobi_grid(ny, nx, 1)).cuda(),
+         torch.zeros((ny, nx), dtype=torch.float32, device="cuda")]
+    tab_d = torch.from_numpy(tab).cuda()
+    with hr.Context(ring_capacity=1) as ctx:
+        regs = [ctx.shadow_alloc(u[0]), ctx.shadow_alloc(u[1])]
+        for L in range(530):                       # seeded only in the first 4 launches
+            ctx.jacobi_check(regs[L % 2], regs[(L + 1) % 2], u[L % 2], u[(L + 1) % 2],
+                             tab_d if L < 4 else None)
+            ctx.kernel_end()
+        got = ctx.flagged()
+        assert ctx.status & hr.HR_W_RING_OVERFLOW
+    assert got == want
+
+
 # ------------------------------------------------------------- full size
 def test_jacobi_full_size(env):
     """4096 x 4096, 16 x 16 blocks, 20 launches, 66 seeded blocks: the flagged
