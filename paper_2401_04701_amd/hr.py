@@ -312,7 +312,8 @@ class Context:
         return self._c
 
     def shadow_alloc(self, tensor) -> int:
-        assert tensor.is_cuda and tensor.element_size() == 4 and tensor.is_contiguous()
+        if not (tensor.is_cuda and tensor.element_size() == 4 and tensor.is_contiguous()):
+            raise ValueError("shadow_alloc needs a contiguous device tensor of 4-byte elements")
         r = ctypes.c_uint32(0)
         _check("hr_shadow_alloc", _lib.hr_shadow_alloc(self._c, _dptr(tensor),
                                                        tensor.numel() * 4, 4, ctypes.byref(r)))
