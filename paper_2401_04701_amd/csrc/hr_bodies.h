@@ -94,12 +94,30 @@ __device__ void reduce_body(const hr_env& e, const hr_gref& gin, const hr_gref& 
         __syncthreads();
     }
     const size_t base = (size_t)lb * n;
+    const size_t o = (size_t)lb * T + t;
     if (act) {
-        for (uint32_t j = t; j < n; j += T) {
-            s[j] = in[base + j];
-            hr_g<0, CHECK>(e, th, gin, base + j, HR_SITE_REDUCE_LOAD);
-            hr_l<1, CHECK>(e, th, sh, n, lds_id, j, HR_SITE_REDUCE_STAGE);
+        // A thread loads at most two input words (n <= 2T), t and t + T.
+        // The shadow words of both are loaded together and both exchanges
+        // are in flight together: a one-block launch is a chain of round
+        // trips, and only this thread touches these words.
+        const bool one = t < n, two = t + T < n;
+        const uint64_t q0 = one ? hr_gload<CHECK>(th, gin, base + t) : 0;
+        const uint64_t q1 = two ? hr_gload<CHECK>(th, gin, base + t + T) : 0;
+        const int32_t v0 = one ? in[base + t] : 0;
+        const int32_t v1 = two ? in[base + t + T] : 0;
+        hr_pend p0{nullptr, 0, 0, 0}, p1{nullptr, 0, 0, 0};
+        if (one) p0 = hr_gi<0, CHECK, true>(e, th, gin, base + t, q0);
+        if (two) p1 = hr_gi<0, CHECK, true>(e, th, gin, base + t + T, q1);
+        if (one) {
+            hr_l<1, CHECK>(e, th, sh, n, lds_id, t, HR_SITE_REDUCE_STAGE);
+            s[t] = v0;
         }
+        if (two) {
+            hr_l<1, CHECK>(e, th, sh, n, lds_id, t + T, HR_SITE_REDUCE_STAGE);
+            s[t + T] = v1;
+        }
+        hr_gs<0, CHECK>(e, th, gin, p0, base + t, HR_SITE_REDUCE_LOAD);
+        hr_gs<0, CHECK>(e, th, gin, p1, base + t + T, HR_SITE_REDUCE_LOAD);
     }
     if (n != 2 * T) hr_bar<CHECK>(e, th);
     const int32_t steps = 31 - __builtin_clz(n);
@@ -116,10 +134,12 @@ __device__ void reduce_body(const hr_env& e, const hr_gref& gin, const hr_gref& 
         if (step != drop) hr_bar<CHECK>(e, th);
     }
     if (act) {
+        // the output word's shadow load is in flight during the LDS read
+        const uint64_t pre_out = hr_gload<CHECK>(th, gout, o);
         const int32_t r = s[0];
         hr_l<0, CHECK>(e, th, sh, n, lds_id, 0, HR_SITE_REDUCE_TOTAL);
-        out[(size_t)lb * T + t] = r;
-        hr_g<1, CHECK>(e, th, gout, (size_t)lb * T + t, HR_SITE_REDUCE_OUT);
+        out[o] = r;
+        hr_gpre<1, CHECK, false>(e, th, gout, o, HR_SITE_REDUCE_OUT, pre_out);
     }
 }
 
