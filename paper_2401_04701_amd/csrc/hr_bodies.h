@@ -12,66 +12,8 @@
 
 #include "hr_device.h"
 
-// A global region as the hooks see it: its shadow, length and report id.
-struct hr_gref {
-    uint64_t* shadow;
-    uint64_t n;
-    uint32_t id;
-};
-
-// Global hook at a lane-affine site (GROUP false) or a data-dependent one.
-template <int KIND, bool CHECK, bool GROUP = false>
-__device__ __forceinline__ void hr_g(const hr_env& e, const hr_thread& t, const hr_gref& g,
-                                     uint64_t index, uint32_t site)
-{
-    if constexpr (CHECK) hr_check<KIND, GROUP>(e, t, g.shadow, g.n, g.id, index, site);
-}
-
-// Global hook on a word loaded earlier by hr_gload.
-template <bool CHECK>
-__device__ __forceinline__ uint64_t hr_gload(const hr_thread& t, const hr_gref& g, uint64_t index)
-{
-    if constexpr (CHECK) return hr_check_load(t, g.shadow, g.n, index);
-    return 0;
-}
-
-template <int KIND, bool CHECK, bool GROUP = true>
-__device__ __forceinline__ void hr_gpre(const hr_env& e, const hr_thread& t, const hr_gref& g,
-                                        uint64_t index, uint32_t site, uint64_t pre)
-{
-    if constexpr (CHECK) hr_check<KIND, GROUP, true>(e, t, g.shadow, g.n, g.id, index, site, pre);
-}
-
-// The two halves of a global hook at a lane-affine site (hr_check_issue /
-// hr_check_settle); `pre` as for hr_gpre when PRE.
-template <int KIND, bool CHECK, bool PRE = false>
-__device__ __forceinline__ hr_pend hr_gi(const hr_env& e, const hr_thread& t, const hr_gref& g,
-                                         uint64_t index, uint64_t pre = 0)
-{
-    if constexpr (CHECK) return hr_check_issue<KIND, PRE>(e, t, g.shadow, g.n, index, pre);
-    return hr_pend{nullptr, 0, 0, 0};
-}
-
-template <int KIND, bool CHECK>
-__device__ __forceinline__ void hr_gs(const hr_env& e, const hr_thread& t, const hr_gref& g,
-                                      const hr_pend& p, uint64_t index, uint32_t site)
-{
-    if constexpr (CHECK) hr_check_settle<KIND>(e, t, p, g.id, index, site);
-}
-
-template <int KIND, bool CHECK>
-__device__ __forceinline__ void hr_l(const hr_env& e, const hr_thread& t, uint32_t* sh,
-                                     uint32_t n, uint32_t id, uint32_t index, uint32_t site)
-{
-    if constexpr (CHECK) hr_access_lds<KIND>(e, t, sh, n, id, index, site);
-}
-
-template <bool CHECK>
-__device__ __forceinline__ void hr_bar(const hr_env& e, hr_thread& t)
-{
-    if constexpr (CHECK) hr_barrier_block(e, t);
-    else __syncthreads();
-}
+#include "hr_hooks.h"
+#include "hr_jacobi.h"
 
 // Tree reduction of in[lb*n .. lb*n+n) (n a power of two, n <= 2T) by T
 // threads in LDS: load, then log2(n) halving steps, step s adding
@@ -140,113 +82,6 @@ __device__ void reduce_body(const hr_env& e, const hr_gref& gin, const hr_gref& 
         hr_l<0, CHECK>(e, th, sh, n, lds_id, 0, HR_SITE_REDUCE_TOTAL);
         out[o] = r;
         hr_gpre<1, CHECK, false>(e, th, gout, o, HR_SITE_REDUCE_OUT, pre_out);
-    }
-}
-
-constexpr uint32_t JACOBI_TILE = 18;
-constexpr uint32_t JACOBI_TILE_WORDS = JACOBI_TILE * JACOBI_TILE;
-
-// One 16x16 tile (logical block lb of a grid nbx tiles wide) of the 5-point
-// sweep u_new = 0.2 (c + n + s + w + e), staged through an 18x18 LDS tile.
-// seeds: NULL or per-block (side << 8 | offset) entries (-1: none); a seeded
-// block's edge thread also writes the neighbour-owned halo cell.
-template <bool CHECK>
-__device__ void jacobi_body(const hr_env& e, const hr_gref& gold, const hr_gref& gnew,
-                            const float* __restrict__ uo, float* __restrict__ un, uint32_t ny,
-                            uint32_t nx, uint32_t nbx, const int32_t* __restrict__ seeds,
-                            uint32_t lb, uint32_t t, float* tile, uint32_t* tsh, uint32_t lds_id)
-{
-    constexpr uint32_t TW = JACOBI_TILE_WORDS, TL = JACOBI_TILE;
-    const uint32_t tx = t & 15u, ty = (t >> 4) & 15u;
-    const uint32_t bx = lb % nbx, by = lb / nbx;
-    const uint32_t gx = bx * 16u + tx, gy = by * 16u + ty;
-    const bool inside = t < 256 && gx < nx && gy < ny;
-    hr_thread th{};
-    if constexpr (CHECK) {
-        th = hr_thread_make(e, lb, t);
-        if (t < 256)
-            for (uint32_t i = t; i < TW; i += 256) tsh[i] = 0;
-        __syncthreads();
-    }
-    const size_t g = (size_t)gy * nx + gx;
-    const uint32_t cl = (ty + 1) * TL + tx + 1;
-    if (inside) {
-        // An edge thread stages at most one row halo cell (north or south)
-        // and one column halo cell (west or east); each pair shares one hook
-        // site, so a wave issues two halo hooks instead of four.  The data
-        // loads are issued first, so that they are in flight together with
-        // the first hook's shadow load.
-        const bool hn = ty == 0 && gy > 0, hs = ty == 15 && gy + 1 < ny;
-        const bool hw = tx == 0 && gx > 0, he = tx == 15 && gx + 1 < nx;
-        const size_t gr = hn ? g - nx : g + nx, gc = hw ? g - 1 : g + 1;
-        const float vc = uo[g];
-        const float vr = hn || hs ? uo[gr] : 0.0f;
-        const float vk = hw || he ? uo[gc] : 0.0f;
-        // Each global hook is settled after the LDS hook of the staging
-        // store that follows it, so the LDS hook runs while the exchange is
-        // in flight.  (The staging hook comes before its store: the store
-        // needs the loaded value, and waiting for it waits for the exchange
-        // too.)
-        const hr_pend pc = hr_gi<0, CHECK>(e, th, gold, g);
-        hr_l<1, CHECK>(e, th, tsh, TW, lds_id, cl, HR_SITE_JACOBI_STAGE);
-        tile[cl] = vc;
-        hr_gs<0, CHECK>(e, th, gold, pc, g, HR_SITE_JACOBI_CENTRE);
-        if (hn || hs) {
-            const uint32_t lr = hn ? tx + 1 : 17 * TL + tx + 1;
-            const hr_pend pr = hr_gi<0, CHECK>(e, th, gold, gr);
-            hr_l<1, CHECK>(e, th, tsh, TW, lds_id, lr, HR_SITE_JACOBI_STAGE);
-            tile[lr] = vr;
-            hr_gs<0, CHECK>(e, th, gold, pr, gr, HR_SITE_JACOBI_HALO);
-        }
-        if (hw || he) {
-            const uint32_t lc = hw ? (ty + 1) * TL : (ty + 1) * TL + 17;
-            const hr_pend pk = hr_gi<0, CHECK>(e, th, gold, gc);
-            hr_l<1, CHECK>(e, th, tsh, TW, lds_id, lc, HR_SITE_JACOBI_STAGE);
-            tile[lc] = vk;
-            hr_gs<0, CHECK>(e, th, gold, pk, gc, HR_SITE_JACOBI_HALO);
-        }
-    }
-    hr_bar<CHECK>(e, th);
-    if (inside) {
-        // the output word's shadow load is in flight during the LDS reads
-        const uint64_t pre_out = hr_gload<CHECK>(th, gnew, g);
-        const float c = tile[cl];
-        hr_l<0, CHECK>(e, th, tsh, TW, lds_id, cl, HR_SITE_JACOBI_TILE);
-        float vn = c, vs = c, vw = c, ve = c;
-        if (gy > 0) {
-            vn = tile[cl - TL];
-            hr_l<0, CHECK>(e, th, tsh, TW, lds_id, cl - TL, HR_SITE_JACOBI_TILE);
-        }
-        if (gy + 1 < ny) {
-            vs = tile[cl + TL];
-            hr_l<0, CHECK>(e, th, tsh, TW, lds_id, cl + TL, HR_SITE_JACOBI_TILE);
-        }
-        if (gx > 0) {
-            vw = tile[cl - 1];
-            hr_l<0, CHECK>(e, th, tsh, TW, lds_id, cl - 1, HR_SITE_JACOBI_TILE);
-        }
-        if (gx + 1 < nx) {
-            ve = tile[cl + 1];
-            hr_l<0, CHECK>(e, th, tsh, TW, lds_id, cl + 1, HR_SITE_JACOBI_TILE);
-        }
-        const float r = 0.2f * (c + vn + vs + vw + ve);
-        un[g] = r;
-        hr_gpre<1, CHECK, false>(e, th, gnew, g, HR_SITE_JACOBI_OUT, pre_out);
-        if (seeds) {
-            const int32_t sd = seeds[lb];
-            if (sd >= 0) {
-                const uint32_t side = (uint32_t)sd >> 8, off = (uint32_t)sd & 255u;
-                int64_t tgt = -1;
-                if (side == 0 && ty == 0 && tx == off && gy > 0) tgt = (int64_t)g - nx;
-                else if (side == 1 && ty == 15 && tx == off && gy + 1 < ny) tgt = (int64_t)g + nx;
-                else if (side == 2 && tx == 0 && ty == off && gx > 0) tgt = (int64_t)g - 1;
-                else if (side == 3 && tx == 15 && ty == off && gx + 1 < nx) tgt = (int64_t)g + 1;
-                if (tgt >= 0) {
-                    un[tgt] = r;
-                    hr_g<1, CHECK>(e, th, gnew, (uint64_t)tgt, HR_SITE_JACOBI_SEED);
-                }
-            }
-        }
     }
 }
 

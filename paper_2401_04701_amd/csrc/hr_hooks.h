@@ -1,0 +1,68 @@
+// Hook call sites of the workload bodies: each wrapper calls the device hook
+// when CHECK is set and compiles to nothing in the plain kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hr_device.h"
+
+// A global region as the hooks see it: its shadow, length and report id.
+struct hr_gref {
+    uint64_t* shadow;
+    uint64_t n;
+    uint32_t id;
+};
+
+// Global hook at a lane-affine site (GROUP false) or a data-dependent one.
+template <int KIND, bool CHECK, bool GROUP = false>
+__device__ __forceinline__ void hr_g(const hr_env& e, const hr_thread& t, const hr_gref& g,
+                                     uint64_t index, uint32_t site)
+{
+    if constexpr (CHECK) hr_check<KIND, GROUP>(e, t, g.shadow, g.n, g.id, index, site);
+}
+
+// Global hook on a word loaded earlier by hr_gload.
+template <bool CHECK>
+__device__ __forceinline__ uint64_t hr_gload(const hr_thread& t, const hr_gref& g, uint64_t index)
+{
+    if constexpr (CHECK) return hr_check_load(t, g.shadow, g.n, index);
+    return 0;
+}
+
+template <int KIND, bool CHECK, bool GROUP = true>
+__device__ __forceinline__ void hr_gpre(const hr_env& e, const hr_thread& t, const hr_gref& g,
+                                        uint64_t index, uint32_t site, uint64_t pre)
+{
+    if constexpr (CHECK) hr_check<KIND, GROUP, true>(e, t, g.shadow, g.n, g.id, index, site, pre);
+}
+
+// The two halves of a global hook at a lane-affine site (hr_check_issue /
+// hr_check_settle); `pre` as for hr_gpre when PRE.
+template <int KIND, bool CHECK, bool PRE = false>
+__device__ __forceinline__ hr_pend hr_gi(const hr_env& e, const hr_thread& t, const hr_gref& g,
+                                         uint64_t index, uint64_t pre = 0)
+{
+    if constexpr (CHECK) return hr_check_issue<KIND, PRE>(e, t, g.shadow, g.n, index, pre);
+    return hr_pend{nullptr, 0, 0, 0};
+}
+
+template <int KIND, bool CHECK>
+__device__ __forceinline__ void hr_gs(const hr_env& e, const hr_thread& t, const hr_gref& g,
+                                      const hr_pend& p, uint64_t index, uint32_t site)
+{
+    if constexpr (CHECK) hr_check_settle<KIND>(e, t, p, g.id, index, site);
+}
+
+template <int KIND, bool CHECK>
+__device__ __forceinline__ void hr_l(const hr_env& e, const hr_thread& t, uint32_t* sh,
+                                     uint32_t n, uint32_t id, uint32_t index, uint32_t site)
+{
+    if constexpr (CHECK) hr_access_lds<KIND>(e, t, sh, n, id, index, site);
+}
+
+template <bool CHECK>
+__device__ __forceinline__ void hr_bar(const hr_env& e, hr_thread& t)
+{
+    if constexpr (CHECK) hr_barrier_block(e, t);
+    else __syncthreads();
+}

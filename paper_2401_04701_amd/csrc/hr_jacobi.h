@@ -1,0 +1,134 @@
+// The 5-point Jacobi sweep: its body as a device function of one logical
+// block, and its standalone kernel.  The sweep's device code lives here
+// alone, so that its measured figures can be tied to these sources.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hr_device.h"
+#include "hr_hooks.h"
+
+constexpr uint32_t JACOBI_TILE = 18;
+constexpr uint32_t JACOBI_TILE_WORDS = JACOBI_TILE * JACOBI_TILE;
+
+// One 16x16 tile (logical block lb of a grid nbx tiles wide) of the 5-point
+// sweep u_new = 0.2 (c + n + s + w + e), staged through an 18x18 LDS tile.
+// seeds: NULL or per-block (side << 8 | offset) entries (-1: none); a seeded
+// block's edge thread also writes the neighbour-owned halo cell.
+template <bool CHECK>
+__device__ void jacobi_body(const hr_env& e, const hr_gref& gold, const hr_gref& gnew,
+                            const float* __restrict__ uo, float* __restrict__ un, uint32_t ny,
+                            uint32_t nx, uint32_t nbx, const int32_t* __restrict__ seeds,
+                            uint32_t lb, uint32_t t, float* tile, uint32_t* tsh, uint32_t lds_id)
+{
+    constexpr uint32_t TW = JACOBI_TILE_WORDS, TL = JACOBI_TILE;
+    const uint32_t tx = t & 15u, ty = (t >> 4) & 15u;
+    const uint32_t bx = lb % nbx, by = lb / nbx;
+    const uint32_t gx = bx * 16u + tx, gy = by * 16u + ty;
+    const bool inside = t < 256 && gx < nx && gy < ny;
+    hr_thread th{};
+    if constexpr (CHECK) {
+        th = hr_thread_make(e, lb, t);
+        if (t < 256)
+            for (uint32_t i = t; i < TW; i += 256) tsh[i] = 0;
+        __syncthreads();
+    }
+    const size_t g = (size_t)gy * nx + gx;
+    const uint32_t cl = (ty + 1) * TL + tx + 1;
+    if (inside) {
+        // An edge thread stages at most one row halo cell (north or south)
+        // and one column halo cell (west or east); each pair shares one hook
+        // site, so a wave issues two halo hooks instead of four.  The data
+        // loads are issued first, so that they are in flight together with
+        // the first hook's shadow load.
+        const bool hn = ty == 0 && gy > 0, hs = ty == 15 && gy + 1 < ny;
+        const bool hw = tx == 0 && gx > 0, he = tx == 15 && gx + 1 < nx;
+        const size_t gr = hn ? g - nx : g + nx, gc = hw ? g - 1 : g + 1;
+        const float vc = uo[g];
+        const float vr = hn || hs ? uo[gr] : 0.0f;
+        const float vk = hw || he ? uo[gc] : 0.0f;
+        // Each global hook is settled after the LDS hook of the staging
+        // store that follows it, so the LDS hook runs while the exchange is
+        // in flight.  (The staging hook comes before its store: the store
+        // needs the loaded value, and waiting for it waits for the exchange
+        // too.)
+        const hr_pend pc = hr_gi<0, CHECK>(e, th, gold, g);
+        hr_l<1, CHECK>(e, th, tsh, TW, lds_id, cl, HR_SITE_JACOBI_STAGE);
+        tile[cl] = vc;
+        hr_gs<0, CHECK>(e, th, gold, pc, g, HR_SITE_JACOBI_CENTRE);
+        if (hn || hs) {
+            const uint32_t lr = hn ? tx + 1 : 17 * TL + tx + 1;
+            const hr_pend pr = hr_gi<0, CHECK>(e, th, gold, gr);
+            hr_l<1, CHECK>(e, th, tsh, TW, lds_id, lr, HR_SITE_JACOBI_STAGE);
+            tile[lr] = vr;
+            hr_gs<0, CHECK>(e, th, gold, pr, gr, HR_SITE_JACOBI_HALO);
+        }
+        if (hw || he) {
+            const uint32_t lc = hw ? (ty + 1) * TL : (ty + 1) * TL + 17;
+            const hr_pend pk = hr_gi<0, CHECK>(e, th, gold, gc);
+            hr_l<1, CHECK>(e, th, tsh, TW, lds_id, lc, HR_SITE_JACOBI_STAGE);
+            tile[lc] = vk;
+            hr_gs<0, CHECK>(e, th, gold, pk, gc, HR_SITE_JACOBI_HALO);
+        }
+    }
+    hr_bar<CHECK>(e, th);
+    if (inside) {
+        // the output word's shadow load is in flight during the LDS reads
+        const uint64_t pre_out = hr_gload<CHECK>(th, gnew, g);
+        const float c = tile[cl];
+        hr_l<0, CHECK>(e, th, tsh, TW, lds_id, cl, HR_SITE_JACOBI_TILE);
+        float vn = c, vs = c, vw = c, ve = c;
+        if (gy > 0) {
+            vn = tile[cl - TL];
+            hr_l<0, CHECK>(e, th, tsh, TW, lds_id, cl - TL, HR_SITE_JACOBI_TILE);
+        }
+        if (gy + 1 < ny) {
+            vs = tile[cl + TL];
+            hr_l<0, CHECK>(e, th, tsh, TW, lds_id, cl + TL, HR_SITE_JACOBI_TILE);
+        }
+        if (gx > 0) {
+            vw = tile[cl - 1];
+            hr_l<0, CHECK>(e, th, tsh, TW, lds_id, cl - 1, HR_SITE_JACOBI_TILE);
+        }
+        if (gx + 1 < nx) {
+            ve = tile[cl + 1];
+            hr_l<0, CHECK>(e, th, tsh, TW, lds_id, cl + 1, HR_SITE_JACOBI_TILE);
+        }
+        const float r = 0.2f * (c + vn + vs + vw + ve);
+        un[g] = r;
+        hr_gpre<1, CHECK, false>(e, th, gnew, g, HR_SITE_JACOBI_OUT, pre_out);
+        if (seeds) {
+            const int32_t sd = seeds[lb];
+            if (sd >= 0) {
+                const uint32_t side = (uint32_t)sd >> 8, off = (uint32_t)sd & 255u;
+                int64_t tgt = -1;
+                if (side == 0 && ty == 0 && tx == off && gy > 0) tgt = (int64_t)g - nx;
+                else if (side == 1 && ty == 15 && tx == off && gy + 1 < ny) tgt = (int64_t)g + nx;
+                else if (side == 2 && tx == 0 && ty == off && gx > 0) tgt = (int64_t)g - 1;
+                else if (side == 3 && tx == 15 && ty == off && gx + 1 < nx) tgt = (int64_t)g + 1;
+                if (tgt >= 0) {
+                    un[tgt] = r;
+                    hr_g<1, CHECK>(e, th, gnew, (uint64_t)tgt, HR_SITE_JACOBI_SEED);
+                }
+            }
+        }
+    }
+}
+
+namespace {
+
+// One 16 x 16 tile per hardware block.  8 waves per SIMD: the hook's scalar
+// registers would otherwise cap the occupancy at 7.
+template <bool CHECK>
+__global__ __launch_bounds__(256, 8) void k_jacobi(hr_kargs a, hr_gref gold, hr_gref gnew,
+                                                const float* __restrict__ uo,
+                                                float* __restrict__ un, uint32_t ny, uint32_t nx,
+                                                const int32_t* __restrict__ seeds)
+{
+    __shared__ float tile[JACOBI_TILE_WORDS];
+    __shared__ uint32_t tsh[CHECK ? JACOBI_TILE_WORDS : 1];
+    jacobi_body<CHECK>(a.env, gold, gnew, uo, un, ny, nx, gridDim.x, seeds,
+                       blockIdx.y * gridDim.x + blockIdx.x, threadIdx.x, tile, tsh, 0);
+}
+
+}  // namespace

@@ -33,18 +33,6 @@ __global__ __launch_bounds__(1024) void k_reduce(hr_kargs a, hr_gref gin, hr_gre
 }
 
 template <bool CHECK>
-__global__ __launch_bounds__(256, 8) void k_jacobi(hr_kargs a, hr_gref gold, hr_gref gnew,
-                                                const float* __restrict__ uo,
-                                                float* __restrict__ un, uint32_t ny, uint32_t nx,
-                                                const int32_t* __restrict__ seeds)
-{
-    __shared__ float tile[JACOBI_TILE_WORDS];
-    __shared__ uint32_t tsh[CHECK ? JACOBI_TILE_WORDS : 1];
-    jacobi_body<CHECK>(a.env, gold, gnew, uo, un, ny, nx, gridDim.x, seeds,
-                       blockIdx.y * gridDim.x + blockIdx.x, threadIdx.x, tile, tsh, 0);
-}
-
-template <bool CHECK>
 __global__ __launch_bounds__(1024) void k_labelprop(hr_kargs a, hr_gref glab, hr_gref grp,
                                                     hr_gref gcol, int32_t* __restrict__ label,
                                                     const int32_t* __restrict__ rp,
