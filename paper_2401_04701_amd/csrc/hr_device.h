@@ -472,12 +472,12 @@ __device__ __forceinline__ T* hr_gat(const hr_kargs& a, const hr_rmap& m, const 
                                      uint32_t slot, T* base, int64_t i, uint32_t site)
 {
     const uint32_t r = m.id[slot];
-    if (r < HR_MAX_REGIONS) {
+    if (r < HR_MAX_REGIONS) {            // else the parameter is not monitored
         if (K == 3) {
-            hr_check<0, true>(a.env, t, a.shadow[r], a.n_elems[r], r, (uint64_t)i, site);
-            hr_check<1, true>(a.env, t, a.shadow[r], a.n_elems[r], r, (uint64_t)i, site);
+            hr_access<0>(a, t, r, (uint64_t)i, site);
+            hr_access<1>(a, t, r, (uint64_t)i, site);
         } else {
-            hr_check<K, true>(a.env, t, a.shadow[r], a.n_elems[r], r, (uint64_t)i, site);
+            hr_access<K>(a, t, r, (uint64_t)i, site);
         }
     }
     return base + i;
