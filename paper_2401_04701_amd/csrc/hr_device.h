@@ -10,8 +10,10 @@
 // status, step the state machine, and publish the new word atomically.  The
 // hook need not be atomic with the access it checks (Sec. III-A, Scenario 1);
 // it only has to finish before the thread passes its next barrier or its
-// launch ends.  Every hook waits for the result of its own atomics, so shadow
-// updates are applied in an order consistent with happens-before.
+// launch ends.  Every hook has the result of its own atomics before then (a
+// hook split in two, issue and settle, reads it at the settle, still before
+// the barrier), so shadow updates are applied in an order consistent with
+// happens-before.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
