@@ -27,8 +27,69 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
+KERNELS_JSON = os.path.join(PKG, "libhr_kernels.json")
+FINGERPRINTED = ["hr_workloads.hip"]
+
+
+def _kernel_bodies(asm: str) -> dict:
+    """Each kernel of a device assembly listing: its instructions and labels,
+    without comments, line records and directives."""
+    out, cur, lines = {}, None, []
+    kernels = set()
+    for ln in asm.splitlines():
+        t = ln.strip()
+        if t.startswith(".amdhsa_kernel "):
+            kernels.add(t.split()[1])
+    for ln in asm.splitlines():
+        t = ln.split(";", 1)[0].rstrip()
+        if cur is None:
+            if t.endswith(":") and t[:-1] in kernels:
+                cur, lines = t[:-1], []
+            continue
+        if t.startswith(".Lfunc_end"):
+            out[cur] = "\n".join(lines)
+            cur = None
+            continue
+        t = t.strip()
+        if not t or (t.startswith(".") and not t.endswith(":")):   # directives
+            continue
+        lines.append(t)
+    return out
+
+
+def kernel_fingerprints(verbose: bool = False) -> str:
+    """SHA-256 of each kernel's gfx950 assembly (instructions and labels
+    only), written next to libhr.so.  A counter summary under profiles/
+    records the fingerprint of the kernel it measured, so a changed kernel
+    is recognised whatever else changed in its source files."""
+    import hashlib
+    import json
+    import tempfile
+    fp = {}
+    with tempfile.TemporaryDirectory() as tmp:
+        for src in FINGERPRINTED:
+            out = os.path.join(tmp, src + ".s")
+            cmd = [hipcc()] + [f for f in HIPCC_FLAGS if f != "-shared"] + [
+                "--cuda-device-only", "-S", "-I", INCLUDE, "-I", CSRC,
+                os.path.join(CSRC, src), "-o", out]
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            res = subprocess.run(cmd, capture_output=True, text=True)
+            if res.returncode != 0:
+                sys.stderr.write(res.stdout + res.stderr)
+                raise RuntimeError(f"hipcc failed producing the assembly of {src}")
+            with open(out) as f:
+                for name, body in _kernel_bodies(f.read()).items():
+                    fp[name] = hashlib.sha256(body.encode()).hexdigest()
+    with open(KERNELS_JSON + ".tmp", "w") as f:
+        json.dump(fp, f, indent=1, sort_keys=True)
+    os.replace(KERNELS_JSON + ".tmp", KERNELS_JSON)
+    return KERNELS_JSON
+
+
 def build(verbose: bool = False) -> str:
-    """Compile every HIP source into libhr.so (always recompiles)."""
+    """Compile every HIP source into libhr.so (always recompiles), and write
+    the kernels' assembly fingerprints."""
     tmp = LIB + ".tmp"
     cmd = [hipcc()] + HIPCC_FLAGS + ["-I", INCLUDE, "-I", CSRC]
     cmd += [os.path.join(CSRC, s) for s in SOURCES] + ["-o", tmp]
@@ -39,6 +100,7 @@ def build(verbose: bool = False) -> str:
         sys.stderr.write(res.stdout + res.stderr)
         raise RuntimeError("hipcc failed building libhr.so")
     os.replace(tmp, LIB)
+    kernel_fingerprints(verbose)
     return LIB
 
 
