@@ -368,6 +368,10 @@ typedef struct {
     uint32_t spin_limit;  /* wait rounds before an item is skipped; 0: 2^24 */
     uint32_t variant;     /* 0: one worker per compute unit, 128 registers per lane;
                              1: two workers per compute unit, 64 registers */
+    uint32_t coalesce;    /* wave grouping of the lanes of one hook instruction
+                             that hit the same shadow word, at data-dependent
+                             sites: 0 the context's setting, 1 off, 2 on; the
+                             result is the same either way */
 } hr_batch_tuning;
 
 /* Prepare a batch: allocate one shadow arena for every job (counted against

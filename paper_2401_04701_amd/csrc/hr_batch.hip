@@ -324,7 +324,7 @@ extern "C" hr_status hr_batch_run(hr_batch b, const hr_batch_tuning* tune, void*
     if (!b) return HR_E_INVAL;
     hr_batch_tuning t = {};
     if (tune) t = *tune;
-    if (t.order > 1 || t.variant > 1) return HR_E_INVAL;
+    if (t.order > 1 || t.variant > 1 || t.coalesce > 2) return HR_E_INVAL;
     const uint32_t cap = b->max_workers[t.variant];
     const uint32_t workers = t.workers ? std::min(t.workers, cap) : cap;
     const uint32_t spin = t.spin_limit ? t.spin_limit : (1u << 24);
@@ -337,6 +337,7 @@ extern "C" hr_status hr_batch_run(hr_batch b, const hr_batch_tuning* tune, void*
         return HR_E_HIP;
     hr_env e = hr_make_env(c);
     e.site_limit = 0;   // site ids are per job; the limit does not apply to a batch
+    if (t.coalesce) e.group = t.coalesce == 2 ? 1u : 0u;
     if (t.variant == 0)
         HR_LAUNCH(k_batch_wide, dim3(workers), dim3(1024), b->lds_bytes, s, e, b->d_inst,
                   b->d_items[t.order], b->n_items, b->d_cursor, b->d_done, spin);

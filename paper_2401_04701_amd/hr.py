@@ -86,7 +86,8 @@ class Instance(ctypes.Structure):
 
 class _Tuning(ctypes.Structure):
     _fields_ = [("workers", ctypes.c_uint32), ("order", ctypes.c_uint32),
-                ("spin_limit", ctypes.c_uint32), ("variant", ctypes.c_uint32)]
+                ("spin_limit", ctypes.c_uint32), ("variant", ctypes.c_uint32),
+                ("coalesce", ctypes.c_uint32)]
 
 
 class ServeJob(ctypes.Structure):
@@ -473,8 +474,10 @@ class Batch:
                                                    ctypes.byref(it)))
         return int(w.value), int(it.value)
 
-    def run(self, workers=0, order=0, variant=0, spin_limit=0, stream=None):
-        t = _Tuning(workers, order, spin_limit, variant)
+    def run(self, workers=0, order=0, variant=0, spin_limit=0, coalesce=0, stream=None):
+        """coalesce: wave grouping at data-dependent sites, 0 the context's
+        setting, 1 off, 2 on."""
+        t = _Tuning(workers, order, spin_limit, variant, coalesce)
         _check("hr_batch_run", _lib.hr_batch_run(self._b, ctypes.byref(t), _stream_ptr(stream)))
 
     def split(self, keys):

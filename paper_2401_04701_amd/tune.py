@@ -1,7 +1,8 @@
 """Autotuner of the batched launch: times candidate tunings of one batch
-(kernel variant, queue order, worker count) on the device and keeps the
-fastest.  Each trial is a full run of the batch (the results are the same
-for every tuning; only the schedule differs)."""
+(kernel variant, queue order, worker count, then coalescing of same-word
+lanes for the best of those) on the device and keeps the fastest.  Each
+trial is a full run of the batch (the results are the same for every
+tuning; only the schedule and the number of atomics differ)."""
 from __future__ import annotations
 
 import itertools
@@ -21,8 +22,8 @@ def autotune(ctx, batch, reps: int = 2, cands=None):
     import torch
     stream = torch.cuda.current_stream()
     timings = {}
-    best, best_ms = None, None
-    for cand in cands or candidates(batch):
+
+    def trial(cand):
         ms = None
         for _ in range(reps):
             ctx.reset()
@@ -34,7 +35,20 @@ def autotune(ctx, batch, reps: int = 2, cands=None):
             t = e0.elapsed_time(e1)
             ms = t if ms is None else min(ms, t)
         key = "v{variant}_o{order}_w{workers}".format(**cand)
+        if cand.get("coalesce"):
+            key += "_c{coalesce}".format(**cand)
         timings[key] = ms
+        return ms
+
+    best, best_ms = None, None
+    for cand in cands or candidates(batch):
+        ms = trial(cand)
         if best_ms is None or ms < best_ms:
+            best, best_ms = cand, ms
+    # coalescing of same-word lanes, off and on, for the best schedule
+    for c in (1, 2):
+        cand = dict(best, coalesce=c)
+        ms = trial(cand)
+        if ms < best_ms:
             best, best_ms = cand, ms
     return best, timings

@@ -93,6 +93,14 @@ def test_batch_small_matches_serial_and_oracle(env):
             b.run(spin_limit=1 << 16)
             per = b.split(ctx.flagged())
             assert ctx.status == 0
+            for coalesce in (1, 2):                   # the run's own choice over the context's
+                say("  coalesce", coalesce)
+                ctx.reset()
+                b.run(spin_limit=1 << 16, coalesce=coalesce)
+                assert ctx.status == 0 and b.split(ctx.flagged()) == per
+            ctx.reset()
+            with pytest.raises(hr.HRError):
+                b.run(coalesce=3)
     for i, (w, p) in enumerate(zip(want, per)):
         assert p == w, (i, specs[i])
 
