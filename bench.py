@@ -172,10 +172,19 @@ def measure_peaks(torch, hr, stream):
     rnd = [0]
     for op, opname in ((0, "cas"), (1, "xchg")):
         for scatter, pat in ((0, "coalesced"), (1, "scattered")):
-            def run(op=op, scatter=scatter):
-                hr.peak_atomic(words, op, rnd[0], scatter, fails)
-                rnd[0] += 1
-            out[f"{opname}_{pat}_per_s"] = n / (_best_ms(torch, stream, run) * 1e-3)
+            # the best over grid sizes: fewer, longer-running blocks keep more
+            # operations in flight per wave
+            best_rate, best_blocks = 0.0, 0
+            for blocks in ((0, 1024, 2048, 4096, 8192) if scatter == 0 else (0,)):
+                def run(op=op, scatter=scatter, blocks=blocks):
+                    hr.peak_atomic(words, op, rnd[0], scatter, fails, blocks)
+                    rnd[0] += 1
+                rate = n / (_best_ms(torch, stream, run) * 1e-3)
+                if rate > best_rate:
+                    best_rate, best_blocks = rate, blocks
+            out[f"{opname}_{pat}_per_s"] = best_rate
+            if scatter == 0:
+                out[f"{opname}_{pat}_blocks"] = best_blocks or min((n + 255) // 256, 65536)
     # spread over a 32 MiB array (the label-propagation shadow size)
     nr = 1 << 22
     for op, opname in ((0, "cas"), (1, "xchg")):

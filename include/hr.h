@@ -477,9 +477,12 @@ hr_status hr_peak_copy(const void* src_dev, void* dst_dev, size_t bytes, void* s
  * scatter 1 permutes words within 64 KiB windows (n should be a multiple of
  * 8192) so the lanes of a wave hit different cache lines; scatter 2 (n a
  * power of two) spreads consecutive operations over the whole array.  Operations that
- * found another value are added to *fails_dev. */
+ * found another value are added to *fails_dev.  blocks: blocks of 256
+ * threads, each thread taking every (blocks * 256)-th word; 0 gives one word
+ * per thread (at most 65536 blocks).  Fewer, longer-running blocks keep more
+ * operations in flight per wave, so a peak is the best over a few. */
 hr_status hr_peak_atomic(uint64_t* words_dev, size_t n, uint32_t op, uint32_t round,
-                         uint32_t scatter, uint32_t* fails_dev, void* stream);
+                         uint32_t scatter, uint32_t* fails_dev, uint32_t blocks, void* stream);
 
 /* LDS 32-bit compare-and-swap throughput: `blocks` blocks of 1024 threads,
  * each thread taking its own LDS word through `iters` successful

@@ -116,15 +116,17 @@ extern "C" hr_status hr_peak_copy(const void* src_dev, void* dst_dev, size_t byt
 }
 
 extern "C" hr_status hr_peak_atomic(uint64_t* words_dev, size_t n, uint32_t op, uint32_t round,
-                                    uint32_t scatter, uint32_t* fails_dev, void* stream)
+                                    uint32_t scatter, uint32_t* fails_dev, uint32_t blocks,
+                                    void* stream)
 {
-    if (!words_dev || !fails_dev || n == 0 || op > 1) return HR_E_INVAL;
+    if (!words_dev || !fails_dev || n == 0 || op > 1 || blocks > 65536) return HR_E_INVAL;
+    const unsigned grid = blocks ? blocks : grid_for(n);
     if (op == 0)
-        HR_LAUNCH(k_atomic<0>, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream, words_dev, n,
-                  round, scatter, fails_dev);
+        HR_LAUNCH(k_atomic<0>, dim3(grid), dim3(256), 0, (hipStream_t)stream, words_dev, n, round,
+                  scatter, fails_dev);
     else
-        HR_LAUNCH(k_atomic<1>, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream, words_dev, n,
-                  round, scatter, fails_dev);
+        HR_LAUNCH(k_atomic<1>, dim3(grid), dim3(256), 0, (hipStream_t)stream, words_dev, n, round,
+                  scatter, fails_dev);
     return HR_OK;
 }
 

@@ -148,7 +148,7 @@ def _load():
         "hr_job_run": [P, P, P, sz, P, P],
         "hr_serve": [P, P, P, u32, P, P, sz, P, P],
         "hr_peak_copy": [P, P, sz, P],
-        "hr_peak_atomic": [P, sz, u32, u32, u32, P, P],
+        "hr_peak_atomic": [P, sz, u32, u32, u32, P, u32, P],
         "hr_peak_load": [P, sz, u32, P, P],
         "hr_peak_lds": [u32, u32, u32, P, P],
     }
@@ -242,9 +242,9 @@ def peak_copy(src, dst, stream=None):
                                              _stream_ptr(stream)))
 
 
-def peak_atomic(words, op, rnd, scatter, fails, stream=None):
+def peak_atomic(words, op, rnd, scatter, fails, blocks=0, stream=None):
     _check("hr_peak_atomic", _lib.hr_peak_atomic(_dptr(words), words.numel(), op, rnd, scatter,
-                                                 _dptr(fails), _stream_ptr(stream)))
+                                                 _dptr(fails), blocks, _stream_ptr(stream)))
 
 
 def peak_lds(blocks, iters, op, fails, stream=None):
