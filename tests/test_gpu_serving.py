@@ -192,3 +192,20 @@ def test_serving_item_cap_arguments(env, stream):
         with pytest.raises(hr.HRError) as e:        # above the launch limit
             hr.serve(ctx, [j.inst for j in js], arrivals, max_items=hr.SERVE_MAX_ITEMS + 1)
         assert e.value.status == hr.HR_E_INVAL
+
+
+@pytest.mark.parametrize("pattern", [si.PAT_LABELPROP, si.PAT_REDUCE, si.PAT_JACOBI])
+def test_serving_single_class_stream(env, stream, pattern):
+    """A stream of one job class runs in one or two lanes; results equal each
+    job alone."""
+    torch, hr, jobs = env
+    specs, js, want = stream
+    pick = [i for i, s in enumerate(specs) if s["pattern"] == pattern]
+    assert pick
+    arrivals = si.poisson_arrivals(10 + pattern, len(pick), 3000.0)
+    say("single-class stream", pattern, len(pick), "jobs")
+    with hr.Context(ring_capacity=1 << 16) as ctx:
+        per, times = hr.serve(ctx, [js[i].inst for i in pick], arrivals)
+    for k, i in enumerate(pick):
+        assert per[k] == want[i], (i, specs[i])
+        assert times[k].status == 0
