@@ -412,9 +412,10 @@ hr_status hr_job_run(const hr_instance* inst, const hr_config* cfg, hr_race* out
  * phase of every resident job side by side.  Jobs are admitted in arrival
  * order, while a job slot, shadow memory under the budget and room under
  * the item cap are free; a job's shadow words stay resident until its last
- * phase has been reported.  Jobs run in three lanes by class (short jobs,
- * label propagation, jobs of more than 1024 items per phase); each lane runs
- * its own iterations, and the lanes' iterations overlap on the device.
+ * phase has been reported.  Jobs run in four lanes by class (short jobs;
+ * label propagation under 64 items per phase; label propagation of 64 items
+ * or more; other jobs of more than 1024 items per phase); each lane runs its
+ * own iterations, and the lanes' iterations overlap on the device.
  * ---------------------------------------------------------------------- */
 
 typedef struct {
@@ -449,7 +450,7 @@ typedef struct {
  * 2j (its first buffer, and its LDS arrays) or 2j+1 (its second buffer); out
  * receives every job's deduplicated records, sorted by (region, space,
  * block if LDS, index); *n_out is their number.  The first lane runs on
- * `stream` with the context's ring and counters; the call creates two
+ * `stream` with the context's ring and counters; the call creates three
  * non-blocking streams (default priority) and their rings for the other
  * lanes, and frees them before it returns.  The context's regions are not
  * touched.

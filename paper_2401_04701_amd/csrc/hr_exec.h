@@ -55,6 +55,14 @@ __device__ __forceinline__ hr_gref uni_gref(const hr_gref& g)
 // job's block size) runs logical block item*pack + g with its own slice of
 // the LDS; threads past the last group, and groups past the job's last
 // block, only take part in the barriers.
+//
+// PATTERNS: bit p set compiles the body of pattern p in.  A kernel built for
+// fewer patterns needs fewer registers; its caller gives it only jobs of
+// those patterns.
+constexpr uint32_t HR_ALL_PATTERNS = (1u << HR_PAT_REDUCE) | (1u << HR_PAT_JACOBI) |
+                                     (1u << HR_PAT_LABELPROP);
+
+template <uint32_t PATTERNS = HR_ALL_PATTERNS>
 __device__ __forceinline__ void run_item(const hr_env& e, const hr_inst_dev& I, uint32_t phase,
                                          uint32_t item, uint32_t* smem)
 {
@@ -67,26 +75,30 @@ __device__ __forceinline__ void run_item(const hr_env& e, const hr_inst_dev& I, 
         lb = item * I.pack;
         lds = smem;
     }
-    switch (I.pattern) {
-    case HR_PAT_REDUCE:
-        reduce_body<true>(e, I.g0, I.g1, (const int32_t*)I.p0, (int32_t*)I.p1, I.n, T, lb, t,
-                          I.drop, (int32_t*)lds, lds + I.n, I.lds_id);
-        break;
-    case HR_PAT_JACOBI: {
-        const bool odd = phase & 1u;
-        const float* uo = (const float*)(odd ? I.p1 : I.p0);
-        float* un = (float*)(odd ? I.p0 : I.p1);
-        jacobi_body<true>(e, odd ? I.g1 : I.g0, odd ? I.g0 : I.g1, uo, un, I.ny, I.n, I.nbx,
-                          (const int32_t*)I.p2, lb, t, (float*)lds, lds + JACOBI_TILE_WORDS,
-                          I.lds_id);
-        break;
+    if constexpr ((PATTERNS >> HR_PAT_REDUCE) & 1u) {
+        if (I.pattern == HR_PAT_REDUCE) {
+            reduce_body<true>(e, I.g0, I.g1, (const int32_t*)I.p0, (int32_t*)I.p1, I.n, T, lb,
+                              t, I.drop, (int32_t*)lds, lds + I.n, I.lds_id);
+            return;
+        }
     }
-    default: {
-        const hr_gref none{nullptr, 0, 0};
-        labelprop_body<true>(e, I.g0, none, none, (int32_t*)I.p0, (const int32_t*)I.p1,
-                             (const int32_t*)I.p2, (const uint8_t*)I.p3, I.n, T, lb, t);
-        break;
+    if constexpr ((PATTERNS >> HR_PAT_JACOBI) & 1u) {
+        if (I.pattern == HR_PAT_JACOBI) {
+            const bool odd = phase & 1u;
+            const float* uo = (const float*)(odd ? I.p1 : I.p0);
+            float* un = (float*)(odd ? I.p0 : I.p1);
+            jacobi_body<true>(e, odd ? I.g1 : I.g0, odd ? I.g0 : I.g1, uo, un, I.ny, I.n, I.nbx,
+                              (const int32_t*)I.p2, lb, t, (float*)lds, lds + JACOBI_TILE_WORDS,
+                              I.lds_id);
+            return;
+        }
     }
+    if constexpr ((PATTERNS >> HR_PAT_LABELPROP) & 1u) {
+        if (I.pattern == HR_PAT_LABELPROP) {
+            const hr_gref none{nullptr, 0, 0};
+            labelprop_body<true>(e, I.g0, none, none, (int32_t*)I.p0, (const int32_t*)I.p1,
+                                 (const int32_t*)I.p2, (const uint8_t*)I.p3, I.n, T, lb, t);
+        }
     }
 }
 

@@ -31,6 +31,8 @@ namespace {
 // One iteration: work item blockIdx.x of the flat list of the resident
 // jobs' items, each job contributing the items of its next phase (prefix[k]
 // = items of the jobs before job k in the list).
+// PATTERNS: the workload patterns the iteration's jobs may have (run_item).
+template <uint32_t PATTERNS>
 __global__ __launch_bounds__(1024, 8) void k_iter(hr_env base, const hr_inst_dev* __restrict__ slots,
                                                const uint32_t* __restrict__ act,
                                                const uint64_t* __restrict__ prefix, uint32_t n_act)
@@ -51,7 +53,22 @@ __global__ __launch_bounds__(1024, 8) void k_iter(hr_env base, const hr_inst_dev
     hr_env e = base;
     e.launch = phase & ((1u << hr::g::LAUNCH_BITS) - 1);
     e.launch_seq = phase;
-    run_item(e, I, phase, item, smem);
+    run_item<PATTERNS>(e, I, phase, item, smem);
+}
+
+using iter_kernel = void (*)(hr_env, const hr_inst_dev*, const uint32_t*, const uint64_t*,
+                             uint32_t);
+
+// The iteration kernel for a set of patterns (bit p: pattern p): one built
+// for that pattern alone when there is one, else the one for all.
+iter_kernel iter_for(uint32_t patterns)
+{
+    switch (patterns) {
+    case 1u << HR_PAT_REDUCE: return k_iter<1u << HR_PAT_REDUCE>;
+    case 1u << HR_PAT_JACOBI: return k_iter<1u << HR_PAT_JACOBI>;
+    case 1u << HR_PAT_LABELPROP: return k_iter<1u << HR_PAT_LABELPROP>;
+    default: return k_iter<HR_ALL_PATTERNS>;
+    }
 }
 
 // First-fit allocator of 256-byte granules inside one device arena.
@@ -154,15 +171,18 @@ hr_status serve_serial(hr_ctx c, const hr_instance* jobs, hr_serve_job* times, u
 // and runs its iterations one after another, while the lanes' iterations
 // overlap on the device.  An iteration lasts as long as its slowest item,
 // so jobs whose phases are long (label propagation, bound by the edge list
-// of its largest hub; jobs of many items) would hold back the short jobs
-// sharing their iterations.
-constexpr uint32_t N_LANES = 3;
-constexpr uint32_t LANE_SHORT = 0, LANE_GRAPH = 1, LANE_LARGE = 2;
-constexpr uint32_t LARGE_ITEMS = 1024;   // items per phase above which a job is large
+// of its largest hub, which grows with the graph; jobs of many items) would
+// hold back the short jobs sharing their iterations.  Four lanes: as many as
+// the device's hardware queues for one process.
+constexpr uint32_t N_LANES = 4;
+constexpr uint32_t LANE_SHORT = 0, LANE_GRAPH = 1, LANE_LARGE = 2, LANE_LARGE_GRAPH = 3;
+constexpr uint32_t LARGE_ITEMS = 1024;        // items per phase above which a job is large
+constexpr uint32_t LARGE_GRAPH_ITEMS = 64;    // the same for label propagation (64 K vertices)
 
 uint32_t lane_of(const hr_instance& in, uint32_t items)
 {
-    if (in.pattern == HR_PAT_LABELPROP) return LANE_GRAPH;
+    if (in.pattern == HR_PAT_LABELPROP)
+        return items >= LARGE_GRAPH_ITEMS ? LANE_LARGE_GRAPH : LANE_GRAPH;
     return items > LARGE_ITEMS ? LANE_LARGE : LANE_SHORT;
 }
 
@@ -243,7 +263,7 @@ hr_status serve_continuous(hr_ctx c, const hr_instance* jobs, hr_serve_job* time
 {
     std::vector<job_state> js(n);
     std::vector<uint32_t> lane_of_job(n);
-    size_t lds[N_LANES] = {0, 0, 0};
+    size_t lds[N_LANES] = {};
     const uint64_t budget_granules = cfg.shadow_budget / (GRANULE_WORDS * 8);
     uint64_t need = 0;
     for (uint32_t j = 0; j < n; ++j) {
@@ -275,11 +295,15 @@ hr_status serve_continuous(hr_ctx c, const hr_instance* jobs, hr_serve_job* time
         const hr_status st = lane_init(L, c, hr_stream(c, stream), k == 0, max_slots);
         if (st != HR_OK) return st;
         L.lds = lds[k];
-        int per_cu = 0;   // the iteration kernel must fit with the lane's largest LDS
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_iter, HR_WORKER_THREADS,
-                                                         L.lds) != hipSuccess ||
-            per_cu <= 0)
-            return HR_E_HIP;
+        for (uint32_t pm : {1u << HR_PAT_REDUCE, 1u << HR_PAT_JACOBI, 1u << HR_PAT_LABELPROP,
+                            HR_ALL_PATTERNS}) {
+            int per_cu = 0;   // the iteration kernels must fit with the lane's largest LDS
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, iter_for(pm),
+                                                             HR_WORKER_THREADS, L.lds) !=
+                    hipSuccess ||
+                per_cu <= 0)
+                return HR_E_HIP;
+        }
         env[k] = env_base;
         env[k].ring = L.ring;
         env[k].ctr = L.ctr;
@@ -323,11 +347,13 @@ hr_status serve_continuous(hr_ctx c, const hr_instance* jobs, hr_serve_job* time
             lane_state& L = b.lane[k];
             if (L.in_flight || L.jobs.empty()) continue;
             uint64_t total = 0;
+            uint32_t patterns = 0;
             for (size_t q = 0; q < L.jobs.size(); ++q) {
                 const job_state& st = js[L.jobs[q]];
                 L.h_prefix[q] = total;
                 L.h_act[q] = st.slot | (st.phase << 20);
                 total += st.items;
+                patterns |= 1u << st.in.pattern;
             }
             L.h_prefix[L.jobs.size()] = total;
             if (hipMemcpyAsync(L.act, L.h_act, sizeof(uint32_t) * L.jobs.size(),
@@ -336,8 +362,8 @@ hr_status serve_continuous(hr_ctx c, const hr_instance* jobs, hr_serve_job* time
                                hipMemcpyHostToDevice, L.s) != hipSuccess ||
                 hr_fill32(L.ctr, HR_CTR_WORDS, L.s) != hipSuccess)
                 return HR_E_HIP;
-            HR_LAUNCH(k_iter, dim3((uint32_t)total), dim3(HR_WORKER_THREADS), L.lds, L.s, env[k],
-                      b.slots, L.act, L.prefix, (uint32_t)L.jobs.size());
+            HR_LAUNCH(iter_for(patterns), dim3((uint32_t)total), dim3(HR_WORKER_THREADS), L.lds,
+                      L.s, env[k], b.slots, L.act, L.prefix, (uint32_t)L.jobs.size());
             if (hipMemcpyAsync(L.h_ctr, L.ctr, sizeof(uint32_t) * HR_CTR_SITES,
                                hipMemcpyDeviceToHost, L.s) != hipSuccess ||
                 hipEventRecord(L.done, L.s) != hipSuccess)
