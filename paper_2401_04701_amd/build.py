@@ -104,7 +104,7 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
-EXAMPLES = ["reduce_block.hip", "stencil3.hip", "histogram.hip"]
+EXAMPLES = ["reduce_block.hip", "stencil3.hip", "histogram.hip", "wave_reduce.hip"]
 EXAMPLES_LIB = os.path.join(PKG, "libhr_examples.so")
 
 

@@ -19,6 +19,7 @@ _PARAMS = {
     "reduce_block": [P, P, i32],
     "stencil3": [P, P, i32, i32],
     "histogram": [P, P, i32, i32],
+    "wave_reduce": [P, P, i32],
 }
 
 

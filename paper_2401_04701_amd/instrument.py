@@ -14,7 +14,10 @@ array accesses and barriers, and rewrites the source text:
 * ``s[i]`` on a ``__shared__`` array ``s`` (LDS) becomes
   ``(*hr_lat<K>(hr_a.env, hr_t, hr_sh_s, N, id, s, (i), line))`` with an LDS
   shadow array ``hr_sh_s`` cleared at kernel start;
-* ``__syncthreads()`` becomes ``hr_barrier_block(hr_a.env, hr_t)``.
+* ``__syncthreads()`` becomes ``hr_barrier_block(hr_a.env, hr_t)``, and
+  ``__syncwarp()`` (with or without a mask: HIP synchronises the whole wave,
+  and the mask must name the active lanes) becomes
+  ``hr_barrier_wave(hr_a.env, hr_t)``.
 
 K is the access kind decided from the expression around the subscript: the
 left side of ``=`` is a write, of a compound assignment or ``++``/``--`` a read
@@ -205,9 +208,9 @@ def analyse(src: str, fn: dict) -> Tuple[List[Edit], Report, dict]:
                 rep.shared_arrays.append((node["name"], int(m.group(2))))
             else:
                 rep.skipped.append(f"shared {node['name']}: {node['type']['qualType']}")
-        if k == "CallExpr" and _callee(node) == "__syncthreads":
+        if k == "CallExpr" and _callee(node) in ("__syncthreads", "__syncwarp"):
             b, e = span(node)
-            edits.append(Edit(b, e, "bar"))
+            edits.append(Edit(b, e, "bar" if _callee(node) == "__syncthreads" else "wbar"))
             rep.barriers += 1
         if k == "ArraySubscriptExpr":
             base = _strip(node["inner"][0])
@@ -265,6 +268,8 @@ def _apply(src: str, lo: int, hi: int, edits: List[Edit]) -> str:
         out.append(src[cur:e.start])
         if e.kind == "bar":
             out.append("hr_barrier_block(hr_a.env, hr_t)")
+        elif e.kind == "wbar":
+            out.append("hr_barrier_wave(hr_a.env, hr_t)")
         else:
             pre, (ib, ie), post = e.parts
             nested = [x for x in edits if ib <= x.start and x.end <= ie and x is not e]

@@ -88,3 +88,26 @@ def test_instrumented_histogram(env, plain):
     assert got == want
     if not plain:
         assert (bins.cpu().numpy() == counts).all()
+
+
+@pytest.mark.parametrize("drop", [-1, 0, 3, 5, 6])
+def test_instrumented_wave_barriers(env, drop):
+    """__syncwarp becomes the checker's wave barrier: per-wave tree sums in
+    LDS race exactly where the dropped wave barrier leaves two steps in one
+    wave epoch (the sub-wave reduction's closed form with 64-lane tiles)."""
+    torch, hr, ex = env
+    blocks = 3
+    x = np.random.default_rng(7 + drop).integers(0, 1 << 20, blocks * 512, dtype=np.int32)
+    inp = torch.from_numpy(x).cuda()
+    out = torch.zeros(blocks * 256, dtype=torch.int32, device="cuda")
+    say("instrumented wave reduction drop", drop)
+    with hr.Context() as ctx:
+        r_in, r_out = ctx.shadow_alloc(inp), ctx.shadow_alloc(out)
+        ex.launch("wave_reduce", ctx, [r_in, r_out], (blocks,), (256,), inp, out, drop)
+        ctx.kernel_end()
+        got = ctx.flagged()
+        assert ctx.status == 0
+    assert got == cf.tile_reduce_flagged(64, blocks, 256, drop)
+    if drop < 0:
+        want = x.astype(np.int64).reshape(blocks, 4, 128).sum(axis=2)
+        assert (out.cpu().numpy().reshape(blocks, 4, 64) == want[:, :, None]).all()

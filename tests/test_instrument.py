@@ -27,6 +27,17 @@ def test_reduction_example_sites_and_kinds():
     assert "hr_launch_reduce_block" in text
 
 
+def test_wave_barrier_example():
+    text, (rep,) = instrument.instrument(os.path.join(EX, "wave_reduce.hip"))
+    assert rep.pointer_params == ["in", "out"] and rep.shared_arrays == [("s", 512)]
+    assert (rep.global_sites, rep.lds_sites, rep.barriers, rep.skipped) == (3, 6, 1, [])
+    body = text.split("LDS shadow cleared")[1]
+    assert "__syncwarp" not in body and "hr_barrier_block" not in body
+    assert body.count("hr_barrier_wave(hr_a.env, hr_t)") == 1
+    # s[base + l] = s[base + l] + s[base + l + h]: two reads, then the write
+    assert sorted(kinds(text, "hr_lat")) == [(0, 16), (0, 16), (0, 19), (1, 12), (1, 13), (1, 16)]
+
+
 def test_histogram_atomic_and_compound_kinds():
     text, (rep,) = instrument.instrument(os.path.join(EX, "histogram.hip"))
     assert sorted(kinds(text, "hr_gat")) == [(0, 10), (2, 12), (3, 11)]
