@@ -23,6 +23,7 @@
 #include <vector>
 
 #include "hr.h"
+#include "hr_arena.h"
 #include "hr_exec.h"
 #include "hr_internal.h"
 
@@ -70,41 +71,6 @@ iter_kernel iter_for(uint32_t patterns)
     default: return k_iter<HR_ALL_PATTERNS>;
     }
 }
-
-// First-fit allocator of 256-byte granules inside one device arena.
-struct arena_alloc {
-    std::map<uint64_t, uint64_t> free_;   // offset -> length, in granules
-    explicit arena_alloc(uint64_t granules) { free_[0] = granules; }
-    bool alloc(uint64_t n, uint64_t* off)
-    {
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second < n) continue;
-            *off = it->first;
-            const uint64_t rest = it->second - n;
-            const uint64_t at = it->first + n;
-            free_.erase(it);
-            if (rest) free_[at] = rest;
-            return true;
-        }
-        return false;
-    }
-    void release(uint64_t off, uint64_t n)
-    {
-        auto it = free_.emplace(off, n).first;
-        auto nx = std::next(it);
-        if (nx != free_.end() && it->first + it->second == nx->first) {
-            it->second += nx->second;
-            free_.erase(nx);
-        }
-        if (it != free_.begin()) {
-            auto pv = std::prev(it);
-            if (pv->first + pv->second == it->first) {
-                pv->second += it->second;
-                free_.erase(it);
-            }
-        }
-    }
-};
 
 constexpr uint64_t GRANULE_WORDS = 32;   // 256 bytes of 8-byte shadow words
 
