@@ -67,8 +67,8 @@ typedef enum { HR_READ = 0, HR_WRITE = 1, HR_ATOMIC = 2 } hr_kind;
 
 typedef struct {
     uint32_t ring_capacity;  /* race records kept on the device; 0: 65536 */
-    uint32_t bc_bits;        /* block-clock width 1..8; 0: 8 */
-    uint32_t wc_bits;        /* wave-clock width 1..6; 0: 6 */
+    uint32_t bc_bits;        /* block-clock width 1..8; 0: 8 (HR_CFG_WORD4: 2) */
+    uint32_t wc_bits;        /* wave-clock width 1..6; 0: 6 (HR_CFG_WORD4: 1) */
     uint32_t flags;          /* HR_CFG_* bits */
     uint64_t shadow_budget;  /* cap on shadow bytes of this context; 0: none */
     uint32_t site_limit;     /* race records kept per call site (site id mod
@@ -84,6 +84,11 @@ typedef struct {
                                 barrier (a tiled partition's sync) and orders
                                 only its tile's lanes.  Wave grouping of hook
                                 lanes only runs with whole waves. */
+    uint32_t thread_bits;    /* HR_CFG_WORD4 only: width of the thread field,
+                                1..10; 0: 8.  The block field gets the rest,
+                                27 - wc_bits - bc_bits - thread_bits bits
+                                (3 to 22; 16 with the defaults). */
+    uint32_t pad;
 } hr_config;
 
 #define HR_SITES 256   /* call-site counters of the report limit */
@@ -95,6 +100,19 @@ typedef struct {
  * by an owner lane (the result is unchanged; only the number of atomics
  * drops under same-word contention).  Off by default. */
 #define HR_CFG_WAVE_GROUPING 2u
+/* 4-byte global shadow words instead of 8-byte ones (the paper sizes its
+ * shadow word by configuration, Sec. IV-A, and leaves footprint trade-offs
+ * to the user): half the shadow memory.  The word holds the state number
+ * (5 bits), the wave clock, the block clock, the thread and the block, of
+ * the configured widths; it has no launch field, so hr_kernel_end returns
+ * every word to the initial state at each launch boundary.  Exact while a
+ * launch has at most 2^K blocks (K the block field's width) and 2^thread_bits
+ * threads per block; beyond that, block ids and thread indices are taken
+ * modulo those powers, and races between accessors that then look alike can
+ * be missed (never invented).  Race records carry 8-byte summaries with
+ * launch 0 and the folded block.  The batched and serving executors reject
+ * such a context. */
+#define HR_CFG_WORD4 4u
 
 /* One flagged location, 48 bytes.  The key is (space, region, block if LDS,
  * index).  The other fields describe how the race was found: `before` and
@@ -155,7 +173,8 @@ hr_status hr_ctx_destroy(hr_ctx c);
 
 /* Monitor `bytes` of device memory at data_dev as 4-byte elements (the
  * shadow-per-element layout of paper Sec. III-A, Fig. 2): allocates an
- * 8-byte shadow word per element, owned by the context and cleared to the
+ * 8-byte shadow word per element (4-byte with HR_CFG_WORD4; the budget
+ * counts whole 8-byte units), owned by the context and cleared to the
  * initial state.  Returns the region id (0..15) in *region_out.
  * Errors: HR_E_INVAL (elem_bytes != 4, bytes not a multiple of 4, 16 regions
  * in use), HR_E_NOMEM (allocation failed or shadow budget exceeded). */
@@ -188,7 +207,10 @@ hr_status hr_dev_args(hr_ctx c, void* out, size_t cap, size_t* size_out);
  * 512 launches it clears the shadow on `stream`.  Races already found stay
  * in the ring; if the ring has overflowed, the global races held in the
  * shadow are first read back and kept for hr_report.  Asynchronous, except
- * at those clears, where it synchronises `stream` to read the ring count. */
+ * at those clears, where it synchronises `stream` to read the ring count.
+ * With HR_CFG_WORD4 it clears the shadow at every call instead, on `stream`
+ * and without synchronising: a word in the race state keeps it when the
+ * ring has overflowed (the clear reads the ring count on the device). */
 hr_status hr_kernel_end(hr_ctx c, void* stream);
 
 /* Start a new job on the same regions: clear shadow memory, report ring,
@@ -228,6 +250,22 @@ hr_status hr_fsm_merge(uint64_t x, uint64_t y, uint32_t wave_bits, uint64_t* out
  * and its clock.  Errors: HR_E_INVAL (null out, unknown space or state tag,
  * wave_bits outside 1..6). */
 hr_status hr_describe(uint32_t space, uint64_t word, uint32_t wave_bits, hr_summary* out);
+
+/* Host evaluation of the device transition on a 4-byte global word
+ * (HR_CFG_WORD4) whose field widths are wc_bits, bc_bits and thread_bits
+ * (as in hr_config, 0 for the defaults), for verification only.  The block
+ * and thread are folded to the word's fields as on the device.  Errors:
+ * HR_E_INVAL (null out, kind > 2, widths out of range, bc or wc beyond its
+ * field). */
+hr_status hr_fsm_step_word4(uint32_t old, uint32_t kind, uint32_t block, uint32_t thread,
+                            uint32_t bc, uint32_t wc, uint32_t wave_bits, uint32_t wc_bits,
+                            uint32_t bc_bits, uint32_t thread_bits, uint32_t* new_out);
+
+/* The 8-byte global word holding the same summary as a 4-byte one (launch
+ * 0), for hr_describe.  Widths as in hr_fsm_step_word4.  Errors: HR_E_INVAL
+ * (null out, widths out of range, a state number above 20). */
+hr_status hr_word4_widen(uint32_t word, uint32_t wc_bits, uint32_t bc_bits, uint32_t thread_bits,
+                         uint64_t* out);
 
 /* ----------------------------------------------------------------------
  * Instrumented workloads.  Each *_check entry launches one instrumented
@@ -378,7 +416,7 @@ typedef struct {
  * the context's shadow budget), register its regions in the context, build
  * the work queues (instance, phase, block) and upload the job table.  inst
  * stays owned by the caller; region[] is filled in.  Errors: HR_E_INVAL (a
- * job's shape), HR_E_NOMEM, HR_E_HIP. */
+ * job's shape, a context with HR_CFG_WORD4), HR_E_NOMEM, HR_E_HIP. */
 hr_status hr_batch_create(hr_ctx c, hr_instance* inst, uint32_t n_inst, hr_batch* out);
 
 /* Run every job of the batch to completion in one persistent launch of
@@ -454,7 +492,8 @@ typedef struct {
  * non-blocking streams (default priority) and their rings for the other
  * lanes, and frees them before it returns.  The context's regions are not
  * touched.
- * Errors: HR_E_INVAL (a job's shape, unsorted arrivals, max_items above
+ * Errors: HR_E_INVAL (a context with HR_CFG_WORD4, a job's shape, unsorted
+ * arrivals, max_items above
  * HR_SERVE_MAX_ITEMS, a job with more items per phase than max_items, cap
  * too small: then *n_out holds the number needed), HR_E_NOMEM (a job larger
  * than the budget, or the device allocation failed), HR_E_HIP. */

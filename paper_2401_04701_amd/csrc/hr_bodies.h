@@ -21,8 +21,8 @@
 // after each step unless s == drop; every thread then writes a[0] to
 // out[lb*T + t].  When n < 2T a thread's step-0 operand was loaded by
 // another thread, so a barrier also follows the loads.
-template <bool CHECK>
-__device__ void reduce_body(const hr_env& e, const hr_gref& gin, const hr_gref& gout,
+template <bool CHECK, class G = hr_gref>
+__device__ void reduce_body(const hr_env& e, const G& gin, const G& gout,
                             const int32_t* __restrict__ in, int32_t* __restrict__ out, uint32_t n,
                             uint32_t T, uint32_t lb, uint32_t t, int32_t drop, int32_t* s,
                             uint32_t* sh, uint32_t lds_id)
@@ -43,11 +43,11 @@ __device__ void reduce_body(const hr_env& e, const hr_gref& gin, const hr_gref& 
         // are in flight together: a one-block launch is a chain of round
         // trips, and only this thread touches these words.
         const bool one = t < n, two = t + T < n;
-        const uint64_t q0 = one ? hr_gload<CHECK>(th, gin, base + t) : 0;
-        const uint64_t q1 = two ? hr_gload<CHECK>(th, gin, base + t + T) : 0;
+        const typename G::word q0 = one ? hr_gload<CHECK>(th, gin, base + t) : 0;
+        const typename G::word q1 = two ? hr_gload<CHECK>(th, gin, base + t + T) : 0;
         const int32_t v0 = one ? in[base + t] : 0;
         const int32_t v1 = two ? in[base + t + T] : 0;
-        hr_pend p0{nullptr, 0, 0, 0}, p1{nullptr, 0, 0, 0};
+        typename G::pend p0{}, p1{};
         if (one) p0 = hr_gi<0, CHECK, true>(e, th, gin, base + t, q0);
         if (two) p1 = hr_gi<0, CHECK, true>(e, th, gin, base + t + T, q1);
         if (one) {
@@ -77,7 +77,7 @@ __device__ void reduce_body(const hr_env& e, const hr_gref& gin, const hr_gref& 
     }
     if (act) {
         // the output word's shadow load is in flight during the LDS read
-        const uint64_t pre_out = hr_gload<CHECK>(th, gout, o);
+        const typename G::word pre_out = hr_gload<CHECK>(th, gout, o);
         const int32_t r = s[0];
         hr_l<0, CHECK>(e, th, sh, n, lds_id, 0, HR_SITE_REDUCE_TOTAL);
         out[o] = r;
@@ -90,9 +90,8 @@ __device__ void reduce_body(const hr_env& e, const hr_gref& gin, const hr_gref& 
 // min of l into label[u], or for a seeded edge a plain read and plain write
 // of label[u].  grp / gcol: optional monitoring of the CSR reads (shadow
 // null when off).
-template <bool CHECK, bool PAIRS = false>
-__device__ void labelprop_body(const hr_env& e, const hr_gref& glab, const hr_gref& grp,
-                               const hr_gref& gcol, int32_t* __restrict__ label,
+template <bool CHECK, bool PAIRS = false, class G = hr_gref>
+__device__ void labelprop_body(const hr_env& e, const G& glab, const G& grp, const G& gcol, int32_t* __restrict__ label,
                                const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
                                const uint8_t* __restrict__ mask, uint32_t n, uint32_t T, uint32_t lb,
                                uint32_t t)
@@ -132,16 +131,16 @@ __device__ void labelprop_body(const hr_env& e, const hr_gref& glab, const hr_gr
         // workload body, can give; they run the one-edge loop below.)
         const auto col_at = [&](int32_t q) { return q < e1 ? (uint32_t)col[q] : 0u; };
         uint32_t a0 = col_at(e0), b0 = col_at(e0 + 1), a1 = col_at(e0 + 2), b1 = col_at(e0 + 3);
-        uint64_t sa = e0 < e1 ? hr_gload<CHECK>(th, glab, a0) : 0;
-        uint64_t sb = e0 + 1 < e1 ? hr_gload<CHECK>(th, glab, b0) : 0;
+        typename G::word sa = e0 < e1 ? hr_gload<CHECK>(th, glab, a0) : 0;
+        typename G::word sb = e0 + 1 < e1 ? hr_gload<CHECK>(th, glab, b0) : 0;
         uint8_t ma = e0 < e1 ? mask[e0] : 0, mb = e0 + 1 < e1 ? mask[e0 + 1] : 0;
         for (int32_t k = e0; k < e1; k += 2) {
             const uint32_t a2 = col_at(k + 4), b2 = col_at(k + 5);
-            const uint64_t na = k + 2 < e1 ? hr_gload<CHECK>(th, glab, a1) : 0;
-            const uint64_t nb = k + 3 < e1 ? hr_gload<CHECK>(th, glab, b1) : 0;
+            const typename G::word na = k + 2 < e1 ? hr_gload<CHECK>(th, glab, a1) : 0;
+            const typename G::word nb = k + 3 < e1 ? hr_gload<CHECK>(th, glab, b1) : 0;
             const uint8_t nma = k + 2 < e1 ? mask[k + 2] : 0, nmb = k + 3 < e1 ? mask[k + 3] : 0;
             const uint32_t ua = a0, ub = b0;
-            const uint64_t qa = sa, qb = sb;
+            const typename G::word qa = sa, qb = sb;
             const uint8_t fa = ma, fb = mb;
             const bool two = k + 1 < e1;
             a0 = a1;
@@ -156,7 +155,7 @@ __device__ void labelprop_body(const hr_env& e, const hr_gref& glab, const hr_gr
                 hr_g<0, CHECK>(e, th, gcol, (uint64_t)k, HR_SITE_LP_CSR);
                 if (two) hr_g<0, CHECK>(e, th, gcol, (uint64_t)k + 1, HR_SITE_LP_CSR);
             }
-            hr_pend pa{nullptr, 0, 0, 0}, pb{nullptr, 0, 0, 0};
+            typename G::pend pa{}, pb{};
             if (ua < n) {
                 if (fa) {
                     const int32_t r = label[ua];
@@ -189,14 +188,14 @@ __device__ void labelprop_body(const hr_env& e, const hr_gref& glab, const hr_gr
     // shadow word of its target, are already in flight.
     uint32_t u0 = e0 < e1 ? (uint32_t)col[e0] : 0u;
     uint32_t u1 = e0 + 1 < e1 ? (uint32_t)col[e0 + 1] : 0u;
-    uint64_t s0 = e0 < e1 ? hr_gload<CHECK>(th, glab, u0) : 0;
+    typename G::word s0 = e0 < e1 ? hr_gload<CHECK>(th, glab, u0) : 0;
     uint8_t m0 = e0 < e1 ? mask[e0] : 0;
     for (int32_t k = e0; k < e1; ++k) {
         const uint32_t u2 = k + 2 < e1 ? (uint32_t)col[k + 2] : 0u;
-        const uint64_t s1 = k + 1 < e1 ? hr_gload<CHECK>(th, glab, u1) : 0;
+        const typename G::word s1 = k + 1 < e1 ? hr_gload<CHECK>(th, glab, u1) : 0;
         const uint8_t m1 = k + 1 < e1 ? mask[k + 1] : 0;
         const uint32_t u = u0;
-        const uint64_t su = s0;
+        const typename G::word su = s0;
         const uint8_t seeded = m0;
         u0 = u1;
         u1 = u2;

@@ -66,12 +66,15 @@ struct hr_env {
     uint32_t group;                     // wave grouping at data-dependent hook sites
     uint32_t site_limit;                // race records per call site; 0: no limit
     uint32_t wave_bits;                 // 6: waves synchronize; s < 6: tiles of 2^s lanes
+    uint32_t word4;                     // 0: 8-byte global words; else the 4-byte
+                                        // word layout (hr::c::layout)
 };
 
 // Plain-old-data block handed to instrumented kernels by value.
 struct hr_kargs {
     hr_env env;
-    uint64_t* shadow[HR_MAX_REGIONS];   // 8-byte shadow word per element
+    uint64_t* shadow[HR_MAX_REGIONS];   // shadow words, one per element (4-byte
+                                        // words at this address when env.word4)
     uint64_t n_elems[HR_MAX_REGIONS];   // elements per region (0: unused)
     void* data[HR_MAX_REGIONS];         // monitored buffer of each region
 };
@@ -387,7 +390,148 @@ __device__ __forceinline__ uint64_t hr_check_load(const hr_thread& t, uint64_t* 
                : 0;
 }
 
-// The same check for a region named by its kernel-argument slot.
+// ---------------------------------------------------------------------------
+// The same hooks on 4-byte global words (a context created with
+// HR_CFG_WORD4; word layout hr::c, e.word4).  Every transition and merge
+// widens its words to the 64-bit layout and narrows the result, so a 4-byte
+// word always holds the summary the 64-bit machine would hold for the same
+// accesses (block ids and thread indices folded to the word's fields), and
+// race records carry widened summaries.
+// ---------------------------------------------------------------------------
+#define HR_NO_REPORT4 (~0u)   // not a word: state numbers stop at 20
+
+__device__ __forceinline__ uint64_t hr_id4(const hr_env& e, const hr_thread& t)
+{
+    return hr::c::pack_id(t.block, t.thread, t.bc, t.wc, e.word4);
+}
+
+__device__ __noinline__ uint32_t hr_fold4(uint32_t* sp, uint32_t mine, uint32_t lost, uint64_t wm,
+                                          uint32_t lay)
+{
+    uint32_t cur = mine;
+    for (;;) {
+        const uint32_t m = hr::c::merge(cur, lost, wm, lay);
+        if (m == cur) return HR_NO_REPORT4;
+        uint32_t seen = cur;
+        if (__hip_atomic_compare_exchange_strong(sp, &seen, m, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT))
+            return (m == hr::T_RACE && lost != hr::T_RACE) ? cur : HR_NO_REPORT4;
+        cur = seen;
+    }
+}
+
+template <int KIND>
+__device__ __forceinline__ void hr_settle4(const hr_env& e, const hr_thread& t, uint32_t* sp,
+                                           uint32_t region, uint64_t index, uint32_t site,
+                                           uint32_t old, uint32_t nw, uint32_t r, uint32_t other,
+                                           uint64_t other_id)
+{
+    constexpr uint32_t k = KIND == 0 ? hr::CL_R : (KIND == 2 ? hr::CL_A : hr::CL_X);
+    const uint64_t wm = hr::g::group_mask(e.wave_bits);
+    const uint32_t lay = e.word4;
+    if (nw == hr::T_RACE) {
+        if (r != hr::T_RACE) {
+            uint64_t before = hr::c::widen(old, lay), with = hr::g::step(hr::T_INIT, hr_id4(e, t), k, wm);
+            if (other != HR_NO_LANE) {
+                const uint64_t pair = hr::g::step(with, other_id, k, wm);
+                if (pair == hr::T_RACE) before = hr::g::step(hr::T_INIT, other_id, k, wm);
+                else with = pair;
+            }
+            hr_ring_push(e, 0, region, t.block, index, t.thread, KIND, site, before, with, 0);
+        }
+        return;
+    }
+    if (r != old) {
+        const uint32_t before = hr_fold4(sp, nw, r, wm, lay);
+        if (before != HR_NO_REPORT4)
+            hr_ring_push(e, 0, region, t.block, index, t.thread, KIND, site,
+                         hr::c::widen(before, lay), hr::c::widen(r, lay), HR_RACE_FOLD);
+    }
+}
+
+template <int KIND, bool GROUP = false, bool PRE = false>
+__device__ __forceinline__ void hr_check4(const hr_env& e, const hr_thread& t, uint32_t* shadow,
+                                          uint64_t n, uint32_t region, uint64_t index,
+                                          uint32_t site = 0, uint32_t pre = 0)
+{
+    if (t.enabled != 1 || !shadow) return;
+    hr_count(e, t);
+    if (index >= n) {
+        hr_set_flag(e, HR_DEVF_RANGE);
+        return;
+    }
+    constexpr uint32_t k = KIND == 0 ? hr::CL_R : (KIND == 2 ? hr::CL_A : hr::CL_X);
+    uint32_t* sp = shadow + index;
+    const uint32_t lay = e.word4;
+    const uint64_t wm = hr::g::group_mask(e.wave_bits);
+    uint32_t other = HR_NO_LANE;
+    if (GROUP && e.group && e.wave_bits == 6) {
+        bool member;
+        other = hr_group((uint64_t)sp >> 2, &member);
+        if (member) return;
+    }
+    const uint32_t old =
+        PRE ? pre : __hip_atomic_load(sp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t nw = hr::c::step(old, hr_id4(e, t), k, wm, lay);
+    uint64_t other_id = 0;
+    if (other != HR_NO_LANE) {
+        other_id = hr::c::pack_id(t.block, t.thread - __lane_id() + other, t.bc, t.wc, lay);
+        nw = hr::c::step(nw, other_id, k, wm, lay);
+    }
+    if (nw == old) return;
+    const uint32_t r = __hip_atomic_exchange(sp, nw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    hr_settle4<KIND>(e, t, sp, region, index, site, old, nw, r, other, other_id);
+}
+
+struct hr_pend4 {
+    uint32_t* sp;        // nullptr: nothing to settle
+    uint32_t old, nw, r;
+};
+
+template <int KIND, bool PRE = false>
+__device__ __forceinline__ hr_pend4 hr_check4_issue(const hr_env& e, const hr_thread& t,
+                                                    uint32_t* shadow, uint64_t n, uint64_t index,
+                                                    uint32_t pre = 0)
+{
+    hr_pend4 p{nullptr, 0, 0, 0};
+    if (t.enabled != 1 || !shadow) return p;
+    hr_count(e, t);
+    if (index >= n) {
+        hr_set_flag(e, HR_DEVF_RANGE);
+        return p;
+    }
+    constexpr uint32_t k = KIND == 0 ? hr::CL_R : (KIND == 2 ? hr::CL_A : hr::CL_X);
+    uint32_t* sp = shadow + index;
+    const uint32_t old =
+        PRE ? pre : __hip_atomic_load(sp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t nw =
+        hr::c::step(old, hr_id4(e, t), k, hr::g::group_mask(e.wave_bits), e.word4);
+    if (nw == old) return p;
+    p.sp = sp;
+    p.old = old;
+    p.nw = nw;
+    p.r = __hip_atomic_exchange(sp, nw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return p;
+}
+
+template <int KIND>
+__device__ __forceinline__ void hr_check4_settle(const hr_env& e, const hr_thread& t,
+                                                 const hr_pend4& p, uint32_t region,
+                                                 uint64_t index, uint32_t site)
+{
+    if (p.sp) hr_settle4<KIND>(e, t, p.sp, region, index, site, p.old, p.nw, p.r, HR_NO_LANE, 0);
+}
+
+__device__ __forceinline__ uint32_t hr_check4_load(const hr_thread& t, uint32_t* shadow,
+                                                   uint64_t n, uint64_t index)
+{
+    return (t.enabled == 1 && shadow && index < n)
+               ? __hip_atomic_load(shadow + index, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+               : 0u;
+}
+
+// The same check for a region named by its kernel-argument slot (the
+// context's word size decides the hook).
 template <int KIND>
 __device__ __forceinline__ void hr_access(const hr_kargs& a, const hr_thread& t, uint32_t region,
                                           uint64_t index, uint32_t site = 0)
@@ -396,7 +540,11 @@ __device__ __forceinline__ void hr_access(const hr_kargs& a, const hr_thread& t,
         if (t.enabled == 1) hr_set_flag(a.env, HR_DEVF_RANGE);
         return;
     }
-    hr_check<KIND, true>(a.env, t, a.shadow[region], a.n_elems[region], region, index, site);
+    if (a.env.word4)
+        hr_check4<KIND, true>(a.env, t, (uint32_t*)a.shadow[region], a.n_elems[region], region,
+                              index, site);
+    else
+        hr_check<KIND, true>(a.env, t, a.shadow[region], a.n_elems[region], region, index, site);
 }
 
 // Check one access to word `index` of a block's LDS array `array_id`, whose
@@ -437,6 +585,13 @@ __device__ __forceinline__ void hr_check_k(const hr_env& e, const hr_thread& t, 
                                            uint64_t* shadow, uint64_t n, uint32_t region,
                                            uint64_t index, uint32_t site = 0)
 {
+    if (e.word4) {
+        uint32_t* s4 = (uint32_t*)shadow;
+        if (kind == 0) hr_check4<0, true>(e, t, s4, n, region, index, site);
+        else if (kind == 1) hr_check4<1, true>(e, t, s4, n, region, index, site);
+        else hr_check4<2, true>(e, t, s4, n, region, index, site);
+        return;
+    }
     if (kind == 0) hr_check<0, true>(e, t, shadow, n, region, index, site);
     else if (kind == 1) hr_check<1, true>(e, t, shadow, n, region, index, site);
     else hr_check<2, true>(e, t, shadow, n, region, index, site);

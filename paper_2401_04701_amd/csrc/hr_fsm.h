@@ -192,6 +192,127 @@ HR_HD uint64_t merge(uint64_t x, uint64_t y, uint64_t wm = WAVE_M)
 }  // namespace g
 
 // ---------------------------------------------------------------------------
+// Global-memory shadow word, 32 bits (the 4-byte footprint variant):
+//   state 5 | wc W | bc B | thread T | block K,   K = 27 - W - B - T.
+// The 21 states reachable in the machine above (INIT, RACE, MB(k), 4 MW,
+// 6 MT, 7 ST) are numbered 0..20; W, B and T are the context's clock and
+// thread widths.  There is no launch field: the runtime returns every word
+// to INIT at each launch boundary instead.  Widening a word gives the 64-bit
+// word of the same summary (launch 0, the block as stored), so transitions
+// and merges are the 64-bit ones.  Exact while a launch's block ids, thread
+// indices and clocks fit their fields.  Block ids and thread indices beyond
+// them are folded (taken modulo 2^K and 2^T), which makes distinct accessors
+// look alike: accesses of two blocks (threads) that share a folded id are
+// treated as one block's (thread's), which can hide a race but never
+// creates one.
+// The layout travels as one word: bc_sh | th_sh << 8 | bl_sh << 16 (the wave
+// clock always starts at bit 5); 0 means the 64-bit word.
+// ---------------------------------------------------------------------------
+namespace c {
+constexpr uint32_t STATE_BITS = 5, WC_SH = 5, N_STATES = 21;
+
+HR_HD uint32_t layout(uint32_t wc_bits, uint32_t bc_bits, uint32_t thread_bits)
+{
+    const uint32_t bc_sh = WC_SH + wc_bits, th_sh = bc_sh + bc_bits, bl_sh = th_sh + thread_bits;
+    return bc_sh | (th_sh << 8) | (bl_sh << 16);
+}
+HR_HD uint32_t bc_sh(uint32_t lay) { return lay & 255u; }
+HR_HD uint32_t th_sh(uint32_t lay) { return (lay >> 8) & 255u; }
+HR_HD uint32_t bl_sh(uint32_t lay) { return (lay >> 16) & 255u; }
+HR_HD uint32_t thread_mask(uint32_t lay) { return (1u << (bl_sh(lay) - th_sh(lay))) - 1u; }
+// The block field keeps K = 32 - bl_sh >= 3 bits (widths are at most 6, 8 and
+// 10), of which at most 22 are used, as in the 64-bit word.
+HR_HD uint32_t block_mask(uint32_t lay) { return (0xFFFFFFFFu >> bl_sh(lay)) & (g::BLOCK_LIMIT - 1u); }
+
+// State code (tag | cW << 3 | cB << 5 | cL << 7, the low 9 bits of the
+// 64-bit word) of each state number, seven 9-bit codes per constant:
+//   0 INIT, 1 RACE, 2-3 MB(R/A), 4-7 MW(k, cL) for k = R, A and cL = k, X,
+//   8-13 MT and 14-19 ST with cW = R, A and (cB, cL) = (cW,cW), (cW,X), (X,X),
+//   20 ST(X, X, X).
+constexpr uint64_t code7(uint32_t a, uint32_t b, uint32_t c_, uint32_t d, uint32_t e, uint32_t f,
+                         uint32_t h)
+{
+    return (uint64_t)a | ((uint64_t)b << 9) | ((uint64_t)c_ << 18) | ((uint64_t)d << 27) |
+           ((uint64_t)e << 36) | ((uint64_t)f << 45) | ((uint64_t)h << 54);
+}
+constexpr uint32_t sc(uint32_t tag, uint32_t cl, uint32_t cb, uint32_t cw)
+{
+    return tag | (cw << 3) | (cb << 5) | (cl << 7);
+}
+constexpr uint64_t CODES0 = code7(0, T_RACE, sc(T_MB, 0, CL_R, 0), sc(T_MB, 0, CL_A, 0),
+                                  sc(T_MW, CL_R, CL_R, 0), sc(T_MW, CL_X, CL_R, 0),
+                                  sc(T_MW, CL_A, CL_A, 0));
+constexpr uint64_t CODES1 = code7(sc(T_MW, CL_X, CL_A, 0), sc(T_MT, CL_R, CL_R, CL_R),
+                                  sc(T_MT, CL_X, CL_R, CL_R), sc(T_MT, CL_X, CL_X, CL_R),
+                                  sc(T_MT, CL_A, CL_A, CL_A), sc(T_MT, CL_X, CL_A, CL_A),
+                                  sc(T_MT, CL_X, CL_X, CL_A));
+constexpr uint64_t CODES2 = code7(sc(T_ST, CL_R, CL_R, CL_R), sc(T_ST, CL_X, CL_R, CL_R),
+                                  sc(T_ST, CL_X, CL_X, CL_R), sc(T_ST, CL_A, CL_A, CL_A),
+                                  sc(T_ST, CL_X, CL_A, CL_A), sc(T_ST, CL_X, CL_X, CL_A),
+                                  sc(T_ST, CL_X, CL_X, CL_X));
+
+HR_HD uint32_t code_of(uint32_t idx)
+{
+    const uint64_t tbl = idx < 7 ? CODES0 : (idx < 14 ? CODES1 : CODES2);
+    const uint32_t j = idx < 7 ? idx : (idx < 14 ? idx - 7 : idx - 14);
+    return (uint32_t)(tbl >> (9 * j)) & 511u;
+}
+
+// State number of a state code (the inverse of code_of on the 21 codes).
+HR_HD uint32_t index_of(uint32_t code)
+{
+    const uint32_t tag = code & 7u, cw = (code >> 3) & 3u, cb = (code >> 5) & 3u,
+                   cl = (code >> 7) & 3u;
+    const uint32_t nx = (cl == CL_X ? 1u : 0u) + (cb == CL_X ? 1u : 0u);
+    if (tag <= T_RACE) return tag;
+    if (tag == T_MB) return 1u + cb;
+    if (tag == T_MW) return 4u + 2u * (cb - 1u) + (cl == CL_X ? 1u : 0u);
+    if (tag == T_MT) return 8u + 3u * (cw - 1u) + nx;
+    return cw == CL_X ? 20u : 14u + 3u * (cw - 1u) + nx;
+}
+
+// 32-bit word -> 64-bit word of the same summary.
+HR_HD uint64_t widen(uint32_t w, uint32_t lay)
+{
+    const uint32_t bs = bc_sh(lay), ts = th_sh(lay), ls = bl_sh(lay);
+    const uint32_t wc = (w >> WC_SH) & ((1u << (bs - WC_SH)) - 1u);
+    const uint32_t bc = (w >> bs) & ((1u << (ts - bs)) - 1u);
+    const uint32_t th = (w >> ts) & ((1u << (ls - ts)) - 1u);
+    const uint32_t bl = w >> ls;
+    return (uint64_t)code_of(w & 31u) | ((uint64_t)wc << g::WC_SH) | ((uint64_t)bc << g::BC_SH) |
+           ((uint64_t)th << g::TH_SH) | ((uint64_t)bl << g::BL_SH);
+}
+
+// 64-bit word (launch 0, fields within the layout's widths) -> 32-bit word.
+HR_HD uint32_t narrow(uint64_t x, uint32_t lay)
+{
+    const uint32_t wc = (uint32_t)(x >> g::WC_SH) & 63u;
+    const uint32_t bc = (uint32_t)(x >> g::BC_SH) & 255u;
+    const uint32_t th = (uint32_t)(x >> g::TH_SH) & 1023u;
+    const uint32_t bl = (uint32_t)(x >> g::BL_SH) & (g::BLOCK_LIMIT - 1u);
+    return index_of((uint32_t)x & 511u) | (wc << WC_SH) | (bc << bc_sh(lay)) |
+           (th << th_sh(lay)) | (bl << bl_sh(lay));
+}
+
+// Identity fields of an access in the 64-bit layout, block and thread folded
+// to the 32-bit word's widths and launch 0.
+HR_HD uint64_t pack_id(uint32_t block, uint32_t thread, uint32_t bc, uint32_t wc, uint32_t lay)
+{
+    return g::pack_id(0, block & block_mask(lay), thread & thread_mask(lay), bc, wc);
+}
+
+HR_HD uint32_t step(uint32_t old, uint64_t id, uint32_t k, uint64_t wm, uint32_t lay)
+{
+    return narrow(g::step(widen(old, lay), id, k, wm), lay);
+}
+
+HR_HD uint32_t merge(uint32_t x, uint32_t y, uint64_t wm, uint32_t lay)
+{
+    return narrow(g::merge(widen(x, lay), widen(y, lay), wm), lay);
+}
+}  // namespace c
+
+// ---------------------------------------------------------------------------
 // LDS shadow word, 32 bits: tag 3 | cW 2 | cB 2 | wc 6 | bc 8 | thread 10.
 // LDS is private to one block and one launch, so there is no launch, block,
 // multi-block state or launch-wide class.

@@ -15,8 +15,8 @@ constexpr uint32_t JACOBI_TILE_WORDS = JACOBI_TILE * JACOBI_TILE;
 // sweep u_new = 0.2 (c + n + s + w + e), staged through an 18x18 LDS tile.
 // seeds: NULL or per-block (side << 8 | offset) entries (-1: none); a seeded
 // block's edge thread also writes the neighbour-owned halo cell.
-template <bool CHECK>
-__device__ void jacobi_body(const hr_env& e, const hr_gref& gold, const hr_gref& gnew,
+template <bool CHECK, class G = hr_gref>
+__device__ void jacobi_body(const hr_env& e, const G& gold, const G& gnew,
                             const float* __restrict__ uo, float* __restrict__ un, uint32_t ny,
                             uint32_t nx, uint32_t nbx, const int32_t* __restrict__ seeds,
                             uint32_t lb, uint32_t t, float* tile, uint32_t* tsh, uint32_t lds_id)
@@ -52,20 +52,20 @@ __device__ void jacobi_body(const hr_env& e, const hr_gref& gold, const hr_gref&
         // in flight.  (The staging hook comes before its store: the store
         // needs the loaded value, and waiting for it waits for the exchange
         // too.)
-        const hr_pend pc = hr_gi<0, CHECK>(e, th, gold, g);
+        const typename G::pend pc = hr_gi<0, CHECK>(e, th, gold, g);
         hr_l<1, CHECK>(e, th, tsh, TW, lds_id, cl, HR_SITE_JACOBI_STAGE);
         tile[cl] = vc;
         hr_gs<0, CHECK>(e, th, gold, pc, g, HR_SITE_JACOBI_CENTRE);
         if (hn || hs) {
             const uint32_t lr = hn ? tx + 1 : 17 * TL + tx + 1;
-            const hr_pend pr = hr_gi<0, CHECK>(e, th, gold, gr);
+            const typename G::pend pr = hr_gi<0, CHECK>(e, th, gold, gr);
             hr_l<1, CHECK>(e, th, tsh, TW, lds_id, lr, HR_SITE_JACOBI_STAGE);
             tile[lr] = vr;
             hr_gs<0, CHECK>(e, th, gold, pr, gr, HR_SITE_JACOBI_HALO);
         }
         if (hw || he) {
             const uint32_t lc = hw ? (ty + 1) * TL : (ty + 1) * TL + 17;
-            const hr_pend pk = hr_gi<0, CHECK>(e, th, gold, gc);
+            const typename G::pend pk = hr_gi<0, CHECK>(e, th, gold, gc);
             hr_l<1, CHECK>(e, th, tsh, TW, lds_id, lc, HR_SITE_JACOBI_STAGE);
             tile[lc] = vk;
             hr_gs<0, CHECK>(e, th, gold, pk, gc, HR_SITE_JACOBI_HALO);
@@ -74,7 +74,7 @@ __device__ void jacobi_body(const hr_env& e, const hr_gref& gold, const hr_gref&
     hr_bar<CHECK>(e, th);
     if (inside) {
         // the output word's shadow load is in flight during the LDS reads
-        const uint64_t pre_out = hr_gload<CHECK>(th, gnew, g);
+        const typename G::word pre_out = hr_gload<CHECK>(th, gnew, g);
         const float c = tile[cl];
         hr_l<0, CHECK>(e, th, tsh, TW, lds_id, cl, HR_SITE_JACOBI_TILE);
         float vn = c, vs = c, vw = c, ve = c;
@@ -129,6 +129,18 @@ __global__ __launch_bounds__(256, 8) void k_jacobi(hr_kargs a, hr_gref gold, hr_
     __shared__ uint32_t tsh[CHECK ? JACOBI_TILE_WORDS : 1];
     jacobi_body<CHECK>(a.env, gold, gnew, uo, un, ny, nx, gridDim.x, seeds,
                        blockIdx.y * gridDim.x + blockIdx.x, threadIdx.x, tile, tsh, 0);
+}
+
+// The checked sweep on 4-byte shadow words.
+__global__ __launch_bounds__(256, 8) void k_jacobi4(hr_kargs a, hr_gref4 gold, hr_gref4 gnew,
+                                                 const float* __restrict__ uo,
+                                                 float* __restrict__ un, uint32_t ny, uint32_t nx,
+                                                 const int32_t* __restrict__ seeds)
+{
+    __shared__ float tile[JACOBI_TILE_WORDS];
+    __shared__ uint32_t tsh[JACOBI_TILE_WORDS];
+    jacobi_body<true>(a.env, gold, gnew, uo, un, ny, nx, gridDim.x, seeds,
+                      blockIdx.y * gridDim.x + blockIdx.x, threadIdx.x, tile, tsh, 0);
 }
 
 }  // namespace

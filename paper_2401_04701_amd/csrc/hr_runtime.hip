@@ -26,6 +26,26 @@ __global__ void k_fill32(uint32_t* __restrict__ p, size_t n, uint32_t v)
     for (; i < n; i += stride) p[i] = v;
 }
 
+// The launch-boundary clear of 4-byte words, two per 8-byte unit: back to
+// the initial state, except that while the ring has overflowed (read on the
+// device) a word in the race state keeps it for the report's scan.
+__global__ void k_clear_word4(uint64_t* __restrict__ p, size_t n, const uint32_t* __restrict__ ctr,
+                              uint32_t ring_cap)
+{
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    if (ctr[HR_CTR_HEAD] <= ring_cap) {
+        for (; i < n; i += stride) p[i] = 0;
+        return;
+    }
+    for (; i < n; i += stride) {
+        const uint64_t v = p[i];
+        const uint64_t lo = (uint32_t)v == hr::T_RACE ? hr::T_RACE : 0u;
+        const uint64_t hi = (uint32_t)(v >> 32) == hr::T_RACE ? hr::T_RACE : 0u;
+        p[i] = lo | (hi << 32);
+    }
+}
+
 hr_status clear_shadows(hr_ctx c, hipStream_t s)
 {
     for (const hr_alloc& al : c->allocs)
@@ -90,6 +110,9 @@ hr_env hr_make_env(hr_ctx c)
     e.group = (c->cfg.flags & HR_CFG_WAVE_GROUPING) ? 1u : 0u;
     e.site_limit = c->cfg.site_limit;
     e.wave_bits = c->cfg.wave_bits;
+    e.word4 = (c->cfg.flags & HR_CFG_WORD4)
+                  ? hr::c::layout(c->cfg.wc_bits, c->cfg.bc_bits, c->cfg.thread_bits)
+                  : 0u;
     return e;
 }
 
@@ -151,11 +174,14 @@ extern "C" hr_status hr_ctx_create(hr_ctx* out, const hr_config* cfg, void* stre
     *out = nullptr;
     hr_config k = {};
     if (cfg) k = *cfg;
+    const bool word4 = (k.flags & HR_CFG_WORD4) != 0;
     if (k.ring_capacity == 0) k.ring_capacity = 65536;
-    if (k.bc_bits == 0) k.bc_bits = 8;
-    if (k.wc_bits == 0) k.wc_bits = 6;
+    if (k.bc_bits == 0) k.bc_bits = word4 ? 2 : 8;
+    if (k.wc_bits == 0) k.wc_bits = word4 ? 1 : 6;
+    if (k.thread_bits == 0) k.thread_bits = word4 ? 8 : 10;
     if (k.bc_bits > 8 || k.wc_bits > 6 || k.ring_capacity > (1u << 26)) return HR_E_INVAL;
-    if (k.flags & ~(HR_CFG_COUNT_CHECKS | HR_CFG_WAVE_GROUPING)) return HR_E_INVAL;
+    if (k.thread_bits > 10 || (!word4 && k.thread_bits != 10)) return HR_E_INVAL;
+    if (k.flags & ~(HR_CFG_COUNT_CHECKS | HR_CFG_WAVE_GROUPING | HR_CFG_WORD4)) return HR_E_INVAL;
     if (k.wave_bits == 0) k.wave_bits = 6;
     if (k.wave_bits > 6) return HR_E_INVAL;
     hr_ctx c = new (std::nothrow) hr_ctx_s();
@@ -201,7 +227,8 @@ extern "C" hr_status hr_shadow_alloc(hr_ctx c, const void* data_dev, size_t byte
     if (c->reg.size() >= (1u << 24)) return HR_E_INVAL;
     const size_t elems = bytes / 4;
     uint32_t alloc = 0;
-    const hr_status st = hr_new_alloc(c, elems, &alloc);
+    const size_t words = (c->cfg.flags & HR_CFG_WORD4) ? (elems + 1) / 2 : elems;
+    const hr_status st = hr_new_alloc(c, words, &alloc);
     if (st != HR_OK) return st;
     *region_out = hr_new_region(c, data_dev, elems, c->allocs[alloc].mem, alloc);
     return HR_OK;
@@ -227,26 +254,40 @@ extern "C" hr_status hr_dev_args(hr_ctx c, void* out, size_t cap, size_t* size_o
     return HR_OK;
 }
 
+static hr_race scanned_race(uint32_t region, size_t index)
+{
+    hr_race x = {};
+    x.space = HR_GLOBAL;
+    x.region = region;
+    x.block = 0xFFFFFFFFu;
+    x.launch = 0xFFFFFFFFu;
+    x.index = index;
+    x.tid = 0xFFFFFFFFu;
+    x.flags = HR_RACE_SCANNED;
+    return x;
+}
+
 // The global races held in the sticky race words of every live region.
 static hr_status scan_races(hr_ctx c, std::vector<hr_race>& out)
 {
+    const bool word4 = (c->cfg.flags & HR_CFG_WORD4) != 0;
     for (uint32_t r = 0; r < c->reg.size(); ++r) {
         if (!c->reg[r].live) continue;
+        if (word4) {
+            std::vector<uint32_t> sh(c->reg[r].elems);
+            if (hipMemcpy(sh.data(), c->reg[r].shadow, sizeof(uint32_t) * sh.size(),
+                          hipMemcpyDeviceToHost) != hipSuccess)
+                return HR_E_HIP;
+            for (size_t i = 0; i < sh.size(); ++i)
+                if (sh[i] == hr::T_RACE) out.push_back(scanned_race(r, i));
+            continue;
+        }
         std::vector<uint64_t> sh(c->reg[r].elems);
         if (hipMemcpy(sh.data(), c->reg[r].shadow, sizeof(uint64_t) * sh.size(),
                       hipMemcpyDeviceToHost) != hipSuccess)
             return HR_E_HIP;
         for (size_t i = 0; i < sh.size(); ++i) {
-            if ((sh[i] & hr::g::TAG_M) != hr::T_RACE) continue;
-            hr_race x = {};
-            x.space = HR_GLOBAL;
-            x.region = r;
-            x.block = 0xFFFFFFFFu;
-            x.launch = 0xFFFFFFFFu;
-            x.index = i;
-            x.tid = 0xFFFFFFFFu;
-            x.flags = HR_RACE_SCANNED;
-            out.push_back(x);
+            if ((sh[i] & hr::g::TAG_M) == hr::T_RACE) out.push_back(scanned_race(r, i));
         }
     }
     return HR_OK;
@@ -256,6 +297,17 @@ extern "C" hr_status hr_kernel_end(hr_ctx c, void* stream)
 {
     if (!c) return HR_E_INVAL;
     c->launch_seq += 1;
+    if (c->cfg.flags & HR_CFG_WORD4) {
+        // No launch field: every boundary returns the words to INIT.
+        hipStream_t s = hr_stream(c, stream);
+        for (const hr_alloc& al : c->allocs) {
+            if (!al.live || al.words == 0) continue;
+            const size_t blocks = std::min<size_t>((al.words + 255) / 256, 8192);
+            HR_LAUNCH(k_clear_word4, dim3((unsigned)blocks), dim3(256), 0, s, al.mem, al.words,
+                      c->ctr, c->cfg.ring_capacity);
+        }
+        return HR_OK;
+    }
     // The launch epoch in a shadow word has 9 bits: before it wraps, return
     // every word to the initial state.  Exact: all earlier accesses happen
     // before all later ones, and the races found so far are in the ring.
@@ -413,6 +465,39 @@ extern "C" hr_status hr_describe(uint32_t space, uint64_t word, uint32_t wave_bi
         d.thread = th;
     }
     *out = d;
+    return HR_OK;
+}
+
+static bool word4_widths(uint32_t* wc_bits, uint32_t* bc_bits, uint32_t* thread_bits)
+{
+    if (*wc_bits == 0) *wc_bits = 1;
+    if (*bc_bits == 0) *bc_bits = 2;
+    if (*thread_bits == 0) *thread_bits = 8;
+    return *wc_bits <= 6 && *bc_bits <= 8 && *thread_bits <= 10;   // the block keeps >= 3 bits
+}
+
+extern "C" hr_status hr_fsm_step_word4(uint32_t old, uint32_t kind, uint32_t block,
+                                       uint32_t thread, uint32_t bc, uint32_t wc,
+                                       uint32_t wave_bits, uint32_t wc_bits, uint32_t bc_bits,
+                                       uint32_t thread_bits, uint32_t* new_out)
+{
+    if (!new_out || kind > 2 || wave_bits < 1 || wave_bits > 6 ||
+        !word4_widths(&wc_bits, &bc_bits, &thread_bits) || bc >= (1u << bc_bits) ||
+        wc >= (1u << wc_bits) || (old & 31u) >= hr::c::N_STATES)
+        return HR_E_INVAL;
+    const uint32_t lay = hr::c::layout(wc_bits, bc_bits, thread_bits);
+    *new_out = hr::c::step(old, hr::c::pack_id(block, thread, bc, wc, lay), hr::kind_class(kind),
+                           hr::g::group_mask(wave_bits), lay);
+    return HR_OK;
+}
+
+extern "C" hr_status hr_word4_widen(uint32_t word, uint32_t wc_bits, uint32_t bc_bits,
+                                    uint32_t thread_bits, uint64_t* out)
+{
+    if (!out || !word4_widths(&wc_bits, &bc_bits, &thread_bits) ||
+        (word & 31u) >= hr::c::N_STATES)
+        return HR_E_INVAL;
+    *out = hr::c::widen(word, hr::c::layout(wc_bits, bc_bits, thread_bits));
     return HR_OK;
 }
 

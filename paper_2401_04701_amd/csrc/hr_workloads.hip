@@ -21,6 +21,16 @@ hr_gref gref(const hr_kargs& a, uint32_t r)
     return g;
 }
 
+hr_gref4 gref4(const hr_kargs& a, uint32_t r)
+{
+    hr_gref4 g{nullptr, 0, r};
+    if (r < HR_MAX_REGIONS) {
+        g.shadow = (uint32_t*)a.shadow[r];
+        g.n = a.n_elems[r];
+    }
+    return g;
+}
+
 template <bool CHECK>
 __global__ __launch_bounds__(1024) void k_reduce(hr_kargs a, hr_gref gin, hr_gref gout,
                                                  const int32_t* __restrict__ in,
@@ -41,6 +51,27 @@ __global__ __launch_bounds__(1024) void k_labelprop(hr_kargs a, hr_gref glab, hr
 {
     labelprop_body<CHECK, true>(a.env, glab, grp, gcol, label, rp, col, mask, n, blockDim.x,
                                 blockIdx.x, threadIdx.x);
+}
+
+// The checked kernels on 4-byte shadow words.
+__global__ __launch_bounds__(1024) void k_reduce4(hr_kargs a, hr_gref4 gin, hr_gref4 gout,
+                                                  const int32_t* __restrict__ in,
+                                                  int32_t* __restrict__ out, uint32_t n,
+                                                  int32_t drop)
+{
+    extern __shared__ uint32_t smem[];
+    reduce_body<true>(a.env, gin, gout, in, out, n, blockDim.x, blockIdx.x, threadIdx.x, drop,
+                      (int32_t*)smem, smem + n, 0);
+}
+
+__global__ __launch_bounds__(1024) void k_labelprop4(hr_kargs a, hr_gref4 glab, hr_gref4 grp,
+                                                     hr_gref4 gcol, int32_t* __restrict__ label,
+                                                     const int32_t* __restrict__ rp,
+                                                     const int32_t* __restrict__ col,
+                                                     const uint8_t* __restrict__ mask, uint32_t n)
+{
+    labelprop_body<true, true>(a.env, glab, grp, gcol, label, rp, col, mask, n, blockDim.x,
+                               blockIdx.x, threadIdx.x);
 }
 
 // ----------------------------------------------------------- interpreter
@@ -134,8 +165,12 @@ extern "C" hr_status hr_reduce_check(hr_ctx c, uint32_t r_in, uint32_t r_out, co
         return HR_E_INVAL;
     hr_kargs a;
     hr_fill_args(c, &a);
-    HR_LAUNCH(k_reduce<true>, dim3(blocks), dim3(threads), (size_t)n * 8, hr_stream(c, stream), a,
-              gref(a, r_in), gref(a, r_out), in_dev, out_dev, n, drop);
+    if (a.env.word4)
+        HR_LAUNCH(k_reduce4, dim3(blocks), dim3(threads), (size_t)n * 8, hr_stream(c, stream), a,
+                  gref4(a, r_in), gref4(a, r_out), in_dev, out_dev, n, drop);
+    else
+        HR_LAUNCH(k_reduce<true>, dim3(blocks), dim3(threads), (size_t)n * 8, hr_stream(c, stream),
+                  a, gref(a, r_in), gref(a, r_out), in_dev, out_dev, n, drop);
     return HR_OK;
 }
 
@@ -167,8 +202,12 @@ extern "C" hr_status hr_jacobi_check(hr_ctx c, uint32_t r_old, uint32_t r_new,
     hr_kargs a;
     hr_fill_args(c, &a);
     const dim3 grid((nx + 15) / 16, (ny + 15) / 16);
-    HR_LAUNCH(k_jacobi<true>, grid, dim3(256), 0, hr_stream(c, stream), a, gref(a, r_old),
-              gref(a, r_new), u_old_dev, u_new_dev, ny, nx, seed_dev);
+    if (a.env.word4)
+        HR_LAUNCH(k_jacobi4, grid, dim3(256), 0, hr_stream(c, stream), a, gref4(a, r_old),
+                  gref4(a, r_new), u_old_dev, u_new_dev, ny, nx, seed_dev);
+    else
+        HR_LAUNCH(k_jacobi<true>, grid, dim3(256), 0, hr_stream(c, stream), a, gref(a, r_old),
+                  gref(a, r_new), u_old_dev, u_new_dev, ny, nx, seed_dev);
     return HR_OK;
 }
 
@@ -203,6 +242,14 @@ extern "C" hr_status hr_labelprop_check(hr_ctx c, uint32_t r_label, uint32_t r_r
     if (r_col != UINT32_MAX && !hr_region_ok(c, r_col, col_dev, 1)) return HR_E_INVAL;
     hr_kargs a;
     hr_fill_args(c, &a);
+    if (a.env.word4) {
+        const hr_gref4 none{nullptr, 0, 0};
+        HR_LAUNCH(k_labelprop4, dim3((n + tpb - 1) / tpb), dim3(tpb), 0, hr_stream(c, stream), a,
+                  gref4(a, r_label), r_row_ptr != UINT32_MAX ? gref4(a, r_row_ptr) : none,
+                  r_col != UINT32_MAX ? gref4(a, r_col) : none, label_dev, row_ptr_dev, col_dev,
+                  mask_dev, n);
+        return HR_OK;
+    }
     const hr_gref none{nullptr, 0, 0};
     HR_LAUNCH(k_labelprop<true>, dim3((n + tpb - 1) / tpb), dim3(tpb), 0, hr_stream(c, stream), a,
               gref(a, r_label), r_row_ptr != UINT32_MAX ? gref(a, r_row_ptr) : none,

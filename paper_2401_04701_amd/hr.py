@@ -27,6 +27,7 @@ HR_GLOBAL, HR_LDS = 0, 1
 HR_READ, HR_WRITE, HR_ATOMIC = 0, 1, 2
 HR_CFG_COUNT_CHECKS = 1
 HR_CFG_WAVE_GROUPING = 2
+HR_CFG_WORD4 = 4
 NO_REGION = 0xFFFFFFFF
 HR_PAT_REDUCE, HR_PAT_JACOBI, HR_PAT_LABELPROP = 0, 1, 2
 HR_SITES = 256
@@ -62,7 +63,8 @@ class _Config(ctypes.Structure):
     _fields_ = [("ring_capacity", ctypes.c_uint32), ("bc_bits", ctypes.c_uint32),
                 ("wc_bits", ctypes.c_uint32), ("flags", ctypes.c_uint32),
                 ("shadow_budget", ctypes.c_uint64), ("site_limit", ctypes.c_uint32),
-                ("wave_bits", ctypes.c_uint32)]
+                ("wave_bits", ctypes.c_uint32), ("thread_bits", ctypes.c_uint32),
+                ("pad", ctypes.c_uint32)]
 
 
 class Summary(ctypes.Structure):
@@ -134,6 +136,8 @@ def _load():
         "hr_fsm_step": [u32, u64, u32, u32, u32, u32, u32, u32, u32, P],
         "hr_fsm_merge": [u64, u64, u32, P],
         "hr_describe": [u32, u64, u32, P],
+        "hr_fsm_step_word4": [u32, u32, u32, u32, u32, u32, u32, u32, u32, u32, P],
+        "hr_word4_widen": [u32, u32, u32, u32, P],
         "hr_reduce_check": [P, u32, u32, P, P, u32, u32, u32, ctypes.c_int32, P],
         "hr_reduce_plain": [P, P, u32, u32, u32, ctypes.c_int32, P],
         "hr_jacobi_check": [P, u32, u32, P, P, u32, u32, P, P],
@@ -165,7 +169,7 @@ EXPORTED = ("hr_ctx_create", "hr_ctx_destroy", "hr_shadow_alloc", "hr_shadow_fre
             "hr_dev_args", "hr_batch_create", "hr_batch_run", "hr_batch_info",
             "hr_batch_destroy", "hr_job_run", "hr_serve",
             "hr_kernel_end", "hr_reset", "hr_report", "hr_check_count", "hr_fsm_step", "hr_fsm_merge",
-            "hr_describe",
+            "hr_describe", "hr_fsm_step_word4", "hr_word4_widen",
             "hr_reduce_check", "hr_reduce_plain", "hr_jacobi_check", "hr_jacobi_plain",
             "hr_labelprop_check", "hr_labelprop_plain", "hr_program_check",
             "hr_peak_copy", "hr_peak_atomic", "hr_peak_load", "hr_peak_lds")
@@ -210,6 +214,26 @@ def describe(space: int, word: int, wave_bits: int = 6) -> dict:
     out = Summary()
     _check("hr_describe", _lib.hr_describe(space, word, wave_bits, ctypes.byref(out)))
     return out.as_dict()
+
+
+def fsm_step_word4(old: int, kind: int, block: int, thread: int, bc: int, wc: int,
+                   wave_bits: int = 6, wc_bits: int = 0, bc_bits: int = 0,
+                   thread_bits: int = 0) -> int:
+    """Host evaluation of the device transition on a 4-byte global word with
+    the given field widths (0: the defaults 1, 2, 8)."""
+    out = ctypes.c_uint32(0)
+    _check("hr_fsm_step_word4", _lib.hr_fsm_step_word4(old, kind, block, thread, bc, wc,
+                                                       wave_bits, wc_bits, bc_bits, thread_bits,
+                                                       ctypes.byref(out)))
+    return int(out.value)
+
+
+def word4_widen(word: int, wc_bits: int = 0, bc_bits: int = 0, thread_bits: int = 0) -> int:
+    """The 8-byte word of the summary a 4-byte word holds (launch 0)."""
+    out = ctypes.c_uint64(0)
+    _check("hr_word4_widen", _lib.hr_word4_widen(word, wc_bits, bc_bits, thread_bits,
+                                                 ctypes.byref(out)))
+    return int(out.value)
 
 
 def fsm_merge(x: int, y: int, wave_bits: int = 6) -> int:
@@ -279,11 +303,13 @@ class Context:
     """A checking job: shadow regions, report ring, launch epochs."""
 
     def __init__(self, ring_capacity=0, bc_bits=0, wc_bits=0, count_checks=False,
-                 shadow_budget=0, wave_grouping=False, site_limit=0, wave_bits=0, stream=None):
+                 shadow_budget=0, wave_grouping=False, site_limit=0, wave_bits=0,
+                 word4=False, thread_bits=0, stream=None):
         flags = (HR_CFG_COUNT_CHECKS if count_checks else 0) | \
-                (HR_CFG_WAVE_GROUPING if wave_grouping else 0)
+                (HR_CFG_WAVE_GROUPING if wave_grouping else 0) | \
+                (HR_CFG_WORD4 if word4 else 0)
         cfg = _Config(ring_capacity, bc_bits, wc_bits, flags, shadow_budget, site_limit,
-                      wave_bits)
+                      wave_bits, thread_bits, 0)
         self.wave_bits = wave_bits or 6
         self._c = ctypes.c_void_p(0)
         self._stream = _stream_ptr(stream)

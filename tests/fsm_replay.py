@@ -69,9 +69,11 @@ def _one_launch_order(log, idx, rng, wave_width):
     return out
 
 
-def replay(log: np.ndarray, order, wave_bits: int = 6) -> set:
+def replay(log: np.ndarray, order, wave_bits: int = 6, word4=None) -> set:
     """Apply the transition function in `order`; return the keys that reached
-    the race state.  LDS shadow starts fresh for every block and launch."""
+    the race state.  LDS shadow starts fresh for every block and launch.
+    word4 = (wc_bits, bc_bits, thread_bits) replays global words as 4-byte
+    words of those widths, which start fresh at every launch."""
     words = {}
     racy = set()
     for i in order:
@@ -81,13 +83,22 @@ def replay(log: np.ndarray, order, wave_bits: int = 6) -> set:
         if sp == hr.HR_LDS:
             wkey = (1, rg, b, ix, L)
             key = (1, rg, b, ix)
+        elif word4 is not None:
+            wkey = (0, rg, 0, ix, L)
+            key = (0, rg, 0, ix)
         else:
             wkey = (0, rg, 0, ix)
             key = wkey
         old = words.get(wkey, 0)
-        new = hr.fsm_step(sp, old, int(r["kind"]), L & 511, b, t, int(r["bc"]), int(r["wc"]),
-                          wave_bits)
+        if sp == hr.HR_GLOBAL and word4 is not None:
+            new = hr.fsm_step_word4(old, int(r["kind"]), b, t, int(r["bc"]), int(r["wc"]),
+                                    wave_bits, *word4)
+            raced = new == hr.T_RACE
+        else:
+            new = hr.fsm_step(sp, old, int(r["kind"]), L & 511, b, t, int(r["bc"]),
+                              int(r["wc"]), wave_bits)
+            raced = (new & 7) == hr.T_RACE
         words[wkey] = new
-        if (new & 7) == hr.T_RACE:
+        if raced:
             racy.add(key)
     return racy

@@ -40,6 +40,11 @@ def test_unknown_config_flags_are_rejected():
     assert hr.lib().hr_ctx_create(ctypes.byref(c), ctypes.byref(cfg), None) == hr.HR_E_INVAL
     cfg = hr._Config(0, 9, 0, 0, 0)                  # block clock wider than 8 bits
     assert hr.lib().hr_ctx_create(ctypes.byref(c), ctypes.byref(cfg), None) == hr.HR_E_INVAL
+    # 4-byte words: a thread field above 10 bits
+    cfg = hr._Config(0, 0, 0, hr.HR_CFG_WORD4, 0, 0, 0, 11)
+    assert hr.lib().hr_ctx_create(ctypes.byref(c), ctypes.byref(cfg), None) == hr.HR_E_INVAL
+    cfg = hr._Config(0, 0, 0, 0, 0, 0, 0, 8)         # a thread width without 4-byte words
+    assert hr.lib().hr_ctx_create(ctypes.byref(c), ctypes.byref(cfg), None) == hr.HR_E_INVAL
     assert not c.value
 
 
