@@ -524,19 +524,26 @@ def main():
     ctx = hr.Context()
     regs = [ctx.shadow_alloc(u[0]), ctx.shadow_alloc(u[1])]
 
-    def checked_step(events):
-        ctx.reset()
+    def checked_step(events, c=ctx, rg=regs, end_events=None):
+        c.reset()
         for L in range(LAUNCHES):
             if events is not None:
                 e0 = torch.cuda.Event(enable_timing=True)
                 e1 = torch.cuda.Event(enable_timing=True)
                 e0.record(stream)
-            ctx.jacobi_check(regs[L % 2], regs[(L + 1) % 2], u[L % 2], u[(L + 1) % 2], tab)
+            c.jacobi_check(rg[L % 2], rg[(L + 1) % 2], u[L % 2], u[(L + 1) % 2], tab)
             if events is not None:
                 e1.record(stream)
                 events.append((e0, e1))
-            ctx.kernel_end()
-        recs, st = ctx.report()
+            if end_events is not None:
+                e2 = torch.cuda.Event(enable_timing=True)
+                e2.record(stream)
+            c.kernel_end()
+            if end_events is not None:
+                e3 = torch.cuda.Event(enable_timing=True)
+                e3.record(stream)
+                end_events.append((e2, e3))
+        recs, st = c.report()
         return recs, st
 
     def plain_step(events):
@@ -573,6 +580,34 @@ def main():
     tp1 = time.perf_counter()
     plain_ms = [a.elapsed_time(b) for a, b in pev]
     ctx.close()
+    ev.clear()                  # release the timing events before the next leg
+    pev.clear()
+
+    # The same job with 4-byte shadow words (default widths: 16-bit block
+    # field, exact for these 65,536 blocks); the launch-boundary clear of
+    # its shadow is timed on its own.
+    ctx4 = hr.Context(word4=True)
+    regs4 = [ctx4.shadow_alloc(u[0]), ctx4.shadow_alloc(u[1])]
+    for _ in range(args.warmup):
+        checked_step(None, ctx4, regs4)
+    torch.cuda.synchronize()
+    ev4, cev4 = [], []
+    t40 = time.perf_counter()
+    for _ in range(args.steps):
+        recs4, st4 = checked_step(ev4, ctx4, regs4)
+    torch.cuda.synchronize()
+    t41 = time.perf_counter()
+    for _ in range(2):                       # the clears, timed apart from the steps
+        checked_step(None, ctx4, regs4, cev4)
+    torch.cuda.synchronize()
+    ctx4.close()
+
+    def keys(rs):
+        return {(int(r["space"]), int(r["region"]), int(r["block"]) if r["space"] else 0,
+                 int(r["index"])) for r in rs}
+    assert st4 == 0 and keys(recs4) == keys(recs)
+    launch4_ms = [a.elapsed_time(b) for a, b in ev4]
+    clear4_ms = [a.elapsed_time(b) for a, b in cev4]
 
     avg_launch_s = float(np.mean(launch_ms)) * 1e-3
     alg = algorithmic_bytes_per_launch(NY, NX)
@@ -606,6 +641,13 @@ def main():
                      "kernel": "k_jacobi<true>", "alg_bytes_per_launch": alg,
                      "avg_launch_ms": avg_launch_s * 1e3},
     }
+    step4_s = (t41 - t40) / args.steps
+    result["word4"] = {"value": checks_per_step / step4_s, "unit": "checks/s",
+                       "ms_per_step": step4_s * 1e3,
+                       "p50_launch_ms": pct(launch4_ms, 50), "p99_launch_ms": pct(launch4_ms, 99),
+                       "p50_clear_ms": pct(clear4_ms, 50),
+                       "shadow_bytes": 2 * NY * NX * 4, "shadow_bytes_8byte": 2 * NY * NX * 8,
+                       "flagged": len(recs4), "same_flagged_set": True}
     if not args.no_peaks:
         peaks = measure_peaks(torch, hr, stream)
         g_rate = n_g / avg_launch_s

@@ -405,6 +405,12 @@ __device__ __forceinline__ uint64_t hr_id4(const hr_env& e, const hr_thread& t)
     return hr::c::pack_id(t.block, t.thread, t.bc, t.wc, e.word4);
 }
 
+// The same identity in the 32-bit layout, for the transition.
+__device__ __forceinline__ uint32_t hr_id32(const hr_env& e, const hr_thread& t)
+{
+    return hr::c::pack_id32(t.block, t.thread, t.bc, t.wc, e.word4);
+}
+
 __device__ __noinline__ uint32_t hr_fold4(uint32_t* sp, uint32_t mine, uint32_t lost, uint64_t wm,
                                           uint32_t lay)
 {
@@ -470,13 +476,15 @@ __device__ __forceinline__ void hr_check4(const hr_env& e, const hr_thread& t, u
         other = hr_group((uint64_t)sp >> 2, &member);
         if (member) return;
     }
+    const uint32_t wm4 = hr::c::group_mask(e.wave_bits, lay);
     const uint32_t old =
         PRE ? pre : __hip_atomic_load(sp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    uint32_t nw = hr::c::step(old, hr_id4(e, t), k, wm, lay);
+    uint32_t nw = hr::c::step(old, hr_id32(e, t), k, wm4, lay);
     uint64_t other_id = 0;
     if (other != HR_NO_LANE) {
-        other_id = hr::c::pack_id(t.block, t.thread - __lane_id() + other, t.bc, t.wc, lay);
-        nw = hr::c::step(nw, other_id, k, wm, lay);
+        const uint32_t ot = t.thread - __lane_id() + other;
+        other_id = hr::c::pack_id(t.block, ot, t.bc, t.wc, lay);
+        nw = hr::c::step(nw, hr::c::pack_id32(t.block, ot, t.bc, t.wc, lay), k, wm4, lay);
     }
     if (nw == old) return;
     const uint32_t r = __hip_atomic_exchange(sp, nw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -505,7 +513,7 @@ __device__ __forceinline__ hr_pend4 hr_check4_issue(const hr_env& e, const hr_th
     const uint32_t old =
         PRE ? pre : __hip_atomic_load(sp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const uint32_t nw =
-        hr::c::step(old, hr_id4(e, t), k, hr::g::group_mask(e.wave_bits), e.word4);
+        hr::c::step(old, hr_id32(e, t), k, hr::c::group_mask(e.wave_bits, e.word4), e.word4);
     if (nw == old) return p;
     p.sp = sp;
     p.old = old;

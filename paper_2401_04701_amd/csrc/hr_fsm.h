@@ -301,9 +301,63 @@ HR_HD uint64_t pack_id(uint32_t block, uint32_t thread, uint32_t bc, uint32_t wc
     return g::pack_id(0, block & block_mask(lay), thread & thread_mask(lay), bc, wc);
 }
 
-HR_HD uint32_t step(uint32_t old, uint64_t id, uint32_t k, uint64_t wm, uint32_t lay)
+// The same identity in the 32-bit layout (clocks within their fields).
+HR_HD uint32_t pack_id32(uint32_t block, uint32_t thread, uint32_t bc, uint32_t wc, uint32_t lay)
 {
-    return narrow(g::step(widen(old, lay), id, k, wm), lay);
+    return ((block & block_mask(lay)) << bl_sh(lay)) | ((thread & thread_mask(lay)) << th_sh(lay)) |
+           (bc << bc_sh(lay)) | (wc << WC_SH);
+}
+
+// Mask of the group (wave or tile) bits of the 32-bit thread field.
+HR_HD uint32_t group_mask(uint32_t s, uint32_t lay)
+{
+    return ((thread_mask(lay) >> s) << s) << th_sh(lay);
+}
+
+// State numbers of the multi-accessor and single-thread states (the classes
+// form a chain, as every reachable state's do).
+HR_HD uint32_t n_of(uint32_t base, uint32_t mul, uint32_t lo, uint32_t nx)
+{
+    return base + mul * (lo - 1u) + nx;
+}
+HR_HD uint32_t st_num(uint32_t cl, uint32_t cb, uint32_t cw)
+{
+    return cw == CL_X ? 20u : n_of(14u, 3u, cw, (cl == CL_X) + (cb == CL_X));
+}
+
+// One transition on the 32-bit word: the 64-bit machine's step (g::step)
+// written over the 32-bit fields, so that no word is widened on the hook's
+// path.  id = pack_id32 of the access; wm = group_mask(s, lay).  It equals
+// narrow(g::step(widen(old), pack_id(...), k, g::group_mask(s))).
+HR_HD uint32_t step(uint32_t old, uint32_t id, uint32_t k, uint32_t wm, uint32_t lay)
+{
+    const uint32_t idx = old & 31u;
+    if (idx == T_RACE) return old;
+    const uint32_t code = code_of(idx);
+    const uint32_t tag = code & 7u, cw = (code >> 3) & 3u, cb = (code >> 5) & 3u,
+                   cl = (code >> 7) & 3u;
+    const uint32_t bs = bc_sh(lay), ts = th_sh(lay), ls = bl_sh(lay);
+    const uint32_t wc_m = ((1u << (bs - WC_SH)) - 1u) << WC_SH;
+    const uint32_t bc_m = ((1u << (ts - bs)) - 1u) << bs;
+    const uint32_t th_m = ((1u << (ls - ts)) - 1u) << ts;
+    const uint32_t bl_m = block_mask(lay) << ls;
+    const uint32_t d = old ^ id;
+    const uint32_t race = T_RACE;
+    const uint32_t keep_t = bl_m | bc_m | th_m | wc_m;   // ST
+    const uint32_t keep_w = bl_m | bc_m | wm | wc_m;     // MT
+    const uint32_t keep_b = bl_m | bc_m;                 // MW
+    if (idx == 0) return st_num(k, k, k) | (id & keep_t);
+    if (tag == T_MB) return conflicts(cb, k) ? race : old;
+    if (d & bl_m) return conflicts(cl, k) ? race : 1u + k;                  // MB(k)
+    if (d & bc_m) return st_num(cl | k, k, k) | (id & keep_t);
+    if (tag == T_MW) return conflicts(cb, k) ? race : old;
+    if (d & wm) return conflicts(cb, k) ? race : (n_of(4u, 2u, k, cl == CL_X) | (id & keep_b));
+    if (d & wc_m) return st_num(cl | k, cb | k, k) | (id & keep_t);
+    if (tag == T_MT) return conflicts(cw, k) ? race : old;
+    if (d & (th_m & ~wm))
+        return conflicts(cw, k) ? race
+                                : (n_of(8u, 3u, k, (cl == CL_X) + (cb == CL_X)) | (id & keep_w));
+    return st_num(cl | k, cb | k, cw | k) | (id & keep_t);
 }
 
 HR_HD uint32_t merge(uint32_t x, uint32_t y, uint64_t wm, uint32_t lay)

@@ -486,8 +486,8 @@ extern "C" hr_status hr_fsm_step_word4(uint32_t old, uint32_t kind, uint32_t blo
         wc >= (1u << wc_bits) || (old & 31u) >= hr::c::N_STATES)
         return HR_E_INVAL;
     const uint32_t lay = hr::c::layout(wc_bits, bc_bits, thread_bits);
-    *new_out = hr::c::step(old, hr::c::pack_id(block, thread, bc, wc, lay), hr::kind_class(kind),
-                           hr::g::group_mask(wave_bits), lay);
+    *new_out = hr::c::step(old, hr::c::pack_id32(block, thread, bc, wc, lay),
+                           hr::kind_class(kind), hr::c::group_mask(wave_bits, lay), lay);
     return HR_OK;
 }
 
