@@ -25,14 +25,18 @@ def say(*a):
     print("[case]", *a, flush=True)
 
 
+@pytest.mark.parametrize("word4", [False, True])
 @pytest.mark.parametrize("drop", [-1, 0, 4, 7, 8])
-def test_instrumented_reduction(env, drop):
+def test_instrumented_reduction(env, drop, word4):
+    """Also with 4-byte global shadow words (block clock of 4 bits for the
+    reduction's 9 barriers): the generic hook dispatches on the context."""
     torch, hr, ex = env
     x = si.reduce_input(si.master_seed(0) + drop)
     inp = torch.from_numpy(x).cuda()
     out = torch.zeros(256, dtype=torch.int32, device="cuda")
-    say("instrumented reduction drop", drop)
-    with hr.Context() as ctx:
+    say("instrumented reduction drop", drop, "word4", word4)
+    kw = {"word4": True, "bc_bits": 4} if word4 else {}
+    with hr.Context(**kw) as ctx:
         r_in, r_out = ctx.shadow_alloc(inp), ctx.shadow_alloc(out)
         ex.launch("reduce_block", ctx, [r_in, r_out], (1,), (256,), inp, out, drop)
         ctx.kernel_end()
