@@ -33,7 +33,11 @@ FINGERPRINTED = ["hr_workloads.hip"]
 
 def _kernel_bodies(asm: str) -> dict:
     """Each kernel of a device assembly listing: its instructions and labels,
-    without comments, line records and directives."""
+    without comments, line records and directives.  Local labels lose the
+    function number the assembler gives them (.LBB<function>_<block>), which
+    changes when other functions are added to the module."""
+    import re
+    local = re.compile(r"\.LBB\d+_(\d+)")
     out, cur, lines = {}, None, []
     kernels = set()
     for ln in asm.splitlines():
@@ -53,7 +57,7 @@ def _kernel_bodies(asm: str) -> dict:
         t = t.strip()
         if not t or (t.startswith(".") and not t.endswith(":")):   # directives
             continue
-        lines.append(t)
+        lines.append(local.sub(r".LBB_\1", t))
     return out
 
 

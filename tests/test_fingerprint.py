@@ -29,8 +29,16 @@ helper:
 def test_parser_keeps_code_only():
     bodies = hb._kernel_bodies(LISTING)
     assert list(bodies) == ["k_a"]                       # helper is not a kernel
-    assert bodies["k_a"].splitlines() == ["s_load_dword s0, s[0:1], 0x0", ".LBB0_1:",
+    assert bodies["k_a"].splitlines() == ["s_load_dword s0, s[0:1], 0x0", ".LBB_1:",
                                           "v_add_u32_e32 v0, s0, v0", "s_endpgm"]
+
+
+def test_fingerprint_ignores_label_function_numbers():
+    """Adding a function before a kernel renumbers its local labels only."""
+    a = hb._kernel_bodies(LISTING)["k_a"]
+    b = hb._kernel_bodies(LISTING.replace(".LBB0_1", ".LBB7_1"))["k_a"]
+    c = hb._kernel_bodies(LISTING.replace(".LBB0_1", ".LBB0_2"))["k_a"]
+    assert a == b and a != c
 
 
 def test_fingerprint_ignores_comments_and_line_records():
