@@ -35,18 +35,19 @@ __device__ void jacobi_body(const hr_env& e, const G& gold, const G& gnew,
     }
     const size_t g = (size_t)gy * nx + gx;
     const uint32_t cl = (ty + 1) * TL + tx + 1;
+    // An edge thread stages at most one row halo cell (north or south) and
+    // one column halo cell (west or east).  The data loads are issued first,
+    // so that they are in flight together with the first hook's shadow load.
+    const bool hn = inside && ty == 0 && gy > 0, hs = inside && ty == 15 && gy + 1 < ny;
+    const bool hw = inside && tx == 0 && gx > 0, he = inside && tx == 15 && gx + 1 < nx;
+    const size_t gr = hn ? g - nx : g + nx, gc = hw ? g - 1 : g + 1;
+    const uint32_t lr = hn ? tx + 1 : 17 * TL + tx + 1;
+    const uint32_t lc = hw ? (ty + 1) * TL : (ty + 1) * TL + 17;
+    float vr = 0.0f, vk = 0.0f;
     if (inside) {
-        // An edge thread stages at most one row halo cell (north or south)
-        // and one column halo cell (west or east); each pair shares one hook
-        // site, so a wave issues two halo hooks instead of four.  The data
-        // loads are issued first, so that they are in flight together with
-        // the first hook's shadow load.
-        const bool hn = ty == 0 && gy > 0, hs = ty == 15 && gy + 1 < ny;
-        const bool hw = tx == 0 && gx > 0, he = tx == 15 && gx + 1 < nx;
-        const size_t gr = hn ? g - nx : g + nx, gc = hw ? g - 1 : g + 1;
         const float vc = uo[g];
-        const float vr = hn || hs ? uo[gr] : 0.0f;
-        const float vk = hw || he ? uo[gc] : 0.0f;
+        vr = hn || hs ? uo[gr] : 0.0f;
+        vk = hw || he ? uo[gc] : 0.0f;
         // Each global hook is settled after the LDS hook of the staging
         // store that follows it, so the LDS hook runs while the exchange is
         // in flight.  (The staging hook comes before its store: the store
@@ -56,19 +57,46 @@ __device__ void jacobi_body(const hr_env& e, const G& gold, const G& gnew,
         hr_l<1, CHECK>(e, th, tsh, TW, lds_id, cl, HR_SITE_JACOBI_STAGE);
         tile[cl] = vc;
         hr_gs<0, CHECK>(e, th, gold, pc, g, HR_SITE_JACOBI_CENTRE);
-        if (hn || hs) {
-            const uint32_t lr = hn ? tx + 1 : 17 * TL + tx + 1;
-            const typename G::pend pr = hr_gi<0, CHECK>(e, th, gold, gr);
-            hr_l<1, CHECK>(e, th, tsh, TW, lds_id, lr, HR_SITE_JACOBI_STAGE);
-            tile[lr] = vr;
-            hr_gs<0, CHECK>(e, th, gold, pr, gr, HR_SITE_JACOBI_HALO);
+    }
+    if constexpr (!CHECK) {
+        if (hn || hs) tile[lr] = vr;
+        if (hw || he) tile[lc] = vk;
+    } else {
+        // The halo reads are checked in one hook section, one check per
+        // lane: a wave's divergent sections run one after another, so a
+        // lane with two halo checks would add a section for the whole
+        // wave.  A lane checks its row halo read, else its column halo read.
+        // The column halo read of a corner lane that also has a row halo is
+        // checked by a proxy lane with no halo of its own: lane (1,1) for
+        // corner (0,0), (1,14) for (0,15), (14,1) for (15,0) and (14,14) for
+        // (15,15).  It is the same access, checked with the corner thread's
+        // identity before the same barrier; the proxy need not own a cell.
+        bool on = hn || hs || hw || he;
+        size_t ha = hn || hs ? gr : gc;
+        hr_thread hth = th;
+        if (t < 256 && (ty == 1 || ty == 14) && (tx == 1 || tx == 14)) {
+            const uint32_t cy = ty == 1 ? 0u : 15u, cx = tx == 1 ? 0u : 15u;
+            const uint32_t cgx = bx * 16u + cx, cgy = by * 16u + cy;
+            const bool row = (cy == 0 && cgy > 0) || (cy == 15 && cgy + 1 < ny);
+            const bool cw = cx == 0 && cgx > 0, ce = cx == 15 && cgx + 1 < nx;
+            if (cgx < nx && cgy < ny && row && (cw || ce)) {
+                const size_t cg = (size_t)cgy * nx + cgx;
+                on = true;
+                ha = cw ? cg - 1 : cg + 1;
+                hth = hr_thread_make(e, lb, cy * 16u + cx);
+            }
         }
-        if (hw || he) {
-            const uint32_t lc = hw ? (ty + 1) * TL : (ty + 1) * TL + 17;
-            const typename G::pend pk = hr_gi<0, CHECK>(e, th, gold, gc);
-            hr_l<1, CHECK>(e, th, tsh, TW, lds_id, lc, HR_SITE_JACOBI_STAGE);
-            tile[lc] = vk;
-            hr_gs<0, CHECK>(e, th, gold, pk, gc, HR_SITE_JACOBI_HALO);
+        if (on) {
+            const typename G::pend ph = hr_gi<0, CHECK>(e, hth, gold, ha);
+            if (hn || hs) {
+                hr_l<1, CHECK>(e, th, tsh, TW, lds_id, lr, HR_SITE_JACOBI_STAGE);
+                tile[lr] = vr;
+            }
+            if (hw || he) {
+                hr_l<1, CHECK>(e, th, tsh, TW, lds_id, lc, HR_SITE_JACOBI_STAGE);
+                tile[lc] = vk;
+            }
+            hr_gs<0, CHECK>(e, hth, gold, ph, ha, HR_SITE_JACOBI_HALO);
         }
     }
     hr_bar<CHECK>(e, th);

@@ -86,6 +86,32 @@ def test_word4_program(env, cfg):
     assert st == 0 and got == want
 
 
+@pytest.mark.parametrize("cfg", [(31, 2, 2, 4, 64, 4, 2, 64, 32), (34, 32, 2, 6, 1024, 4, 1, 1024, 512),
+                                 (35, 4, 2, 5, 128, 6, 3, 16, 8)],
+                         ids=lambda c: f"seed{c[0]}_tile{c[1]}")
+def test_word4_tile_programs(env, cfg):
+    """Tiles of 2^s lanes as the synchronization groups, on 4-byte words."""
+    torch, hr = env
+    seed, tile, launches, blocks, threads, phases, max_ops, gw, lw = cfg
+    prog = si.random_program(seed, launches=launches, blocks=blocks, threads=threads,
+                             phases=phases, max_ops=max_ops, global_regions=2, global_words=gw,
+                             lds_words=lw, p_lds=0.4, scope_p=(0.2, 0.6, 0.2), wave_width=tile)
+    want = oracle.flagged_program(prog, tile)
+    say("word4 tile program", cfg, "oracle flags", len(want))
+    got, st = run_program(torch, hr, prog, dict(PROG_W4, wave_bits=tile.bit_length() - 1))
+    assert st == 0 and got == want
+
+
+def test_word4_switched_off_threads(env):
+    torch, hr = env
+    prog = si.random_program(42, launches=2, blocks=6, threads=256, phases=4, max_ops=3,
+                             global_regions=2, global_words=128, lds_words=64, p_switch=0.3)
+    want = oracle.flagged_program(prog)
+    say("word4 switch ops, oracle flags", len(want))
+    got, st = run_program(torch, hr, prog, PROG_W4)
+    assert st == 0 and got == want
+
+
 def test_word4_ring_overflow_recovers_global_set(env):
     """A one-record ring over two launches: the launch-boundary clear keeps
     the race words, so the report's scan still finds every global race."""

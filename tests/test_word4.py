@@ -10,7 +10,7 @@ import oracle
 import synth_inputs as si
 from fsm_replay import random_orders, replay
 from paper_2401_04701_amd import hr
-from test_fsm import SETTINGS, widen
+from test_fsm import SETTINGS, TILE_SETTINGS, widen
 
 G = hr.HR_GLOBAL
 # wave clock, block clock and thread widths; the block field gets 27 - 15 = 12 bits
@@ -36,6 +36,27 @@ def test_word4_flags_oracle_set_in_every_order(setting):
         wide = widen(log, ww)
         for order in random_orders(wide, 8, seed=s):
             assert replay(wide, order, word4=WIDTHS) == want, (setting, s)
+        racy += len(want)
+    assert racy > 0
+
+
+@pytest.mark.parametrize("setting", TILE_SETTINGS)
+def test_word4_with_tiles_flags_oracle_set_in_every_order(setting):
+    """Tiles of 2^s lanes as the synchronization groups: the group bits are
+    the thread field's bits from s up."""
+    blocks, threads, tw, phases, max_ops, gw, lw, launches = setting
+    wb = tw.bit_length() - 1
+    racy = 0
+    for s in range(20):
+        prog = si.random_program(6151 * s + tw * 7 + threads, launches=launches,
+                                 blocks=blocks, threads=threads, phases=phases,
+                                 max_ops=max_ops, global_regions=2, global_words=gw,
+                                 lds_words=lw, kind_p=(0.5, 0.25, 0.25),
+                                 scope_p=(0.2, 0.55, 0.25), wave_width=tw)
+        log = oracle.model_program(prog, tw)
+        want = oracle.flagged(log.copy(), tw)
+        for order in random_orders(log, 6, seed=s, wave_width=tw):
+            assert replay(log, order, wb, word4=WIDTHS) == want, (setting, s)
         racy += len(want)
     assert racy > 0
 
