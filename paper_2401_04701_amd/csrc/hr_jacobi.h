@@ -160,7 +160,7 @@ __global__ __launch_bounds__(256, 8) void k_jacobi(hr_kargs a, hr_gref gold, hr_
 }
 
 // The checked sweep on 4-byte shadow words.
-__global__ __launch_bounds__(256, 8) void k_jacobi4(hr_kargs a, hr_gref4 gold, hr_gref4 gnew,
+__global__ __launch_bounds__(256, 7) void k_jacobi4(hr_kargs a, hr_gref4 gold, hr_gref4 gnew,
                                                  const float* __restrict__ uo,
                                                  float* __restrict__ un, uint32_t ny, uint32_t nx,
                                                  const int32_t* __restrict__ seeds)
