@@ -67,11 +67,11 @@ __device__ void reduce_body(const hr_env& e, const G& gin, const G& gout,
         const uint32_t h = n >> (step + 1);
         if (act && t < h) {
             const int32_t x = s[t];
-            hr_l<0, CHECK>(e, th, sh, n, lds_id, t, HR_SITE_REDUCE_LEFT);
             const int32_t y = s[t + h];
-            hr_l<0, CHECK>(e, th, sh, n, lds_id, t + h, HR_SITE_REDUCE_RIGHT);
             s[t] = x + y;
-            hr_l<1, CHECK>(e, th, sh, n, lds_id, t, HR_SITE_REDUCE_SUM);
+            if constexpr (CHECK)
+                hr_lds_rrw(e, th, sh, n, lds_id, t, t + h, HR_SITE_REDUCE_LEFT,
+                           HR_SITE_REDUCE_RIGHT, HR_SITE_REDUCE_SUM);
         }
         if (step != drop) hr_bar<CHECK>(e, th);
     }

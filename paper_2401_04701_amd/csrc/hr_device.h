@@ -588,6 +588,64 @@ __device__ __forceinline__ void hr_access_lds(const hr_env& e, const hr_thread& 
     }
 }
 
+// The LDS hooks of one reduction step of a thread: a read of word a, a read
+// of word b, then a write of word a, with no other access of the thread in
+// between.  The read and the write of word a are applied in one update (the
+// order in which nothing lands between them), and the two words' loads and
+// compare-and-swaps are in flight together, so that the step costs two LDS
+// round trips instead of six.  Sites: read a, read b, write a.
+__device__ __forceinline__ void hr_lds_rrw(const hr_env& e, const hr_thread& t, uint32_t* sh,
+                                           uint32_t n_words, uint32_t array_id, uint32_t a,
+                                           uint32_t b, uint32_t site_ra, uint32_t site_rb,
+                                           uint32_t site_wa)
+{
+    if (t.enabled != 1) return;
+    hr_count(e, t);
+    hr_count(e, t);
+    hr_count(e, t);
+    if (a >= n_words || b >= n_words) {
+        hr_set_flag(e, HR_DEVF_RANGE);
+        return;
+    }
+    const uint32_t wm = hr::l::group_mask(e.wave_bits);
+    const uint32_t rid = hr::l::step(hr::T_INIT, t.lid, hr::CL_R), wid = hr::l::step(hr::T_INIT, t.lid, hr::CL_X);
+    uint32_t* pa = sh + a;
+    uint32_t* pb = sh + b;
+    uint32_t oa = __hip_atomic_load(pa, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    uint32_t ob = __hip_atomic_load(pb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    bool da = false, db = false;
+    while (!(da && db)) {
+        const uint32_t ma = hr::l::step(oa, t.lid, hr::CL_R, wm);     // word a after the read
+        const uint32_t na = hr::l::step(ma, t.lid, hr::CL_X, wm);     // and after the write
+        const uint32_t nb = hr::l::step(ob, t.lid, hr::CL_R, wm);
+        if (!da && na == oa) da = true;
+        if (!db && nb == ob) db = true;
+        uint32_t sa = oa, sb = ob;
+        const bool ga = !da && __hip_atomic_compare_exchange_strong(
+                                   pa, &sa, na, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+        const bool gb = !db && __hip_atomic_compare_exchange_strong(
+                                   pb, &sb, nb, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (ga) {
+            da = true;
+            if (ma == hr::T_RACE)
+                hr_ring_push(e, 1, array_id, t.block, a, t.thread, 0, site_ra, oa, rid, 0);
+            else if (na == hr::T_RACE)
+                hr_ring_push(e, 1, array_id, t.block, a, t.thread, 1, site_wa, ma, wid, 0);
+        } else if (!da) {
+            oa = sa;
+        }
+        if (gb) {
+            db = true;
+            if (nb == hr::T_RACE)
+                hr_ring_push(e, 1, array_id, t.block, b, t.thread, 0, site_rb, ob, rid, 0);
+        } else if (!db) {
+            ob = sb;
+        }
+    }
+}
+
 // Runtime-kind forms (used where the kind is data, as in the interpreter).
 __device__ __forceinline__ void hr_check_k(const hr_env& e, const hr_thread& t, uint32_t kind,
                                            uint64_t* shadow, uint64_t n, uint32_t region,
