@@ -15,7 +15,11 @@ constexpr uint32_t JACOBI_TILE_WORDS = JACOBI_TILE * JACOBI_TILE;
 // sweep u_new = 0.2 (c + n + s + w + e), staged through an 18x18 LDS tile.
 // seeds: NULL or per-block (side << 8 | offset) entries (-1: none); a seeded
 // block's edge thread also writes the neighbour-owned halo cell.
-template <bool CHECK, class G = hr_gref>
+// ONE_HALO: the halo reads are checked in one hook section per wave (the
+// standalone kernels); without it, in two (the batch and serving workers,
+// which inline every workload body under one register budget: the proxy
+// lanes' second identity would spill there).
+template <bool CHECK, class G = hr_gref, bool ONE_HALO = false>
 __device__ void jacobi_body(const hr_env& e, const G& gold, const G& gnew,
                             const float* __restrict__ uo, float* __restrict__ un, uint32_t ny,
                             uint32_t nx, uint32_t nbx, const int32_t* __restrict__ seeds,
@@ -41,8 +45,10 @@ __device__ void jacobi_body(const hr_env& e, const G& gold, const G& gnew,
     const bool hn = inside && ty == 0 && gy > 0, hs = inside && ty == 15 && gy + 1 < ny;
     const bool hw = inside && tx == 0 && gx > 0, he = inside && tx == 15 && gx + 1 < nx;
     const size_t gr = hn ? g - nx : g + nx, gc = hw ? g - 1 : g + 1;
-    const uint32_t lr = hn ? tx + 1 : 17 * TL + tx + 1;
-    const uint32_t lc = hw ? (ty + 1) * TL : (ty + 1) * TL + 17;
+    // LDS words of the row and column halo cells, computed where they are used
+    const auto lrow = [&] { return hn ? tx + 1 : 17 * TL + tx + 1; };
+    const auto lcol = [&] { return hw ? (ty + 1) * TL : (ty + 1) * TL + 17; };
+    const uint32_t lr = ONE_HALO ? lrow() : 0u, lc = ONE_HALO ? lcol() : 0u;
     float vr = 0.0f, vk = 0.0f;
     if (inside) {
         const float vc = uo[g];
@@ -59,8 +65,23 @@ __device__ void jacobi_body(const hr_env& e, const G& gold, const G& gnew,
         hr_gs<0, CHECK>(e, th, gold, pc, g, HR_SITE_JACOBI_CENTRE);
     }
     if constexpr (!CHECK) {
-        if (hn || hs) tile[lr] = vr;
-        if (hw || he) tile[lc] = vk;
+        if (hn || hs) tile[ONE_HALO ? lr : lrow()] = vr;
+        if (hw || he) tile[ONE_HALO ? lc : lcol()] = vk;
+    } else if constexpr (!ONE_HALO) {
+        if (hn || hs) {
+            const uint32_t lr = lrow();
+            const typename G::pend pr = hr_gi<0, CHECK>(e, th, gold, gr);
+            hr_l<1, CHECK>(e, th, tsh, TW, lds_id, lr, HR_SITE_JACOBI_STAGE);
+            tile[lr] = vr;
+            hr_gs<0, CHECK>(e, th, gold, pr, gr, HR_SITE_JACOBI_HALO);
+        }
+        if (hw || he) {
+            const uint32_t lc = lcol();
+            const typename G::pend pk = hr_gi<0, CHECK>(e, th, gold, gc);
+            hr_l<1, CHECK>(e, th, tsh, TW, lds_id, lc, HR_SITE_JACOBI_STAGE);
+            tile[lc] = vk;
+            hr_gs<0, CHECK>(e, th, gold, pk, gc, HR_SITE_JACOBI_HALO);
+        }
     } else {
         // The halo reads are checked in one hook section, one check per
         // lane: a wave's divergent sections run one after another, so a
@@ -155,8 +176,9 @@ __global__ __launch_bounds__(256, 8) void k_jacobi(hr_kargs a, hr_gref gold, hr_
 {
     __shared__ float tile[JACOBI_TILE_WORDS];
     __shared__ uint32_t tsh[CHECK ? JACOBI_TILE_WORDS : 1];
-    jacobi_body<CHECK>(a.env, gold, gnew, uo, un, ny, nx, gridDim.x, seeds,
-                       blockIdx.y * gridDim.x + blockIdx.x, threadIdx.x, tile, tsh, 0);
+    jacobi_body<CHECK, hr_gref, true>(a.env, gold, gnew, uo, un, ny, nx, gridDim.x, seeds,
+                                      blockIdx.y * gridDim.x + blockIdx.x, threadIdx.x, tile,
+                                      tsh, 0);
 }
 
 // The checked sweep on 4-byte shadow words.
@@ -167,8 +189,9 @@ __global__ __launch_bounds__(256, 7) void k_jacobi4(hr_kargs a, hr_gref4 gold, h
 {
     __shared__ float tile[JACOBI_TILE_WORDS];
     __shared__ uint32_t tsh[JACOBI_TILE_WORDS];
-    jacobi_body<true>(a.env, gold, gnew, uo, un, ny, nx, gridDim.x, seeds,
-                      blockIdx.y * gridDim.x + blockIdx.x, threadIdx.x, tile, tsh, 0);
+    jacobi_body<true, hr_gref4, true>(a.env, gold, gnew, uo, un, ny, nx, gridDim.x, seeds,
+                                      blockIdx.y * gridDim.x + blockIdx.x, threadIdx.x, tile,
+                                      tsh, 0);
 }
 
 }  // namespace
