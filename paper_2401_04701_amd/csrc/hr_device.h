@@ -405,11 +405,6 @@ __device__ __forceinline__ uint64_t hr_id4(const hr_env& e, const hr_thread& t)
     return hr::c::pack_id(t.block, t.thread, t.bc, t.wc, e.word4);
 }
 
-// The same identity in the 32-bit layout, for the transition.
-__device__ __forceinline__ uint32_t hr_id32(const hr_env& e, const hr_thread& t)
-{
-    return hr::c::pack_id32(t.block, t.thread, t.bc, t.wc, e.word4);
-}
 
 __device__ __noinline__ uint32_t hr_fold4(uint32_t* sp, uint32_t mine, uint32_t lost, uint64_t wm,
                                           uint32_t lay)
@@ -455,7 +450,8 @@ __device__ __forceinline__ void hr_settle4(const hr_env& e, const hr_thread& t, 
     }
 }
 
-template <int KIND, bool GROUP = false, bool PRE = false>
+// LAY: the word layout as a compile-time constant (0: the context's, e.word4).
+template <int KIND, bool GROUP = false, bool PRE = false, uint32_t LAY = 0>
 __device__ __forceinline__ void hr_check4(const hr_env& e, const hr_thread& t, uint32_t* shadow,
                                           uint64_t n, uint32_t region, uint64_t index,
                                           uint32_t site = 0, uint32_t pre = 0)
@@ -468,7 +464,7 @@ __device__ __forceinline__ void hr_check4(const hr_env& e, const hr_thread& t, u
     }
     constexpr uint32_t k = KIND == 0 ? hr::CL_R : (KIND == 2 ? hr::CL_A : hr::CL_X);
     uint32_t* sp = shadow + index;
-    const uint32_t lay = e.word4;
+    const uint32_t lay = LAY ? LAY : e.word4;
     const uint64_t wm = hr::g::group_mask(e.wave_bits);
     uint32_t other = HR_NO_LANE;
     if (GROUP && e.group && e.wave_bits == 6) {
@@ -479,7 +475,7 @@ __device__ __forceinline__ void hr_check4(const hr_env& e, const hr_thread& t, u
     const uint32_t wm4 = hr::c::group_mask(e.wave_bits, lay);
     const uint32_t old =
         PRE ? pre : __hip_atomic_load(sp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    uint32_t nw = hr::c::step(old, hr_id32(e, t), k, wm4, lay);
+    uint32_t nw = hr::c::step(old, hr::c::pack_id32(t.block, t.thread, t.bc, t.wc, lay), k, wm4, lay);
     uint64_t other_id = 0;
     if (other != HR_NO_LANE) {
         const uint32_t ot = t.thread - __lane_id() + other;
@@ -496,7 +492,7 @@ struct hr_pend4 {
     uint32_t old, nw, r;
 };
 
-template <int KIND, bool PRE = false>
+template <int KIND, bool PRE = false, uint32_t LAY = 0>
 __device__ __forceinline__ hr_pend4 hr_check4_issue(const hr_env& e, const hr_thread& t,
                                                     uint32_t* shadow, uint64_t n, uint64_t index,
                                                     uint32_t pre = 0)
@@ -512,8 +508,9 @@ __device__ __forceinline__ hr_pend4 hr_check4_issue(const hr_env& e, const hr_th
     uint32_t* sp = shadow + index;
     const uint32_t old =
         PRE ? pre : __hip_atomic_load(sp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const uint32_t nw =
-        hr::c::step(old, hr_id32(e, t), k, hr::c::group_mask(e.wave_bits, e.word4), e.word4);
+    const uint32_t lay = LAY ? LAY : e.word4;
+    const uint32_t nw = hr::c::step(old, hr::c::pack_id32(t.block, t.thread, t.bc, t.wc, lay), k,
+                                    hr::c::group_mask(e.wave_bits, lay), lay);
     if (nw == old) return p;
     p.sp = sp;
     p.old = old;

@@ -211,11 +211,14 @@ HR_HD uint64_t merge(uint64_t x, uint64_t y, uint64_t wm = WAVE_M)
 namespace c {
 constexpr uint32_t STATE_BITS = 5, WC_SH = 5, N_STATES = 21;
 
-HR_HD uint32_t layout(uint32_t wc_bits, uint32_t bc_bits, uint32_t thread_bits)
+constexpr uint32_t layout(uint32_t wc_bits, uint32_t bc_bits, uint32_t thread_bits)
 {
-    const uint32_t bc_sh = WC_SH + wc_bits, th_sh = bc_sh + bc_bits, bl_sh = th_sh + thread_bits;
-    return bc_sh | (th_sh << 8) | (bl_sh << 16);
+    return (WC_SH + wc_bits) | ((WC_SH + wc_bits + bc_bits) << 8) |
+           ((WC_SH + wc_bits + bc_bits + thread_bits) << 16);
 }
+// The default widths (wave clock 1, block clock 2, thread 8: a 16-bit block
+// field), for which kernels can be compiled with the layout as a constant.
+constexpr uint32_t DEFAULT_LAYOUT = layout(1, 2, 8);
 HR_HD uint32_t bc_sh(uint32_t lay) { return lay & 255u; }
 HR_HD uint32_t th_sh(uint32_t lay) { return (lay >> 8) & 255u; }
 HR_HD uint32_t bl_sh(uint32_t lay) { return (lay >> 16) & 255u; }

@@ -18,13 +18,16 @@ struct hr_gref {
     using pend = hr_pend;
 };
 
-struct hr_gref4 {
+// LAY: the 4-byte word layout as a compile-time constant (0: the context's).
+template <uint32_t LAY>
+struct hr_gref4t {
     uint32_t* shadow;
     uint64_t n;
     uint32_t id;
     using word = uint32_t;
     using pend = hr_pend4;
 };
+using hr_gref4 = hr_gref4t<0>;
 
 // Global hook at a lane-affine site (GROUP false) or a data-dependent one.
 template <int KIND, bool CHECK, bool GROUP = false>
@@ -81,37 +84,41 @@ __device__ __forceinline__ void hr_bar(const hr_env& e, hr_thread& t)
 }
 
 // The global hooks on 4-byte words.
-template <int KIND, bool CHECK, bool GROUP = false>
-__device__ __forceinline__ void hr_g(const hr_env& e, const hr_thread& t, const hr_gref4& g,
+template <int KIND, bool CHECK, bool GROUP = false, uint32_t LAY = 0>
+__device__ __forceinline__ void hr_g(const hr_env& e, const hr_thread& t, const hr_gref4t<LAY>& g,
                                      uint64_t index, uint32_t site)
 {
-    if constexpr (CHECK) hr_check4<KIND, GROUP>(e, t, g.shadow, g.n, g.id, index, site);
+    if constexpr (CHECK) hr_check4<KIND, GROUP, false, LAY>(e, t, g.shadow, g.n, g.id, index, site);
 }
 
-template <bool CHECK>
-__device__ __forceinline__ uint32_t hr_gload(const hr_thread& t, const hr_gref4& g, uint64_t index)
+template <bool CHECK, uint32_t LAY = 0>
+__device__ __forceinline__ uint32_t hr_gload(const hr_thread& t, const hr_gref4t<LAY>& g,
+                                             uint64_t index)
 {
     if constexpr (CHECK) return hr_check4_load(t, g.shadow, g.n, index);
     return 0;
 }
 
-template <int KIND, bool CHECK, bool GROUP = true>
-__device__ __forceinline__ void hr_gpre(const hr_env& e, const hr_thread& t, const hr_gref4& g,
-                                        uint64_t index, uint32_t site, uint32_t pre)
+template <int KIND, bool CHECK, bool GROUP = true, uint32_t LAY = 0>
+__device__ __forceinline__ void hr_gpre(const hr_env& e, const hr_thread& t,
+                                        const hr_gref4t<LAY>& g, uint64_t index, uint32_t site,
+                                        uint32_t pre)
 {
-    if constexpr (CHECK) hr_check4<KIND, GROUP, true>(e, t, g.shadow, g.n, g.id, index, site, pre);
+    if constexpr (CHECK)
+        hr_check4<KIND, GROUP, true, LAY>(e, t, g.shadow, g.n, g.id, index, site, pre);
 }
 
-template <int KIND, bool CHECK, bool PRE = false>
-__device__ __forceinline__ hr_pend4 hr_gi(const hr_env& e, const hr_thread& t, const hr_gref4& g,
-                                          uint64_t index, uint32_t pre = 0)
+template <int KIND, bool CHECK, bool PRE = false, uint32_t LAY = 0>
+__device__ __forceinline__ hr_pend4 hr_gi(const hr_env& e, const hr_thread& t,
+                                          const hr_gref4t<LAY>& g, uint64_t index,
+                                          uint32_t pre = 0)
 {
-    if constexpr (CHECK) return hr_check4_issue<KIND, PRE>(e, t, g.shadow, g.n, index, pre);
+    if constexpr (CHECK) return hr_check4_issue<KIND, PRE, LAY>(e, t, g.shadow, g.n, index, pre);
     return hr_pend4{nullptr, 0, 0, 0};
 }
 
-template <int KIND, bool CHECK>
-__device__ __forceinline__ void hr_gs(const hr_env& e, const hr_thread& t, const hr_gref4& g,
+template <int KIND, bool CHECK, uint32_t LAY = 0>
+__device__ __forceinline__ void hr_gs(const hr_env& e, const hr_thread& t, const hr_gref4t<LAY>& g,
                                       const hr_pend4& p, uint64_t index, uint32_t site)
 {
     if constexpr (CHECK) hr_check4_settle<KIND>(e, t, p, g.id, index, site);

@@ -181,17 +181,21 @@ __global__ __launch_bounds__(256, 8) void k_jacobi(hr_kargs a, hr_gref gold, hr_
                                       tsh, 0);
 }
 
-// The checked sweep on 4-byte shadow words.
-__global__ __launch_bounds__(256, 7) void k_jacobi4(hr_kargs a, hr_gref4 gold, hr_gref4 gnew,
+// The checked sweep on 4-byte shadow words, with the word layout as a
+// constant (LAY) or the context's (LAY = 0).  7 waves per SIMD: the 4-byte
+// hook needs a few more registers than the 8-byte one.
+template <uint32_t LAY>
+__global__ __launch_bounds__(256, 7) void k_jacobi4(hr_kargs a, hr_gref4t<LAY> gold,
+                                                 hr_gref4t<LAY> gnew,
                                                  const float* __restrict__ uo,
                                                  float* __restrict__ un, uint32_t ny, uint32_t nx,
                                                  const int32_t* __restrict__ seeds)
 {
     __shared__ float tile[JACOBI_TILE_WORDS];
     __shared__ uint32_t tsh[JACOBI_TILE_WORDS];
-    jacobi_body<true, hr_gref4, true>(a.env, gold, gnew, uo, un, ny, nx, gridDim.x, seeds,
-                                      blockIdx.y * gridDim.x + blockIdx.x, threadIdx.x, tile,
-                                      tsh, 0);
+    jacobi_body<true, hr_gref4t<LAY>, true>(a.env, gold, gnew, uo, un, ny, nx, gridDim.x, seeds,
+                                            blockIdx.y * gridDim.x + blockIdx.x, threadIdx.x,
+                                            tile, tsh, 0);
 }
 
 }  // namespace

@@ -21,9 +21,10 @@ hr_gref gref(const hr_kargs& a, uint32_t r)
     return g;
 }
 
-hr_gref4 gref4(const hr_kargs& a, uint32_t r)
+template <uint32_t LAY = 0>
+hr_gref4t<LAY> gref4(const hr_kargs& a, uint32_t r)
 {
-    hr_gref4 g{nullptr, 0, r};
+    hr_gref4t<LAY> g{nullptr, 0, r};
     if (r < HR_MAX_REGIONS) {
         g.shadow = (uint32_t*)a.shadow[r];
         g.n = a.n_elems[r];
@@ -202,8 +203,12 @@ extern "C" hr_status hr_jacobi_check(hr_ctx c, uint32_t r_old, uint32_t r_new,
     hr_kargs a;
     hr_fill_args(c, &a);
     const dim3 grid((nx + 15) / 16, (ny + 15) / 16);
-    if (a.env.word4)
-        HR_LAUNCH(k_jacobi4, grid, dim3(256), 0, hr_stream(c, stream), a, gref4(a, r_old),
+    constexpr uint32_t DL = hr::c::DEFAULT_LAYOUT;
+    if (a.env.word4 == DL)
+        HR_LAUNCH(k_jacobi4<DL>, grid, dim3(256), 0, hr_stream(c, stream), a, gref4<DL>(a, r_old),
+                  gref4<DL>(a, r_new), u_old_dev, u_new_dev, ny, nx, seed_dev);
+    else if (a.env.word4)
+        HR_LAUNCH(k_jacobi4<0>, grid, dim3(256), 0, hr_stream(c, stream), a, gref4(a, r_old),
                   gref4(a, r_new), u_old_dev, u_new_dev, ny, nx, seed_dev);
     else
         HR_LAUNCH(k_jacobi<true>, grid, dim3(256), 0, hr_stream(c, stream), a, gref(a, r_old),
