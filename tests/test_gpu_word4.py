@@ -158,6 +158,22 @@ def test_word4_jacobi(env, ny, nx, launches, count):
     assert got == oracle.flagged(log) == cf.jacobi_flagged(ny, nx, launches, seeds)
 
 
+def test_word4_jacobi_layout_kernels_agree(env):
+    """The default widths run the stencil compiled with the word layout as a
+    constant; other widths that still fit run the kernel reading the layout
+    from the context.  Both give the closed form's set."""
+    torch, hr = env
+    ny, nx, launches = 256, 192, 3
+    seeds = si.jacobi_seeds(ny, nx, 57, count=12)
+    tab = si.jacobi_seed_table(ny, nx, seeds)
+    want = cf.jacobi_flagged(ny, nx, launches, seeds)
+    assert want
+    say("word4 layout kernels")
+    for widths in ({}, {"wc_bits": 2, "bc_bits": 3, "thread_bits": 9}):
+        got, st, _, _ = run_jacobi(torch, hr, ny, nx, launches, tab, w4(**widths))
+        assert st == 0 and got == want, widths
+
+
 def test_word4_jacobi_output_matches_plain(env):
     torch, hr = env
     ny, nx = 80, 48
