@@ -91,10 +91,10 @@ __device__ void reduce_body(const hr_env& e, const G& gin, const G& gout,
 // of label[u].  grp / gcol: optional monitoring of the CSR reads (shadow
 // null when off).
 template <bool CHECK, bool PAIRS = false, class G = hr_gref>
-__device__ void labelprop_body(const hr_env& e, const G& glab, const G& grp, const G& gcol, int32_t* __restrict__ label,
-                               const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
-                               const uint8_t* __restrict__ mask, uint32_t n, uint32_t T, uint32_t lb,
-                               uint32_t t)
+__device__ void labelprop_body(const hr_env& e, const G& glab, const G& grp, const G& gcol,
+                               int32_t* __restrict__ label, const int32_t* __restrict__ rp,
+                               const int32_t* __restrict__ col, const uint8_t* __restrict__ mask,
+                               uint32_t n, uint32_t T, uint32_t lb, uint32_t t)
 {
     const uint32_t v = lb * T + t;
     if (t >= T || v >= n) return;

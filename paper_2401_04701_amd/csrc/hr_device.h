@@ -392,11 +392,12 @@ __device__ __forceinline__ uint64_t hr_check_load(const hr_thread& t, uint64_t* 
 
 // ---------------------------------------------------------------------------
 // The same hooks on 4-byte global words (a context created with
-// HR_CFG_WORD4; word layout hr::c, e.word4).  Every transition and merge
-// widens its words to the 64-bit layout and narrows the result, so a 4-byte
-// word always holds the summary the 64-bit machine would hold for the same
-// accesses (block ids and thread indices folded to the word's fields), and
-// race records carry widened summaries.
+// HR_CFG_WORD4; word layout hr::c, e.word4).  The transition is the 64-bit
+// one written over the 32-bit fields (hr::c::step) and the merge of the
+// fold path widens both words, so a 4-byte word always holds the summary
+// the 64-bit machine would hold for the same accesses (block ids and thread
+// indices folded to the word's fields).  Race records carry widened
+// summaries.
 // ---------------------------------------------------------------------------
 #define HR_NO_REPORT4 (~0u)   // not a word: state numbers stop at 20
 
@@ -404,7 +405,6 @@ __device__ __forceinline__ uint64_t hr_id4(const hr_env& e, const hr_thread& t)
 {
     return hr::c::pack_id(t.block, t.thread, t.bc, t.wc, e.word4);
 }
-
 
 __device__ __noinline__ uint32_t hr_fold4(uint32_t* sp, uint32_t mine, uint32_t lost, uint64_t wm,
                                           uint32_t lay)
@@ -432,7 +432,8 @@ __device__ __forceinline__ void hr_settle4(const hr_env& e, const hr_thread& t, 
     const uint32_t lay = e.word4;
     if (nw == hr::T_RACE) {
         if (r != hr::T_RACE) {
-            uint64_t before = hr::c::widen(old, lay), with = hr::g::step(hr::T_INIT, hr_id4(e, t), k, wm);
+            uint64_t before = hr::c::widen(old, lay);
+            uint64_t with = hr::g::step(hr::T_INIT, hr_id4(e, t), k, wm);
             if (other != HR_NO_LANE) {
                 const uint64_t pair = hr::g::step(with, other_id, k, wm);
                 if (pair == hr::T_RACE) before = hr::g::step(hr::T_INIT, other_id, k, wm);
@@ -475,7 +476,8 @@ __device__ __forceinline__ void hr_check4(const hr_env& e, const hr_thread& t, u
     const uint32_t wm4 = hr::c::group_mask(e.wave_bits, lay);
     const uint32_t old =
         PRE ? pre : __hip_atomic_load(sp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    uint32_t nw = hr::c::step(old, hr::c::pack_id32(t.block, t.thread, t.bc, t.wc, lay), k, wm4, lay);
+    const uint32_t id = hr::c::pack_id32(t.block, t.thread, t.bc, t.wc, lay);
+    uint32_t nw = hr::c::step(old, id, k, wm4, lay);
     uint64_t other_id = 0;
     if (other != HR_NO_LANE) {
         const uint32_t ot = t.thread - __lane_id() + other;
@@ -605,7 +607,8 @@ __device__ __forceinline__ void hr_lds_rrw(const hr_env& e, const hr_thread& t, 
         return;
     }
     const uint32_t wm = hr::l::group_mask(e.wave_bits);
-    const uint32_t rid = hr::l::step(hr::T_INIT, t.lid, hr::CL_R), wid = hr::l::step(hr::T_INIT, t.lid, hr::CL_X);
+    const uint32_t rid = hr::l::step(hr::T_INIT, t.lid, hr::CL_R);
+    const uint32_t wid = hr::l::step(hr::T_INIT, t.lid, hr::CL_X);
     uint32_t* pa = sh + a;
     uint32_t* pb = sh + b;
     uint32_t oa = __hip_atomic_load(pa, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);

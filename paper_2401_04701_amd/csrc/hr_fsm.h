@@ -225,7 +225,10 @@ HR_HD uint32_t bl_sh(uint32_t lay) { return (lay >> 16) & 255u; }
 HR_HD uint32_t thread_mask(uint32_t lay) { return (1u << (bl_sh(lay) - th_sh(lay))) - 1u; }
 // The block field keeps K = 32 - bl_sh >= 3 bits (widths are at most 6, 8 and
 // 10), of which at most 22 are used, as in the 64-bit word.
-HR_HD uint32_t block_mask(uint32_t lay) { return (0xFFFFFFFFu >> bl_sh(lay)) & (g::BLOCK_LIMIT - 1u); }
+HR_HD uint32_t block_mask(uint32_t lay)
+{
+    return (0xFFFFFFFFu >> bl_sh(lay)) & (g::BLOCK_LIMIT - 1u);
+}
 
 // State code (tag | cW << 3 | cB << 5 | cL << 7, the low 9 bits of the
 // 64-bit word) of each state number, seven 9-bit codes per constant:
