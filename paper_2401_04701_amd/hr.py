@@ -300,7 +300,9 @@ class DeviceProgram:
 
 
 class Context:
-    """A checking job: shadow regions, report ring, launch epochs."""
+    """A checking job: shadow regions, report ring, launch epochs.  The
+    arguments are the fields of hr_config; word4=True selects 4-byte global
+    shadow words (HR_CFG_WORD4), whose thread field is thread_bits wide."""
 
     def __init__(self, ring_capacity=0, bc_bits=0, wc_bits=0, count_checks=False,
                  shadow_budget=0, wave_grouping=False, site_limit=0, wave_bits=0,
