@@ -53,14 +53,14 @@ def algorithmic_bytes_per_launch(ny: int, nx: int) -> int:
     return cells * (4 + 4) + 2 * cells * (8 + 8)
 
 
-def counter_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed counter summary, or
-    None when the kernel changed since the counters were taken: its built
-    assembly fingerprint differs from the recorded one, and so does the hash
-    of the sources it compiles from."""
+def counter_traffic(kernel: str, summary: str = "k_jacobi_check_4096x4096_hbm_counters.md"):
+    """HBM bytes per launch of `kernel` from its committed counter summary
+    under profiles/, or None when the kernel changed since the counters were
+    taken: its built assembly fingerprint differs from the recorded one, and
+    so does the hash of the sources it compiles from."""
     import hashlib
     import re as _re
-    path = os.path.join(ROOT, "profiles", "k_jacobi_check_4096x4096_hbm_counters.md")
+    path = os.path.join(ROOT, "profiles", summary)
     if not os.path.exists(path):
         return None
     m = _re.search(r"```json\n(.*?)\n```", open(path).read(), flags=_re.S)
@@ -292,7 +292,9 @@ def bench_labelprop(args, torch, si, hr, stream):
     avg = float(np.mean(launch_ms)) * 1e-3
     res["flagged"] = int(len(recs))
     res["roofline"] = {"bound": "hbm", "achieved": alg / avg / 1e9, "peak": HBM_PEAK_GBS,
-                       "unit": "GB/s", "frac": alg / avg / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                       "unit": "GB/s", "frac": alg / avg / 1e9 / HBM_PEAK_GBS,
+                       "traffic": counter_traffic(
+                           "k_labelprop<true>", "k_labelprop_check_rmat22_hbm_counters.md"),
                        "kernel": "k_labelprop<true>", "alg_bytes_per_launch": alg,
                        "avg_launch_ms": avg * 1e3}
     print(json.dumps(res), flush=True)
