@@ -421,6 +421,26 @@ __device__ __noinline__ uint32_t hr_fold4(uint32_t* sp, uint32_t mine, uint32_t 
     }
 }
 
+// The record of a race completed by a 4-byte hook, in the 8-byte layout.
+// Out of line with scalar arguments: the rare path.
+__device__ __noinline__ void hr_race4(hr_race_rec* ring, uint32_t* ctr, uint32_t ring_cap,
+                                      uint32_t site_limit, uint32_t launch_seq, uint32_t head,
+                                      uint32_t region, uint32_t block, uint64_t index,
+                                      uint32_t thread, uint32_t bc, uint32_t wc, uint32_t k,
+                                      uint32_t old, uint32_t lay, uint64_t wm, uint32_t other,
+                                      uint64_t other_id)
+{
+    uint64_t before = hr::c::widen(old, lay);
+    uint64_t with = hr::g::step(hr::T_INIT, hr::c::pack_id(block, thread, bc, wc, lay), k, wm);
+    if (other != HR_NO_LANE) {
+        const uint64_t pair = hr::g::step(with, other_id, k, wm);
+        if (pair == hr::T_RACE) before = hr::g::step(hr::T_INIT, other_id, k, wm);
+        else with = pair;
+    }
+    hr_push_rec(ring, ctr, ring_cap, site_limit, launch_seq, head, region, block, index, thread,
+                before, with, 0);
+}
+
 template <int KIND>
 __device__ __forceinline__ void hr_settle4(const hr_env& e, const hr_thread& t, uint32_t* sp,
                                            uint32_t region, uint64_t index, uint32_t site,
@@ -431,16 +451,10 @@ __device__ __forceinline__ void hr_settle4(const hr_env& e, const hr_thread& t, 
     const uint64_t wm = hr::g::group_mask(e.wave_bits);
     const uint32_t lay = e.word4;
     if (nw == hr::T_RACE) {
-        if (r != hr::T_RACE) {
-            uint64_t before = hr::c::widen(old, lay);
-            uint64_t with = hr::g::step(hr::T_INIT, hr_id4(e, t), k, wm);
-            if (other != HR_NO_LANE) {
-                const uint64_t pair = hr::g::step(with, other_id, k, wm);
-                if (pair == hr::T_RACE) before = hr::g::step(hr::T_INIT, other_id, k, wm);
-                else with = pair;
-            }
-            hr_ring_push(e, 0, region, t.block, index, t.thread, KIND, site, before, with, 0);
-        }
+        if (r != hr::T_RACE)
+            hr_race4(e.ring, e.ctr, e.ring_cap, e.site_limit, e.launch_seq,
+                     0u | ((uint32_t)KIND << 8) | ((site & 0xFFFFu) << 16), region, t.block, index,
+                     t.thread, t.bc, t.wc, k, old, lay, wm, other, other_id);
         return;
     }
     if (r != old) {

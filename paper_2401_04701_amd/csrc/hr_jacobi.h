@@ -182,10 +182,11 @@ __global__ __launch_bounds__(256, 8) void k_jacobi(hr_kargs a, hr_gref gold, hr_
 }
 
 // The checked sweep on 4-byte shadow words, with the word layout as a
-// constant (LAY) or the context's (LAY = 0).  7 waves per SIMD: the 4-byte
-// hook needs a few more registers than the 8-byte one.
+// constant (LAY) or the context's (LAY = 0).  With a constant layout it fits
+// 8 waves per SIMD; the context-layout kernel needs a few more registers
+// and runs 7.
 template <uint32_t LAY>
-__global__ __launch_bounds__(256, 7) void k_jacobi4(hr_kargs a, hr_gref4t<LAY> gold,
+__global__ __launch_bounds__(256, LAY ? 8 : 7) void k_jacobi4(hr_kargs a, hr_gref4t<LAY> gold,
                                                  hr_gref4t<LAY> gnew,
                                                  const float* __restrict__ uo,
                                                  float* __restrict__ un, uint32_t ny, uint32_t nx,
