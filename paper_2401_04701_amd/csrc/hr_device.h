@@ -250,6 +250,25 @@ __device__ __forceinline__ uint32_t hr_group(uint64_t word_addr, bool* member)
     return other;
 }
 
+// The record of a race completed by a global hook: the completing access
+// alone or, with a group partner, the pair of lanes (if they race with each
+// other) or their summary.  Out of line with scalar arguments: the rare path.
+__device__ __noinline__ void hr_race8(hr_race_rec* ring, uint32_t* ctr, uint32_t ring_cap,
+                                      uint32_t site_limit, uint32_t launch_seq, uint32_t head,
+                                      uint32_t region, uint32_t block, uint64_t index,
+                                      uint32_t thread, uint64_t gid, uint32_t k, uint64_t old,
+                                      uint64_t wm, uint32_t other, uint64_t other_id)
+{
+    uint64_t before = old, with = hr::g::step(hr::T_INIT, gid, k, wm);
+    if (other != HR_NO_LANE) {
+        const uint64_t pair = hr::g::step(with, other_id, k, wm);
+        if (pair == hr::T_RACE) before = hr::g::step(hr::T_INIT, other_id, k, wm);
+        else with = pair;
+    }
+    hr_push_rec(ring, ctr, ring_cap, site_limit, launch_seq, head, region, block, index, thread,
+                before, with, 0);
+}
+
 // Check one access of kind KIND (0 read, 1 write, 2 atomic) to element
 // `index` of a global region whose shadow is shadow[0..n); `region` is the
 // id written into a race record.  GROUP marks a call site whose addresses
@@ -283,17 +302,10 @@ __device__ __forceinline__ void hr_settle(const hr_env& e, const hr_thread& t, u
     constexpr uint32_t k = KIND == 0 ? hr::CL_R : (KIND == 2 ? hr::CL_A : hr::CL_X);
     const uint64_t wm = hr::g::group_mask(e.wave_bits);
     if (nw == hr::T_RACE) {
-        if (r != hr::T_RACE) {
-            // the completing access alone; with a group partner, the pair
-            // of lanes (if they race with each other) or their summary
-            uint64_t before = old, with = hr::g::step(hr::T_INIT, t.gid, k, wm);
-            if (other != HR_NO_LANE) {
-                const uint64_t pair = hr::g::step(with, other_id, k, wm);
-                if (pair == hr::T_RACE) before = hr::g::step(hr::T_INIT, other_id, k, wm);
-                else with = pair;
-            }
-            hr_ring_push(e, 0, region, t.block, index, t.thread, KIND, site, before, with, 0);
-        }
+        if (r != hr::T_RACE)
+            hr_race8(e.ring, e.ctr, e.ring_cap, e.site_limit, e.launch_seq,
+                     ((uint32_t)KIND << 8) | ((site & 0xFFFFu) << 16), region, t.block, index,
+                     t.thread, t.gid, k, old, wm, other, other_id);
         return;
     }
     if (r != old) {
