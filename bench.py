@@ -12,8 +12,9 @@ report (device-to-host copy of the flagged set).
 
 Prints one JSON line: checks/s, slowdown against the same kernel without
 hooks, p50/p99 per-launch latency, the roofline of the instrumented kernel,
-measured device peaks, and the CPU oracle timed on a sample of the job, on
-one core and on the host threads available (at most 16).
+measured device peaks, and the CPU oracle timed on the same records (launch
+0 of the job by default, the whole job with --cpu-full-job) on the host
+threads available (at most 16), and on one core.
 """
 from __future__ import annotations
 
@@ -45,12 +46,17 @@ def jacobi_check_counts(ny: int, nx: int, seeded_writes: int):
 
 
 def algorithmic_bytes_per_launch(ny: int, nx: int) -> int:
-    """HBM bytes one checked sweep must move: the stencil's own data (4-byte
-    read of u_old and 4-byte write of u_new per cell) plus, for each of the
-    two monitored arrays, one 8-byte shadow word read and written back per
-    cell (every word changes state at least once per launch)."""
-    cells = ny * nx
-    return cells * (4 + 4) + 2 * cells * (8 + 8)
+    """HBM bytes the checking method must move in one sweep: for each of the
+    two monitored arrays, every 8-byte shadow word is read and written back
+    once (each word changes state at least once per launch, and streaming
+    it costs its line's read and write-back), 16 bytes per monitored word."""
+    return 2 * ny * nx * (8 + 8)
+
+
+def data_bytes_per_launch(ny: int, nx: int) -> int:
+    """HBM bytes of the stencil's own data in one sweep: a 4-byte read of
+    u_old and a 4-byte write of u_new per cell."""
+    return ny * nx * (4 + 4)
 
 
 def counter_traffic(kernel: str, summary: str = "k_jacobi_check_4096x4096_hbm_counters.md"):
@@ -87,66 +93,54 @@ def pct(a, q):
     return float(np.percentile(np.asarray(a, dtype=np.float64), q))
 
 
-def cpu_baseline():
-    """The oracle, single-threaded, on a 768 x 768 sample of the job (about
-    10 s of CPU work)."""
+def host_cpu():
+    """The host's CPU model and the threads this process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "nproc": os.cpu_count(),
+            "threads_available": len(os.sched_getaffinity(0))}
+
+
+def cpu_baseline(gpu_keys, full_job=False):
+    """The oracle on the same records the GPU checks: the access log of the
+    4096 x 4096 job modelled and checked piece by piece (one launch, one band
+    of 16 block rows with its neighbour rows; oracle/goldens.py), over worker
+    processes on the host threads available (at most 16).  By default the
+    sample is launch 0 of the job's 20; full_job runs all 20 launches.  Its
+    flagged set is compared with the GPU's keys of the launch's output array
+    (region 1 for launch 0).  Also one band of launch 0 on one core."""
     import oracle
     import synth_inputs as si
-    n = 768
-    seeds = si.jacobi_seeds(n, n, si.master_seed(1))
-    tab = si.jacobi_seed_table(n, n, seeds)
+    from oracle import goldens
+    oracle.build(force=False)
+    seeds = si.jacobi_seeds(NY, NX, si.master_seed(1))
+    tab = si.jacobi_seed_table(NY, NX, seeds)
+    launches = list(range(LAUNCHES)) if full_job else [0]
+    keys, checks, dt, workers = goldens.jacobi_streamed(NY, NX, LAUNCHES, tab,
+                                                        launch_list=launches)
+    want = gpu_keys if full_job else {k for k in gpu_keys if k[1] == 1}
     t0 = time.perf_counter()
-    checks = 0
-    flagged = set()
-    for L in range(LAUNCHES):
-        log = oracle.model_jacobi(n, n, 1, tab, launch0=L)
-        checks += log.shape[0]
-        flagged |= oracle.flagged(log)
-    dt = time.perf_counter() - t0
-    return {"value": checks / dt, "unit": "checks/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n}x{n} grid ({n * n / (NY * NX):.4f} of the cells), {LAUNCHES} launches, "
-                      f"{len(seeds)} seeded blocks: access-log generation plus pairwise check, "
-                      f"{checks} checks in {dt:.1f} s, {len(flagged)} flagged",
-            "seconds": dt}
-
-
-def _oracle_ready(_):
-    import oracle
-    oracle._lib()
-    return os.getpid()
-
-
-def _oracle_launch(job):
-    """One launch of the sampled job through the oracle (a worker task)."""
-    import oracle
-    n, L, tab = job
-    log = oracle.model_jacobi(n, n, 1, tab, launch0=L)
-    return int(log.shape[0]), oracle.flagged(log)
-
-
-def cpu_baseline_parallel():
-    """The same oracle on the same sample with its launches spread over
-    worker processes, one launch per task (a launch boundary orders every
-    access of a launch before the next launch, so races never span two
-    launches).  Workers: the host threads this process may use, at most 16.
-    The pool is started and warm before the timed region."""
-    import multiprocessing as mp
-    import synth_inputs as si
-    n = 768
-    seeds = si.jacobi_seeds(n, n, si.master_seed(1))
-    tab = si.jacobi_seed_table(n, n, seeds)
-    workers = max(1, min(16, len(os.sched_getaffinity(0))))
-    with mp.get_context("spawn").Pool(workers) as pool:
-        pool.map(_oracle_ready, range(4 * workers), chunksize=1)
-        t0 = time.perf_counter()
-        res = pool.map(_oracle_launch, [(n, L, tab) for L in range(LAUNCHES)], chunksize=1)
-        dt = time.perf_counter() - t0
-    checks = sum(c for c, _ in res)
-    flagged = set().union(*(f for _, f in res))
+    goldens._JAC.update(ny=NY, nx=NX, tab=tab)
+    _, one_checks = goldens._jacobi_piece((0, 0, 16))
+    one_dt = time.perf_counter() - t0
+    what = "the whole job (20 launches)" if full_job else "launch 0 of the job's 20"
     return {"value": checks / dt, "unit": "checks/s", "cores": workers, "kind": "oracle",
-            "sample": f"{n}x{n} grid, {LAUNCHES} launches over {workers} worker processes, "
-                      f"{checks} checks in {dt:.2f} s, {len(flagged)} flagged",
-            "seconds": dt}
+            "sample": f"{what} on the full {NY}x{NX} grid, the same records the GPU checks: "
+                      f"{checks} checks in {dt:.1f} s over {workers} worker processes, "
+                      f"{len(keys)} flagged",
+            "seconds": dt, "checks": checks, "flagged": len(keys),
+            "same_flagged_set_as_gpu": keys == want,
+            "single_core": {"value": one_checks / one_dt, "unit": "checks/s", "cores": 1,
+                            "sample": f"launch 0, block rows 0-15 (with row 16): {one_checks} "
+                                      f"checks in {one_dt:.1f} s"},
+            "host": host_cpu()}
 
 
 def _best_ms(torch, stream, fn, reps=6):
@@ -471,6 +465,9 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-full-job", action="store_true",
+                    help="time the oracle on all 20 launches of the job (a few minutes of "
+                         "host time) instead of launch 0")
     ap.add_argument("--no-peaks", action="store_true")
     ap.add_argument("--verify-count", action="store_true",
                     help="first run one job with the device access counter (untimed)")
@@ -614,6 +611,7 @@ def main():
     avg_launch_s = float(np.mean(launch_ms)) * 1e-3
     alg = algorithmic_bytes_per_launch(NY, NX)
     achieved = alg / avg_launch_s / 1e9
+    with_data = alg + data_bytes_per_launch(NY, NX)
     result = {
         "metric": "instrumented accesses checked/sec + slowdown vs uninstrumented; p50/p99 check latency",
         "value": checks_per_step / step_s,
@@ -641,7 +639,13 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic("k_jacobi<true>"),
                      "kernel": "k_jacobi<true>", "alg_bytes_per_launch": alg,
-                     "avg_launch_ms": avg_launch_s * 1e3},
+                     "alg_bytes": "16 B per monitored shadow word (8 B read, 8 B written "
+                                  "back), 2 x 4096 x 4096 words",
+                     "avg_launch_ms": avg_launch_s * 1e3,
+                     "with_stencil_data": {
+                         "bytes_per_launch": with_data,
+                         "achieved": with_data / avg_launch_s / 1e9,
+                         "frac": with_data / avg_launch_s / 1e9 / HBM_PEAK_GBS}},
     }
     step4_s = (t41 - t40) / args.steps
     result["word4"] = {"value": checks_per_step / step4_s, "unit": "checks/s",
@@ -657,8 +661,11 @@ def main():
                             "peak_xchg_per_s": peaks["xchg_coalesced_per_s"],
                             "frac": g_rate / peaks["xchg_coalesced_per_s"], **peaks}
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline()
-        result["cpu_baseline_parallel"] = cpu_baseline_parallel()
+        remap = {regs[0]: 0, regs[1]: 1}
+        gpu_keys = {(int(r["space"]),
+                     int(r["region"]) if r["space"] else remap[int(r["region"])],
+                     int(r["block"]) if r["space"] else 0, int(r["index"])) for r in recs}
+        result["cpu_baseline"] = cpu_baseline(gpu_keys, full_job=args.cpu_full_job)
     print(json.dumps(result), flush=True)
 
 

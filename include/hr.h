@@ -52,8 +52,15 @@ typedef enum {
      * and was skipped; that job's results are incomplete. */
     HR_W_STALLED = 8,
     /* Some call site reached hr_config.site_limit: its further race records
-     * were dropped, so the reported set may be incomplete. */
+     * were dropped.  hr_report still completes the global-memory part of the
+     * set from the sticky race states in shadow memory; LDS races whose
+     * records were dropped are lost. */
     HR_W_REPORT_LIMITED = 16,
+    /* HR_CFG_WORD4 only: some checked thread's block id or thread index did
+     * not fit the 4-byte word's block or thread field, so ids were taken
+     * modulo the field widths; races between accessors whose ids fold
+     * together may be missing from the set (none is ever invented). */
+    HR_W_FOLDED = 32,
     HR_E_INVAL = -1,   /* bad argument */
     HR_E_NOMEM = -2,   /* allocation failed or shadow budget exceeded */
     HR_E_HIP = -3,     /* a HIP runtime call failed */
@@ -65,6 +72,11 @@ typedef enum { HR_GLOBAL = 0, HR_LDS = 1 } hr_space;
  * the paper's state machine (Sec. III-B). */
 typedef enum { HR_READ = 0, HR_WRITE = 1, HR_ATOMIC = 2 } hr_kind;
 
+/* Configuration of a context.  The paper exposes the checker's settings as a
+ * configuration, among them bounds on the shadow metadata that trade memory
+ * for range (Sec. IV, introduction), and makes the scalar clocks' widths
+ * configurable, with checking stopped by a warning when a clock overflows
+ * (Sec. III-A, footnote on clock sizes).  Zero fields take the defaults. */
 typedef struct {
     uint32_t ring_capacity;  /* race records kept on the device; 0: 65536 */
     uint32_t bc_bits;        /* block-clock width 1..8; 0: 8 (HR_CFG_WORD4: 2) */
@@ -108,8 +120,8 @@ typedef struct {
  * every word to the initial state at each launch boundary.  Exact while a
  * launch has at most 2^K blocks (K the block field's width) and 2^thread_bits
  * threads per block; beyond that, block ids and thread indices are taken
- * modulo those powers, and races between accessors that then look alike can
- * be missed (never invented).  Race records carry 8-byte summaries with
+ * modulo those powers, races between accessors that then look alike can be
+ * missed (never invented), and hr_report warns HR_W_FOLDED.  Race records carry 8-byte summaries with
  * launch 0 and the folded block.  The batched and serving executors reject
  * such a context. */
 #define HR_CFG_WORD4 4u
@@ -162,13 +174,25 @@ typedef struct {
     uint32_t thread;        /* the thread (HR_S_THREAD) */
 } hr_summary;
 
-/* Create a context whose default stream is `stream`.  Allocates the report
- * ring and counters on the current HIP device.  cfg may be NULL (defaults).
- * Errors: HR_E_INVAL (cfg out of range), HR_E_NOMEM, HR_E_HIP. */
+/* Create a context whose default stream is `stream` (paper Sec. IV: the
+ * checker's configuration; Sec. III-A, footnote on clock sizes: the clock
+ * widths of cfg bound the block and wave clocks).  Allocates the report ring
+ * and counters on the current HIP device; the context owns them and every
+ * shadow region later allocated in it.  cfg may be NULL (defaults); it is
+ * copied.  *out receives the context, or NULL on error.
+ * Errors: HR_E_INVAL (out NULL, cfg out of range: unknown flags, bc_bits > 8,
+ * wc_bits > 6, wave_bits > 6, ring_capacity > 2^26, thread_bits set without
+ * HR_CFG_WORD4 or above 10), HR_E_NOMEM (a device allocation failed),
+ * HR_E_HIP. */
 hr_status hr_ctx_create(hr_ctx* out, const hr_config* cfg, void* stream);
 
-/* Free every device allocation of the context.  Blocks until its default
- * stream is idle. */
+/* Free every device allocation of the context: shadow regions, batch arenas,
+ * report ring and counters (the tool allocates the metadata of the data it
+ * monitors and frees it again, Sec. IV-C; here the context owns all of it,
+ * while the monitored buffers and the streams stay the caller's).  Blocks
+ * until its default stream is idle; c is invalid afterwards.  Errors:
+ * HR_E_INVAL (c NULL), HR_E_HIP (the stream reported an error; the memory is
+ * freed all the same). */
 hr_status hr_ctx_destroy(hr_ctx c);
 
 /* Monitor `bytes` of device memory at data_dev as 4-byte elements (the
@@ -196,14 +220,24 @@ hr_status hr_region_enable(hr_ctx c, uint32_t region, uint32_t on);
  * HR_E_STATE (the region is a view into a batch's shared allocation). */
 hr_status hr_shadow_free(hr_ctx c, uint32_t region);
 
-/* Copy the plain-old-data block that instrumented kernels receive (shadow
- * pointers, region sizes, report ring, current launch epoch) into out
- * (host memory, cap bytes).  *size_out receives its size.  The block is
- * valid until the next hr_kernel_end.  Errors: HR_E_INVAL (cap too small). */
+/* Copy the plain-old-data block that instrumented kernels receive into out
+ * (host memory, cap bytes; *size_out, when not NULL, receives its size).  It
+ * carries what the per-access update of Algorithm 1 (Sec. IV-B) takes
+ * besides the thread's own identity and clocks: the shadow address of each
+ * region (the update's sAddr comes from it and the element index), the
+ * region sizes, the report ring and counters, the clock limits and the
+ * current launch epoch.  The device pointers in it stay owned by the context.
+ * The block is valid until the next hr_kernel_end, hr_reset or region
+ * change.  Errors: HR_E_INVAL (c NULL, out NULL, or cap too small: *size_out
+ * still receives the size needed). */
 hr_status hr_dev_args(hr_ctx c, void* out, size_t cap, size_t* size_out);
 
 /* Mark a kernel-launch boundary: every access of the launches before it
- * happens before every access after it.  Advances the launch epoch; every
+ * happens before every access after it (Sec. II-B: threads of one grid
+ * synchronize only through barriers; a later launch on the same stream
+ * starts after the earlier one ends).  Call it after each checked launch,
+ * on the launch's stream.  Errors: HR_E_INVAL (c NULL), HR_E_HIP.  Advances
+ * the launch epoch; every
  * 512 launches it clears the shadow on `stream`.  Races already found stay
  * in the ring; if the ring has overflowed, the global races held in the
  * shadow are first read back and kept for hr_report.  Asynchronous, except
@@ -218,10 +252,15 @@ hr_status hr_kernel_end(hr_ctx c, void* stream);
 hr_status hr_reset(hr_ctx c, void* stream);
 
 /* Synchronise `stream`, then copy out the flagged set: one record per racy
- * key, sorted by (space, region, block if LDS, index), unique.  Writes up to
- * cap records to out (host) and the full count to *n_out.  Returns the
- * warning bits, HR_E_INVAL if cap is too small (*n_out then holds the count),
- * or HR_E_HIP. */
+ * key, sorted by (space, region, block if LDS, index), unique (races are
+ * reported once per unique address, Sec. V-C).  Writes up to cap records to
+ * out (host memory owned by the caller) and the full count to *n_out.  When
+ * race records are missing (the ring overflowed, or a call site reached
+ * site_limit) the global-memory part of the set is completed from the sticky
+ * race states in shadow memory (those records carry HR_RACE_SCANNED).
+ * Returns the warning bits, HR_E_INVAL (c or n_out NULL, or cap too small:
+ * *n_out then holds the count), or HR_E_HIP.  The ring is not cleared (see
+ * hr_reset). */
 hr_status hr_report(hr_ctx c, hr_race* out, size_t cap, size_t* n_out, void* stream);
 
 /* Synchronise `stream` and read the checked-access counter (only counts when

@@ -28,6 +28,7 @@
 #define HR_DEVF_RANGE 4u
 #define HR_DEVF_STALL 8u    // a batched item gave up waiting for its phase
 #define HR_DEVF_LIMIT 16u   // a call site reached its record limit
+#define HR_DEVF_FOLD 32u    // a block or thread id exceeded a 4-byte word's field
 
 // Counter words.
 #define HR_CTR_HEAD 0     // ring append index
@@ -90,6 +91,21 @@ struct hr_thread {
                          // bit 1 is set while the thread is switched off
 };
 
+__device__ __forceinline__ void hr_set_flag(const hr_env& e, uint32_t bit)
+{
+    __hip_atomic_fetch_or(e.ctr + HR_CTR_FLAGS, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// A 4-byte word keeps block ids and thread indices modulo its field widths:
+// two accessors whose ids fold together look like one, which can hide a race
+// between them.  The first lane of each wave with such a thread raises the
+// HR_DEVF_FOLD flag, out of line (the rare path).
+__device__ __noinline__ void hr_fold_flag(uint32_t* ctr)
+{
+    __hip_atomic_fetch_or(ctr + HR_CTR_FLAGS, HR_DEVF_FOLD, __ATOMIC_RELAXED,
+                          __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ __forceinline__ hr_thread hr_thread_make(const hr_env& e, uint32_t block,
                                                     uint32_t thread)
 {
@@ -101,12 +117,13 @@ __device__ __forceinline__ hr_thread hr_thread_make(const hr_env& e, uint32_t bl
     t.enabled = 1;
     t.gid = hr::g::pack_id(e.launch, block, thread, 0, 0);
     t.lid = hr::l::pack_id(thread, 0, 0);
+    if (e.word4) {
+        const bool folded = (block & ~hr::c::block_mask(e.word4)) != 0 ||
+                            (thread & ~hr::c::thread_mask(e.word4)) != 0;
+        const uint64_t m = __ballot(folded);
+        if (m && __lane_id() == (uint32_t)__builtin_ctzll(m)) hr_fold_flag(e.ctr);
+    }
     return t;
-}
-
-__device__ __forceinline__ void hr_set_flag(const hr_env& e, uint32_t bit)
-{
-    __hip_atomic_fetch_or(e.ctr + HR_CTR_FLAGS, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Debug counting of checked accesses: one atomic per wave and hook, spread

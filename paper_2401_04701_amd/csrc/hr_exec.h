@@ -129,11 +129,6 @@ __device__ __forceinline__ hr_inst_dev load_uniform(const hr_inst_dev& G)
     return I;
 }
 
-// Shape checks and derived sizes of one job; fills blocks (and threads for
-// jacobi), the element counts of its two monitored buffers and the LDS bytes
-// of one work item.
-bool hr_instance_shape(hr_instance& in, size_t elems[2], size_t* lds_bytes);
-
 // Descriptor of a job whose shadow words are at sh0 / sh1; report ids r0/r1.
 hr_inst_dev hr_make_inst_dev(const hr_instance& in, const size_t elems[2], uint64_t* sh0,
                              uint64_t* sh1, uint32_t r0, uint32_t r1, uint32_t done_off);

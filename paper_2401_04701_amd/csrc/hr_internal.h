@@ -41,6 +41,12 @@ struct hr_ctx_s {
 };
 
 hipStream_t hr_stream(hr_ctx c, void* stream);
+// Apply the defaults of hr_config and check its ranges (false: invalid).
+bool hr_config_normalize(const hr_config* cfg, hr_config* out);
+// The hooks' environment of a normalized configuration over the given ring,
+// counters and debug counters, at launch number launch_seq.
+hr_env hr_env_of(const hr_config& cfg, hr_race_rec* ring, uint32_t* ctr,
+                 unsigned long long* count, uint32_t launch_seq);
 hr_env hr_make_env(hr_ctx c);
 void hr_fill_args(hr_ctx c, hr_kargs* a);
 // A region usable through kernel arguments (id < HR_MAX_REGIONS), registered
@@ -52,6 +58,33 @@ uint32_t hr_new_region(hr_ctx c, const void* data, size_t elems, uint64_t* shado
 void hr_free_alloc(hr_ctx c, uint32_t alloc);
 hipError_t hr_fill64(uint64_t* p, size_t n, hipStream_t s);
 hipError_t hr_fill32(uint32_t* p, size_t n, hipStream_t s);
+// Sort race records by key (space, region, block if LDS, index) and keep
+// the first of each key, in place; returns the number kept.
+size_t hr_sort_unique(hr_race* recs, size_t n);
+// Append a scanned record to ring[] for every race-state word among the
+// shadow words [first, first + n) of a region (4-byte words when word4),
+// taking slots from *count; ring must have room for n more records.  With
+// ring null the race words are only counted in *count.
+hipError_t hr_scan_races_dev(const uint64_t* sh, size_t n, size_t first, bool word4,
+                             uint32_t region, hr_race_rec* ring, uint32_t* count, hipStream_t s);
+
+// Shape checks and derived sizes of one job (hr_instance); fills blocks (and
+// threads for jacobi), the element counts of its two monitored buffers and
+// the LDS bytes of one work item of the batched and serving executors.
+bool hr_instance_shape(hr_instance& in, size_t elems[2], size_t* lds_bytes);
+
+// The checked kernels of the workloads with prepared kernel arguments (the
+// regions are not validated here; the hr_*_check entries do that).
+hr_status hr_launch_reduce(const hr_kargs& a, uint32_t r_in, uint32_t r_out, const int32_t* in_dev,
+                           int32_t* out_dev, uint32_t n, uint32_t threads, uint32_t blocks,
+                           int32_t drop, hipStream_t s);
+hr_status hr_launch_jacobi(const hr_kargs& a, uint32_t r_old, uint32_t r_new,
+                           const float* u_old_dev, float* u_new_dev, uint32_t ny, uint32_t nx,
+                           const int32_t* seed_dev, hipStream_t s);
+hr_status hr_launch_labelprop(const hr_kargs& a, uint32_t r_label, uint32_t r_row_ptr,
+                              uint32_t r_col, int32_t* label_dev, const int32_t* row_ptr_dev,
+                              const int32_t* col_dev, const uint8_t* mask_dev, uint32_t n,
+                              uint32_t tpb, hipStream_t s);
 
 #define HR_HIP_CHECK(expr)                              \
     do {                                                \

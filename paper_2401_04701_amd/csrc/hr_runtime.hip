@@ -27,14 +27,15 @@ __global__ void k_fill32(uint32_t* __restrict__ p, size_t n, uint32_t v)
 }
 
 // The launch-boundary clear of 4-byte words, two per 8-byte unit: back to
-// the initial state, except that while the ring has overflowed (read on the
+// the initial state, except that while some race record is missing from the
+// ring (it overflowed, or a call site reached its record limit; read on the
 // device) a word in the race state keeps it for the report's scan.
 __global__ void k_clear_word4(uint64_t* __restrict__ p, size_t n, const uint32_t* __restrict__ ctr,
                               uint32_t ring_cap)
 {
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     const size_t stride = (size_t)gridDim.x * blockDim.x;
-    if (ctr[HR_CTR_HEAD] <= ring_cap) {
+    if (ctr[HR_CTR_HEAD] <= ring_cap && !(ctr[HR_CTR_FLAGS] & HR_DEVF_LIMIT)) {
         for (; i < n; i += stride) p[i] = 0;
         return;
     }
@@ -53,23 +54,71 @@ hr_status clear_shadows(hr_ctx c, hipStream_t s)
     return HR_OK;
 }
 
-struct key_less {
-    static uint32_t kb(const hr_race& r) { return r.space == HR_LDS ? r.block : 0u; }
-    bool operator()(const hr_race& a, const hr_race& b) const
-    {
-        if (a.space != b.space) return a.space < b.space;
-        if (a.region != b.region) return a.region < b.region;
-        if (kb(a) != kb(b)) return kb(a) < kb(b);
-        if (a.index != b.index) return a.index < b.index;
-        return a.launch < b.launch;
+// The global races among n shadow words: each word in the race state is
+// appended to ring[] as a scanned record (only its key is valid) at the
+// index taken from *count, or only counted when ring is null.  The caller
+// sizes ring for every word it scans.
+__global__ void k_scan_races(const uint64_t* __restrict__ sh, size_t n, size_t first,
+                             uint32_t word4, uint32_t region, hr_race_rec* __restrict__ ring,
+                             uint32_t* __restrict__ count)
+{
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) {
+        const size_t e = first + i;
+        const bool race = word4 ? ((const uint32_t*)sh)[e] == hr::T_RACE
+                                : (sh[e] & hr::g::TAG_M) == hr::T_RACE;
+        if (!race) continue;
+        const uint32_t slot =
+            __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (!ring) continue;
+        uint4* p = reinterpret_cast<uint4*>(ring + slot);
+        p[0] = make_uint4(0u, region, 0xFFFFFFFFu, 0xFFFFFFFFu);
+        p[1] = make_uint4((uint32_t)e, (uint32_t)(e >> 32), 0u, 0u);
+        p[2] = make_uint4(0u, 0u, 0xFFFFFFFFu, HR_RACE_SCANNED);
     }
-    static bool same(const hr_race& a, const hr_race& b)
-    {
-        return a.space == b.space && a.region == b.region && kb(a) == kb(b) && a.index == b.index;
-    }
-};
+}
 
 }  // namespace
+
+namespace {
+uint32_t key_block(const hr_race& r) { return r.space == HR_LDS ? r.block : 0u; }
+
+bool key_less(const hr_race& a, const hr_race& b)
+{
+    if (a.space != b.space) return a.space < b.space;
+    if (a.region != b.region) return a.region < b.region;
+    if (key_block(a) != key_block(b)) return key_block(a) < key_block(b);
+    if (a.index != b.index) return a.index < b.index;
+    return a.launch < b.launch;
+}
+
+bool key_same(const hr_race& a, const hr_race& b)
+{
+    return a.space == b.space && a.region == b.region && key_block(a) == key_block(b) &&
+           a.index == b.index;
+}
+}  // namespace
+
+size_t hr_sort_unique(hr_race* recs, size_t n)
+{
+    std::sort(recs, recs + n, key_less);
+    size_t m = 0;
+    for (size_t i = 0; i < n; ++i)
+        if (m == 0 || !key_same(recs[m - 1], recs[i])) recs[m++] = recs[i];
+    return m;
+}
+
+hipError_t hr_scan_races_dev(const uint64_t* sh, size_t n, size_t first, bool word4,
+                             uint32_t region, hr_race_rec* ring, uint32_t* count, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    const size_t blocks = std::min<size_t>((n + 255) / 256, 8192);
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(k_scan_races, dim3((unsigned)blocks), dim3(256), 0, s, sh, n, first,
+                       word4 ? 1u : 0u, region, ring, count);
+    return hipGetLastError();
+}
 
 // Clears run as kernels rather than hipMemsetAsync so the calls stay safe
 // inside a captured HIP graph.
@@ -96,24 +145,30 @@ hipStream_t hr_stream(hr_ctx c, void* stream)
     return stream ? (hipStream_t)stream : c->stream;
 }
 
-hr_env hr_make_env(hr_ctx c)
+hr_env hr_env_of(const hr_config& cfg, hr_race_rec* ring, uint32_t* ctr,
+                 unsigned long long* count, uint32_t launch_seq)
 {
     hr_env e{};
-    e.ring = c->ring;
-    e.ctr = c->ctr;
-    e.count = (c->cfg.flags & HR_CFG_COUNT_CHECKS) ? c->count : nullptr;
-    e.ring_cap = c->cfg.ring_capacity;
-    e.launch = c->launch_seq & ((1u << hr::g::LAUNCH_BITS) - 1);
-    e.launch_seq = c->launch_seq;
-    e.bc_max = (1u << c->cfg.bc_bits) - 1;
-    e.wc_max = (1u << c->cfg.wc_bits) - 1;
-    e.group = (c->cfg.flags & HR_CFG_WAVE_GROUPING) ? 1u : 0u;
-    e.site_limit = c->cfg.site_limit;
-    e.wave_bits = c->cfg.wave_bits;
-    e.word4 = (c->cfg.flags & HR_CFG_WORD4)
-                  ? hr::c::layout(c->cfg.wc_bits, c->cfg.bc_bits, c->cfg.thread_bits)
+    e.ring = ring;
+    e.ctr = ctr;
+    e.count = (cfg.flags & HR_CFG_COUNT_CHECKS) ? count : nullptr;
+    e.ring_cap = cfg.ring_capacity;
+    e.launch = launch_seq & ((1u << hr::g::LAUNCH_BITS) - 1);
+    e.launch_seq = launch_seq;
+    e.bc_max = (1u << cfg.bc_bits) - 1;
+    e.wc_max = (1u << cfg.wc_bits) - 1;
+    e.group = (cfg.flags & HR_CFG_WAVE_GROUPING) ? 1u : 0u;
+    e.site_limit = cfg.site_limit;
+    e.wave_bits = cfg.wave_bits;
+    e.word4 = (cfg.flags & HR_CFG_WORD4)
+                  ? hr::c::layout(cfg.wc_bits, cfg.bc_bits, cfg.thread_bits)
                   : 0u;
     return e;
+}
+
+hr_env hr_make_env(hr_ctx c)
+{
+    return hr_env_of(c->cfg, c->ring, c->ctr, c->count, c->launch_seq);
 }
 
 void hr_fill_args(hr_ctx c, hr_kargs* a)
@@ -168,10 +223,8 @@ void hr_free_alloc(hr_ctx c, uint32_t alloc)
         if (r.alloc == alloc) r.live = false;
 }
 
-extern "C" hr_status hr_ctx_create(hr_ctx* out, const hr_config* cfg, void* stream)
+bool hr_config_normalize(const hr_config* cfg, hr_config* out)
 {
-    if (!out) return HR_E_INVAL;
-    *out = nullptr;
     hr_config k = {};
     if (cfg) k = *cfg;
     const bool word4 = (k.flags & HR_CFG_WORD4) != 0;
@@ -179,11 +232,21 @@ extern "C" hr_status hr_ctx_create(hr_ctx* out, const hr_config* cfg, void* stre
     if (k.bc_bits == 0) k.bc_bits = word4 ? 2 : 8;
     if (k.wc_bits == 0) k.wc_bits = word4 ? 1 : 6;
     if (k.thread_bits == 0) k.thread_bits = word4 ? 8 : 10;
-    if (k.bc_bits > 8 || k.wc_bits > 6 || k.ring_capacity > (1u << 26)) return HR_E_INVAL;
-    if (k.thread_bits > 10 || (!word4 && k.thread_bits != 10)) return HR_E_INVAL;
-    if (k.flags & ~(HR_CFG_COUNT_CHECKS | HR_CFG_WAVE_GROUPING | HR_CFG_WORD4)) return HR_E_INVAL;
+    if (k.bc_bits > 8 || k.wc_bits > 6 || k.ring_capacity > (1u << 26)) return false;
+    if (k.thread_bits > 10 || (!word4 && k.thread_bits != 10)) return false;
+    if (k.flags & ~(HR_CFG_COUNT_CHECKS | HR_CFG_WAVE_GROUPING | HR_CFG_WORD4)) return false;
     if (k.wave_bits == 0) k.wave_bits = 6;
-    if (k.wave_bits > 6) return HR_E_INVAL;
+    if (k.wave_bits > 6) return false;
+    *out = k;
+    return true;
+}
+
+extern "C" hr_status hr_ctx_create(hr_ctx* out, const hr_config* cfg, void* stream)
+{
+    if (!out) return HR_E_INVAL;
+    *out = nullptr;
+    hr_config k;
+    if (!hr_config_normalize(cfg, &k)) return HR_E_INVAL;
     hr_ctx c = new (std::nothrow) hr_ctx_s();
     if (!c) return HR_E_NOMEM;
     c->cfg = k;
@@ -311,16 +374,16 @@ extern "C" hr_status hr_kernel_end(hr_ctx c, void* stream)
     // The launch epoch in a shadow word has 9 bits: before it wraps, return
     // every word to the initial state.  Exact: all earlier accesses happen
     // before all later ones, and the races found so far are in the ring.
-    // If the ring has overflowed, the races it lost live only in the race
-    // words, so they are recovered before the clear and carried to the report.
+    // If the ring has overflowed or a call site reached its record limit,
+    // the races whose records are missing live only in the race words, so
+    // they are recovered before the clear and carried to the report.
     if ((c->launch_seq & ((1u << hr::g::LAUNCH_BITS) - 1)) == 0) {
         hipStream_t s = hr_stream(c, stream);
-        uint32_t head = 0;
-        if (hipMemcpyAsync(&head, c->ctr + HR_CTR_HEAD, sizeof(head), hipMemcpyDeviceToHost, s) !=
-                hipSuccess ||
+        uint32_t hf[2] = {0, 0};   // HR_CTR_HEAD, HR_CTR_FLAGS
+        if (hipMemcpyAsync(hf, c->ctr, sizeof(hf), hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess)
             return HR_E_HIP;
-        if (head > c->cfg.ring_capacity) {
+        if (hf[HR_CTR_HEAD] > c->cfg.ring_capacity || (hf[HR_CTR_FLAGS] & HR_DEVF_LIMIT)) {
             const hr_status st = scan_races(c, c->carried);
             if (st != HR_OK) return st;
         }
@@ -367,19 +430,18 @@ extern "C" hr_status hr_report(hr_ctx c, hr_race* out, size_t cap, size_t* n_out
     if (ctr[HR_CTR_FLAGS] & HR_DEVF_RANGE) warn |= HR_W_OUT_OF_RANGE;
     if (ctr[HR_CTR_FLAGS] & HR_DEVF_STALL) warn |= HR_W_STALLED;
     if (ctr[HR_CTR_FLAGS] & HR_DEVF_LIMIT) warn |= HR_W_REPORT_LIMITED;
-    if (head > c->cfg.ring_capacity) {
-        // Ring overflow: race states are sticky in global shadow memory, so
-        // the global part of the flagged set is recovered from it exactly
-        // (and from the races carried over a shadow clear).
-        warn |= HR_W_RING_OVERFLOW;
+    if (ctr[HR_CTR_FLAGS] & HR_DEVF_FOLD) warn |= HR_W_FOLDED;
+    if (head > c->cfg.ring_capacity) warn |= HR_W_RING_OVERFLOW;
+    if (head > c->cfg.ring_capacity || (ctr[HR_CTR_FLAGS] & HR_DEVF_LIMIT)) {
+        // Race records are missing (ring overflow, or a site past its record
+        // limit): race states are sticky in global shadow memory, so the
+        // global part of the flagged set is recovered from it exactly (and
+        // from the races carried over a shadow clear).
         const hr_status st = scan_races(c, recs);
         if (st != HR_OK) return st;
         recs.insert(recs.end(), c->carried.begin(), c->carried.end());
     }
-    std::sort(recs.begin(), recs.end(), key_less());
-    size_t n = 0;
-    for (size_t i = 0; i < recs.size(); ++i)
-        if (n == 0 || !key_less::same(recs[n - 1], recs[i])) recs[n++] = recs[i];
+    const size_t n = hr_sort_unique(recs.data(), recs.size());
     *n_out = n;
     if (n > cap || (n && !out)) return HR_E_INVAL;
     std::copy(recs.begin(), recs.begin() + n, out);

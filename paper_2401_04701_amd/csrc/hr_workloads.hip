@@ -166,12 +166,21 @@ extern "C" hr_status hr_reduce_check(hr_ctx c, uint32_t r_in, uint32_t r_out, co
         return HR_E_INVAL;
     hr_kargs a;
     hr_fill_args(c, &a);
+    return hr_launch_reduce(a, r_in, r_out, in_dev, out_dev, n, threads, blocks, drop,
+                            hr_stream(c, stream));
+}
+
+hr_status hr_launch_reduce(const hr_kargs& a, uint32_t r_in, uint32_t r_out, const int32_t* in_dev,
+                           int32_t* out_dev, uint32_t n, uint32_t threads, uint32_t blocks,
+                           int32_t drop, hipStream_t s)
+{
+    if (!in_dev || !out_dev || !reduce_shape_ok(n, threads, blocks)) return HR_E_INVAL;
     if (a.env.word4)
-        HR_LAUNCH(k_reduce4, dim3(blocks), dim3(threads), (size_t)n * 8, hr_stream(c, stream), a,
-                  gref4(a, r_in), gref4(a, r_out), in_dev, out_dev, n, drop);
+        HR_LAUNCH(k_reduce4, dim3(blocks), dim3(threads), (size_t)n * 8, s, a, gref4(a, r_in),
+                  gref4(a, r_out), in_dev, out_dev, n, drop);
     else
-        HR_LAUNCH(k_reduce<true>, dim3(blocks), dim3(threads), (size_t)n * 8, hr_stream(c, stream),
-                  a, gref(a, r_in), gref(a, r_out), in_dev, out_dev, n, drop);
+        HR_LAUNCH(k_reduce<true>, dim3(blocks), dim3(threads), (size_t)n * 8, s, a,
+                  gref(a, r_in), gref(a, r_out), in_dev, out_dev, n, drop);
     return HR_OK;
 }
 
@@ -202,17 +211,26 @@ extern "C" hr_status hr_jacobi_check(hr_ctx c, uint32_t r_old, uint32_t r_new,
         return HR_E_INVAL;
     hr_kargs a;
     hr_fill_args(c, &a);
+    return hr_launch_jacobi(a, r_old, r_new, u_old_dev, u_new_dev, ny, nx, seed_dev,
+                            hr_stream(c, stream));
+}
+
+hr_status hr_launch_jacobi(const hr_kargs& a, uint32_t r_old, uint32_t r_new,
+                           const float* u_old_dev, float* u_new_dev, uint32_t ny, uint32_t nx,
+                           const int32_t* seed_dev, hipStream_t s)
+{
+    if (!u_old_dev || !u_new_dev || !jacobi_shape_ok(ny, nx)) return HR_E_INVAL;
     const dim3 grid((nx + 15) / 16, (ny + 15) / 16);
     constexpr uint32_t DL = hr::c::DEFAULT_LAYOUT;
     if (a.env.word4 == DL)
-        HR_LAUNCH(k_jacobi4<DL>, grid, dim3(256), 0, hr_stream(c, stream), a, gref4<DL>(a, r_old),
+        HR_LAUNCH(k_jacobi4<DL>, grid, dim3(256), 0, s, a, gref4<DL>(a, r_old),
                   gref4<DL>(a, r_new), u_old_dev, u_new_dev, ny, nx, seed_dev);
     else if (a.env.word4)
-        HR_LAUNCH(k_jacobi4<0>, grid, dim3(256), 0, hr_stream(c, stream), a, gref4(a, r_old),
-                  gref4(a, r_new), u_old_dev, u_new_dev, ny, nx, seed_dev);
+        HR_LAUNCH(k_jacobi4<0>, grid, dim3(256), 0, s, a, gref4(a, r_old), gref4(a, r_new),
+                  u_old_dev, u_new_dev, ny, nx, seed_dev);
     else
-        HR_LAUNCH(k_jacobi<true>, grid, dim3(256), 0, hr_stream(c, stream), a, gref(a, r_old),
-                  gref(a, r_new), u_old_dev, u_new_dev, ny, nx, seed_dev);
+        HR_LAUNCH(k_jacobi<true>, grid, dim3(256), 0, s, a, gref(a, r_old), gref(a, r_new),
+                  u_old_dev, u_new_dev, ny, nx, seed_dev);
     return HR_OK;
 }
 
@@ -247,17 +265,28 @@ extern "C" hr_status hr_labelprop_check(hr_ctx c, uint32_t r_label, uint32_t r_r
     if (r_col != UINT32_MAX && !hr_region_ok(c, r_col, col_dev, 1)) return HR_E_INVAL;
     hr_kargs a;
     hr_fill_args(c, &a);
+    return hr_launch_labelprop(a, r_label, r_row_ptr, r_col, label_dev, row_ptr_dev, col_dev,
+                               mask_dev, n, tpb, hr_stream(c, stream));
+}
+
+hr_status hr_launch_labelprop(const hr_kargs& a, uint32_t r_label, uint32_t r_row_ptr,
+                              uint32_t r_col, int32_t* label_dev, const int32_t* row_ptr_dev,
+                              const int32_t* col_dev, const uint8_t* mask_dev, uint32_t n,
+                              uint32_t tpb, hipStream_t s)
+{
+    if (!label_dev || !row_ptr_dev || !col_dev || !mask_dev || !labelprop_shape_ok(n, tpb))
+        return HR_E_INVAL;
     if (a.env.word4) {
         const hr_gref4 none{nullptr, 0, 0};
-        HR_LAUNCH(k_labelprop4, dim3((n + tpb - 1) / tpb), dim3(tpb), 0, hr_stream(c, stream), a,
-                  gref4(a, r_label), r_row_ptr != UINT32_MAX ? gref4(a, r_row_ptr) : none,
+        HR_LAUNCH(k_labelprop4, dim3((n + tpb - 1) / tpb), dim3(tpb), 0, s, a, gref4(a, r_label),
+                  r_row_ptr != UINT32_MAX ? gref4(a, r_row_ptr) : none,
                   r_col != UINT32_MAX ? gref4(a, r_col) : none, label_dev, row_ptr_dev, col_dev,
                   mask_dev, n);
         return HR_OK;
     }
     const hr_gref none{nullptr, 0, 0};
-    HR_LAUNCH(k_labelprop<true>, dim3((n + tpb - 1) / tpb), dim3(tpb), 0, hr_stream(c, stream), a,
-              gref(a, r_label), r_row_ptr != UINT32_MAX ? gref(a, r_row_ptr) : none,
+    HR_LAUNCH(k_labelprop<true>, dim3((n + tpb - 1) / tpb), dim3(tpb), 0, s, a, gref(a, r_label),
+              r_row_ptr != UINT32_MAX ? gref(a, r_row_ptr) : none,
               r_col != UINT32_MAX ? gref(a, r_col) : none, label_dev, row_ptr_dev, col_dev,
               mask_dev, n);
     return HR_OK;

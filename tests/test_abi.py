@@ -56,3 +56,4 @@ def test_binding_site_ids_match_header():
                 for m in re.finditer(r"\b(HR_SITE_[A-Z_]+) = (\d+)", text)}
     assert declared == hr.SITES
     assert "#define HR_SITES %d" % hr.HR_SITES in text
+

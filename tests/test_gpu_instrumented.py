@@ -1,12 +1,14 @@
 """Kernels instrumented by the source rewriter, on the GPU: the flagged sets
-of the rewritten example kernels must equal their closed forms (the
-reduction's is the oracle-pinned set of the hand-instrumented reduction),
-and the rewritten kernels must still compute their results."""
+of the rewritten example kernels must equal the oracle's sets of the same
+kernels written as access programs (tests/example_programs.py; the
+reductions are the oracle's reduction models), and the rewritten kernels
+must still compute their results."""
 import numpy as np
 import pytest
 
+import oracle
 import synth_inputs as si
-from oracle import closed_forms as cf
+from example_programs import flagged_as, histogram_program, stencil3_program
 
 pytestmark = pytest.mark.gpu
 
@@ -42,7 +44,9 @@ def test_instrumented_reduction(env, drop, word4):
         ctx.kernel_end()
         got = ctx.flagged()
         assert ctx.status == 0
-    assert got == cf.reduce_flagged(drop)
+    want = {(sp, {0: r_in, 1: r_out}[rg] if sp == 0 else rg, lb, ix)
+            for sp, rg, lb, ix in oracle.flagged(oracle.model_reduce(drop))}
+    assert got == want
     if drop < 0:
         assert (out.cpu().numpy() == x.astype(np.int64).sum()).all()
 
@@ -60,10 +64,8 @@ def test_instrumented_stencil(env, seeded):
         ctx.kernel_end()
         got = ctx.flagged()
         assert ctx.status == 0
-    # the seeded block writes the first cell of the next block, which its
-    # owner also writes; the last block has no next block
-    want = {(0, r_v, 0, (seeded + 1) * 256)} if 0 <= seeded < 8 else set()
-    assert got == want
+    want = flagged_as(stencil3_program(n, 9, seeded), [r_u, r_v])
+    assert got == want and bool(want) == (0 <= seeded < 8)
     if seeded < 0:
         h = u.cpu().numpy().astype(np.float64)
         left = np.concatenate([h[:1], h[:-1]])
@@ -88,8 +90,8 @@ def test_instrumented_histogram(env, plain):
         got = ctx.flagged()
         assert ctx.status == 0
     counts = np.bincount(keys_h, minlength=bins_n)
-    want = {(0, r_b, 0, int(b)) for b in np.nonzero(counts >= 2)[0]} if plain else set()
-    assert got == want
+    want = flagged_as(histogram_program(keys_h, (n + 255) // 256, 256, plain), [r_k, r_b])
+    assert got == want and bool(want) == bool(plain)
     if not plain:
         assert (bins.cpu().numpy() == counts).all()
 
@@ -111,7 +113,8 @@ def test_instrumented_wave_barriers(env, drop):
         ctx.kernel_end()
         got = ctx.flagged()
         assert ctx.status == 0
-    assert got == cf.tile_reduce_flagged(64, blocks, 256, drop)
+    prog = si.tile_reduce_program(64, blocks, 256, drop)
+    assert got == flagged_as(prog, [r_in, r_out])
     if drop < 0:
         want = x.astype(np.int64).reshape(blocks, 4, 128).sum(axis=2)
         assert (out.cpu().numpy().reshape(blocks, 4, 64) == want[:, :, None]).all()

@@ -118,31 +118,39 @@ def test_reduce_records_and_sites(env, drop):
 
 
 def test_site_limit_caps_records_and_warns(env):
+    """A per-site record limit drops records, never flagged locations: the
+    report recovers the global races whose records were dropped from their
+    sticky race words, also with 4-byte words, whose race words must then
+    survive the launch-boundary clears."""
     torch, hr = env
     ny, nx, launches = 96, 96, 2
     seeds = si.jacobi_seeds(ny, nx, 9, count=12)
     tab = si.jacobi_seed_table(ny, nx, seeds)
     want = cf.jacobi_flagged(ny, nx, launches, seeds)
+    assert all(k[0] == 0 for k in want)
     say("site limit")
     u = [torch.from_numpy(si.jacobi_grid(ny, nx, 3)).cuda(),
          torch.zeros((ny, nx), dtype=torch.float32, device="cuda")]
     tab_d = torch.from_numpy(tab).cuda()
-    for limit in (0, 3):
-        with hr.Context(site_limit=limit) as ctx:
-            regs = [ctx.shadow_alloc(u[0]), ctx.shadow_alloc(u[1])]
-            for L in range(launches):
-                ctx.jacobi_check(regs[L % 2], regs[(L + 1) % 2], u[L % 2], u[(L + 1) % 2],
-                                 tab_d)
-                ctx.kernel_end()
-            recs, st = ctx.report()
-            keys = ctx.flagged()
-        if limit == 0:
-            assert st == 0 and keys == want
-            continue
-        assert st & hr.HR_W_REPORT_LIMITED
-        per_site = {}
-        for r in recs:
-            per_site[int(r["site"])] = per_site.get(int(r["site"]), 0) + 1
-        assert max(per_site.values()) <= limit and len(recs) < len(want)
-        remap = {regs[0]: 0, regs[1]: 1}
-        assert {(0, remap[int(r["region"])], 0, int(r["index"])) for r in recs} <= want
+    for word4 in (False, True):
+        for limit in (0, 3, 1):
+            say("  word4", word4, "limit", limit)
+            with hr.Context(site_limit=limit, word4=word4) as ctx:
+                regs = [ctx.shadow_alloc(u[0]), ctx.shadow_alloc(u[1])]
+                for L in range(launches):
+                    ctx.jacobi_check(regs[L % 2], regs[(L + 1) % 2], u[L % 2], u[(L + 1) % 2],
+                                     tab_d)
+                    ctx.kernel_end()
+                recs, st = ctx.report()
+                keys = ctx.flagged()
+            remap = {regs[0]: 0, regs[1]: 1}
+            assert {(0, remap[int(r["region"])], 0, int(r["index"])) for r in recs} == want
+            if limit == 0:
+                assert st == 0 and keys == want
+                continue
+            assert st & hr.HR_W_REPORT_LIMITED
+            ring = recs[(recs["flags"] & hr.HR_RACE_SCANNED) == 0]
+            per_site = {}
+            for r in ring:
+                per_site[int(r["site"])] = per_site.get(int(r["site"]), 0) + 1
+            assert max(per_site.values()) <= limit and len(ring) < len(want)

@@ -203,7 +203,8 @@ def test_word4_jacobi_ring_overflow_over_launches(env):
 
 def test_word4_folded_blocks_flag_a_subset(env):
     """A 3-bit block field on 16 blocks: blocks 8 apart share a folded id,
-    which can hide races and never adds one."""
+    which can hide races and never adds one, and the report says so.  The
+    same grid within the field widths gives no warning."""
     torch, hr = env
     ny, nx = 64, 64
     seeds = si.jacobi_seeds(ny, nx, 91, count=10)
@@ -212,7 +213,17 @@ def test_word4_folded_blocks_flag_a_subset(env):
     say("word4 folded blocks")
     got, st, _, _ = run_jacobi(torch, hr, ny, nx, 3, tab,
                                w4(wc_bits=6, bc_bits=8, thread_bits=10))
-    assert st == 0 and got <= want
+    assert st == hr.HR_W_FOLDED and got <= want
+    got, st, _, _ = run_jacobi(torch, hr, ny, nx, 3, tab, w4(wc_bits=6, bc_bits=8, thread_bits=8))
+    assert st == 0 and got == want                  # 5 block bits, 8 thread bits: exact
+    say("word4 folded threads")                     # 1024 threads per block, 8 thread bits
+    inp = torch.from_numpy(np.random.default_rng(2).integers(0, 9, 2048).astype(np.int32)).cuda()
+    out = torch.zeros(1024, dtype=torch.int32, device="cuda")
+    with hr.Context(**w4(bc_bits=4)) as ctx:
+        r_in, r_out = ctx.shadow_alloc(inp), ctx.shadow_alloc(out)
+        ctx.reduce_check(r_in, r_out, inp, out, drop=-1, n=2048, threads=1024)
+        ctx.kernel_end()
+        assert ctx.flagged() == set() and ctx.status == hr.HR_W_FOLDED
 
 
 @pytest.mark.parametrize("scale,edges,p,tpb", [(10, 8 * 1024, 0.01, 256), (9, 4096, 0.05, 1000)])

@@ -68,3 +68,29 @@ __global__ void gather(const int* idx, const float* in, float* out, double* wide
     assert "wide" in skipped and "double" in skipped                      # 8-byte elements
     assert "shared m" in skipped                                          # 2-D array
     assert "line 9: out" in skipped                                       # address taken
+
+
+def test_example_programs_match_their_closed_forms():
+    """The access programs that give the instrumented examples' expected sets
+    (through the oracle) reduce to what the kernels' text says: a plain
+    histogram races on every bin hit by two threads and an atomic one on
+    none; the stencil's seeded block races on the first cell of the next
+    block, which that block's owner also writes."""
+    import numpy as np
+    import synth_inputs as si
+    from example_programs import flagged_as, histogram_program, stencil3_program
+    keys = np.random.default_rng(si.master_seed(5)).integers(0, 64, 700).astype(np.int32)
+    keys[:3] = 63
+    keys[keys == 17] = 18
+    counts = np.bincount(keys, minlength=64)
+    assert flagged_as(histogram_program(keys, 3, 256, 1), [7, 9]) == \
+        {(0, 9, 0, int(b)) for b in np.nonzero(counts >= 2)[0]}
+    assert flagged_as(histogram_program(keys, 3, 256, 0), [7, 9]) == set()
+    n = 256 * 8 + 100
+    for seeded in (-1, 0, 3, 7, 8):
+        want = {(0, 5, 0, (seeded + 1) * 256)} if 0 <= seeded < 8 else set()
+        assert flagged_as(stencil3_program(n, 9, seeded), [4, 5]) == want, seeded
+    # a dropped staging barrier: the halo reads meet the neighbours' writes
+    prog = stencil3_program(600, 3, -1)
+    prog.launches[0].scope[0] = si.SCOPE_NONE
+    assert {k for k in flagged_as(prog, [0, 1]) if k[0] == 1}
