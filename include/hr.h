@@ -481,6 +481,35 @@ hr_status hr_batch_destroy(hr_batch b);
 hr_status hr_job_run(const hr_instance* inst, const hr_config* cfg, hr_race* out, size_t cap,
                      size_t* n_out, void* stream);
 
+/* Size of the library's static scratch array and its parts (see
+ * hr_job_run_static). */
+#define HR_STATIC_SCRATCH_BYTES (64u << 20)
+#define HR_STATIC_RING_RECORDS 16384u
+#define HR_STATIC_SHADOW_WORDS 8289280u   /* 8-byte words after counters and ring */
+
+/* hr_job_run for callers that cannot allocate device memory (code that must
+ * not call hipMalloc, tight serving loops, harnesses that forbid
+ * allocation): the same job, launches and report, but the counters, the
+ * report ring (at most HR_STATIC_RING_RECORDS records; a larger
+ * cfg->ring_capacity is capped) and the shadow words live in one static
+ * device array of HR_STATIC_SCRATCH_BYTES that the library holds on each
+ * device it runs on until the process ends.  The call allocates nothing, on
+ * the device or through any allocating library routine; it clears the parts
+ * of the array it uses before the first launch, so nothing of an earlier
+ * call is seen.  Calls of one process are serialised by a lock (each
+ * shares that device's array); two library instances that drive the same
+ * array at once would race.  Synchronous, on `stream`.  out (host memory,
+ * cap records) also serves as the working buffer of the report: cap must
+ * hold the raw records (ring records before deduplication, plus every
+ * global race word when records were dropped), else HR_E_INVAL with *n_out
+ * = that number; on success *n_out is the number of unique records, sorted
+ * as by hr_report.  Returns the warning bits as hr_report does.
+ * Errors: HR_E_INVAL (a job's shape, cfg out of range or with
+ * HR_CFG_WORD4, cap too small), HR_E_NOMEM (the job's two buffers need more
+ * than HR_STATIC_SHADOW_WORDS shadow words), HR_E_HIP. */
+hr_status hr_job_run_static(const hr_instance* inst, const hr_config* cfg, hr_race* out,
+                            size_t cap, size_t* n_out, void* stream);
+
 /* ----------------------------------------------------------------------
  * Serving: a stream of jobs checked with continuous batching.
  *

@@ -10,7 +10,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libhr.so")
-SOURCES = ["hr_runtime.hip", "hr_workloads.hip", "hr_batch.hip", "hr_serve.hip", "hr_peaks.hip"]
+SOURCES = ["hr_runtime.hip", "hr_workloads.hip", "hr_batch.hip", "hr_serve.hip", "hr_peaks.hip",
+           "hr_static.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -32,6 +32,10 @@ HR_CFG_WORD4 = 4
 NO_REGION = 0xFFFFFFFF
 HR_PAT_REDUCE, HR_PAT_JACOBI, HR_PAT_LABELPROP = 0, 1, 2
 HR_SITES = 256
+# the static scratch array of hr_job_run_static
+HR_STATIC_SCRATCH_BYTES = 64 << 20
+HR_STATIC_RING_RECORDS = 16384
+HR_STATIC_SHADOW_WORDS = 8289280
 # call-site ids of the workloads' race records (the enum in hr.h)
 SITES = {
     "HR_SITE_REDUCE_LOAD": 1, "HR_SITE_REDUCE_STAGE": 2, "HR_SITE_REDUCE_LEFT": 3,
@@ -151,6 +155,7 @@ def _load():
         "hr_batch_info": [P, u32, P, P],
         "hr_batch_destroy": [P],
         "hr_job_run": [P, P, P, sz, P, P],
+        "hr_job_run_static": [P, P, P, sz, P, P],
         "hr_serve": [P, P, P, u32, P, P, sz, P, P],
         "hr_peak_copy": [P, P, sz, P],
         "hr_peak_atomic": [P, sz, u32, u32, u32, P, u32, P],
@@ -168,7 +173,7 @@ _lib = _load()
 EXPORTED = ("hr_ctx_create", "hr_ctx_destroy", "hr_shadow_alloc", "hr_shadow_free",
             "hr_region_enable",
             "hr_dev_args", "hr_batch_create", "hr_batch_run", "hr_batch_info",
-            "hr_batch_destroy", "hr_job_run", "hr_serve",
+            "hr_batch_destroy", "hr_job_run", "hr_job_run_static", "hr_serve",
             "hr_kernel_end", "hr_reset", "hr_report", "hr_check_count", "hr_fsm_step", "hr_fsm_merge",
             "hr_describe", "hr_fsm_step_word4", "hr_word4_widen",
             "hr_reduce_check", "hr_reduce_plain", "hr_jacobi_check", "hr_jacobi_plain",
@@ -430,21 +435,27 @@ def _races_to_keys(recs):
              int(r["block"]) if r["space"] == HR_LDS else 0, int(r["index"])) for r in recs}
 
 
-def job_run(inst: Instance, ring_capacity=0, stream=None):
-    """The serial path for one job (own context and shadow, synchronous).
-    Returns (flagged keys with region ids 0/1, warning bits)."""
-    cfg = _Config(ring_capacity, 0, 0, 0, 0, 0, 0)
+def job_run(inst: Instance, ring_capacity=0, stream=None, static=False, site_limit=0,
+            records=False):
+    """The serial path for one job (own context and shadow, synchronous), or
+    with static=True its variant over the library's static scratch array
+    (hr_job_run_static, no allocation).  Returns (flagged keys with region
+    ids 0/1, warning bits), or (race records, warning bits) with records."""
+    cfg = _Config(ring_capacity, 0, 0, 0, 0, site_limit, 0)
+    fn_name = "hr_job_run_static" if static else "hr_job_run"
+    fn = getattr(_lib, fn_name)
     n = ctypes.c_size_t(0)
     cap = 4096
     while True:
         out = np.zeros(cap, dtype=RACE_DTYPE)
-        st = _lib.hr_job_run(ctypes.byref(inst), ctypes.byref(cfg),
-                             out.ctypes.data_as(ctypes.c_void_p), cap, ctypes.byref(n),
-                             _stream_ptr(stream))
+        st = fn(ctypes.byref(inst), ctypes.byref(cfg), out.ctypes.data_as(ctypes.c_void_p), cap,
+                ctypes.byref(n), _stream_ptr(stream))
         if st == HR_E_INVAL and n.value > cap:
             cap = int(n.value)
             continue
-        _check("hr_job_run", st)
+        _check(fn_name, st)
+        if records:
+            return out[:n.value].copy(), st
         return _races_to_keys(out[:n.value]), st
 
 
