@@ -607,6 +607,25 @@ def main():
     assert st4 == 0 and keys(recs4) == keys(recs)
     launch4_ms = [a.elapsed_time(b) for a, b in ev4]
     clear4_ms = [a.elapsed_time(b) for a, b in cev4]
+    ev4.clear()
+    cev4.clear()
+
+    # The same job under each shadow map the autotuner knows (row-major and
+    # tiles): per-launch time and the flagged set, which must not change.
+    from paper_2401_04701_amd import tune
+    map_ms, map_same = {}, True
+    for tile in tune.TILES:
+        ctxm = hr.Context()
+        regsm = [ctxm.shadow_alloc(u[0], tile=tile), ctxm.shadow_alloc(u[1], tile=tile)]
+        checked_step(None, ctxm, regsm)
+        evm = []
+        for _ in range(3):
+            recsm, stm = checked_step(evm, ctxm, regsm)
+        torch.cuda.synchronize()
+        ctxm.close()
+        map_same &= stm == 0 and keys(recsm) == keys(recs)
+        map_ms[tune.tile_name(tile)] = pct([a.elapsed_time(b) for a, b in evm], 50)
+        evm.clear()
 
     avg_launch_s = float(np.mean(launch_ms)) * 1e-3
     alg = algorithmic_bytes_per_launch(NY, NX)
@@ -654,6 +673,9 @@ def main():
                        "p50_clear_ms": pct(clear4_ms, 50),
                        "shadow_bytes": 2 * NY * NX * 4, "shadow_bytes_8byte": 2 * NY * NX * 8,
                        "flagged": len(recs4), "same_flagged_set": True}
+    result["shadow_map"] = {"headline_map": "rowmajor", "p50_launch_ms": map_ms,
+                            "fastest": min(map_ms, key=map_ms.get),
+                            "same_flagged_set": bool(map_same)}
     if not args.no_peaks:
         peaks = measure_peaks(torch, hr, stream)
         g_rate = n_g / avg_launch_s

@@ -100,7 +100,10 @@ typedef struct {
                                 1..10; 0: 8.  The block field gets the rest,
                                 27 - wc_bits - bc_bits - thread_bits bits
                                 (3 to 22; 16 with the defaults). */
-    uint32_t pad;
+    uint32_t coalesce_width; /* with HR_CFG_WAVE_GROUPING: lanes are grouped
+                                within aligned segments of this many lanes
+                                (a power of two, 2..64); 0: 64, the whole
+                                wave.  Must be 0 without the flag. */
 } hr_config;
 
 #define HR_SITES 256   /* call-site counters of the report limit */
@@ -182,7 +185,9 @@ typedef struct {
  * copied.  *out receives the context, or NULL on error.
  * Errors: HR_E_INVAL (out NULL, cfg out of range: unknown flags, bc_bits > 8,
  * wc_bits > 6, wave_bits > 6, ring_capacity > 2^26, thread_bits set without
- * HR_CFG_WORD4 or above 10), HR_E_NOMEM (a device allocation failed),
+ * HR_CFG_WORD4 or above 10, coalesce_width not 0 or a power of two in
+ * 2..64, or set without HR_CFG_WAVE_GROUPING), HR_E_NOMEM (a device
+ * allocation failed),
  * HR_E_HIP. */
 hr_status hr_ctx_create(hr_ctx* out, const hr_config* cfg, void* stream);
 
@@ -204,6 +209,29 @@ hr_status hr_ctx_destroy(hr_ctx c);
  * in use), HR_E_NOMEM (allocation failed or shadow budget exceeded). */
 hr_status hr_shadow_alloc(hr_ctx c, const void* data_dev, size_t bytes, uint32_t elem_bytes,
                           uint32_t* region_out);
+
+/* Largest tile side of a tiled shadow map, log2 (tiles up to 16 x 16). */
+#define HR_TILE_LOG2_MAX 4u
+
+/* Monitor a rows x cols row-major array of 4-byte elements at data_dev with
+ * a tiled address-to-shadow map.  The paper keeps one shadow entry per
+ * monitored element (Sec. III-A, Fig. 2) but leaves where it lives open;
+ * here the shadow words of each tile of 2^tile_w_log2 columns by
+ * 2^tile_h_log2 rows are consecutive, tiles in row-major order, so that a
+ * 2-D access pattern whose lanes walk down a column (a stencil's west or
+ * east halo) touches few shadow cache lines.  Element (r, c) has its word at
+ * ((r >> th) * ceil(cols / 2^tw) + (c >> tw)) << (tw + th)
+ *   | (r mod 2^th) << tw | (c mod 2^tw)
+ * (tw, th the two logs); the array is padded to whole tiles in shadow memory
+ * only.  Both logs 0 give the row-major map of hr_shadow_alloc.  Element
+ * indices (hooks, race records) stay row-major: r * cols + c.  Owned by the
+ * context and cleared to the initial state, as hr_shadow_alloc; the 2-D
+ * workloads (hr_jacobi_check) need cols equal to their row width.
+ * Errors: HR_E_INVAL (elem_bytes != 4, a zero side, a tile log above
+ * HR_TILE_LOG2_MAX, 16 regions in use), HR_E_NOMEM. */
+hr_status hr_shadow_alloc_2d(hr_ctx c, const void* data_dev, uint32_t rows, uint32_t cols,
+                             uint32_t elem_bytes, uint32_t tile_w_log2, uint32_t tile_h_log2,
+                             uint32_t* region_out);
 
 /* Switch the monitoring of a region off (on = 0) or back on, for the
  * kernels launched afterwards (the paper lets a tool enable or disable the
@@ -447,8 +475,15 @@ typedef struct {
                              1: two workers per compute unit, 64 registers */
     uint32_t coalesce;    /* wave grouping of the lanes of one hook instruction
                              that hit the same shadow word, at data-dependent
-                             sites: 0 the context's setting, 1 off, 2 on; the
+                             sites: 0 the context's setting, 1 off, or the
+                             coalescing width (a power of two, 2..64: lanes
+                             group within aligned segments of that many); the
                              result is the same either way */
+    uint32_t tile;        /* shadow map of the stencil jobs' grids: tw | th << 4
+                             (tiles of 2^tw columns by 2^th rows, each side at
+                             most 2^HR_TILE_LOG2_MAX; 0: row-major), as
+                             hr_shadow_alloc_2d; it stays for later runs and
+                             reports.  The result is the same for every map. */
 } hr_batch_tuning;
 
 /* Prepare a batch: allocate one shadow arena for every job (counted against

@@ -172,8 +172,10 @@ hr_inst_dev hr_make_inst_dev(const hr_instance& in, const size_t elems[2], uint6
     d.lds_words = in.pattern == HR_PAT_REDUCE   ? 2 * in.n
                   : in.pattern == HR_PAT_JACOBI ? 2 * JACOBI_TILE_WORDS
                                                 : 0;
-    d.g0 = hr_gref{sh0, sh0 ? elems[0] : 0, r0};
-    d.g1 = hr_gref{sh1, sh1 ? elems[1] : 0, r1};
+    // row-major maps; a jacobi job's rows are nx elements wide
+    const uint32_t cols = in.pattern == HR_PAT_JACOBI ? in.n : 0u;
+    d.g0 = hr_gref{sh0, sh0 ? elems[0] : 0, r0, hr_lay_rows(cols)};
+    d.g1 = hr_gref{sh1, sh1 ? elems[1] : 0, r1, hr_lay_rows(cols)};
     d.p0 = in.data[0];
     d.p1 = const_cast<void*>(in.data[1]);
     d.p2 = in.data[2];
@@ -184,6 +186,9 @@ hr_inst_dev hr_make_inst_dev(const hr_instance& in, const size_t elems[2], uint6
 struct hr_batch_s {
     hr_ctx ctx;
     uint32_t n_inst;
+    std::vector<hr_inst_dev> hd;          // host copy of the job table
+    std::vector<uint32_t> rows;           // rows of each job's 2-D regions (jacobi), else 0
+    uint32_t tile = 0;                    // shadow map of the jacobi jobs (hr_batch_tuning)
     uint32_t arena;                       // allocation holding every instance's shadow
     hr_inst_dev* d_inst = nullptr;
     uint64_t* d_items[2] = {nullptr, nullptr};   // phase-major, largest-first orders
@@ -214,12 +219,20 @@ extern "C" hr_status hr_batch_create(hr_ctx c, hr_instance* inst, uint32_t n_ins
     if (!c || !inst || !out || n_inst == 0 || n_inst >= (1u << 24)) return HR_E_INVAL;
     *out = nullptr;
     if (c->cfg.flags & HR_CFG_WORD4) return HR_E_INVAL;   // the arena holds 8-byte words
-    std::vector<size_t> el(2 * (size_t)n_inst);
+    std::vector<size_t> el(2 * (size_t)n_inst), words(2 * (size_t)n_inst);
     size_t total = 0, lds = 0;
     for (uint32_t i = 0; i < n_inst; ++i) {
         size_t lb = 0;
         if (!hr_instance_shape(inst[i], &el[2 * i], &lb)) return HR_E_INVAL;
-        total += el[2 * i] + el[2 * i + 1];
+        for (int k = 0; k < 2; ++k) words[2 * i + k] = el[2 * i + k];
+        if (inst[i].pattern == HR_PAT_JACOBI) {
+            // room for every tiled shadow map: both sides padded to whole
+            // tiles of the largest side
+            constexpr size_t T = size_t(1) << HR_TILE_LOG2_MAX;
+            const size_t padded = ((inst[i].ny + T - 1) / T * T) * ((inst[i].n + T - 1) / T * T);
+            words[2 * i] = words[2 * i + 1] = padded;
+        }
+        total += words[2 * i] + words[2 * i + 1];
         lds = std::max(lds, lb);
     }
     hr_batch b = new (std::nothrow) hr_batch_s();
@@ -235,19 +248,22 @@ extern "C" hr_status hr_batch_create(hr_ctx c, hr_instance* inst, uint32_t n_ins
         return st;
     }
     b->arena = arena;
-    std::vector<hr_inst_dev> hd(n_inst);
+    std::vector<hr_inst_dev>& hd = b->hd;
+    hd.resize(n_inst);
+    b->rows.assign(n_inst, 0u);
     uint64_t* base = c->allocs[arena].mem;
     size_t off = 0;
     uint32_t done_off = 0;
     for (uint32_t i = 0; i < n_inst; ++i) {
         hr_instance& in = inst[i];
         in.region[0] = in.region[1] = UINT32_MAX;
+        if (in.pattern == HR_PAT_JACOBI) b->rows[i] = in.ny;
         uint64_t* sh[2] = {nullptr, nullptr};
         for (int k = 0; k < 2; ++k) {
             if (!el[2 * i + k]) continue;
             sh[k] = base + off;
             in.region[k] = hr_new_region(c, in.data[k], el[2 * i + k], sh[k], arena);
-            off += el[2 * i + k];
+            off += words[2 * i + k];
         }
         hd[i] = hr_make_inst_dev(in, &el[2 * i], sh[0], sh[1], in.region[0], in.region[1],
                                  done_off);
@@ -325,12 +341,36 @@ extern "C" hr_status hr_batch_run(hr_batch b, const hr_batch_tuning* tune, void*
     if (!b) return HR_E_INVAL;
     hr_batch_tuning t = {};
     if (tune) t = *tune;
-    if (t.order > 1 || t.variant > 1 || t.coalesce > 2) return HR_E_INVAL;
+    if (t.order > 1 || t.variant > 1) return HR_E_INVAL;
+    if (t.coalesce > 1 && !hr_coalesce_width_ok(t.coalesce)) return HR_E_INVAL;
     const uint32_t cap = b->max_workers[t.variant];
     const uint32_t workers = t.workers ? std::min(t.workers, cap) : cap;
     const uint32_t spin = t.spin_limit ? t.spin_limit : (1u << 24);
+    const uint32_t tw = t.tile & 15u, th = (t.tile >> 4) & 15u;
+    if ((t.tile >> 8) || tw > HR_TILE_LOG2_MAX || th > HR_TILE_LOG2_MAX) return HR_E_INVAL;
     hr_ctx c = b->ctx;
     hipStream_t s = hr_stream(c, stream);
+    if (t.tile != b->tile) {
+        // Another shadow map for the jacobi jobs: their descriptors and
+        // regions take it (the arena has room for the padding), once the
+        // runs before that read the old table have finished.
+        for (uint32_t i = 0; i < b->n_inst; ++i) {
+            if (!b->rows[i]) continue;
+            hr_inst_dev& d = b->hd[i];
+            const uint32_t nx = d.n;
+            const hr_lay tiled{nx, (nx + (1u << tw) - 1u) >> tw, tw, th};
+            d.g0.lay = d.g1.lay = t.tile ? tiled : hr_lay_rows(nx);
+            for (uint32_t r : {d.g0.id, d.g1.id}) {
+                c->reg[r].lay = t.tile ? tiled : hr_lay{};
+                c->reg[r].rows = b->rows[i];
+            }
+        }
+        if (hipStreamSynchronize(s) != hipSuccess ||
+            hipMemcpy(b->d_inst, b->hd.data(), sizeof(hr_inst_dev) * b->n_inst,
+                      hipMemcpyHostToDevice) != hipSuccess)
+            return HR_E_HIP;
+        b->tile = t.tile;
+    }
     // every run starts from initial shadow and empty phase counters
     if (hr_fill64(c->allocs[b->arena].mem, c->allocs[b->arena].words, s) != hipSuccess ||
         hr_fill32(b->d_done, b->n_done, s) != hipSuccess ||
@@ -338,7 +378,7 @@ extern "C" hr_status hr_batch_run(hr_batch b, const hr_batch_tuning* tune, void*
         return HR_E_HIP;
     hr_env e = hr_make_env(c);
     e.site_limit = 0;   // site ids are per job; the limit does not apply to a batch
-    if (t.coalesce) e.group = t.coalesce == 2 ? 1u : 0u;
+    if (t.coalesce) e.group = t.coalesce == 1 ? 0u : t.coalesce;
     if (t.variant == 0)
         HR_LAUNCH(k_batch_wide, dim3(workers), dim3(1024), b->lds_bytes, s, e, b->d_inst,
                   b->d_items[t.order], b->n_items, b->d_cursor, b->d_done, spin);

@@ -64,20 +64,73 @@ struct hr_env {
     uint32_t launch_seq;                // launch sequence number (reports)
     uint32_t bc_max;                    // last valid block-clock value
     uint32_t wc_max;                    // last valid wave-clock value
-    uint32_t group;                     // wave grouping at data-dependent hook sites
+    uint32_t group;                     // wave grouping at data-dependent hook sites:
+                                        // 0 off, else lanes per grouping segment
     uint32_t site_limit;                // race records per call site; 0: no limit
     uint32_t wave_bits;                 // 6: waves synchronize; s < 6: tiles of 2^s lanes
     uint32_t word4;                     // 0: 8-byte global words; else the 4-byte
                                         // word layout (hr::c::layout)
 };
 
+// Shadow layout of a region (the address-to-shadow map): the element at row
+// r, column c of a row-major array `cols` elements wide has its shadow word
+// at offset
+//   ((r >> th) * tiles_x + (c >> tw)) << (tw + th)      (its tile)
+//   | (r & (2^th - 1)) << tw | (c & (2^tw - 1))          (its place in the tile)
+// so a tile of 2^tw x 2^th elements owns consecutive shadow words.  tw = th
+// = 0 is the row-major identity map (offset = element index); a 1-D region
+// is one row.
+struct hr_lay {
+    uint32_t cols;      // elements per row
+    uint32_t tiles_x;   // tiles per row of tiles: ceil(cols / 2^tw)
+    uint32_t tw, th;    // log2 of the tile's width and height
+};
+
+__host__ __device__ __forceinline__ uint64_t hr_lay_off2(const hr_lay& L, uint32_t r, uint32_t c)
+{
+    return ((((uint64_t)(r >> L.th) * L.tiles_x + (c >> L.tw)) << (L.tw + L.th)) |
+            ((uint64_t)(r & ((1u << L.th) - 1u)) << L.tw) | (uint64_t)(c & ((1u << L.tw) - 1u)));
+}
+
+// The shadow offset of element `index` (a division by cols for tiled maps).
+__host__ __device__ __forceinline__ uint64_t hr_lay_off(const hr_lay& L, uint64_t index)
+{
+    if ((L.tw | L.th) == 0) return index;
+    const uint64_t r = index / L.cols;
+    return hr_lay_off2(L, (uint32_t)r, (uint32_t)(index - r * L.cols));
+}
+
+// The element index whose shadow word sits at offset `off` under map L of an
+// array of `rows` rows, or UINT64_MAX for a word of a tile's padding.
+__host__ __device__ __forceinline__ uint64_t hr_lay_index(const hr_lay& L, uint32_t rows,
+                                                          uint64_t off)
+{
+    if ((L.tw | L.th) == 0) return off;
+    const uint32_t tb = L.tw + L.th;
+    const uint64_t tile = off >> tb, in = off & ((1ull << tb) - 1u);
+    const uint64_t r = ((tile / L.tiles_x) << L.th) | (in >> L.tw);
+    const uint64_t c = ((tile % L.tiles_x) << L.tw) | (in & ((1u << L.tw) - 1u));
+    return (r < rows && c < L.cols) ? r * L.cols + c : UINT64_MAX;
+}
+
+// Shadow words of a region of `elems` elements (`rows` rows) under map L:
+// a tiled map pads the array to whole tiles.
+__host__ __device__ __forceinline__ uint64_t hr_lay_words(const hr_lay& L, uint32_t rows,
+                                                          uint64_t elems)
+{
+    if ((L.tw | L.th) == 0) return elems;
+    const uint64_t tile_rows = (rows + (1u << L.th) - 1u) >> L.th;
+    return (tile_rows * L.tiles_x) << (L.tw + L.th);
+}
+
 // Plain-old-data block handed to instrumented kernels by value.
 struct hr_kargs {
     hr_env env;
-    uint64_t* shadow[HR_MAX_REGIONS];   // shadow words, one per element (4-byte
+    uint64_t* shadow[HR_MAX_REGIONS];   // shadow words of each region (4-byte
                                         // words at this address when env.word4)
     uint64_t n_elems[HR_MAX_REGIONS];   // elements per region (0: unused)
     void* data[HR_MAX_REGIONS];         // monitored buffer of each region
+    hr_lay lay[HR_MAX_REGIONS];         // address-to-shadow map of each region
 };
 
 // Per-thread checker state, kept in registers.
@@ -220,6 +273,10 @@ __device__ __noinline__ uint64_t hr_fold(uint64_t* sp, uint64_t mine, uint64_t l
 // leave a note for the owner.  Lanes whose bucket went to another word just
 // update alone, so the grouping never changes the result, only the number
 // of atomics.
+//
+// Coalescing width: lanes group only within aligned segments of `width`
+// lanes (a power of two, 2..64): each segment has its own `width` buckets.
+// Narrower segments do less work per hook and merge less.
 #define HR_GROUP_SLOTS 1024   // one byte per thread of a block, per table
 #define HR_NO_LANE 64u
 
@@ -230,7 +287,7 @@ __device__ __forceinline__ uint32_t hr_flat_thread()
 
 // Returns the lane of another member for an owner (HR_NO_LANE if alone) and
 // sets *member for lanes whose update the owner makes.
-__device__ __forceinline__ uint32_t hr_group(uint64_t word_addr, bool* member)
+__device__ __forceinline__ uint32_t hr_group(uint64_t word_addr, uint32_t width, bool* member)
 {
     const uint32_t lane = __lane_id();
     const uint64_t act = __ballot(1);
@@ -244,7 +301,9 @@ __device__ __forceinline__ uint32_t hr_group(uint64_t word_addr, bool* member)
     __shared__ uint8_t owner_of[HR_GROUP_SLOTS];
     __shared__ uint8_t partner[HR_GROUP_SLOTS];
     const uint32_t base = hr_flat_thread() & ~63u;
-    const uint32_t h = (key ^ (key >> 6) ^ (key >> 12) ^ (uint32_t)(word_addr >> 32)) & 63u;
+    const uint32_t h = ((lane & ~(width - 1u)) |
+                        ((key ^ (key >> 6) ^ (key >> 12) ^ (uint32_t)(word_addr >> 32)) &
+                         (width - 1u))) & 63u;
     // Relaxed wave-scope atomics keep the compiler from forwarding a lane's
     // own store; the hardware runs a wave's LDS operations in issue order.
     __hip_atomic_store(&partner[base + lane], (uint8_t)HR_NO_LANE, __ATOMIC_RELAXED,
@@ -287,8 +346,9 @@ __device__ __noinline__ void hr_race8(hr_race_rec* ring, uint32_t* ctr, uint32_t
 }
 
 // Check one access of kind KIND (0 read, 1 write, 2 atomic) to element
-// `index` of a global region whose shadow is shadow[0..n); `region` is the
-// id written into a race record.  GROUP marks a call site whose addresses
+// `index` (< n) of a global region whose shadow word for that element is
+// shadow[off] (off: the region's address-to-shadow map applied to index);
+// `region` is the id written into a race record.  GROUP marks a call site whose addresses
 // depend on data (a gather or scatter); there the wave grouping runs when
 // the context enables it.  Call sites with lane-affine addresses (the lanes
 // of a wave touch distinct words by construction) never group.
@@ -336,7 +396,7 @@ __device__ __forceinline__ void hr_settle(const hr_env& e, const hr_thread& t, u
 template <int KIND, bool GROUP = false, bool PRE = false>
 __device__ __forceinline__ void hr_check(const hr_env& e, const hr_thread& t, uint64_t* shadow,
                                          uint64_t n, uint32_t region, uint64_t index,
-                                         uint32_t site = 0, uint64_t pre = 0)
+                                         uint64_t off, uint32_t site = 0, uint64_t pre = 0)
 {
     if (t.enabled != 1 || !shadow) return;      // thread switched off / region not monitored
     hr_count(e, t);
@@ -345,12 +405,12 @@ __device__ __forceinline__ void hr_check(const hr_env& e, const hr_thread& t, ui
         return;
     }
     constexpr uint32_t k = KIND == 0 ? hr::CL_R : (KIND == 2 ? hr::CL_A : hr::CL_X);
-    uint64_t* sp = shadow + index;
+    uint64_t* sp = shadow + off;
     const uint64_t wm = hr::g::group_mask(e.wave_bits);
     uint32_t other = HR_NO_LANE;
     if (GROUP && e.group && e.wave_bits == 6) {     // lanes of one tile only when tiles are waves
         bool member;
-        other = hr_group((uint64_t)sp >> 3, &member);
+        other = hr_group((uint64_t)sp >> 3, e.group, &member);
         if (member) return;
     }
     const uint64_t old =
@@ -379,7 +439,7 @@ struct hr_pend {
 template <int KIND, bool PRE = false>
 __device__ __forceinline__ hr_pend hr_check_issue(const hr_env& e, const hr_thread& t,
                                                   uint64_t* shadow, uint64_t n, uint64_t index,
-                                                  uint64_t pre = 0)
+                                                  uint64_t off, uint64_t pre = 0)
 {
     hr_pend p{nullptr, 0, 0, 0};
     if (t.enabled != 1 || !shadow) return p;
@@ -389,7 +449,7 @@ __device__ __forceinline__ hr_pend hr_check_issue(const hr_env& e, const hr_thre
         return p;
     }
     constexpr uint32_t k = KIND == 0 ? hr::CL_R : (KIND == 2 ? hr::CL_A : hr::CL_X);
-    uint64_t* sp = shadow + index;
+    uint64_t* sp = shadow + off;
     const uint64_t old =
         PRE ? pre : __hip_atomic_load(sp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const uint64_t nw = hr::g::step(old, t.gid, k, hr::g::group_mask(e.wave_bits));
@@ -410,12 +470,12 @@ __device__ __forceinline__ void hr_check_settle(const hr_env& e, const hr_thread
 }
 
 // The early load of hr_check<..., PRE = true>: the shadow word of element
-// `index`, or 0 when the check will not use it.
+// `index` (at shadow[off]), or 0 when the check will not use it.
 __device__ __forceinline__ uint64_t hr_check_load(const hr_thread& t, uint64_t* shadow,
-                                                  uint64_t n, uint64_t index)
+                                                  uint64_t n, uint64_t index, uint64_t off)
 {
     return (t.enabled == 1 && shadow && index < n)
-               ? __hip_atomic_load(shadow + index, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+               ? __hip_atomic_load(shadow + off, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
                : 0;
 }
 
@@ -498,7 +558,7 @@ __device__ __forceinline__ void hr_settle4(const hr_env& e, const hr_thread& t, 
 template <int KIND, bool GROUP = false, bool PRE = false, uint32_t LAY = 0>
 __device__ __forceinline__ void hr_check4(const hr_env& e, const hr_thread& t, uint32_t* shadow,
                                           uint64_t n, uint32_t region, uint64_t index,
-                                          uint32_t site = 0, uint32_t pre = 0)
+                                          uint64_t off, uint32_t site = 0, uint32_t pre = 0)
 {
     if (t.enabled != 1 || !shadow) return;
     hr_count(e, t);
@@ -507,13 +567,13 @@ __device__ __forceinline__ void hr_check4(const hr_env& e, const hr_thread& t, u
         return;
     }
     constexpr uint32_t k = KIND == 0 ? hr::CL_R : (KIND == 2 ? hr::CL_A : hr::CL_X);
-    uint32_t* sp = shadow + index;
+    uint32_t* sp = shadow + off;
     const uint32_t lay = LAY ? LAY : e.word4;
     const uint64_t wm = hr::g::group_mask(e.wave_bits);
     uint32_t other = HR_NO_LANE;
     if (GROUP && e.group && e.wave_bits == 6) {
         bool member;
-        other = hr_group((uint64_t)sp >> 2, &member);
+        other = hr_group((uint64_t)sp >> 2, e.group, &member);
         if (member) return;
     }
     const uint32_t wm4 = hr::c::group_mask(e.wave_bits, lay);
@@ -540,7 +600,7 @@ struct hr_pend4 {
 template <int KIND, bool PRE = false, uint32_t LAY = 0>
 __device__ __forceinline__ hr_pend4 hr_check4_issue(const hr_env& e, const hr_thread& t,
                                                     uint32_t* shadow, uint64_t n, uint64_t index,
-                                                    uint32_t pre = 0)
+                                                    uint64_t off, uint32_t pre = 0)
 {
     hr_pend4 p{nullptr, 0, 0, 0};
     if (t.enabled != 1 || !shadow) return p;
@@ -550,7 +610,7 @@ __device__ __forceinline__ hr_pend4 hr_check4_issue(const hr_env& e, const hr_th
         return p;
     }
     constexpr uint32_t k = KIND == 0 ? hr::CL_R : (KIND == 2 ? hr::CL_A : hr::CL_X);
-    uint32_t* sp = shadow + index;
+    uint32_t* sp = shadow + off;
     const uint32_t old =
         PRE ? pre : __hip_atomic_load(sp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const uint32_t lay = LAY ? LAY : e.word4;
@@ -573,10 +633,10 @@ __device__ __forceinline__ void hr_check4_settle(const hr_env& e, const hr_threa
 }
 
 __device__ __forceinline__ uint32_t hr_check4_load(const hr_thread& t, uint32_t* shadow,
-                                                   uint64_t n, uint64_t index)
+                                                   uint64_t n, uint64_t index, uint64_t off)
 {
     return (t.enabled == 1 && shadow && index < n)
-               ? __hip_atomic_load(shadow + index, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+               ? __hip_atomic_load(shadow + off, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
                : 0u;
 }
 
@@ -590,11 +650,13 @@ __device__ __forceinline__ void hr_access(const hr_kargs& a, const hr_thread& t,
         if (t.enabled == 1) hr_set_flag(a.env, HR_DEVF_RANGE);
         return;
     }
+    const uint64_t off = hr_lay_off(a.lay[region], index);
     if (a.env.word4)
         hr_check4<KIND, true>(a.env, t, (uint32_t*)a.shadow[region], a.n_elems[region], region,
-                              index, site);
+                              index, off, site);
     else
-        hr_check<KIND, true>(a.env, t, a.shadow[region], a.n_elems[region], region, index, site);
+        hr_check<KIND, true>(a.env, t, a.shadow[region], a.n_elems[region], region, index, off,
+                             site);
 }
 
 // Check one access to word `index` of a block's LDS array `array_id`, whose
@@ -692,18 +754,18 @@ __device__ __forceinline__ void hr_lds_rrw(const hr_env& e, const hr_thread& t, 
 // Runtime-kind forms (used where the kind is data, as in the interpreter).
 __device__ __forceinline__ void hr_check_k(const hr_env& e, const hr_thread& t, uint32_t kind,
                                            uint64_t* shadow, uint64_t n, uint32_t region,
-                                           uint64_t index, uint32_t site = 0)
+                                           uint64_t index, uint64_t off, uint32_t site = 0)
 {
     if (e.word4) {
         uint32_t* s4 = (uint32_t*)shadow;
-        if (kind == 0) hr_check4<0, true>(e, t, s4, n, region, index, site);
-        else if (kind == 1) hr_check4<1, true>(e, t, s4, n, region, index, site);
-        else hr_check4<2, true>(e, t, s4, n, region, index, site);
+        if (kind == 0) hr_check4<0, true>(e, t, s4, n, region, index, off, site);
+        else if (kind == 1) hr_check4<1, true>(e, t, s4, n, region, index, off, site);
+        else hr_check4<2, true>(e, t, s4, n, region, index, off, site);
         return;
     }
-    if (kind == 0) hr_check<0, true>(e, t, shadow, n, region, index, site);
-    else if (kind == 1) hr_check<1, true>(e, t, shadow, n, region, index, site);
-    else hr_check<2, true>(e, t, shadow, n, region, index, site);
+    if (kind == 0) hr_check<0, true>(e, t, shadow, n, region, index, off, site);
+    else if (kind == 1) hr_check<1, true>(e, t, shadow, n, region, index, off, site);
+    else hr_check<2, true>(e, t, shadow, n, region, index, off, site);
 }
 
 __device__ __forceinline__ void hr_access_lds_k(const hr_env& e, const hr_thread& t,

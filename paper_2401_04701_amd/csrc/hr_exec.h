@@ -48,7 +48,8 @@ __device__ __forceinline__ T* unip(T* p)
 
 __device__ __forceinline__ hr_gref uni_gref(const hr_gref& g)
 {
-    return hr_gref{unip(g.shadow), uni64(g.n), uni(g.id)};
+    return hr_gref{unip(g.shadow), uni64(g.n), uni(g.id),
+                   hr_lay{uni(g.lay.cols), uni(g.lay.tiles_x), uni(g.lay.tw), uni(g.lay.th)}};
 }
 
 // Work item `item` of `phase`: thread group g (threads g*T .. g*T+T-1, T the

@@ -6,16 +6,30 @@
 
 #include "hr_device.h"
 
-// A global region as the hooks see it: its shadow, length and report id;
-// hr_gref4 for a context with 4-byte words.  Bodies written over a region
-// type G use G::word for a pre-loaded shadow word and G::pend for a split
-// hook in flight.
+// An element of a global region as a hook takes it: its index (checked
+// against the region's length and reported) and the offset of its shadow
+// word (the region's address-to-shadow map applied to the index).
+struct hr_el {
+    uint64_t index, off;
+};
+
+// A global region as the hooks see it: its shadow, length, report id and
+// address-to-shadow map; hr_gref4 for a context with 4-byte words.  Bodies
+// written over a region type G use G::word for a pre-loaded shadow word and
+// G::pend for a split hook in flight, and name elements either by index
+// (at) or, in a 2-D array, by row and column (at2, no division).
 struct hr_gref {
     uint64_t* shadow;
     uint64_t n;
     uint32_t id;
+    hr_lay lay;
     using word = uint64_t;
     using pend = hr_pend;
+    __device__ __forceinline__ hr_el at(uint64_t index) const { return {index, hr_lay_off(lay, index)}; }
+    __device__ __forceinline__ hr_el at2(uint32_t r, uint32_t c, uint64_t index) const
+    {
+        return {index, hr_lay_off2(lay, r, c)};
+    }
 };
 
 // LAY: the 4-byte word layout as a compile-time constant (0: the context's).
@@ -24,41 +38,85 @@ struct hr_gref4t {
     uint32_t* shadow;
     uint64_t n;
     uint32_t id;
+    hr_lay lay;
     using word = uint32_t;
     using pend = hr_pend4;
+    __device__ __forceinline__ hr_el at(uint64_t index) const { return {index, hr_lay_off(lay, index)}; }
+    __device__ __forceinline__ hr_el at2(uint32_t r, uint32_t c, uint64_t index) const
+    {
+        return {index, hr_lay_off2(lay, r, c)};
+    }
 };
 using hr_gref4 = hr_gref4t<0>;
 
+// The row-major map of a region `cols` elements wide (or of a 1-D region).
+__host__ __device__ __forceinline__ hr_lay hr_lay_rows(uint32_t cols)
+{
+    return hr_lay{cols, cols, 0u, 0u};
+}
+
 // Global hook at a lane-affine site (GROUP false) or a data-dependent one.
+// Every global wrapper takes the element as an hr_el, or as an index (then
+// the region's map gives the shadow offset).
+template <int KIND, bool CHECK, bool GROUP = false>
+__device__ __forceinline__ void hr_g(const hr_env& e, const hr_thread& t, const hr_gref& g,
+                                     hr_el x, uint32_t site)
+{
+    if constexpr (CHECK) hr_check<KIND, GROUP>(e, t, g.shadow, g.n, g.id, x.index, x.off, site);
+}
+
 template <int KIND, bool CHECK, bool GROUP = false>
 __device__ __forceinline__ void hr_g(const hr_env& e, const hr_thread& t, const hr_gref& g,
                                      uint64_t index, uint32_t site)
 {
-    if constexpr (CHECK) hr_check<KIND, GROUP>(e, t, g.shadow, g.n, g.id, index, site);
+    if constexpr (CHECK) hr_g<KIND, CHECK, GROUP>(e, t, g, g.at(index), site);
 }
 
 // Global hook on a word loaded earlier by hr_gload.
 template <bool CHECK>
+__device__ __forceinline__ uint64_t hr_gload(const hr_thread& t, const hr_gref& g, hr_el x)
+{
+    if constexpr (CHECK) return hr_check_load(t, g.shadow, g.n, x.index, x.off);
+    return 0;
+}
+
+template <bool CHECK>
 __device__ __forceinline__ uint64_t hr_gload(const hr_thread& t, const hr_gref& g, uint64_t index)
 {
-    if constexpr (CHECK) return hr_check_load(t, g.shadow, g.n, index);
+    if constexpr (CHECK) return hr_gload<CHECK>(t, g, g.at(index));
     return 0;
+}
+
+template <int KIND, bool CHECK, bool GROUP = true>
+__device__ __forceinline__ void hr_gpre(const hr_env& e, const hr_thread& t, const hr_gref& g,
+                                        hr_el x, uint32_t site, uint64_t pre)
+{
+    if constexpr (CHECK)
+        hr_check<KIND, GROUP, true>(e, t, g.shadow, g.n, g.id, x.index, x.off, site, pre);
 }
 
 template <int KIND, bool CHECK, bool GROUP = true>
 __device__ __forceinline__ void hr_gpre(const hr_env& e, const hr_thread& t, const hr_gref& g,
                                         uint64_t index, uint32_t site, uint64_t pre)
 {
-    if constexpr (CHECK) hr_check<KIND, GROUP, true>(e, t, g.shadow, g.n, g.id, index, site, pre);
+    if constexpr (CHECK) hr_gpre<KIND, CHECK, GROUP>(e, t, g, g.at(index), site, pre);
 }
 
 // The two halves of a global hook at a lane-affine site (hr_check_issue /
 // hr_check_settle); `pre` as for hr_gpre when PRE.
 template <int KIND, bool CHECK, bool PRE = false>
 __device__ __forceinline__ hr_pend hr_gi(const hr_env& e, const hr_thread& t, const hr_gref& g,
+                                         hr_el x, uint64_t pre = 0)
+{
+    if constexpr (CHECK) return hr_check_issue<KIND, PRE>(e, t, g.shadow, g.n, x.index, x.off, pre);
+    return hr_pend{nullptr, 0, 0, 0};
+}
+
+template <int KIND, bool CHECK, bool PRE = false>
+__device__ __forceinline__ hr_pend hr_gi(const hr_env& e, const hr_thread& t, const hr_gref& g,
                                          uint64_t index, uint64_t pre = 0)
 {
-    if constexpr (CHECK) return hr_check_issue<KIND, PRE>(e, t, g.shadow, g.n, index, pre);
+    if constexpr (CHECK) return hr_gi<KIND, CHECK, PRE>(e, t, g, g.at(index), pre);
     return hr_pend{nullptr, 0, 0, 0};
 }
 
@@ -86,17 +144,41 @@ __device__ __forceinline__ void hr_bar(const hr_env& e, hr_thread& t)
 // The global hooks on 4-byte words.
 template <int KIND, bool CHECK, bool GROUP = false, uint32_t LAY = 0>
 __device__ __forceinline__ void hr_g(const hr_env& e, const hr_thread& t, const hr_gref4t<LAY>& g,
+                                     hr_el x, uint32_t site)
+{
+    if constexpr (CHECK)
+        hr_check4<KIND, GROUP, false, LAY>(e, t, g.shadow, g.n, g.id, x.index, x.off, site);
+}
+
+template <int KIND, bool CHECK, bool GROUP = false, uint32_t LAY = 0>
+__device__ __forceinline__ void hr_g(const hr_env& e, const hr_thread& t, const hr_gref4t<LAY>& g,
                                      uint64_t index, uint32_t site)
 {
-    if constexpr (CHECK) hr_check4<KIND, GROUP, false, LAY>(e, t, g.shadow, g.n, g.id, index, site);
+    if constexpr (CHECK) hr_g<KIND, CHECK, GROUP, LAY>(e, t, g, g.at(index), site);
+}
+
+template <bool CHECK, uint32_t LAY = 0>
+__device__ __forceinline__ uint32_t hr_gload(const hr_thread& t, const hr_gref4t<LAY>& g, hr_el x)
+{
+    if constexpr (CHECK) return hr_check4_load(t, g.shadow, g.n, x.index, x.off);
+    return 0;
 }
 
 template <bool CHECK, uint32_t LAY = 0>
 __device__ __forceinline__ uint32_t hr_gload(const hr_thread& t, const hr_gref4t<LAY>& g,
                                              uint64_t index)
 {
-    if constexpr (CHECK) return hr_check4_load(t, g.shadow, g.n, index);
+    if constexpr (CHECK) return hr_gload<CHECK, LAY>(t, g, g.at(index));
     return 0;
+}
+
+template <int KIND, bool CHECK, bool GROUP = true, uint32_t LAY = 0>
+__device__ __forceinline__ void hr_gpre(const hr_env& e, const hr_thread& t,
+                                        const hr_gref4t<LAY>& g, hr_el x, uint32_t site,
+                                        uint32_t pre)
+{
+    if constexpr (CHECK)
+        hr_check4<KIND, GROUP, true, LAY>(e, t, g.shadow, g.n, g.id, x.index, x.off, site, pre);
 }
 
 template <int KIND, bool CHECK, bool GROUP = true, uint32_t LAY = 0>
@@ -104,8 +186,16 @@ __device__ __forceinline__ void hr_gpre(const hr_env& e, const hr_thread& t,
                                         const hr_gref4t<LAY>& g, uint64_t index, uint32_t site,
                                         uint32_t pre)
 {
+    if constexpr (CHECK) hr_gpre<KIND, CHECK, GROUP, LAY>(e, t, g, g.at(index), site, pre);
+}
+
+template <int KIND, bool CHECK, bool PRE = false, uint32_t LAY = 0>
+__device__ __forceinline__ hr_pend4 hr_gi(const hr_env& e, const hr_thread& t,
+                                          const hr_gref4t<LAY>& g, hr_el x, uint32_t pre = 0)
+{
     if constexpr (CHECK)
-        hr_check4<KIND, GROUP, true, LAY>(e, t, g.shadow, g.n, g.id, index, site, pre);
+        return hr_check4_issue<KIND, PRE, LAY>(e, t, g.shadow, g.n, x.index, x.off, pre);
+    return hr_pend4{nullptr, 0, 0, 0};
 }
 
 template <int KIND, bool CHECK, bool PRE = false, uint32_t LAY = 0>
@@ -113,7 +203,7 @@ __device__ __forceinline__ hr_pend4 hr_gi(const hr_env& e, const hr_thread& t,
                                           const hr_gref4t<LAY>& g, uint64_t index,
                                           uint32_t pre = 0)
 {
-    if constexpr (CHECK) return hr_check4_issue<KIND, PRE, LAY>(e, t, g.shadow, g.n, index, pre);
+    if constexpr (CHECK) return hr_gi<KIND, CHECK, PRE, LAY>(e, t, g, g.at(index), pre);
     return hr_pend4{nullptr, 0, 0, 0};
 }
 

@@ -20,11 +20,14 @@ struct hr_alloc {
 struct hr_region {
     const void* data;    // monitored buffer
     size_t elems;        // 4-byte elements
-    uint64_t* shadow;    // one 8-byte word per element, inside allocs[alloc]
+    uint64_t* shadow;    // its shadow words (8- or 4-byte), inside allocs[alloc]
     uint32_t alloc;
     bool live;
     bool monitored;      // cleared by hr_region_enable(..., 0)
+    hr_lay lay = {};     // address-to-shadow map (zero: row-major, 1-D)
+    uint32_t rows = 0;   // rows of a tiled map
 };
+
 
 struct hr_ctx_s {
     hipStream_t stream;
@@ -41,6 +44,8 @@ struct hr_ctx_s {
 };
 
 hipStream_t hr_stream(hr_ctx c, void* stream);
+// A coalescing width: a power of two in 2..64.
+inline bool hr_coalesce_width_ok(uint32_t w) { return w >= 2 && w <= 64 && (w & (w - 1)) == 0; }
 // Apply the defaults of hr_config and check its ranges (false: invalid).
 bool hr_config_normalize(const hr_config* cfg, hr_config* out);
 // The hooks' environment of a normalized configuration over the given ring,
@@ -55,6 +60,8 @@ bool hr_region_ok(hr_ctx c, uint32_t r, const void* data, size_t min_elems);
 // Allocate `words` cleared shadow words as a new allocation.
 hr_status hr_new_alloc(hr_ctx c, size_t words, uint32_t* alloc_out);
 uint32_t hr_new_region(hr_ctx c, const void* data, size_t elems, uint64_t* shadow, uint32_t alloc);
+// Shadow words of a region (tiles' padding included).
+size_t hr_region_words(const hr_region& r);
 void hr_free_alloc(hr_ctx c, uint32_t alloc);
 hipError_t hr_fill64(uint64_t* p, size_t n, hipStream_t s);
 hipError_t hr_fill32(uint32_t* p, size_t n, hipStream_t s);
@@ -65,8 +72,11 @@ size_t hr_sort_unique(hr_race* recs, size_t n);
 // shadow words [first, first + n) of a region (4-byte words when word4),
 // taking slots from *count; ring must have room for n more records.  With
 // ring null the race words are only counted in *count.
+// rows / lay: the region's map (row-major when lay is zero), which turns a
+// word's offset back into its element index.
 hipError_t hr_scan_races_dev(const uint64_t* sh, size_t n, size_t first, bool word4,
-                             uint32_t region, hr_race_rec* ring, uint32_t* count, hipStream_t s);
+                             uint32_t region, hr_race_rec* ring, uint32_t* count, hipStream_t s,
+                             uint32_t rows = 0, const hr_lay& lay = hr_lay{});
 
 // Shape checks and derived sizes of one job (hr_instance); fills blocks (and
 // threads for jacobi), the element counts of its two monitored buffers and

@@ -59,7 +59,7 @@ __device__ void jacobi_body(const hr_env& e, const G& gold, const G& gnew,
         // in flight.  (The staging hook comes before its store: the store
         // needs the loaded value, and waiting for it waits for the exchange
         // too.)
-        const typename G::pend pc = hr_gi<0, CHECK>(e, th, gold, g);
+        const typename G::pend pc = hr_gi<0, CHECK>(e, th, gold, gold.at2(gy, gx, g));
         hr_l<1, CHECK>(e, th, tsh, TW, lds_id, cl, HR_SITE_JACOBI_STAGE);
         tile[cl] = vc;
         hr_gs<0, CHECK>(e, th, gold, pc, g, HR_SITE_JACOBI_CENTRE);
@@ -70,14 +70,16 @@ __device__ void jacobi_body(const hr_env& e, const G& gold, const G& gnew,
     } else if constexpr (!ONE_HALO) {
         if (hn || hs) {
             const uint32_t lr = lrow();
-            const typename G::pend pr = hr_gi<0, CHECK>(e, th, gold, gr);
+            const typename G::pend pr =
+                hr_gi<0, CHECK>(e, th, gold, gold.at2(hn ? gy - 1 : gy + 1, gx, gr));
             hr_l<1, CHECK>(e, th, tsh, TW, lds_id, lr, HR_SITE_JACOBI_STAGE);
             tile[lr] = vr;
             hr_gs<0, CHECK>(e, th, gold, pr, gr, HR_SITE_JACOBI_HALO);
         }
         if (hw || he) {
             const uint32_t lc = lcol();
-            const typename G::pend pk = hr_gi<0, CHECK>(e, th, gold, gc);
+            const typename G::pend pk =
+                hr_gi<0, CHECK>(e, th, gold, gold.at2(gy, hw ? gx - 1 : gx + 1, gc));
             hr_l<1, CHECK>(e, th, tsh, TW, lds_id, lc, HR_SITE_JACOBI_STAGE);
             tile[lc] = vk;
             hr_gs<0, CHECK>(e, th, gold, pk, gc, HR_SITE_JACOBI_HALO);
@@ -94,6 +96,8 @@ __device__ void jacobi_body(const hr_env& e, const G& gold, const G& gnew,
         // identity before the same barrier; the proxy need not own a cell.
         bool on = hn || hs || hw || he;
         size_t ha = hn || hs ? gr : gc;
+        uint32_t hy = hn ? gy - 1 : (hs ? gy + 1 : gy);
+        uint32_t hx = hn || hs ? gx : (hw ? gx - 1 : gx + 1);
         hr_thread hth = th;
         if (t < 256 && (ty == 1 || ty == 14) && (tx == 1 || tx == 14)) {
             const uint32_t cy = ty == 1 ? 0u : 15u, cx = tx == 1 ? 0u : 15u;
@@ -104,11 +108,13 @@ __device__ void jacobi_body(const hr_env& e, const G& gold, const G& gnew,
                 const size_t cg = (size_t)cgy * nx + cgx;
                 on = true;
                 ha = cw ? cg - 1 : cg + 1;
+                hy = cgy;
+                hx = cw ? cgx - 1 : cgx + 1;
                 hth = hr_thread_make(e, lb, cy * 16u + cx);
             }
         }
         if (on) {
-            const typename G::pend ph = hr_gi<0, CHECK>(e, hth, gold, ha);
+            const typename G::pend ph = hr_gi<0, CHECK>(e, hth, gold, gold.at2(hy, hx, ha));
             if (hn || hs) {
                 hr_l<1, CHECK>(e, th, tsh, TW, lds_id, lr, HR_SITE_JACOBI_STAGE);
                 tile[lr] = vr;
@@ -123,7 +129,8 @@ __device__ void jacobi_body(const hr_env& e, const G& gold, const G& gnew,
     hr_bar<CHECK>(e, th);
     if (inside) {
         // the output word's shadow load is in flight during the LDS reads
-        const typename G::word pre_out = hr_gload<CHECK>(th, gnew, g);
+        const hr_el xo = gnew.at2(gy, gx, g);
+        const typename G::word pre_out = hr_gload<CHECK>(th, gnew, xo);
         const float c = tile[cl];
         hr_l<0, CHECK>(e, th, tsh, TW, lds_id, cl, HR_SITE_JACOBI_TILE);
         float vn = c, vs = c, vw = c, ve = c;
@@ -145,29 +152,51 @@ __device__ void jacobi_body(const hr_env& e, const G& gold, const G& gnew,
         }
         const float r = 0.2f * (c + vn + vs + vw + ve);
         un[g] = r;
-        hr_gpre<1, CHECK, false>(e, th, gnew, g, HR_SITE_JACOBI_OUT, pre_out);
+        hr_gpre<1, CHECK, false>(e, th, gnew, xo, HR_SITE_JACOBI_OUT, pre_out);
         if (seeds) {
             const int32_t sd = seeds[lb];
             if (sd >= 0) {
                 const uint32_t side = (uint32_t)sd >> 8, off = (uint32_t)sd & 255u;
-                int64_t tgt = -1;
-                if (side == 0 && ty == 0 && tx == off && gy > 0) tgt = (int64_t)g - nx;
-                else if (side == 1 && ty == 15 && tx == off && gy + 1 < ny) tgt = (int64_t)g + nx;
-                else if (side == 2 && tx == 0 && ty == off && gx > 0) tgt = (int64_t)g - 1;
-                else if (side == 3 && tx == 15 && ty == off && gx + 1 < nx) tgt = (int64_t)g + 1;
-                if (tgt >= 0) {
+                uint32_t sy = gy, sx = gx;   // the neighbour-owned target cell
+                bool hit = false;
+                if (side == 0 && ty == 0 && tx == off && gy > 0) hit = true, sy = gy - 1;
+                else if (side == 1 && ty == 15 && tx == off && gy + 1 < ny) hit = true, sy = gy + 1;
+                else if (side == 2 && tx == 0 && ty == off && gx > 0) hit = true, sx = gx - 1;
+                else if (side == 3 && tx == 15 && ty == off && gx + 1 < nx) hit = true, sx = gx + 1;
+                if (hit) {
+                    const size_t tgt = (size_t)sy * nx + sx;
                     un[tgt] = r;
-                    hr_g<1, CHECK>(e, th, gnew, (uint64_t)tgt, HR_SITE_JACOBI_SEED);
+                    hr_g<1, CHECK>(e, th, gnew, gnew.at2(sy, sx, tgt), HR_SITE_JACOBI_SEED);
                 }
             }
         }
     }
 }
 
+// A global region whose 2-D shadow map is fixed at compile time: TW = TH = 0
+// is the row-major map (the shadow offset is the element index itself), TW,
+// TH > 0 tiles of 2^TW x 2^TH elements with constant shifts, and TW < 0 the
+// region's own map at run time.
+template <int TW, int TH>
+struct hr_gref_map : hr_gref {
+    __device__ __forceinline__ hr_el at2(uint32_t r, uint32_t c, uint64_t index) const
+    {
+        if constexpr (TW < 0) {
+            return hr_gref::at2(r, c, index);
+        } else if constexpr (TW == 0 && TH == 0) {
+            return {index, index};
+        } else {
+            const uint64_t tile = (uint64_t)(r >> TH) * lay.tiles_x + (c >> TW);
+            return {index, (tile << (TW + TH)) | ((uint64_t)(r & ((1u << TH) - 1u)) << TW) |
+                               (uint64_t)(c & ((1u << TW) - 1u))};
+        }
+    }
+};
+
 namespace {
 
-// One 16 x 16 tile per hardware block.  8 waves per SIMD: the hook's scalar
-// registers would otherwise cap the occupancy at 7.
+// One 16 x 16 tile per hardware block, on row-major shadow maps.  8 waves per
+// SIMD: the hook's scalar registers would otherwise cap the occupancy at 7.
 template <bool CHECK>
 __global__ __launch_bounds__(256, 8) void k_jacobi(hr_kargs a, hr_gref gold, hr_gref gnew,
                                                 const float* __restrict__ uo,
@@ -176,9 +205,25 @@ __global__ __launch_bounds__(256, 8) void k_jacobi(hr_kargs a, hr_gref gold, hr_
 {
     __shared__ float tile[JACOBI_TILE_WORDS];
     __shared__ uint32_t tsh[CHECK ? JACOBI_TILE_WORDS : 1];
-    jacobi_body<CHECK, hr_gref, true>(a.env, gold, gnew, uo, un, ny, nx, gridDim.x, seeds,
-                                      blockIdx.y * gridDim.x + blockIdx.x, threadIdx.x, tile,
-                                      tsh, 0);
+    using G = hr_gref_map<0, 0>;
+    jacobi_body<CHECK, G, true>(a.env, G{gold}, G{gnew}, uo, un, ny, nx, gridDim.x, seeds,
+                                blockIdx.y * gridDim.x + blockIdx.x, threadIdx.x, tile, tsh, 0);
+}
+
+// The checked sweep on tiled shadow maps: both grids tiled by 2^TW x 2^TH
+// (constant shifts), or TW < 0: each grid's own map, read at run time.
+template <int TW, int TH>
+__global__ __launch_bounds__(256, 8) void k_jacobi_tiled(hr_kargs a, hr_gref gold, hr_gref gnew,
+                                                         const float* __restrict__ uo,
+                                                         float* __restrict__ un, uint32_t ny,
+                                                         uint32_t nx,
+                                                         const int32_t* __restrict__ seeds)
+{
+    __shared__ float tile[JACOBI_TILE_WORDS];
+    __shared__ uint32_t tsh[JACOBI_TILE_WORDS];
+    using G = hr_gref_map<TW, TH>;
+    jacobi_body<true, G, true>(a.env, G{gold}, G{gnew}, uo, un, ny, nx, gridDim.x, seeds,
+                               blockIdx.y * gridDim.x + blockIdx.x, threadIdx.x, tile, tsh, 0);
 }
 
 // The checked sweep on 4-byte shadow words, with the word layout as a

@@ -58,17 +58,20 @@ hr_status clear_shadows(hr_ctx c, hipStream_t s)
 // appended to ring[] as a scanned record (only its key is valid) at the
 // index taken from *count, or only counted when ring is null.  The caller
 // sizes ring for every word it scans.
+// The words are at offsets first .. first + n - 1 of the region's shadow;
+// rows and lay give the region's map back to element indices.
 __global__ void k_scan_races(const uint64_t* __restrict__ sh, size_t n, size_t first,
                              uint32_t word4, uint32_t region, hr_race_rec* __restrict__ ring,
-                             uint32_t* __restrict__ count)
+                             uint32_t* __restrict__ count, uint32_t rows, hr_lay lay)
 {
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     for (; i < n; i += stride) {
-        const size_t e = first + i;
-        const bool race = word4 ? ((const uint32_t*)sh)[e] == hr::T_RACE
-                                : (sh[e] & hr::g::TAG_M) == hr::T_RACE;
-        if (!race) continue;
+        const size_t o = first + i;
+        const bool race = word4 ? ((const uint32_t*)sh)[o] == hr::T_RACE
+                                : (sh[o] & hr::g::TAG_M) == hr::T_RACE;
+        const uint64_t e = hr_lay_index(lay, rows, o);
+        if (!race || e == UINT64_MAX) continue;
         const uint32_t slot =
             __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (!ring) continue;
@@ -110,13 +113,14 @@ size_t hr_sort_unique(hr_race* recs, size_t n)
 }
 
 hipError_t hr_scan_races_dev(const uint64_t* sh, size_t n, size_t first, bool word4,
-                             uint32_t region, hr_race_rec* ring, uint32_t* count, hipStream_t s)
+                             uint32_t region, hr_race_rec* ring, uint32_t* count, hipStream_t s,
+                             uint32_t rows, const hr_lay& lay)
 {
     if (n == 0) return hipSuccess;
     const size_t blocks = std::min<size_t>((n + 255) / 256, 8192);
     (void)hipGetLastError();
     hipLaunchKernelGGL(k_scan_races, dim3((unsigned)blocks), dim3(256), 0, s, sh, n, first,
-                       word4 ? 1u : 0u, region, ring, count);
+                       word4 ? 1u : 0u, region, ring, count, rows, lay);
     return hipGetLastError();
 }
 
@@ -157,7 +161,7 @@ hr_env hr_env_of(const hr_config& cfg, hr_race_rec* ring, uint32_t* ctr,
     e.launch_seq = launch_seq;
     e.bc_max = (1u << cfg.bc_bits) - 1;
     e.wc_max = (1u << cfg.wc_bits) - 1;
-    e.group = (cfg.flags & HR_CFG_WAVE_GROUPING) ? 1u : 0u;
+    e.group = (cfg.flags & HR_CFG_WAVE_GROUPING) ? cfg.coalesce_width : 0u;
     e.site_limit = cfg.site_limit;
     e.wave_bits = cfg.wave_bits;
     e.word4 = (cfg.flags & HR_CFG_WORD4)
@@ -181,6 +185,7 @@ void hr_fill_args(hr_ctx c, hr_kargs* a)
         a->shadow[r] = c->reg[r].monitored ? c->reg[r].shadow : nullptr;
         a->n_elems[r] = c->reg[r].elems;
         a->data[r] = const_cast<void*>(c->reg[r].data);
+        a->lay[r] = c->reg[r].lay;
     }
 }
 
@@ -212,6 +217,11 @@ uint32_t hr_new_region(hr_ctx c, const void* data, size_t elems, uint64_t* shado
     return (uint32_t)(c->reg.size() - 1);
 }
 
+size_t hr_region_words(const hr_region& r)
+{
+    return hr_lay_words(r.lay, r.rows, r.elems);
+}
+
 void hr_free_alloc(hr_ctx c, uint32_t alloc)
 {
     hr_alloc& al = c->allocs[alloc];
@@ -237,6 +247,12 @@ bool hr_config_normalize(const hr_config* cfg, hr_config* out)
     if (k.flags & ~(HR_CFG_COUNT_CHECKS | HR_CFG_WAVE_GROUPING | HR_CFG_WORD4)) return false;
     if (k.wave_bits == 0) k.wave_bits = 6;
     if (k.wave_bits > 6) return false;
+    if (k.flags & HR_CFG_WAVE_GROUPING) {
+        if (k.coalesce_width == 0) k.coalesce_width = 64;
+        if (!hr_coalesce_width_ok(k.coalesce_width)) return false;
+    } else if (k.coalesce_width) {
+        return false;   // a width without grouping
+    }
     *out = k;
     return true;
 }
@@ -297,6 +313,29 @@ extern "C" hr_status hr_shadow_alloc(hr_ctx c, const void* data_dev, size_t byte
     return HR_OK;
 }
 
+extern "C" hr_status hr_shadow_alloc_2d(hr_ctx c, const void* data_dev, uint32_t rows,
+                                        uint32_t cols, uint32_t elem_bytes, uint32_t tile_w_log2,
+                                        uint32_t tile_h_log2, uint32_t* region_out)
+{
+    if (!c || !region_out || elem_bytes != 4 || rows == 0 || cols == 0) return HR_E_INVAL;
+    if (tile_w_log2 > HR_TILE_LOG2_MAX || tile_h_log2 > HR_TILE_LOG2_MAX ||
+        tile_w_log2 + tile_h_log2 > 2 * HR_TILE_LOG2_MAX)
+        return HR_E_INVAL;
+    if (c->reg.size() >= (1u << 24)) return HR_E_INVAL;
+    hr_lay L{cols, (cols + (1u << tile_w_log2) - 1u) >> tile_w_log2, tile_w_log2, tile_h_log2};
+    if ((tile_w_log2 | tile_h_log2) == 0) L = hr_lay{};   // row-major: the identity map
+    const size_t elems = (size_t)rows * cols;
+    const size_t lw = hr_lay_words(L, rows, elems);
+    const size_t words = (c->cfg.flags & HR_CFG_WORD4) ? (lw + 1) / 2 : lw;
+    uint32_t alloc = 0;
+    const hr_status st = hr_new_alloc(c, words, &alloc);
+    if (st != HR_OK) return st;
+    *region_out = hr_new_region(c, data_dev, elems, c->allocs[alloc].mem, alloc);
+    c->reg[*region_out].lay = L;
+    c->reg[*region_out].rows = rows;
+    return HR_OK;
+}
+
 extern "C" hr_status hr_shadow_free(hr_ctx c, uint32_t region)
 {
     if (!c || region >= c->reg.size() || !c->reg[region].live) return HR_E_INVAL;
@@ -336,21 +375,25 @@ static hr_status scan_races(hr_ctx c, std::vector<hr_race>& out)
     const bool word4 = (c->cfg.flags & HR_CFG_WORD4) != 0;
     for (uint32_t r = 0; r < c->reg.size(); ++r) {
         if (!c->reg[r].live) continue;
+        const hr_region& g = c->reg[r];
+        const size_t words = hr_region_words(g);
         if (word4) {
-            std::vector<uint32_t> sh(c->reg[r].elems);
-            if (hipMemcpy(sh.data(), c->reg[r].shadow, sizeof(uint32_t) * sh.size(),
+            std::vector<uint32_t> sh(words);
+            if (hipMemcpy(sh.data(), g.shadow, sizeof(uint32_t) * sh.size(),
                           hipMemcpyDeviceToHost) != hipSuccess)
                 return HR_E_HIP;
             for (size_t i = 0; i < sh.size(); ++i)
-                if (sh[i] == hr::T_RACE) out.push_back(scanned_race(r, i));
+                if (sh[i] == hr::T_RACE && hr_lay_index(g.lay, g.rows, i) != UINT64_MAX)
+                    out.push_back(scanned_race(r, hr_lay_index(g.lay, g.rows, i)));
             continue;
         }
-        std::vector<uint64_t> sh(c->reg[r].elems);
-        if (hipMemcpy(sh.data(), c->reg[r].shadow, sizeof(uint64_t) * sh.size(),
+        std::vector<uint64_t> sh(words);
+        if (hipMemcpy(sh.data(), g.shadow, sizeof(uint64_t) * sh.size(),
                       hipMemcpyDeviceToHost) != hipSuccess)
             return HR_E_HIP;
         for (size_t i = 0; i < sh.size(); ++i) {
-            if ((sh[i] & hr::g::TAG_M) == hr::T_RACE) out.push_back(scanned_race(r, i));
+            if ((sh[i] & hr::g::TAG_M) == hr::T_RACE && hr_lay_index(g.lay, g.rows, i) != UINT64_MAX)
+                out.push_back(scanned_race(r, hr_lay_index(g.lay, g.rows, i)));
         }
     }
     return HR_OK;

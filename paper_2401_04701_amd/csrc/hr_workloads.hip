@@ -11,25 +11,39 @@
 
 namespace {
 
-hr_gref gref(const hr_kargs& a, uint32_t r)
+// The hooks' view of kernel-argument region r.  cols: the row width a 2-D
+// workload indexes the region with, which is the width of a row-major map
+// (a tiled map carries its own and must agree; the launchers check that).
+hr_gref gref(const hr_kargs& a, uint32_t r, uint32_t cols = 0)
 {
-    hr_gref g{nullptr, 0, r};
+    hr_gref g{nullptr, 0, r, hr_lay_rows(cols)};
     if (r < HR_MAX_REGIONS) {
         g.shadow = a.shadow[r];
         g.n = a.n_elems[r];
+        if (a.lay[r].tw | a.lay[r].th) g.lay = a.lay[r];
     }
     return g;
 }
 
 template <uint32_t LAY = 0>
-hr_gref4t<LAY> gref4(const hr_kargs& a, uint32_t r)
+hr_gref4t<LAY> gref4(const hr_kargs& a, uint32_t r, uint32_t cols = 0)
 {
-    hr_gref4t<LAY> g{nullptr, 0, r};
+    hr_gref4t<LAY> g{nullptr, 0, r, hr_lay_rows(cols)};
     if (r < HR_MAX_REGIONS) {
         g.shadow = (uint32_t*)a.shadow[r];
         g.n = a.n_elems[r];
+        if (a.lay[r].tw | a.lay[r].th) g.lay = a.lay[r];
     }
     return g;
+}
+
+// A region's map fits a 2-D workload nx elements wide: row-major, or tiled
+// over rows of exactly nx elements.
+bool lay_fits(const hr_kargs& a, uint32_t r, uint32_t nx)
+{
+    if (r >= HR_MAX_REGIONS) return false;
+    const hr_lay& L = a.lay[r];
+    return (L.tw | L.th) == 0 || L.cols == nx;
 }
 
 template <bool CHECK>
@@ -137,7 +151,8 @@ __global__ __launch_bounds__(1024) void k_program(hr_kargs a, prog_map pm, uint3
                 if (kind == 0) (void)*(volatile uint32_t*)(d + idx);
                 else if (kind == 1) d[idx] = t + 1;
                 else atomicAdd(d + idx, 1u);
-                hr_check_k(a.env, th, kind, a.shadow[r], a.n_elems[r], r, idx, p + 1);
+                hr_check_k(a.env, th, kind, a.shadow[r], a.n_elems[r], r, idx,
+                           hr_lay_off(a.lay[r], idx), p + 1);
             }
         }
         const uint8_t sc = scope[p];
@@ -220,17 +235,27 @@ hr_status hr_launch_jacobi(const hr_kargs& a, uint32_t r_old, uint32_t r_new,
                            const int32_t* seed_dev, hipStream_t s)
 {
     if (!u_old_dev || !u_new_dev || !jacobi_shape_ok(ny, nx)) return HR_E_INVAL;
+    if (!lay_fits(a, r_old, nx) || !lay_fits(a, r_new, nx)) return HR_E_INVAL;
     const dim3 grid((nx + 15) / 16, (ny + 15) / 16);
     constexpr uint32_t DL = hr::c::DEFAULT_LAYOUT;
     if (a.env.word4 == DL)
-        HR_LAUNCH(k_jacobi4<DL>, grid, dim3(256), 0, s, a, gref4<DL>(a, r_old),
-                  gref4<DL>(a, r_new), u_old_dev, u_new_dev, ny, nx, seed_dev);
+        HR_LAUNCH(k_jacobi4<DL>, grid, dim3(256), 0, s, a, gref4<DL>(a, r_old, nx),
+                  gref4<DL>(a, r_new, nx), u_old_dev, u_new_dev, ny, nx, seed_dev);
     else if (a.env.word4)
-        HR_LAUNCH(k_jacobi4<0>, grid, dim3(256), 0, s, a, gref4(a, r_old), gref4(a, r_new),
-                  u_old_dev, u_new_dev, ny, nx, seed_dev);
-    else
-        HR_LAUNCH(k_jacobi<true>, grid, dim3(256), 0, s, a, gref(a, r_old), gref(a, r_new),
-                  u_old_dev, u_new_dev, ny, nx, seed_dev);
+        HR_LAUNCH(k_jacobi4<0>, grid, dim3(256), 0, s, a, gref4(a, r_old, nx),
+                  gref4(a, r_new, nx), u_old_dev, u_new_dev, ny, nx, seed_dev);
+    else {
+        // the kernel with the grids' map as a constant when there is one
+        const hr_lay &lo = a.lay[r_old], &ln = a.lay[r_new];
+        const uint32_t to = lo.tw | lo.th << 4, tn = ln.tw | ln.th << 4;
+        auto k = k_jacobi_tiled<-1, -1>;
+        if (to == 0 && tn == 0) k = k_jacobi<true>;
+        else if (to == tn && to == (2u | 2u << 4)) k = k_jacobi_tiled<2, 2>;
+        else if (to == tn && to == (2u | 1u << 4)) k = k_jacobi_tiled<2, 1>;
+        else if (to == tn && to == (3u | 1u << 4)) k = k_jacobi_tiled<3, 1>;
+        HR_LAUNCH(k, grid, dim3(256), 0, s, a, gref(a, r_old, nx), gref(a, r_new, nx), u_old_dev,
+                  u_new_dev, ny, nx, seed_dev);
+    }
     return HR_OK;
 }
 

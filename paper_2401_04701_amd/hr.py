@@ -32,6 +32,7 @@ HR_CFG_WORD4 = 4
 NO_REGION = 0xFFFFFFFF
 HR_PAT_REDUCE, HR_PAT_JACOBI, HR_PAT_LABELPROP = 0, 1, 2
 HR_SITES = 256
+HR_TILE_LOG2_MAX = 4
 # the static scratch array of hr_job_run_static
 HR_STATIC_SCRATCH_BYTES = 64 << 20
 HR_STATIC_RING_RECORDS = 16384
@@ -69,7 +70,7 @@ class _Config(ctypes.Structure):
                 ("wc_bits", ctypes.c_uint32), ("flags", ctypes.c_uint32),
                 ("shadow_budget", ctypes.c_uint64), ("site_limit", ctypes.c_uint32),
                 ("wave_bits", ctypes.c_uint32), ("thread_bits", ctypes.c_uint32),
-                ("pad", ctypes.c_uint32)]
+                ("coalesce_width", ctypes.c_uint32)]
 
 
 class Summary(ctypes.Structure):
@@ -94,7 +95,7 @@ class Instance(ctypes.Structure):
 class _Tuning(ctypes.Structure):
     _fields_ = [("workers", ctypes.c_uint32), ("order", ctypes.c_uint32),
                 ("spin_limit", ctypes.c_uint32), ("variant", ctypes.c_uint32),
-                ("coalesce", ctypes.c_uint32)]
+                ("coalesce", ctypes.c_uint32), ("tile", ctypes.c_uint32)]
 
 
 class ServeJob(ctypes.Structure):
@@ -131,6 +132,7 @@ def _load():
         "hr_ctx_create": [P, P, P],
         "hr_ctx_destroy": [P],
         "hr_shadow_alloc": [P, P, sz, u32, P],
+        "hr_shadow_alloc_2d": [P, P, u32, u32, u32, u32, u32, P],
         "hr_shadow_free": [P, u32],
         "hr_region_enable": [P, u32, u32],
         "hr_dev_args": [P, P, sz, P],
@@ -170,7 +172,8 @@ def _load():
 
 
 _lib = _load()
-EXPORTED = ("hr_ctx_create", "hr_ctx_destroy", "hr_shadow_alloc", "hr_shadow_free",
+EXPORTED = ("hr_ctx_create", "hr_ctx_destroy", "hr_shadow_alloc", "hr_shadow_alloc_2d",
+            "hr_shadow_free",
             "hr_region_enable",
             "hr_dev_args", "hr_batch_create", "hr_batch_run", "hr_batch_info",
             "hr_batch_destroy", "hr_job_run", "hr_job_run_static", "hr_serve",
@@ -312,12 +315,12 @@ class Context:
 
     def __init__(self, ring_capacity=0, bc_bits=0, wc_bits=0, count_checks=False,
                  shadow_budget=0, wave_grouping=False, site_limit=0, wave_bits=0,
-                 word4=False, thread_bits=0, stream=None):
+                 word4=False, thread_bits=0, coalesce_width=0, stream=None):
         flags = (HR_CFG_COUNT_CHECKS if count_checks else 0) | \
                 (HR_CFG_WAVE_GROUPING if wave_grouping else 0) | \
                 (HR_CFG_WORD4 if word4 else 0)
         cfg = _Config(ring_capacity, bc_bits, wc_bits, flags, shadow_budget, site_limit,
-                      wave_bits, thread_bits, 0)
+                      wave_bits, thread_bits, coalesce_width)
         self.wave_bits = wave_bits or 6
         self._c = ctypes.c_void_p(0)
         self._stream = _stream_ptr(stream)
@@ -346,10 +349,20 @@ class Context:
     def handle(self):
         return self._c
 
-    def shadow_alloc(self, tensor) -> int:
+    def shadow_alloc(self, tensor, tile=None) -> int:
+        """Monitor `tensor`.  tile=(tw, th): a 2-D tensor's shadow words in
+        tiles of 2**tw columns by 2**th rows (hr_shadow_alloc_2d); None or
+        (0, 0) keeps the row-major map."""
         if not (tensor.is_cuda and tensor.element_size() == 4 and tensor.is_contiguous()):
             raise ValueError("shadow_alloc needs a contiguous device tensor of 4-byte elements")
         r = ctypes.c_uint32(0)
+        if tile is not None:
+            if tensor.dim() != 2:
+                raise ValueError("a tiled shadow map needs a 2-D tensor")
+            rows, cols = tensor.shape
+            _check("hr_shadow_alloc_2d", _lib.hr_shadow_alloc_2d(
+                self._c, _dptr(tensor), rows, cols, 4, tile[0], tile[1], ctypes.byref(r)))
+            return int(r.value)
         _check("hr_shadow_alloc", _lib.hr_shadow_alloc(self._c, _dptr(tensor),
                                                        tensor.numel() * 4, 4, ctypes.byref(r)))
         return int(r.value)
@@ -514,10 +527,13 @@ class Batch:
                                                    ctypes.byref(it)))
         return int(w.value), int(it.value)
 
-    def run(self, workers=0, order=0, variant=0, spin_limit=0, coalesce=0, stream=None):
+    def run(self, workers=0, order=0, variant=0, spin_limit=0, coalesce=0, tile=None,
+            stream=None):
         """coalesce: wave grouping at data-dependent sites, 0 the context's
-        setting, 1 off, 2 on."""
-        t = _Tuning(workers, order, spin_limit, variant, coalesce)
+        setting, 1 off, else the coalescing width (2..64 lanes).  tile=(tw,
+        th): the stencil jobs' shadow map (None: row-major)."""
+        t = _Tuning(workers, order, spin_limit, variant, coalesce,
+                    0 if tile is None else (tile[0] | tile[1] << 4))
         _check("hr_batch_run", _lib.hr_batch_run(self._b, ctypes.byref(t), _stream_ptr(stream)))
 
     def split(self, keys):

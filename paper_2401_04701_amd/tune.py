@@ -1,11 +1,23 @@
-"""Autotuner of the batched launch: times candidate tunings of one batch
-(kernel variant, queue order, worker count, then coalescing of same-word
-lanes for the best of those) on the device and keeps the fastest.  Each
-trial is a full run of the batch (the results are the same for every
-tuning; only the schedule and the number of atomics differ)."""
+"""Autotuner of the batched launch: times candidate tunings of one batch on
+the device and keeps the fastest.  It picks, in turn, the schedule (kernel
+variant, queue order, worker count), the shadow map of the stencil jobs'
+grids (row-major, or tiles of 4 x 4, 8 x 2, 2 x 8 or 16 x 1 elements) and
+the coalescing width of same-word lanes (grouping off, or within segments
+of 8, 16 or 64 lanes).  Each trial is a full run of the batch; the results
+are the same for every tuning, only the schedule, the shadow lines touched
+and the number of atomics differ."""
 from __future__ import annotations
 
 import itertools
+
+# shadow maps: (tw, th) = log2 of the tile's width and height; None: row-major
+TILES = (None, (2, 2), (3, 1), (1, 3), (4, 0))
+# coalescing widths: 1 = grouping off, else lanes per grouping segment
+WIDTHS = (1, 8, 16, 64)
+
+
+def tile_name(tile) -> str:
+    return "rowmajor" if tile is None else f"{1 << tile[0]}x{1 << tile[1]}"
 
 
 def candidates(batch):
@@ -17,8 +29,19 @@ def candidates(batch):
     return out
 
 
-def autotune(ctx, batch, reps: int = 2, cands=None):
-    """Return (best tuning dict, {tuning key: best ms})."""
+def key_of(cand) -> str:
+    key = "v{variant}_o{order}_w{workers}".format(**cand)
+    if "tile" in cand:
+        key += "_t" + tile_name(cand["tile"])
+    if cand.get("coalesce"):
+        key += "_c{coalesce}".format(**cand)
+    return key
+
+
+def autotune(ctx, batch, reps: int = 2, cands=None, tiles=TILES, widths=WIDTHS):
+    """Return (best tuning dict, {tuning key: best ms}).  The schedule is
+    chosen first over `cands`, then the shadow map for it, then the
+    coalescing width for both."""
     import torch
     stream = torch.cuda.current_stream()
     timings = {}
@@ -34,21 +57,18 @@ def autotune(ctx, batch, reps: int = 2, cands=None):
             e1.synchronize()
             t = e0.elapsed_time(e1)
             ms = t if ms is None else min(ms, t)
-        key = "v{variant}_o{order}_w{workers}".format(**cand)
-        if cand.get("coalesce"):
-            key += "_c{coalesce}".format(**cand)
-        timings[key] = ms
+        timings[key_of(cand)] = ms
         return ms
 
-    best, best_ms = None, None
-    for cand in cands or candidates(batch):
-        ms = trial(cand)
-        if best_ms is None or ms < best_ms:
-            best, best_ms = cand, ms
-    # coalescing of same-word lanes, off and on, for the best schedule
-    for c in (1, 2):
-        cand = dict(best, coalesce=c)
-        ms = trial(cand)
-        if ms < best_ms:
-            best, best_ms = cand, ms
+    def best_of(options, base):
+        best, best_ms = None, None
+        for cand in options:
+            ms = trial(dict(base, **cand))
+            if best_ms is None or ms < best_ms:
+                best, best_ms = dict(base, **cand), ms
+        return best, best_ms
+
+    best, best_ms = best_of(cands or candidates(batch), {})
+    best, best_ms = best_of([{"tile": t} for t in tiles], best)
+    best, best_ms = best_of([{"coalesce": c} for c in widths], best)
     return best, timings

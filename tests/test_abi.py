@@ -45,6 +45,11 @@ def test_unknown_config_flags_are_rejected():
     assert hr.lib().hr_ctx_create(ctypes.byref(c), ctypes.byref(cfg), None) == hr.HR_E_INVAL
     cfg = hr._Config(0, 0, 0, 0, 0, 0, 0, 8)         # a thread width without 4-byte words
     assert hr.lib().hr_ctx_create(ctypes.byref(c), ctypes.byref(cfg), None) == hr.HR_E_INVAL
+    # coalescing widths: a power of two in 2..64, and only with wave grouping
+    for width, flags in ((3, hr.HR_CFG_WAVE_GROUPING), (128, hr.HR_CFG_WAVE_GROUPING),
+                         (1, hr.HR_CFG_WAVE_GROUPING), (16, 0)):
+        cfg = hr._Config(0, 0, 0, flags, 0, 0, 0, 0, width)
+        assert hr.lib().hr_ctx_create(ctypes.byref(c), ctypes.byref(cfg), None) == hr.HR_E_INVAL
     assert not c.value
 
 

@@ -64,10 +64,16 @@ PROGRAMS = [
 ]
 
 
-def run_program(torch, hr, prog, block_perm_seed=None, ctx_kwargs=None):
-    data = [torch.zeros(w, dtype=torch.int32, device="cuda") for w in prog.global_words]
+def run_program(torch, hr, prog, block_perm_seed=None, ctx_kwargs=None, tile=None, cols=13):
+    """tile: give every global region a tiled shadow map, the region viewed as
+    a 2-D array `cols` elements wide (rounded up to whole rows)."""
+    if tile is None:
+        data = [torch.zeros(w, dtype=torch.int32, device="cuda") for w in prog.global_words]
+    else:
+        data = [torch.zeros(((w + cols - 1) // cols, cols), dtype=torch.int32, device="cuda")
+                for w in prog.global_words]
     with hr.Context(**(ctx_kwargs or {})) as ctx:
-        regs = [ctx.shadow_alloc(d) for d in data]
+        regs = [ctx.shadow_alloc(d, tile=tile) for d in data]
         for launch in prog.launches:
             dp = hr.DeviceProgram(launch)
             bmap = None
@@ -99,6 +105,28 @@ def test_program_flagged_set(env, cfg):
     # wave grouping of same-word lanes changes the number of atomics only
     got3, st3 = run_program(torch, hr, prog, ctx_kwargs={"wave_grouping": True})
     assert st3 == 0 and got3 == want
+    # so does a tiled address-to-shadow map (ragged rows of 13 elements)
+    got4, st4 = run_program(torch, hr, prog, tile=(2, 1))
+    assert st4 == 0 and got4 == want
+
+
+@pytest.mark.parametrize("tile,cols", [((2, 2), 16), ((3, 1), 7), ((1, 3), 100), ((4, 4), 33),
+                                       ((0, 2), 5)])
+def test_program_tiled_shadow_map(env, tile, cols):
+    """The generic hook's index-to-shadow map (a division by the row width)
+    on ragged tiles, with and without wave grouping: the verdict is the
+    oracle's, which knows nothing of shadow layouts."""
+    torch, hr = env
+    prog = si.random_program(31, launches=2, blocks=12, threads=256, phases=5, max_ops=3,
+                             global_regions=3, global_words=700, lds_words=128, p_lds=0.3)
+    want = oracle.flagged_program(prog)
+    assert len(want) > 0
+    say("program tiled map", tile, cols)
+    got, st = run_program(torch, hr, prog, tile=tile, cols=cols)
+    assert st == 0 and got == want
+    got2, st2 = run_program(torch, hr, prog, tile=tile, cols=cols,
+                            ctx_kwargs={"wave_grouping": True})
+    assert st2 == 0 and got2 == want
 
 
 def test_program_race_free_variants(env):
@@ -128,12 +156,23 @@ JACOBI = [(64, 64, 3, 6), (50, 37, 2, 5), (33, 80, 4, 8), (96, 17, 3, 4), (16, 1
           (15, 33, 2, 1)]
 
 
-def run_jacobi(torch, hr, ny, nx, launches, tab, ctx_kwargs=None, grid_seed=1):
+# Shadow maps of the stencil's grids: row-major, tiles of 4 x 4, 8 x 2 and
+# 2 x 8 elements (one 128-byte line of 8-byte words per tile) and of 4 x 2
+# (the kernels with a constant map: row-major, 4 x 4, 8 x 2, 4 x 2; the
+# others read the map at run time).
+TILES = [None, (2, 2), (3, 1), (1, 3), (2, 1)]
+
+
+def tile_id(t):
+    return "rowmajor" if t is None else f"tile{1 << t[0]}x{1 << t[1]}"
+
+
+def run_jacobi(torch, hr, ny, nx, launches, tab, ctx_kwargs=None, grid_seed=1, tile=None):
     u = [torch.from_numpy(si.jacobi_grid(ny, nx, grid_seed)).cuda(),
          torch.zeros((ny, nx), dtype=torch.float32, device="cuda")]
     tab_d = None if tab is None else torch.from_numpy(tab).cuda()
     with hr.Context(**(ctx_kwargs or {})) as ctx:
-        regs = [ctx.shadow_alloc(u[0]), ctx.shadow_alloc(u[1])]
+        regs = [ctx.shadow_alloc(u[0], tile=tile), ctx.shadow_alloc(u[1], tile=tile)]
         for L in range(launches):
             ctx.jacobi_check(regs[L % 2], regs[(L + 1) % 2], u[L % 2], u[(L + 1) % 2], tab_d)
             ctx.kernel_end()
@@ -143,13 +182,15 @@ def run_jacobi(torch, hr, ny, nx, launches, tab, ctx_kwargs=None, grid_seed=1):
     return got, st, u, count
 
 
+@pytest.mark.parametrize("tile", TILES, ids=tile_id)
 @pytest.mark.parametrize("ny,nx,launches,count", JACOBI)
-def test_jacobi_flagged_set(env, ny, nx, launches, count):
+def test_jacobi_flagged_set(env, ny, nx, launches, count, tile):
     torch, hr = env
     seeds = si.jacobi_seeds(ny, nx, si.master_seed(1) + nx, count=count)
     tab = si.jacobi_seed_table(ny, nx, seeds)
-    say("jacobi", ny, nx, launches, count)
-    got, st, _, n = run_jacobi(torch, hr, ny, nx, launches, tab, {"count_checks": True})
+    say("jacobi", ny, nx, launches, count, tile_id(tile))
+    got, st, _, n = run_jacobi(torch, hr, ny, nx, launches, tab, {"count_checks": True},
+                               tile=tile)
     log = oracle.model_jacobi(ny, nx, launches, tab)
     assert st == 0
     assert n == log.shape[0]
@@ -332,6 +373,37 @@ def test_launch_epoch_wrap(env):
     assert got == set()
 
 
+@pytest.mark.parametrize("tile", TILES[1:], ids=tile_id)
+def test_ring_overflow_tiled_map(env, tile):
+    """With a ring of one record the global set comes back from the race
+    words, whose tiled offsets (ragged edge tiles included) map back to
+    element indices."""
+    torch, hr = env
+    ny, nx = 70, 45
+    seeds = si.jacobi_seeds(ny, nx, 91, count=6)
+    tab = si.jacobi_seed_table(ny, nx, seeds)
+    want = cf.jacobi_flagged(ny, nx, 3, seeds)
+    assert len(want) > 1
+    say("ring overflow, tiled map", tile_id(tile))
+    got, st, _, _ = run_jacobi(torch, hr, ny, nx, 3, tab, {"ring_capacity": 1}, tile=tile)
+    assert st & hr.HR_W_RING_OVERFLOW
+    assert got == want == oracle.flagged(oracle.model_jacobi(ny, nx, 3, tab))
+
+
+def test_tiled_map_argument_checks(env):
+    torch, hr = env
+    u = torch.zeros((40, 24), dtype=torch.float32, device="cuda")
+    v = torch.zeros((40, 24), dtype=torch.float32, device="cuda")
+    with hr.Context() as ctx:
+        with pytest.raises(hr.HRError):
+            ctx.shadow_alloc(u, tile=(5, 0))           # a tile side above 16
+        # a tiled map whose rows are not the stencil's rows is refused
+        r0 = ctx.shadow_alloc(u.view(24, 40), tile=(2, 2))
+        r1 = ctx.shadow_alloc(v, tile=(2, 2))
+        with pytest.raises(hr.HRError):
+            ctx.jacobi_check(r0, r1, u, v, None)
+
+
 def test_ring_overflow_across_epoch_wrap(env):
     """Races seen only before the launch epoch wraps, with a ring that holds
     one record: the clear at the wrap must not lose the global races that
@@ -366,11 +438,12 @@ def golden(name):
         return json.load(f)
 
 
-def test_jacobi_full_size(env):
+@pytest.mark.parametrize("tile", TILES, ids=tile_id)
+def test_jacobi_full_size(env, tile):
     """4096 x 4096, 16 x 16 blocks, 20 launches, 66 seeded blocks: the flagged
     set equals the oracle's on the whole job's access log (streamed by
     oracle/goldens.py into tests/golden/), and the device access count equals
-    the number of records the oracle checked."""
+    the number of records the oracle checked; under every shadow map."""
     torch, hr = env
     ny = nx = 4096
     launches = 20
@@ -378,9 +451,9 @@ def test_jacobi_full_size(env):
     want = {tuple(k) for k in gold["keys"]}
     seeds = si.jacobi_seeds(ny, nx, si.master_seed(1))
     tab = si.jacobi_seed_table(ny, nx, seeds)
-    say("jacobi full size", ny, nx, launches, len(seeds))
+    say("jacobi full size", ny, nx, launches, len(seeds), tile_id(tile))
     got, st, _, n = run_jacobi(torch, hr, ny, nx, launches, tab, {"count_checks": True},
-                               grid_seed=si.master_seed(1))
+                               grid_seed=si.master_seed(1), tile=tile)
     assert st == 0
     assert got == want and len(want) == gold["flagged"]
     assert n == gold["checks"]

@@ -93,14 +93,20 @@ def test_batch_small_matches_serial_and_oracle(env):
             b.run(spin_limit=1 << 16)
             per = b.split(ctx.flagged())
             assert ctx.status == 0
-            for coalesce in (1, 2):                   # the run's own choice over the context's
-                say("  coalesce", coalesce)
+            # the run's own choice over the context's: off, or a coalescing
+            # width; and the stencil jobs' shadow map (tiles of 4 x 4, 2 x 8,
+            # 16 x 1, then row-major again)
+            for coalesce, tile in ((1, None), (2, (2, 2)), (16, (1, 3)), (64, (4, 0)),
+                                   (8, None)):
+                say("  coalesce", coalesce, "tile", tile)
                 ctx.reset()
-                b.run(spin_limit=1 << 16, coalesce=coalesce)
+                b.run(spin_limit=1 << 16, coalesce=coalesce, tile=tile)
                 assert ctx.status == 0 and b.split(ctx.flagged()) == per
             ctx.reset()
             with pytest.raises(hr.HRError):
                 b.run(coalesce=3)
+            with pytest.raises(hr.HRError):
+                b.run(tile=(5, 0))
     for i, (w, p) in enumerate(zip(want, per)):
         assert p == w, (i, specs[i])
 
@@ -119,12 +125,15 @@ def test_batch_full_manifest(env):
     with hr.Context(ring_capacity=1 << 20) as ctx:
         with hr.Batch(ctx, [j.inst for j in js]) as b:
             say("  workers", b.info(0), b.info(1))
-            b.run(spin_limit=1 << 18)
-            per = b.split(ctx.flagged())
-            say("  status", ctx.status)
-            assert ctx.status == 0
-    for i, (w, p) in enumerate(zip(want, per)):
-        assert p == w, (i, specs[i])
+            for tile in (None, (2, 2), (1, 3)):       # the stencil jobs' shadow maps
+                say("  shadow map", tile)
+                ctx.reset()
+                b.run(spin_limit=1 << 18, tile=tile)
+                per = b.split(ctx.flagged())
+                say("  status", ctx.status)
+                assert ctx.status == 0
+                for i, (w, p) in enumerate(zip(want, per)):
+                    assert p == w, (i, specs[i], tile)
     rng = np.random.default_rng(1)
     for i in rng.choice(len(js), 12, replace=False):
         got, st = js[int(i)].serial(ring_capacity=1 << 20)
