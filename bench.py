@@ -288,8 +288,8 @@ def bench_labelprop(args, torch, si, hr, stream):
     res["roofline"] = {"bound": "hbm", "achieved": alg / avg / 1e9, "peak": HBM_PEAK_GBS,
                        "unit": "GB/s", "frac": alg / avg / 1e9 / HBM_PEAK_GBS,
                        "traffic": counter_traffic(
-                           "k_labelprop<true>", "k_labelprop_check_rmat22_hbm_counters.md"),
-                       "kernel": "k_labelprop<true>", "alg_bytes_per_launch": alg,
+                           "k_labelprop<1>", "k_labelprop_check_rmat22_hbm_counters.md"),
+                       "kernel": "k_labelprop<1>", "alg_bytes_per_launch": alg,
                        "avg_launch_ms": avg * 1e3}
     print(json.dumps(res), flush=True)
 
@@ -656,8 +656,8 @@ def main():
         "plain_p50_launch_ms": pct(plain_ms, 50),
         "flagged": int(flagged_count),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic("k_jacobi<true>"),
-                     "kernel": "k_jacobi<true>", "alg_bytes_per_launch": alg,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic("k_jacobi<1>"),
+                     "kernel": "k_jacobi<1>", "alg_bytes_per_launch": alg,
                      "alg_bytes": "16 B per monitored shadow word (8 B read, 8 B written "
                                   "back), 2 x 4096 x 4096 words",
                      "avg_launch_ms": avg_launch_s * 1e3,

@@ -61,6 +61,9 @@ typedef enum {
      * modulo the field widths; races between accessors whose ids fold
      * together may be missing from the set (none is ever invented). */
     HR_W_FOLDED = 32,
+    /* HR_CFG_ACCESS_LOG only: more accesses than log_capacity; the log holds
+     * the first log_capacity of them (in no particular order). */
+    HR_W_LOG_TRUNCATED = 64,
     HR_E_INVAL = -1,   /* bad argument */
     HR_E_NOMEM = -2,   /* allocation failed or shadow budget exceeded */
     HR_E_HIP = -3,     /* a HIP runtime call failed */
@@ -104,6 +107,10 @@ typedef struct {
                                 within aligned segments of this many lanes
                                 (a power of two, 2..64); 0: 64, the whole
                                 wave.  Must be 0 without the flag. */
+    uint32_t log_capacity;   /* with HR_CFG_ACCESS_LOG: access records kept on
+                                the device, at most 2^28; 0: 2^20.  Must be 0
+                                without the flag. */
+    uint32_t pad;
 } hr_config;
 
 #define HR_SITES 256   /* call-site counters of the report limit */
@@ -128,6 +135,10 @@ typedef struct {
  * launch 0 and the folded block.  The batched and serving executors reject
  * such a context. */
 #define HR_CFG_WORD4 4u
+/* Debug: every hook also appends the access it checks to a bounded device
+ * log (hr_access_log), so that the accesses the checker saw can be compared
+ * one by one with a model of the program.  Implies HR_CFG_COUNT_CHECKS. */
+#define HR_CFG_ACCESS_LOG 8u
 
 /* One flagged location, 48 bytes.  The key is (space, region, block if LDS,
  * index).  The other fields describe how the race was found: `before` and
@@ -294,6 +305,31 @@ hr_status hr_report(hr_ctx c, hr_race* out, size_t cap, size_t* n_out, void* str
 /* Synchronise `stream` and read the checked-access counter (only counts when
  * the context was created with HR_CFG_COUNT_CHECKS). */
 hr_status hr_check_count(hr_ctx c, uint64_t* out, void* stream);
+
+/* One checked access as a hook saw it (HR_CFG_ACCESS_LOG), 32 bytes: the
+ * inputs of the per-access update of Algorithm 1 (Sec. IV-B: the address,
+ * the access kind, the thread and its barrier clocks) plus the launch. */
+typedef struct {
+    uint64_t index;     /* element index (global) or LDS word */
+    uint32_t region;    /* region id (global) or LDS array id */
+    uint32_t block;     /* the accessing logical block (owner of an LDS word) */
+    uint32_t launch;    /* launch sequence number within the job */
+    uint16_t thread;    /* thread within its block */
+    uint8_t space;      /* hr_space */
+    uint8_t kind;       /* hr_kind */
+    uint8_t bc, wc;     /* block and wave clocks */
+    uint16_t site;      /* call-site id */
+    uint32_t pad;
+} hr_access_rec;
+
+/* Synchronise `stream` and copy the access log of a context created with
+ * HR_CFG_ACCESS_LOG into out (host memory, cap records): every access the
+ * hooks checked since the context was created or last reset, in no
+ * particular order.  *n_out receives the number of records held
+ * (min(accesses, log_capacity)).  Returns HR_W_LOG_TRUNCATED when accesses
+ * were dropped, HR_E_INVAL (c or n_out NULL, no log, or cap below *n_out),
+ * HR_E_HIP.  The log is cleared by hr_reset. */
+hr_status hr_access_log(hr_ctx c, hr_access_rec* out, size_t cap, size_t* n_out, void* stream);
 
 /* Host evaluation of the device transition function, for verification of
  * the state machine; not used by the checking path.  space: hr_space; old:

@@ -21,7 +21,7 @@
 // after each step unless s == drop; every thread then writes a[0] to
 // out[lb*T + t].  When n < 2T a thread's step-0 operand was loaded by
 // another thread, so a barrier also follows the loads.
-template <bool CHECK, class G = hr_gref>
+template <int CHECK, class G = hr_gref>
 __device__ void reduce_body(const hr_env& e, const G& gin, const G& gout,
                             const int32_t* __restrict__ in, int32_t* __restrict__ out, uint32_t n,
                             uint32_t T, uint32_t lb, uint32_t t, int32_t drop, int32_t* s,
@@ -48,8 +48,8 @@ __device__ void reduce_body(const hr_env& e, const G& gin, const G& gout,
         const int32_t v0 = one ? in[base + t] : 0;
         const int32_t v1 = two ? in[base + t + T] : 0;
         typename G::pend p0{}, p1{};
-        if (one) p0 = hr_gi<0, CHECK, true>(e, th, gin, base + t, q0);
-        if (two) p1 = hr_gi<0, CHECK, true>(e, th, gin, base + t + T, q1);
+        if (one) p0 = hr_gi<0, CHECK, true>(e, th, gin, base + t, HR_SITE_REDUCE_LOAD, q0);
+        if (two) p1 = hr_gi<0, CHECK, true>(e, th, gin, base + t + T, HR_SITE_REDUCE_LOAD, q1);
         if (one) {
             hr_l<1, CHECK>(e, th, sh, n, lds_id, t, HR_SITE_REDUCE_STAGE);
             s[t] = v0;
@@ -70,7 +70,7 @@ __device__ void reduce_body(const hr_env& e, const G& gin, const G& gout,
             const int32_t y = s[t + h];
             s[t] = x + y;
             if constexpr (CHECK)
-                hr_lds_rrw(e, th, sh, n, lds_id, t, t + h, HR_SITE_REDUCE_LEFT,
+                hr_lds_rrw<CHECK == 2>(e, th, sh, n, lds_id, t, t + h, HR_SITE_REDUCE_LEFT,
                            HR_SITE_REDUCE_RIGHT, HR_SITE_REDUCE_SUM);
         }
         if (step != drop) hr_bar<CHECK>(e, th);
@@ -90,7 +90,7 @@ __device__ void reduce_body(const hr_env& e, const G& gin, const G& gout,
 // min of l into label[u], or for a seeded edge a plain read and plain write
 // of label[u].  grp / gcol: optional monitoring of the CSR reads (shadow
 // null when off).
-template <bool CHECK, bool PAIRS = false, class G = hr_gref>
+template <int CHECK, bool PAIRS = false, class G = hr_gref>
 __device__ void labelprop_body(const hr_env& e, const G& glab, const G& grp, const G& gcol,
                                int32_t* __restrict__ label, const int32_t* __restrict__ rp,
                                const int32_t* __restrict__ col, const uint8_t* __restrict__ mask,
@@ -164,7 +164,7 @@ __device__ void labelprop_body(const hr_env& e, const G& glab, const G& grp, con
                     hr_g<1, CHECK, true>(e, th, glab, ua, HR_SITE_LP_SEED_WRITE);
                 } else {
                     atomicMin(label + ua, l);
-                    pa = hr_gi<2, CHECK, true>(e, th, glab, ua, qa);
+                    pa = hr_gi<2, CHECK, true>(e, th, glab, ua, HR_SITE_LP_MIN, qa);
                 }
             }
             if (two && ub < n) {
@@ -175,7 +175,7 @@ __device__ void labelprop_body(const hr_env& e, const G& glab, const G& grp, con
                     hr_g<1, CHECK, true>(e, th, glab, ub, HR_SITE_LP_SEED_WRITE);
                 } else {
                     atomicMin(label + ub, l);
-                    pb = hr_gi<2, CHECK, true>(e, th, glab, ub, qb);
+                    pb = hr_gi<2, CHECK, true>(e, th, glab, ub, HR_SITE_LP_MIN, qb);
                 }
             }
             hr_gs<2, CHECK>(e, th, glab, pa, ua, HR_SITE_LP_MIN);

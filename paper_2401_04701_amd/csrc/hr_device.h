@@ -34,7 +34,8 @@
 #define HR_CTR_HEAD 0     // ring append index
 #define HR_CTR_FLAGS 1    // warning bits
 #define HR_CTR_SITES 2    // HR_SITES per-site record counters
-#define HR_CTR_WORDS (HR_CTR_SITES + HR_SITES)
+#define HR_CTR_LOG (HR_CTR_SITES + HR_SITES)   // access-log append index
+#define HR_CTR_WORDS (HR_CTR_LOG + 1)
 #define HR_COUNT_SLOTS 256   // checked-access counters, spread by block
 
 // Record appended on a transition into the race state (matches hr_race).
@@ -70,6 +71,9 @@ struct hr_env {
     uint32_t wave_bits;                 // 6: waves synchronize; s < 6: tiles of 2^s lanes
     uint32_t word4;                     // 0: 8-byte global words; else the 4-byte
                                         // word layout (hr::c::layout)
+    hr_access_rec* log;                 // access log (debug), or null; only
+                                        // written while count is not null
+    uint32_t log_cap;
 };
 
 // Shadow layout of a region (the address-to-shadow map): the element at row
@@ -179,9 +183,31 @@ __device__ __forceinline__ hr_thread hr_thread_make(const hr_env& e, uint32_t bl
     return t;
 }
 
+// Append one access to the debug access log.
+__device__ __forceinline__ void hr_log_push(hr_access_rec* log, uint32_t* ctr, uint32_t cap,
+                                         uint64_t index, uint32_t region, uint32_t block,
+                                         uint32_t launch_seq, uint32_t thread, uint32_t tag,
+                                         uint32_t clocks)
+{
+    const uint32_t slot =
+        __hip_atomic_fetch_add(ctr + HR_CTR_LOG, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (slot >= cap) return;
+    // two 16-byte stores of the 32-byte record (layout of hr_access_rec)
+    uint4* p = reinterpret_cast<uint4*>(log + slot);
+    p[0] = make_uint4((uint32_t)index, (uint32_t)(index >> 32), region, block);
+    p[1] = make_uint4(launch_seq, (thread & 0xFFFFu) | (tag << 16), clocks, 0u);
+}
+
 // Debug counting of checked accesses: one atomic per wave and hook, spread
-// over HR_COUNT_SLOTS words by block to avoid a single hot address.
-__device__ __forceinline__ void hr_count(const hr_env& e, const hr_thread& t)
+// over HR_COUNT_SLOTS words by block to avoid a single hot address.  In the
+// hooks instantiated with LOG (the kernels a context with an access log
+// launches), each lane also appends its access (space, region or LDS array,
+// index, kind, call site, and the thread's identity and clocks); the other
+// kernels carry no logging code at all.
+template <bool LOG = false>
+__device__ __forceinline__ void hr_count(const hr_env& e, const hr_thread& t, uint32_t space,
+                                         uint32_t region, uint64_t index, uint32_t kind,
+                                         uint32_t site)
 {
     if (e.count) {
         const uint64_t m = __ballot(1);
@@ -189,6 +215,12 @@ __device__ __forceinline__ void hr_count(const hr_env& e, const hr_thread& t)
             __hip_atomic_fetch_add(e.count + (t.block % HR_COUNT_SLOTS),
                                    (unsigned long long)__popcll(m), __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
+        if constexpr (LOG) {
+            if (e.log)
+                hr_log_push(e.log, e.ctr, e.log_cap, index, region, t.block, e.launch_seq,
+                            t.thread, (space & 0xFFu) | ((kind & 0xFFu) << 8),
+                            (t.bc & 0xFFu) | ((t.wc & 0xFFu) << 8) | ((site & 0xFFFFu) << 16));
+        }
     }
 }
 
@@ -393,13 +425,13 @@ __device__ __forceinline__ void hr_settle(const hr_env& e, const hr_thread& t, u
     }
 }
 
-template <int KIND, bool GROUP = false, bool PRE = false>
+template <int KIND, bool GROUP = false, bool PRE = false, bool LOG = false>
 __device__ __forceinline__ void hr_check(const hr_env& e, const hr_thread& t, uint64_t* shadow,
                                          uint64_t n, uint32_t region, uint64_t index,
                                          uint64_t off, uint32_t site = 0, uint64_t pre = 0)
 {
     if (t.enabled != 1 || !shadow) return;      // thread switched off / region not monitored
-    hr_count(e, t);
+    hr_count<LOG>(e, t, 0, region, index, KIND, site);
     if (index >= n) {
         hr_set_flag(e, HR_DEVF_RANGE);
         return;
@@ -436,14 +468,15 @@ struct hr_pend {
     uint64_t old, nw, r;
 };
 
-template <int KIND, bool PRE = false>
+template <int KIND, bool PRE = false, bool LOG = false>
 __device__ __forceinline__ hr_pend hr_check_issue(const hr_env& e, const hr_thread& t,
-                                                  uint64_t* shadow, uint64_t n, uint64_t index,
-                                                  uint64_t off, uint64_t pre = 0)
+                                                  uint64_t* shadow, uint64_t n, uint32_t region,
+                                                  uint64_t index, uint64_t off, uint32_t site,
+                                                  uint64_t pre = 0)
 {
     hr_pend p{nullptr, 0, 0, 0};
     if (t.enabled != 1 || !shadow) return p;
-    hr_count(e, t);
+    hr_count<LOG>(e, t, 0, region, index, KIND, site);
     if (index >= n) {
         hr_set_flag(e, HR_DEVF_RANGE);
         return p;
@@ -555,13 +588,13 @@ __device__ __forceinline__ void hr_settle4(const hr_env& e, const hr_thread& t, 
 }
 
 // LAY: the word layout as a compile-time constant (0: the context's, e.word4).
-template <int KIND, bool GROUP = false, bool PRE = false, uint32_t LAY = 0>
+template <int KIND, bool GROUP = false, bool PRE = false, uint32_t LAY = 0, bool LOG = false>
 __device__ __forceinline__ void hr_check4(const hr_env& e, const hr_thread& t, uint32_t* shadow,
                                           uint64_t n, uint32_t region, uint64_t index,
                                           uint64_t off, uint32_t site = 0, uint32_t pre = 0)
 {
     if (t.enabled != 1 || !shadow) return;
-    hr_count(e, t);
+    hr_count<LOG>(e, t, 0, region, index, KIND, site);
     if (index >= n) {
         hr_set_flag(e, HR_DEVF_RANGE);
         return;
@@ -597,14 +630,15 @@ struct hr_pend4 {
     uint32_t old, nw, r;
 };
 
-template <int KIND, bool PRE = false, uint32_t LAY = 0>
+template <int KIND, bool PRE = false, uint32_t LAY = 0, bool LOG = false>
 __device__ __forceinline__ hr_pend4 hr_check4_issue(const hr_env& e, const hr_thread& t,
-                                                    uint32_t* shadow, uint64_t n, uint64_t index,
-                                                    uint64_t off, uint32_t pre = 0)
+                                                    uint32_t* shadow, uint64_t n, uint32_t region,
+                                                    uint64_t index, uint64_t off, uint32_t site,
+                                                    uint32_t pre = 0)
 {
     hr_pend4 p{nullptr, 0, 0, 0};
     if (t.enabled != 1 || !shadow) return p;
-    hr_count(e, t);
+    hr_count<LOG>(e, t, 0, region, index, KIND, site);
     if (index >= n) {
         hr_set_flag(e, HR_DEVF_RANGE);
         return p;
@@ -663,13 +697,13 @@ __device__ __forceinline__ void hr_access(const hr_kargs& a, const hr_thread& t,
 // 4-byte shadow words live in LDS at `sh` (n_words of them, cleared to 0 at
 // block start).  LDS atomics are cheap, so this path keeps the
 // compare-and-swap loop.
-template <int KIND>
+template <int KIND, bool LOG = false>
 __device__ __forceinline__ void hr_access_lds(const hr_env& e, const hr_thread& t, uint32_t* sh,
                                               uint32_t n_words, uint32_t array_id, uint32_t index,
                                               uint32_t site = 0)
 {
     if (t.enabled != 1) return;
-    hr_count(e, t);
+    hr_count<LOG>(e, t, 1, array_id, index, KIND, site);
     if (index >= n_words) {
         hr_set_flag(e, HR_DEVF_RANGE);
         return;
@@ -698,15 +732,16 @@ __device__ __forceinline__ void hr_access_lds(const hr_env& e, const hr_thread& 
 // order in which nothing lands between them), and the two words' loads and
 // compare-and-swaps are in flight together, so that the step costs two LDS
 // round trips instead of six.  Sites: read a, read b, write a.
+template <bool LOG = false>
 __device__ __forceinline__ void hr_lds_rrw(const hr_env& e, const hr_thread& t, uint32_t* sh,
                                            uint32_t n_words, uint32_t array_id, uint32_t a,
                                            uint32_t b, uint32_t site_ra, uint32_t site_rb,
                                            uint32_t site_wa)
 {
     if (t.enabled != 1) return;
-    hr_count(e, t);
-    hr_count(e, t);
-    hr_count(e, t);
+    hr_count<LOG>(e, t, 1, array_id, a, 0, site_ra);
+    hr_count<LOG>(e, t, 1, array_id, b, 0, site_rb);
+    hr_count<LOG>(e, t, 1, array_id, a, 1, site_wa);
     if (a >= n_words || b >= n_words) {
         hr_set_flag(e, HR_DEVF_RANGE);
         return;
@@ -752,30 +787,32 @@ __device__ __forceinline__ void hr_lds_rrw(const hr_env& e, const hr_thread& t, 
 }
 
 // Runtime-kind forms (used where the kind is data, as in the interpreter).
+template <bool LOG = false>
 __device__ __forceinline__ void hr_check_k(const hr_env& e, const hr_thread& t, uint32_t kind,
                                            uint64_t* shadow, uint64_t n, uint32_t region,
                                            uint64_t index, uint64_t off, uint32_t site = 0)
 {
     if (e.word4) {
         uint32_t* s4 = (uint32_t*)shadow;
-        if (kind == 0) hr_check4<0, true>(e, t, s4, n, region, index, off, site);
-        else if (kind == 1) hr_check4<1, true>(e, t, s4, n, region, index, off, site);
-        else hr_check4<2, true>(e, t, s4, n, region, index, off, site);
+        if (kind == 0) hr_check4<0, true, false, 0, LOG>(e, t, s4, n, region, index, off, site);
+        else if (kind == 1) hr_check4<1, true, false, 0, LOG>(e, t, s4, n, region, index, off, site);
+        else hr_check4<2, true, false, 0, LOG>(e, t, s4, n, region, index, off, site);
         return;
     }
-    if (kind == 0) hr_check<0, true>(e, t, shadow, n, region, index, off, site);
-    else if (kind == 1) hr_check<1, true>(e, t, shadow, n, region, index, off, site);
-    else hr_check<2, true>(e, t, shadow, n, region, index, off, site);
+    if (kind == 0) hr_check<0, true, false, LOG>(e, t, shadow, n, region, index, off, site);
+    else if (kind == 1) hr_check<1, true, false, LOG>(e, t, shadow, n, region, index, off, site);
+    else hr_check<2, true, false, LOG>(e, t, shadow, n, region, index, off, site);
 }
 
+template <bool LOG = false>
 __device__ __forceinline__ void hr_access_lds_k(const hr_env& e, const hr_thread& t,
                                                 uint32_t kind, uint32_t* sh, uint32_t n_words,
                                                 uint32_t array_id, uint32_t index,
                                                 uint32_t site = 0)
 {
-    if (kind == 0) hr_access_lds<0>(e, t, sh, n_words, array_id, index, site);
-    else if (kind == 1) hr_access_lds<1>(e, t, sh, n_words, array_id, index, site);
-    else hr_access_lds<2>(e, t, sh, n_words, array_id, index, site);
+    if (kind == 0) hr_access_lds<0, LOG>(e, t, sh, n_words, array_id, index, site);
+    else if (kind == 1) hr_access_lds<1, LOG>(e, t, sh, n_words, array_id, index, site);
+    else hr_access_lds<2, LOG>(e, t, sh, n_words, array_id, index, site);
 }
 
 __device__ __forceinline__ void hr_retag(const hr_env& e, hr_thread& t)

@@ -78,7 +78,7 @@ __device__ __forceinline__ void run_item(const hr_env& e, const hr_inst_dev& I, 
     }
     if constexpr ((PATTERNS >> HR_PAT_REDUCE) & 1u) {
         if (I.pattern == HR_PAT_REDUCE) {
-            reduce_body<true>(e, I.g0, I.g1, (const int32_t*)I.p0, (int32_t*)I.p1, I.n, T, lb,
+            reduce_body<1>(e, I.g0, I.g1, (const int32_t*)I.p0, (int32_t*)I.p1, I.n, T, lb,
                               t, I.drop, (int32_t*)lds, lds + I.n, I.lds_id);
             return;
         }
@@ -88,7 +88,7 @@ __device__ __forceinline__ void run_item(const hr_env& e, const hr_inst_dev& I, 
             const bool odd = phase & 1u;
             const float* uo = (const float*)(odd ? I.p1 : I.p0);
             float* un = (float*)(odd ? I.p0 : I.p1);
-            jacobi_body<true>(e, odd ? I.g1 : I.g0, odd ? I.g0 : I.g1, uo, un, I.ny, I.n, I.nbx,
+            jacobi_body<1>(e, odd ? I.g1 : I.g0, odd ? I.g0 : I.g1, uo, un, I.ny, I.n, I.nbx,
                               (const int32_t*)I.p2, lb, t, (float*)lds, lds + JACOBI_TILE_WORDS,
                               I.lds_id);
             return;
@@ -97,7 +97,7 @@ __device__ __forceinline__ void run_item(const hr_env& e, const hr_inst_dev& I, 
     if constexpr ((PATTERNS >> HR_PAT_LABELPROP) & 1u) {
         if (I.pattern == HR_PAT_LABELPROP) {
             const hr_gref none{nullptr, 0, 0};
-            labelprop_body<true>(e, I.g0, none, none, (int32_t*)I.p0, (const int32_t*)I.p1,
+            labelprop_body<1>(e, I.g0, none, none, (int32_t*)I.p0, (const int32_t*)I.p1,
                                  (const int32_t*)I.p2, (const uint8_t*)I.p3, I.n, T, lb, t);
         }
     }

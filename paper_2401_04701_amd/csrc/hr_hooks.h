@@ -1,5 +1,7 @@
 // Hook call sites of the workload bodies: each wrapper calls the device hook
-// when CHECK is set and compiles to nothing in the plain kernels.
+// when CHECK is set and compiles to nothing in the plain kernels (CHECK 0).
+// CHECK 1 is the checking kernel; CHECK 2 the same with the debug access
+// log compiled in (hr_count<LOG>), for contexts made with an access log.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -58,14 +60,14 @@ __host__ __device__ __forceinline__ hr_lay hr_lay_rows(uint32_t cols)
 // Global hook at a lane-affine site (GROUP false) or a data-dependent one.
 // Every global wrapper takes the element as an hr_el, or as an index (then
 // the region's map gives the shadow offset).
-template <int KIND, bool CHECK, bool GROUP = false>
+template <int KIND, int CHECK, bool GROUP = false>
 __device__ __forceinline__ void hr_g(const hr_env& e, const hr_thread& t, const hr_gref& g,
                                      hr_el x, uint32_t site)
 {
-    if constexpr (CHECK) hr_check<KIND, GROUP>(e, t, g.shadow, g.n, g.id, x.index, x.off, site);
+    if constexpr (CHECK) hr_check<KIND, GROUP, false, CHECK == 2>(e, t, g.shadow, g.n, g.id, x.index, x.off, site);
 }
 
-template <int KIND, bool CHECK, bool GROUP = false>
+template <int KIND, int CHECK, bool GROUP = false>
 __device__ __forceinline__ void hr_g(const hr_env& e, const hr_thread& t, const hr_gref& g,
                                      uint64_t index, uint32_t site)
 {
@@ -73,29 +75,29 @@ __device__ __forceinline__ void hr_g(const hr_env& e, const hr_thread& t, const 
 }
 
 // Global hook on a word loaded earlier by hr_gload.
-template <bool CHECK>
+template <int CHECK>
 __device__ __forceinline__ uint64_t hr_gload(const hr_thread& t, const hr_gref& g, hr_el x)
 {
     if constexpr (CHECK) return hr_check_load(t, g.shadow, g.n, x.index, x.off);
     return 0;
 }
 
-template <bool CHECK>
+template <int CHECK>
 __device__ __forceinline__ uint64_t hr_gload(const hr_thread& t, const hr_gref& g, uint64_t index)
 {
     if constexpr (CHECK) return hr_gload<CHECK>(t, g, g.at(index));
     return 0;
 }
 
-template <int KIND, bool CHECK, bool GROUP = true>
+template <int KIND, int CHECK, bool GROUP = true>
 __device__ __forceinline__ void hr_gpre(const hr_env& e, const hr_thread& t, const hr_gref& g,
                                         hr_el x, uint32_t site, uint64_t pre)
 {
     if constexpr (CHECK)
-        hr_check<KIND, GROUP, true>(e, t, g.shadow, g.n, g.id, x.index, x.off, site, pre);
+        hr_check<KIND, GROUP, true, CHECK == 2>(e, t, g.shadow, g.n, g.id, x.index, x.off, site, pre);
 }
 
-template <int KIND, bool CHECK, bool GROUP = true>
+template <int KIND, int CHECK, bool GROUP = true>
 __device__ __forceinline__ void hr_gpre(const hr_env& e, const hr_thread& t, const hr_gref& g,
                                         uint64_t index, uint32_t site, uint64_t pre)
 {
@@ -103,38 +105,39 @@ __device__ __forceinline__ void hr_gpre(const hr_env& e, const hr_thread& t, con
 }
 
 // The two halves of a global hook at a lane-affine site (hr_check_issue /
-// hr_check_settle); `pre` as for hr_gpre when PRE.
-template <int KIND, bool CHECK, bool PRE = false>
+// hr_check_settle; both take the call site); `pre` as for hr_gpre when PRE.
+template <int KIND, int CHECK, bool PRE = false>
 __device__ __forceinline__ hr_pend hr_gi(const hr_env& e, const hr_thread& t, const hr_gref& g,
-                                         hr_el x, uint64_t pre = 0)
+                                         hr_el x, uint32_t site, uint64_t pre = 0)
 {
-    if constexpr (CHECK) return hr_check_issue<KIND, PRE>(e, t, g.shadow, g.n, x.index, x.off, pre);
+    if constexpr (CHECK)
+        return hr_check_issue<KIND, PRE, CHECK == 2>(e, t, g.shadow, g.n, g.id, x.index, x.off, site, pre);
     return hr_pend{nullptr, 0, 0, 0};
 }
 
-template <int KIND, bool CHECK, bool PRE = false>
+template <int KIND, int CHECK, bool PRE = false>
 __device__ __forceinline__ hr_pend hr_gi(const hr_env& e, const hr_thread& t, const hr_gref& g,
-                                         uint64_t index, uint64_t pre = 0)
+                                         uint64_t index, uint32_t site, uint64_t pre = 0)
 {
-    if constexpr (CHECK) return hr_gi<KIND, CHECK, PRE>(e, t, g, g.at(index), pre);
+    if constexpr (CHECK) return hr_gi<KIND, CHECK, PRE>(e, t, g, g.at(index), site, pre);
     return hr_pend{nullptr, 0, 0, 0};
 }
 
-template <int KIND, bool CHECK>
+template <int KIND, int CHECK>
 __device__ __forceinline__ void hr_gs(const hr_env& e, const hr_thread& t, const hr_gref& g,
                                       const hr_pend& p, uint64_t index, uint32_t site)
 {
     if constexpr (CHECK) hr_check_settle<KIND>(e, t, p, g.id, index, site);
 }
 
-template <int KIND, bool CHECK>
+template <int KIND, int CHECK>
 __device__ __forceinline__ void hr_l(const hr_env& e, const hr_thread& t, uint32_t* sh,
                                      uint32_t n, uint32_t id, uint32_t index, uint32_t site)
 {
-    if constexpr (CHECK) hr_access_lds<KIND>(e, t, sh, n, id, index, site);
+    if constexpr (CHECK) hr_access_lds<KIND, CHECK == 2>(e, t, sh, n, id, index, site);
 }
 
-template <bool CHECK>
+template <int CHECK>
 __device__ __forceinline__ void hr_bar(const hr_env& e, hr_thread& t)
 {
     if constexpr (CHECK) hr_barrier_block(e, t);
@@ -142,29 +145,29 @@ __device__ __forceinline__ void hr_bar(const hr_env& e, hr_thread& t)
 }
 
 // The global hooks on 4-byte words.
-template <int KIND, bool CHECK, bool GROUP = false, uint32_t LAY = 0>
+template <int KIND, int CHECK, bool GROUP = false, uint32_t LAY = 0>
 __device__ __forceinline__ void hr_g(const hr_env& e, const hr_thread& t, const hr_gref4t<LAY>& g,
                                      hr_el x, uint32_t site)
 {
     if constexpr (CHECK)
-        hr_check4<KIND, GROUP, false, LAY>(e, t, g.shadow, g.n, g.id, x.index, x.off, site);
+        hr_check4<KIND, GROUP, false, LAY, CHECK == 2>(e, t, g.shadow, g.n, g.id, x.index, x.off, site);
 }
 
-template <int KIND, bool CHECK, bool GROUP = false, uint32_t LAY = 0>
+template <int KIND, int CHECK, bool GROUP = false, uint32_t LAY = 0>
 __device__ __forceinline__ void hr_g(const hr_env& e, const hr_thread& t, const hr_gref4t<LAY>& g,
                                      uint64_t index, uint32_t site)
 {
     if constexpr (CHECK) hr_g<KIND, CHECK, GROUP, LAY>(e, t, g, g.at(index), site);
 }
 
-template <bool CHECK, uint32_t LAY = 0>
+template <int CHECK, uint32_t LAY = 0>
 __device__ __forceinline__ uint32_t hr_gload(const hr_thread& t, const hr_gref4t<LAY>& g, hr_el x)
 {
     if constexpr (CHECK) return hr_check4_load(t, g.shadow, g.n, x.index, x.off);
     return 0;
 }
 
-template <bool CHECK, uint32_t LAY = 0>
+template <int CHECK, uint32_t LAY = 0>
 __device__ __forceinline__ uint32_t hr_gload(const hr_thread& t, const hr_gref4t<LAY>& g,
                                              uint64_t index)
 {
@@ -172,16 +175,16 @@ __device__ __forceinline__ uint32_t hr_gload(const hr_thread& t, const hr_gref4t
     return 0;
 }
 
-template <int KIND, bool CHECK, bool GROUP = true, uint32_t LAY = 0>
+template <int KIND, int CHECK, bool GROUP = true, uint32_t LAY = 0>
 __device__ __forceinline__ void hr_gpre(const hr_env& e, const hr_thread& t,
                                         const hr_gref4t<LAY>& g, hr_el x, uint32_t site,
                                         uint32_t pre)
 {
     if constexpr (CHECK)
-        hr_check4<KIND, GROUP, true, LAY>(e, t, g.shadow, g.n, g.id, x.index, x.off, site, pre);
+        hr_check4<KIND, GROUP, true, LAY, CHECK == 2>(e, t, g.shadow, g.n, g.id, x.index, x.off, site, pre);
 }
 
-template <int KIND, bool CHECK, bool GROUP = true, uint32_t LAY = 0>
+template <int KIND, int CHECK, bool GROUP = true, uint32_t LAY = 0>
 __device__ __forceinline__ void hr_gpre(const hr_env& e, const hr_thread& t,
                                         const hr_gref4t<LAY>& g, uint64_t index, uint32_t site,
                                         uint32_t pre)
@@ -189,25 +192,27 @@ __device__ __forceinline__ void hr_gpre(const hr_env& e, const hr_thread& t,
     if constexpr (CHECK) hr_gpre<KIND, CHECK, GROUP, LAY>(e, t, g, g.at(index), site, pre);
 }
 
-template <int KIND, bool CHECK, bool PRE = false, uint32_t LAY = 0>
+template <int KIND, int CHECK, bool PRE = false, uint32_t LAY = 0>
 __device__ __forceinline__ hr_pend4 hr_gi(const hr_env& e, const hr_thread& t,
-                                          const hr_gref4t<LAY>& g, hr_el x, uint32_t pre = 0)
-{
-    if constexpr (CHECK)
-        return hr_check4_issue<KIND, PRE, LAY>(e, t, g.shadow, g.n, x.index, x.off, pre);
-    return hr_pend4{nullptr, 0, 0, 0};
-}
-
-template <int KIND, bool CHECK, bool PRE = false, uint32_t LAY = 0>
-__device__ __forceinline__ hr_pend4 hr_gi(const hr_env& e, const hr_thread& t,
-                                          const hr_gref4t<LAY>& g, uint64_t index,
+                                          const hr_gref4t<LAY>& g, hr_el x, uint32_t site,
                                           uint32_t pre = 0)
 {
-    if constexpr (CHECK) return hr_gi<KIND, CHECK, PRE, LAY>(e, t, g, g.at(index), pre);
+    if constexpr (CHECK)
+        return hr_check4_issue<KIND, PRE, LAY, CHECK == 2>(e, t, g.shadow, g.n, g.id, x.index, x.off, site,
+                                               pre);
     return hr_pend4{nullptr, 0, 0, 0};
 }
 
-template <int KIND, bool CHECK, uint32_t LAY = 0>
+template <int KIND, int CHECK, bool PRE = false, uint32_t LAY = 0>
+__device__ __forceinline__ hr_pend4 hr_gi(const hr_env& e, const hr_thread& t,
+                                          const hr_gref4t<LAY>& g, uint64_t index, uint32_t site,
+                                          uint32_t pre = 0)
+{
+    if constexpr (CHECK) return hr_gi<KIND, CHECK, PRE, LAY>(e, t, g, g.at(index), site, pre);
+    return hr_pend4{nullptr, 0, 0, 0};
+}
+
+template <int KIND, int CHECK, uint32_t LAY = 0>
 __device__ __forceinline__ void hr_gs(const hr_env& e, const hr_thread& t, const hr_gref4t<LAY>& g,
                                       const hr_pend4& p, uint64_t index, uint32_t site)
 {

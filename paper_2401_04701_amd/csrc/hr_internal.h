@@ -9,6 +9,7 @@
 #include "hr_device.h"
 
 static_assert(sizeof(hr_race) == sizeof(hr_race_rec), "hr_race layout");
+static_assert(sizeof(hr_access_rec) == 32, "hr_access_rec layout");
 
 // One device allocation of shadow words (a region's own, or a batch arena).
 struct hr_alloc {
@@ -38,6 +39,7 @@ struct hr_ctx_s {
     hr_race_rec* ring;
     uint32_t* ctr;
     unsigned long long* count;       // HR_COUNT_SLOTS debug counters
+    hr_access_rec* log;              // access log (HR_CFG_ACCESS_LOG), or null
     uint32_t launch_seq;             // launches since the job started
     uint64_t shadow_bytes;           // live shadow memory
     std::vector<hr_race> carried;    // global races recovered before a shadow clear
@@ -51,7 +53,7 @@ bool hr_config_normalize(const hr_config* cfg, hr_config* out);
 // The hooks' environment of a normalized configuration over the given ring,
 // counters and debug counters, at launch number launch_seq.
 hr_env hr_env_of(const hr_config& cfg, hr_race_rec* ring, uint32_t* ctr,
-                 unsigned long long* count, uint32_t launch_seq);
+                 unsigned long long* count, uint32_t launch_seq, hr_access_rec* log = nullptr);
 hr_env hr_make_env(hr_ctx c);
 void hr_fill_args(hr_ctx c, hr_kargs* a);
 // A region usable through kernel arguments (id < HR_MAX_REGIONS), registered

@@ -19,7 +19,7 @@ constexpr uint32_t JACOBI_TILE_WORDS = JACOBI_TILE * JACOBI_TILE;
 // standalone kernels); without it, in two (the batch and serving workers,
 // which inline every workload body under one register budget: the proxy
 // lanes' second identity would spill there).
-template <bool CHECK, class G = hr_gref, bool ONE_HALO = false>
+template <int CHECK, class G = hr_gref, bool ONE_HALO = false>
 __device__ void jacobi_body(const hr_env& e, const G& gold, const G& gnew,
                             const float* __restrict__ uo, float* __restrict__ un, uint32_t ny,
                             uint32_t nx, uint32_t nbx, const int32_t* __restrict__ seeds,
@@ -59,7 +59,8 @@ __device__ void jacobi_body(const hr_env& e, const G& gold, const G& gnew,
         // in flight.  (The staging hook comes before its store: the store
         // needs the loaded value, and waiting for it waits for the exchange
         // too.)
-        const typename G::pend pc = hr_gi<0, CHECK>(e, th, gold, gold.at2(gy, gx, g));
+        const typename G::pend pc = hr_gi<0, CHECK>(e, th, gold, gold.at2(gy, gx, g),
+                                                      HR_SITE_JACOBI_CENTRE);
         hr_l<1, CHECK>(e, th, tsh, TW, lds_id, cl, HR_SITE_JACOBI_STAGE);
         tile[cl] = vc;
         hr_gs<0, CHECK>(e, th, gold, pc, g, HR_SITE_JACOBI_CENTRE);
@@ -71,7 +72,8 @@ __device__ void jacobi_body(const hr_env& e, const G& gold, const G& gnew,
         if (hn || hs) {
             const uint32_t lr = lrow();
             const typename G::pend pr =
-                hr_gi<0, CHECK>(e, th, gold, gold.at2(hn ? gy - 1 : gy + 1, gx, gr));
+                hr_gi<0, CHECK>(e, th, gold, gold.at2(hn ? gy - 1 : gy + 1, gx, gr),
+                                HR_SITE_JACOBI_HALO);
             hr_l<1, CHECK>(e, th, tsh, TW, lds_id, lr, HR_SITE_JACOBI_STAGE);
             tile[lr] = vr;
             hr_gs<0, CHECK>(e, th, gold, pr, gr, HR_SITE_JACOBI_HALO);
@@ -79,7 +81,8 @@ __device__ void jacobi_body(const hr_env& e, const G& gold, const G& gnew,
         if (hw || he) {
             const uint32_t lc = lcol();
             const typename G::pend pk =
-                hr_gi<0, CHECK>(e, th, gold, gold.at2(gy, hw ? gx - 1 : gx + 1, gc));
+                hr_gi<0, CHECK>(e, th, gold, gold.at2(gy, hw ? gx - 1 : gx + 1, gc),
+                                HR_SITE_JACOBI_HALO);
             hr_l<1, CHECK>(e, th, tsh, TW, lds_id, lc, HR_SITE_JACOBI_STAGE);
             tile[lc] = vk;
             hr_gs<0, CHECK>(e, th, gold, pk, gc, HR_SITE_JACOBI_HALO);
@@ -114,7 +117,8 @@ __device__ void jacobi_body(const hr_env& e, const G& gold, const G& gnew,
             }
         }
         if (on) {
-            const typename G::pend ph = hr_gi<0, CHECK>(e, hth, gold, gold.at2(hy, hx, ha));
+            const typename G::pend ph = hr_gi<0, CHECK>(e, hth, gold, gold.at2(hy, hx, ha),
+                                                                 HR_SITE_JACOBI_HALO);
             if (hn || hs) {
                 hr_l<1, CHECK>(e, th, tsh, TW, lds_id, lr, HR_SITE_JACOBI_STAGE);
                 tile[lr] = vr;
@@ -195,9 +199,10 @@ struct hr_gref_map : hr_gref {
 
 namespace {
 
-// One 16 x 16 tile per hardware block, on row-major shadow maps.  8 waves per
-// SIMD: the hook's scalar registers would otherwise cap the occupancy at 7.
-template <bool CHECK>
+// One 16 x 16 tile per hardware block, on row-major shadow maps (CHECK 0:
+// plain, 1: checked).  8 waves per SIMD: the hook's scalar registers would
+// otherwise cap the occupancy at 7.
+template <int CHECK>
 __global__ __launch_bounds__(256, 8) void k_jacobi(hr_kargs a, hr_gref gold, hr_gref gnew,
                                                 const float* __restrict__ uo,
                                                 float* __restrict__ un, uint32_t ny, uint32_t nx,
@@ -212,7 +217,8 @@ __global__ __launch_bounds__(256, 8) void k_jacobi(hr_kargs a, hr_gref gold, hr_
 
 // The checked sweep on tiled shadow maps: both grids tiled by 2^TW x 2^TH
 // (constant shifts), or TW < 0: each grid's own map, read at run time.
-template <int TW, int TH>
+// CHECK 2: with the debug access log (any map; row-major maps run here too).
+template <int TW, int TH, int CHECK = 1>
 __global__ __launch_bounds__(256, 8) void k_jacobi_tiled(hr_kargs a, hr_gref gold, hr_gref gnew,
                                                          const float* __restrict__ uo,
                                                          float* __restrict__ un, uint32_t ny,
@@ -222,15 +228,15 @@ __global__ __launch_bounds__(256, 8) void k_jacobi_tiled(hr_kargs a, hr_gref gol
     __shared__ float tile[JACOBI_TILE_WORDS];
     __shared__ uint32_t tsh[JACOBI_TILE_WORDS];
     using G = hr_gref_map<TW, TH>;
-    jacobi_body<true, G, true>(a.env, G{gold}, G{gnew}, uo, un, ny, nx, gridDim.x, seeds,
+    jacobi_body<CHECK, G, true>(a.env, G{gold}, G{gnew}, uo, un, ny, nx, gridDim.x, seeds,
                                blockIdx.y * gridDim.x + blockIdx.x, threadIdx.x, tile, tsh, 0);
 }
 
 // The checked sweep on 4-byte shadow words, with the word layout as a
-// constant (LAY) or the context's (LAY = 0).  With a constant layout it fits
+// constant (LAY) or the context's (LAY = 0); CHECK 2 adds the access log.  With a constant layout it fits
 // 8 waves per SIMD; the context-layout kernel needs a few more registers
 // and runs 7.
-template <uint32_t LAY>
+template <uint32_t LAY, int CHECK = 1>
 __global__ __launch_bounds__(256, LAY ? 8 : 7) void k_jacobi4(hr_kargs a, hr_gref4t<LAY> gold,
                                                  hr_gref4t<LAY> gnew,
                                                  const float* __restrict__ uo,
@@ -239,7 +245,7 @@ __global__ __launch_bounds__(256, LAY ? 8 : 7) void k_jacobi4(hr_kargs a, hr_gre
 {
     __shared__ float tile[JACOBI_TILE_WORDS];
     __shared__ uint32_t tsh[JACOBI_TILE_WORDS];
-    jacobi_body<true, hr_gref4t<LAY>, true>(a.env, gold, gnew, uo, un, ny, nx, gridDim.x, seeds,
+    jacobi_body<CHECK, hr_gref4t<LAY>, true>(a.env, gold, gnew, uo, un, ny, nx, gridDim.x, seeds,
                                             blockIdx.y * gridDim.x + blockIdx.x, threadIdx.x,
                                             tile, tsh, 0);
 }

@@ -150,12 +150,14 @@ hipStream_t hr_stream(hr_ctx c, void* stream)
 }
 
 hr_env hr_env_of(const hr_config& cfg, hr_race_rec* ring, uint32_t* ctr,
-                 unsigned long long* count, uint32_t launch_seq)
+                 unsigned long long* count, uint32_t launch_seq, hr_access_rec* log)
 {
     hr_env e{};
     e.ring = ring;
     e.ctr = ctr;
-    e.count = (cfg.flags & HR_CFG_COUNT_CHECKS) ? count : nullptr;
+    e.count = (cfg.flags & (HR_CFG_COUNT_CHECKS | HR_CFG_ACCESS_LOG)) ? count : nullptr;
+    e.log = (cfg.flags & HR_CFG_ACCESS_LOG) ? log : nullptr;
+    e.log_cap = e.log ? cfg.log_capacity : 0u;
     e.ring_cap = cfg.ring_capacity;
     e.launch = launch_seq & ((1u << hr::g::LAUNCH_BITS) - 1);
     e.launch_seq = launch_seq;
@@ -172,7 +174,7 @@ hr_env hr_env_of(const hr_config& cfg, hr_race_rec* ring, uint32_t* ctr,
 
 hr_env hr_make_env(hr_ctx c)
 {
-    return hr_env_of(c->cfg, c->ring, c->ctr, c->count, c->launch_seq);
+    return hr_env_of(c->cfg, c->ring, c->ctr, c->count, c->launch_seq, c->log);
 }
 
 void hr_fill_args(hr_ctx c, hr_kargs* a)
@@ -244,7 +246,15 @@ bool hr_config_normalize(const hr_config* cfg, hr_config* out)
     if (k.thread_bits == 0) k.thread_bits = word4 ? 8 : 10;
     if (k.bc_bits > 8 || k.wc_bits > 6 || k.ring_capacity > (1u << 26)) return false;
     if (k.thread_bits > 10 || (!word4 && k.thread_bits != 10)) return false;
-    if (k.flags & ~(HR_CFG_COUNT_CHECKS | HR_CFG_WAVE_GROUPING | HR_CFG_WORD4)) return false;
+    if (k.flags &
+        ~(HR_CFG_COUNT_CHECKS | HR_CFG_WAVE_GROUPING | HR_CFG_WORD4 | HR_CFG_ACCESS_LOG))
+        return false;
+    if (k.flags & HR_CFG_ACCESS_LOG) {
+        if (k.log_capacity == 0) k.log_capacity = 1u << 20;
+        if (k.log_capacity > (1u << 28)) return false;
+    } else if (k.log_capacity) {
+        return false;   // a log size without the log
+    }
     if (k.wave_bits == 0) k.wave_bits = 6;
     if (k.wave_bits > 6) return false;
     if (k.flags & HR_CFG_WAVE_GROUPING) {
@@ -273,7 +283,9 @@ extern "C" hr_status hr_ctx_create(hr_ctx* out, const hr_config* cfg, void* stre
     }
     if (hipMalloc(&c->ring, sizeof(hr_race_rec) * (size_t)k.ring_capacity) != hipSuccess ||
         hipMalloc(&c->ctr, sizeof(uint32_t) * HR_CTR_WORDS) != hipSuccess ||
-        hipMalloc(&c->count, sizeof(unsigned long long) * HR_COUNT_SLOTS) != hipSuccess) {
+        hipMalloc(&c->count, sizeof(unsigned long long) * HR_COUNT_SLOTS) != hipSuccess ||
+        ((k.flags & HR_CFG_ACCESS_LOG) &&
+         hipMalloc(&c->log, sizeof(hr_access_rec) * (size_t)k.log_capacity) != hipSuccess)) {
         hr_ctx_destroy(c);
         return HR_E_NOMEM;
     }
@@ -295,6 +307,7 @@ extern "C" hr_status hr_ctx_destroy(hr_ctx c)
     if (c->ring) (void)hipFree(c->ring);
     if (c->ctr) (void)hipFree(c->ctr);
     if (c->count) (void)hipFree(c->count);
+    if (c->log) (void)hipFree(c->log);
     delete c;
     return e == hipSuccess ? HR_OK : HR_E_HIP;
 }
@@ -502,6 +515,22 @@ extern "C" hr_status hr_check_count(hr_ctx c, uint64_t* out, void* stream)
     for (int i = 0; i < HR_COUNT_SLOTS; ++i) sum += slots[i];
     *out = sum;
     return HR_OK;
+}
+
+extern "C" hr_status hr_access_log(hr_ctx c, hr_access_rec* out, size_t cap, size_t* n_out,
+                                   void* stream)
+{
+    if (!c || !n_out || !c->log) return HR_E_INVAL;
+    if (hipStreamSynchronize(hr_stream(c, stream)) != hipSuccess) return HR_E_HIP;
+    uint32_t head = 0;
+    if (hipMemcpy(&head, c->ctr + HR_CTR_LOG, sizeof(head), hipMemcpyDeviceToHost) != hipSuccess)
+        return HR_E_HIP;
+    const size_t n = std::min<size_t>(head, c->cfg.log_capacity);
+    *n_out = n;
+    if (n > cap || (n && !out)) return HR_E_INVAL;
+    if (n && hipMemcpy(out, c->log, sizeof(hr_access_rec) * n, hipMemcpyDeviceToHost) != hipSuccess)
+        return HR_E_HIP;
+    return head > c->cfg.log_capacity ? HR_W_LOG_TRUNCATED : HR_OK;
 }
 
 extern "C" hr_status hr_fsm_step(uint32_t space, uint64_t old, uint32_t kind, uint32_t launch,

@@ -274,6 +274,7 @@ hr_status serve_continuous(hr_ctx c, const hr_instance* jobs, hr_serve_job* time
         env[k].ring = L.ring;
         env[k].ctr = L.ctr;
         env[k].site_limit = 0;   // site ids are per job; the limit does not apply here
+        env[k].log = nullptr;    // nor does the access log: lane counters restart per iteration
     }
     arena_alloc arena(arena_granules);
     std::vector<uint32_t> free_slots;

@@ -46,7 +46,8 @@ bool lay_fits(const hr_kargs& a, uint32_t r, uint32_t nx)
     return (L.tw | L.th) == 0 || L.cols == nx;
 }
 
-template <bool CHECK>
+// CHECK 0: plain, 1: checked, 2: checked with the debug access log.
+template <int CHECK>
 __global__ __launch_bounds__(1024) void k_reduce(hr_kargs a, hr_gref gin, hr_gref gout,
                                                  const int32_t* __restrict__ in,
                                                  int32_t* __restrict__ out, uint32_t n,
@@ -57,7 +58,7 @@ __global__ __launch_bounds__(1024) void k_reduce(hr_kargs a, hr_gref gin, hr_gre
                        (int32_t*)smem, smem + n, 0);
 }
 
-template <bool CHECK>
+template <int CHECK>
 __global__ __launch_bounds__(1024) void k_labelprop(hr_kargs a, hr_gref glab, hr_gref grp,
                                                     hr_gref gcol, int32_t* __restrict__ label,
                                                     const int32_t* __restrict__ rp,
@@ -69,24 +70,26 @@ __global__ __launch_bounds__(1024) void k_labelprop(hr_kargs a, hr_gref glab, hr
 }
 
 // The checked kernels on 4-byte shadow words.
+template <int CHECK = 1>
 __global__ __launch_bounds__(1024) void k_reduce4(hr_kargs a, hr_gref4 gin, hr_gref4 gout,
                                                   const int32_t* __restrict__ in,
                                                   int32_t* __restrict__ out, uint32_t n,
                                                   int32_t drop)
 {
     extern __shared__ uint32_t smem[];
-    reduce_body<true>(a.env, gin, gout, in, out, n, blockDim.x, blockIdx.x, threadIdx.x, drop,
-                      (int32_t*)smem, smem + n, 0);
+    reduce_body<CHECK>(a.env, gin, gout, in, out, n, blockDim.x, blockIdx.x, threadIdx.x, drop,
+                       (int32_t*)smem, smem + n, 0);
 }
 
+template <int CHECK = 1>
 __global__ __launch_bounds__(1024) void k_labelprop4(hr_kargs a, hr_gref4 glab, hr_gref4 grp,
                                                      hr_gref4 gcol, int32_t* __restrict__ label,
                                                      const int32_t* __restrict__ rp,
                                                      const int32_t* __restrict__ col,
                                                      const uint8_t* __restrict__ mask, uint32_t n)
 {
-    labelprop_body<true, true>(a.env, glab, grp, gcol, label, rp, col, mask, n, blockDim.x,
-                               blockIdx.x, threadIdx.x);
+    labelprop_body<CHECK, true>(a.env, glab, grp, gcol, label, rp, col, mask, n, blockDim.x,
+                                blockIdx.x, threadIdx.x);
 }
 
 // ----------------------------------------------------------- interpreter
@@ -94,6 +97,7 @@ struct prog_map {
     uint32_t r[8];
 };
 
+template <bool LOG = false>
 __global__ __launch_bounds__(1024) void k_program(hr_kargs a, prog_map pm, uint32_t blocks,
                                                   uint32_t threads, uint32_t phases,
                                                   const uint8_t* __restrict__ scope,
@@ -140,7 +144,7 @@ __global__ __launch_bounds__(1024) void k_program(hr_kargs a, prog_map pm, uint3
                 if (kind == 0) (void)*(volatile uint32_t*)(ldata + idx);
                 else if (kind == 1) ldata[idx] = t + 1;
                 else atomicAdd(ldata + idx, 1u);
-                hr_access_lds_k(a.env, th, kind, lsh, lds_words, 0, idx, p + 1);
+                hr_access_lds_k<LOG>(a.env, th, kind, lsh, lds_words, 0, idx, p + 1);
             } else {
                 const uint32_t r = pm.r[reg];
                 if (r >= HR_MAX_REGIONS || idx >= a.n_elems[r]) {
@@ -151,7 +155,7 @@ __global__ __launch_bounds__(1024) void k_program(hr_kargs a, prog_map pm, uint3
                 if (kind == 0) (void)*(volatile uint32_t*)(d + idx);
                 else if (kind == 1) d[idx] = t + 1;
                 else atomicAdd(d + idx, 1u);
-                hr_check_k(a.env, th, kind, a.shadow[r], a.n_elems[r], r, idx,
+                hr_check_k<LOG>(a.env, th, kind, a.shadow[r], a.n_elems[r], r, idx,
                            hr_lay_off(a.lay[r], idx), p + 1);
             }
         }
@@ -190,12 +194,14 @@ hr_status hr_launch_reduce(const hr_kargs& a, uint32_t r_in, uint32_t r_out, con
                            int32_t drop, hipStream_t s)
 {
     if (!in_dev || !out_dev || !reduce_shape_ok(n, threads, blocks)) return HR_E_INVAL;
+    // a context with an access log runs the kernels that write it
+    const bool log = a.env.log != nullptr;
     if (a.env.word4)
-        HR_LAUNCH(k_reduce4, dim3(blocks), dim3(threads), (size_t)n * 8, s, a, gref4(a, r_in),
-                  gref4(a, r_out), in_dev, out_dev, n, drop);
+        HR_LAUNCH(log ? k_reduce4<2> : k_reduce4<1>, dim3(blocks), dim3(threads), (size_t)n * 8, s,
+                  a, gref4(a, r_in), gref4(a, r_out), in_dev, out_dev, n, drop);
     else
-        HR_LAUNCH(k_reduce<true>, dim3(blocks), dim3(threads), (size_t)n * 8, s, a,
-                  gref(a, r_in), gref(a, r_out), in_dev, out_dev, n, drop);
+        HR_LAUNCH(log ? k_reduce<2> : k_reduce<1>, dim3(blocks), dim3(threads), (size_t)n * 8, s,
+                  a, gref(a, r_in), gref(a, r_out), in_dev, out_dev, n, drop);
     return HR_OK;
 }
 
@@ -204,7 +210,7 @@ extern "C" hr_status hr_reduce_plain(const int32_t* in_dev, int32_t* out_dev, ui
 {
     if (!in_dev || !out_dev || !reduce_shape_ok(n, threads, blocks)) return HR_E_INVAL;
     hr_kargs a{};
-    HR_LAUNCH(k_reduce<false>, dim3(blocks), dim3(threads), (size_t)n * 4, (hipStream_t)stream, a,
+    HR_LAUNCH(k_reduce<0>, dim3(blocks), dim3(threads), (size_t)n * 4, (hipStream_t)stream, a,
               hr_gref{}, hr_gref{}, in_dev, out_dev, n, drop);
     return HR_OK;
 }
@@ -238,7 +244,13 @@ hr_status hr_launch_jacobi(const hr_kargs& a, uint32_t r_old, uint32_t r_new,
     if (!lay_fits(a, r_old, nx) || !lay_fits(a, r_new, nx)) return HR_E_INVAL;
     const dim3 grid((nx + 15) / 16, (ny + 15) / 16);
     constexpr uint32_t DL = hr::c::DEFAULT_LAYOUT;
-    if (a.env.word4 == DL)
+    if (a.env.log && a.env.word4)   // the kernels with the access log: any map
+        HR_LAUNCH((k_jacobi4<0, 2>), grid, dim3(256), 0, s, a, gref4(a, r_old, nx),
+                  gref4(a, r_new, nx), u_old_dev, u_new_dev, ny, nx, seed_dev);
+    else if (a.env.log)
+        HR_LAUNCH((k_jacobi_tiled<-1, -1, 2>), grid, dim3(256), 0, s, a, gref(a, r_old, nx),
+                  gref(a, r_new, nx), u_old_dev, u_new_dev, ny, nx, seed_dev);
+    else if (a.env.word4 == DL)
         HR_LAUNCH(k_jacobi4<DL>, grid, dim3(256), 0, s, a, gref4<DL>(a, r_old, nx),
                   gref4<DL>(a, r_new, nx), u_old_dev, u_new_dev, ny, nx, seed_dev);
     else if (a.env.word4)
@@ -249,7 +261,7 @@ hr_status hr_launch_jacobi(const hr_kargs& a, uint32_t r_old, uint32_t r_new,
         const hr_lay &lo = a.lay[r_old], &ln = a.lay[r_new];
         const uint32_t to = lo.tw | lo.th << 4, tn = ln.tw | ln.th << 4;
         auto k = k_jacobi_tiled<-1, -1>;
-        if (to == 0 && tn == 0) k = k_jacobi<true>;
+        if (to == 0 && tn == 0) k = k_jacobi<1>;
         else if (to == tn && to == (2u | 2u << 4)) k = k_jacobi_tiled<2, 2>;
         else if (to == tn && to == (2u | 1u << 4)) k = k_jacobi_tiled<2, 1>;
         else if (to == tn && to == (3u | 1u << 4)) k = k_jacobi_tiled<3, 1>;
@@ -265,7 +277,7 @@ extern "C" hr_status hr_jacobi_plain(const float* u_old_dev, float* u_new_dev, u
     if (!u_old_dev || !u_new_dev || !jacobi_shape_ok(ny, nx)) return HR_E_INVAL;
     hr_kargs a{};
     const dim3 grid((nx + 15) / 16, (ny + 15) / 16);
-    HR_LAUNCH(k_jacobi<false>, grid, dim3(256), 0, (hipStream_t)stream, a, hr_gref{}, hr_gref{},
+    HR_LAUNCH(k_jacobi<0>, grid, dim3(256), 0, (hipStream_t)stream, a, hr_gref{}, hr_gref{},
               u_old_dev, u_new_dev, ny, nx, seed_dev);
     return HR_OK;
 }
@@ -301,16 +313,19 @@ hr_status hr_launch_labelprop(const hr_kargs& a, uint32_t r_label, uint32_t r_ro
 {
     if (!label_dev || !row_ptr_dev || !col_dev || !mask_dev || !labelprop_shape_ok(n, tpb))
         return HR_E_INVAL;
+    const bool log = a.env.log != nullptr;
     if (a.env.word4) {
         const hr_gref4 none{nullptr, 0, 0};
-        HR_LAUNCH(k_labelprop4, dim3((n + tpb - 1) / tpb), dim3(tpb), 0, s, a, gref4(a, r_label),
+        HR_LAUNCH(log ? k_labelprop4<2> : k_labelprop4<1>, dim3((n + tpb - 1) / tpb), dim3(tpb),
+                  0, s, a, gref4(a, r_label),
                   r_row_ptr != UINT32_MAX ? gref4(a, r_row_ptr) : none,
                   r_col != UINT32_MAX ? gref4(a, r_col) : none, label_dev, row_ptr_dev, col_dev,
                   mask_dev, n);
         return HR_OK;
     }
     const hr_gref none{nullptr, 0, 0};
-    HR_LAUNCH(k_labelprop<true>, dim3((n + tpb - 1) / tpb), dim3(tpb), 0, s, a, gref(a, r_label),
+    HR_LAUNCH(log ? k_labelprop<2> : k_labelprop<1>, dim3((n + tpb - 1) / tpb), dim3(tpb), 0, s,
+              a, gref(a, r_label),
               r_row_ptr != UINT32_MAX ? gref(a, r_row_ptr) : none,
               r_col != UINT32_MAX ? gref(a, r_col) : none, label_dev, row_ptr_dev, col_dev,
               mask_dev, n);
@@ -324,7 +339,7 @@ extern "C" hr_status hr_labelprop_plain(int32_t* label_dev, const int32_t* row_p
     if (!label_dev || !row_ptr_dev || !col_dev || !mask_dev || !labelprop_shape_ok(n, tpb))
         return HR_E_INVAL;
     hr_kargs a{};
-    HR_LAUNCH(k_labelprop<false>, dim3((n + tpb - 1) / tpb), dim3(tpb), 0, (hipStream_t)stream, a,
+    HR_LAUNCH(k_labelprop<0>, dim3((n + tpb - 1) / tpb), dim3(tpb), 0, (hipStream_t)stream, a,
               hr_gref{}, hr_gref{}, hr_gref{}, label_dev, row_ptr_dev, col_dev, mask_dev, n);
     return HR_OK;
 }
@@ -354,7 +369,8 @@ extern "C" hr_status hr_program_check(hr_ctx c, const uint32_t* regions_host, ui
     hr_kargs a;
     hr_fill_args(c, &a);
     const size_t lds_bytes = (size_t)lds_words * 2 * sizeof(uint32_t);
-    HR_LAUNCH(k_program, dim3(blocks), dim3(threads), lds_bytes, hr_stream(c, stream), a,
+    HR_LAUNCH(a.env.log ? k_program<true> : k_program<false>, dim3(blocks), dim3(threads),
+              lds_bytes, hr_stream(c, stream), a,
                        pm, blocks, threads, phases, scope_dev, wave_mask_dev, op_off_dev, n_op_off,
                        ops_dev, n_ops, block_map_dev, lds_words);
     return HR_OK;

@@ -21,6 +21,7 @@ HR_W_OUT_OF_RANGE = 4
 HR_W_STALLED = 8
 HR_W_REPORT_LIMITED = 16
 HR_W_FOLDED = 32
+HR_W_LOG_TRUNCATED = 64
 HR_RACE_FOLD, HR_RACE_SCANNED = 1, 2
 HR_S_INIT, HR_S_RACE, HR_S_BLOCKS, HR_S_WAVES, HR_S_THREADS, HR_S_THREAD = range(6)
 HR_E_INVAL, HR_E_NOMEM, HR_E_HIP, HR_E_STATE = -1, -2, -3, -4
@@ -29,6 +30,7 @@ HR_READ, HR_WRITE, HR_ATOMIC = 0, 1, 2
 HR_CFG_COUNT_CHECKS = 1
 HR_CFG_WAVE_GROUPING = 2
 HR_CFG_WORD4 = 4
+HR_CFG_ACCESS_LOG = 8
 NO_REGION = 0xFFFFFFFF
 HR_PAT_REDUCE, HR_PAT_JACOBI, HR_PAT_LABELPROP = 0, 1, 2
 HR_SITES = 256
@@ -57,6 +59,12 @@ RACE_DTYPE = np.dtype([("space", np.uint8), ("kind", np.uint8), ("site", np.uint
                        ("index", np.uint64), ("before", np.uint64), ("with", np.uint64),
                        ("tid", np.uint32), ("flags", np.uint32)])
 assert RACE_DTYPE.itemsize == 48
+# hr_access_rec: one checked access of the debug access log
+ACCESS_DTYPE = np.dtype([("index", np.uint64), ("region", np.uint32), ("block", np.uint32),
+                         ("launch", np.uint32), ("thread", np.uint16), ("space", np.uint8),
+                         ("kind", np.uint8), ("bc", np.uint8), ("wc", np.uint8),
+                         ("site", np.uint16), ("pad", np.uint32)])
+assert ACCESS_DTYPE.itemsize == 32
 
 
 class HRError(RuntimeError):
@@ -70,7 +78,8 @@ class _Config(ctypes.Structure):
                 ("wc_bits", ctypes.c_uint32), ("flags", ctypes.c_uint32),
                 ("shadow_budget", ctypes.c_uint64), ("site_limit", ctypes.c_uint32),
                 ("wave_bits", ctypes.c_uint32), ("thread_bits", ctypes.c_uint32),
-                ("coalesce_width", ctypes.c_uint32)]
+                ("coalesce_width", ctypes.c_uint32), ("log_capacity", ctypes.c_uint32),
+                ("pad", ctypes.c_uint32)]
 
 
 class Summary(ctypes.Structure):
@@ -140,6 +149,7 @@ def _load():
         "hr_reset": [P, P],
         "hr_report": [P, P, sz, P, P],
         "hr_check_count": [P, P, P],
+        "hr_access_log": [P, P, sz, P, P],
         "hr_fsm_step": [u32, u64, u32, u32, u32, u32, u32, u32, u32, P],
         "hr_fsm_merge": [u64, u64, u32, P],
         "hr_describe": [u32, u64, u32, P],
@@ -177,7 +187,8 @@ EXPORTED = ("hr_ctx_create", "hr_ctx_destroy", "hr_shadow_alloc", "hr_shadow_all
             "hr_region_enable",
             "hr_dev_args", "hr_batch_create", "hr_batch_run", "hr_batch_info",
             "hr_batch_destroy", "hr_job_run", "hr_job_run_static", "hr_serve",
-            "hr_kernel_end", "hr_reset", "hr_report", "hr_check_count", "hr_fsm_step", "hr_fsm_merge",
+            "hr_kernel_end", "hr_reset", "hr_report", "hr_check_count", "hr_access_log",
+            "hr_fsm_step", "hr_fsm_merge",
             "hr_describe", "hr_fsm_step_word4", "hr_word4_widen",
             "hr_reduce_check", "hr_reduce_plain", "hr_jacobi_check", "hr_jacobi_plain",
             "hr_labelprop_check", "hr_labelprop_plain", "hr_program_check",
@@ -315,12 +326,14 @@ class Context:
 
     def __init__(self, ring_capacity=0, bc_bits=0, wc_bits=0, count_checks=False,
                  shadow_budget=0, wave_grouping=False, site_limit=0, wave_bits=0,
-                 word4=False, thread_bits=0, coalesce_width=0, stream=None):
+                 word4=False, thread_bits=0, coalesce_width=0, access_log=False,
+                 log_capacity=0, stream=None):
         flags = (HR_CFG_COUNT_CHECKS if count_checks else 0) | \
                 (HR_CFG_WAVE_GROUPING if wave_grouping else 0) | \
-                (HR_CFG_WORD4 if word4 else 0)
+                (HR_CFG_WORD4 if word4 else 0) | \
+                (HR_CFG_ACCESS_LOG if access_log else 0)
         cfg = _Config(ring_capacity, bc_bits, wc_bits, flags, shadow_budget, site_limit,
-                      wave_bits, thread_bits, coalesce_width)
+                      wave_bits, thread_bits, coalesce_width, log_capacity, 0)
         self.wave_bits = wave_bits or 6
         self._c = ctypes.c_void_p(0)
         self._stream = _stream_ptr(stream)
@@ -408,6 +421,20 @@ class Context:
         return int(out.value)
 
     # ------------------------------------------------------- workloads
+    def access_log(self, stream=None):
+        """The debug access log (a context made with access_log=True): one
+        ACCESS_DTYPE record per checked access, unordered.  Returns
+        (records, warning bits)."""
+        n = ctypes.c_size_t(0)
+        st = _lib.hr_access_log(self._c, None, 0, ctypes.byref(n), _stream_ptr(stream))
+        if st == HR_E_INVAL and n.value == 0:
+            _check("hr_access_log", st)
+        out = np.zeros(n.value, dtype=ACCESS_DTYPE)
+        st = _lib.hr_access_log(self._c, out.ctypes.data_as(ctypes.c_void_p), n.value,
+                                ctypes.byref(n), _stream_ptr(stream))
+        _check("hr_access_log", st)
+        return out[:n.value], st
+
     def shadow_free(self, region: int):
         _check("hr_shadow_free", _lib.hr_shadow_free(self._c, region))
 
