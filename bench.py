@@ -480,6 +480,9 @@ def main():
     ap.add_argument("--rates", default="100,250,500,1000,2500,5000",
                     help="serving: arrival rates in jobs/s")
     ap.add_argument("--serve-jobs", type=int, default=2000, help="serving: jobs per stream")
+    ap.add_argument("--calibration-copy", action="store_true",
+                    help="first copy 256 MiB once with the library's copy kernel, the "
+                         "calibration of the HBM byte counters of a counter run")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the checker runs each job on a single device "
@@ -493,6 +496,12 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    if args.calibration_copy:
+        src = torch.empty(1 << 28, dtype=torch.uint8, device="cuda").random_(0, 255)
+        dst = torch.empty_like(src)
+        hr.peak_copy(src, dst)
+        torch.cuda.synchronize()
+        del src, dst
     if args.workload == "labelprop":
         return bench_labelprop(args, torch, si, hr, stream)
     if args.workload == "reduce":

@@ -78,7 +78,8 @@ __device__ __forceinline__ void run_item(const hr_env& e, const hr_inst_dev& I, 
     }
     if constexpr ((PATTERNS >> HR_PAT_REDUCE) & 1u) {
         if (I.pattern == HR_PAT_REDUCE) {
-            reduce_body<1>(e, I.g0, I.g1, (const int32_t*)I.p0, (int32_t*)I.p1, I.n, T, lb,
+            using G = hr_gref_1d;   // 1-D regions: the identity map
+            reduce_body<1>(e, G{I.g0}, G{I.g1}, (const int32_t*)I.p0, (int32_t*)I.p1, I.n, T, lb,
                               t, I.drop, (int32_t*)lds, lds + I.n, I.lds_id);
             return;
         }
@@ -96,9 +97,11 @@ __device__ __forceinline__ void run_item(const hr_env& e, const hr_inst_dev& I, 
     }
     if constexpr ((PATTERNS >> HR_PAT_LABELPROP) & 1u) {
         if (I.pattern == HR_PAT_LABELPROP) {
-            const hr_gref none{nullptr, 0, 0};
-            labelprop_body<1>(e, I.g0, none, none, (int32_t*)I.p0, (const int32_t*)I.p1,
-                                 (const int32_t*)I.p2, (const uint8_t*)I.p3, I.n, T, lb, t);
+            using G = hr_gref_1d;
+            const G none{};
+            labelprop_body<1, false, G>(e, G{I.g0}, none, none, (int32_t*)I.p0,
+                                        (const int32_t*)I.p1, (const int32_t*)I.p2,
+                                        (const uint8_t*)I.p3, I.n, T, lb, t);
         }
     }
 }

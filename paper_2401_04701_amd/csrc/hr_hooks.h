@@ -67,25 +67,11 @@ __device__ __forceinline__ void hr_g(const hr_env& e, const hr_thread& t, const 
     if constexpr (CHECK) hr_check<KIND, GROUP, false, CHECK == 2>(e, t, g.shadow, g.n, g.id, x.index, x.off, site);
 }
 
-template <int KIND, int CHECK, bool GROUP = false>
-__device__ __forceinline__ void hr_g(const hr_env& e, const hr_thread& t, const hr_gref& g,
-                                     uint64_t index, uint32_t site)
-{
-    if constexpr (CHECK) hr_g<KIND, CHECK, GROUP>(e, t, g, g.at(index), site);
-}
-
 // Global hook on a word loaded earlier by hr_gload.
 template <int CHECK>
 __device__ __forceinline__ uint64_t hr_gload(const hr_thread& t, const hr_gref& g, hr_el x)
 {
     if constexpr (CHECK) return hr_check_load(t, g.shadow, g.n, x.index, x.off);
-    return 0;
-}
-
-template <int CHECK>
-__device__ __forceinline__ uint64_t hr_gload(const hr_thread& t, const hr_gref& g, uint64_t index)
-{
-    if constexpr (CHECK) return hr_gload<CHECK>(t, g, g.at(index));
     return 0;
 }
 
@@ -97,13 +83,6 @@ __device__ __forceinline__ void hr_gpre(const hr_env& e, const hr_thread& t, con
         hr_check<KIND, GROUP, true, CHECK == 2>(e, t, g.shadow, g.n, g.id, x.index, x.off, site, pre);
 }
 
-template <int KIND, int CHECK, bool GROUP = true>
-__device__ __forceinline__ void hr_gpre(const hr_env& e, const hr_thread& t, const hr_gref& g,
-                                        uint64_t index, uint32_t site, uint64_t pre)
-{
-    if constexpr (CHECK) hr_gpre<KIND, CHECK, GROUP>(e, t, g, g.at(index), site, pre);
-}
-
 // The two halves of a global hook at a lane-affine site (hr_check_issue /
 // hr_check_settle; both take the call site); `pre` as for hr_gpre when PRE.
 template <int KIND, int CHECK, bool PRE = false>
@@ -112,14 +91,6 @@ __device__ __forceinline__ hr_pend hr_gi(const hr_env& e, const hr_thread& t, co
 {
     if constexpr (CHECK)
         return hr_check_issue<KIND, PRE, CHECK == 2>(e, t, g.shadow, g.n, g.id, x.index, x.off, site, pre);
-    return hr_pend{nullptr, 0, 0, 0};
-}
-
-template <int KIND, int CHECK, bool PRE = false>
-__device__ __forceinline__ hr_pend hr_gi(const hr_env& e, const hr_thread& t, const hr_gref& g,
-                                         uint64_t index, uint32_t site, uint64_t pre = 0)
-{
-    if constexpr (CHECK) return hr_gi<KIND, CHECK, PRE>(e, t, g, g.at(index), site, pre);
     return hr_pend{nullptr, 0, 0, 0};
 }
 
@@ -153,25 +124,10 @@ __device__ __forceinline__ void hr_g(const hr_env& e, const hr_thread& t, const 
         hr_check4<KIND, GROUP, false, LAY, CHECK == 2>(e, t, g.shadow, g.n, g.id, x.index, x.off, site);
 }
 
-template <int KIND, int CHECK, bool GROUP = false, uint32_t LAY = 0>
-__device__ __forceinline__ void hr_g(const hr_env& e, const hr_thread& t, const hr_gref4t<LAY>& g,
-                                     uint64_t index, uint32_t site)
-{
-    if constexpr (CHECK) hr_g<KIND, CHECK, GROUP, LAY>(e, t, g, g.at(index), site);
-}
-
 template <int CHECK, uint32_t LAY = 0>
 __device__ __forceinline__ uint32_t hr_gload(const hr_thread& t, const hr_gref4t<LAY>& g, hr_el x)
 {
     if constexpr (CHECK) return hr_check4_load(t, g.shadow, g.n, x.index, x.off);
-    return 0;
-}
-
-template <int CHECK, uint32_t LAY = 0>
-__device__ __forceinline__ uint32_t hr_gload(const hr_thread& t, const hr_gref4t<LAY>& g,
-                                             uint64_t index)
-{
-    if constexpr (CHECK) return hr_gload<CHECK, LAY>(t, g, g.at(index));
     return 0;
 }
 
@@ -182,14 +138,6 @@ __device__ __forceinline__ void hr_gpre(const hr_env& e, const hr_thread& t,
 {
     if constexpr (CHECK)
         hr_check4<KIND, GROUP, true, LAY, CHECK == 2>(e, t, g.shadow, g.n, g.id, x.index, x.off, site, pre);
-}
-
-template <int KIND, int CHECK, bool GROUP = true, uint32_t LAY = 0>
-__device__ __forceinline__ void hr_gpre(const hr_env& e, const hr_thread& t,
-                                        const hr_gref4t<LAY>& g, uint64_t index, uint32_t site,
-                                        uint32_t pre)
-{
-    if constexpr (CHECK) hr_gpre<KIND, CHECK, GROUP, LAY>(e, t, g, g.at(index), site, pre);
 }
 
 template <int KIND, int CHECK, bool PRE = false, uint32_t LAY = 0>
@@ -203,18 +151,75 @@ __device__ __forceinline__ hr_pend4 hr_gi(const hr_env& e, const hr_thread& t,
     return hr_pend4{nullptr, 0, 0, 0};
 }
 
-template <int KIND, int CHECK, bool PRE = false, uint32_t LAY = 0>
-__device__ __forceinline__ hr_pend4 hr_gi(const hr_env& e, const hr_thread& t,
-                                          const hr_gref4t<LAY>& g, uint64_t index, uint32_t site,
-                                          uint32_t pre = 0)
-{
-    if constexpr (CHECK) return hr_gi<KIND, CHECK, PRE, LAY>(e, t, g, g.at(index), site, pre);
-    return hr_pend4{nullptr, 0, 0, 0};
-}
-
 template <int KIND, int CHECK, uint32_t LAY = 0>
 __device__ __forceinline__ void hr_gs(const hr_env& e, const hr_thread& t, const hr_gref4t<LAY>& g,
                                       const hr_pend4& p, uint64_t index, uint32_t site)
 {
     if constexpr (CHECK) hr_check4_settle<KIND>(e, t, p, g.id, index, site);
 }
+
+// The wrappers taking an element index: G is the region's own type, so a
+// region type with a compile-time map (hr_map) turns the index into its
+// shadow offset without the run-time map's division.
+template <int KIND, int CHECK, bool GROUP = false, class G>
+__device__ __forceinline__ void hr_g(const hr_env& e, const hr_thread& t, const G& g,
+                                     uint64_t index, uint32_t site)
+{
+    if constexpr (CHECK) hr_g<KIND, CHECK, GROUP>(e, t, g, g.at(index), site);
+}
+
+template <int CHECK, class G>
+__device__ __forceinline__ typename G::word hr_gload(const hr_thread& t, const G& g,
+                                                     uint64_t index)
+{
+    if constexpr (CHECK) return hr_gload<CHECK>(t, g, g.at(index));
+    return 0;
+}
+
+template <int KIND, int CHECK, bool GROUP = true, class G>
+__device__ __forceinline__ void hr_gpre(const hr_env& e, const hr_thread& t, const G& g,
+                                        uint64_t index, uint32_t site, typename G::word pre)
+{
+    if constexpr (CHECK) hr_gpre<KIND, CHECK, GROUP>(e, t, g, g.at(index), site, pre);
+}
+
+template <int KIND, int CHECK, bool PRE = false, class G>
+__device__ __forceinline__ typename G::pend hr_gi(const hr_env& e, const hr_thread& t, const G& g,
+                                                  uint64_t index, uint32_t site,
+                                                  typename G::word pre = 0)
+{
+    if constexpr (CHECK) return hr_gi<KIND, CHECK, PRE>(e, t, g, g.at(index), site, pre);
+    return typename G::pend{nullptr, 0, 0, 0};
+}
+
+// A region type whose map is fixed at compile time: TW = TH = 0 is the
+// row-major map (the shadow offset is the element index itself; 1-D
+// regions), TW, TH > 0 tiles of 2^TW x 2^TH elements with constant shifts,
+// and TW < 0 the region's own map at run time.  Base: hr_gref or
+// hr_gref4t<LAY>.
+template <class Base, int TW, int TH>
+struct hr_map : Base {
+    __device__ __forceinline__ hr_el at(uint64_t index) const
+    {
+        if constexpr (TW == 0 && TH == 0) return {index, index};
+        else return Base::at(index);
+    }
+    __device__ __forceinline__ hr_el at2(uint32_t r, uint32_t c, uint64_t index) const
+    {
+        if constexpr (TW < 0) {
+            return Base::at2(r, c, index);
+        } else if constexpr (TW == 0 && TH == 0) {
+            return {index, index};
+        } else {
+            const uint64_t tile = (uint64_t)(r >> TH) * this->lay.tiles_x + (c >> TW);
+            return {index, (tile << (TW + TH)) | ((uint64_t)(r & ((1u << TH) - 1u)) << TW) |
+                               (uint64_t)(c & ((1u << TW) - 1u))};
+        }
+    }
+};
+template <int TW, int TH>
+using hr_gref_map = hr_map<hr_gref, TW, TH>;
+// 1-D regions under the identity map
+using hr_gref_1d = hr_map<hr_gref, 0, 0>;
+template <uint32_t LAY>
+using hr_gref4_1d = hr_map<hr_gref4t<LAY>, 0, 0>;

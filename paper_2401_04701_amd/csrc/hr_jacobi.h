@@ -177,26 +177,6 @@ __device__ void jacobi_body(const hr_env& e, const G& gold, const G& gnew,
     }
 }
 
-// A global region whose 2-D shadow map is fixed at compile time: TW = TH = 0
-// is the row-major map (the shadow offset is the element index itself), TW,
-// TH > 0 tiles of 2^TW x 2^TH elements with constant shifts, and TW < 0 the
-// region's own map at run time.
-template <int TW, int TH>
-struct hr_gref_map : hr_gref {
-    __device__ __forceinline__ hr_el at2(uint32_t r, uint32_t c, uint64_t index) const
-    {
-        if constexpr (TW < 0) {
-            return hr_gref::at2(r, c, index);
-        } else if constexpr (TW == 0 && TH == 0) {
-            return {index, index};
-        } else {
-            const uint64_t tile = (uint64_t)(r >> TH) * lay.tiles_x + (c >> TW);
-            return {index, (tile << (TW + TH)) | ((uint64_t)(r & ((1u << TH) - 1u)) << TW) |
-                               (uint64_t)(c & ((1u << TW) - 1u))};
-        }
-    }
-};
-
 namespace {
 
 // One 16 x 16 tile per hardware block, on row-major shadow maps (CHECK 0:

@@ -37,6 +37,12 @@ hr_gref4t<LAY> gref4(const hr_kargs& a, uint32_t r, uint32_t cols = 0)
     return g;
 }
 
+// A region's map is the row-major identity (what the 1-D workloads assume).
+bool lay_flat(const hr_kargs& a, uint32_t r)
+{
+    return r >= HR_MAX_REGIONS || (a.lay[r].tw | a.lay[r].th) == 0;
+}
+
 // A region's map fits a 2-D workload nx elements wide: row-major, or tiled
 // over rows of exactly nx elements.
 bool lay_fits(const hr_kargs& a, uint32_t r, uint32_t nx)
@@ -54,8 +60,9 @@ __global__ __launch_bounds__(1024) void k_reduce(hr_kargs a, hr_gref gin, hr_gre
                                                  int32_t drop)
 {
     extern __shared__ uint32_t smem[];
-    reduce_body<CHECK>(a.env, gin, gout, in, out, n, blockDim.x, blockIdx.x, threadIdx.x, drop,
-                       (int32_t*)smem, smem + n, 0);
+    using G = hr_gref_1d;
+    reduce_body<CHECK>(a.env, G{gin}, G{gout}, in, out, n, blockDim.x, blockIdx.x, threadIdx.x,
+                       drop, (int32_t*)smem, smem + n, 0);
 }
 
 template <int CHECK>
@@ -65,8 +72,9 @@ __global__ __launch_bounds__(1024) void k_labelprop(hr_kargs a, hr_gref glab, hr
                                                     const int32_t* __restrict__ col,
                                                     const uint8_t* __restrict__ mask, uint32_t n)
 {
-    labelprop_body<CHECK, true>(a.env, glab, grp, gcol, label, rp, col, mask, n, blockDim.x,
-                                blockIdx.x, threadIdx.x);
+    using G = hr_gref_1d;
+    labelprop_body<CHECK, true, G>(a.env, G{glab}, G{grp}, G{gcol}, label, rp, col, mask, n,
+                                   blockDim.x, blockIdx.x, threadIdx.x);
 }
 
 // The checked kernels on 4-byte shadow words.
@@ -77,8 +85,9 @@ __global__ __launch_bounds__(1024) void k_reduce4(hr_kargs a, hr_gref4 gin, hr_g
                                                   int32_t drop)
 {
     extern __shared__ uint32_t smem[];
-    reduce_body<CHECK>(a.env, gin, gout, in, out, n, blockDim.x, blockIdx.x, threadIdx.x, drop,
-                       (int32_t*)smem, smem + n, 0);
+    using G = hr_gref4_1d<0>;
+    reduce_body<CHECK>(a.env, G{gin}, G{gout}, in, out, n, blockDim.x, blockIdx.x, threadIdx.x,
+                       drop, (int32_t*)smem, smem + n, 0);
 }
 
 template <int CHECK = 1>
@@ -88,8 +97,9 @@ __global__ __launch_bounds__(1024) void k_labelprop4(hr_kargs a, hr_gref4 glab, 
                                                      const int32_t* __restrict__ col,
                                                      const uint8_t* __restrict__ mask, uint32_t n)
 {
-    labelprop_body<CHECK, true>(a.env, glab, grp, gcol, label, rp, col, mask, n, blockDim.x,
-                                blockIdx.x, threadIdx.x);
+    using G = hr_gref4_1d<0>;
+    labelprop_body<CHECK, true, G>(a.env, G{glab}, G{grp}, G{gcol}, label, rp, col, mask, n,
+                                   blockDim.x, blockIdx.x, threadIdx.x);
 }
 
 // ----------------------------------------------------------- interpreter
@@ -194,6 +204,7 @@ hr_status hr_launch_reduce(const hr_kargs& a, uint32_t r_in, uint32_t r_out, con
                            int32_t drop, hipStream_t s)
 {
     if (!in_dev || !out_dev || !reduce_shape_ok(n, threads, blocks)) return HR_E_INVAL;
+    if (!lay_flat(a, r_in) || !lay_flat(a, r_out)) return HR_E_INVAL;
     // a context with an access log runs the kernels that write it
     const bool log = a.env.log != nullptr;
     if (a.env.word4)
@@ -312,6 +323,8 @@ hr_status hr_launch_labelprop(const hr_kargs& a, uint32_t r_label, uint32_t r_ro
                               uint32_t tpb, hipStream_t s)
 {
     if (!label_dev || !row_ptr_dev || !col_dev || !mask_dev || !labelprop_shape_ok(n, tpb))
+        return HR_E_INVAL;
+    if (!lay_flat(a, r_label) || !lay_flat(a, r_row_ptr) || !lay_flat(a, r_col))
         return HR_E_INVAL;
     const bool log = a.env.log != nullptr;
     if (a.env.word4) {
