@@ -98,7 +98,9 @@ typedef struct {
                                 wave-scope barrier of the job is a tile
                                 barrier (a tiled partition's sync) and orders
                                 only its tile's lanes.  Wave grouping of hook
-                                lanes only runs with whole waves. */
+                                lanes only runs with whole waves.  With
+                                HR_CFG_NESTED_TILES: the tiles nested in the
+                                waves (1..5). */
     uint32_t thread_bits;    /* HR_CFG_WORD4 only: width of the thread field,
                                 1..10; 0: 8.  The block field gets the rest,
                                 27 - wc_bits - bc_bits - thread_bits bits
@@ -139,6 +141,17 @@ typedef struct {
  * log (hr_access_log), so that the accesses the checker saw can be compared
  * one by one with a model of the program.  Implies HR_CFG_COUNT_CHECKS. */
 #define HR_CFG_ACCESS_LOG 8u
+/* Tiles nested in waves: the synchronization below the warp that the paper
+ * leaves to future work (Sec. VI), as cooperative-groups tiles use it beside
+ * wave barriers.  wave_bits = s (1..5, required) names aligned tiles of 2^s
+ * lanes that have their own barrier; wave barriers still order whole waves.
+ * Shadow words then carry a tile level and a tile clock (the nested machine;
+ * block ids below 2^20, block clock width at most 5, wave clock width at
+ * most 4, default 5 and 4, tile clock 4 bits).  The access-program
+ * interpreter (hr_program_check, scope 3 = tile barrier) runs such jobs; the
+ * other workloads, the batched and serving executors and hr_job_run_static
+ * reject such a context.  Not with HR_CFG_WORD4 or HR_CFG_WAVE_GROUPING. */
+#define HR_CFG_NESTED_TILES 16u
 
 /* One flagged location, 48 bytes.  The key is (space, region, block if LDS,
  * index).  The other fields describe how the race was found: `before` and
@@ -319,7 +332,7 @@ typedef struct {
     uint8_t kind;       /* hr_kind */
     uint8_t bc, wc;     /* block and wave clocks */
     uint16_t site;      /* call-site id */
-    uint32_t pad;
+    uint32_t tc;        /* tile clock (a context with HR_CFG_NESTED_TILES), else 0 */
 } hr_access_rec;
 
 /* Synchronise `stream` and copy the access log of a context created with
@@ -346,6 +359,21 @@ hr_status hr_fsm_step(uint32_t space, uint64_t old, uint32_t kind, uint32_t laun
  * exchange overwrote a concurrent update; for verification only.  wave_bits
  * as in hr_fsm_step. */
 hr_status hr_fsm_merge(uint64_t x, uint64_t y, uint32_t wave_bits, uint64_t* out);
+
+/* Host evaluation of the transition of the nested-tile machine (contexts
+ * made with HR_CFG_NESTED_TILES: tiles of 2^tile_bits lanes, tile_bits 1..5,
+ * nested in the waves, each with its own barrier and tile clock tc), for
+ * verification only.  space: hr_space; old: shadow word (low 32 bits for
+ * LDS); the identity is the access's launch, block (< 2^20), thread (<
+ * 1024) and block, wave and tile clocks (< 32, 16 and 16).  Errors:
+ * HR_E_INVAL (null out, kind > 2, an identity field out of range). */
+hr_status hr_fsm_step_nested(uint32_t space, uint64_t old, uint32_t kind, uint32_t launch,
+                             uint32_t block, uint32_t thread, uint32_t bc, uint32_t wc,
+                             uint32_t tc, uint32_t tile_bits, uint64_t* new_out);
+
+/* Host evaluation of the nested-tile machine's merge of two global words
+ * (as hr_fsm_merge), for verification only. */
+hr_status hr_fsm_merge_nested(uint64_t x, uint64_t y, uint32_t tile_bits, uint64_t* out);
 
 /* Decode a shadow summary word of `space` (for instance the `before` and
  * `with` fields of a race record) of a context with the given wave_bits: the
@@ -455,7 +483,9 @@ hr_status hr_labelprop_plain(int32_t* label_dev, const int32_t* row_ptr_dev,
  * i = (p * blocks + b) * threads + t, then the phase ends with nothing
  * (scope 0), a wave barrier in waves (tiles, when the context's wave_bits
  * is below 6) whose bit is set in wave_mask_dev[p] (scope 1; groups past the
- * 64th never synchronize) or a block barrier (scope 2).  Operation word: bits 0..23 index,
+ * 64th never synchronize), a block barrier (scope 2), or, in a context with
+ * HR_CFG_NESTED_TILES, a tile barrier in the tiles whose bit is set (scope
+ * 3; scope 1 then orders whole waves).  Operation word: bits 0..23 index,
  * 24..26 program region (global: regions_host[region] is the context region;
  * LDS: array 0 of lds_words int32), 27..28 hr_kind, or 3 for an operation
  * that switches the thread's checking off (bit 0 clear) or on (bit 0 set)

@@ -26,7 +26,7 @@ REC_DTYPE = np.dtype([
     ("index", np.uint64), ("space", np.uint32), ("region", np.uint32),
     ("lds_block", np.uint32), ("kind", np.uint32), ("launch", np.uint32),
     ("block", np.uint32), ("thread", np.uint32), ("bc", np.uint32),
-    ("wc", np.uint32), ("pad", np.uint32)])
+    ("wc", np.uint32), ("tc", np.uint32)])
 KEY_DTYPE = np.dtype([("index", np.uint64), ("space", np.uint32),
                       ("region", np.uint32), ("lds_block", np.uint32),
                       ("pad", np.uint32)])
@@ -66,6 +66,12 @@ def _lib():
         lib.orc_model_labelprop.restype = sz
         lib.orc_model_launch.argtypes = [u32, u32, u32, u32, P, P, P, P, u32, P, sz]
         lib.orc_model_launch.restype = sz
+        lib.orc_flagged_nested.argtypes = [P, sz, u32, u32, P, sz, ctypes.POINTER(sz)]
+        lib.orc_flagged_nested.restype = i32
+        lib.orc_race_pair_nested.argtypes = [P, P, u32, u32]
+        lib.orc_race_pair_nested.restype = i32
+        lib.orc_model_launch_nested.argtypes = [u32, u32, u32, u32, P, P, P, P, u32, u32, P, sz]
+        lib.orc_model_launch_nested.restype = sz
         _lib_handle = lib
     return _lib_handle
 
@@ -75,16 +81,18 @@ def _ptr(a):
 
 
 # --------------------------------------------------------------------------
-def flagged(recs: np.ndarray, wave_width: int = 64) -> set:
-    """Set of racy keys of an access log (REC_DTYPE array; sorted in place)."""
+def flagged(recs: np.ndarray, wave_width: int = 64, tile_width: int = 0) -> set:
+    """Set of racy keys of an access log (REC_DTYPE array; sorted in place).
+    tile_width: tiles of that many lanes nested in the waves, with their own
+    barriers and tile epochs (the records' tc); 0: none."""
     recs = np.ascontiguousarray(recs, dtype=REC_DTYPE)
     lib = _lib()
     n_out = ctypes.c_size_t(0)
     cap = 1024
     while True:
         out = np.zeros(cap, dtype=KEY_DTYPE)
-        rc = lib.orc_flagged(_ptr(recs), recs.shape[0], wave_width, _ptr(out), cap,
-                             ctypes.byref(n_out))
+        rc = lib.orc_flagged_nested(_ptr(recs), recs.shape[0], wave_width, tile_width,
+                                    _ptr(out), cap, ctypes.byref(n_out))
         if rc == 0:
             break
         cap = int(n_out.value)
@@ -93,10 +101,10 @@ def flagged(recs: np.ndarray, wave_width: int = 64) -> set:
             for k in out}
 
 
-def race_pair(p: np.ndarray, c: np.ndarray, wave_width: int = 64) -> bool:
+def race_pair(p: np.ndarray, c: np.ndarray, wave_width: int = 64, tile_width: int = 0) -> bool:
     p = np.ascontiguousarray(p, dtype=REC_DTYPE).reshape(1)
     c = np.ascontiguousarray(c, dtype=REC_DTYPE).reshape(1)
-    return bool(_lib().orc_race_pair(_ptr(p), _ptr(c), wave_width))
+    return bool(_lib().orc_race_pair_nested(_ptr(p), _ptr(c), wave_width, tile_width))
 
 
 def make_records(rows) -> np.ndarray:
@@ -149,21 +157,22 @@ def model_labelprop(row_ptr, col, mask, launches: int, tpb: int = 256,
                       launch0, launches, tpb, int(monitor_csr), _ptr(keep))
 
 
-def model_launch(launch, index: int, wave_width: int = 64) -> np.ndarray:
-    """Access log of one launch of an interpreted barrier program."""
+def model_launch(launch, index: int, wave_width: int = 64, tile_width: int = 0) -> np.ndarray:
+    """Access log of one launch of an interpreted barrier program (tile
+    barriers, scope 3, advance the tile epochs of tile_width-lane tiles)."""
     scope = np.ascontiguousarray(launch.scope, dtype=np.uint8)
     wm = np.ascontiguousarray(launch.wave_mask, dtype=np.uint64)
     off = np.ascontiguousarray(launch.op_off, dtype=np.int32)
     ops = np.ascontiguousarray(launch.ops, dtype=np.uint32)
-    return _run_model(_lib().orc_model_launch, index, launch.blocks, launch.threads,
+    return _run_model(_lib().orc_model_launch_nested, index, launch.blocks, launch.threads,
                       launch.phases, _ptr(scope), _ptr(wm), _ptr(off), _ptr(ops),
-                      wave_width)
+                      wave_width, tile_width)
 
 
-def model_program(program, wave_width: int = 64) -> np.ndarray:
-    logs = [model_launch(l, i, wave_width) for i, l in enumerate(program.launches)]
+def model_program(program, wave_width: int = 64, tile_width: int = 0) -> np.ndarray:
+    logs = [model_launch(l, i, wave_width, tile_width) for i, l in enumerate(program.launches)]
     return np.concatenate(logs) if logs else np.zeros(0, dtype=REC_DTYPE)
 
 
-def flagged_program(program, wave_width: int = 64) -> set:
-    return flagged(model_program(program, wave_width), wave_width)
+def flagged_program(program, wave_width: int = 64, tile_width: int = 0) -> set:
+    return flagged(model_program(program, wave_width, tile_width), wave_width, tile_width)

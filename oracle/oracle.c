@@ -18,7 +18,13 @@
  *     a differing block clock BC means "block-synchronised"),
  *   - wave-scope barriers (within one wave and one block epoch, an access in
  *     wave-barrier epoch e precedes every access in a later wave epoch;
- *     Sec. III-B "Further Extension", warp-scope barriers with a warp clock WC).
+ *     Sec. III-B "Further Extension", warp-scope barriers with a warp clock WC),
+ *   - optionally, tile barriers nested in the waves (synchronization of groups
+ *     below a warp, which the paper leaves as future work, Sec. VI): within
+ *     one tile of tile_width lanes, one block epoch and one wave epoch, an
+ *     access in tile-barrier epoch e precedes every access in a later tile
+ *     epoch.  A wave barrier restarts the tile epochs, as a block barrier
+ *     restarts the wave epochs.
  * Atomics are a third class of access (Sec. III-B): two atomics never race
  * with each other, an atomic and a plain read or write do.  Atomics and
  * fences create no happens-before.  Lanes of one wave are not ordered by
@@ -46,7 +52,7 @@ typedef struct {
     uint32_t thread;     /* linear thread id within the block */
     uint32_t bc;         /* block-barrier epoch of the accessing thread */
     uint32_t wc;         /* wave-barrier epoch (reset at each block barrier) */
-    uint32_t pad;
+    uint32_t tc;         /* tile-barrier epoch (reset at each wave or block barrier) */
 } orc_rec;               /* 48 bytes */
 
 typedef struct {
@@ -57,7 +63,8 @@ typedef struct {
 /* ---------------------------------------------------------------------- */
 /* The pairwise predicate (Sec. II-A definition; Sec. II-B scopes).        */
 /* ---------------------------------------------------------------------- */
-int orc_race_pair(const orc_rec* p, const orc_rec* c, uint32_t wave_width)
+int orc_race_pair_nested(const orc_rec* p, const orc_rec* c, uint32_t wave_width,
+                         uint32_t tile_width)
 {
     /* different threads */
     if (p->block == c->block && p->thread == c->thread) return 0;
@@ -68,11 +75,21 @@ int orc_race_pair(const orc_rec* p, const orc_rec* c, uint32_t wave_width)
     if (p->block == c->block) {
         /* ordered by a block barrier */
         if (p->bc != c->bc) return 0;
-        /* ordered by a wave barrier: same wave, same block epoch */
-        if (p->thread / wave_width == c->thread / wave_width && p->wc != c->wc)
-            return 0;
+        if (p->thread / wave_width == c->thread / wave_width) {
+            /* ordered by a wave barrier: same wave, same block epoch */
+            if (p->wc != c->wc) return 0;
+            /* ordered by a tile barrier: same tile, same wave epoch */
+            if (tile_width && p->thread / tile_width == c->thread / tile_width &&
+                p->tc != c->tc)
+                return 0;
+        }
     }
     return 1;
+}
+
+int orc_race_pair(const orc_rec* p, const orc_rec* c, uint32_t wave_width)
+{
+    return orc_race_pair_nested(p, c, wave_width, 0);
 }
 
 static int cmp_loc(const orc_rec* a, const orc_rec* b)
@@ -95,7 +112,7 @@ static int cmp_rec(const void* x, const void* y)
 }
 
 /* Does the group recs[0..n) (one location, one launch) hold a racing pair? */
-static int group_races(const orc_rec* g, size_t n, uint32_t wave_width,
+static int group_races(const orc_rec* g, size_t n, uint32_t wave_width, uint32_t tile_width,
                        size_t* scratch_w, size_t* scratch_r, size_t* scratch_a)
 {
     size_t nw = 0, nr = 0, na = 0;
@@ -107,12 +124,13 @@ static int group_races(const orc_rec* g, size_t n, uint32_t wave_width,
     /* a write against every other access */
     for (size_t i = 0; i < nw; ++i)
         for (size_t j = 0; j < n; ++j)
-            if (j != scratch_w[i] && orc_race_pair(&g[scratch_w[i]], &g[j], wave_width))
+            if (j != scratch_w[i] &&
+                orc_race_pair_nested(&g[scratch_w[i]], &g[j], wave_width, tile_width))
                 return 1;
     /* a plain read against an atomic */
     for (size_t i = 0; i < nr; ++i)
         for (size_t j = 0; j < na; ++j)
-            if (orc_race_pair(&g[scratch_r[i]], &g[scratch_a[j]], wave_width))
+            if (orc_race_pair_nested(&g[scratch_r[i]], &g[scratch_a[j]], wave_width, tile_width))
                 return 1;
     return 0;
 }
@@ -122,8 +140,8 @@ static int group_races(const orc_rec* g, size_t n, uint32_t wave_width,
  * sorted, unique racy keys to out (up to cap) and their count to *n_out.
  * Returns 0, or -1 when out is too small (then *n_out holds the needed count).
  */
-int orc_flagged(orc_rec* recs, size_t n, uint32_t wave_width,
-                orc_key* out, size_t cap, size_t* n_out)
+int orc_flagged_nested(orc_rec* recs, size_t n, uint32_t wave_width, uint32_t tile_width,
+                       orc_key* out, size_t cap, size_t* n_out)
 {
     if (wave_width == 0) wave_width = 64;
     qsort(recs, n, sizeof(orc_rec), cmp_rec);
@@ -147,7 +165,7 @@ int orc_flagged(orc_rec* recs, size_t n, uint32_t wave_width,
         for (size_t a = i; a < k && !racy;) {
             size_t b = a + 1;
             while (b < k && recs[b].launch == recs[a].launch) ++b;
-            racy = group_races(&recs[a], b - a, wave_width, sw, sr, sa);
+            racy = group_races(&recs[a], b - a, wave_width, tile_width, sw, sr, sa);
             a = b;
         }
         if (racy) {
@@ -168,6 +186,12 @@ int orc_flagged(orc_rec* recs, size_t n, uint32_t wave_width,
     return rc;
 }
 
+int orc_flagged(orc_rec* recs, size_t n, uint32_t wave_width,
+                orc_key* out, size_t cap, size_t* n_out)
+{
+    return orc_flagged_nested(recs, n, wave_width, 0, out, cap, n_out);
+}
+
 /* ---------------------------------------------------------------------- */
 /* Access-log models of the workloads.  Each walks the workload's program  */
 /* thread by thread and emits one record per instrumented access, with the */
@@ -178,9 +202,9 @@ typedef struct {
     size_t cap, n;
 } sink;
 
-static void emit(sink* s, uint32_t space, uint32_t region, uint64_t index,
-                 uint32_t kind, uint32_t launch, uint32_t block,
-                 uint32_t thread, uint32_t bc, uint32_t wc)
+static void emit_tc(sink* s, uint32_t space, uint32_t region, uint64_t index,
+                    uint32_t kind, uint32_t launch, uint32_t block,
+                    uint32_t thread, uint32_t bc, uint32_t wc, uint32_t tc)
 {
     if (s->out && s->n < s->cap) {
         orc_rec* r = &s->out[s->n];
@@ -194,9 +218,16 @@ static void emit(sink* s, uint32_t space, uint32_t region, uint64_t index,
         r->thread = thread;
         r->bc = bc;
         r->wc = wc;
-        r->pad = 0;
+        r->tc = tc;
     }
     s->n++;
+}
+
+static void emit(sink* s, uint32_t space, uint32_t region, uint64_t index,
+                 uint32_t kind, uint32_t launch, uint32_t block,
+                 uint32_t thread, uint32_t bc, uint32_t wc)
+{
+    emit_tc(s, space, region, index, kind, launch, block, thread, bc, wc, 0);
 }
 
 /*
@@ -359,24 +390,27 @@ size_t orc_model_labelprop(uint32_t n, const int32_t* row_ptr, const int32_t* co
  * One launch of an interpreted barrier program (layout documented with the
  * program generator): per phase, every thread's operations, then the phase's
  * barrier.  A block barrier advances the block epoch and restarts the wave
- * epoch; a wave barrier advances the wave epoch of the waves in wave_mask.
- * An operation of kind 3 switches the thread's monitoring off (index bit 0
- * clear) or on (set): the accesses a switched-off thread makes are not
+ * and tile epochs; a wave barrier advances the wave epoch of the waves in
+ * wave_mask and restarts their tile epochs; a tile barrier (scope 3, with
+ * tile_width lanes per tile) advances the tile epoch of the tiles in the
+ * mask.  An operation of kind 3 switches the thread's monitoring off (index
+ * bit 0 clear) or on (set): the accesses a switched-off thread makes are not
  * monitored, so they are not in the log (paper Sec. IV-A: the instrumentation
  * of individual threads can be enabled or disabled at run time).
  */
-size_t orc_model_launch(uint32_t launch, uint32_t blocks, uint32_t threads,
-                        uint32_t phases, const uint8_t* scope,
-                        const uint64_t* wave_mask, const int32_t* op_off,
-                        const uint32_t* ops, uint32_t wave_width,
-                        orc_rec* out, size_t cap)
+size_t orc_model_launch_nested(uint32_t launch, uint32_t blocks, uint32_t threads,
+                               uint32_t phases, const uint8_t* scope,
+                               const uint64_t* wave_mask, const int32_t* op_off,
+                               const uint32_t* ops, uint32_t wave_width, uint32_t tile_width,
+                               orc_rec* out, size_t cap)
 {
     sink s = {out, cap, 0};
     if (wave_width == 0) wave_width = 64;
     for (uint32_t b = 0; b < blocks; ++b) {
         for (uint32_t t = 0; t < threads; ++t) {
-            uint32_t bc = 0, wc = 0, on = 1;
+            uint32_t bc = 0, wc = 0, tc = 0, on = 1;
             const uint32_t w = t / wave_width;
+            const uint32_t g = tile_width ? t / tile_width : 0;
             for (uint32_t p = 0; p < phases; ++p) {
                 const size_t i = ((size_t)p * blocks + b) * threads + t;
                 for (int32_t k = op_off[i]; k < op_off[i + 1]; ++k) {
@@ -386,13 +420,24 @@ size_t orc_model_launch(uint32_t launch, uint32_t blocks, uint32_t threads,
                         continue;
                     }
                     if (on)
-                        emit(&s, (op >> 29) & 1, (op >> 24) & 7, op & 0xFFFFFF,
-                             (op >> 27) & 3, launch, b, t, bc, wc);
+                        emit_tc(&s, (op >> 29) & 1, (op >> 24) & 7, op & 0xFFFFFF,
+                                (op >> 27) & 3, launch, b, t, bc, wc, tc);
                 }
-                if (scope[p] == 2) { ++bc; wc = 0; }
-                else if (scope[p] == 1 && w < 64 && ((wave_mask[p] >> w) & 1)) ++wc;
+                if (scope[p] == 2) { ++bc; wc = 0; tc = 0; }
+                else if (scope[p] == 1 && w < 64 && ((wave_mask[p] >> w) & 1)) { ++wc; tc = 0; }
+                else if (scope[p] == 3 && tile_width && g < 64 && ((wave_mask[p] >> g) & 1)) ++tc;
             }
         }
     }
     return s.n;
+}
+
+size_t orc_model_launch(uint32_t launch, uint32_t blocks, uint32_t threads,
+                        uint32_t phases, const uint8_t* scope,
+                        const uint64_t* wave_mask, const int32_t* op_off,
+                        const uint32_t* ops, uint32_t wave_width,
+                        orc_rec* out, size_t cap)
+{
+    return orc_model_launch_nested(launch, blocks, threads, phases, scope, wave_mask, op_off,
+                                   ops, wave_width, 0, out, cap);
 }

@@ -187,7 +187,7 @@ __device__ __forceinline__ hr_thread hr_thread_make(const hr_env& e, uint32_t bl
 __device__ __forceinline__ void hr_log_push(hr_access_rec* log, uint32_t* ctr, uint32_t cap,
                                          uint64_t index, uint32_t region, uint32_t block,
                                          uint32_t launch_seq, uint32_t thread, uint32_t tag,
-                                         uint32_t clocks)
+                                         uint32_t clocks, uint32_t tc = 0)
 {
     const uint32_t slot =
         __hip_atomic_fetch_add(ctr + HR_CTR_LOG, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -195,7 +195,7 @@ __device__ __forceinline__ void hr_log_push(hr_access_rec* log, uint32_t* ctr, u
     // two 16-byte stores of the 32-byte record (layout of hr_access_rec)
     uint4* p = reinterpret_cast<uint4*>(log + slot);
     p[0] = make_uint4((uint32_t)index, (uint32_t)(index >> 32), region, block);
-    p[1] = make_uint4(launch_seq, (thread & 0xFFFFu) | (tag << 16), clocks, 0u);
+    p[1] = make_uint4(launch_seq, (thread & 0xFFFFu) | (tag << 16), clocks, tc);
 }
 
 // Debug counting of checked accesses: one atomic per wave and hook, spread

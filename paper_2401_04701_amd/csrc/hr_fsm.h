@@ -420,4 +420,189 @@ HR_HD uint32_t step(uint32_t old, uint32_t id, uint32_t k, uint32_t wm = WAVE_M)
 }
 }  // namespace l
 
+// ---------------------------------------------------------------------------
+// Tiles nested in waves.  The paper leaves synchronization below the warp to
+// future work (Sec. VI); cooperative-groups tiles give every aligned group of
+// 2^s lanes (s < 6) its own barrier, used beside wave barriers.  This machine
+// adds the tile level between the wave and the thread: a tile barrier
+// advances the tile clock tc (restarted by wave and block barriers), and two
+// accesses of one tile in one wave epoch are ordered exactly when their tile
+// epochs differ.  Summaries gain one scope level:
+//   MTI(cL, cB, k)       one wave in the latest block epoch; >= 2 tiles in
+//                        its latest wave epoch, all of class k
+//   MT(cL, cB, cW, k)    one tile in the latest wave epoch; >= 2 threads in
+//                        its latest tile epoch, all of class k
+//   ST(cL, cB, cW, cT)   one thread in the latest tile epoch
+// besides INIT, RACE, MB(k) and MW(cL, k), with cT <= cW <= cB <= cL.  The
+// relation goes one step further: ... other wave, later wave epoch, other
+// tile, later tile epoch, other thread, same thread.  The tile of a thread is
+// the top 10 - s bits of its index (tile_mask(s)).
+//
+// Global word, 64 bits, least significant first:
+//   tag 3 | cT 2 | cW 2 | cB 2 | cL 2 | tc 4 | wc 4 | bc 6 | thread 10 |
+//   block 20 | launch 9
+// LDS word, 32 bits: tag 3 | cT 2 | cW 2 | cB 2 | tc 4 | wc 4 | bc 5 | thread 10
+// (the nested mode bounds the block clock at 5 bits, the wave and tile
+// clocks at 4, and launches at 2^20 blocks).
+// ---------------------------------------------------------------------------
+enum : uint32_t { T_MTI = 6u };
+
+namespace n {
+constexpr uint32_t TAG_SH = 0, CT_SH = 3, CW_SH = 5, CB_SH = 7, CL_SH = 9, TC_SH = 11, WC_SH = 15,
+                   BC_SH = 19, TH_SH = 25, BL_SH = 35, LA_SH = 55;
+constexpr uint64_t TAG_M = 7ull;
+constexpr uint64_t CT_M = 3ull << CT_SH, CW_M = 3ull << CW_SH, CB_M = 3ull << CB_SH,
+                   CL_M = 3ull << CL_SH;
+constexpr uint64_t TC_M = 15ull << TC_SH, WC_M = 15ull << WC_SH, BC_M = 63ull << BC_SH;
+constexpr uint64_t TH_M = 1023ull << TH_SH;
+constexpr uint64_t WAVE_M = 15ull << (TH_SH + 6);
+constexpr uint64_t BL_M = ((1ull << 20) - 1) << BL_SH;
+constexpr uint64_t LA_M = 511ull << LA_SH;
+constexpr uint32_t BLOCK_LIMIT = 1u << 20;
+constexpr uint32_t BC_LIMIT = 32, WC_LIMIT = 16, TC_LIMIT = 16;   // clock values that fit
+
+// Mask of the thread bits naming the tile (tiles of 2^s lanes, s < 6).
+HR_HD uint64_t tile_mask(uint32_t s) { return (uint64_t)((1023u >> s) << s) << TH_SH; }
+
+HR_HD uint64_t pack_id(uint32_t launch, uint32_t block, uint32_t thread, uint32_t bc, uint32_t wc,
+                       uint32_t tc)
+{
+    return ((uint64_t)(launch & 511u) << LA_SH) | ((uint64_t)(block & (BLOCK_LIMIT - 1)) << BL_SH) |
+           ((uint64_t)(thread & 1023u) << TH_SH) | ((uint64_t)(bc & 63u) << BC_SH) |
+           ((uint64_t)(wc & 15u) << WC_SH) | ((uint64_t)(tc & 15u) << TC_SH);
+}
+
+HR_HD uint64_t mk(uint32_t tag, uint32_t cl, uint32_t cb, uint32_t cw, uint32_t ct)
+{
+    return (uint64_t)tag | ((uint64_t)cl << CL_SH) | ((uint64_t)cb << CB_SH) |
+           ((uint64_t)cw << CW_SH) | ((uint64_t)ct << CT_SH);
+}
+
+// One transition: old word, identity of the access, its class k, and the
+// tile mask tm = tile_mask(s).
+HR_HD uint64_t step(uint64_t old, uint64_t id, uint32_t k, uint64_t tm)
+{
+    const uint32_t tag = (uint32_t)(old & TAG_M);
+    if (tag == T_RACE) return old;
+    const uint64_t d = old ^ id;
+    const uint32_t cl = (uint32_t)(old >> CL_SH) & 3u, cb = (uint32_t)(old >> CB_SH) & 3u;
+    const uint32_t cw = (uint32_t)(old >> CW_SH) & 3u, ct = (uint32_t)(old >> CT_SH) & 3u;
+    const uint64_t race = T_RACE;
+    const uint64_t keep_b = LA_M | BL_M | BC_M;            // MW
+    const uint64_t keep_i = keep_b | WAVE_M | WC_M;        // MTI
+    const uint64_t keep_m = keep_b | tm | WC_M | TC_M;     // MT
+    const uint64_t keep_t = keep_b | TH_M | WC_M | TC_M;   // ST
+    if (tag == T_INIT || (d & LA_M)) return mk(T_ST, k, k, k, k) | (id & keep_t);
+    if (tag == T_MB) return conflicts(cb, k) ? race : old;
+    if (d & BL_M) return conflicts(cl, k) ? race : (mk(T_MB, 0, cl | k, 0, 0) | (id & LA_M));
+    if (d & BC_M) return mk(T_ST, cl | k, k, k, k) | (id & keep_t);
+    if (tag == T_MW) return conflicts(cb, k) ? race : old;
+    if (d & WAVE_M) return conflicts(cb, k) ? race : (mk(T_MW, cl, k, 0, 0) | (id & keep_b));
+    if (d & WC_M) return mk(T_ST, cl | k, cb | k, k, k) | (id & keep_t);
+    if (tag == T_MTI) return conflicts(cw, k) ? race : old;
+    if (d & tm) return conflicts(cw, k) ? race : (mk(T_MTI, cl, cb, k, 0) | (id & keep_i));
+    if (d & TC_M) return mk(T_ST, cl | k, cb | k, cw | k, k) | (id & keep_t);
+    if (tag == T_MT) return conflicts(ct, k) ? race : old;
+    if (d & TH_M) return conflicts(ct, k) ? race : (mk(T_MT, cl, cb, cw, k) | (id & keep_m));
+    return mk(T_ST, cl | k, cb | k, cw | k, ct | k) | (id & keep_t);
+}
+
+// The summary of the union of the access sets of x and y (x of the current
+// launch), under the same condition as g::merge, one scope level deeper.
+HR_HD uint64_t merge(uint64_t x, uint64_t y, uint64_t tm)
+{
+    const uint32_t tx = (uint32_t)(x & TAG_M), ty = (uint32_t)(y & TAG_M);
+    const uint64_t race = T_RACE;
+    if (tx == T_RACE || ty == T_RACE) return race;
+    if (ty == T_INIT || ((x ^ y) & LA_M)) return x;
+    if (tx == T_INIT) return y;
+    const auto cls = [](uint64_t w, uint32_t sh) { return (uint32_t)(w >> sh) & 3u; };
+    const uint64_t d = x ^ y;
+    if (tx == T_MB || ty == T_MB || (d & BL_M)) {
+        const uint32_t c = (tx == T_MB ? cls(x, CB_SH) : cls(x, CL_SH)) |
+                           (ty == T_MB ? cls(y, CB_SH) : cls(y, CL_SH));
+        return c == CL_X ? race : (mk(T_MB, 0, c, 0, 0) | (x & LA_M));
+    }
+    const uint32_t cl = cls(x, CL_SH) | cls(y, CL_SH);
+    // an earlier epoch at any level is ordered before the newer one, which
+    // keeps its detail (clocks never wrap: an overflow stops checking)
+    if (d & BC_M) {
+        const uint64_t nw = (x & BC_M) > (y & BC_M) ? x : y;
+        return (nw & ~CL_M) | ((uint64_t)cl << CL_SH);
+    }
+    const uint64_t keep_b = LA_M | BL_M | BC_M;
+    if (tx == T_MW || ty == T_MW || (d & WAVE_M)) {
+        const uint32_t c = cls(x, CB_SH) | cls(y, CB_SH);
+        return c == CL_X ? race : (mk(T_MW, cl, c, 0, 0) | (x & keep_b));
+    }
+    const uint32_t cb = cls(x, CB_SH) | cls(y, CB_SH);
+    if (d & WC_M) {
+        const uint64_t nw = (x & WC_M) > (y & WC_M) ? x : y;
+        return (nw & ~(CL_M | CB_M)) | ((uint64_t)cl << CL_SH) | ((uint64_t)cb << CB_SH);
+    }
+    if (tx == T_MTI || ty == T_MTI || (d & tm)) {
+        const uint32_t c = cls(x, CW_SH) | cls(y, CW_SH);
+        return c == CL_X ? race : (mk(T_MTI, cl, cb, c, 0) | (x & (keep_b | WAVE_M | WC_M)));
+    }
+    const uint32_t cw = cls(x, CW_SH) | cls(y, CW_SH);
+    if (d & TC_M) {
+        const uint64_t nw = (x & TC_M) > (y & TC_M) ? x : y;
+        return (nw & ~(CL_M | CB_M | CW_M)) | ((uint64_t)cl << CL_SH) | ((uint64_t)cb << CB_SH) |
+               ((uint64_t)cw << CW_SH);
+    }
+    if (tx == T_MT || ty == T_MT || (d & TH_M)) {
+        const uint32_t c = cls(x, CT_SH) | cls(y, CT_SH);
+        return c == CL_X ? race : (mk(T_MT, cl, cb, cw, c) | (x & (keep_b | tm | WC_M | TC_M)));
+    }
+    return mk(T_ST, cl, cb, cw, cls(x, CT_SH) | cls(y, CT_SH)) |
+           (x & (keep_b | TH_M | WC_M | TC_M));
+}
+}  // namespace n
+
+namespace nl {
+constexpr uint32_t TAG_SH = 0, CT_SH = 3, CW_SH = 5, CB_SH = 7, TC_SH = 9, WC_SH = 13, BC_SH = 17,
+                   TH_SH = 22;
+constexpr uint32_t TAG_M = 7u;
+constexpr uint32_t TC_M = 15u << TC_SH, WC_M = 15u << WC_SH, BC_M = 31u << BC_SH;
+constexpr uint32_t TH_M = 1023u << TH_SH;
+constexpr uint32_t WAVE_M = 15u << (TH_SH + 6);
+
+HR_HD uint32_t tile_mask(uint32_t s) { return ((1023u >> s) << s) << TH_SH; }
+
+HR_HD uint32_t pack_id(uint32_t thread, uint32_t bc, uint32_t wc, uint32_t tc)
+{
+    return ((thread & 1023u) << TH_SH) | ((bc & 31u) << BC_SH) | ((wc & 15u) << WC_SH) |
+           ((tc & 15u) << TC_SH);
+}
+
+HR_HD uint32_t mk(uint32_t tag, uint32_t cb, uint32_t cw, uint32_t ct)
+{
+    return tag | (cb << CB_SH) | (cw << CW_SH) | (ct << CT_SH);
+}
+
+// One transition on an LDS word (one block, one launch: no launch, block or
+// launch-wide class).
+HR_HD uint32_t step(uint32_t old, uint32_t id, uint32_t k, uint32_t tm)
+{
+    const uint32_t tag = old & TAG_M;
+    if (tag == T_RACE) return old;
+    const uint32_t d = old ^ id;
+    const uint32_t cb = (old >> CB_SH) & 3u, cw = (old >> CW_SH) & 3u, ct = (old >> CT_SH) & 3u;
+    const uint32_t race = T_RACE;
+    const uint32_t keep_t = BC_M | TH_M | WC_M | TC_M;
+    if (tag == T_INIT || (d & BC_M)) return mk(T_ST, k, k, k) | (id & keep_t);
+    if (tag == T_MW) return conflicts(cb, k) ? race : old;
+    if (d & WAVE_M) return conflicts(cb, k) ? race : (mk(T_MW, k, 0, 0) | (id & BC_M));
+    if (d & WC_M) return mk(T_ST, cb | k, k, k) | (id & keep_t);
+    if (tag == T_MTI) return conflicts(cw, k) ? race : old;
+    if (d & tm)
+        return conflicts(cw, k) ? race : (mk(T_MTI, cb, k, 0) | (id & (BC_M | WAVE_M | WC_M)));
+    if (d & TC_M) return mk(T_ST, cb | k, cw | k, k) | (id & keep_t);
+    if (tag == T_MT) return conflicts(ct, k) ? race : old;
+    if (d & TH_M)
+        return conflicts(ct, k) ? race : (mk(T_MT, cb, cw, k) | (id & (BC_M | tm | WC_M | TC_M)));
+    return mk(T_ST, cb | k, cw | k, ct | k) | (id & keep_t);
+}
+}  // namespace nl
+
 }  // namespace hr

@@ -240,14 +240,24 @@ bool hr_config_normalize(const hr_config* cfg, hr_config* out)
     hr_config k = {};
     if (cfg) k = *cfg;
     const bool word4 = (k.flags & HR_CFG_WORD4) != 0;
+    const bool nested = (k.flags & HR_CFG_NESTED_TILES) != 0;
+    if (nested) {
+        // tiles of 2^wave_bits lanes inside whole waves; the nested words'
+        // clock fields hold 5 and 4 bits, and the flat options do not apply
+        if (k.wave_bits < 1 || k.wave_bits > 5 || word4 || (k.flags & HR_CFG_WAVE_GROUPING))
+            return false;
+        if (k.bc_bits == 0) k.bc_bits = 5;
+        if (k.wc_bits == 0) k.wc_bits = 4;
+        if (k.bc_bits > 5 || k.wc_bits > 4) return false;
+    }
     if (k.ring_capacity == 0) k.ring_capacity = 65536;
     if (k.bc_bits == 0) k.bc_bits = word4 ? 2 : 8;
     if (k.wc_bits == 0) k.wc_bits = word4 ? 1 : 6;
     if (k.thread_bits == 0) k.thread_bits = word4 ? 8 : 10;
     if (k.bc_bits > 8 || k.wc_bits > 6 || k.ring_capacity > (1u << 26)) return false;
     if (k.thread_bits > 10 || (!word4 && k.thread_bits != 10)) return false;
-    if (k.flags &
-        ~(HR_CFG_COUNT_CHECKS | HR_CFG_WAVE_GROUPING | HR_CFG_WORD4 | HR_CFG_ACCESS_LOG))
+    if (k.flags & ~(HR_CFG_COUNT_CHECKS | HR_CFG_WAVE_GROUPING | HR_CFG_WORD4 |
+                    HR_CFG_ACCESS_LOG | HR_CFG_NESTED_TILES))
         return false;
     if (k.flags & HR_CFG_ACCESS_LOG) {
         if (k.log_capacity == 0) k.log_capacity = 1u << 20;
@@ -632,6 +642,34 @@ extern "C" hr_status hr_word4_widen(uint32_t word, uint32_t wc_bits, uint32_t bc
         (word & 31u) >= hr::c::N_STATES)
         return HR_E_INVAL;
     *out = hr::c::widen(word, hr::c::layout(wc_bits, bc_bits, thread_bits));
+    return HR_OK;
+}
+
+extern "C" hr_status hr_fsm_step_nested(uint32_t space, uint64_t old, uint32_t kind,
+                                        uint32_t launch, uint32_t block, uint32_t thread,
+                                        uint32_t bc, uint32_t wc, uint32_t tc, uint32_t tile_bits,
+                                        uint64_t* new_out)
+{
+    if (!new_out || kind > 2 || space > 1 || thread > 1023 || tile_bits < 1 || tile_bits > 5)
+        return HR_E_INVAL;
+    if (block >= hr::n::BLOCK_LIMIT || bc >= hr::n::BC_LIMIT || wc >= hr::n::WC_LIMIT ||
+        tc >= hr::n::TC_LIMIT)
+        return HR_E_INVAL;
+    const uint32_t k = hr::kind_class(kind);
+    if (space == HR_GLOBAL)
+        *new_out = hr::n::step(old, hr::n::pack_id(launch, block, thread, bc, wc, tc), k,
+                               hr::n::tile_mask(tile_bits));
+    else
+        *new_out = hr::nl::step((uint32_t)old, hr::nl::pack_id(thread, bc, wc, tc), k,
+                                hr::nl::tile_mask(tile_bits));
+    return HR_OK;
+}
+
+extern "C" hr_status hr_fsm_merge_nested(uint64_t x, uint64_t y, uint32_t tile_bits,
+                                         uint64_t* out)
+{
+    if (!out || tile_bits < 1 || tile_bits > 5) return HR_E_INVAL;
+    *out = hr::n::merge(x, y, hr::n::tile_mask(tile_bits));
     return HR_OK;
 }
 

@@ -8,6 +8,7 @@
 #include "hr_bodies.h"
 #include "hr_device.h"
 #include "hr_internal.h"
+#include "hr_nested.h"
 
 namespace {
 
@@ -175,6 +176,77 @@ __global__ __launch_bounds__(1024) void k_program(hr_kargs a, prog_map pm, uint3
     }
 }
 
+// The interpreter on the nested machine: tiles of 2^wave_bits lanes inside
+// 64-lane waves.  A phase ends with nothing (scope 0), a wave barrier in the
+// waves whose bit is set in wmask[p] (scope 1), a block barrier (scope 2) or
+// a tile barrier in the tiles whose bit is set in wmask[p] (scope 3; tiles
+// past the 64th never synchronize).
+template <bool LOG = false>
+__global__ __launch_bounds__(1024) void k_program_nested(
+    hr_kargs a, prog_map pm, uint32_t blocks, uint32_t threads, uint32_t phases,
+    const uint8_t* __restrict__ scope, const uint64_t* __restrict__ wmask,
+    const int32_t* __restrict__ op_off, size_t n_op_off, const uint32_t* __restrict__ ops,
+    size_t n_ops, const uint32_t* __restrict__ bmap, uint32_t lds_words)
+{
+    extern __shared__ uint32_t smem[];
+    uint32_t* ldata = smem;
+    uint32_t* lsh = smem + lds_words;
+    const uint32_t b = bmap ? bmap[blockIdx.x] : blockIdx.x;
+    if (b >= blocks) return;                      // uniform over the block
+    const uint32_t t = threadIdx.x;
+    hr_tn th = hr_tn_make(a.env, b, t);
+    for (uint32_t i = t; i < lds_words; i += blockDim.x) {
+        ldata[i] = 0;
+        lsh[i] = 0;
+    }
+    __syncthreads();
+    const uint32_t w = t >> 6, g = t >> a.env.wave_bits;   // the thread's wave and tile
+    for (uint32_t p = 0; p < phases; ++p) {
+        const size_t i = ((size_t)p * blocks + b) * threads + t;
+        int64_t k0 = 0, k1 = 0;
+        if (i + 1 < n_op_off) {
+            k0 = op_off[i];
+            k1 = op_off[i + 1];
+        }
+        if (k0 < 0) k0 = 0;
+        if (k1 > (int64_t)n_ops) k1 = (int64_t)n_ops;
+        for (int64_t k = k0; k < k1; ++k) {
+            const uint32_t op = ops[k];
+            const uint32_t idx = op & 0xFFFFFFu, reg = (op >> 24) & 7u, kind = (op >> 27) & 3u;
+            if (kind == 3) {
+                hr_tn_enable(th, idx & 1u);
+                continue;
+            }
+            if ((op >> 29) & 1u) {
+                if (idx >= lds_words) {
+                    hr_set_flag(a.env, HR_DEVF_RANGE);
+                    continue;
+                }
+                if (kind == 0) (void)*(volatile uint32_t*)(ldata + idx);
+                else if (kind == 1) ldata[idx] = t + 1;
+                else atomicAdd(ldata + idx, 1u);
+                hr_naccess_lds_k<LOG>(a.env, th, kind, lsh, lds_words, 0, idx, p + 1);
+            } else {
+                const uint32_t r = pm.r[reg];
+                if (r >= HR_MAX_REGIONS || idx >= a.n_elems[r]) {
+                    hr_set_flag(a.env, HR_DEVF_RANGE);
+                    continue;
+                }
+                uint32_t* d = (uint32_t*)a.data[r];
+                if (kind == 0) (void)*(volatile uint32_t*)(d + idx);
+                else if (kind == 1) d[idx] = t + 1;
+                else atomicAdd(d + idx, 1u);
+                hr_ncheck_k<LOG>(a.env, th, kind, a.shadow[r], a.n_elems[r], r, idx,
+                                 hr_lay_off(a.lay[r], idx), p + 1);
+            }
+        }
+        const uint8_t sc = scope[p];
+        if (sc == 2) hr_nbarrier_block(a.env, th);
+        else if (sc == 1 && w < 64 && ((wmask[p] >> w) & 1ull)) hr_nbarrier_wave(a.env, th);
+        else if (sc == 3 && g < 64 && ((wmask[p] >> g) & 1ull)) hr_nbarrier_tile(a.env, th);
+    }
+}
+
 }  // namespace
 
 // ======================================================================
@@ -189,6 +261,7 @@ extern "C" hr_status hr_reduce_check(hr_ctx c, uint32_t r_in, uint32_t r_out, co
                                      int32_t* out_dev, uint32_t n, uint32_t threads,
                                      uint32_t blocks, int32_t drop, void* stream)
 {
+    if (c && (c->cfg.flags & HR_CFG_NESTED_TILES)) return HR_E_INVAL;   // no tile level here
     if (!c || !reduce_shape_ok(n, threads, blocks) ||
         !hr_region_ok(c, r_in, in_dev, (size_t)n * blocks) ||
         !hr_region_ok(c, r_out, out_dev, (size_t)threads * blocks))
@@ -237,6 +310,7 @@ extern "C" hr_status hr_jacobi_check(hr_ctx c, uint32_t r_old, uint32_t r_new,
                                      const float* u_old_dev, float* u_new_dev, uint32_t ny,
                                      uint32_t nx, const int32_t* seed_dev, void* stream)
 {
+    if (c && (c->cfg.flags & HR_CFG_NESTED_TILES)) return HR_E_INVAL;   // no tile level here
     if (!c || !jacobi_shape_ok(ny, nx)) return HR_E_INVAL;
     const size_t cells = (size_t)ny * nx;
     if (!hr_region_ok(c, r_old, u_old_dev, cells) || !hr_region_ok(c, r_new, u_new_dev, cells))
@@ -305,6 +379,7 @@ extern "C" hr_status hr_labelprop_check(hr_ctx c, uint32_t r_label, uint32_t r_r
                                         const uint8_t* mask_dev, uint32_t n, uint32_t tpb,
                                         void* stream)
 {
+    if (c && (c->cfg.flags & HR_CFG_NESTED_TILES)) return HR_E_INVAL;   // no tile level here
     if (!c || !row_ptr_dev || !col_dev || !mask_dev || !labelprop_shape_ok(n, tpb) ||
         !hr_region_ok(c, r_label, label_dev, n))
         return HR_E_INVAL;
@@ -382,8 +457,11 @@ extern "C" hr_status hr_program_check(hr_ctx c, const uint32_t* regions_host, ui
     hr_kargs a;
     hr_fill_args(c, &a);
     const size_t lds_bytes = (size_t)lds_words * 2 * sizeof(uint32_t);
-    HR_LAUNCH(a.env.log ? k_program<true> : k_program<false>, dim3(blocks), dim3(threads),
-              lds_bytes, hr_stream(c, stream), a,
+    const bool nested = (c->cfg.flags & HR_CFG_NESTED_TILES) != 0;
+    if (nested && blocks > hr::n::BLOCK_LIMIT) return HR_E_INVAL;
+    auto kern = a.env.log ? k_program<true> : k_program<false>;
+    if (nested) kern = a.env.log ? k_program_nested<true> : k_program_nested<false>;
+    HR_LAUNCH(kern, dim3(blocks), dim3(threads), lds_bytes, hr_stream(c, stream), a,
                        pm, blocks, threads, phases, scope_dev, wave_mask_dev, op_off_dev, n_op_off,
                        ops_dev, n_ops, block_map_dev, lds_words);
     return HR_OK;

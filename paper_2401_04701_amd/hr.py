@@ -31,6 +31,7 @@ HR_CFG_COUNT_CHECKS = 1
 HR_CFG_WAVE_GROUPING = 2
 HR_CFG_WORD4 = 4
 HR_CFG_ACCESS_LOG = 8
+HR_CFG_NESTED_TILES = 16
 NO_REGION = 0xFFFFFFFF
 HR_PAT_REDUCE, HR_PAT_JACOBI, HR_PAT_LABELPROP = 0, 1, 2
 HR_SITES = 256
@@ -63,7 +64,7 @@ assert RACE_DTYPE.itemsize == 48
 ACCESS_DTYPE = np.dtype([("index", np.uint64), ("region", np.uint32), ("block", np.uint32),
                          ("launch", np.uint32), ("thread", np.uint16), ("space", np.uint8),
                          ("kind", np.uint8), ("bc", np.uint8), ("wc", np.uint8),
-                         ("site", np.uint16), ("pad", np.uint32)])
+                         ("site", np.uint16), ("tc", np.uint32)])
 assert ACCESS_DTYPE.itemsize == 32
 
 
@@ -152,6 +153,8 @@ def _load():
         "hr_access_log": [P, P, sz, P, P],
         "hr_fsm_step": [u32, u64, u32, u32, u32, u32, u32, u32, u32, P],
         "hr_fsm_merge": [u64, u64, u32, P],
+        "hr_fsm_step_nested": [u32, u64, u32, u32, u32, u32, u32, u32, u32, u32, P],
+        "hr_fsm_merge_nested": [u64, u64, u32, P],
         "hr_describe": [u32, u64, u32, P],
         "hr_fsm_step_word4": [u32, u32, u32, u32, u32, u32, u32, u32, u32, u32, P],
         "hr_word4_widen": [u32, u32, u32, u32, P],
@@ -188,7 +191,7 @@ EXPORTED = ("hr_ctx_create", "hr_ctx_destroy", "hr_shadow_alloc", "hr_shadow_all
             "hr_dev_args", "hr_batch_create", "hr_batch_run", "hr_batch_info",
             "hr_batch_destroy", "hr_job_run", "hr_job_run_static", "hr_serve",
             "hr_kernel_end", "hr_reset", "hr_report", "hr_check_count", "hr_access_log",
-            "hr_fsm_step", "hr_fsm_merge",
+            "hr_fsm_step", "hr_fsm_merge", "hr_fsm_step_nested", "hr_fsm_merge_nested",
             "hr_describe", "hr_fsm_step_word4", "hr_word4_widen",
             "hr_reduce_check", "hr_reduce_plain", "hr_jacobi_check", "hr_jacobi_plain",
             "hr_labelprop_check", "hr_labelprop_plain", "hr_program_check",
@@ -226,6 +229,21 @@ def fsm_step(space: int, old: int, kind: int, launch: int, block: int, thread: i
     out = ctypes.c_uint64(0)
     _check("hr_fsm_step", _lib.hr_fsm_step(space, old, kind, launch, block, thread, bc, wc,
                                            wave_bits, ctypes.byref(out)))
+    return int(out.value)
+
+
+def fsm_step_nested(space: int, old: int, kind: int, launch: int, block: int, thread: int,
+                    bc: int, wc: int, tc: int, tile_bits: int) -> int:
+    """Host evaluation of the nested-tile machine's transition (verification)."""
+    out = ctypes.c_uint64(0)
+    _check("hr_fsm_step_nested", _lib.hr_fsm_step_nested(space, old, kind, launch, block, thread,
+                                                         bc, wc, tc, tile_bits, ctypes.byref(out)))
+    return int(out.value)
+
+
+def fsm_merge_nested(x: int, y: int, tile_bits: int) -> int:
+    out = ctypes.c_uint64(0)
+    _check("hr_fsm_merge_nested", _lib.hr_fsm_merge_nested(x, y, tile_bits, ctypes.byref(out)))
     return int(out.value)
 
 
@@ -322,16 +340,19 @@ class DeviceProgram:
 class Context:
     """A checking job: shadow regions, report ring, launch epochs.  The
     arguments are the fields of hr_config; word4=True selects 4-byte global
-    shadow words (HR_CFG_WORD4), whose thread field is thread_bits wide."""
+    shadow words (HR_CFG_WORD4), whose thread field is thread_bits wide;
+    nested_tiles=True (HR_CFG_NESTED_TILES) makes tiles of 2**wave_bits
+    lanes with their own barriers nested in whole waves."""
 
     def __init__(self, ring_capacity=0, bc_bits=0, wc_bits=0, count_checks=False,
                  shadow_budget=0, wave_grouping=False, site_limit=0, wave_bits=0,
                  word4=False, thread_bits=0, coalesce_width=0, access_log=False,
-                 log_capacity=0, stream=None):
+                 log_capacity=0, nested_tiles=False, stream=None):
         flags = (HR_CFG_COUNT_CHECKS if count_checks else 0) | \
                 (HR_CFG_WAVE_GROUPING if wave_grouping else 0) | \
                 (HR_CFG_WORD4 if word4 else 0) | \
-                (HR_CFG_ACCESS_LOG if access_log else 0)
+                (HR_CFG_ACCESS_LOG if access_log else 0) | \
+                (HR_CFG_NESTED_TILES if nested_tiles else 0)
         cfg = _Config(ring_capacity, bc_bits, wc_bits, flags, shadow_budget, site_limit,
                       wave_bits, thread_bits, coalesce_width, log_capacity, 0)
         self.wave_bits = wave_bits or 6

@@ -190,6 +190,7 @@ KIND_R, KIND_W, KIND_A = 0, 1, 2
 KIND_SWITCH = 3          # not an access: switches the thread's monitoring off / on
 SPACE_GLOBAL, SPACE_LDS = 0, 1
 SCOPE_NONE, SCOPE_WAVE, SCOPE_BLOCK = 0, 1, 2
+SCOPE_TILE = 3           # a tile barrier, in the tiles whose bit is set in wave_mask
 
 
 def op_word(space: int, region: int, kind: int, index: int) -> int:
@@ -256,22 +257,27 @@ def random_program(seed: int, launches: int = 2, blocks: int = 2,
                    lds_words: int = 64, p_lds: float = 0.3,
                    kind_p=(0.5, 0.25, 0.25), scope_p=(0.3, 0.3, 0.4),
                    p_active: float = 1.0, wave_width: int = 64,
-                   p_switch: float = 0.0) -> Program:
+                   p_switch: float = 0.0, tile_width: int = 0) -> Program:
     """Random barrier program.  Addresses are drawn from small ranges so that
     conflicting accesses from different threads are common.  Every thread of
     a block sees the same phase structure, so barriers are uniform.
     wave_width only shapes the wave masks of wave-barrier phases.  A share
-    p_switch of the operations switch the thread's monitoring off or on."""
+    p_switch of the operations switch the thread's monitoring off or on.
+    tile_width > 0: scope_p has a fourth entry, the share of phases ending
+    with a tile barrier (tiles of tile_width lanes nested in the waves), whose
+    mask selects tiles."""
     rng = np.random.default_rng(seed)
     waves = min(64, (threads + wave_width - 1) // wave_width)
+    tiles = min(64, (threads + tile_width - 1) // tile_width) if tile_width else 0
     out = []
     kind_p = np.asarray(kind_p, dtype=np.float64)
     for _ in range(launches):
-        scopes = rng.choice(3, size=phases, p=scope_p).astype(np.uint8)
+        scopes = rng.choice(4 if tile_width else 3, size=phases, p=scope_p).astype(np.uint8)
         masks = np.zeros(phases, dtype=np.uint64)
         for p in range(phases):
-            if scopes[p] == SCOPE_WAVE:
-                bits = rng.random(waves) < 0.7
+            if scopes[p] in (SCOPE_WAVE, SCOPE_TILE):
+                groups = waves if scopes[p] == SCOPE_WAVE else tiles
+                bits = rng.random(groups) < 0.7
                 m = 0
                 for w in np.nonzero(bits)[0]:
                     m |= 1 << int(w)
@@ -341,6 +347,76 @@ def tile_reduce_program(tile: int, blocks: int, threads: int, drop: int = -1) ->
     masks = [mask if sc == SCOPE_WAVE else 0 for sc in scopes]
     launch = build_launch(blocks, threads, scopes, masks, per)
     return Program([launch], [blocks * threads * 2, blocks * threads], 2 * threads)
+
+
+def nested_reduce_program(tile: int, waves: int, blocks: int, drop_tile: int = -1,
+                          drop_wave: int = -1, wave: int = 64) -> Program:
+    """Two-level wave-synchronous reduction with tiles nested in waves, as an
+    access program (tile barriers: scope 3; wave barriers: scope 1).
+
+    Stage 1, per tile of `tile` lanes (a power of two): lane l reads global
+    input words l and l + tile of its tile's segment (region 0) and stores
+    them to its LDS segment of 2 * tile words, then log2(2 * tile) halving
+    steps (lanes l < h read seg[l] and seg[l + h], write seg[l]), each ended
+    by a tile barrier in every tile unless step == drop_tile.  Stage 2, per
+    wave of `wave` lanes: lane 0 of each tile reads its segment's seg[0] and
+    writes it to the wave's slot array (T = wave / tile slots, after all
+    segments), then a wave barrier; log2(T) halving steps over the slots
+    (lanes l < h read slot[l], slot[l + h], write slot[l]), each ended by a
+    wave barrier unless step == drop_wave.  Finally every lane reads slot 0
+    of its wave and writes global out[b * threads + t] (region 1).  One
+    launch; threads = waves * wave."""
+    assert tile >= 2 and tile & (tile - 1) == 0 and wave % tile == 0 and wave <= 64
+    T = wave // tile
+    assert T >= 2 and T & (T - 1) == 0
+    threads = waves * wave
+    tiles = threads // tile
+    assert tiles <= 64, "the barrier mask holds 64 groups"
+    n = 2 * tile
+    s1 = n.bit_length() - 1
+    s2 = T.bit_length() - 1
+    seg_words = tiles * n
+    phases = 1 + s1 + 1 + s2 + 1
+    per = [[[[] for _ in range(threads)] for _ in range(blocks)] for _ in range(phases)]
+    for b in range(blocks):
+        for t in range(threads):
+            l, g = t % tile, t // tile
+            base, gbase = g * n, b * threads * 2 + g * n
+            w, lw = t // wave, t % wave
+            slots = seg_words + w * T
+            ph = per[0][b][t]
+            for j in (l, l + tile):
+                ph.append(op_word(SPACE_GLOBAL, 0, KIND_R, gbase + j))
+                ph.append(op_word(SPACE_LDS, 0, KIND_W, base + j))
+            for st in range(s1):
+                h = n >> (st + 1)
+                if l < h:
+                    per[1 + st][b][t] += [op_word(SPACE_LDS, 0, KIND_R, base + l),
+                                          op_word(SPACE_LDS, 0, KIND_R, base + l + h),
+                                          op_word(SPACE_LDS, 0, KIND_W, base + l)]
+            if l == 0:
+                per[1 + s1][b][t] += [op_word(SPACE_LDS, 0, KIND_R, base),
+                                      op_word(SPACE_LDS, 0, KIND_W, slots + (g % T))]
+            for st in range(s2):
+                h = T >> (st + 1)
+                if lw < h:
+                    per[2 + s1 + st][b][t] += [op_word(SPACE_LDS, 0, KIND_R, slots + lw),
+                                               op_word(SPACE_LDS, 0, KIND_R, slots + lw + h),
+                                               op_word(SPACE_LDS, 0, KIND_W, slots + lw)]
+            per[phases - 1][b][t] += [op_word(SPACE_LDS, 0, KIND_R, slots),
+                                      op_word(SPACE_GLOBAL, 1, KIND_W, b * threads + t)]
+    all_tiles, all_waves = (1 << tiles) - 1, (1 << waves) - 1
+    # the loads end with a tile barrier, each tile step with one (unless
+    # dropped), the slot writes with a wave barrier, each wave step with one
+    # (unless dropped); the final reads and writes end with nothing
+    scopes = ([SCOPE_TILE] + [SCOPE_NONE if st == drop_tile else SCOPE_TILE for st in range(s1)] +
+              [SCOPE_WAVE] + [SCOPE_NONE if st == drop_wave else SCOPE_WAVE for st in range(s2)] +
+              [SCOPE_NONE])
+    masks = [all_tiles if sc == SCOPE_TILE else (all_waves if sc == SCOPE_WAVE else 0)
+             for sc in scopes]
+    assert len(scopes) == phases
+    launch = build_launch(blocks, threads, scopes, masks, per)
+    return Program([launch], [blocks * threads * 2, blocks * threads], seg_words + waves * T)
 
 
 # --------------------------------------------------------------------------

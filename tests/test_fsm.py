@@ -315,3 +315,80 @@ def test_tile_barrier_orders_only_its_tile():
     # after a wave barrier is ordered
     assert (hr.fsm_step(G, hr.fsm_step(G, 0, W, 1, 0, 1, 0, 0), R, 1, 0, 5, 0, 1) & 7) \
         != hr.T_RACE
+
+
+# ------------------------------------------------------ tiles nested in waves
+NESTED_SETTINGS = [
+    # blocks, threads, tile width, phases, max_ops, gwords, lwords, launches
+    (1, 8, 2, 5, 2, 3, 2, 2),
+    (2, 8, 4, 4, 2, 3, 3, 2),
+    (1, 96, 16, 4, 1, 40, 24, 2),     # two waves of 16-lane tiles (one partial)
+    (1, 128, 8, 3, 1, 48, 24, 1),
+    (1, 12, 2, 6, 1, 8, 6, 1),
+]
+
+
+@pytest.mark.parametrize("setting", NESTED_SETTINGS)
+def test_fsm_nested_tiles_flag_oracle_set_in_every_order(setting):
+    """Tiles nested in waves, each with their own barrier: the nested machine
+    reaches the oracle's set (waves of 64 lanes, tiles of the given width) in
+    every happens-before-consistent order, on programs mixing block, wave and
+    tile barriers."""
+    from fsm_replay import random_orders_nested, replay_nested
+    blocks, threads, tw, phases, max_ops, gw, lw, launches = setting
+    tb = tw.bit_length() - 1
+    racy = clean = 0
+    for s in range(30):
+        prog = si.random_program(4441 * s + tw * 3 + threads, launches=launches,
+                                 blocks=blocks, threads=threads, phases=phases,
+                                 max_ops=max_ops, global_regions=2, global_words=gw,
+                                 lds_words=lw, kind_p=(0.5, 0.25, 0.25),
+                                 scope_p=(0.2, 0.2, 0.15, 0.45), tile_width=tw)
+        log = oracle.model_program(prog, 64, tw)
+        want = oracle.flagged(log.copy(), 64, tw)
+        for order in random_orders_nested(log, 8, seed=s, tile_width=tw):
+            assert replay_nested(log, order, tb) == want, (setting, s)
+        touched = {(int(r["space"]), int(r["region"]), int(r["lds_block"]), int(r["index"]))
+                   for r in log}
+        racy += len(want)
+        clean += len(touched - want)
+    assert racy > 0 and clean > 0
+
+
+def test_nested_merge_is_the_summary_of_the_union():
+    """The fold's merge on the nested machine: merging the words two halves
+    of a barrier-consistent access sequence leave (the second half applied
+    to a fresh word) gives the race state exactly when the whole sequence
+    races, and otherwise the word the whole sequence leaves, up to the
+    identity fields that only pick which accessor is named."""
+    from fsm_replay import random_orders_nested
+    rng = np.random.default_rng(5)
+    checked = 0
+    for s in range(60):
+        prog = si.random_program(77 * s + 1, launches=1, blocks=2, threads=8, phases=4,
+                                 max_ops=2, global_regions=1, global_words=2, lds_words=1,
+                                 p_lds=0.0, kind_p=(0.5, 0.25, 0.25),
+                                 scope_p=(0.2, 0.2, 0.15, 0.45), tile_width=2)
+        log = oracle.model_program(prog, 64, 2)
+        for order in random_orders_nested(log, 3, seed=s, tile_width=2):
+            for key in {(int(log["region"][i]), int(log["index"][i])) for i in order}:
+                seq = [i for i in order if (int(log["region"][i]), int(log["index"][i])) == key]
+                cut = int(rng.integers(0, len(seq) + 1))
+
+                def run(part, start=0):
+                    w = start
+                    for i in part:
+                        r = log[i]
+                        w = hr.fsm_step_nested(0, w, int(r["kind"]), 0, int(r["block"]),
+                                               int(r["thread"]), int(r["bc"]), int(r["wc"]),
+                                               int(r["tc"]), 1)
+                    return w
+                whole = run(seq)
+                # the first part as seen, then the rest as an update that
+                # started from the first part's word and was overwritten
+                x = run(seq[:cut])
+                y = run(seq[cut:], x)
+                m = hr.fsm_merge_nested(y, x, 1)
+                assert ((m & 7) == hr.T_RACE) == ((whole & 7) == hr.T_RACE), (s, key, cut)
+                checked += 1
+    assert checked > 100
