@@ -64,6 +64,11 @@ typedef enum {
     /* HR_CFG_ACCESS_LOG only: more accesses than log_capacity; the log holds
      * the first log_capacity of them (in no particular order). */
     HR_W_LOG_TRUNCATED = 64,
+    /* A masked wave barrier (__syncwarp(mask) in an instrumented kernel)
+     * named only part of its caller's synchronization group (tile, or wave
+     * when wave_bits is 6): it was not taken as ordering anything, so the
+     * set may hold races that the barrier prevents (none is missed). */
+    HR_W_PARTIAL_BARRIER = 128,
     HR_E_INVAL = -1,   /* bad argument */
     HR_E_NOMEM = -2,   /* allocation failed or shadow budget exceeded */
     HR_E_HIP = -3,     /* a HIP runtime call failed */
@@ -278,7 +283,10 @@ hr_status hr_shadow_free(hr_ctx c, uint32_t region);
  * besides the thread's own identity and clocks: the shadow address of each
  * region (the update's sAddr comes from it and the element index), the
  * region sizes, the report ring and counters, the clock limits and the
- * current launch epoch.  The device pointers in it stay owned by the context.
+ * current launch epoch.  Its env.nested field is 1 in a context made with
+ * HR_CFG_NESTED_TILES: kernels must then check with the nested hooks
+ * (hr_tn, hr_nested.h), as the instrumenter's launchers do.  The device
+ * pointers in it stay owned by the context.
  * The block is valid until the next hr_kernel_end, hr_reset or region
  * change.  Errors: HR_E_INVAL (c NULL, out NULL, or cap too small: *size_out
  * still receives the size needed). */

@@ -109,7 +109,8 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
-EXAMPLES = ["reduce_block.hip", "stencil3.hip", "histogram.hip", "wave_reduce.hip"]
+EXAMPLES = ["reduce_block.hip", "stencil3.hip", "histogram.hip", "wave_reduce.hip",
+            "tile_reduce.hip"]
 EXAMPLES_LIB = os.path.join(PKG, "libhr_examples.so")
 
 

@@ -29,6 +29,7 @@
 #define HR_DEVF_STALL 8u    // a batched item gave up waiting for its phase
 #define HR_DEVF_LIMIT 16u   // a call site reached its record limit
 #define HR_DEVF_FOLD 32u    // a block or thread id exceeded a 4-byte word's field
+#define HR_DEVF_MASK 64u    // a masked wave barrier named less than its caller's group
 
 // Counter words.
 #define HR_CTR_HEAD 0     // ring append index
@@ -74,6 +75,8 @@ struct hr_env {
     hr_access_rec* log;                 // access log (debug), or null; only
                                         // written while count is not null
     uint32_t log_cap;
+    uint32_t nested;                    // 1: tiles of 2^wave_bits lanes nested in
+                                        // waves (the hr_tn hooks of hr_nested.h)
 };
 
 // Shadow layout of a region (the address-to-shadow map): the element at row
@@ -863,6 +866,18 @@ __device__ __forceinline__ T* hr_lat(const hr_env& e, const hr_thread& t, uint32
     return base + i;
 }
 
+// The checker state of a thread of an instrumented kernel: the flat
+// machine's hr_thread, or the nested machine's hr_tn (hr_nested.h).
+template <class T>
+__device__ T hr_start(const hr_env& e, uint32_t block, uint32_t thread);
+
+template <>
+__device__ __forceinline__ hr_thread hr_start<hr_thread>(const hr_env& e, uint32_t block,
+                                                         uint32_t thread)
+{
+    return hr_thread_make(e, block, thread);
+}
+
 // Switch the checking of this thread's accesses off or on (the paper lets a
 // tool enable or disable individual threads at run time, for instance to
 // track only a representative thread of each group of symmetric threads,
@@ -905,4 +920,48 @@ __device__ __forceinline__ void hr_barrier_wave(const hr_env& e, hr_thread& t)
         hr_set_flag(e, HR_DEVF_CLOCK);
     }
     hr_retag(e, t);
+}
+
+// The level a masked wave barrier (__syncwarp(mask): the lanes named in
+// `mask` synchronize) reaches for the calling thread, whose linear index in
+// its block is `thread`: HR_MASK_WAVE when the mask names every lane of the
+// caller's wave (a last wave of a block may be partial), HR_MASK_TILE when
+// it names every lane of the caller's aligned tile of 2^wave_bits lanes,
+// else HR_MASK_NONE (a mask that leaves out part of the caller's tile, or
+// the caller itself).  Every lane named by one mask gets the same answer
+// when the mask names whole tiles.  The paper's warp barriers (Sec. III-B)
+// cover a whole warp; groups below it are the future work of Sec. VI.
+enum { HR_MASK_NONE = 0, HR_MASK_TILE = 1, HR_MASK_WAVE = 2 };
+
+__device__ __forceinline__ uint32_t hr_mask_level(const hr_env& e, uint32_t thread, uint64_t mask)
+{
+    const uint32_t nthreads = blockDim.x * blockDim.y * blockDim.z;
+    const uint32_t lane = thread & 63u;
+    const uint32_t lanes = min(64u, nthreads - (thread & ~63u));
+    const uint64_t exists = lanes >= 64u ? ~0ull : ((1ull << lanes) - 1ull);
+    if (!((mask >> lane) & 1ull)) return HR_MASK_NONE;
+    if ((mask & exists) == exists) return HR_MASK_WAVE;
+    const uint32_t s = e.wave_bits;
+    if (s >= 6u) return HR_MASK_NONE;
+    const uint32_t w = 1u << s;
+    const uint64_t tile = (((1ull << w) - 1ull) << (lane & ~(w - 1u))) & exists;
+    return (mask & tile) == tile ? HR_MASK_TILE : HR_MASK_NONE;
+}
+
+// Masked wave barrier on the flat machine, whose synchronization groups are
+// the context's tiles (whole waves when wave_bits is 6): a mask that covers
+// the caller's group orders that group (a wider mask also orders lanes of
+// other groups, which this machine cannot express: it checks as if they
+// were not ordered, so it may report more, never less).  A narrower mask is
+// not taken as ordering anything, and hr_report warns HR_W_PARTIAL_BARRIER.
+__device__ __forceinline__ void hr_barrier_mask(const hr_env& e, hr_thread& t, uint64_t mask)
+{
+    if (hr_mask_level(e, t.thread, mask) != HR_MASK_NONE) {
+        hr_barrier_wave(e, t);
+        return;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (t.enabled == 1) hr_set_flag(e, HR_DEVF_MASK);
 }

@@ -210,3 +210,89 @@ __device__ __forceinline__ void hr_tn_enable(hr_tn& t, bool on)
 {
     t.enabled = on ? (t.enabled & ~2u) : (t.enabled | 2u);
 }
+
+// ---------------------------------------------------------------------------
+// Instrumented kernels on the nested machine: the rewriter's kernels are
+// templates over the thread state, and these overloads make the hr_tn
+// instance check with the nested hooks.
+// ---------------------------------------------------------------------------
+template <>
+__device__ __forceinline__ hr_tn hr_start<hr_tn>(const hr_env& e, uint32_t block, uint32_t thread)
+{
+    return hr_tn_make(e, block, thread);
+}
+
+__device__ __forceinline__ void hr_thread_enable(hr_tn& t, bool on) { hr_tn_enable(t, on); }
+
+__device__ __forceinline__ void hr_barrier_block(const hr_env& e, hr_tn& t)
+{
+    hr_nbarrier_block(e, t);
+}
+
+__device__ __forceinline__ void hr_barrier_wave(const hr_env& e, hr_tn& t)
+{
+    hr_nbarrier_wave(e, t);
+}
+
+// Masked wave barrier with tiles nested in waves: a mask that names the
+// caller's whole wave is a wave barrier, one that names the caller's whole
+// tile (and perhaps other tiles, whose mutual order this machine does not
+// express: it may then report more, never less) a tile barrier; a narrower
+// mask orders nothing, and hr_report warns HR_W_PARTIAL_BARRIER.
+__device__ __forceinline__ void hr_barrier_mask(const hr_env& e, hr_tn& t, uint64_t mask)
+{
+    const uint32_t level = hr_mask_level(e, t.thread, mask);
+    if (level == HR_MASK_WAVE) {
+        hr_nbarrier_wave(e, t);
+    } else if (level == HR_MASK_TILE) {
+        hr_nbarrier_tile(e, t);
+    } else {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (t.enabled == 1) hr_set_flag(e, HR_DEVF_MASK);
+    }
+}
+
+// A global access through a kernel-argument region (as hr_access).
+template <int KIND>
+__device__ __forceinline__ void hr_naccess(const hr_kargs& a, const hr_tn& t, uint32_t region,
+                                           uint64_t index, uint32_t site = 0)
+{
+    if (region >= HR_MAX_REGIONS) {
+        if (t.enabled == 1) hr_set_flag(a.env, HR_DEVF_RANGE);
+        return;
+    }
+    hr_ncheck<KIND>(a.env, t, a.shadow[region], a.n_elems[region], region, index,
+                          hr_lay_off(a.lay[region], index), site);
+}
+
+template <int K, class T>
+__device__ __forceinline__ T* hr_gat(const hr_kargs& a, const hr_rmap& m, const hr_tn& t,
+                                     uint32_t slot, T* base, int64_t i, uint32_t site)
+{
+    const uint32_t r = m.id[slot];
+    if (r < HR_MAX_REGIONS) {
+        if (K == 3) {
+            hr_naccess<0>(a, t, r, (uint64_t)i, site);
+            hr_naccess<1>(a, t, r, (uint64_t)i, site);
+        } else {
+            hr_naccess<K>(a, t, r, (uint64_t)i, site);
+        }
+    }
+    return base + i;
+}
+
+template <int K, class T>
+__device__ __forceinline__ T* hr_lat(const hr_env& e, const hr_tn& t, uint32_t* sh, uint32_t n,
+                                     uint32_t id, T* base, int64_t i, uint32_t site)
+{
+    const uint32_t idx = (i < 0 || i > (int64_t)UINT32_MAX) ? UINT32_MAX : (uint32_t)i;
+    if (K == 3) {
+        hr_naccess_lds<0>(e, t, sh, n, id, idx, site);
+        hr_naccess_lds<1>(e, t, sh, n, id, idx, site);
+    } else {
+        hr_naccess_lds<K>(e, t, sh, n, id, idx, site);
+    }
+    return base + i;
+}

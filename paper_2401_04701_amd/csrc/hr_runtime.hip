@@ -166,6 +166,7 @@ hr_env hr_env_of(const hr_config& cfg, hr_race_rec* ring, uint32_t* ctr,
     e.group = (cfg.flags & HR_CFG_WAVE_GROUPING) ? cfg.coalesce_width : 0u;
     e.site_limit = cfg.site_limit;
     e.wave_bits = cfg.wave_bits;
+    e.nested = (cfg.flags & HR_CFG_NESTED_TILES) ? 1u : 0u;
     e.word4 = (cfg.flags & HR_CFG_WORD4)
                   ? hr::c::layout(cfg.wc_bits, cfg.bc_bits, cfg.thread_bits)
                   : 0u;
@@ -497,6 +498,7 @@ extern "C" hr_status hr_report(hr_ctx c, hr_race* out, size_t cap, size_t* n_out
     if (ctr[HR_CTR_FLAGS] & HR_DEVF_STALL) warn |= HR_W_STALLED;
     if (ctr[HR_CTR_FLAGS] & HR_DEVF_LIMIT) warn |= HR_W_REPORT_LIMITED;
     if (ctr[HR_CTR_FLAGS] & HR_DEVF_FOLD) warn |= HR_W_FOLDED;
+    if (ctr[HR_CTR_FLAGS] & HR_DEVF_MASK) warn |= HR_W_PARTIAL_BARRIER;
     if (head > c->cfg.ring_capacity) warn |= HR_W_RING_OVERFLOW;
     if (head > c->cfg.ring_capacity || (ctr[HR_CTR_FLAGS] & HR_DEVF_LIMIT)) {
         // Race records are missing (ring overflow, or a site past its record

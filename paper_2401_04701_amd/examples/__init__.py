@@ -20,6 +20,7 @@ _PARAMS = {
     "stencil3": [P, P, i32, i32],
     "histogram": [P, P, i32, i32],
     "wave_reduce": [P, P, i32],
+    "tile_reduce": [P, P, i32, i32, i32],
 }
 
 

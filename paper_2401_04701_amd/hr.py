@@ -22,6 +22,7 @@ HR_W_STALLED = 8
 HR_W_REPORT_LIMITED = 16
 HR_W_FOLDED = 32
 HR_W_LOG_TRUNCATED = 64
+HR_W_PARTIAL_BARRIER = 128
 HR_RACE_FOLD, HR_RACE_SCANNED = 1, 2
 HR_S_INIT, HR_S_RACE, HR_S_BLOCKS, HR_S_WAVES, HR_S_THREADS, HR_S_THREAD = range(6)
 HR_E_INVAL, HR_E_NOMEM, HR_E_HIP, HR_E_STATE = -1, -2, -3, -4

@@ -15,9 +15,13 @@ array accesses and barriers, and rewrites the source text:
   ``(*hr_lat<K>(hr_a.env, hr_t, hr_sh_s, N, id, s, (i), line))`` with an LDS
   shadow array ``hr_sh_s`` cleared at kernel start;
 * ``__syncthreads()`` becomes ``hr_barrier_block(hr_a.env, hr_t)``, and
-  ``__syncwarp()`` (with or without a mask: HIP synchronises the whole wave,
-  and the mask must name the active lanes) becomes
-  ``hr_barrier_wave(hr_a.env, hr_t)``.
+  ``__syncwarp(mask)`` becomes ``hr_barrier_mask(hr_a.env, hr_t, mask)``
+  (``__syncwarp()``: the full mask), which takes the barrier at the level
+  the mask names for the calling lane: its whole wave, or its whole aligned
+  tile of the context's tile width (``hr_config.wave_bits``), which HIP
+  code reaches by letting each tile call ``__syncwarp`` with its own lanes'
+  mask.  A mask narrower than that orders nothing for the checker, and the
+  report warns of it.
 
 K is the access kind decided from the expression around the subscript: the
 left side of ``=`` is a write, of a compound assignment or ``++``/``--`` a read
@@ -27,11 +31,15 @@ source line.  Subscripts of other shapes (multi-dimensional arrays, members,
 an address taken for another use, elements not 4 bytes wide) are left
 unchecked and listed in the report.
 
-Each kernel gains two parameters (``hr_kargs hr_a, hr_rmap hr_m``) and an
-``extern "C"`` launcher ``hr_launch_<kernel>(ctx, regions, n_regions, grid,
+Each kernel becomes a template over the checker's thread state
+(``hr_thread``: block and wave, or tile, barriers; ``hr_tn``: tiles nested
+in waves, for a context made with ``HR_CFG_NESTED_TILES``), gains two
+parameters (``hr_kargs hr_a, hr_rmap hr_m``) and an ``extern "C"`` launcher ``hr_launch_<kernel>(ctx, regions, n_regions, grid,
 block, lds_bytes, stream, <original parameters>)``; ``regions[j]`` is the
 context region (from ``hr_shadow_alloc``) of the kernel's j-th pointer
-parameter, which must point at the region's start.
+parameter, which must point at the region's start.  The launcher runs the
+instance the context asks for.  Kernels that are already templates, or that
+have C linkage, are not supported.
 """
 from __future__ import annotations
 
@@ -208,9 +216,18 @@ def analyse(src: str, fn: dict) -> Tuple[List[Edit], Report, dict]:
                 rep.shared_arrays.append((node["name"], int(m.group(2))))
             else:
                 rep.skipped.append(f"shared {node['name']}: {node['type']['qualType']}")
-        if k == "CallExpr" and _callee(node) in ("__syncthreads", "__syncwarp"):
+        if k == "CallExpr" and _callee(node) == "__syncthreads":
             b, e = span(node)
-            edits.append(Edit(b, e, "bar" if _callee(node) == "__syncthreads" else "wbar"))
+            edits.append(Edit(b, e, "bar"))
+            rep.barriers += 1
+        if k == "CallExpr" and _callee(node) == "__syncwarp":
+            b, e = span(node)
+            args = (node.get("inner") or [])[1:]
+            if args:                            # the mask expression, itself rewritten
+                edits.append(Edit(b, e, "wbar", ("hr_barrier_mask(hr_a.env, hr_t, "
+                                                 "(unsigned long long)(", span(args[0]), "))")))
+            else:
+                edits.append(Edit(b, e, "wbar"))
             rep.barriers += 1
         if k == "ArraySubscriptExpr":
             base = _strip(node["inner"][0])
@@ -268,8 +285,8 @@ def _apply(src: str, lo: int, hi: int, edits: List[Edit]) -> str:
         out.append(src[cur:e.start])
         if e.kind == "bar":
             out.append("hr_barrier_block(hr_a.env, hr_t)")
-        elif e.kind == "wbar":
-            out.append("hr_barrier_wave(hr_a.env, hr_t)")
+        elif e.kind == "wbar" and not e.parts:
+            out.append("hr_barrier_mask(hr_a.env, hr_t, ~0ull)")
         else:
             pre, (ib, ie), post = e.parts
             nested = [x for x in edits if ib <= x.start and x.end <= ie and x is not e]
@@ -302,11 +319,34 @@ extern "C" hr_status hr_launch_{name}(hr_ctx hr_c, const uint32_t* hr_regions,
         hr_m.id[j] = hr_regions[j];
     }}
     (void)hipGetLastError();
-    hipLaunchKernelGGL({name}, dim3(hr_gx, hr_gy, hr_gz), dim3(hr_bx, hr_by, hr_bz), hr_lds,
-                       (hipStream_t)hr_stream{sep}{args}, hr_a, hr_m);
+    if (hr_a.env.nested)
+        hipLaunchKernelGGL({name}<hr_tn>, dim3(hr_gx, hr_gy, hr_gz), dim3(hr_bx, hr_by, hr_bz),
+                           hr_lds, (hipStream_t)hr_stream{sep}{args}, hr_a, hr_m);
+    else
+        hipLaunchKernelGGL({name}<hr_thread>, dim3(hr_gx, hr_gy, hr_gz),
+                           dim3(hr_bx, hr_by, hr_bz), hr_lds, (hipStream_t)hr_stream{sep}{args},
+                           hr_a, hr_m);
     return hipGetLastError() == hipSuccess ? HR_OK : HR_E_HIP;
 }}
 """
+
+
+def _template_point(src: str, name: str) -> int:
+    """Where `template <class hr_T>` goes before kernel `name`'s definition:
+    at the start of the line that holds its __global__ (so a leading
+    `static` stays after it)."""
+    ms = [m for m in re.finditer(r"__global__\s+(?:__launch_bounds__\s*\([^)]*\)\s*)?void\s+"
+                                 + re.escape(name) + r"\s*\(", src)]
+    if len(ms) != 1:
+        raise RuntimeError(f"{name}: expected one definition, found {len(ms)}")
+    line = src.rfind("\n", 0, ms[0].start()) + 1
+    lead = src[line:ms[0].start()]
+    if re.search(r"\btemplate\b|extern\s*\"C\"", src[max(0, line - 200):ms[0].start()]
+                 .split(";")[-1].split("}")[-1]):
+        raise RuntimeError(f"{name}: template kernels and kernels with C linkage are not supported")
+    if lead.strip() and lead.strip() not in ("static", "inline", "static inline"):
+        raise RuntimeError(f"{name}: unsupported declaration prefix {lead.strip()!r}")
+    return line
 
 
 def instrument(path: str, kernels: Optional[List[str]] = None, extra_args=()) -> Tuple[str, List[Report]]:
@@ -323,6 +363,7 @@ def instrument(path: str, kernels: Optional[List[str]] = None, extra_args=()) ->
         edits, rep, pos = analyse(src, fn)
         if len(rep.pointer_params) > 8:
             raise RuntimeError(f"{name}: more than 8 pointer parameters")
+        inserts.append((_template_point(src, name), "template <class hr_T>\n"))
         edits_all += edits
         sig = ", hr_kargs hr_a, hr_rmap hr_m" if pos["params_end"] is not None else \
               "hr_kargs hr_a, hr_rmap hr_m"
@@ -330,7 +371,7 @@ def instrument(path: str, kernels: Optional[List[str]] = None, extra_args=()) ->
             inserts.append((pos["params_end"], sig))
         else:                                   # no parameters: insert inside "()"
             inserts.append((src.index("(", src.index(name, span(fn)[0])) + 1, sig))
-        pro = ["", "    hr_thread hr_t = hr_thread_make(hr_a.env, blockIdx.x + gridDim.x * "
+        pro = ["", "    hr_T hr_t = hr_start<hr_T>(hr_a.env, blockIdx.x + gridDim.x * "
                    "(blockIdx.y + gridDim.y * blockIdx.z), threadIdx.x + blockDim.x * "
                    "(threadIdx.y + blockDim.y * threadIdx.z));"]
         for arr, words in rep.shared_arrays:
@@ -348,14 +389,14 @@ def instrument(path: str, kernels: Optional[List[str]] = None, extra_args=()) ->
         reports.append(rep)
     # apply: edits (non-overlapping at top level) and insertions
     points = sorted(set([0, len(src)] + [p for p, _ in inserts]))
-    out = []
+    out = [text for p, text in inserts if p == 0]
     for a, b in zip(points[:-1], points[1:]):
         out.append(_apply(src, a, b, edits_all))
         out.extend(text for p, text in inserts if p == b)
     body = "".join(out)
     head = ('// Instrumented by paper_2401_04701_amd.instrument: every checked access calls\n'
             '// the race checker\'s shadow update (hr_gat / hr_lat), barriers advance its\n'
-            '// clocks.  Generated file.\n#include "hr_device.h"\n')
+            '// clocks.  Generated file.\n#include "hr_nested.h"\n')
     return head + body + "".join(launchers), reports
 
 

@@ -74,11 +74,49 @@ def stencil3_program(n: int, blocks: int, seeded_block: int) -> si.Program:
     return si.Program([launch], [n, n], 258)
 
 
-def flagged_as(program: si.Program, regions, wave_width: int = 64) -> set:
+def flagged_as(program: si.Program, regions, wave_width: int = 64, tile_width: int = 0) -> set:
     """Oracle flagged set of a program with its global regions renamed to the
     context regions `regions` (program region j -> regions[j]); LDS keys keep
     array id 0."""
     out = set()
-    for sp, rg, lb, ix in oracle.flagged_program(program, wave_width):
+    for sp, rg, lb, ix in oracle.flagged_program(program, wave_width, tile_width):
         out.add((sp, regions[rg] if sp == 0 else rg, lb, ix))
     return out
+
+
+def _rescope(program: si.Program, fn) -> si.Program:
+    launches = []
+    for l in program.launches:
+        scope, mask = zip(*(fn(int(sc), int(m), l.threads) for sc, m in zip(l.scope, l.wave_mask)))
+        launches.append(si.Launch(l.blocks, l.threads, np.array(scope, dtype=np.uint8),
+                                  np.array(mask, dtype=np.uint64), l.op_off, l.ops))
+    return si.Program(launches, program.global_words, program.lds_words)
+
+
+def as_tile_groups(program: si.Program, tile: int) -> si.Program:
+    """A program with tile barriers (scope 3) and wave barriers as a checker
+    whose only groups below the block are tiles of `tile` lanes sees it (to
+    be evaluated with wave width `tile`): a tile barrier stays a barrier of
+    its tiles, and a wave barrier becomes a barrier of every tile of the
+    waves it names, each tile on its own."""
+    per = 64 // tile
+
+    def fn(sc, m, threads):
+        if sc == si.SCOPE_TILE:
+            return si.SCOPE_WAVE, m
+        if sc == si.SCOPE_WAVE:
+            tiles = 0
+            for w in range(64):
+                if (m >> w) & 1:
+                    for g in range(w * per, min(64, (w + 1) * per)):
+                        tiles |= 1 << g
+            return si.SCOPE_WAVE, tiles
+        return sc, m
+    return _rescope(program, fn)
+
+
+def without_tile_barriers(program: si.Program) -> si.Program:
+    """The program as a checker of whole waves sees it when the tile
+    barriers' masks are narrower than its groups: no ordering at all."""
+    return _rescope(program, lambda sc, m, threads: (si.SCOPE_NONE, 0) if sc == si.SCOPE_TILE
+                    else (sc, m))

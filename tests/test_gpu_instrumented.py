@@ -8,7 +8,8 @@ import pytest
 
 import oracle
 import synth_inputs as si
-from example_programs import flagged_as, histogram_program, stencil3_program
+from example_programs import (as_tile_groups, flagged_as, histogram_program, stencil3_program,
+                              without_tile_barriers)
 
 pytestmark = pytest.mark.gpu
 
@@ -96,8 +97,9 @@ def test_instrumented_histogram(env, plain):
         assert (bins.cpu().numpy() == counts).all()
 
 
+@pytest.mark.parametrize("nested", [False, True])
 @pytest.mark.parametrize("drop", [-1, 0, 3, 5, 6])
-def test_instrumented_wave_barriers(env, drop):
+def test_instrumented_wave_barriers(env, drop, nested):
     """__syncwarp becomes the checker's wave barrier: per-wave tree sums in
     LDS race exactly where the dropped wave barrier leaves two steps in one
     wave epoch (the sub-wave reduction's closed form with 64-lane tiles)."""
@@ -106,8 +108,10 @@ def test_instrumented_wave_barriers(env, drop):
     x = np.random.default_rng(7 + drop).integers(0, 1 << 20, blocks * 512, dtype=np.int32)
     inp = torch.from_numpy(x).cuda()
     out = torch.zeros(blocks * 256, dtype=torch.int32, device="cuda")
-    say("instrumented wave reduction drop", drop)
-    with hr.Context() as ctx:
+    say("instrumented wave reduction drop", drop, "nested", nested)
+    # with tiles nested in waves, a whole-wave __syncwarp() is a wave barrier
+    kw = {"nested_tiles": True, "wave_bits": 3} if nested else {}
+    with hr.Context(**kw) as ctx:
         r_in, r_out = ctx.shadow_alloc(inp), ctx.shadow_alloc(out)
         ex.launch("wave_reduce", ctx, [r_in, r_out], (blocks,), (256,), inp, out, drop)
         ctx.kernel_end()
@@ -118,3 +122,62 @@ def test_instrumented_wave_barriers(env, drop):
     if drop < 0:
         want = x.astype(np.int64).reshape(blocks, 4, 128).sum(axis=2)
         assert (out.cpu().numpy().reshape(blocks, 4, 64) == want[:, :, None]).all()
+
+
+TILE_DROPS = [(-1, -1), (0, -1), (2, -1), (-1, 0), (1, 0)]
+
+
+@pytest.mark.parametrize("tile", [4, 8, 16])
+@pytest.mark.parametrize("threads", [64, 128])
+def test_instrumented_masked_tile_barriers(env, tile, threads):
+    """__syncwarp(mask of the caller's tile) and whole-wave __syncwarp() in
+    one kernel (examples/tile_reduce.hip: tiles reduce with tile barriers,
+    waves combine the tiles' sums with wave barriers), with barriers dropped:
+
+    * tiles nested in waves: the tile masks are tile barriers and the full
+      masks wave barriers, so the set is the oracle's nested set of the
+      kernel's access program, and empty with every barrier (dropping the
+      last tile step's barrier leaves no race with 4-lane tiles: that step
+      and the next are lane 0's alone);
+    * tiles as the only groups (wave_bits = log2 tile): both kinds order the
+      caller's tile only -- the oracle's set with every barrier made a tile
+      barrier (a superset: it reports cross-tile pairs the wave orders);
+    * whole waves (wave_bits 6): tile masks are narrower than the group and
+      order nothing, with HR_W_PARTIAL_BARRIER -- the oracle's set without
+      the tile barriers."""
+    torch, hr, ex = env
+    blocks, waves = 3, threads // 64
+    tb = tile.bit_length() - 1
+    x = np.random.default_rng(11 + tile).integers(0, 1 << 20, blocks * threads * 2,
+                                                  dtype=np.int32)
+    inp = torch.from_numpy(x).cuda()
+    for dt, dw in TILE_DROPS:
+        if dw >= (64 // tile).bit_length() - 1:
+            continue
+        prog = si.nested_reduce_program(tile, waves, blocks, dt, dw)
+        for mode in ("nested", "tiles", "waves"):
+            say("instrumented tile reduction", tile, threads, dt, dw, mode)
+            out = torch.zeros(blocks * threads, dtype=torch.int32, device="cuda")
+            kw = {"nested": {"nested_tiles": True, "wave_bits": tb},
+                  "tiles": {"wave_bits": tb}, "waves": {}}[mode]
+            with hr.Context(**kw) as ctx:
+                r_in, r_out = ctx.shadow_alloc(inp), ctx.shadow_alloc(out)
+                ex.launch("tile_reduce", ctx, [r_in, r_out], (blocks,), (threads,), inp, out,
+                          tile, dt, dw)
+                ctx.kernel_end()
+                got, st = ctx.flagged(), ctx.status
+            regs = [r_in, r_out]
+            if mode == "nested":
+                want = flagged_as(prog, regs, 64, tile)
+                assert st == 0 and got == want
+                if dt == dw == -1:
+                    assert want == set()
+            elif mode == "tiles":
+                want = flagged_as(as_tile_groups(prog, tile), regs, tile)
+                assert st == 0 and got == want
+            else:
+                want = flagged_as(without_tile_barriers(prog), regs, 64)
+                assert st == hr.HR_W_PARTIAL_BARRIER and got == want
+            if dt == dw == -1:
+                sums = x.astype(np.int64).reshape(blocks, waves, 128).sum(axis=2)
+                assert (out.cpu().numpy().reshape(blocks, waves, 64) == sums[:, :, None]).all()

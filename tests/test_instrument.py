@@ -33,9 +33,56 @@ def test_wave_barrier_example():
     assert (rep.global_sites, rep.lds_sites, rep.barriers, rep.skipped) == (3, 6, 1, [])
     body = text.split("LDS shadow cleared")[1]
     assert "__syncwarp" not in body and "hr_barrier_block" not in body
-    assert body.count("hr_barrier_wave(hr_a.env, hr_t)") == 1
+    assert body.count("hr_barrier_mask(hr_a.env, hr_t, ~0ull)") == 1   # no mask: the whole wave
     # s[base + l] = s[base + l] + s[base + l + h]: two reads, then the write
     assert sorted(kinds(text, "hr_lat")) == [(0, 16), (0, 16), (0, 19), (1, 12), (1, 13), (1, 16)]
+
+
+def test_masked_wave_barriers_and_thread_state():
+    """__syncwarp(mask) keeps its mask for the checker's barrier (which takes
+    the tile or wave level from it at run time); the kernel becomes a
+    template over the thread state, and the launcher runs the nested-machine
+    instance in contexts with nested tiles."""
+    text, (rep,) = instrument.instrument(os.path.join(EX, "tile_reduce.hip"))
+    assert (rep.global_sites, rep.lds_sites, rep.barriers, rep.skipped) == (3, 11, 4, [])
+    body = text.split("LDS shadow cleared")[1]
+    assert "__syncwarp" not in body
+    assert body.count("hr_barrier_mask(hr_a.env, hr_t, (unsigned long long)(mine))") == 2
+    assert body.count("hr_barrier_mask(hr_a.env, hr_t, ~0ull)") == 2
+    assert "template <class hr_T>\n__global__ void tile_reduce(" in text
+    assert "hr_T hr_t = hr_start<hr_T>(hr_a.env," in text
+    launcher = text.split("hr_launch_tile_reduce")[1]
+    assert "if (hr_a.env.nested)" in launcher
+    assert "tile_reduce<hr_tn>" in launcher and "tile_reduce<hr_thread>" in launcher
+    assert '#include "hr_nested.h"' in text
+
+
+def test_mask_expression_is_rewritten_and_unsupported_kernels(tmp_path):
+    src = tmp_path / "k.hip"
+    src.write_text("""#include <hip/hip_runtime.h>
+static __global__ void k(const unsigned long long* masks, const int* sel, int* out)
+{
+    __syncwarp(masks[threadIdx.x / 8]);
+    __syncwarp((unsigned long long)sel[threadIdx.x]);
+    out[threadIdx.x] = 1;
+}
+""")
+    text, (rep,) = instrument.instrument(str(src))
+    assert rep.barriers == 2 and rep.global_sites == 2
+    # 8-byte elements are not checked: that mask's load stays as written
+    assert "hr_barrier_mask(hr_a.env, hr_t, (unsigned long long)(masks[threadIdx.x / 8]))" in text
+    assert any("masks" in x for x in rep.skipped)
+    # a 4-byte element read inside the mask is checked like any other read
+    assert ("hr_barrier_mask(hr_a.env, hr_t, (unsigned long long)((unsigned long long)"
+            "(*hr_gat<0>(hr_a, hr_m, hr_t, 1, sel, (threadIdx.x), 5))))") in text
+    assert "template <class hr_T>\nstatic __global__ void k(" in text
+    bad = tmp_path / "t.hip"
+    bad.write_text("""#include <hip/hip_runtime.h>
+extern "C" __global__ void kc(int* out) { out[threadIdx.x] = 0; }
+""")
+    import pytest
+    with pytest.raises(RuntimeError, match="C linkage"):
+        instrument.instrument(str(bad))
 
 
 def test_histogram_atomic_and_compound_kinds():
@@ -94,3 +141,27 @@ def test_example_programs_match_their_closed_forms():
     prog = stencil3_program(600, 3, -1)
     prog.launches[0].scope[0] = si.SCOPE_NONE
     assert {k for k in flagged_as(prog, [0, 1]) if k[0] == 1}
+
+
+def test_tile_reduce_views_of_the_barriers():
+    """The expected sets of examples/tile_reduce.hip under the three ways a
+    context can take its barriers: tiles nested in waves (exact), tiles as
+    the only groups (wave barriers order each tile alone) and whole waves
+    (tile masks order nothing).  The coarser views only add keys, and the
+    race-free kernel is race-free only when nested."""
+    import oracle
+    import synth_inputs as si
+    from example_programs import as_tile_groups, without_tile_barriers
+    for tile in (4, 8):
+        for dt, dw in ((-1, -1), (0, -1), (-1, 0)):
+            p = si.nested_reduce_program(tile, 2, 2, dt, dw)
+            exact = oracle.flagged_program(p, 64, tile)
+            tiles = oracle.flagged_program(as_tile_groups(p, tile), tile)
+            waves = oracle.flagged_program(without_tile_barriers(p), 64)
+            assert exact <= tiles and exact <= waves
+            assert (exact == set()) == (dt == dw == -1)
+            assert tiles != exact and waves != exact or dt == 0
+            # without tile barriers every word of a segment's first half
+            # that two lanes touch (all but word 0, lane 0's alone) races
+            seg = {k[3] for k in waves if k[0] == si.SPACE_LDS and k[3] < 2 * 128}
+            assert seg == {g * 2 * tile + j for g in range(128 // tile) for j in range(1, tile)}
