@@ -415,6 +415,12 @@ def bench_serving(args, torch, si, hr, stream):
     note("warm-up")
     hr.serve(ctx, insts[:64], np.zeros(64), stream=stream)
     hr.serve(ctx, insts[:16], np.zeros(16), serial=True, stream=stream)
+    pat = np.array([s["pattern"] for s in specs])
+    big = np.array([bool(s.get("big")) for s in specs])
+    classes = {"reduce": pat == si.PAT_REDUCE,
+               "stencil_small": (pat == si.PAT_JACOBI) & ~big,
+               "stencil_4096sq": big,
+               "labelprop": pat == si.PAT_LABELPROP}
     out, equal = [], True
     for rate in rates:
         arr = si.poisson_arrivals(si.master_seed(4) + int(rate), len(js), rate)
@@ -422,7 +428,7 @@ def bench_serving(args, torch, si, hr, stream):
         for mode in ("served", "serial"):
             note("rate", rate, mode)
             sets[mode], times = hr.serve(ctx, insts, arr, serial=(mode == "serial"),
-                                         stream=stream)
+                                         large_burst=args.serve_large_burst, stream=stream)
             fin = np.array([t.finish_s for t in times])
             lat = fin - arr
             span = float(fin.max())
@@ -430,9 +436,13 @@ def bench_serving(args, torch, si, hr, stream):
                          "makespan_s": span, "p50_ms": pct(lat, 50) * 1e3,
                          "p99_ms": pct(lat, 99) * 1e3,
                          "clean_status": all(t.status == 0 for t in times),
-                         "flagged": int(sum(t.flagged for t in times))}
-            note("  %.0f jobs/s, p50 %.2f ms, p99 %.2f ms"
-                 % (row[mode]["jobs_per_s"], row[mode]["p50_ms"], row[mode]["p99_ms"]))
+                         "flagged": int(sum(t.flagged for t in times)),
+                         "by_class": {c: {"jobs": int(m.sum()), "p50_ms": pct(lat[m], 50) * 1e3,
+                                          "p99_ms": pct(lat[m], 99) * 1e3}
+                                      for c, m in classes.items() if m.any()}}
+            note("  %.0f jobs/s, p50 %.2f ms, p99 %.2f ms; p50 by class %s"
+                 % (row[mode]["jobs_per_s"], row[mode]["p50_ms"], row[mode]["p99_ms"],
+                    {c: round(v["p50_ms"], 3) for c, v in row[mode]["by_class"].items()}))
         # every job's flagged set served in the mix equals its set run alone
         row["equal_results"] = (sets["served"] == sets["serial"]
                                 and row["served"]["clean_status"]
@@ -452,8 +462,10 @@ def bench_serving(args, torch, si, hr, stream):
         "config": {"workload": "serving_poisson_stream_%d_jobs_5pct_4096sq_stencil" % len(js),
                    "jobs": len(js), "full_size_jobs": sum(bool(s.get("big")) for s in specs),
                    "checks_per_stream": int(checks), "shadow_budget_bytes": 64 << 30,
+                   "large_burst": args.serve_large_burst or "all phases",
                    "parallelism": "single GPU"},
         "p50_ms": top["served"]["p50_ms"], "p99_ms": top["served"]["p99_ms"],
+        "p50_ms_by_class": {c: v["p50_ms"] for c, v in top["served"]["by_class"].items()},
         "served_vs_serial": top["served_vs_serial_jobs_per_s"],
         "equal_results": bool(equal), "rates": out}
     print(json.dumps(res), flush=True)
@@ -480,6 +492,8 @@ def main():
     ap.add_argument("--rates", default="100,250,500,1000,2500,5000",
                     help="serving: arrival rates in jobs/s")
     ap.add_argument("--serve-jobs", type=int, default=2000, help="serving: jobs per stream")
+    ap.add_argument("--serve-large-burst", type=int, default=0,
+                    help="serving: phases of a large stencil job per iteration (0: all)")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="first copy 256 MiB once with the library's copy kernel, the "
                          "calibration of the HBM byte counters of a counter run")

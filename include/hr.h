@@ -49,7 +49,8 @@ typedef enum {
      * neither checked nor performed by the library's own kernels. */
     HR_W_OUT_OF_RANGE = 4,
     /* A batched work item waited too long for the previous phase of its job
-     * and was skipped; that job's results are incomplete. */
+     * and was skipped, or a tile of a served large stencil job waited too
+     * long at its barrier and went on; that job's results are incomplete. */
     HR_W_STALLED = 8,
     /* Some call site reached hr_config.site_limit: its further race records
      * were dropped.  hr_report still completes the global-memory part of the
@@ -630,7 +631,10 @@ hr_status hr_job_run_static(const hr_instance* inst, const hr_config* cfg, hr_ra
  * phase has been reported.  Jobs run in four lanes by class (short jobs;
  * label propagation under 64 items per phase; label propagation of 64 items
  * or more; other jobs of more than 1024 items per phase); each lane runs its
- * own iterations, and the lanes' iterations overlap on the device.
+ * own iterations, and the lanes' iterations overlap on the device.  The
+ * large-job lane runs one job at a time, in admission order; a stencil job
+ * there runs large_burst phases per iteration, as launches of the kernel
+ * hr_jacobi_check runs. 
  * ---------------------------------------------------------------------- */
 
 typedef struct {
@@ -651,7 +655,8 @@ typedef struct {
     uint32_t max_items;      /* work items (1024-thread blocks) of the resident
                                 jobs' phases in one iteration, at most
                                 HR_SERVE_MAX_ITEMS; 0: HR_SERVE_MAX_ITEMS */
-    uint32_t pad;
+    uint32_t large_burst;    /* phases of a large stencil job that one iteration
+                                of the large-job lane runs; 0: all remaining */
 } hr_serve_config;
 
 /* One iteration is one launch of 1024-thread blocks, whose grid may not

@@ -29,7 +29,7 @@ def hipcc() -> str:
 
 
 KERNELS_JSON = os.path.join(PKG, "libhr_kernels.json")
-FINGERPRINTED = ["hr_workloads.hip"]
+FINGERPRINTED = ["hr_workloads.hip", "hr_serve.hip"]
 
 
 def _kernel_bodies(asm: str) -> dict:

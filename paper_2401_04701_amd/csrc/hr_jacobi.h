@@ -19,11 +19,64 @@ constexpr uint32_t JACOBI_TILE_WORDS = JACOBI_TILE * JACOBI_TILE;
 // standalone kernels); without it, in two (the batch and serving workers,
 // which inline every workload body under one register budget: the proxy
 // lanes' second identity would spill there).
-template <int CHECK, class G = hr_gref, bool ONE_HALO = false>
+// The synchronization of a tile's threads in jacobi_body: the hardware
+// block's barrier, with the LDS shadow cleared in the body.
+struct hr_block_sync {
+    static constexpr bool CLEARS = true;   // the body clears its LDS shadow
+    template <int CHECK>
+    __device__ __forceinline__ void bar(const hr_env& e, hr_thread& t) { hr_bar<CHECK>(e, t); }
+};
+
+// The synchronization of the 256 threads (4 waves) of one tile when a
+// hardware block runs several tiles side by side: a barrier of those waves
+// alone, on an arrival counter in LDS, so that a tile's waves do not wait
+// for the other tiles' slowest wave.  The kernel clears the LDS shadow and
+// the counter, then passes one block barrier, before the body runs.  Every
+// wave of the tile reaches each barrier (the body's barriers are not under
+// divergent control), and all are resident with their block, so the wait
+// ends; it is bounded all the same, and a wait that runs out is reported as
+// a stall (HR_DEVF_STALL) and goes on.  For the checker it is the tile's
+// block barrier: it advances the block clock as hr_barrier_block does.
+struct hr_tile_sync {
+    static constexpr bool CLEARS = false;
+    static constexpr uint32_t SPIN_LIMIT = 1u << 22;
+    uint32_t* arrive;     // the tile's counter in LDS, zero before the body
+    uint32_t target;      // arrivals that end the next barrier
+    template <int CHECK>
+    __device__ __forceinline__ void bar(const hr_env& e, hr_thread& t)
+    {
+        target += 4u;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        if (__lane_id() == 0)
+            __hip_atomic_fetch_add(arrive, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        for (uint32_t spin = 0;
+             __hip_atomic_load(arrive, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) < target;
+             ++spin) {
+            if (spin >= SPIN_LIMIT) {
+                hr_set_flag(e, HR_DEVF_STALL);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        if constexpr (CHECK) {
+            t.bc += 1;
+            t.wc = 0;
+            if (t.bc > e.bc_max && (t.enabled & 1u)) {
+                t.enabled &= ~1u;
+                hr_set_flag(e, HR_DEVF_CLOCK);
+            }
+            hr_retag(e, t);
+        }
+    }
+};
+
+template <int CHECK, class G = hr_gref, bool ONE_HALO = false, class SYNC = hr_block_sync>
 __device__ void jacobi_body(const hr_env& e, const G& gold, const G& gnew,
                             const float* __restrict__ uo, float* __restrict__ un, uint32_t ny,
                             uint32_t nx, uint32_t nbx, const int32_t* __restrict__ seeds,
-                            uint32_t lb, uint32_t t, float* tile, uint32_t* tsh, uint32_t lds_id)
+                            uint32_t lb, uint32_t t, float* tile, uint32_t* tsh, uint32_t lds_id,
+                            SYNC sync = SYNC{})
 {
     constexpr uint32_t TW = JACOBI_TILE_WORDS, TL = JACOBI_TILE;
     const uint32_t tx = t & 15u, ty = (t >> 4) & 15u;
@@ -33,9 +86,11 @@ __device__ void jacobi_body(const hr_env& e, const G& gold, const G& gnew,
     hr_thread th{};
     if constexpr (CHECK) {
         th = hr_thread_make(e, lb, t);
-        if (t < 256)
-            for (uint32_t i = t; i < TW; i += 256) tsh[i] = 0;
-        __syncthreads();
+        if constexpr (SYNC::CLEARS) {
+            if (t < 256)
+                for (uint32_t i = t; i < TW; i += 256) tsh[i] = 0;
+            __syncthreads();
+        }
     }
     const size_t g = (size_t)gy * nx + gx;
     const uint32_t cl = (ty + 1) * TL + tx + 1;
@@ -130,7 +185,7 @@ __device__ void jacobi_body(const hr_env& e, const G& gold, const G& gnew,
             hr_gs<0, CHECK>(e, hth, gold, ph, ha, HR_SITE_JACOBI_HALO);
         }
     }
-    hr_bar<CHECK>(e, th);
+    sync.template bar<CHECK>(e, th);
     if (inside) {
         // the output word's shadow load is in flight during the LDS reads
         const hr_el xo = gnew.at2(gy, gx, g);
@@ -193,6 +248,47 @@ __global__ __launch_bounds__(256, 8) void k_jacobi(hr_kargs a, hr_gref gold, hr_
     using G = hr_gref_map<0, 0>;
     jacobi_body<CHECK, G, true>(a.env, G{gold}, G{gnew}, uo, un, ny, nx, gridDim.x, seeds,
                                 blockIdx.y * gridDim.x + blockIdx.x, threadIdx.x, tile, tsh, 0);
+}
+
+// Four consecutive tiles per 1024-thread block, each quarter of the block
+// running the tuned body of k_jacobi on its own tile (row-major maps,
+// checked), for launches that share the device with other streams' work:
+// 1024-thread blocks of other kernels find room as this kernel's blocks
+// retire, where 256-thread blocks would take every freed slot back.
+// TILE_SYNC: each quarter syncs its own waves (hr_tile_sync) after one
+// block barrier at the start; else the body's barriers are the whole
+// block's.  Quarters past the last tile run the body without a cell.  A
+// template, so that only the sources that launch it compile it.
+template <int CHECK = 1, bool TILE_SYNC = true>
+__global__ __launch_bounds__(1024, 8) void k_jacobi_x4(hr_kargs a, hr_gref gold, hr_gref gnew,
+                                                    const float* __restrict__ uo,
+                                                    float* __restrict__ un, uint32_t ny,
+                                                    uint32_t nx, uint32_t nbx, uint32_t tiles,
+                                                    const int32_t* __restrict__ seeds)
+{
+    __shared__ float tile[4][JACOBI_TILE_WORDS];
+    __shared__ uint32_t tsh[4][JACOBI_TILE_WORDS];
+    __shared__ uint32_t arrive[4];
+    using G = hr_gref_map<0, 0>;
+    const uint32_t q = threadIdx.x >> 8;
+    uint32_t lb = blockIdx.x * 4u + q, t = threadIdx.x & 255u;
+    if (lb >= tiles) {
+        lb = blockIdx.x * 4u;
+        t = UINT32_MAX;
+    }
+    if constexpr (TILE_SYNC) {
+        if constexpr (CHECK)
+            for (uint32_t i = threadIdx.x; i < 4 * JACOBI_TILE_WORDS; i += 1024)
+                tsh[i / JACOBI_TILE_WORDS][i % JACOBI_TILE_WORDS] = 0;
+        if (threadIdx.x < 4) arrive[threadIdx.x] = 0;
+        __syncthreads();
+        jacobi_body<CHECK, G, true, hr_tile_sync>(a.env, G{gold}, G{gnew}, uo, un, ny, nx, nbx,
+                                                  seeds, lb, t, tile[q], tsh[q], 0,
+                                                  hr_tile_sync{&arrive[q], 0u});
+    } else {
+        jacobi_body<CHECK, G, true>(a.env, G{gold}, G{gnew}, uo, un, ny, nx, nbx, seeds, lb, t,
+                                    tile[q], tsh[q], 0);
+    }
 }
 
 // The checked sweep on tiled shadow maps: both grids tiled by 2^TW x 2^TH

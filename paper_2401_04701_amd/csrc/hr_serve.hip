@@ -57,6 +57,25 @@ __global__ __launch_bounds__(1024, 8) void k_iter(hr_env base, const hr_inst_dev
     run_item<PATTERNS>(e, I, phase, item, smem);
 }
 
+// One phase of a stencil job of the large lane: the stencil's tuned body,
+// four tiles to a 1024-thread block (k_jacobi_x4), on the job's shadow
+// words in the arena, under the lane's environment with the phase's launch
+// epoch.
+hr_status launch_stencil_phase(const hr_env& e, const hr_inst_dev& d, uint32_t phase,
+                               hipStream_t s)
+{
+    const bool odd = phase & 1u;
+    hr_kargs a{};
+    a.env = e;
+    a.env.launch = phase & ((1u << hr::g::LAUNCH_BITS) - 1);
+    a.env.launch_seq = phase;
+    const uint32_t nbx = (d.n + 15) / 16, tiles = nbx * ((d.ny + 15) / 16);
+    HR_LAUNCH(k_jacobi_x4<1>, dim3((tiles + 3) / 4), dim3(1024), 0, s, a, odd ? d.g1 : d.g0,
+              odd ? d.g0 : d.g1, (const float*)(odd ? d.p1 : d.p0), (float*)(odd ? d.p0 : d.p1),
+              d.ny, d.n, nbx, tiles, (const int32_t*)d.p2);
+    return HR_OK;
+}
+
 using iter_kernel = void (*)(hr_env, const hr_inst_dev*, const uint32_t*, const uint64_t*,
                              uint32_t);
 
@@ -80,6 +99,7 @@ struct job_state {
     uint64_t off = 0, granules = 0;   // arena placement
     uint32_t items = 0;               // work items of one phase
     uint32_t slot = 0, phase = 0;
+    uint32_t burst = 1;               // phases its lane's iteration in flight runs
     int32_t status = 0;
     bool running = false;             // in its lane's iteration in flight
 };
@@ -140,6 +160,17 @@ hr_status serve_serial(hr_ctx c, const hr_instance* jobs, hr_serve_job* times, u
 // of its largest hub, which grows with the graph; jobs of many items) would
 // hold back the short jobs sharing their iterations.  Four lanes: as many as
 // the device's hardware queues for one process.
+//
+// The large lane runs its jobs one at a time, in admission order: a job of
+// that many items fills the device by itself, so sharing iterations among
+// several would only stretch every one of them (each would finish near the
+// end of their common span), and one job at a time keeps the blocks in
+// flight to one job's grid, leaving room for the short lanes as they
+// retire.  A stencil job there runs all its remaining phases in one
+// iteration, as back-to-back launches of the tuned stencil body (the one a
+// standalone check runs, four tiles to a 1024-thread block so that the
+// short lanes' blocks find room beside it), each phase with its own launch
+// epoch; hr_serve_config.large_burst caps the phases of one iteration.
 constexpr uint32_t N_LANES = 4;
 constexpr uint32_t LANE_SHORT = 0, LANE_GRAPH = 1, LANE_LARGE = 2, LANE_LARGE_GRAPH = 3;
 constexpr uint32_t LARGE_ITEMS = 1024;        // items per phase above which a job is large
@@ -309,33 +340,49 @@ hr_status serve_continuous(hr_ctx c, const hr_instance* jobs, hr_serve_job* time
             ++next;
         }
         // an idle lane with resident jobs starts its next iteration: the next
-        // phase of each of them
+        // phase of each of them (the large lane: of its first job)
         for (uint32_t k = 0; k < N_LANES; ++k) {
             lane_state& L = b.lane[k];
             if (L.in_flight || L.jobs.empty()) continue;
-            uint64_t total = 0;
-            uint32_t patterns = 0;
-            for (size_t q = 0; q < L.jobs.size(); ++q) {
-                const job_state& st = js[L.jobs[q]];
-                L.h_prefix[q] = total;
-                L.h_act[q] = st.slot | (st.phase << 20);
-                total += st.items;
-                patterns |= 1u << st.in.pattern;
+            const size_t n_run = k == LANE_LARGE ? 1 : L.jobs.size();
+            if (hr_fill32(L.ctr, HR_CTR_WORDS, L.s) != hipSuccess) return HR_E_HIP;
+            job_state& first = js[L.jobs[0]];
+            if (k == LANE_LARGE && first.in.pattern == HR_PAT_JACOBI) {
+                // its next phases, one launch of the stencil kernel each
+                const hr_inst_dev& d = b.h_desc[first.slot];
+                const uint32_t last = cfg.large_burst
+                                          ? std::min(first.in.phases, first.phase + cfg.large_burst)
+                                          : first.in.phases;
+                for (uint32_t p = first.phase; p < last; ++p) {
+                    const hr_status ls = launch_stencil_phase(env[k], d, p, L.s);
+                    if (ls != HR_OK) return ls;
+                }
+                first.burst = last - first.phase;
+            } else {
+                uint64_t total = 0;
+                uint32_t patterns = 0;
+                for (size_t q = 0; q < n_run; ++q) {
+                    job_state& st = js[L.jobs[q]];
+                    L.h_prefix[q] = total;
+                    L.h_act[q] = st.slot | (st.phase << 20);
+                    total += st.items;
+                    patterns |= 1u << st.in.pattern;
+                    st.burst = 1;
+                }
+                L.h_prefix[n_run] = total;
+                if (hipMemcpyAsync(L.act, L.h_act, sizeof(uint32_t) * n_run,
+                                   hipMemcpyHostToDevice, L.s) != hipSuccess ||
+                    hipMemcpyAsync(L.prefix, L.h_prefix, sizeof(uint64_t) * (n_run + 1),
+                                   hipMemcpyHostToDevice, L.s) != hipSuccess)
+                    return HR_E_HIP;
+                HR_LAUNCH(iter_for(patterns), dim3((uint32_t)total), dim3(HR_WORKER_THREADS),
+                          L.lds, L.s, env[k], b.slots, L.act, L.prefix, (uint32_t)n_run);
             }
-            L.h_prefix[L.jobs.size()] = total;
-            if (hipMemcpyAsync(L.act, L.h_act, sizeof(uint32_t) * L.jobs.size(),
-                               hipMemcpyHostToDevice, L.s) != hipSuccess ||
-                hipMemcpyAsync(L.prefix, L.h_prefix, sizeof(uint64_t) * (L.jobs.size() + 1),
-                               hipMemcpyHostToDevice, L.s) != hipSuccess ||
-                hr_fill32(L.ctr, HR_CTR_WORDS, L.s) != hipSuccess)
-                return HR_E_HIP;
-            HR_LAUNCH(iter_for(patterns), dim3((uint32_t)total), dim3(HR_WORKER_THREADS), L.lds,
-                      L.s, env[k], b.slots, L.act, L.prefix, (uint32_t)L.jobs.size());
             if (hipMemcpyAsync(L.h_ctr, L.ctr, sizeof(uint32_t) * HR_CTR_SITES,
                                hipMemcpyDeviceToHost, L.s) != hipSuccess ||
                 hipEventRecord(L.done, L.s) != hipSuccess)
                 return HR_E_HIP;
-            for (uint32_t j : L.jobs) js[j].running = true;
+            for (size_t q = 0; q < n_run; ++q) js[L.jobs[q]].running = true;
             L.in_flight = true;
         }
         // collect the lanes whose iteration has finished
@@ -359,6 +406,7 @@ hr_status serve_continuous(hr_ctx c, const hr_instance* jobs, hr_serve_job* time
             int warn = 0;
             if (flags & HR_DEVF_CLOCK) warn |= HR_W_CLOCK_OVERFLOW;
             if (flags & HR_DEVF_RANGE) warn |= HR_W_OUT_OF_RANGE;
+            if (flags & HR_DEVF_STALL) warn |= HR_W_STALLED;
             if (head > c->cfg.ring_capacity) {
                 // recover the global part of the iteration's jobs from their
                 // sticky race words
@@ -395,7 +443,8 @@ hr_status serve_continuous(hr_ctx c, const hr_instance* jobs, hr_serve_job* time
                 }
                 st.running = false;
                 st.status |= warn;
-                if (++st.phase < st.in.phases) {
+                st.phase += st.burst;
+                if (st.phase < st.in.phases) {
                     still.push_back(j);
                     continue;
                 }

@@ -127,6 +127,26 @@ def test_serving_mix_equals_alone(env, stream, budget_jobs, slots, rate):
     say("  p50 %.3f ms p99 %.3f ms" % (1e3 * np.percentile(lat, 50), 1e3 * np.percentile(lat, 99)))
 
 
+@pytest.mark.parametrize("burst", [1, 3])
+def test_serving_large_lane_bursts(env, stream, burst):
+    """The large lane runs its stencil jobs one at a time, `burst` phases per
+    iteration (the default runs all of a job's phases in one): the sets do
+    not depend on it, and the large jobs finish in admission order."""
+    torch, hr, jobs = env
+    specs, js, want = stream
+    arrivals = si.poisson_arrivals(9, len(js), 5000.0)
+    say("serve with large-lane bursts of", burst)
+    with hr.Context(ring_capacity=1 << 16) as ctx:
+        per, times = hr.serve(ctx, [j.inst for j in js], arrivals, large_burst=burst)
+    for i, (w, p) in enumerate(zip(want, per)):
+        assert p == w, (i, specs[i])
+        assert times[i].status == 0 and times[i].flagged == len(w)
+    big = [i for i, s in enumerate(specs) if s.get("big")]
+    assert len(big) >= 2
+    fin = np.array([times[i].finish_s for i in big])
+    assert np.all(np.diff(fin) > 0)
+
+
 def test_serving_serial_replay(env, stream):
     torch, hr, jobs = env
     specs, js, want = stream
