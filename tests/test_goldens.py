@@ -60,3 +60,29 @@ def test_streamed_oracle_equals_whole_log_oracle():
                                                     n_workers=2)
     assert keys == whole and len(whole) > 10
     assert checks == oracle.model_labelprop(rp, col, mask, 2, 64).shape[0]
+
+
+def _closed_form(spec, a):
+    p = spec["pattern"]
+    if p == si.PAT_REDUCE:
+        return cf.reduce_n_flagged(spec["n"], spec["threads"], spec["blocks"], spec["drop"])
+    if p == si.PAT_JACOBI:
+        return cf.jacobi_flagged(spec["ny"], spec["nx"], spec["phases"], a["seeds"])
+    return cf.labelprop_flagged(a["row_ptr"], a["col"], a["mask"])
+
+
+def test_batched_and_serving_goldens_match_closed_forms():
+    """Every job's oracle set in the batched-manifest and serving-stream
+    goldens (whole jobs, the full-size stencils streamed) equals what the
+    job's workload definition fixes in closed form."""
+    for name, specs in (("batched_manifest_1000.json", si.batched_manifest(si.master_seed(3))),
+                        ("serving_stream_40.json", goldens.serving_test_stream())):
+        g = load(name)["jobs"]
+        assert [e["index"] for e in g] == [s["index"] for s in specs]
+        flagged = 0
+        for e, s in zip(g, specs):
+            want = _closed_form(s, si.instance_inputs(s))
+            assert (e["pattern"], e["flagged"], e["sha256"]) == \
+                (s["pattern"], len(want), goldens.key_digest(want)), (name, s["index"])
+            flagged += len(want)
+        assert flagged > 0

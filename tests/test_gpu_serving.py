@@ -6,11 +6,16 @@ with full-size 4096 x 4096 stencil jobs."""
 import numpy as np
 import pytest
 
+import json
+import os
+
 import oracle
 import synth_inputs as si
 from oracle import closed_forms as cf
+from oracle.goldens import key_digest, serving_test_stream
 
 pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
 @pytest.fixture(scope="module")
@@ -80,13 +85,18 @@ def items_of(spec):
 @pytest.fixture(scope="module")
 def stream(env):
     torch, hr, jobs = env
-    specs = si.serving_stream(si.master_seed(4), n_jobs=40, max_blocks=12, max_threads=512,
-                              max_lds_kib=8.0, seeded_frac=0.5, jacobi_phases=4,
-                              labelprop_phases=3)
+    specs = serving_test_stream()
     say("stream of", len(specs), "jobs,", sum(bool(s.get("big")) for s in specs), "full-size")
     arrays = [si.instance_inputs(s) for s in specs]
     want = [expected(s, a, use_oracle=True) for s, a in zip(specs, arrays)]
     assert sum(bool(w) for w in want) >= 8
+    # every job's expected set is the oracle's on the whole job, the
+    # full-size stencils included (streamed by oracle/goldens.py)
+    with open(os.path.join(GOLDEN, "serving_stream_40.json")) as f:
+        golden = json.load(f)["jobs"]
+    assert [g["index"] for g in golden] == [s["index"] for s in specs]
+    for i, (g, w) in enumerate(zip(golden, want)):
+        assert (len(w), key_digest(w)) == (g["flagged"], g["sha256"]), (i, specs[i])
     js = [jobs.Job(s, a) for s, a in zip(specs, arrays)]
     return specs, js, want
 

@@ -5,11 +5,21 @@ executor variants change the schedule, never the result."""
 import numpy as np
 import pytest
 
+import json
+import os
+
 import oracle
 import synth_inputs as si
 from oracle import closed_forms as cf
+from oracle.goldens import key_digest
 
 pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def load_golden(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
 
 
 @pytest.fixture(scope="module")
@@ -113,10 +123,13 @@ def test_batch_small_matches_serial_and_oracle(env):
 
 def test_batch_full_manifest(env):
     """The 1000-job manifest (blocks 1-512, threads 64-1024, LDS 1-64 KiB,
-    10 % seeded) in one persistent launch against the closed forms, and a
-    sample of jobs against the serial path."""
+    10 % seeded) in one persistent launch against the oracle's sets of the
+    whole jobs (tests/golden/batched_manifest_1000.json) and the closed
+    forms, and a sample of jobs against the serial path."""
     torch, hr, jobs = env
     specs = si.batched_manifest(si.master_seed(3))
+    golden = load_golden("batched_manifest_1000.json")["jobs"]
+    assert [g["index"] for g in golden] == [s["index"] for s in specs]
     say("building 1000 job inputs")
     arrays = [si.instance_inputs(s) for s in specs]
     want = [expected(s, a, use_oracle=False) for s, a in zip(specs, arrays)]
@@ -134,6 +147,10 @@ def test_batch_full_manifest(env):
                 assert ctx.status == 0
                 for i, (w, p) in enumerate(zip(want, per)):
                     assert p == w, (i, specs[i], tile)
+                # every job's set against the oracle's, run on the whole
+                # job by oracle/goldens.py
+                for i, (g, p) in enumerate(zip(golden, per)):
+                    assert (len(p), key_digest(p)) == (g["flagged"], g["sha256"]), (i, tile)
     rng = np.random.default_rng(1)
     for i in rng.choice(len(js), 12, replace=False):
         got, st = js[int(i)].serial(ring_capacity=1 << 20)
