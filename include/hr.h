@@ -158,6 +158,15 @@ typedef struct {
  * other workloads, the batched and serving executors and hr_job_run_static
  * reject such a context.  Not with HR_CFG_WORD4 or HR_CFG_WAVE_GROUPING. */
 #define HR_CFG_NESTED_TILES 16u
+/* Global-word transitions read from the flat table of the state machine
+ * (the paper's encoding, Sec. IV-B: an array indexed by the old state and
+ * the transition labels) instead of computed by bit logic; the same machine
+ * and the same results, at another cost, for the autotuner to time.  The
+ * context holds the table (32 KiB) in device memory.  The stencil's checked
+ * kernel (row-major maps) and the access-program interpreter honour it; the
+ * other workloads, the executors and hr_job_run_static reject such a
+ * context.  Not with HR_CFG_WORD4, HR_CFG_NESTED_TILES or HR_CFG_ACCESS_LOG. */
+#define HR_CFG_FSM_TABLE 32u
 
 /* One flagged location, 48 bytes.  The key is (space, region, block if LDS,
  * index).  The other fields describe how the race was found: `before` and
@@ -362,6 +371,14 @@ hr_status hr_access_log(hr_ctx c, hr_access_rec* out, size_t cap, size_t* n_out,
 hr_status hr_fsm_step(uint32_t space, uint64_t old, uint32_t kind, uint32_t launch,
                       uint32_t block, uint32_t thread, uint32_t bc, uint32_t wc,
                       uint32_t wave_bits, uint64_t* new_out);
+
+/* The same transition of a global word through the flat table that a
+ * context made with HR_CFG_FSM_TABLE uses (for verification: it must equal
+ * hr_fsm_step on every input).  Arguments as hr_fsm_step, global words only
+ * (space must be HR_GLOBAL). */
+hr_status hr_fsm_step_table(uint32_t space, uint64_t old, uint32_t kind, uint32_t launch,
+                            uint32_t block, uint32_t thread, uint32_t bc, uint32_t wc,
+                            uint32_t wave_bits, uint64_t* new_out);
 
 /* Host evaluation of the device merge of two global shadow words (the summary
  * of the union of their access sets; x of the current launch), used when an

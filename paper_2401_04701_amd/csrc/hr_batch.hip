@@ -218,7 +218,7 @@ extern "C" hr_status hr_batch_create(hr_ctx c, hr_instance* inst, uint32_t n_ins
 {
     if (!c || !inst || !out || n_inst == 0 || n_inst >= (1u << 24)) return HR_E_INVAL;
     *out = nullptr;
-    if (c->cfg.flags & (HR_CFG_WORD4 | HR_CFG_NESTED_TILES))
+    if (c->cfg.flags & (HR_CFG_WORD4 | HR_CFG_NESTED_TILES | HR_CFG_FSM_TABLE))
         return HR_E_INVAL;   // the arena holds flat 8-byte words
     std::vector<size_t> el(2 * (size_t)n_inst), words(2 * (size_t)n_inst);
     size_t total = 0, lds = 0;

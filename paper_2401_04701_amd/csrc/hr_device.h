@@ -428,10 +428,22 @@ __device__ __forceinline__ void hr_settle(const hr_env& e, const hr_thread& t, u
     }
 }
 
-template <int KIND, bool GROUP = false, bool PRE = false, bool LOG = false>
+// The transition of a global word: the bit logic of hr::g::step, or with
+// TABLE the same machine read from its flat table `tab` (hr::g::step_tab;
+// a context made with HR_CFG_FSM_TABLE holds the table in device memory).
+template <bool TABLE>
+__device__ __forceinline__ uint64_t hr_step8(const uint16_t* tab, uint64_t old, uint64_t id,
+                                             uint32_t k, uint64_t wm)
+{
+    if constexpr (TABLE) return hr::g::step_tab(tab, old, id, k, wm);
+    else return hr::g::step(old, id, k, wm);
+}
+
+template <int KIND, bool GROUP = false, bool PRE = false, bool LOG = false, bool TABLE = false>
 __device__ __forceinline__ void hr_check(const hr_env& e, const hr_thread& t, uint64_t* shadow,
                                          uint64_t n, uint32_t region, uint64_t index,
-                                         uint64_t off, uint32_t site = 0, uint64_t pre = 0)
+                                         uint64_t off, uint32_t site = 0, uint64_t pre = 0,
+                                         const uint16_t* tab = nullptr)
 {
     if (t.enabled != 1 || !shadow) return;      // thread switched off / region not monitored
     hr_count<LOG>(e, t, 0, region, index, KIND, site);
@@ -450,11 +462,11 @@ __device__ __forceinline__ void hr_check(const hr_env& e, const hr_thread& t, ui
     }
     const uint64_t old =
         PRE ? pre : __hip_atomic_load(sp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    uint64_t nw = hr::g::step(old, t.gid, k, wm);
+    uint64_t nw = hr_step8<TABLE>(tab, old, t.gid, k, wm);
     uint64_t other_id = 0;
     if (other != HR_NO_LANE) {
         other_id = hr::g::pack_id(e.launch, t.block, t.thread - __lane_id() + other, t.bc, t.wc);
-        nw = hr::g::step(nw, other_id, k, wm);
+        nw = hr_step8<TABLE>(tab, nw, other_id, k, wm);
     }
     if (nw == old) return;
     const uint64_t r = __hip_atomic_exchange(sp, nw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -471,11 +483,11 @@ struct hr_pend {
     uint64_t old, nw, r;
 };
 
-template <int KIND, bool PRE = false, bool LOG = false>
+template <int KIND, bool PRE = false, bool LOG = false, bool TABLE = false>
 __device__ __forceinline__ hr_pend hr_check_issue(const hr_env& e, const hr_thread& t,
                                                   uint64_t* shadow, uint64_t n, uint32_t region,
                                                   uint64_t index, uint64_t off, uint32_t site,
-                                                  uint64_t pre = 0)
+                                                  uint64_t pre = 0, const uint16_t* tab = nullptr)
 {
     hr_pend p{nullptr, 0, 0, 0};
     if (t.enabled != 1 || !shadow) return p;
@@ -488,7 +500,7 @@ __device__ __forceinline__ hr_pend hr_check_issue(const hr_env& e, const hr_thre
     uint64_t* sp = shadow + off;
     const uint64_t old =
         PRE ? pre : __hip_atomic_load(sp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const uint64_t nw = hr::g::step(old, t.gid, k, hr::g::group_mask(e.wave_bits));
+    const uint64_t nw = hr_step8<TABLE>(tab, old, t.gid, k, hr::g::group_mask(e.wave_bits));
     if (nw == old) return p;
     p.sp = sp;
     p.old = old;
@@ -790,10 +802,11 @@ __device__ __forceinline__ void hr_lds_rrw(const hr_env& e, const hr_thread& t, 
 }
 
 // Runtime-kind forms (used where the kind is data, as in the interpreter).
-template <bool LOG = false>
+template <bool LOG = false, bool TABLE = false>
 __device__ __forceinline__ void hr_check_k(const hr_env& e, const hr_thread& t, uint32_t kind,
                                            uint64_t* shadow, uint64_t n, uint32_t region,
-                                           uint64_t index, uint64_t off, uint32_t site = 0)
+                                           uint64_t index, uint64_t off, uint32_t site = 0,
+                                           const uint16_t* tab = nullptr)
 {
     if (e.word4) {
         uint32_t* s4 = (uint32_t*)shadow;
@@ -802,9 +815,12 @@ __device__ __forceinline__ void hr_check_k(const hr_env& e, const hr_thread& t, 
         else hr_check4<2, true, false, 0, LOG>(e, t, s4, n, region, index, off, site);
         return;
     }
-    if (kind == 0) hr_check<0, true, false, LOG>(e, t, shadow, n, region, index, off, site);
-    else if (kind == 1) hr_check<1, true, false, LOG>(e, t, shadow, n, region, index, off, site);
-    else hr_check<2, true, false, LOG>(e, t, shadow, n, region, index, off, site);
+    if (kind == 0)
+        hr_check<0, true, false, LOG, TABLE>(e, t, shadow, n, region, index, off, site, 0, tab);
+    else if (kind == 1)
+        hr_check<1, true, false, LOG, TABLE>(e, t, shadow, n, region, index, off, site, 0, tab);
+    else
+        hr_check<2, true, false, LOG, TABLE>(e, t, shadow, n, region, index, off, site, 0, tab);
 }
 
 template <bool LOG = false>

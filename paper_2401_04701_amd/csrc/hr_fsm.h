@@ -50,8 +50,11 @@ enum : uint32_t { CL_R = 1u, CL_A = 2u, CL_X = 3u };
 enum : uint32_t { T_INIT = 0u, T_RACE = 1u, T_MB = 2u, T_MW = 3u, T_MT = 4u, T_ST = 5u };
 
 // Access kinds of the C ABI (plain read, plain write, atomic) -> class.
-HR_HD uint32_t kind_class(uint32_t kind) { return kind == 0u ? CL_R : (kind == 2u ? CL_A : CL_X); }
-HR_HD bool conflicts(uint32_t cls, uint32_t k) { return (cls | k) == CL_X; }
+HR_HD constexpr uint32_t kind_class(uint32_t kind)
+{
+    return kind == 0u ? CL_R : (kind == 2u ? CL_A : CL_X);
+}
+HR_HD constexpr bool conflicts(uint32_t cls, uint32_t k) { return (cls | k) == CL_X; }
 
 // ---------------------------------------------------------------------------
 // Global-memory shadow word, 64 bits, least significant first:
@@ -75,21 +78,25 @@ constexpr uint64_t WAVE_M = 15ull << (TH_SH + 6);     // wave within the block
 
 // Mask of the thread bits naming the synchronization group: the wave (s =
 // 6) or a tile of 2^s lanes.
-HR_HD uint64_t group_mask(uint32_t s) { return (uint64_t)((1023u >> s) << s) << TH_SH; }
+HR_HD constexpr uint64_t group_mask(uint32_t s)
+{
+    return (uint64_t)((1023u >> s) << s) << TH_SH;
+}
 constexpr uint64_t BL_M = ((1ull << 22) - 1) << BL_SH;
 constexpr uint64_t LA_M = 511ull << LA_SH;
 constexpr uint32_t BLOCK_LIMIT = 1u << 22;
 constexpr uint32_t LAUNCH_BITS = 9;
 
 // Identity fields of the accessing thread, packed in place.
-HR_HD uint64_t pack_id(uint32_t launch, uint32_t block, uint32_t thread, uint32_t bc, uint32_t wc)
+HR_HD constexpr uint64_t pack_id(uint32_t launch, uint32_t block, uint32_t thread, uint32_t bc,
+                                 uint32_t wc)
 {
     return ((uint64_t)(launch & 511u) << LA_SH) | ((uint64_t)(block & (BLOCK_LIMIT - 1)) << BL_SH) |
            ((uint64_t)(thread & 1023u) << TH_SH) | ((uint64_t)(bc & 255u) << BC_SH) |
            ((uint64_t)(wc & 63u) << WC_SH);
 }
 
-HR_HD uint64_t mk(uint32_t tag, uint32_t cl, uint32_t cb, uint32_t cw)
+HR_HD constexpr uint64_t mk(uint32_t tag, uint32_t cl, uint32_t cb, uint32_t cw)
 {
     return ((uint64_t)tag << TAG_SH) | ((uint64_t)cl << CL_SH) | ((uint64_t)cb << CB_SH) |
            ((uint64_t)cw << CW_SH);
@@ -97,7 +104,7 @@ HR_HD uint64_t mk(uint32_t tag, uint32_t cl, uint32_t cb, uint32_t cw)
 
 // One transition: old shadow word, identity of the access, class k of the
 // access, mask of the group bits of the thread index.
-HR_HD uint64_t step(uint64_t old, uint64_t id, uint32_t k, uint64_t wm = WAVE_M)
+HR_HD constexpr uint64_t step(uint64_t old, uint64_t id, uint32_t k, uint64_t wm = WAVE_M)
 {
     const uint32_t tag = (uint32_t)(old & TAG_M);
     if (tag == T_RACE) return old;
@@ -130,6 +137,124 @@ HR_HD uint64_t step(uint64_t old, uint64_t id, uint32_t k, uint64_t wm = WAVE_M)
     if (d & lm) return conflicts(cw, k) ? race : (mk(T_MT, cl, cb, k) | (id & keep_w));
     // Same thread.
     return mk(T_ST, cl | k, cb | k, cw | k) | (id & keep_t);
+}
+
+// ---------------------------------------------------------------------------
+// The same transition as a flat table (the paper's encoding of its machine,
+// Sec. IV-B: an array indexed by the old state and the transition labels).
+// The labels are the relation of the access to the stored history -- 0 new
+// launch (or an initial word), 1 other block, 2 later block epoch, 3 other
+// wave, 4 later wave epoch, 5 other thread, 6 same thread, decided from the
+// XOR of the two words in that order -- and the access class.  The index
+// concatenates the old tag (3 bits), the relation (3 bits), the old word's
+// class fields cW, cB, cL (its bits 3..8) and the access class; the entry
+// is the new word's low 9 bits (tag and classes), or TAB_SAME for an
+// unchanged word.  The identity fields the new state keeps come from the
+// access (ST: thread; MT: group; MW: block; MB: launch; RACE: none).  The
+// table is built at compile time from step() itself, so both encodings are
+// one machine; which one runs faster is a matter of measurement.
+// ---------------------------------------------------------------------------
+constexpr uint32_t TAB_SIZE = 64u << 8;   // every 3-bit tag (words of other tags are
+                                          // not made by the machine, but any word reads
+                                          // an entry inside the table)
+constexpr uint16_t TAB_SAME = 0x8000u;
+
+struct step_table {
+    uint16_t e[TAB_SIZE];
+};
+
+HR_HD constexpr uint32_t relation(uint64_t old, uint64_t id, uint64_t wm)
+{
+    const uint64_t d = old ^ id;
+    const uint32_t tag = (uint32_t)(old & TAG_M);
+    return (tag == T_INIT || (d & LA_M)) ? 0u
+           : (d & BL_M)                  ? 1u
+           : (d & BC_M)                  ? 2u
+           : (d & wm)                    ? 3u
+           : (d & WC_M)                  ? 4u
+           : (d & (TH_M & ~wm))          ? 5u
+                                         : 6u;
+}
+
+HR_HD constexpr uint32_t tab_index(uint64_t old, uint32_t rel, uint32_t k)
+{
+    return ((((uint32_t)(old & TAG_M) << 3) | rel) << 8) | ((uint32_t)(old >> CW_SH) & 63u) << 2 | k;
+}
+
+// Identity fields a word of tag `tag` keeps.
+HR_HD constexpr uint64_t keep_of(uint32_t tag, uint64_t wm)
+{
+    return tag == T_ST   ? (LA_M | BL_M | BC_M | TH_M | WC_M)
+           : tag == T_MT ? (LA_M | BL_M | BC_M | wm | WC_M)
+           : tag == T_MW ? (LA_M | BL_M | BC_M)
+           : tag == T_MB ? LA_M
+                         : 0ull;
+}
+
+// A stored word and an access in relation `rel` to it: identity fields that
+// differ from the word's in exactly the field the relation names.
+HR_HD constexpr uint64_t rel_id(uint32_t rel)
+{
+    return rel == 0u   ? pack_id(2, 5, 67, 3, 2)
+           : rel == 1u ? pack_id(1, 6, 67, 3, 2)
+           : rel == 2u ? pack_id(1, 5, 67, 4, 2)
+           : rel == 3u ? pack_id(1, 5, 131, 3, 2)
+           : rel == 4u ? pack_id(1, 5, 67, 3, 3)
+           : rel == 5u ? pack_id(1, 5, 68, 3, 2)
+                       : pack_id(1, 5, 67, 3, 2);
+}
+
+constexpr step_table make_step_table()
+{
+    step_table t{};
+    for (uint32_t tag = 0; tag < 8; ++tag)
+        for (uint32_t rel = 0; rel < 8; ++rel)
+            for (uint32_t c = 0; c < 64; ++c)
+                for (uint32_t k = 0; k < 4; ++k) {
+                    const uint32_t i = (((tag << 3) | rel) << 8) | (c << 2) | k;
+                    if (rel > 6 || k == 0) {
+                        t.e[i] = TAB_SAME;
+                        continue;
+                    }
+                    const uint64_t old = (uint64_t)tag | ((uint64_t)c << CW_SH) |
+                                         (tag == T_INIT ? 0ull : pack_id(1, 5, 67, 3, 2));
+                    const uint64_t nw = step(old, rel_id(rel), k, WAVE_M);
+                    t.e[i] = nw == old ? TAB_SAME : (uint16_t)(nw & 511u);
+                }
+    return t;
+}
+
+// On the representatives the table was built from, table entry plus kept
+// identity fields rebuild step()'s word (checked at compile time where the
+// device table is defined).
+constexpr bool step_table_consistent()
+{
+    const step_table t = make_step_table();
+    for (uint32_t tag = 0; tag < 8; ++tag)
+        for (uint32_t rel = 0; rel < 7; ++rel)
+            for (uint32_t c = 0; c < 64; ++c)
+                for (uint32_t k = 1; k < 4; ++k) {
+                    const uint64_t old = (uint64_t)tag | ((uint64_t)c << CW_SH) |
+                                         (tag == T_INIT ? 0ull : pack_id(1, 5, 67, 3, 2));
+                    const uint64_t id = rel_id(rel);
+                    if (relation(old, id, WAVE_M) != rel && tag != T_INIT) return false;
+                    const uint64_t nw = step(old, id, k, WAVE_M);
+                    const uint16_t e = t.e[tab_index(old, relation(old, id, WAVE_M), k)];
+                    const uint64_t got =
+                        e == TAB_SAME ? old : ((uint64_t)e | (id & keep_of(e & 7u, WAVE_M)));
+                    if (got != nw) return false;
+                }
+    return true;
+}
+
+// One transition through the table `tab` (make_step_table()).
+HR_HD uint64_t step_tab(const uint16_t* tab, uint64_t old, uint64_t id, uint32_t k,
+                        uint64_t wm = WAVE_M)
+{
+    if ((old & TAG_M) == T_RACE) return old;
+    const uint16_t e = tab[tab_index(old, relation(old, id, wm), k)];
+    if (e == TAB_SAME) return old;
+    return (uint64_t)e | (id & keep_of(e & 7u, wm));
 }
 
 // Summary of the union of the access sets summarised by x and y, where x

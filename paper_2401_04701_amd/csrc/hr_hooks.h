@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "hr_device.h"
 
 // An element of a global region as a hook takes it: its index (checked
@@ -27,12 +29,26 @@ struct hr_gref {
     hr_lay lay;
     using word = uint64_t;
     using pend = hr_pend;
+    static constexpr bool TABLE = false;   // transitions by the bit logic
+    __device__ __forceinline__ const uint16_t* table() const { return nullptr; }
     __device__ __forceinline__ hr_el at(uint64_t index) const { return {index, hr_lay_off(lay, index)}; }
     __device__ __forceinline__ hr_el at2(uint32_t r, uint32_t c, uint64_t index) const
     {
         return {index, hr_lay_off2(lay, r, c)};
     }
 };
+
+// An 8-byte-word region whose hooks take their transitions from the flat
+// table of the machine (hr::g::step_tab) at `tab`.
+struct hr_gref_tab : hr_gref {
+    const uint16_t* tab;
+    static constexpr bool TABLE = true;
+    __device__ __forceinline__ const uint16_t* table() const { return tab; }
+};
+
+// Overloads for the 8-byte-word region types (hr_gref and types built on it).
+template <class G>
+using hr_if8 = std::enable_if_t<std::is_base_of<hr_gref, G>::value, int>;
 
 // LAY: the 4-byte word layout as a compile-time constant (0: the context's).
 template <uint32_t LAY>
@@ -60,42 +76,46 @@ __host__ __device__ __forceinline__ hr_lay hr_lay_rows(uint32_t cols)
 // Global hook at a lane-affine site (GROUP false) or a data-dependent one.
 // Every global wrapper takes the element as an hr_el, or as an index (then
 // the region's map gives the shadow offset).
-template <int KIND, int CHECK, bool GROUP = false>
-__device__ __forceinline__ void hr_g(const hr_env& e, const hr_thread& t, const hr_gref& g,
-                                     hr_el x, uint32_t site)
+template <int KIND, int CHECK, bool GROUP = false, class G, hr_if8<G> = 0>
+__device__ __forceinline__ void hr_g(const hr_env& e, const hr_thread& t, const G& g, hr_el x,
+                                     uint32_t site)
 {
-    if constexpr (CHECK) hr_check<KIND, GROUP, false, CHECK == 2>(e, t, g.shadow, g.n, g.id, x.index, x.off, site);
+    if constexpr (CHECK)
+        hr_check<KIND, GROUP, false, CHECK == 2, G::TABLE>(e, t, g.shadow, g.n, g.id, x.index,
+                                                           x.off, site, 0, g.table());
 }
 
 // Global hook on a word loaded earlier by hr_gload.
-template <int CHECK>
-__device__ __forceinline__ uint64_t hr_gload(const hr_thread& t, const hr_gref& g, hr_el x)
+template <int CHECK, class G, hr_if8<G> = 0>
+__device__ __forceinline__ uint64_t hr_gload(const hr_thread& t, const G& g, hr_el x)
 {
     if constexpr (CHECK) return hr_check_load(t, g.shadow, g.n, x.index, x.off);
     return 0;
 }
 
-template <int KIND, int CHECK, bool GROUP = true>
-__device__ __forceinline__ void hr_gpre(const hr_env& e, const hr_thread& t, const hr_gref& g,
-                                        hr_el x, uint32_t site, uint64_t pre)
+template <int KIND, int CHECK, bool GROUP = true, class G, hr_if8<G> = 0>
+__device__ __forceinline__ void hr_gpre(const hr_env& e, const hr_thread& t, const G& g, hr_el x,
+                                        uint32_t site, uint64_t pre)
 {
     if constexpr (CHECK)
-        hr_check<KIND, GROUP, true, CHECK == 2>(e, t, g.shadow, g.n, g.id, x.index, x.off, site, pre);
+        hr_check<KIND, GROUP, true, CHECK == 2, G::TABLE>(e, t, g.shadow, g.n, g.id, x.index,
+                                                          x.off, site, pre, g.table());
 }
 
 // The two halves of a global hook at a lane-affine site (hr_check_issue /
 // hr_check_settle; both take the call site); `pre` as for hr_gpre when PRE.
-template <int KIND, int CHECK, bool PRE = false>
-__device__ __forceinline__ hr_pend hr_gi(const hr_env& e, const hr_thread& t, const hr_gref& g,
-                                         hr_el x, uint32_t site, uint64_t pre = 0)
+template <int KIND, int CHECK, bool PRE = false, class G, hr_if8<G> = 0>
+__device__ __forceinline__ hr_pend hr_gi(const hr_env& e, const hr_thread& t, const G& g, hr_el x,
+                                         uint32_t site, uint64_t pre = 0)
 {
     if constexpr (CHECK)
-        return hr_check_issue<KIND, PRE, CHECK == 2>(e, t, g.shadow, g.n, g.id, x.index, x.off, site, pre);
+        return hr_check_issue<KIND, PRE, CHECK == 2, G::TABLE>(e, t, g.shadow, g.n, g.id, x.index,
+                                                               x.off, site, pre, g.table());
     return hr_pend{nullptr, 0, 0, 0};
 }
 
-template <int KIND, int CHECK>
-__device__ __forceinline__ void hr_gs(const hr_env& e, const hr_thread& t, const hr_gref& g,
+template <int KIND, int CHECK, class G, hr_if8<G> = 0>
+__device__ __forceinline__ void hr_gs(const hr_env& e, const hr_thread& t, const G& g,
                                       const hr_pend& p, uint64_t index, uint32_t site)
 {
     if constexpr (CHECK) hr_check_settle<KIND>(e, t, p, g.id, index, site);

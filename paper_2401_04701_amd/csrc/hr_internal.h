@@ -40,6 +40,7 @@ struct hr_ctx_s {
     uint32_t* ctr;
     unsigned long long* count;       // HR_COUNT_SLOTS debug counters
     hr_access_rec* log;              // access log (HR_CFG_ACCESS_LOG), or null
+    uint16_t* fsm_tab;               // flat transition table (HR_CFG_FSM_TABLE), or null
     uint32_t launch_seq;             // launches since the job started
     uint64_t shadow_bytes;           // live shadow memory
     std::vector<hr_race> carried;    // global races recovered before a shadow clear

@@ -291,6 +291,25 @@ __global__ __launch_bounds__(1024, 8) void k_jacobi_x4(hr_kargs a, hr_gref gold,
     }
 }
 
+// The checked sweep of k_jacobi with every global transition read from the
+// flat table of the machine at `tab` (a context made with
+// HR_CFG_FSM_TABLE; row-major maps).  A template, so that only the sources
+// that launch it compile it.
+template <int CHECK = 1>
+__global__ __launch_bounds__(256, 8) void k_jacobi_tab(hr_kargs a, hr_gref gold, hr_gref gnew,
+                                                    const float* __restrict__ uo,
+                                                    float* __restrict__ un, uint32_t ny,
+                                                    uint32_t nx, const int32_t* __restrict__ seeds,
+                                                    const uint16_t* __restrict__ tab)
+{
+    __shared__ float tile[JACOBI_TILE_WORDS];
+    __shared__ uint32_t tsh[CHECK ? JACOBI_TILE_WORDS : 1];
+    using G = hr_map<hr_gref_tab, 0, 0>;
+    jacobi_body<CHECK, G, true>(a.env, G{hr_gref_tab{gold, tab}}, G{hr_gref_tab{gnew, tab}}, uo,
+                                un, ny, nx, gridDim.x, seeds, blockIdx.y * gridDim.x + blockIdx.x,
+                                threadIdx.x, tile, tsh, 0);
+}
+
 // The checked sweep on tiled shadow maps: both grids tiled by 2^TW x 2^TH
 // (constant shifts), or TW < 0: each grid's own map, read at run time.
 // CHECK 2: with the debug access log (any map; row-major maps run here too).

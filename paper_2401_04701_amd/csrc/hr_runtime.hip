@@ -236,6 +236,11 @@ void hr_free_alloc(hr_ctx c, uint32_t alloc)
         if (r.alloc == alloc) r.live = false;
 }
 
+// The flat transition table of the global-word machine, built at compile
+// time from its bit logic (hr::g::make_step_table).
+static constexpr hr::g::step_table FSM_TABLE = hr::g::make_step_table();
+static_assert(hr::g::step_table_consistent(), "the flat table must rebuild hr::g::step");
+
 bool hr_config_normalize(const hr_config* cfg, hr_config* out)
 {
     hr_config k = {};
@@ -258,7 +263,10 @@ bool hr_config_normalize(const hr_config* cfg, hr_config* out)
     if (k.bc_bits > 8 || k.wc_bits > 6 || k.ring_capacity > (1u << 26)) return false;
     if (k.thread_bits > 10 || (!word4 && k.thread_bits != 10)) return false;
     if (k.flags & ~(HR_CFG_COUNT_CHECKS | HR_CFG_WAVE_GROUPING | HR_CFG_WORD4 |
-                    HR_CFG_ACCESS_LOG | HR_CFG_NESTED_TILES))
+                    HR_CFG_ACCESS_LOG | HR_CFG_NESTED_TILES | HR_CFG_FSM_TABLE))
+        return false;
+    if ((k.flags & HR_CFG_FSM_TABLE) &&
+        (k.flags & (HR_CFG_WORD4 | HR_CFG_NESTED_TILES | HR_CFG_ACCESS_LOG)))
         return false;
     if (k.flags & HR_CFG_ACCESS_LOG) {
         if (k.log_capacity == 0) k.log_capacity = 1u << 20;
@@ -296,9 +304,15 @@ extern "C" hr_status hr_ctx_create(hr_ctx* out, const hr_config* cfg, void* stre
         hipMalloc(&c->ctr, sizeof(uint32_t) * HR_CTR_WORDS) != hipSuccess ||
         hipMalloc(&c->count, sizeof(unsigned long long) * HR_COUNT_SLOTS) != hipSuccess ||
         ((k.flags & HR_CFG_ACCESS_LOG) &&
-         hipMalloc(&c->log, sizeof(hr_access_rec) * (size_t)k.log_capacity) != hipSuccess)) {
+         hipMalloc(&c->log, sizeof(hr_access_rec) * (size_t)k.log_capacity) != hipSuccess) ||
+        ((k.flags & HR_CFG_FSM_TABLE) && hipMalloc(&c->fsm_tab, sizeof(FSM_TABLE)) != hipSuccess)) {
         hr_ctx_destroy(c);
         return HR_E_NOMEM;
+    }
+    if (c->fsm_tab && hipMemcpy(c->fsm_tab, FSM_TABLE.e, sizeof(FSM_TABLE),
+                                hipMemcpyHostToDevice) != hipSuccess) {
+        hr_ctx_destroy(c);
+        return HR_E_HIP;
     }
     if (hr_fill32(c->ctr, HR_CTR_WORDS, c->stream) != hipSuccess ||
         hr_fill64((uint64_t*)c->count, HR_COUNT_SLOTS, c->stream) != hipSuccess) {
@@ -319,6 +333,7 @@ extern "C" hr_status hr_ctx_destroy(hr_ctx c)
     if (c->ctr) (void)hipFree(c->ctr);
     if (c->count) (void)hipFree(c->count);
     if (c->log) (void)hipFree(c->log);
+    if (c->fsm_tab) (void)hipFree(c->fsm_tab);
     delete c;
     return e == hipSuccess ? HR_OK : HR_E_HIP;
 }
@@ -560,6 +575,18 @@ extern "C" hr_status hr_fsm_step(uint32_t space, uint64_t old, uint32_t kind, ui
         *new_out = hr::l::step((uint32_t)old, hr::l::pack_id(thread, bc, wc), k,
                                hr::l::group_mask(wave_bits));
     }
+    return HR_OK;
+}
+
+extern "C" hr_status hr_fsm_step_table(uint32_t space, uint64_t old, uint32_t kind,
+                                       uint32_t launch, uint32_t block, uint32_t thread,
+                                       uint32_t bc, uint32_t wc, uint32_t wave_bits,
+                                       uint64_t* new_out)
+{
+    if (!new_out || kind > 2 || space != HR_GLOBAL || thread > 1023) return HR_E_INVAL;
+    if (wave_bits < 1 || wave_bits > 6 || block >= hr::g::BLOCK_LIMIT) return HR_E_INVAL;
+    *new_out = hr::g::step_tab(FSM_TABLE.e, old, hr::g::pack_id(launch, block, thread, bc, wc),
+                               hr::kind_class(kind), hr::g::group_mask(wave_bits));
     return HR_OK;
 }
 

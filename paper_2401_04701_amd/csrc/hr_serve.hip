@@ -495,7 +495,7 @@ extern "C" hr_status hr_serve(hr_ctx c, const hr_instance* jobs, hr_serve_job* t
                               size_t cap, size_t* n_out, void* stream)
 {
     if (!c || !jobs || !times || !n_out || n_jobs == 0 || n_jobs >= (1u << 30)) return HR_E_INVAL;
-    if (c->cfg.flags & (HR_CFG_WORD4 | HR_CFG_NESTED_TILES))
+    if (c->cfg.flags & (HR_CFG_WORD4 | HR_CFG_NESTED_TILES | HR_CFG_FSM_TABLE))
         return HR_E_INVAL;   // the arenas hold flat 8-byte words
     hr_serve_config cfg = {};
     if (cfg_in) cfg = *cfg_in;

@@ -63,7 +63,8 @@ extern "C" hr_status hr_job_run_static(const hr_instance* inst, const hr_config*
     size_t el[2] = {0, 0}, lds = 0;
     if (!hr_instance_shape(in, el, &lds)) return HR_E_INVAL;
     hr_config k;
-    if (!hr_config_normalize(cfg, &k) || (k.flags & (HR_CFG_WORD4 | HR_CFG_NESTED_TILES)))
+    if (!hr_config_normalize(cfg, &k) ||
+        (k.flags & (HR_CFG_WORD4 | HR_CFG_NESTED_TILES | HR_CFG_FSM_TABLE)))
         return HR_E_INVAL;
     k.ring_capacity = std::min<uint32_t>(k.ring_capacity, HR_STATIC_RING_RECORDS);
     if (el[0] + el[1] > HR_STATIC_SHADOW_WORDS) return HR_E_NOMEM;

@@ -108,7 +108,8 @@ struct prog_map {
     uint32_t r[8];
 };
 
-template <bool LOG = false>
+// TABLE: global transitions from the flat table at tab (HR_CFG_FSM_TABLE).
+template <bool LOG = false, bool TABLE = false>
 __global__ __launch_bounds__(1024) void k_program(hr_kargs a, prog_map pm, uint32_t blocks,
                                                   uint32_t threads, uint32_t phases,
                                                   const uint8_t* __restrict__ scope,
@@ -116,7 +117,7 @@ __global__ __launch_bounds__(1024) void k_program(hr_kargs a, prog_map pm, uint3
                                                   const int32_t* __restrict__ op_off,
                                                   size_t n_op_off, const uint32_t* __restrict__ ops,
                                                   size_t n_ops, const uint32_t* __restrict__ bmap,
-                                                  uint32_t lds_words)
+                                                  uint32_t lds_words, const uint16_t* tab)
 {
     extern __shared__ uint32_t smem[];
     uint32_t* ldata = smem;
@@ -166,8 +167,8 @@ __global__ __launch_bounds__(1024) void k_program(hr_kargs a, prog_map pm, uint3
                 if (kind == 0) (void)*(volatile uint32_t*)(d + idx);
                 else if (kind == 1) d[idx] = t + 1;
                 else atomicAdd(d + idx, 1u);
-                hr_check_k<LOG>(a.env, th, kind, a.shadow[r], a.n_elems[r], r, idx,
-                           hr_lay_off(a.lay[r], idx), p + 1);
+                hr_check_k<LOG, TABLE>(a.env, th, kind, a.shadow[r], a.n_elems[r], r, idx,
+                                       hr_lay_off(a.lay[r], idx), p + 1, tab);
             }
         }
         const uint8_t sc = scope[p];
@@ -261,7 +262,8 @@ extern "C" hr_status hr_reduce_check(hr_ctx c, uint32_t r_in, uint32_t r_out, co
                                      int32_t* out_dev, uint32_t n, uint32_t threads,
                                      uint32_t blocks, int32_t drop, void* stream)
 {
-    if (c && (c->cfg.flags & HR_CFG_NESTED_TILES)) return HR_E_INVAL;   // no tile level here
+    if (c && (c->cfg.flags & (HR_CFG_NESTED_TILES | HR_CFG_FSM_TABLE)))
+        return HR_E_INVAL;   // no tile level, no table form here
     if (!c || !reduce_shape_ok(n, threads, blocks) ||
         !hr_region_ok(c, r_in, in_dev, (size_t)n * blocks) ||
         !hr_region_ok(c, r_out, out_dev, (size_t)threads * blocks))
@@ -317,6 +319,16 @@ extern "C" hr_status hr_jacobi_check(hr_ctx c, uint32_t r_old, uint32_t r_new,
         return HR_E_INVAL;
     hr_kargs a;
     hr_fill_args(c, &a);
+    if (c->cfg.flags & HR_CFG_FSM_TABLE) {
+        // the transitions from the flat table: the row-major kernel only
+        if (!c->fsm_tab || !u_old_dev || !u_new_dev || !lay_flat(a, r_old) ||
+            !lay_flat(a, r_new) || !lay_fits(a, r_old, nx) || !lay_fits(a, r_new, nx))
+            return HR_E_INVAL;
+        HR_LAUNCH(k_jacobi_tab<1>, dim3((nx + 15) / 16, (ny + 15) / 16), dim3(256), 0,
+                  hr_stream(c, stream), a, gref(a, r_old, nx), gref(a, r_new, nx), u_old_dev,
+                  u_new_dev, ny, nx, seed_dev, (const uint16_t*)c->fsm_tab);
+        return HR_OK;
+    }
     return hr_launch_jacobi(a, r_old, r_new, u_old_dev, u_new_dev, ny, nx, seed_dev,
                             hr_stream(c, stream));
 }
@@ -379,7 +391,8 @@ extern "C" hr_status hr_labelprop_check(hr_ctx c, uint32_t r_label, uint32_t r_r
                                         const uint8_t* mask_dev, uint32_t n, uint32_t tpb,
                                         void* stream)
 {
-    if (c && (c->cfg.flags & HR_CFG_NESTED_TILES)) return HR_E_INVAL;   // no tile level here
+    if (c && (c->cfg.flags & (HR_CFG_NESTED_TILES | HR_CFG_FSM_TABLE)))
+        return HR_E_INVAL;   // no tile level, no table form here
     if (!c || !row_ptr_dev || !col_dev || !mask_dev || !labelprop_shape_ok(n, tpb) ||
         !hr_region_ok(c, r_label, label_dev, n))
         return HR_E_INVAL;
@@ -459,10 +472,17 @@ extern "C" hr_status hr_program_check(hr_ctx c, const uint32_t* regions_host, ui
     const size_t lds_bytes = (size_t)lds_words * 2 * sizeof(uint32_t);
     const bool nested = (c->cfg.flags & HR_CFG_NESTED_TILES) != 0;
     if (nested && blocks > hr::n::BLOCK_LIMIT) return HR_E_INVAL;
+    if (nested) {
+        auto kern = a.env.log ? k_program_nested<true> : k_program_nested<false>;
+        HR_LAUNCH(kern, dim3(blocks), dim3(threads), lds_bytes, hr_stream(c, stream), a, pm,
+                  blocks, threads, phases, scope_dev, wave_mask_dev, op_off_dev, n_op_off, ops_dev,
+                  n_ops, block_map_dev, lds_words);
+        return HR_OK;
+    }
     auto kern = a.env.log ? k_program<true> : k_program<false>;
-    if (nested) kern = a.env.log ? k_program_nested<true> : k_program_nested<false>;
-    HR_LAUNCH(kern, dim3(blocks), dim3(threads), lds_bytes, hr_stream(c, stream), a,
-                       pm, blocks, threads, phases, scope_dev, wave_mask_dev, op_off_dev, n_op_off,
-                       ops_dev, n_ops, block_map_dev, lds_words);
+    if (c->fsm_tab) kern = k_program<false, true>;
+    HR_LAUNCH(kern, dim3(blocks), dim3(threads), lds_bytes, hr_stream(c, stream), a, pm, blocks,
+              threads, phases, scope_dev, wave_mask_dev, op_off_dev, n_op_off, ops_dev, n_ops,
+              block_map_dev, lds_words, (const uint16_t*)c->fsm_tab);
     return HR_OK;
 }

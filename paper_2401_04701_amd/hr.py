@@ -33,6 +33,7 @@ HR_CFG_WAVE_GROUPING = 2
 HR_CFG_WORD4 = 4
 HR_CFG_ACCESS_LOG = 8
 HR_CFG_NESTED_TILES = 16
+HR_CFG_FSM_TABLE = 32
 NO_REGION = 0xFFFFFFFF
 HR_PAT_REDUCE, HR_PAT_JACOBI, HR_PAT_LABELPROP = 0, 1, 2
 HR_SITES = 256
@@ -153,6 +154,7 @@ def _load():
         "hr_check_count": [P, P, P],
         "hr_access_log": [P, P, sz, P, P],
         "hr_fsm_step": [u32, u64, u32, u32, u32, u32, u32, u32, u32, P],
+        "hr_fsm_step_table": [u32, u64, u32, u32, u32, u32, u32, u32, u32, P],
         "hr_fsm_merge": [u64, u64, u32, P],
         "hr_fsm_step_nested": [u32, u64, u32, u32, u32, u32, u32, u32, u32, u32, P],
         "hr_fsm_merge_nested": [u64, u64, u32, P],
@@ -192,7 +194,8 @@ EXPORTED = ("hr_ctx_create", "hr_ctx_destroy", "hr_shadow_alloc", "hr_shadow_all
             "hr_dev_args", "hr_batch_create", "hr_batch_run", "hr_batch_info",
             "hr_batch_destroy", "hr_job_run", "hr_job_run_static", "hr_serve",
             "hr_kernel_end", "hr_reset", "hr_report", "hr_check_count", "hr_access_log",
-            "hr_fsm_step", "hr_fsm_merge", "hr_fsm_step_nested", "hr_fsm_merge_nested",
+            "hr_fsm_step", "hr_fsm_step_table", "hr_fsm_merge", "hr_fsm_step_nested",
+            "hr_fsm_merge_nested",
             "hr_describe", "hr_fsm_step_word4", "hr_word4_widen",
             "hr_reduce_check", "hr_reduce_plain", "hr_jacobi_check", "hr_jacobi_plain",
             "hr_labelprop_check", "hr_labelprop_plain", "hr_program_check",
@@ -230,6 +233,17 @@ def fsm_step(space: int, old: int, kind: int, launch: int, block: int, thread: i
     out = ctypes.c_uint64(0)
     _check("hr_fsm_step", _lib.hr_fsm_step(space, old, kind, launch, block, thread, bc, wc,
                                            wave_bits, ctypes.byref(out)))
+    return int(out.value)
+
+
+def fsm_step_table(old: int, kind: int, launch: int, block: int, thread: int, bc: int, wc: int,
+                   wave_bits: int = 6) -> int:
+    """The global-word transition through the flat table (HR_CFG_FSM_TABLE);
+    it must equal fsm_step(HR_GLOBAL, ...) on every input."""
+    out = ctypes.c_uint64(0)
+    _check("hr_fsm_step_table", _lib.hr_fsm_step_table(HR_GLOBAL, old, kind, launch, block,
+                                                       thread, bc, wc, wave_bits,
+                                                       ctypes.byref(out)))
     return int(out.value)
 
 
@@ -343,17 +357,20 @@ class Context:
     arguments are the fields of hr_config; word4=True selects 4-byte global
     shadow words (HR_CFG_WORD4), whose thread field is thread_bits wide;
     nested_tiles=True (HR_CFG_NESTED_TILES) makes tiles of 2**wave_bits
-    lanes with their own barriers nested in whole waves."""
+    lanes with their own barriers nested in whole waves; fsm_table=True
+    (HR_CFG_FSM_TABLE) reads the global-word transitions from the machine's
+    flat table."""
 
     def __init__(self, ring_capacity=0, bc_bits=0, wc_bits=0, count_checks=False,
                  shadow_budget=0, wave_grouping=False, site_limit=0, wave_bits=0,
                  word4=False, thread_bits=0, coalesce_width=0, access_log=False,
-                 log_capacity=0, nested_tiles=False, stream=None):
+                 log_capacity=0, nested_tiles=False, fsm_table=False, stream=None):
         flags = (HR_CFG_COUNT_CHECKS if count_checks else 0) | \
                 (HR_CFG_WAVE_GROUPING if wave_grouping else 0) | \
                 (HR_CFG_WORD4 if word4 else 0) | \
                 (HR_CFG_ACCESS_LOG if access_log else 0) | \
-                (HR_CFG_NESTED_TILES if nested_tiles else 0)
+                (HR_CFG_NESTED_TILES if nested_tiles else 0) | \
+                (HR_CFG_FSM_TABLE if fsm_table else 0)
         cfg = _Config(ring_capacity, bc_bits, wc_bits, flags, shadow_budget, site_limit,
                       wave_bits, thread_bits, coalesce_width, log_capacity, 0)
         self.wave_bits = wave_bits or 6

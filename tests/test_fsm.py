@@ -392,3 +392,43 @@ def test_nested_merge_is_the_summary_of_the_union():
                 assert ((m & 7) == hr.T_RACE) == ((whole & 7) == hr.T_RACE), (s, key, cut)
                 checked += 1
     assert checked > 100
+
+
+def test_flat_table_equals_bit_logic():
+    """The flat-table transition (HR_CFG_FSM_TABLE, built at compile time
+    from the bit logic) equals the bit logic on every word: all eight tags
+    and class fields against accesses in each relation, random raw words,
+    and words reached by random access sequences; group widths 2..64."""
+    rng = np.random.default_rng(17)
+    n = 0
+    for tag in range(8):
+        for cls in range(64):
+            base = tag | (cls << 3) | (int(rng.integers(0, 1 << 55)) << 9)
+            for rel_args in ((1, 5, 67, 3, 2), (2, 5, 67, 3, 2), (1, 6, 67, 3, 2),
+                             (1, 5, 67, 4, 2), (1, 5, 131, 3, 2), (1, 5, 67, 3, 3),
+                             (1, 5, 68, 3, 2)):
+                for kind in range(3):
+                    for wb in (6, 3):
+                        old = base if tag else 0
+                        a = hr.fsm_step(hr.HR_GLOBAL, old, kind, *rel_args, wave_bits=wb)
+                        assert hr.fsm_step_table(old, kind, *rel_args, wave_bits=wb) == a
+                        n += 1
+    for trial in range(4000):
+        old = int(rng.integers(0, 2 ** 63)) * int(rng.integers(1, 3)) if trial % 2 else 0
+        for _ in range(int(rng.integers(0, 4))):
+            old = hr.fsm_step(hr.HR_GLOBAL, old, int(rng.integers(0, 3)), int(rng.integers(0, 3)),
+                              int(rng.integers(0, 3)), int(rng.integers(0, 200)),
+                              int(rng.integers(0, 3)), int(rng.integers(0, 3)),
+                              int(rng.integers(1, 7)))
+        args = (int(rng.integers(0, 3)), int(rng.integers(0, 3)), int(rng.integers(0, 3)),
+                int(rng.integers(0, 200)), int(rng.integers(0, 3)), int(rng.integers(0, 3)),
+                int(rng.integers(1, 7)))
+        assert hr.fsm_step_table(old, *args) == hr.fsm_step(hr.HR_GLOBAL, old, *args)
+        n += 1
+    assert n > 20000
+    import ctypes
+    out = ctypes.c_uint64(0)
+    assert hr.lib().hr_fsm_step_table(hr.HR_GLOBAL, 0, 0, 0, 0, 0, 0, 0, 6,
+                                      ctypes.byref(out)) == 0
+    assert hr.lib().hr_fsm_step_table(hr.HR_LDS, 0, 0, 0, 0, 0, 0, 0, 6,
+                                      ctypes.byref(out)) == hr.HR_E_INVAL   # global words only
