@@ -59,6 +59,27 @@ def data_bytes_per_launch(ny: int, nx: int) -> int:
     return ny * nx * (4 + 4)
 
 
+def counter_record(kernel: str, summary: str):
+    """The machine-readable record of a committed counter summary under
+    profiles/ for `kernel`, or None when the kernel's built assembly
+    fingerprint differs from the recorded one."""
+    import re as _re
+    path = os.path.join(ROOT, "profiles", summary)
+    if not os.path.exists(path):
+        return None
+    m = _re.search(r"```json\n(.*?)\n```", open(path).read(), flags=_re.S)
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    fp_path = os.path.join(ROOT, "paper_2401_04701_amd", "libhr_kernels.json")
+    if rec.get("kernel") != kernel or not os.path.exists(fp_path):
+        return None
+    with open(fp_path) as f:
+        if json.load(f).get(rec["isa_symbol"]) != rec["isa_sha256"]:
+            return None
+    return rec
+
+
 def counter_traffic(kernel: str, summary: str = "k_jacobi_check_4096x4096_hbm_counters.md"):
     """HBM bytes per launch of `kernel` from its committed counter summary
     under profiles/, or None when the kernel changed since the counters were
@@ -724,6 +745,17 @@ def main():
         result["atomic"] = {"global_checks_per_s": g_rate,
                             "peak_xchg_per_s": peaks["xchg_coalesced_per_s"],
                             "frac": g_rate / peaks["xchg_coalesced_per_s"], **peaks}
+        # the memory-side atomic requests the kernel actually issues (its
+        # exchanges and fold compare-and-swaps, 8 lanes of 8-byte words per
+        # request; hooks whose word does not change issue none), from the
+        # committed L2 counters while the kernel is the one they measured
+        rec = counter_record("k_jacobi<1>", "k_jacobi_check_4096x4096_l2_counters.md")
+        if rec:
+            req_s = rec["ea_atomic_requests_per_launch"] / avg_launch_s
+            peak_req = peaks["xchg_coalesced_per_s"] / rec["lanes_per_request"]
+            result["atomic"].update(ea_requests_per_launch=rec["ea_atomic_requests_per_launch"],
+                                    ea_requests_per_s=req_s, peak_requests_per_s=peak_req,
+                                    requests_frac=req_s / peak_req)
     if not args.no_cpu_baseline:
         remap = {regs[0]: 0, regs[1]: 1}
         gpu_keys = {(int(r["space"]),
