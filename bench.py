@@ -449,7 +449,8 @@ def bench_serving(args, torch, si, hr, stream):
         for mode in ("served", "serial"):
             note("rate", rate, mode)
             sets[mode], times = hr.serve(ctx, insts, arr, serial=(mode == "serial"),
-                                         large_burst=args.serve_large_burst, stream=stream)
+                                         large_burst=args.serve_large_burst,
+                                         lane_burst=args.serve_lane_burst, stream=stream)
             fin = np.array([t.finish_s for t in times])
             lat = fin - arr
             span = float(fin.max())
@@ -484,6 +485,7 @@ def bench_serving(args, torch, si, hr, stream):
                    "jobs": len(js), "full_size_jobs": sum(bool(s.get("big")) for s in specs),
                    "checks_per_stream": int(checks), "shadow_budget_bytes": 64 << 30,
                    "large_burst": args.serve_large_burst or "all phases",
+                   "lane_burst": args.serve_lane_burst or "library default",
                    "parallelism": "single GPU"},
         "p50_ms": top["served"]["p50_ms"], "p99_ms": top["served"]["p99_ms"],
         "p50_ms_by_class": {c: v["p50_ms"] for c, v in top["served"]["by_class"].items()},
@@ -515,6 +517,8 @@ def main():
     ap.add_argument("--serve-jobs", type=int, default=2000, help="serving: jobs per stream")
     ap.add_argument("--serve-large-burst", type=int, default=0,
                     help="serving: phases of a large stencil job per iteration (0: all)")
+    ap.add_argument("--serve-lane-burst", type=int, default=0,
+                    help="serving: phases per iteration of the short-job lane (0: the library's)")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="first copy 256 MiB once with the library's copy kernel, the "
                          "calibration of the HBM byte counters of a counter run")

@@ -674,6 +674,11 @@ typedef struct {
                                 HR_SERVE_MAX_ITEMS; 0: HR_SERVE_MAX_ITEMS */
     uint32_t large_burst;    /* phases of a large stencil job that one iteration
                                 of the large-job lane runs; 0: all remaining */
+    uint32_t lane_burst;     /* phases one iteration of the short-job lane
+                                runs: the next lane_burst phases of its
+                                resident jobs, as launches back to back; 0: 2,
+                                at most 64 */
+    uint32_t pad;
 } hr_serve_config;
 
 /* One iteration is one launch of 1024-thread blocks, whose grid may not

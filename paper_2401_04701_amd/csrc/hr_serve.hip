@@ -161,6 +161,11 @@ hr_status serve_serial(hr_ctx c, const hr_instance* jobs, hr_serve_job* times, u
 // hold back the short jobs sharing their iterations.  Four lanes: as many as
 // the device's hardware queues for one process.
 //
+// The short-job lane runs two phases of its jobs per iteration
+// (hr_serve_config.lane_burst), as two launches back to back: a small
+// stencil's 20 phases then cost 10 host round trips instead of 20, while a
+// job that arrives meanwhile waits for at most two launches.
+//
 // The large lane runs its jobs one at a time, in admission order: a job of
 // that many items fills the device by itself, so sharing iterations among
 // several would only stretch every one of them (each would finish near the
@@ -228,7 +233,9 @@ struct serve_buffers {
     }
 };
 
-hr_status lane_init(lane_state& L, hr_ctx c, hipStream_t caller, bool first, uint32_t max_slots)
+// burst: iterations a lane enqueues at once (each with its own job list).
+hr_status lane_init(lane_state& L, hr_ctx c, hipStream_t caller, bool first, uint32_t max_slots,
+                    uint32_t burst)
 {
     if (first) {
         L.s = caller;
@@ -244,11 +251,11 @@ hr_status lane_init(lane_state& L, hr_ctx c, hipStream_t caller, bool first, uin
             return HR_E_NOMEM;
     }
     if (hipEventCreateWithFlags(&L.done, hipEventDisableTiming) != hipSuccess) return HR_E_HIP;
-    if (hipMalloc(&L.act, sizeof(uint32_t) * max_slots) != hipSuccess ||
-        hipMalloc(&L.prefix, sizeof(uint64_t) * (max_slots + 1)) != hipSuccess ||
-        hipHostMalloc(&L.h_act, sizeof(uint32_t) * max_slots, hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc(&L.h_prefix, sizeof(uint64_t) * (max_slots + 1), hipHostMallocDefault) !=
-            hipSuccess ||
+    const size_t na = (size_t)max_slots * burst, np = (size_t)(max_slots + 1) * burst;
+    if (hipMalloc(&L.act, sizeof(uint32_t) * na) != hipSuccess ||
+        hipMalloc(&L.prefix, sizeof(uint64_t) * np) != hipSuccess ||
+        hipHostMalloc(&L.h_act, sizeof(uint32_t) * na, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(&L.h_prefix, sizeof(uint64_t) * np, hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc(&L.h_ctr, sizeof(uint32_t) * HR_CTR_SITES, hipHostMallocDefault) !=
             hipSuccess)
         return HR_E_NOMEM;
@@ -289,7 +296,8 @@ hr_status serve_continuous(hr_ctx c, const hr_instance* jobs, hr_serve_job* time
     const hr_env env_base = hr_make_env(c);
     for (uint32_t k = 0; k < N_LANES; ++k) {
         lane_state& L = b.lane[k];
-        const hr_status st = lane_init(L, c, hr_stream(c, stream), k == 0, max_slots);
+        const hr_status st = lane_init(L, c, hr_stream(c, stream), k == 0, max_slots,
+                                       k == LANE_SHORT ? cfg.lane_burst : 1u);
         if (st != HR_OK) return st;
         L.lds = lds[k];
         for (uint32_t pm : {1u << HR_PAT_REDUCE, 1u << HR_PAT_JACOBI, 1u << HR_PAT_LABELPROP,
@@ -359,24 +367,41 @@ hr_status serve_continuous(hr_ctx c, const hr_instance* jobs, hr_serve_job* time
                 }
                 first.burst = last - first.phase;
             } else {
-                uint64_t total = 0;
-                uint32_t patterns = 0;
+                // iteration j of the burst runs phase phase + j of every job
+                // that has it; each iteration has its own job list
+                const uint32_t burst = k == LANE_SHORT ? cfg.lane_burst : 1u;
+                uint32_t iters = 0;
+                for (uint32_t j = 0; j < burst; ++j) {
+                    uint32_t* act = L.h_act + (size_t)j * max_slots;
+                    uint64_t* pre = L.h_prefix + (size_t)j * (max_slots + 1);
+                    uint64_t total = 0;
+                    uint32_t patterns = 0, m = 0;
+                    for (size_t q = 0; q < n_run; ++q) {
+                        const job_state& st = js[L.jobs[q]];
+                        if (st.phase + j >= st.in.phases) continue;
+                        pre[m] = total;
+                        act[m] = st.slot | ((st.phase + j) << 20);
+                        total += st.items;
+                        patterns |= 1u << st.in.pattern;
+                        ++m;
+                    }
+                    if (m == 0) break;
+                    pre[m] = total;
+                    uint32_t* d_act = L.act + (size_t)j * max_slots;
+                    uint64_t* d_pre = L.prefix + (size_t)j * (max_slots + 1);
+                    if (hipMemcpyAsync(d_act, act, sizeof(uint32_t) * m, hipMemcpyHostToDevice,
+                                       L.s) != hipSuccess ||
+                        hipMemcpyAsync(d_pre, pre, sizeof(uint64_t) * (m + 1),
+                                       hipMemcpyHostToDevice, L.s) != hipSuccess)
+                        return HR_E_HIP;
+                    HR_LAUNCH(iter_for(patterns), dim3((uint32_t)total), dim3(HR_WORKER_THREADS),
+                              L.lds, L.s, env[k], b.slots, d_act, d_pre, m);
+                    ++iters;
+                }
                 for (size_t q = 0; q < n_run; ++q) {
                     job_state& st = js[L.jobs[q]];
-                    L.h_prefix[q] = total;
-                    L.h_act[q] = st.slot | (st.phase << 20);
-                    total += st.items;
-                    patterns |= 1u << st.in.pattern;
-                    st.burst = 1;
+                    st.burst = std::min(iters, st.in.phases - st.phase);
                 }
-                L.h_prefix[n_run] = total;
-                if (hipMemcpyAsync(L.act, L.h_act, sizeof(uint32_t) * n_run,
-                                   hipMemcpyHostToDevice, L.s) != hipSuccess ||
-                    hipMemcpyAsync(L.prefix, L.h_prefix, sizeof(uint64_t) * (n_run + 1),
-                                   hipMemcpyHostToDevice, L.s) != hipSuccess)
-                    return HR_E_HIP;
-                HR_LAUNCH(iter_for(patterns), dim3((uint32_t)total), dim3(HR_WORKER_THREADS),
-                          L.lds, L.s, env[k], b.slots, L.act, L.prefix, (uint32_t)n_run);
             }
             if (hipMemcpyAsync(L.h_ctr, L.ctr, sizeof(uint32_t) * HR_CTR_SITES,
                                hipMemcpyDeviceToHost, L.s) != hipSuccess ||
@@ -502,7 +527,10 @@ extern "C" hr_status hr_serve(hr_ctx c, const hr_instance* jobs, hr_serve_job* t
     if (cfg.max_slots == 0) cfg.max_slots = 1024;
     if (cfg.shadow_budget == 0) cfg.shadow_budget = 64ull << 30;
     if (cfg.max_items == 0) cfg.max_items = HR_SERVE_MAX_ITEMS;
-    if (cfg.max_slots >= (1u << 20) || cfg.max_items > HR_SERVE_MAX_ITEMS) return HR_E_INVAL;
+    if (cfg.lane_burst == 0) cfg.lane_burst = 2;
+    if (cfg.max_slots >= (1u << 20) || cfg.max_items > HR_SERVE_MAX_ITEMS ||
+        cfg.lane_burst > 64)
+        return HR_E_INVAL;
     for (uint32_t j = 0; j < n_jobs; ++j) {
         times[j].admit_s = times[j].finish_s = -1.0;
         times[j].flagged = 0;

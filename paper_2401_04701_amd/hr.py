@@ -120,14 +120,15 @@ class ServeJob(ctypes.Structure):
 class _ServeConfig(ctypes.Structure):
     _fields_ = [("shadow_budget", ctypes.c_uint64), ("max_slots", ctypes.c_uint32),
                 ("serial", ctypes.c_uint32), ("max_items", ctypes.c_uint32),
-                ("large_burst", ctypes.c_uint32)]
+                ("large_burst", ctypes.c_uint32), ("lane_burst", ctypes.c_uint32),
+                ("pad", ctypes.c_uint32)]
 
 
 SERVE_MAX_ITEMS = (1 << 22) - 1    # work items of one serving iteration (one launch)
 
 assert ctypes.sizeof(Instance) == 72
 assert ctypes.sizeof(ServeJob) == 32
-assert ctypes.sizeof(_ServeConfig) == 24
+assert ctypes.sizeof(_ServeConfig) == 32
 
 
 def _load():
@@ -539,12 +540,13 @@ def job_run(inst: Instance, ring_capacity=0, stream=None, static=False, site_lim
 
 
 def serve(ctx: Context, instances, arrivals, shadow_budget=0, max_slots=0, serial=False,
-          max_items=0, large_burst=0, stream=None):
+          max_items=0, large_burst=0, lane_burst=0, stream=None):
     """Check a stream of jobs arriving at `arrivals` (seconds from the call,
     non-decreasing) with continuous batching, or one at a time (serial).
     max_items caps the work items (1024-thread blocks) of one iteration
     (0: SERVE_MAX_ITEMS); large_burst: phases of a large stencil job per
-    iteration of the large-job lane (0: all remaining).  Returns (per-job flagged keys with job-local
+    iteration of the large-job lane (0: all remaining); lane_burst: phases
+    per iteration of the short-job lane (0: 2).  Returns (per-job flagged keys with job-local
     region ids 0/1, ServeJob array with admission/finish times, flagged
     counts and warning bits)."""
     n = len(instances)
@@ -553,7 +555,7 @@ def serve(ctx: Context, instances, arrivals, shadow_budget=0, max_slots=0, seria
     for j, a in enumerate(arrivals):
         times[j].arrival_s = float(a)
     cfg = _ServeConfig(int(shadow_budget), int(max_slots), int(bool(serial)), int(max_items),
-                       int(large_burst))
+                       int(large_burst), int(lane_burst), 0)
     cnt = ctypes.c_size_t(0)
     cap = 1 << 20          # a larger count re-runs the whole stream
     while True:

@@ -137,17 +137,19 @@ def test_serving_mix_equals_alone(env, stream, budget_jobs, slots, rate):
     say("  p50 %.3f ms p99 %.3f ms" % (1e3 * np.percentile(lat, 50), 1e3 * np.percentile(lat, 99)))
 
 
-@pytest.mark.parametrize("burst", [1, 3])
-def test_serving_large_lane_bursts(env, stream, burst):
+@pytest.mark.parametrize("burst,lane", [(1, 1), (3, 2), (0, 5), (2, 64)])
+def test_serving_bursts(env, stream, burst, lane):
     """The large lane runs its stencil jobs one at a time, `burst` phases per
-    iteration (the default runs all of a job's phases in one): the sets do
-    not depend on it, and the large jobs finish in admission order."""
+    iteration (0: all of a job's phases in one); the other lanes run `lane`
+    phases of their jobs per iteration: the sets do not depend on either,
+    and the large jobs finish in admission order."""
     torch, hr, jobs = env
     specs, js, want = stream
     arrivals = si.poisson_arrivals(9, len(js), 5000.0)
-    say("serve with large-lane bursts of", burst)
+    say("serve with large-lane bursts of", burst, "and lane bursts of", lane)
     with hr.Context(ring_capacity=1 << 16) as ctx:
-        per, times = hr.serve(ctx, [j.inst for j in js], arrivals, large_burst=burst)
+        per, times = hr.serve(ctx, [j.inst for j in js], arrivals, large_burst=burst,
+                              lane_burst=lane)
     for i, (w, p) in enumerate(zip(want, per)):
         assert p == w, (i, specs[i])
         assert times[i].status == 0 and times[i].flagged == len(w)
@@ -221,6 +223,9 @@ def test_serving_item_cap_arguments(env, stream):
         assert e.value.status == hr.HR_E_INVAL
         with pytest.raises(hr.HRError) as e:        # above the launch limit
             hr.serve(ctx, [j.inst for j in js], arrivals, max_items=hr.SERVE_MAX_ITEMS + 1)
+        assert e.value.status == hr.HR_E_INVAL
+        with pytest.raises(hr.HRError) as e:        # more than 64 phases per iteration
+            hr.serve(ctx, [j.inst for j in js], arrivals, lane_burst=65)
         assert e.value.status == hr.HR_E_INVAL
 
 
