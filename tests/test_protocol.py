@@ -82,6 +82,26 @@ def test_protocol_with_tiles_reports_oracle_set(tw):
     assert ps.STATS["folds"] > folds0
 
 
+@pytest.mark.parametrize("tile,threads", [(2, 8), (4, 8), (2, 66)])
+def test_protocol_nested_tiles_reports_oracle_set(tile, threads):
+    """The exchange + fold protocol on the nested machine: tiles of `tile`
+    lanes with their own barriers inside 64-lane waves (66 threads: a
+    second, partial wave), interleaved with wave and block barriers; every
+    schedule reports the oracle's nested set."""
+    folds0 = ps.STATS["folds"]
+    for s in range(12 if threads > 8 else 30):
+        prog = si.random_program(104729 * s + tile + threads, launches=2, blocks=2,
+                                 threads=threads, phases=4, max_ops=1 if threads > 8 else 2,
+                                 global_regions=1, global_words=2, lds_words=2,
+                                 kind_p=(0.5, 0.2, 0.3), scope_p=(0.2, 0.2, 0.15, 0.45),
+                                 tile_width=tile)
+        want = oracle.flagged_program(prog, 64, tile)
+        for sched in range(12):
+            pushed, _ = ps.simulate(prog, 64, seed=100 * s + sched, nested=tile)
+            assert set(pushed) == want, (tile, threads, s, sched)
+    assert ps.STATS["folds"] > folds0
+
+
 # --------------------------------------------------------------------------
 # The hooks as the tuned kernels issue them (protocol_pipe.py): preloaded
 # words, split issue and settle, and wave grouping, each and together.
