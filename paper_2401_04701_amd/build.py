@@ -110,7 +110,7 @@ def build(verbose: bool = False) -> str:
 
 
 EXAMPLES = ["reduce_block.hip", "stencil3.hip", "histogram.hip", "wave_reduce.hip",
-            "tile_reduce.hip"]
+            "tile_reduce.hip", "cg_reduce.hip"]
 EXAMPLES_LIB = os.path.join(PKG, "libhr_examples.so")
 
 

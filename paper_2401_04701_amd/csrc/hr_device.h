@@ -964,6 +964,14 @@ __device__ __forceinline__ uint32_t hr_mask_level(const hr_env& e, uint32_t thre
     return (mask & tile) == tile ? HR_MASK_TILE : HR_MASK_NONE;
 }
 
+// The mask of the calling lane's aligned group of n lanes (n a power of two
+// up to 64): a cooperative-groups tile of n lanes.
+__device__ __forceinline__ uint64_t hr_lane_tile_mask(uint32_t n)
+{
+    if (n >= 64u) return ~0ull;
+    return ((1ull << n) - 1ull) << (__lane_id() & ~(n - 1u));
+}
+
 // Masked wave barrier on the flat machine, whose synchronization groups are
 // the context's tiles (whole waves when wave_bits is 6): a mask that covers
 // the caller's group orders that group (a wider mask also orders lanes of

@@ -21,6 +21,7 @@ _PARAMS = {
     "histogram": [P, P, i32, i32],
     "wave_reduce": [P, P, i32],
     "tile_reduce": [P, P, i32, i32, i32],
+    "cg_reduce": [P, P, i32, i32],
 }
 
 

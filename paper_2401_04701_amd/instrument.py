@@ -220,6 +220,8 @@ def analyse(src: str, fn: dict) -> Tuple[List[Edit], Report, dict]:
             b, e = span(node)
             edits.append(Edit(b, e, "bar"))
             rep.barriers += 1
+        if k in ("CallExpr", "CXXMemberCallExpr"):
+            _cg_sync(src, node, edits, rep)
         if k == "CallExpr" and _callee(node) == "__syncwarp":
             b, e = span(node)
             args = (node.get("inner") or [])[1:]
@@ -271,6 +273,38 @@ def analyse(src: str, fn: dict) -> Tuple[List[Edit], Report, dict]:
     return edits, rep, pos
 
 
+def _cg_sync(src: str, node: dict, edits: List[Edit], rep: Report) -> bool:
+    """A cooperative-groups sync(): on a thread_block_tile<N> it becomes the
+    checker's barrier for the calling lane's aligned N-lane tile (its wave
+    when N is 64), on a thread_block the block barrier.  Other groups (grid,
+    coalesced and run-time sized groups) are left as they are and reported:
+    the checker then orders nothing there, which may report more races,
+    never fewer."""
+    inner = node.get("inner") or []
+    if not inner:
+        return False
+    callee = _strip(inner[0])
+    if callee.get("kind") != "MemberExpr" or callee.get("name") != "sync":
+        return False
+    base = _strip((callee.get("inner") or [{}])[0])
+    ty = base.get("type", {})
+    text = " ".join(t for t in (ty.get("qualType", ""), ty.get("desugaredQualType", "")) if t)
+    b, e = span(node)
+    m = re.search(r"thread_block_tile<\s*(\d+)", text)
+    if m:
+        n = int(m.group(1))
+        edits.append(Edit(b, e, "text", (f"hr_barrier_mask(hr_a.env, hr_t, hr_lane_tile_mask({n}))",)))
+        rep.barriers += 1
+        return True
+    if re.search(r"(^|[\s:])thread_block\b", text):
+        edits.append(Edit(b, e, "bar"))
+        rep.barriers += 1
+        return True
+    if "cooperative_groups" in text or re.search(r"(grid|coalesced|thread)_group", text):
+        rep.skipped.append(f"line {_line_of(src, b)}: sync() of {text.split()[0]} is not modelled")
+    return False
+
+
 def _apply(src: str, lo: int, hi: int, edits: List[Edit]) -> str:
     """src[lo:hi] with the edits inside that range applied (nested edits
     inside a subscript's index are applied recursively)."""
@@ -287,6 +321,8 @@ def _apply(src: str, lo: int, hi: int, edits: List[Edit]) -> str:
             out.append("hr_barrier_block(hr_a.env, hr_t)")
         elif e.kind == "wbar" and not e.parts:
             out.append("hr_barrier_mask(hr_a.env, hr_t, ~0ull)")
+        elif e.kind == "text":
+            out.append(e.parts[0])
         else:
             pre, (ib, ie), post = e.parts
             nested = [x for x in edits if ib <= x.start and x.end <= ie and x is not e]

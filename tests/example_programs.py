@@ -120,3 +120,19 @@ def without_tile_barriers(program: si.Program) -> si.Program:
     barriers' masks are narrower than its groups: no ordering at all."""
     return _rescope(program, lambda sc, m, threads: (si.SCOPE_NONE, 0) if sc == si.SCOPE_TILE
                     else (sc, m))
+
+
+def insert_block_barrier(program: si.Program, before: int) -> si.Program:
+    """The program with an empty phase ending in a block barrier inserted
+    before phase `before` of every launch (a block-wide sync between two
+    phases)."""
+    launches = []
+    for l in program.launches:
+        cut = before * l.blocks * l.threads
+        op_off = np.concatenate([l.op_off[:cut],
+                                 np.full(l.blocks * l.threads, l.op_off[cut], l.op_off.dtype),
+                                 l.op_off[cut:]])
+        scope = np.insert(l.scope, before, si.SCOPE_BLOCK).astype(np.uint8)
+        mask = np.insert(l.wave_mask, before, 0).astype(np.uint64)
+        launches.append(si.Launch(l.blocks, l.threads, scope, mask, op_off, l.ops))
+    return si.Program(launches, program.global_words, program.lds_words)

@@ -8,8 +8,8 @@ import pytest
 
 import oracle
 import synth_inputs as si
-from example_programs import (as_tile_groups, flagged_as, histogram_program, stencil3_program,
-                              without_tile_barriers)
+from example_programs import (as_tile_groups, flagged_as, histogram_program,
+                              insert_block_barrier, stencil3_program, without_tile_barriers)
 
 pytestmark = pytest.mark.gpu
 
@@ -178,6 +178,46 @@ def test_instrumented_masked_tile_barriers(env, tile, threads):
             else:
                 want = flagged_as(without_tile_barriers(prog), regs, 64)
                 assert st == hr.HR_W_PARTIAL_BARRIER and got == want
+            if dt == dw == -1:
+                sums = x.astype(np.int64).reshape(blocks, waves, 128).sum(axis=2)
+                assert (out.cpu().numpy().reshape(blocks, waves, 64) == sums[:, :, None]).all()
+
+
+@pytest.mark.parametrize("threads", [64, 128])
+def test_instrumented_cooperative_groups(env, threads):
+    """The two-level reduction written with cooperative groups
+    (examples/cg_reduce.hip): tile.sync() of a thread_block_tile<8> is the
+    8-lane tile barrier, wave.sync() of a thread_block_tile<64> the wave
+    barrier, block.sync() the block barrier -- the same sets, under the
+    three kinds of context, as the __syncwarp(mask) version."""
+    torch, hr, ex = env
+    blocks, waves, tile = 3, threads // 64, 8
+    x = np.random.default_rng(5 + threads).integers(0, 1 << 20, blocks * threads * 2,
+                                                    dtype=np.int32)
+    inp = torch.from_numpy(x).cuda()
+    for dt, dw in TILE_DROPS:
+        prog = si.nested_reduce_program(tile, waves, blocks, dt, dw)
+        prog = insert_block_barrier(prog, prog.launches[0].phases - 1)
+        for mode in ("nested", "tiles", "waves"):
+            say("instrumented cooperative groups", threads, dt, dw, mode)
+            out = torch.zeros(blocks * threads, dtype=torch.int32, device="cuda")
+            kw = {"nested": {"nested_tiles": True, "wave_bits": 3}, "tiles": {"wave_bits": 3},
+                  "waves": {}}[mode]
+            with hr.Context(**kw) as ctx:
+                r_in, r_out = ctx.shadow_alloc(inp), ctx.shadow_alloc(out)
+                ex.launch("cg_reduce", ctx, [r_in, r_out], (blocks,), (threads,), inp, out, dt, dw)
+                ctx.kernel_end()
+                got, st = ctx.flagged(), ctx.status
+            regs = [r_in, r_out]
+            if mode == "nested":
+                assert st == 0 and got == flagged_as(prog, regs, 64, tile)
+                if dt == dw == -1:
+                    assert got == set()
+            elif mode == "tiles":
+                assert st == 0 and got == flagged_as(as_tile_groups(prog, tile), regs, tile)
+            else:
+                assert st == hr.HR_W_PARTIAL_BARRIER
+                assert got == flagged_as(without_tile_barriers(prog), regs, 64)
             if dt == dw == -1:
                 sums = x.astype(np.int64).reshape(blocks, waves, 128).sum(axis=2)
                 assert (out.cpu().numpy().reshape(blocks, waves, 64) == sums[:, :, None]).all()

@@ -165,3 +165,32 @@ def test_tile_reduce_views_of_the_barriers():
             # that two lanes touch (all but word 0, lane 0's alone) races
             seg = {k[3] for k in waves if k[0] == si.SPACE_LDS and k[3] < 2 * 128}
             assert seg == {g * 2 * tile + j for g in range(128 // tile) for j in range(1, tile)}
+
+
+def test_cooperative_groups_syncs():
+    """sync() of a thread_block_tile<N> becomes the barrier of the calling
+    lane's N-lane tile, of a thread_block the block barrier; a grid or
+    coalesced group's sync stays as written and is reported."""
+    text, (rep,) = instrument.instrument(os.path.join(EX, "cg_reduce.hip"))
+    body = text.split("LDS shadow cleared")[1]
+    assert body.count("hr_barrier_mask(hr_a.env, hr_t, hr_lane_tile_mask(8))") == 2
+    assert body.count("hr_barrier_mask(hr_a.env, hr_t, hr_lane_tile_mask(64))") == 2
+    assert body.count("hr_barrier_block(hr_a.env, hr_t)") == 1
+    assert ".sync()" not in body and rep.barriers == 5 and rep.skipped == []
+
+
+def test_cooperative_groups_unmodelled_syncs(tmp_path):
+    src = tmp_path / "k.hip"
+    src.write_text("""#include <hip/hip_runtime.h>
+#include <hip/hip_cooperative_groups.h>
+namespace cg = cooperative_groups;
+__global__ void k(int* out)
+{
+    cg::coalesced_group active = cg::coalesced_threads();
+    active.sync();
+    out[threadIdx.x] = 1;
+}
+""")
+    text, (rep,) = instrument.instrument(str(src))
+    assert "active.sync()" in text and rep.barriers == 0
+    assert any("not modelled" in x for x in rep.skipped)
