@@ -195,8 +195,8 @@ struct lane_state {
     hr_race_rec* ring = nullptr;     // the context's ring and counters for the
     uint32_t* ctr = nullptr;         // first lane, own ones for the others
     bool own_ring = false;
-    uint32_t* act = nullptr;         // device copies of the iteration's job list
-    uint64_t* prefix = nullptr;
+    uint32_t* act = nullptr;         // device copies of the job lists of the
+    uint64_t* prefix = nullptr;      // iterations one burst launches (max_slots each)
     uint32_t* h_act = nullptr;       // pinned staging
     uint64_t* h_prefix = nullptr;
     uint32_t* h_ctr = nullptr;       // counters after the iteration
