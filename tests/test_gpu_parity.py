@@ -489,3 +489,59 @@ def test_labelprop_full_size(env):
         ks = sorted(got)
         assert len(got) == gold["flagged"] and key_digest(got) == gold["sha256"]
         assert [list(k) for k in ks[:16]] == gold["first_keys"]
+
+
+def _sparse_launch(blocks, threads, scopes, entries):
+    """A launch of `blocks` x `threads` in which only the (phase, block,
+    thread) keys of `entries` have operations (op lists)."""
+    n = len(scopes) * blocks * threads
+    counts = np.zeros(n, dtype=np.int64)
+    idx = {(p * blocks + b) * threads + t: ops for (p, b, t), ops in entries.items()}
+    for i, ops in idx.items():
+        counts[i] = len(ops)
+    op_off = np.zeros(n + 1, dtype=np.int32)
+    op_off[1:] = np.cumsum(counts)
+    flat = np.zeros(int(op_off[-1]), dtype=np.uint32)
+    for i, ops in idx.items():
+        flat[op_off[i]:op_off[i] + len(ops)] = ops
+    return si.Launch(blocks, threads, np.asarray(scopes, np.uint8),
+                     np.zeros(len(scopes), np.uint64), op_off, flat)
+
+
+@pytest.mark.parametrize("table", [False, True])
+def test_program_largest_block_ids(env, table):
+    """2^22 - 1 logical blocks, the most a launch may have: accessors whose
+    block ids differ only in the top bits of the 22-bit field (1 and
+    2^21 + 1) race, the last block's LDS race carries its id, and ordered
+    or atomic accesses of far-apart blocks stay clean -- the oracle's set."""
+    torch, hr = env
+    B = (1 << 22) - 1
+    G, L, R, W, A = si.SPACE_GLOBAL, si.SPACE_LDS, si.KIND_R, si.KIND_W, si.KIND_A
+    op = si.op_word
+    entries = {
+        (0, 0, 0): [op(G, 0, W, 0)], (0, B - 1, 1): [op(G, 0, R, 0)],           # race
+        (0, 1, 0): [op(G, 0, W, 2)], (0, (1 << 21) + 1, 0): [op(G, 0, W, 2)],   # race
+        (0, 1 << 21, 0): [op(G, 0, W, 1)], (1, 1 << 21, 1): [op(G, 0, R, 1)],   # ordered
+        (0, B - 1, 0): [op(G, 0, W, 3)], (1, B - 1, 1): [op(G, 0, W, 3)],       # ordered
+        (0, 2, 0): [op(G, 0, A, 4)], (0, B - 2, 1): [op(G, 0, A, 4)],           # atomics
+        (1, B - 1, 0): [op(L, 0, W, 0)],                                          # LDS race
+    }
+    entries[(1, B - 1, 1)] = entries[(1, B - 1, 1)] + [op(L, 0, W, 0)]
+    launch = _sparse_launch(B, 2, [si.SCOPE_BLOCK, si.SCOPE_NONE], entries)
+    prog = si.Program([launch], [8], 2)
+    want = oracle.flagged_program(prog)
+    assert want == {(0, 0, 0, 0), (0, 0, 0, 2), (1, 0, B - 1, 0)}
+    say("largest block ids, table", table)
+    data = torch.zeros(8, dtype=torch.int32, device="cuda")
+    with hr.Context(fsm_table=table) as ctx:
+        reg = ctx.shadow_alloc(data)
+        ctx.program_check(hr.DeviceProgram(launch), [reg], 2)
+        ctx.kernel_end()
+        got, st = ctx.flagged(), ctx.status
+    assert st == 0
+    assert {(sp, 0 if sp == 0 else rg, lb, ix) for sp, rg, lb, ix in got} == want
+    with hr.Context() as ctx:                  # one block more than the field holds
+        reg = ctx.shadow_alloc(data)
+        big = _sparse_launch(B + 1, 1, [si.SCOPE_NONE], {})
+        with pytest.raises(hr.HRError):
+            ctx.program_check(hr.DeviceProgram(big), [reg], 2)
