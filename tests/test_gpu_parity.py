@@ -545,3 +545,52 @@ def test_program_largest_block_ids(env, table):
         big = _sparse_launch(B + 1, 1, [si.SCOPE_NONE], {})
         with pytest.raises(hr.HRError):
             ctx.program_check(hr.DeviceProgram(big), [reg], 2)
+
+
+def test_program_largest_threads_and_nested_block_ids(env):
+    """1024-thread blocks (16 waves): lanes of the first and last wave race,
+    a wave barrier in the last wave orders its own lanes only; and with
+    tiles nested in waves, 2^20 blocks, the most the nested words hold (ids
+    below 2^20): block ids that differ only in the top bit of their 20-bit
+    field race.
+    Each set is the oracle's."""
+    torch, hr = env
+    G, L, R, W = si.SPACE_GLOBAL, si.SPACE_LDS, si.KIND_R, si.KIND_W
+    op = si.op_word
+    entries = {
+        (0, 1, 0): [op(G, 0, W, 0)], (0, 1, 1023): [op(G, 0, R, 0)],        # race
+        (0, 0, 960): [op(L, 0, W, 5)], (1, 0, 1023): [op(L, 0, R, 5)],      # wave 15: ordered
+        (0, 0, 959): [op(L, 0, W, 6)], (1, 0, 1022): [op(L, 0, R, 6)],      # waves 14, 15: race
+    }
+    launch = _sparse_launch(2, 1024, [si.SCOPE_WAVE, si.SCOPE_NONE], entries)
+    launch.wave_mask[0] = 1 << 15                                            # only wave 15 syncs
+    prog = si.Program([launch], [8], 8)
+    want = oracle.flagged_program(prog)
+    assert want == {(0, 0, 0, 0), (1, 0, 0, 6)}
+    data = torch.zeros(8, dtype=torch.int32, device="cuda")
+    say("1024-thread blocks")
+    with hr.Context() as ctx:
+        reg = ctx.shadow_alloc(data)
+        ctx.program_check(hr.DeviceProgram(launch), [reg], 8)
+        ctx.kernel_end()
+        got, st = ctx.flagged(), ctx.status
+    assert st == 0 and {(sp, 0 if sp == 0 else rg, lb, ix) for sp, rg, lb, ix in got} == want
+
+    B = 1 << 20
+    entries = {(0, 1, 0): [op(G, 0, W, 1)], (0, (1 << 19) + 1, 1): [op(G, 0, W, 1)],   # race
+               (0, B - 1, 0): [op(G, 0, W, 2)], (1, B - 1, 1): [op(G, 0, R, 2)]}    # tile-ordered
+    launch = _sparse_launch(B, 2, [si.SCOPE_TILE, si.SCOPE_NONE], entries)
+    launch.wave_mask[0] = 1                                                  # tile 0 syncs
+    prog = si.Program([launch], [8], 2)
+    want = oracle.flagged_program(prog, 64, 2)
+    assert want == {(0, 0, 0, 1)}
+    say("nested, 2^20 blocks")
+    with hr.Context(nested_tiles=True, wave_bits=1) as ctx:
+        reg = ctx.shadow_alloc(data)
+        ctx.program_check(hr.DeviceProgram(launch), [reg], 2)
+        ctx.kernel_end()
+        got, st = ctx.flagged(), ctx.status
+        assert st == 0 and {(sp, 0, lb, ix) for sp, rg, lb, ix in got} == want
+        with pytest.raises(hr.HRError):        # one block more than the nested field holds
+            ctx.program_check(hr.DeviceProgram(_sparse_launch(B + 1, 1, [si.SCOPE_NONE], {})),
+                              [reg], 2)
