@@ -167,6 +167,10 @@ typedef struct {
  * other workloads, the executors and hr_job_run_static reject such a
  * context.  Not with HR_CFG_WORD4, HR_CFG_NESTED_TILES or HR_CFG_ACCESS_LOG. */
 #define HR_CFG_FSM_TABLE 32u
+/* As HR_CFG_FSM_TABLE (which it implies), with the stencil's checked kernel
+ * reading the table from a copy in each block's LDS; the interpreter reads
+ * the device-memory copy. */
+#define HR_CFG_FSM_TABLE_LDS 64u
 
 /* One flagged location, 48 bytes.  The key is (space, region, block if LDS,
  * index).  The other fields describe how the race was found: `before` and

@@ -293,9 +293,11 @@ __global__ __launch_bounds__(1024, 8) void k_jacobi_x4(hr_kargs a, hr_gref gold,
 
 // The checked sweep of k_jacobi with every global transition read from the
 // flat table of the machine at `tab` (a context made with
-// HR_CFG_FSM_TABLE; row-major maps).  A template, so that only the sources
-// that launch it compile it.
-template <int CHECK = 1>
+// HR_CFG_FSM_TABLE; row-major maps).  LDS_TAB: each block first copies the
+// table into its LDS (32 KiB, which leaves room for 4 blocks per compute
+// unit) and reads it there (HR_CFG_FSM_TABLE_LDS).  A template, so that
+// only the sources that launch it compile it.
+template <int CHECK = 1, bool LDS_TAB = false>
 __global__ __launch_bounds__(256, 8) void k_jacobi_tab(hr_kargs a, hr_gref gold, hr_gref gnew,
                                                     const float* __restrict__ uo,
                                                     float* __restrict__ un, uint32_t ny,
@@ -305,8 +307,17 @@ __global__ __launch_bounds__(256, 8) void k_jacobi_tab(hr_kargs a, hr_gref gold,
     __shared__ float tile[JACOBI_TILE_WORDS];
     __shared__ uint32_t tsh[CHECK ? JACOBI_TILE_WORDS : 1];
     using G = hr_map<hr_gref_tab, 0, 0>;
-    jacobi_body<CHECK, G, true>(a.env, G{hr_gref_tab{gold, tab}}, G{hr_gref_tab{gnew, tab}}, uo,
-                                un, ny, nx, gridDim.x, seeds, blockIdx.y * gridDim.x + blockIdx.x,
+    const uint16_t* t = tab;
+    if constexpr (LDS_TAB) {
+        // the copy is complete before the body's first hook: the body's
+        // first block barrier (after its LDS shadow clear) follows it
+        __shared__ uint4 stab[sizeof(hr::g::step_table) / sizeof(uint4)];
+        const uint4* src = reinterpret_cast<const uint4*>(tab);
+        for (uint32_t i = threadIdx.x; i < sizeof(stab) / sizeof(uint4); i += 256) stab[i] = src[i];
+        t = reinterpret_cast<const uint16_t*>(stab);
+    }
+    jacobi_body<CHECK, G, true>(a.env, G{hr_gref_tab{gold, t}}, G{hr_gref_tab{gnew, t}}, uo, un,
+                                ny, nx, gridDim.x, seeds, blockIdx.y * gridDim.x + blockIdx.x,
                                 threadIdx.x, tile, tsh, 0);
 }
 

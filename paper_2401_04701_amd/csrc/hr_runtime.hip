@@ -262,8 +262,10 @@ bool hr_config_normalize(const hr_config* cfg, hr_config* out)
     if (k.thread_bits == 0) k.thread_bits = word4 ? 8 : 10;
     if (k.bc_bits > 8 || k.wc_bits > 6 || k.ring_capacity > (1u << 26)) return false;
     if (k.thread_bits > 10 || (!word4 && k.thread_bits != 10)) return false;
+    if (k.flags & HR_CFG_FSM_TABLE_LDS) k.flags |= HR_CFG_FSM_TABLE;
     if (k.flags & ~(HR_CFG_COUNT_CHECKS | HR_CFG_WAVE_GROUPING | HR_CFG_WORD4 |
-                    HR_CFG_ACCESS_LOG | HR_CFG_NESTED_TILES | HR_CFG_FSM_TABLE))
+                    HR_CFG_ACCESS_LOG | HR_CFG_NESTED_TILES | HR_CFG_FSM_TABLE |
+                    HR_CFG_FSM_TABLE_LDS))
         return false;
     if ((k.flags & HR_CFG_FSM_TABLE) &&
         (k.flags & (HR_CFG_WORD4 | HR_CFG_NESTED_TILES | HR_CFG_ACCESS_LOG)))

@@ -324,9 +324,10 @@ extern "C" hr_status hr_jacobi_check(hr_ctx c, uint32_t r_old, uint32_t r_new,
         if (!c->fsm_tab || !u_old_dev || !u_new_dev || !lay_flat(a, r_old) ||
             !lay_flat(a, r_new) || !lay_fits(a, r_old, nx) || !lay_fits(a, r_new, nx))
             return HR_E_INVAL;
-        HR_LAUNCH(k_jacobi_tab<1>, dim3((nx + 15) / 16, (ny + 15) / 16), dim3(256), 0,
-                  hr_stream(c, stream), a, gref(a, r_old, nx), gref(a, r_new, nx), u_old_dev,
-                  u_new_dev, ny, nx, seed_dev, (const uint16_t*)c->fsm_tab);
+        auto k = (c->cfg.flags & HR_CFG_FSM_TABLE_LDS) ? k_jacobi_tab<1, true> : k_jacobi_tab<1>;
+        HR_LAUNCH(k, dim3((nx + 15) / 16, (ny + 15) / 16), dim3(256), 0, hr_stream(c, stream), a,
+                  gref(a, r_old, nx), gref(a, r_new, nx), u_old_dev, u_new_dev, ny, nx, seed_dev,
+                  (const uint16_t*)c->fsm_tab);
         return HR_OK;
     }
     return hr_launch_jacobi(a, r_old, r_new, u_old_dev, u_new_dev, ny, nx, seed_dev,

@@ -34,6 +34,7 @@ HR_CFG_WORD4 = 4
 HR_CFG_ACCESS_LOG = 8
 HR_CFG_NESTED_TILES = 16
 HR_CFG_FSM_TABLE = 32
+HR_CFG_FSM_TABLE_LDS = 64
 NO_REGION = 0xFFFFFFFF
 HR_PAT_REDUCE, HR_PAT_JACOBI, HR_PAT_LABELPROP = 0, 1, 2
 HR_SITES = 256
@@ -360,7 +361,8 @@ class Context:
     nested_tiles=True (HR_CFG_NESTED_TILES) makes tiles of 2**wave_bits
     lanes with their own barriers nested in whole waves; fsm_table=True
     (HR_CFG_FSM_TABLE) reads the global-word transitions from the machine's
-    flat table."""
+    flat table in device memory, fsm_table="lds" (HR_CFG_FSM_TABLE_LDS) from
+    a copy in each block's LDS in the stencil kernel."""
 
     def __init__(self, ring_capacity=0, bc_bits=0, wc_bits=0, count_checks=False,
                  shadow_budget=0, wave_grouping=False, site_limit=0, wave_bits=0,
@@ -371,7 +373,8 @@ class Context:
                 (HR_CFG_WORD4 if word4 else 0) | \
                 (HR_CFG_ACCESS_LOG if access_log else 0) | \
                 (HR_CFG_NESTED_TILES if nested_tiles else 0) | \
-                (HR_CFG_FSM_TABLE if fsm_table else 0)
+                (HR_CFG_FSM_TABLE if fsm_table else 0) | \
+                (HR_CFG_FSM_TABLE_LDS if fsm_table == "lds" else 0)
         cfg = _Config(ring_capacity, bc_bits, wc_bits, flags, shadow_budget, site_limit,
                       wave_bits, thread_bits, coalesce_width, log_capacity, 0)
         self.wave_bits = wave_bits or 6

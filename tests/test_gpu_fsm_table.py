@@ -53,20 +53,24 @@ def test_table_jacobi_equals_oracle(env, ny, nx, launches, count):
     got, st, u = run_jacobi(torch, hr, ny, nx, launches, tab, fsm_table=True)
     want = oracle.flagged(oracle.model_jacobi(ny, nx, launches, tab))
     assert st == 0 and got == want
+    got_lds, st, _ = run_jacobi(torch, hr, ny, nx, launches, tab, fsm_table="lds")
+    assert st == 0 and got_lds == want
     bits, _, ub = run_jacobi(torch, hr, ny, nx, launches, tab)
     assert bits == got
     if not count:     # race-free: the sweep's output is the bit-logic kernel's, exactly
         assert torch.equal(u[launches % 2], ub[launches % 2])
 
 
-def test_table_jacobi_full_size(env):
+@pytest.mark.parametrize("mode", [True, "lds"])
+def test_table_jacobi_full_size(env, mode):
     """4096 x 4096, 20 launches, 66 seeded blocks: the oracle's set of the
-    whole job (tests/golden), as the bit-logic kernel gives it."""
+    whole job (tests/golden), as the bit-logic kernel gives it; the table in
+    device memory, or copied into each block's LDS."""
     torch, hr = env
     g = json.load(open(os.path.join(GOLDEN, "jacobi_4096x4096_20launches.json")))
     ny, nx, launches, seeds, tab = jacobi_full_workload()
-    say("table jacobi full size")
-    got, st, _ = run_jacobi(torch, hr, ny, nx, launches, tab, fsm_table=True)
+    say("table jacobi full size", mode)
+    got, st, _ = run_jacobi(torch, hr, ny, nx, launches, tab, fsm_table=mode)
     assert st == 0 and (len(got), key_digest(got)) == (g["flagged"], g["sha256"])
 
 
