@@ -658,39 +658,16 @@ def main():
     ev4.clear()
     cev4.clear()
 
-    # The same job under each shadow map the autotuner knows (row-major and
-    # tiles): per-launch time and the flagged set, which must not change.
+    # The same job under each shadow map and transition encoding the
+    # autotuner knows (tune.autotune_stencil): per-launch time and the
+    # flagged set, which must not change (and must be the headline's).
     from paper_2401_04701_amd import tune
-    map_ms, map_same = {}, True
-    for tile in tune.TILES:
-        ctxm = hr.Context()
-        regsm = [ctxm.shadow_alloc(u[0], tile=tile), ctxm.shadow_alloc(u[1], tile=tile)]
-        checked_step(None, ctxm, regsm)
-        evm = []
-        for _ in range(3):
-            recsm, stm = checked_step(evm, ctxm, regsm)
-        torch.cuda.synchronize()
-        ctxm.close()
-        map_same &= stm == 0 and keys(recsm) == keys(recs)
-        map_ms[tune.tile_name(tile)] = pct([a.elapsed_time(b) for a, b in evm], 50)
-        evm.clear()
-
-    # The same job with the transitions read from the machine's flat table
-    # (the paper's encoding) instead of computed by bit logic: timed against
-    # the headline's bit logic; the flagged set must not change.
-    fsm_ms, fsm_same = {"bits": map_ms["rowmajor"]}, True
-    for name, mode in (("table", True), ("table_lds", "lds")):
-        ctxf = hr.Context(fsm_table=mode)
-        regsf = [ctxf.shadow_alloc(u[0]), ctxf.shadow_alloc(u[1])]
-        checked_step(None, ctxf, regsf)
-        evf = []
-        for _ in range(3):
-            recsf, stf = checked_step(evf, ctxf, regsf)
-        torch.cuda.synchronize()
-        ctxf.close()
-        fsm_same &= stf == 0 and keys(recsf) == keys(recs)
-        fsm_ms[name] = pct([a.elapsed_time(b) for a, b in evf], 50)
-        evf.clear()
+    tuned, trials, tuned_set = tune.autotune_stencil(hr, u, tab, LAUNCHES, stream=stream)
+    map_ms = {k[len("map_"):]: v for k, v in trials.items() if k.startswith("map_")}
+    fsm_ms = {k[len("fsm_"):]: v for k, v in trials.items() if k.startswith("fsm_")}
+    remap = {regs[0]: 0, regs[1]: 1}
+    head_set = {(sp, remap[rg] if sp == 0 else rg, lb, ix) for sp, rg, lb, ix in keys(recs)}
+    map_same = fsm_same = tuned_set == head_set
 
     avg_launch_s = float(np.mean(launch_ms)) * 1e-3
     alg = algorithmic_bytes_per_launch(NY, NX)
@@ -744,6 +721,9 @@ def main():
     result["fsm_encoding"] = {"headline": "bits", "p50_launch_ms": fsm_ms,
                               "fastest": min(fsm_ms, key=fsm_ms.get),
                               "same_flagged_set": bool(fsm_same)}
+    result["stencil_autotune"] = {"best": {"tile": tune.tile_name(tuned["tile"]),
+                                           "fsm": tuned["fsm"]},
+                                  "trials_p50_launch_ms": trials}
     if not args.no_peaks:
         peaks = measure_peaks(torch, hr, stream)
         g_rate = n_g / avg_launch_s

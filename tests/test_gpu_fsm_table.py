@@ -126,3 +126,22 @@ def test_table_context_limits(env):
         ru, rv = ctx.shadow_alloc(u, tile=(2, 2)), ctx.shadow_alloc(v, tile=(2, 2))
         with pytest.raises(hr.HRError):                  # the table kernel is row-major only
             ctx.jacobi_check(ru, rv, u, v, None)
+
+
+def test_stencil_autotuner(env):
+    """tune.autotune_stencil times one stencil job under every shadow map and
+    transition encoding; every trial flags the oracle's set, and it names a
+    best map and encoding among those it timed."""
+    torch, hr = env
+    from paper_2401_04701_amd import tune
+    ny, nx, launches = 96, 80, 3
+    seeds = si.jacobi_seeds(ny, nx, si.master_seed(1) + 7, count=4)
+    tab = si.jacobi_seed_table(ny, nx, seeds)
+    u = [torch.from_numpy(si.jacobi_grid(ny, nx, 2)).cuda(),
+         torch.zeros((ny, nx), dtype=torch.float32, device="cuda")]
+    best, trials, flagged = tune.autotune_stencil(hr, u, torch.from_numpy(tab).cuda(), launches,
+                                                  reps=2)
+    assert flagged == oracle.flagged(oracle.model_jacobi(ny, nx, launches, tab))
+    assert {"map_" + tune.tile_name(t) for t in tune.TILES} <= set(trials)
+    assert {"fsm_bits", "fsm_table", "fsm_table_lds"} <= set(trials)
+    assert best["tile"] in tune.TILES and best["fsm"] in ("bits", "table", "table_lds")
