@@ -469,7 +469,8 @@ enum {
  * thread then writes its block's sum to out_dev[b*threads + t].  drop
  * names a step whose barrier is removed (a seeded race); a value outside
  * 0..log2(n)-1 keeps all barriers.  LDS array id 0.  The paper-sized case
- * is n = 512, threads = 256, blocks = 1. */
+ * is n = 512, threads = 256, blocks = 1.  HR_E_INVAL also for a context
+ * with HR_CFG_NESTED_TILES or HR_CFG_FSM_TABLE. */
 hr_status hr_reduce_check(hr_ctx c, uint32_t r_in, uint32_t r_out, const int32_t* in_dev,
                           int32_t* out_dev, uint32_t n, uint32_t threads, uint32_t blocks,
                           int32_t drop, void* stream);
@@ -482,7 +483,10 @@ hr_status hr_reduce_plain(const int32_t* in_dev, int32_t* out_dev, uint32_t n, u
  * value.  seed_dev: NULL or int32 per block (row-major block order): -1, or
  * side << 8 | offset, in which case that block's edge thread next to halo
  * cell `offset` on `side` (0 N, 1 S, 2 W, 3 E) also writes that
- * neighbour-owned cell of u_new (a seeded cross-block race). */
+ * neighbour-owned cell of u_new (a seeded cross-block race).  A context
+ * with HR_CFG_FSM_TABLE runs the table kernel, on row-major maps only
+ * (HR_E_INVAL for tiled regions); one with HR_CFG_NESTED_TILES is
+ * rejected (HR_E_INVAL). */
 hr_status hr_jacobi_check(hr_ctx c, uint32_t r_old, uint32_t r_new, const float* u_old_dev,
                           float* u_new_dev, uint32_t ny, uint32_t nx, const int32_t* seed_dev,
                           void* stream);
@@ -498,7 +502,8 @@ hr_status hr_jacobi_plain(const float* u_old_dev, float* u_new_dev, uint32_t ny,
  * without edges still passes some col and mask buffer), else HR_E_INVAL;
  * row_ptr_dev[n] must not exceed the length of col_dev and mask_dev, which
  * is not checked (it lies in device memory).  Limits: 1 <= tpb <= 1024,
- * ceil(n / tpb) < 2^22 blocks. */
+ * ceil(n / tpb) < 2^22 blocks.  HR_E_INVAL also for a context with
+ * HR_CFG_NESTED_TILES or HR_CFG_FSM_TABLE. */
 hr_status hr_labelprop_check(hr_ctx c, uint32_t r_label, uint32_t r_row_ptr, uint32_t r_col,
                              int32_t* label_dev, const int32_t* row_ptr_dev,
                              const int32_t* col_dev, const uint8_t* mask_dev, uint32_t n,
@@ -586,7 +591,8 @@ typedef struct {
  * the context's shadow budget), register its regions in the context, build
  * the work queues (instance, phase, block) and upload the job table.  inst
  * stays owned by the caller; region[] is filled in.  Errors: HR_E_INVAL (a
- * job's shape, a context with HR_CFG_WORD4), HR_E_NOMEM, HR_E_HIP. */
+ * job's shape, a context with HR_CFG_WORD4, HR_CFG_NESTED_TILES or
+ * HR_CFG_FSM_TABLE), HR_E_NOMEM, HR_E_HIP. */
 hr_status hr_batch_create(hr_ctx c, hr_instance* inst, uint32_t n_inst, hr_batch* out);
 
 /* Run every job of the batch to completion in one persistent launch of
@@ -700,11 +706,12 @@ typedef struct {
  * non-blocking streams (default priority) and their rings for the other
  * lanes, and frees them before it returns.  The context's regions are not
  * touched.
- * Errors: HR_E_INVAL (a context with HR_CFG_WORD4, a job's shape, unsorted
- * arrivals, max_items above
- * HR_SERVE_MAX_ITEMS, a job with more items per phase than max_items, cap
- * too small: then *n_out holds the number needed), HR_E_NOMEM (a job larger
- * than the budget, or the device allocation failed), HR_E_HIP. */
+ * Errors: HR_E_INVAL (a context with HR_CFG_WORD4, HR_CFG_NESTED_TILES or
+ * HR_CFG_FSM_TABLE, a job's shape, unsorted arrivals, max_items above
+ * HR_SERVE_MAX_ITEMS, a job with more items per phase than max_items,
+ * lane_burst above 64, cap too small: then *n_out holds the number needed),
+ * HR_E_NOMEM (a job larger than the budget, or the device allocation
+ * failed), HR_E_HIP. */
 hr_status hr_serve(hr_ctx c, const hr_instance* jobs, hr_serve_job* times, uint32_t n_jobs,
                    const hr_serve_config* cfg, hr_race* out, size_t cap, size_t* n_out,
                    void* stream);
