@@ -175,7 +175,8 @@ typedef struct {
 /* One flagged location, 48 bytes.  The key is (space, region, block if LDS,
  * index).  The other fields describe how the race was found: `before` and
  * `with` are two shadow summaries (global- or LDS-word layout, by space;
- * decode them with hr_describe) whose accesses include a racing pair.
+ * decode them with hr_describe, or hr_describe_nested in a context with
+ * HR_CFG_NESTED_TILES) whose accesses include a racing pair.
  * `before` is the word the race state replaced.  `with` is the completing
  * access alone (a single-thread summary holding its launch, block, thread,
  * block clock, wave clock and class) or, for a record made while folding
@@ -206,7 +207,9 @@ typedef enum {
     HR_S_BLOCKS = 2,        /* accesses from >= 2 blocks, all of class_block */
     HR_S_WAVES = 3,         /* one block; >= 2 waves in its latest block epoch */
     HR_S_THREADS = 4,       /* one wave; >= 2 threads in its latest wave epoch */
-    HR_S_THREAD = 5         /* one thread in the latest wave epoch */
+    HR_S_THREAD = 5,        /* one thread in the latest wave epoch */
+    HR_S_TILES = 6          /* tiles nested in waves: one wave; >= 2 tiles in its
+                               latest wave epoch (hr_describe_nested) */
 } hr_summary_state;
 
 typedef struct {
@@ -219,6 +222,25 @@ typedef struct {
     uint32_t wave, wc;      /* the wave (or tile) and its clock */
     uint32_t thread;        /* the thread (HR_S_THREAD) */
 } hr_summary;
+
+/* A shadow summary of a context with HR_CFG_NESTED_TILES decoded
+ * (hr_describe_nested): waves of 64 lanes, each split into tiles with their
+ * own barriers and clocks.  In it HR_S_THREADS means one tile with >= 2
+ * threads in its latest tile epoch, HR_S_THREAD one thread in that epoch,
+ * and HR_S_TILES one wave with >= 2 tiles in its latest wave epoch.  Fields
+ * a state does not keep are UINT32_MAX, classes 0, as in hr_summary. */
+typedef struct {
+    uint32_t state;         /* hr_summary_state */
+    uint32_t class_launch;  /* class of the (single) block's accesses this launch */
+    uint32_t class_block;   /* class in the latest block epoch (HR_S_BLOCKS: of all) */
+    uint32_t class_wave;    /* class in the latest wave epoch */
+    uint32_t class_tile;    /* class in the latest tile epoch */
+    uint32_t launch;        /* launch epoch (global words; 9 bits) */
+    uint32_t block, bc;     /* the block and its block clock */
+    uint32_t wave, wc;      /* the wave (thread / 64) and its wave clock */
+    uint32_t tile, tc;      /* the tile (thread >> tile_bits) and its tile clock */
+    uint32_t thread;        /* the thread (HR_S_THREAD) */
+} hr_summary_nested;
 
 /* Create a context whose default stream is `stream` (paper Sec. IV: the
  * checker's configuration; Sec. III-A, footnote on clock sizes: the clock
@@ -411,6 +433,15 @@ hr_status hr_fsm_merge_nested(uint64_t x, uint64_t y, uint32_t tile_bits, uint64
  * and its clock.  Errors: HR_E_INVAL (null out, unknown space or state tag,
  * wave_bits outside 1..6). */
 hr_status hr_describe(uint32_t space, uint64_t word, uint32_t wave_bits, hr_summary* out);
+
+/* Decode a shadow summary word of `space` of a context with
+ * HR_CFG_NESTED_TILES and tiles of 2^tile_bits lanes (its wave_bits): the
+ * `before` and `with` fields of that context's race records use this layout
+ * (paper Sec. III-A's summaries, with the tile level of the nested machine
+ * added below the wave).  Errors: HR_E_INVAL (null out, unknown space or
+ * state tag, tile_bits outside 1..5). */
+hr_status hr_describe_nested(uint32_t space, uint64_t word, uint32_t tile_bits,
+                             hr_summary_nested* out);
 
 /* Host evaluation of the device transition on a 4-byte global word
  * (HR_CFG_WORD4) whose field widths are wc_bits, bc_bits and thread_bits

@@ -643,6 +643,68 @@ extern "C" hr_status hr_describe(uint32_t space, uint64_t word, uint32_t wave_bi
     return HR_OK;
 }
 
+extern "C" hr_status hr_describe_nested(uint32_t space, uint64_t word, uint32_t tile_bits,
+                                        hr_summary_nested* out)
+{
+    if (!out || space > HR_LDS || tile_bits < 1 || tile_bits > 5) return HR_E_INVAL;
+    const uint32_t none = UINT32_MAX;
+    hr_summary_nested d = {};
+    d.launch = d.block = d.bc = d.wave = d.wc = d.tile = d.tc = d.thread = none;
+    uint32_t tag, cl = 0, cb, cw, ct, bc, wc, tc, th;
+    if (space == HR_GLOBAL) {
+        namespace n = hr::n;
+        tag = (uint32_t)(word & n::TAG_M);
+        cl = (uint32_t)(word >> n::CL_SH) & 3u;
+        cb = (uint32_t)(word >> n::CB_SH) & 3u;
+        cw = (uint32_t)(word >> n::CW_SH) & 3u;
+        ct = (uint32_t)(word >> n::CT_SH) & 3u;
+        bc = (uint32_t)(word >> n::BC_SH) & 63u;
+        wc = (uint32_t)(word >> n::WC_SH) & 15u;
+        tc = (uint32_t)(word >> n::TC_SH) & 15u;
+        th = (uint32_t)(word >> n::TH_SH) & 1023u;
+        if (tag > hr::T_MTI) return HR_E_INVAL;
+        if (tag >= hr::T_MB) d.launch = (uint32_t)(word >> n::LA_SH) & 511u;
+        if (tag >= hr::T_MW) d.block = (uint32_t)(word >> n::BL_SH) & (n::BLOCK_LIMIT - 1);
+    } else {
+        namespace nl = hr::nl;
+        const uint32_t w = (uint32_t)word;
+        tag = w & nl::TAG_M;
+        cb = (w >> nl::CB_SH) & 3u;
+        cw = (w >> nl::CW_SH) & 3u;
+        ct = (w >> nl::CT_SH) & 3u;
+        bc = (w >> nl::BC_SH) & 31u;
+        wc = (w >> nl::WC_SH) & 15u;
+        tc = (w >> nl::TC_SH) & 15u;
+        th = (w >> nl::TH_SH) & 1023u;
+        if (tag > hr::T_MTI || tag == hr::T_MB) return HR_E_INVAL;
+    }
+    // Tag order of the nested machine, from the widest group down: MB
+    // (blocks), MW (waves), MTI (tiles of one wave), MT (threads of one
+    // tile), ST (one thread).
+    const bool mw = tag == hr::T_MW, mti = tag == hr::T_MTI, mt = tag == hr::T_MT,
+               st = tag == hr::T_ST;
+    d.state = mti ? (uint32_t)HR_S_TILES : tag;
+    if (tag == hr::T_MB) d.class_block = cb;
+    if (mw || mti || mt || st) {
+        d.class_launch = cl;
+        d.class_block = cb;
+        d.bc = bc;
+    }
+    if (mti || mt || st) {
+        d.class_wave = cw;
+        d.wave = th >> 6;
+        d.wc = wc;
+    }
+    if (mt || st) {
+        d.class_tile = ct;
+        d.tile = th >> tile_bits;
+        d.tc = tc;
+    }
+    if (st) d.thread = th;
+    *out = d;
+    return HR_OK;
+}
+
 static bool word4_widths(uint32_t* wc_bits, uint32_t* bc_bits, uint32_t* thread_bits)
 {
     if (*wc_bits == 0) *wc_bits = 1;

@@ -24,7 +24,7 @@ HR_W_FOLDED = 32
 HR_W_LOG_TRUNCATED = 64
 HR_W_PARTIAL_BARRIER = 128
 HR_RACE_FOLD, HR_RACE_SCANNED = 1, 2
-HR_S_INIT, HR_S_RACE, HR_S_BLOCKS, HR_S_WAVES, HR_S_THREADS, HR_S_THREAD = range(6)
+HR_S_INIT, HR_S_RACE, HR_S_BLOCKS, HR_S_WAVES, HR_S_THREADS, HR_S_THREAD, HR_S_TILES = range(7)
 HR_E_INVAL, HR_E_NOMEM, HR_E_HIP, HR_E_STATE = -1, -2, -3, -4
 HR_GLOBAL, HR_LDS = 0, 1
 HR_READ, HR_WRITE, HR_ATOMIC = 0, 1, 2
@@ -96,6 +96,17 @@ class Summary(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class SummaryNested(ctypes.Structure):
+    """hr_summary_nested: a decoded summary of a context with tiles nested
+    in waves (UINT32_MAX: field not kept)."""
+    _fields_ = [(f, ctypes.c_uint32) for f in
+                ("state", "class_launch", "class_block", "class_wave", "class_tile", "launch",
+                 "block", "bc", "wave", "wc", "tile", "tc", "thread")]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class Instance(ctypes.Structure):
     """hr_instance: one checked job of a batch (see include/hr.h)."""
     _fields_ = [("pattern", ctypes.c_uint32), ("blocks", ctypes.c_uint32),
@@ -161,6 +172,7 @@ def _load():
         "hr_fsm_step_nested": [u32, u64, u32, u32, u32, u32, u32, u32, u32, u32, P],
         "hr_fsm_merge_nested": [u64, u64, u32, P],
         "hr_describe": [u32, u64, u32, P],
+        "hr_describe_nested": [u32, u64, u32, P],
         "hr_fsm_step_word4": [u32, u32, u32, u32, u32, u32, u32, u32, u32, u32, P],
         "hr_word4_widen": [u32, u32, u32, u32, P],
         "hr_reduce_check": [P, u32, u32, P, P, u32, u32, u32, ctypes.c_int32, P],
@@ -198,7 +210,7 @@ EXPORTED = ("hr_ctx_create", "hr_ctx_destroy", "hr_shadow_alloc", "hr_shadow_all
             "hr_kernel_end", "hr_reset", "hr_report", "hr_check_count", "hr_access_log",
             "hr_fsm_step", "hr_fsm_step_table", "hr_fsm_merge", "hr_fsm_step_nested",
             "hr_fsm_merge_nested",
-            "hr_describe", "hr_fsm_step_word4", "hr_word4_widen",
+            "hr_describe", "hr_describe_nested", "hr_fsm_step_word4", "hr_word4_widen",
             "hr_reduce_check", "hr_reduce_plain", "hr_jacobi_check", "hr_jacobi_plain",
             "hr_labelprop_check", "hr_labelprop_plain", "hr_program_check",
             "hr_peak_copy", "hr_peak_atomic", "hr_peak_load", "hr_peak_lds")
@@ -268,6 +280,15 @@ def describe(space: int, word: int, wave_bits: int = 6) -> dict:
     """Decode a shadow summary word (a race record's `before` or `with`)."""
     out = Summary()
     _check("hr_describe", _lib.hr_describe(space, word, wave_bits, ctypes.byref(out)))
+    return out.as_dict()
+
+
+def describe_nested(space: int, word: int, tile_bits: int) -> dict:
+    """Decode a shadow summary word of a context with tiles of 2**tile_bits
+    lanes nested in waves."""
+    out = SummaryNested()
+    _check("hr_describe_nested", _lib.hr_describe_nested(space, word, tile_bits,
+                                                         ctypes.byref(out)))
     return out.as_dict()
 
 

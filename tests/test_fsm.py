@@ -394,6 +394,118 @@ def test_nested_merge_is_the_summary_of_the_union():
     assert checked > 100
 
 
+def test_describe_nested_decodes_each_summary_state():
+    """hr_describe_nested against summaries the nested machine builds, tiles
+    of 4 lanes (tile_bits 2) nested in 64-lane waves."""
+    G, L = hr.HR_GLOBAL, hr.HR_LDS
+    R, W, A = hr.HR_READ, hr.HR_WRITE, hr.HR_ATOMIC
+    none = 0xFFFFFFFF
+
+    def step(sp, old, kind, launch, block, thread, bc, wc, tc):
+        return hr.fsm_step_nested(sp, old, kind, launch, block, thread, bc, wc, tc, 2)
+
+    st = step(G, 0, R, 3, 5, 70, 2, 1, 4)                # one thread: wave 1, tile 17
+    d = hr.describe_nested(G, st, 2)
+    assert d == {"state": hr.HR_S_THREAD, "class_launch": 1, "class_block": 1, "class_wave": 1,
+                 "class_tile": 1, "launch": 3, "block": 5, "bc": 2, "wave": 1, "wc": 1,
+                 "tile": 17, "tc": 4, "thread": 70}
+    mt = step(G, st, R, 3, 5, 71, 2, 1, 4)               # another thread of that tile
+    d = hr.describe_nested(G, mt, 2)
+    assert d["state"] == hr.HR_S_THREADS and d["thread"] == none
+    assert (d["tile"], d["tc"], d["class_tile"], d["wave"], d["wc"]) == (17, 4, 1, 1, 1)
+    mti = step(G, mt, R, 3, 5, 75, 2, 1, 0)              # another tile of that wave
+    d = hr.describe_nested(G, mti, 2)
+    assert d["state"] == hr.HR_S_TILES and d["tile"] == none and d["tc"] == none
+    assert (d["wave"], d["wc"], d["class_wave"], d["block"], d["bc"]) == (1, 1, 1, 5, 2)
+    assert d["class_tile"] == 0
+    # a write from yet another tile of the wave in that wave epoch races
+    assert hr.describe_nested(G, step(G, mti, W, 3, 5, 80, 2, 1, 0), 2)["state"] == hr.HR_S_RACE
+    mw = step(G, mti, R, 3, 5, 200, 2, 0, 0)             # another wave of the block
+    d = hr.describe_nested(G, mw, 2)
+    assert d["state"] == hr.HR_S_WAVES and d["wave"] == none and d["wc"] == none
+    assert (d["class_block"], d["class_wave"], d["block"], d["bc"]) == (1, 0, 5, 2)
+    mb = step(G, mw, R, 3, 6, 0, 0, 0, 0)                # another block
+    d = hr.describe_nested(G, mb, 2)
+    assert d["state"] == hr.HR_S_BLOCKS and d["block"] == none and d["bc"] == none
+    assert (d["launch"], d["class_block"]) == (3, 1)
+    t2 = step(G, st, A, 3, 5, 70, 2, 1, 5)               # same thread, later tile epoch
+    d = hr.describe_nested(G, t2, 2)
+    assert (d["state"], d["class_tile"], d["class_wave"], d["tc"]) == (hr.HR_S_THREAD, 2, 3, 5)
+    assert hr.describe_nested(G, 0, 2)["state"] == hr.HR_S_INIT
+    # the same thread index splits into another tile number at another width
+    assert hr.describe_nested(G, st, 4)["tile"] == 70 >> 4
+    # LDS words carry no launch, block or launch class
+    ls = step(L, 0, W, 0, 0, 130, 4, 2, 3)
+    d = hr.describe_nested(L, ls, 2)
+    assert (d["state"], d["thread"], d["bc"], d["wc"], d["wave"], d["tile"], d["tc"]) == \
+        (hr.HR_S_THREAD, 130, 4, 2, 2, 32, 3)
+    assert d["launch"] == none and d["block"] == none and d["class_launch"] == 0
+    lt = step(L, step(L, 0, R, 0, 0, 1, 0, 0, 0), R, 0, 0, 5, 0, 0, 0)
+    d = hr.describe_nested(L, lt, 2)
+    assert (d["state"], d["wave"], d["class_wave"]) == (hr.HR_S_TILES, 0, 1)
+    for bad in ((L, mb & 7, 2), (G, 7, 2), (G, st, 0), (G, st, 6), (2, st, 2)):
+        with pytest.raises(hr.HRError):
+            hr.describe_nested(*bad)
+
+
+def _host_records_nested(log, order, tile_bits):
+    """Race records of the nested machine as the hook would make them,
+    replaying `order` on the host."""
+    words, recs = {}, []
+    for i in order:
+        r = log[i]
+        sp, rg, ix = int(r["space"]), int(r["region"]), int(r["index"])
+        b, t, L = int(r["block"]), int(r["thread"]), int(r["launch"])
+        wkey = (1, rg, b, ix, L) if sp == hr.HR_LDS else (0, rg, 0, ix)
+        old = words.get(wkey, 0)
+        args = (int(r["kind"]), L & 511 if sp == hr.HR_GLOBAL else 0, b, t, int(r["bc"]),
+                int(r["wc"]), int(r["tc"]), tile_bits)
+        new = hr.fsm_step_nested(sp, old, *args)
+        words[wkey] = new
+        if (new & 7) == hr.T_RACE and (old & 7) != hr.T_RACE:
+            rec = np.zeros(1, dtype=hr.RACE_DTYPE)[0]
+            rec["space"], rec["kind"], rec["region"] = sp, int(r["kind"]), rg
+            rec["block"], rec["launch"], rec["index"], rec["tid"] = b, L, ix, t
+            rec["before"] = old
+            rec["with"] = hr.fsm_step_nested(sp, 0, *args)
+            recs.append(rec)
+    return recs
+
+
+def test_nested_record_check_accepts_host_records_and_rejects_planted():
+    """The record validity check in its nested form accepts every record a
+    host replay of the nested machine makes, on programs mixing block, wave
+    and tile barriers, and rejects each with a planted mistake (another
+    thread as the completing access, an empty history, another kind)."""
+    from fsm_replay import random_orders_nested
+    from race_records import by_key, record_key, record_problem
+    checked = rejected = 0
+    for s in range(40):
+        tw = (2, 4)[s % 2]
+        tb = tw.bit_length() - 1
+        prog = si.random_program(5231 * s + 3, launches=2, blocks=2, threads=8, phases=4,
+                                 max_ops=2, global_regions=2, global_words=3, lds_words=2,
+                                 kind_p=(0.5, 0.25, 0.25), scope_p=(0.2, 0.2, 0.15, 0.45),
+                                 tile_width=tw)
+        log = oracle.model_program(prog, 64, tw)
+        keys = by_key(log)
+        for order in random_orders_nested(log, 3, seed=s, tile_width=tw):
+            for rec in _host_records_nested(log, order, tb):
+                k = keys[record_key(rec)]
+                assert record_problem(rec, k, wave_bits=tb, nested=True) is None, (s, rec)
+                checked += 1
+                bad = rec.copy()
+                bad["tid"] = int(rec["tid"]) ^ 1
+                rejected += record_problem(bad, k, wave_bits=tb, nested=True) is not None
+                bad = rec.copy()
+                bad["before"] = 0
+                rejected += record_problem(bad, k, wave_bits=tb, nested=True) is not None
+                bad = rec.copy()
+                bad["kind"] = (int(rec["kind"]) + 1) % 3
+                rejected += record_problem(bad, k, wave_bits=tb, nested=True) is not None
+    assert checked > 50 and rejected == 3 * checked
+
+
 def test_flat_table_equals_bit_logic():
     """The flat-table transition (HR_CFG_FSM_TABLE, built at compile time
     from the bit logic) equals the bit logic on every word: all eight tags

@@ -122,6 +122,42 @@ def test_nested_access_log(env, cfg):
     assert dev.shape == ora.shape and np.array_equal(dev, ora)
 
 
+@pytest.mark.parametrize("cfg", NESTED, ids=lambda c: f"seed{c[0]}")
+def test_nested_records_name_racing_pairs(env, cfg):
+    """Race records of a nested context: `before` and `with`, decoded in the
+    nested layout (hr_describe_nested), hold a pair of the oracle's log at
+    the record's key that races with tiles nested in waves, and `with` is
+    the completing access alone (thread, block, class in its tile epoch)."""
+    from race_records import by_key, record_key, record_problem
+    torch, hr = env
+    seed, blocks, threads, tile, phases, max_ops, gw, lw, p_lds = cfg
+    prog = si.random_program(9000 + seed, launches=2, blocks=blocks, threads=threads,
+                             phases=phases, max_ops=max_ops, global_regions=2, global_words=gw,
+                             lds_words=lw, p_lds=p_lds, kind_p=(0.55, 0.2, 0.25),
+                             scope_p=(0.2, 0.2, 0.15, 0.45), tile_width=tile)
+    log = oracle.model_program(prog, 64, tile)
+    want = oracle.flagged(log.copy(), 64, tile)
+    tb = tile.bit_length() - 1
+    say("nested records", cfg, "oracle flags", len(want))
+    data = [torch.zeros(w, dtype=torch.int32, device="cuda") for w in prog.global_words]
+    with hr.Context(nested_tiles=True, wave_bits=tb) as ctx:
+        regs = [ctx.shadow_alloc(d) for d in data]
+        for launch in prog.launches:
+            ctx.program_check(hr.DeviceProgram(launch), regs, prog.lds_words)
+            ctx.kernel_end()
+        recs, st = ctx.report()
+    assert st == 0 and len(recs) == len(want)
+    keys = by_key(log)
+    region_map = {r: i for i, r in enumerate(regs)}
+    seen = set()
+    for rec in recs:
+        k = record_key(rec, region_map)
+        why = record_problem(rec, keys[k], wave_bits=tb, nested=True)
+        assert why is None, (k, why, rec)
+        seen.add(k)
+    assert seen == want
+
+
 def test_nested_mode_limits(env):
     torch, hr = env
     with pytest.raises(hr.HRError):
