@@ -10,6 +10,11 @@ hook.  One step is one whole checking job on resident inputs: reset the
 shadow, 20 instrumented launches with their launch boundaries, and the
 report (device-to-host copy of the flagged set).
 
+The timed jobs record one pair of HIP events around each job's launches
+(the mean launch time of the roofline) and none between them; the per-launch
+latency percentiles come from the same number of jobs run right after, with
+a pair around every launch.
+
 Prints one JSON line: checks/s, slowdown against the same kernel without
 hooks, p50/p99 per-launch latency, the roofline of the instrumented kernel,
 measured device peaks, and the CPU oracle timed on the same records (launch
@@ -226,30 +231,81 @@ def measure_peaks(torch, hr, stream):
     return out
 
 
-def _timed_job(args, torch, stream, job, launches):
-    """Warm up, then time `steps` whole jobs; per-launch HIP events."""
+class Timing:
+    """HIP events on the launch stream.  per_launch: a pair around every
+    launch, for the per-launch latency percentiles; each pair leaves the
+    device idle for a few microseconds between launches.  Otherwise one pair
+    around all the launches of a job (end() after its last launch), so that
+    the timed jobs run their launches back to back as a caller's would."""
+
+    def __init__(self, torch, stream, per_launch):
+        self.torch, self.stream, self.per_launch = torch, stream, per_launch
+        self.pairs, self.counts = [], []
+        self._first, self._n = None, 0
+
+    def _event(self):
+        e = self.torch.cuda.Event(enable_timing=True)
+        e.record(self.stream)
+        return e
+
+    def launch(self, fn):
+        if self.per_launch:
+            e0 = self._event()
+            fn()
+            self.pairs.append((e0, self._event()))
+            self.counts.append(1)
+            return
+        if self._first is None:
+            self._first = self._event()
+        fn()
+        self._n += 1
+
+    def end(self):
+        if self._first is not None:
+            self.pairs.append((self._first, self._event()))
+            self.counts.append(self._n)
+            self._first, self._n = None, 0
+
+    def ms(self):
+        """Per pair: one launch (per_launch), or one job's launches."""
+        return [a.elapsed_time(b) for a, b in self.pairs]
+
+    def mean_launch_ms(self):
+        return sum(self.ms()) / max(1, sum(self.counts))
+
+
+def _timed_launch(timing, fn):
+    if timing is None:
+        fn()
+    else:
+        timing.launch(fn)
+
+
+def _end_launches(timing):
+    if timing is not None:
+        timing.end()
+
+
+def _timed_job(args, torch, stream, job):
+    """Warm up, then time `steps` whole jobs with one event pair around each
+    job's launches; then run `steps` more with a pair around every launch for
+    the latency percentiles.  Returns (seconds per job, mean launch ms of the
+    timed jobs, per-launch ms, the last timed job's result)."""
     for _ in range(args.warmup):
         job(None)
     torch.cuda.synchronize()
-    ev = []
+    span = Timing(torch, stream, per_launch=False)
     t0 = time.perf_counter()
     out = None
     for _ in range(args.steps):
-        out = job(ev)
+        out = job(span)
     torch.cuda.synchronize()
     step_s = (time.perf_counter() - t0) / args.steps
-    return step_s, [a.elapsed_time(b) for a, b in ev], out
-
-
-def _launch_events(torch, stream, events, fn):
-    if events is None:
-        fn()
-        return
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    fn()
-    e1.record(stream)
-    events.append((e0, e1))
+    each = Timing(torch, stream, per_launch=True)
+    for _ in range(args.steps):
+        job(each)
+    torch.cuda.synchronize()
+    return step_s, span.mean_launch_ms(), each.ms(), out
 
 
 def _common(args, metric_value, step_s, launch_ms, plain_ms, plain_step_s, workload, extra):
@@ -282,18 +338,20 @@ def bench_labelprop(args, torch, si, hr, stream):
         ctx.reset()
         label.copy_(init)
         for _ in range(launches):
-            _launch_events(torch, stream, ev, lambda: ctx.labelprop_check(
+            _timed_launch(ev, lambda: ctx.labelprop_check(
                 r_lab, label, rp_d, col_d, mask_d, tpb=tpb))
             ctx.kernel_end()
+        _end_launches(ev)
         return ctx.report()
 
     def plain(ev):
         label.copy_(init)
         for _ in range(launches):
-            _launch_events(torch, stream, ev, lambda: hr.labelprop_plain(label, rp_d, col_d, mask_d, tpb))
+            _timed_launch(ev, lambda: hr.labelprop_plain(label, rp_d, col_d, mask_d, tpb))
+        _end_launches(ev)
 
-    step_s, launch_ms, (recs, st) = _timed_job(args, torch, stream, job, launches)
-    pstep_s, plain_ms, _ = _timed_job(args, torch, stream, plain, launches)
+    step_s, avg_ms, launch_ms, (recs, st) = _timed_job(args, torch, stream, job)
+    pstep_s, _, plain_ms, _ = _timed_job(args, torch, stream, plain)
     ctx.close()
     assert st == 0
     res = _common(args, checks_per_launch * launches / step_s, step_s, launch_ms, plain_ms,
@@ -304,7 +362,7 @@ def bench_labelprop(args, torch, si, hr, stream):
     # vertex, col + mask + label min per edge) plus one 8-byte shadow load per
     # check; the shadow words themselves change only a few times per launch
     alg = n * (8 + 4) + edges * (4 + 1 + 4) + checks_per_launch * 8 + n * 16
-    avg = float(np.mean(launch_ms)) * 1e-3
+    avg = avg_ms * 1e-3
     res["flagged"] = int(len(recs))
     res["roofline"] = {"bound": "hbm", "achieved": alg / avg / 1e9, "peak": HBM_PEAK_GBS,
                        "unit": "GB/s", "frac": alg / avg / 1e9 / HBM_PEAK_GBS,
@@ -326,16 +384,18 @@ def bench_reduce(args, torch, si, hr, stream):
     def job(ev):
         ctx.reset()
         for _ in range(reps):
-            _launch_events(torch, stream, ev, lambda: ctx.reduce_check(r_in, r_out, x, out, 3))
+            _timed_launch(ev, lambda: ctx.reduce_check(r_in, r_out, x, out, 3))
             ctx.kernel_end()
+        _end_launches(ev)
         return ctx.report()
 
     def plain(ev):
         for _ in range(reps):
-            _launch_events(torch, stream, ev, lambda: hr.reduce_plain(x, out, 3))
+            _timed_launch(ev, lambda: hr.reduce_plain(x, out, 3))
+        _end_launches(ev)
 
-    step_s, launch_ms, (recs, st) = _timed_job(args, torch, stream, job, reps)
-    pstep_s, plain_ms, _ = _timed_job(args, torch, stream, plain, reps)
+    step_s, _, launch_ms, (recs, st) = _timed_job(args, torch, stream, job)
+    pstep_s, _, plain_ms, _ = _timed_job(args, torch, stream, plain)
     ctx.close()
     res = _common(args, 3069 * reps / step_s, step_s, launch_ms, plain_ms, pstep_s,
                   "reduce_lds_int32x512_1block256_drop3", {"launches_per_step": reps,
@@ -372,10 +432,11 @@ def bench_batched(args, torch, si, hr, stream):
 
     def job(ev):
         ctx.reset()
-        _launch_events(torch, stream, ev, lambda: batch.run(**best))
+        _timed_launch(ev, lambda: batch.run(**best))
+        _end_launches(ev)
         return ctx.report()
 
-    step_s, launch_ms, (recs, st) = _timed_job(args, torch, stream, job, 1)
+    step_s, _, launch_ms, (recs, st) = _timed_job(args, torch, stream, job)
     assert st == 0
     per_batch = batch.split({(int(r["space"]), int(r["region"]),
                               int(r["block"]) if r["space"] == hr.HR_LDS else 0, int(r["index"]))
@@ -571,92 +632,48 @@ def main():
     ctx = hr.Context()
     regs = [ctx.shadow_alloc(u[0]), ctx.shadow_alloc(u[1])]
 
-    def checked_step(events, c=ctx, rg=regs, end_events=None):
+    def checked_step(timing, c=ctx, rg=regs, clears=None):
         c.reset()
         for L in range(LAUNCHES):
-            if events is not None:
-                e0 = torch.cuda.Event(enable_timing=True)
-                e1 = torch.cuda.Event(enable_timing=True)
-                e0.record(stream)
-            c.jacobi_check(rg[L % 2], rg[(L + 1) % 2], u[L % 2], u[(L + 1) % 2], tab)
-            if events is not None:
-                e1.record(stream)
-                events.append((e0, e1))
-            if end_events is not None:
-                e2 = torch.cuda.Event(enable_timing=True)
-                e2.record(stream)
-            c.kernel_end()
-            if end_events is not None:
-                e3 = torch.cuda.Event(enable_timing=True)
-                e3.record(stream)
-                end_events.append((e2, e3))
-        recs, st = c.report()
-        return recs, st
+            _timed_launch(timing, lambda: c.jacobi_check(rg[L % 2], rg[(L + 1) % 2], u[L % 2],
+                                                         u[(L + 1) % 2], tab))
+            if clears is None:
+                c.kernel_end()
+            else:
+                clears.launch(c.kernel_end)      # the 4-byte words' boundary clears
+        _end_launches(timing)
+        return c.report()
 
-    def plain_step(events):
+    def plain_step(timing):
         for L in range(LAUNCHES):
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            hr.jacobi_plain(u[L % 2], u[(L + 1) % 2], tab)
-            e1.record(stream)
-            events.append((e0, e1))
+            _timed_launch(timing, lambda: hr.jacobi_plain(u[L % 2], u[(L + 1) % 2], tab))
+        _end_launches(timing)
 
-    for _ in range(args.warmup):
-        checked_step(None)
-    torch.cuda.synchronize()
-    ev = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        recs, st = checked_step(ev)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    launch_ms = [a.elapsed_time(b) for a, b in ev]
-    step_s = (t1 - t0) / args.steps
+    step_s, avg_launch_ms, launch_ms, (recs, st) = _timed_job(args, torch, stream, checked_step)
     flagged_count = len(recs)
     assert st == 0 and flagged_count > 0
-
-    pev = []
-    for _ in range(max(1, args.warmup)):
-        plain_step([])
-    torch.cuda.synchronize()
-    tp0 = time.perf_counter()
-    for _ in range(args.steps):
-        plain_step(pev)
-    torch.cuda.synchronize()
-    tp1 = time.perf_counter()
-    plain_ms = [a.elapsed_time(b) for a, b in pev]
+    pstep_s, _, plain_ms, _ = _timed_job(args, torch, stream, plain_step)
     ctx.close()
-    ev.clear()                  # release the timing events before the next leg
-    pev.clear()
 
     # The same job with 4-byte shadow words (default widths: 16-bit block
     # field, exact for these 65,536 blocks); the launch-boundary clear of
     # its shadow is timed on its own.
     ctx4 = hr.Context(word4=True)
     regs4 = [ctx4.shadow_alloc(u[0]), ctx4.shadow_alloc(u[1])]
-    for _ in range(args.warmup):
-        checked_step(None, ctx4, regs4)
+    step4_s, _, launch4_ms, (recs4, st4) = _timed_job(
+        args, torch, stream, lambda t: checked_step(t, ctx4, regs4))
+    clears = Timing(torch, stream, per_launch=True)
+    for _ in range(2):
+        checked_step(None, ctx4, regs4, clears)
     torch.cuda.synchronize()
-    ev4, cev4 = [], []
-    t40 = time.perf_counter()
-    for _ in range(args.steps):
-        recs4, st4 = checked_step(ev4, ctx4, regs4)
-    torch.cuda.synchronize()
-    t41 = time.perf_counter()
-    for _ in range(2):                       # the clears, timed apart from the steps
-        checked_step(None, ctx4, regs4, cev4)
-    torch.cuda.synchronize()
+    clear4_ms = clears.ms()
+    del clears
     ctx4.close()
 
     def keys(rs):
         return {(int(r["space"]), int(r["region"]), int(r["block"]) if r["space"] else 0,
                  int(r["index"])) for r in rs}
     assert st4 == 0 and keys(recs4) == keys(recs)
-    launch4_ms = [a.elapsed_time(b) for a, b in ev4]
-    clear4_ms = [a.elapsed_time(b) for a, b in cev4]
-    ev4.clear()
-    cev4.clear()
 
     # The same job under each shadow map and transition encoding the
     # autotuner knows (tune.autotune_stencil): per-launch time and the
@@ -669,7 +686,7 @@ def main():
     head_set = {(sp, remap[rg] if sp == 0 else rg, lb, ix) for sp, rg, lb, ix in keys(recs)}
     map_same = fsm_same = tuned_set == head_set
 
-    avg_launch_s = float(np.mean(launch_ms)) * 1e-3
+    avg_launch_s = avg_launch_ms * 1e-3
     alg = algorithmic_bytes_per_launch(NY, NX)
     achieved = alg / avg_launch_s / 1e9
     with_data = alg + data_bytes_per_launch(NY, NX)
@@ -692,7 +709,7 @@ def main():
                    "global_checks_per_launch": int(n_g), "lds_checks_per_launch": int(n_l),
                    "parallelism": "single GPU"},
         "slowdown": float(np.median(launch_ms) / np.median(plain_ms)),
-        "slowdown_step": step_s / ((tp1 - tp0) / args.steps),
+        "slowdown_step": step_s / pstep_s,
         "p50_launch_ms": pct(launch_ms, 50),
         "p99_launch_ms": pct(launch_ms, 99),
         "plain_p50_launch_ms": pct(plain_ms, 50),
@@ -708,7 +725,6 @@ def main():
                          "achieved": with_data / avg_launch_s / 1e9,
                          "frac": with_data / avg_launch_s / 1e9 / HBM_PEAK_GBS}},
     }
-    step4_s = (t41 - t40) / args.steps
     result["word4"] = {"value": checks_per_step / step4_s, "unit": "checks/s",
                        "ms_per_step": step4_s * 1e3,
                        "p50_launch_ms": pct(launch4_ms, 50), "p99_launch_ms": pct(launch4_ms, 99),
