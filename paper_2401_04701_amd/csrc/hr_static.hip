@@ -128,7 +128,10 @@ extern "C" hr_status hr_job_run_static(const hr_instance* inst, const hr_config*
     int warn = 0;
     if (flags & HR_DEVF_CLOCK) warn |= HR_W_CLOCK_OVERFLOW;
     if (flags & HR_DEVF_RANGE) warn |= HR_W_OUT_OF_RANGE;
+    if (flags & HR_DEVF_STALL) warn |= HR_W_STALLED;
     if (flags & HR_DEVF_LIMIT) warn |= HR_W_REPORT_LIMITED;
+    if (flags & HR_DEVF_FOLD) warn |= HR_W_FOLDED;
+    if (flags & HR_DEVF_MASK) warn |= HR_W_PARTIAL_BARRIER;
     if (head > k.ring_capacity) warn |= HR_W_RING_OVERFLOW;
     const size_t n_ring = std::min(head, k.ring_capacity);
     const bool scan = head > k.ring_capacity || (flags & HR_DEVF_LIMIT);
