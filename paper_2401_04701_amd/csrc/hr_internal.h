@@ -36,8 +36,9 @@ struct hr_ctx_s {
     hr_config cfg;
     std::vector<hr_alloc> allocs;
     std::vector<hr_region> reg;      // region ids index this vector; never reused
-    hr_race_rec* ring;
-    uint32_t* ctr;
+    uint32_t* ctr;                   // counters, then (at HR_CTR_BYTES) the ring:
+    hr_race_rec* ring;               // one allocation, so one copy reads both
+    uint32_t last_head = 0;          // records the last report read
     unsigned long long* count;       // HR_COUNT_SLOTS debug counters
     hr_access_rec* log;              // access log (HR_CFG_ACCESS_LOG), or null
     uint16_t* fsm_tab;               // flat transition table (HR_CFG_FSM_TABLE), or null
@@ -45,6 +46,10 @@ struct hr_ctx_s {
     uint64_t shadow_bytes;           // live shadow memory
     std::vector<hr_race> carried;    // global races recovered before a shadow clear
 };
+
+// Bytes of the counter words at the start of a context's counter-and-ring
+// allocation (the ring follows, 256-byte aligned).
+constexpr size_t HR_CTR_BYTES = (HR_CTR_WORDS * sizeof(uint32_t) + 255) / 256 * 256;
 
 hipStream_t hr_stream(hr_ctx c, void* stream);
 // A coalescing width: a power of two in 2..64.

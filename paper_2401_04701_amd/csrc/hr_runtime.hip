@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstring>
 #include <new>
 #include <vector>
 
@@ -302,9 +303,13 @@ extern "C" hr_status hr_ctx_create(hr_ctx* out, const hr_config* cfg, void* stre
         delete c;
         return HR_E_HIP;
     }
-    if (hipMalloc(&c->ring, sizeof(hr_race_rec) * (size_t)k.ring_capacity) != hipSuccess ||
-        hipMalloc(&c->ctr, sizeof(uint32_t) * HR_CTR_WORDS) != hipSuccess ||
-        hipMalloc(&c->count, sizeof(unsigned long long) * HR_COUNT_SLOTS) != hipSuccess ||
+    if (hipMalloc(&c->ctr, HR_CTR_BYTES + sizeof(hr_race_rec) * (size_t)k.ring_capacity) !=
+        hipSuccess) {
+        hr_ctx_destroy(c);
+        return HR_E_NOMEM;
+    }
+    c->ring = (hr_race_rec*)((uint8_t*)c->ctr + HR_CTR_BYTES);
+    if (hipMalloc(&c->count, sizeof(unsigned long long) * HR_COUNT_SLOTS) != hipSuccess ||
         ((k.flags & HR_CFG_ACCESS_LOG) &&
          hipMalloc(&c->log, sizeof(hr_access_rec) * (size_t)k.log_capacity) != hipSuccess) ||
         ((k.flags & HR_CFG_FSM_TABLE) && hipMalloc(&c->fsm_tab, sizeof(FSM_TABLE)) != hipSuccess)) {
@@ -331,8 +336,7 @@ extern "C" hr_status hr_ctx_destroy(hr_ctx c)
     hipError_t e = hipStreamSynchronize(c->stream);
     for (hr_alloc& al : c->allocs)
         if (al.live) (void)hipFree(al.mem);
-    if (c->ring) (void)hipFree(c->ring);
-    if (c->ctr) (void)hipFree(c->ctr);
+    if (c->ctr) (void)hipFree(c->ctr);   // the ring's memory too
     if (c->count) (void)hipFree(c->count);
     if (c->log) (void)hipFree(c->log);
     if (c->fsm_tab) (void)hipFree(c->fsm_tab);
@@ -500,14 +504,25 @@ extern "C" hr_status hr_report(hr_ctx c, hr_race* out, size_t cap, size_t* n_out
 {
     if (!c || !n_out) return HR_E_INVAL;
     hipStream_t s = hr_stream(c, stream);
-    if (hipStreamSynchronize(s) != hipSuccess) return HR_E_HIP;
+    // One copy, after the stream's work, reads the counters and as many ring
+    // records as the last report found (at least 64); a second copy reads
+    // the rest when there are more.
+    const uint32_t pre = std::min(c->cfg.ring_capacity, std::max(64u, c->last_head));
+    std::vector<uint8_t> buf(HR_CTR_BYTES + sizeof(hr_race_rec) * (size_t)pre);
+    if (hipMemcpyAsync(buf.data(), c->ctr, buf.size(), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return HR_E_HIP;
     uint32_t ctr[HR_CTR_SITES];
-    if (hipMemcpy(ctr, c->ctr, sizeof(ctr), hipMemcpyDeviceToHost) != hipSuccess) return HR_E_HIP;
+    std::memcpy(ctr, buf.data(), sizeof(ctr));
     const uint32_t head = ctr[HR_CTR_HEAD];
     const uint32_t n_ring = std::min(head, c->cfg.ring_capacity);
+    c->last_head = n_ring;
     std::vector<hr_race> recs(n_ring);
-    if (n_ring &&
-        hipMemcpy(recs.data(), c->ring, sizeof(hr_race) * n_ring, hipMemcpyDeviceToHost) != hipSuccess)
+    const uint32_t have = std::min(n_ring, pre);
+    if (have) std::memcpy(recs.data(), buf.data() + HR_CTR_BYTES, sizeof(hr_race) * have);
+    if (n_ring > have &&
+        hipMemcpy(recs.data() + have, c->ring + have, sizeof(hr_race) * (n_ring - have),
+                  hipMemcpyDeviceToHost) != hipSuccess)
         return HR_E_HIP;
     int warn = 0;
     if (ctr[HR_CTR_FLAGS] & HR_DEVF_CLOCK) warn |= HR_W_CLOCK_OVERFLOW;
