@@ -64,12 +64,15 @@ def _expand(launch, narrow, tiles=False, nested=0):
 STATS = {"folds": 0, "fold_rounds": 0}
 
 
-def simulate(program, narrow: int, seed: int, tiles: bool = False, nested: int = 0):
+def simulate(program, narrow: int, seed: int, tiles: bool = False, nested: int = 0,
+             blind: float = 0.0):
     """tiles: the checker synchronizes tiles of `narrow` lanes (wave_bits =
     log2 narrow) instead of relabelling them onto 64-lane waves.  nested: a
     tile width; the nested machine (hr_fsm_step_nested / hr_fsm_merge_nested)
     with tiles of that many lanes inside 64-lane waves, each level with its
-    own barriers and clock."""
+    own barriers and clock.  blind: the probability that a global hook
+    skips its load and steps from the initial word instead (the blind
+    exchange: publish the access alone, then fold back what it replaced)."""
     rng = np.random.default_rng(seed)
     wb = int(narrow).bit_length() - 1 if tiles else 6
     if nested:
@@ -110,7 +113,8 @@ def simulate(program, narrow: int, seed: int, tiles: bool = False, nested: int =
                 assert all(th.pc == len(th.ops) for th in ths), "barrier deadlock"
                 break
             th = runnable[int(rng.integers(0, len(runnable)))]
-            _micro_step(th, L, gwords, lwords, pushed, wb, bool(nested))
+            _micro_step(th, L, gwords, lwords, pushed, wb, bool(nested),
+                        blind > 0 and rng.random() < blind)
     return pushed, gwords
 
 
@@ -128,16 +132,16 @@ def _merge(x, y, wb, nested):
     return hr.fsm_merge_nested(x, y, wb) if nested else hr.fsm_merge(x, y, wb)
 
 
-def _micro_step(th, L, gwords, lwords, pushed, wb=6, nested=False):
+def _micro_step(th, L, gwords, lwords, pushed, wb=6, nested=False, blind=False):
     if th.hook is None:
         _, space, region, index, kind = th.ops[th.pc]
         th.hook = {"space": space, "region": region, "index": index, "kind": kind,
-                   "stage": "load"}
+                   "stage": "load", "blind": blind}
     h = th.hook
     if h["space"] == si.SPACE_GLOBAL:
         key = (0, h["region"], 0, h["index"])
         if h["stage"] == "load":
-            old = gwords.get(key, 0)
+            old = 0 if h["blind"] else gwords.get(key, 0)
             nw = _step(hr.HR_GLOBAL, old, h["kind"], L, th, wb, nested)
             if nw == old:
                 return _done(th)

@@ -49,6 +49,35 @@ def test_protocol_reports_oracle_set_under_any_schedule(setting):
     assert ps.STATS["folds"] > folds0, "schedules never exercised the fold-back path"
 
 
+@pytest.mark.parametrize("blind", [0.5, 1.0])
+@pytest.mark.parametrize("setting", SETTINGS[:4])
+def test_protocol_blind_exchanges_report_oracle_set(setting, blind):
+    """Global hooks that skip their load and publish the access alone (the
+    word a fresh location would get), then fold back the word the exchange
+    replaced: under any schedule the flagged set is still the oracle's.  The
+    merge keeps a newer block or wave epoch's detail over an older one of
+    the same block or wave, which makes a summary of everything before as
+    good a starting point as the current word."""
+    blocks, threads, ww, phases, max_ops, gw, lw, launches, kp = setting
+    folds0 = ps.STATS["folds"]
+    racy = 0
+    for s in range(20):
+        prog = si.random_program(7919 * s + 31 * blocks + threads, launches=launches,
+                                 blocks=blocks, threads=threads, phases=phases,
+                                 max_ops=max_ops, global_regions=1, global_words=gw,
+                                 lds_words=lw, kind_p=kp, scope_p=(0.4, 0.3, 0.3),
+                                 p_lds=0.2, wave_width=ww)
+        log = oracle.model_program(prog, ww)
+        want = oracle.flagged(log.copy(), ww)
+        for sched in range(20):
+            pushed, words = ps.simulate(prog, ww, seed=500 * s + sched, blind=blind)
+            assert set(pushed) == want, (setting, blind, s, sched)
+            race_words = {k for k, w in words.items() if w == ps.RACE}
+            assert race_words == {k for k in want if k[0] == 0}
+        racy += len(want)
+    assert racy > 0 and ps.STATS["folds"] > folds0
+
+
 def test_protocol_contended_single_location():
     """Many threads of several blocks, waves and epochs on one or two words:
     the exchange overwrites concurrent updates constantly."""
