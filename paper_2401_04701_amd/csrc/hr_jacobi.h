@@ -114,16 +114,16 @@ __device__ void jacobi_body(const hr_env& e, const G& gold, const G& gnew,
         // in flight.  (The staging hook comes before its store: the store
         // needs the loaded value, and waiting for it waits for the exchange
         // too.)
-        // The centre check on 8-byte words is blind: it steps from the
-        // initial word and exchanges without loading the word first, and
-        // the settle folds back the word the exchange replaced.  A word of
-        // an earlier launch adds nothing to that fold, and a neighbouring
-        // block's halo read of this launch merges in as another block's
-        // access, so the result is the loaded check's; the wave starts with
-        // one round trip instead of two.  (4-byte words load as before.)
-        constexpr bool BLIND = sizeof(typename G::word) == 8;
-        const typename G::pend pc = hr_gi<0, CHECK, BLIND>(e, th, gold, gold.at2(gy, gx, g),
-                                                             HR_SITE_JACOBI_CENTRE, 0);
+        // The centre check is blind: it steps from the initial word and
+        // exchanges without loading the word first, and the settle folds
+        // back the word the exchange replaced.  A word of an earlier launch
+        // (or, with 4-byte words, the cleared word) adds nothing to that
+        // fold, and a neighbouring block's halo read of this launch merges
+        // in as another block's access, so the result is the loaded check's;
+        // the wave starts with one round trip instead of two.  (The 4-byte
+        // merge is the 8-byte one on widened words.)
+        const typename G::pend pc = hr_gi<0, CHECK, true>(e, th, gold, gold.at2(gy, gx, g),
+                                                            HR_SITE_JACOBI_CENTRE, 0);
         hr_l<1, CHECK>(e, th, tsh, TW, lds_id, cl, HR_SITE_JACOBI_STAGE);
         tile[cl] = vc;
         hr_gs<0, CHECK>(e, th, gold, pc, g, HR_SITE_JACOBI_CENTRE);
